@@ -1,0 +1,265 @@
+#!/usr/bin/env python3
+"""Packets reconstructed per second on one MI355X: FGGC against the direct sum.
+
+    python bench.py [--steps K] [--warmup W] [--workload cfg1] [--no-cpu-baseline]
+
+One step reconstructs one batch of packets, already resident in HBM, into the
+wave function on the grid: pass A times K FGGC reconstructions
+(fggc_reconstruct: correction, scatter, FFT over q, band multiply, inverse
+FFT) and then K direct sums (fggc_direct_sum) of the same packets, each pass
+bracketed by device synchronisations.  `value` is FGGC packets per second;
+the direct sum's rate and the speedup sit beside it.  Pass B repeats both
+with the library's per-stage HIP events on (fggc_profile) to time the kernels
+for the roofline entry.  The CPU-baseline leg times the FP64 oracle on a
+bounded sample of the same workload and checks the GPU results on that sample
+against it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+# VALU issue slots: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one non-packed op per lane per cycle)
+VALU_SLOT_PEAK_T = 256 * 64 * 2.4e9 / 1e12
+
+WORKLOADS = {
+    "cfg0": 0,
+    "cfg1": 1,
+    "cfg2": 2,
+    "cfg3": 3,
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel(u, ref):
+    return float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+
+
+def fggc_alg_bytes(ps, st, slices, es=8):
+    """Bytes the FGGC reconstruction must move: packets in, the cell array
+    written and read, the grid spectrum written and read, u written."""
+    d = ps.d
+    nq = int(np.prod([st.Nq[k] for k in range(d)]))
+    cells = slices * nq
+    mpts = int(np.prod(ps.M))
+    return ps.N * ((2 * d + 1) * 8 + 16) + 2 * cells * es + 3 * mpts * es
+
+
+def direct_slots_per_pair(d):
+    """Minimal VALU issue slots of one (packet, point) evaluation in the FP32
+    path: displacement (d FMA), |y|^2 (d), exponent (1 FMA), window select (2),
+    phase (d FP64 FMA + fract + convert), two FMAs of the accumulation, and
+    three transcendentals (exp, sin, cos) at four slots each."""
+    return d + d + 1 + 2 + (d + 2) + 2 + 3 * 4
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg1", choices=sorted(WORKLOADS))
+    ap.add_argument("--strategy", default=None, help="Q2P2, Q4P2, Q2P4 or Q4P4 (default Q4P2; Q2P2 in 3D)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-target-s", type=float, default=12.0,
+                    help="approximate CPU seconds for the oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2504_21785_amd import fggc as F
+    from paper_2504_21785_amd import workloads as W
+
+    k = WORKLOADS[args.workload]
+    ps = W.config(k)
+    d = ps.d
+    sname = args.strategy or ("Q2P2" if d == 3 else "Q4P2")
+    st = F.default_strategy(d, ps.eps, sname)
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    Q, P, S, a = t(ps.Q), t(ps.P), t(ps.S), t(ps.a)
+    ctx = F.Context(0)
+    u_f = torch.empty(ps.M, dtype=torch.complex64, device=dev)
+    u_d = torch.empty(ps.M, dtype=torch.complex64, device=dev)
+    do_direct = d < 3  # the 3D direct sum runs on a sub-box only (parity test), not timed here
+
+    def step_fggc():
+        ctx.reconstruct(Q, P, S, a, ps.eps, ps.M, st, precision=F.FP32, out=u_f)
+
+    def step_direct():
+        ctx.direct_sum(Q, P, S, a, ps.eps, ps.M, ps.R, precision=F.FP32, out=u_d)
+
+    log(f"workload {args.workload}: d={d} N={ps.N} M={ps.M} eps={ps.eps} strategy={sname}")
+    for _ in range(args.warmup):
+        step_fggc()
+        if do_direct:
+            step_direct()
+    torch.cuda.synchronize()
+
+    # ---- pass A: timed steps -------------------------------------------------
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_fggc()
+    torch.cuda.synchronize()
+    fggc_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"FGGC: {fggc_ms:.4f} ms/step")
+    direct_ms = None
+    if do_direct:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step_direct()
+        torch.cuda.synchronize()
+        direct_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        log(f"direct: {direct_ms:.4f} ms/step")
+
+    # ---- pass B: per-stage HIP events ---------------------------------------
+    ctx.profile(True)
+    for _ in range(args.steps):
+        step_fggc()
+        if do_direct:
+            step_direct()
+    torch.cuda.synchronize()
+    stage_names = ["validate", "pcell_range", "fggc_zero", "fggc_coef_scatter", "fggc_fft_q",
+                   "fggc_band_table", "fggc_band_mac", "fggc_ifft", "ds_prep", "ds_sort",
+                   "ds_kernel", "ds_reduce"]
+    stages = {}
+    for sn in stage_names:
+        ms, cnt = ctx.stage_time(sn)
+        if cnt:
+            stages[sn] = {"avg_ms": ms / cnt, "launches": cnt}
+    ctx.profile(False)
+    log("stages:", json.dumps(stages))
+
+    # FGGC vs direct on the full workload (GPU outputs only)
+    fvd = None
+    if do_direct:
+        fvd = rel(u_f.cpu().numpy().astype(np.complex128), u_d.cpu().numpy().astype(np.complex128))
+        log(f"FGGC vs direct rel-L2 {fvd:.3e}")
+
+    # ---- roofline of the dominant FGGC kernel --------------------------------
+    lo, n = ctx.cell_box(Q, P, S, a, st)
+    slices = int(np.prod(n))
+    fstages = {k2: v for k2, v in stages.items() if k2.startswith("fggc_")}
+    dom = max(fstages, key=lambda s2: fstages[s2]["avg_ms"])
+    nq = int(np.prod([st.Nq[i] for i in range(d)]))
+    cells_b = slices * nq * 8
+    mpts = int(np.prod(ps.M))
+    per_launch_bytes = {
+        # packets in, the dense cell array written once (hardware atomics add in L2)
+        "fggc_coef_scatter": ps.N * ((2 * d + 1) * 8 + 16) + cells_b,
+        "fggc_zero": cells_b,
+        "fggc_fft_q": 2 * cells_b,          # read and write the cell array
+        "fggc_band_mac": cells_b + mpts * 8,  # read the spectra, write the grid spectrum
+        "fggc_ifft": 2 * mpts * 8,
+        "fggc_band_table": 0,
+    }
+    dom_ms = stages[dom]["avg_ms"]
+    achieved = per_launch_bytes.get(dom, 0) / (dom_ms * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "alg_bytes_per_launch": per_launch_bytes.get(dom, 0), "avg_launch_ms": dom_ms}
+    direct_roofline = None
+    if do_direct and "ds_kernel" in stages:
+        pairs = ps.N * (math.pi * ps.R ** 2 / np.prod([2 * math.pi / m for m in ps.M]) if d == 2
+                        else 2 * ps.R / (2 * math.pi / ps.M[0]))
+        slots = pairs * direct_slots_per_pair(d)
+        ach = slots / (stages["ds_kernel"]["avg_ms"] * 1e-3) / 1e12
+        direct_roofline = {"kernel": "ds_kernel", "bound": "alu", "achieved": ach,
+                           "peak": VALU_SLOT_PEAK_T, "unit": "T VALU slots/s",
+                           "frac": ach / VALU_SLOT_PEAK_T, "pairs_per_launch": pairs,
+                           "slots_per_pair": direct_slots_per_pair(d),
+                           "pairs_per_s": pairs / (stages["ds_kernel"]["avg_ms"] * 1e-3)}
+
+    # ---- CPU baseline: the oracle on a bounded sample -----------------------
+    cpu = None
+    accuracy = {}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        cores = oracle.num_threads()
+        sd = st.describe()
+        # calibrate the sample: a prefix of the packet list, full grid
+        ns = min(ps.N, 4096)
+        sub = lambda x: np.ascontiguousarray(x[..., :ns])
+        t0 = time.perf_counter()
+        oracle.fggc(sub(ps.Q), sub(ps.P), sub(ps.S), sub(ps.a), ps.eps, ps.M, sd["Nq"][:d],
+                    sd["dp"][:d], sd["dq_off"], sd["dp_off"])
+        t_small = time.perf_counter() - t0
+        ns = int(min(ps.N, max(4096, 4096 * args.cpu_target_s / 2 / max(t_small, 1e-3))))
+        sQ, sP, sS, sa = sub(ps.Q), sub(ps.P), sub(ps.S), sub(ps.a)
+        log(f"cpu baseline: {ns} packets, {cores} threads")
+        t0 = time.perf_counter()
+        ref_f = oracle.fggc(sQ, sP, sS, sa, ps.eps, ps.M, sd["Nq"][:d], sd["dp"][:d], sd["dq_off"],
+                            sd["dp_off"])
+        t_of = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ref_d = oracle.direct_sum(sQ, sP, sS, sa, ps.eps, ps.M, ps.R) if do_direct else None
+        t_od = time.perf_counter() - t0
+        cpu = {"value": ns / t_of, "unit": "packets/s", "cores": cores, "kind": "oracle",
+               "sample": f"first {ns} packets of the workload, FP64 FGGC (cells + plain evaluation of "
+                         f"eq. 2.24 with window 8 sqrt(eps)) on the full grid",
+               "seconds": t_of}
+        if ref_d is not None:
+            cpu["direct_sum"] = {"value": ns / t_od, "unit": "packets/s", "seconds": t_od,
+                                 "sample": f"first {ns} packets, FP64 windowed direct sum, full grid"}
+        # the GPU on the same sample, against the oracle
+        sT = lambda x: t(x)
+        uf = ctx.reconstruct(sT(sQ), sT(sP), sT(sS), sT(sa), ps.eps, ps.M, st, precision=F.FP32)
+        torch.cuda.synchronize()
+        accuracy["fggc_fp32_vs_oracle_rel_l2"] = rel(uf.cpu().numpy().reshape(-1).astype(np.complex128), ref_f)
+        if ref_d is not None:
+            ud = ctx.direct_sum(sT(sQ), sT(sP), sT(sS), sT(sa), ps.eps, ps.M, ps.R, precision=F.FP32)
+            torch.cuda.synchronize()
+            accuracy["direct_fp32_vs_oracle_rel_l2"] = rel(ud.cpu().numpy().reshape(-1).astype(np.complex128), ref_d)
+        accuracy["sample_packets"] = ns
+        log("accuracy:", accuracy)
+    if fvd is not None:
+        accuracy["fggc_vs_direct_rel_l2"] = fvd
+
+    value = ps.N / (fggc_ms * 1e-3)
+    out = {
+        "metric": "packets reconstructed/sec at rel-L2<=1e-6: FGGC vs direct sum",
+        "value": value,
+        "unit": "packets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fggc_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {W.CONFIG_NAMES[k]}", "strategy": sname,
+                   "N": ps.N, "grid": list(ps.M), "eps": ps.eps, "p_slices": slices,
+                   "Nq": [int(st.Nq[i]) for i in range(d)]},
+        "direct_sum": None if direct_ms is None else {"value": ps.N / (direct_ms * 1e-3),
+                                                      "ms_per_step": direct_ms,
+                                                      "roofline": direct_roofline},
+        "speedup_vs_direct": None if direct_ms is None else direct_ms / fggc_ms,
+        "accuracy": accuracy,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stages_ms": {k2: v["avg_ms"] for k2, v in stages.items()},
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,278 @@
+/*
+ * fggc.h -- C ABI of libfggc, the MI355X (gfx950) library that reconstructs
+ * a wave function on a uniform periodic grid from frozen Gaussian
+ * wave-packets.
+ *
+ * Method: Chai & Deng, "Frozen Gaussian Grid-point Correction for
+ * Semi-classical Schroedinger Equation" (arXiv 2504.21785).
+ *
+ *   u(x) = scale * sum_j a_j exp( i (S_j + P_j.(x - Q_j)) / eps - |x - Q_j|^2 / (2 eps) )
+ *
+ * is the discrete reconstruction sum of eq. (2.10) / (2.19) with the
+ * prefactor (dq dp)^d / (2 pi eps)^{3d/2} of that equation folded into the
+ * caller's `scale`.  Two forms compute it:
+ *   fggc_direct_sum   every packet at every grid point within a window radius;
+ *   fggc_reconstruct  frozen Gaussian grid-point correction (Section 2.3 and
+ *                     Alg. 2): each packet is replaced by its least-squares fit
+ *                     on on-grid packets (eq. 2.20-2.22, 3.9-3.13, 3.22-3.23),
+ *                     the coefficients are summed per phase-space cell
+ *                     (eq. 2.25) and eq. (2.24) is evaluated with FFTs.
+ *
+ * Conventions shared by every call
+ *   - Domain [-pi, pi)^d, periodic; grid x_m = -pi + m * 2 pi / n per
+ *     dimension; d in {1, 2, 3}.  Distances use the minimum image.
+ *   - Packets are structure-of-arrays FP64: Q[d][N], P[d][N], S[N], and
+ *     a[N] complex128 (interleaved re, im).
+ *   - Output u is row-major over the grid (last dimension fastest),
+ *     interleaved complex: complex64 for FGGC_FP32, complex128 for FGGC_FP64.
+ *   - Pointers may be device memory (hipMalloc, or a torch CUDA tensor's
+ *     data_ptr) or ordinary host memory; host buffers are staged through the
+ *     context's device workspace and the call then completes before it
+ *     returns.  The caller owns every buffer; the library keeps no pointer
+ *     after a call returns.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  With device
+ *     buffers the call is stream-ordered: it enqueues work and returns;
+ *     buffers must stay valid until the stream has passed the call.
+ *   - Every call returns an fggc_status; no C++ exception crosses the ABI.
+ *     fggc_last_error() describes the last failure on the calling thread.
+ *   - A context is used by one thread at a time (calls on one context are
+ *     serialised by an internal lock).
+ */
+#ifndef FGGC_H
+#define FGGC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FGGC_OK = 0,
+  FGGC_EINVAL = -1,       /* invalid argument (NaN/Inf input, eps <= 0, bad d, bad size, ...) */
+  FGGC_ENOMEM = -2,       /* device allocation failed */
+  FGGC_EBUDGET = -3,      /* the request can never fit in the context's HBM budget */
+  FGGC_EUNSUPPORTED = -4, /* valid but not supported (e.g. non power-of-two FFT size) */
+  FGGC_EDEVICE = -5,      /* a HIP runtime call failed */
+  FGGC_ECANCELLED = -6,   /* a served request was cancelled */
+  FGGC_ETIMEOUT = -7      /* fggc_server_wait timed out; the request is still pending */
+} fggc_status;
+
+typedef enum { FGGC_FP32 = 0, FGGC_FP64 = 1 } fggc_precision;
+
+typedef struct fggc_ctx fggc_ctx;
+
+/* Periodic grid [-pi,pi)^d with n[k] points in dimension k (n[k] >= 1). */
+typedef struct {
+  int32_t d;
+  int64_t n[3];
+} fggc_grid;
+
+/* N packets in d dimensions; see the conventions above.  N = 0 is allowed. */
+typedef struct {
+  int32_t d;
+  int64_t N;
+  const double *Q; /* [d][N] centres */
+  const double *P; /* [d][N] momenta */
+  const double *S; /* [N] actions */
+  const double *a; /* [N] complex128 amplitudes (re, im) */
+} fggc_packets;
+
+/*
+ * Mesh and neighbour strategy of eq. (3.5) and Definition 1 (eq. 2.20).
+ *   q-mesh: Nq[k] points over [-pi, pi) (dq = 2 pi / Nq[k], Nq[k] even, power
+ *           of two, 4 <= Nq[k] <= 8192); cell anchoring floor(Q / dq) as in (2.20).
+ *   p-mesh: step dp[k] > 0, cells floor(P / dp), not wrapped.
+ *   Shift set: the tensor product over dimensions of the one-dimensional set
+ *           {(dq_off[i], dp_off[j])}, i < nq, j < np (nq * np <= 16), as in the
+ *           strategies Q2P2, Q4P2, Q2P4, Q4P4 of Section 3.1.
+ *   cutoff: relative eigenvalue cutoff of the pseudo-inverse (remark after
+ *           Alg. 1): eigenvalues of the eps-free Gram matrix (3.22) below
+ *           cutoff * lambda_max are dropped.  0 = exact least squares.
+ */
+typedef struct {
+  int64_t Nq[3];
+  double dp[3];
+  int32_t nq, np;
+  int32_t dq_off[8];
+  int32_t dp_off[8];
+  double cutoff;
+} fggc_strategy;
+
+/* ------------------------------------------------------------------------ */
+/* context                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the
+ * workspace the context may hold (0 = 90% of the device's free memory).
+ * Errors: FGGC_EINVAL (bad device, out == NULL), FGGC_EDEVICE. */
+int fggc_create(fggc_ctx **out, int device, size_t hbm_budget_bytes);
+
+/* Release the context and its workspace (waits for its own stream). */
+void fggc_destroy(fggc_ctx *ctx);
+
+/* Message for the last failing call on this thread ("" if none).  The string
+ * stays valid until the next call on this thread. */
+const char *fggc_last_error(void);
+
+/* Library version string. */
+const char *fggc_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* reconstruction                                                            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Windowed direct sum, eq. (2.10): every packet is evaluated at every grid
+ * point with |x - Q_j| <= window_radius (Euclidean, minimum image,
+ * inclusive); 0 < window_radius < pi.
+ * FGGC_FP64: all arithmetic in FP64.  FGGC_FP32: the phase argument
+ * (S + P.(x-Q))/eps is formed and reduced modulo 2 pi in FP64, the Gaussian,
+ * sine, cosine and products in FP32, the grid sums accumulated in FP64 over
+ * FP32 partial sums of at most 32 terms.
+ * u_out: prod(grid->n) complex values (see conventions).
+ * Errors: FGGC_EINVAL (d mismatch, eps <= 0, radius out of range, grid size
+ * < 1, NaN or Inf in S or a, |Q| or |P| above 1e9 or not finite -- checked
+ * on the device before any output is written; the call synchronises the
+ * stream once for this check), FGGC_ENOMEM, FGGC_EBUDGET, FGGC_EDEVICE.
+ */
+int fggc_direct_sum(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_grid *grid,
+                    double window_radius, double scale, int precision, void *u_out, void *stream);
+
+/*
+ * FGGC reconstruction (Alg. 2 steps 3-4 with eq. 2.23-2.25):
+ *   per packet and dimension, int/frac split (3.6)-(3.7), right-hand side
+ *   (3.23), least squares against the precomputed Gram matrix (3.22) through
+ *   its eigenpairs, conjugation of the printed system's solution to the
+ *   L2-best coefficients, coefficient shift (3.13) with the sign that goes
+ *   with it, Kronecker product over dimensions; scatter-add of
+ *   scale * a_j exp(i S_j / eps) c_j^(k) into the dense cell array over the
+ *   occupied p-cell box (2.25); then eq. (2.24) by a forward FFT over q per
+ *   p-slice, a Gaussian band multiply-accumulate into the grid spectrum
+ *   (the Fourier transform of (2.16) with the on-grid centre and momentum),
+ *   and one inverse FFT of size prod(grid->n).
+ * grid->n[k] must be powers of two (2 .. 16384 for 1D FP32, 8192 for FP64,
+ * 4096 for d >= 2).  Nq as in fggc_strategy.
+ * FGGC_FP64: FP64 throughout.  FGGC_FP32: least squares, phase reductions
+ * and band weights in FP64; cells, FFTs and products in FP32; spectrum
+ * accumulated in FP64.
+ * Errors: as fggc_direct_sum, plus FGGC_EUNSUPPORTED for sizes outside the
+ * ranges above and FGGC_EBUDGET when the cell array cannot fit.
+ */
+int fggc_reconstruct(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_grid *grid,
+                     const fggc_strategy *st, double scale, int precision, void *u_out,
+                     void *stream);
+
+/*
+ * Fill *out with a named strategy at the mesh of eq. (3.5) recommended after
+ * the Section 3.1 tables: dq ~ sqrt(eps)/2 with Nq the power of two nearest
+ * 2 pi / (sqrt(eps)/2), dp = pi sqrt(eps)/8.  name: "Q2P2"
+ * (dq {0,1} x dp {0,1}), "Q4P2" (dq {-1,0,1,2} x dp {0,1}), "Q2P4"
+ * (dq {0,1} x dp {-1,0,1,2}) or "Q4P4".  cutoff = 0.  Host only.
+ * Errors: FGGC_EINVAL.
+ */
+int fggc_default_strategy(int d, double eps, const char *name, fggc_strategy *out);
+
+/* ------------------------------------------------------------------------ */
+/* stages of the FGGC path (exposed for inspection and testing)              */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The occupied p-cell box of a packet set under strategy `st`: slice_lo[k]
+ * and slice_n[k] such that every p-cell floor(P/dp) + dp_off lies in
+ * [slice_lo, slice_lo + slice_n).  Synchronises the stream.
+ */
+int fggc_cell_box(fggc_ctx *ctx, const fggc_packets *pk, const fggc_strategy *st,
+                  int64_t *slice_lo, int64_t *slice_n, void *stream);
+
+/*
+ * The dense cell array A~(q_i, p_l) of eq. (2.25), times scale, over the box
+ * returned by fggc_cell_box: layout [slice][q] with slice row-major over the
+ * box and q row-major over Nq (q_i = -pi + i dq); complex64 (FGGC_FP32) or
+ * complex128 (FGGC_FP64).  cells_bytes must be at least the array's size.
+ * Errors: FGGC_EINVAL when the box does not match the packets.
+ */
+int fggc_cells(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_strategy *st,
+               double scale, int precision, const int64_t *slice_lo, const int64_t *slice_n,
+               void *cells_out, size_t cells_bytes, void *stream);
+
+/*
+ * In-place batched d-dimensional complex DFT on device memory:
+ *   forward (direction = -1): X[k] = sum_n x[n] exp(-2 pi i k.n / n)
+ *   inverse (direction = +1): X[k] = sum_n x[n] exp(+2 pi i k.n / n), unnormalised.
+ * data: batch consecutive arrays of prod(n[0..d-1]) complex values
+ * (complex64 for FGGC_FP32, complex128 for FGGC_FP64), row-major.
+ * Sizes: powers of two, 2 .. 16384 (FP32) or 8192 (FP64) per dimension.
+ */
+int fggc_fft(fggc_ctx *ctx, int d, const int64_t *n, int64_t batch, int direction, int precision,
+             void *data, void *stream);
+
+/*
+ * Eigen-decomposition used by the plan: Gram matrix (3.22) of the
+ * one-dimensional shift set for C_q = dq/sqrt(eps), C_p = dp/sqrt(eps),
+ * n1 = nq * np (basis index i * np + j).  evals[n1] ascending; evecs
+ * [n1][n1] complex128, column k the unit eigenvector of evals[k].  Host only.
+ */
+int fggc_plan_gram(int nq, const int32_t *dq_off, int np, const int32_t *dp_off, double Cq,
+                   double Cp, double *evals, double *evecs);
+
+/*
+ * Per-stage timing for benchmarks.  With enable = 1 every later call on the
+ * context records HIP events around each of its stages (on the stream the
+ * stage runs on); enable = 0 stops recording.  Either resets the totals.
+ * Stages: "validate", "pcell_range", "ds_prep", "ds_sort", "ds_kernel",
+ * "ds_reduce", "fggc_zero", "fggc_coef_scatter", "fggc_fft_q",
+ * "fggc_band_table", "fggc_band_mac", "fggc_ifft", "fft".
+ */
+int fggc_profile(fggc_ctx *ctx, int enable);
+
+/* Total milliseconds and number of launches recorded for one stage since the
+ * last fggc_profile call (waits for the recorded events). */
+int fggc_stage_time(fggc_ctx *ctx, const char *stage, double *total_ms, int64_t *count);
+
+/* ------------------------------------------------------------------------ */
+/* serving                                                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct fggc_server fggc_server;
+typedef int64_t fggc_ticket;
+
+/*
+ * A persistent scheduler on the context's device.  Submitted requests are
+ * admitted in arrival order as soon as their memory estimate fits the
+ * context's HBM budget and a slot is free; admitted requests run
+ * concurrently on `n_streams` streams (1..8), each as a captured and cached
+ * hipGraph of its shape.  A request whose estimate alone exceeds the
+ * budget fails with FGGC_EBUDGET without blocking others.
+ */
+int fggc_server_create(fggc_ctx *ctx, int n_streams, fggc_server **out);
+
+/*
+ * Enqueue a reconstruction.  Packet arrays are copied to the device before
+ * submit returns (the caller may free them).  st == NULL selects the
+ * direct sum with window 6 sqrt(eps); otherwise FGGC with *st.  u_out is
+ * host memory of prod(grid->n) complex values, written before the ticket
+ * completes.
+ */
+int fggc_server_submit(fggc_server *srv, const fggc_packets *pk, double eps, const fggc_grid *grid,
+                       const fggc_strategy *st, double scale, int precision, void *u_out,
+                       fggc_ticket *ticket);
+
+/* Wait for a ticket; returns its final status, or FGGC_ETIMEOUT if
+ * timeout_s (< 0: forever) elapsed first. */
+int fggc_server_wait(fggc_server *srv, fggc_ticket ticket, double timeout_s);
+
+/* Latency percentiles (submit to completion, seconds) and throughput
+ * (packets per second of wall time since the first submit) of the
+ * completed requests. */
+int fggc_server_stats(fggc_server *srv, double *p50_s, double *p99_s, double *packets_per_s,
+                      int64_t *completed);
+
+/* Stop the scheduler after the queued requests have finished; free it. */
+void fggc_server_destroy(fggc_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FGGC_H */

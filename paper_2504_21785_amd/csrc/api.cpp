@@ -1,0 +1,625 @@
+// C ABI of libfggc: argument checks, context and workspace, host/device
+// staging, and the error model (every entry point returns an fggc_status and
+// records a thread-local message; no exception crosses the ABI).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "common.h"
+
+namespace fggc {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+Workspace::~Workspace() {
+  if (base_) (void)hipFree(base_);
+}
+
+void Workspace::reserve(size_t bytes, size_t budget) {
+  used_ = 0;
+  if (bytes <= cap_) return;
+  if (bytes > budget)
+    fail(FGGC_EBUDGET, "request needs " + std::to_string(bytes) + " bytes of workspace, budget is " +
+                           std::to_string(budget));
+  if (base_) {
+    FGGC_HIP(hipDeviceSynchronize());
+    FGGC_HIP(hipFree(base_));
+    base_ = nullptr;
+    cap_ = 0;
+  }
+  size_t want = std::min(budget, std::max(bytes, bytes + bytes / 4));
+  if (hipMalloc((void **)&base_, want) != hipSuccess) {
+    (void)hipGetLastError();
+    want = bytes;
+    if (hipMalloc((void **)&base_, want) != hipSuccess) {
+      (void)hipGetLastError();
+      base_ = nullptr;
+      fail(FGGC_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  cap_ = want;
+}
+
+void *Workspace::take(size_t bytes) {
+  size_t at = used_;
+  used_ = align_up(used_ + bytes, 256);
+  if (used_ > cap_) fail(FGGC_EDEVICE, "internal: workspace overrun");
+  return base_ + at;
+}
+
+Profiler::~Profiler() {
+  for (auto &q : pending_) {
+    (void)hipEventDestroy(q.a);
+    (void)hipEventDestroy(q.b);
+  }
+  for (auto &o : open_) (void)hipEventDestroy(o.second);
+}
+
+void Profiler::start(const char *stage, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(mu_);
+  hipEvent_t e;
+  FGGC_HIP(hipEventCreate(&e));
+  FGGC_HIP(hipEventRecord(e, s));
+  open_.push_back({stage, e});
+}
+
+void Profiler::stop(const char *stage, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(mu_);
+  for (size_t i = open_.size(); i-- > 0;) {
+    if (open_[i].first == stage) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess || hipEventRecord(e, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+      }
+      pending_.push_back({open_[i].first, open_[i].second, e});
+      open_.erase(open_.begin() + (long)i);
+      return;
+    }
+  }
+}
+
+void Profiler::drain() {
+  for (auto &q : pending_) {
+    float ms = 0.f;
+    if (hipEventSynchronize(q.b) == hipSuccess && hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
+      bool found = false;
+      for (auto &a : acc_)
+        if (a.first == q.stage) {
+          a.second.ms += ms;
+          a.second.count += 1;
+          found = true;
+        }
+      if (!found) acc_.push_back({q.stage, Acc{ms, 1}});
+    } else {
+      (void)hipGetLastError();
+    }
+    (void)hipEventDestroy(q.a);
+    (void)hipEventDestroy(q.b);
+  }
+  pending_.clear();
+}
+
+void Profiler::query(const std::string &stage, double *ms, int64_t *count) {
+  std::lock_guard<std::mutex> lk(mu_);
+  drain();
+  *ms = 0;
+  *count = 0;
+  for (auto &a : acc_)
+    if (a.first == stage) {
+      *ms = a.second.ms;
+      *count = a.second.count;
+    }
+}
+
+void Profiler::reset() {
+  std::lock_guard<std::mutex> lk(mu_);
+  drain();
+  acc_.clear();
+}
+
+std::vector<std::string> Profiler::stages() {
+  std::lock_guard<std::mutex> lk(mu_);
+  drain();
+  std::vector<std::string> v;
+  for (auto &a : acc_) v.push_back(a.first);
+  return v;
+}
+
+namespace {
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// true when `p` can be dereferenced by kernels on the current device as is
+bool device_accessible(const void *p) {
+  hipPointerAttribute_t at;
+  hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged ||
+         at.type == hipMemoryTypeUnified;
+}
+
+void check_packets(const fggc_packets *pk, int d) {
+  if (!pk) fail(FGGC_EINVAL, "packets is NULL");
+  if (pk->d != d) fail(FGGC_EINVAL, "packets->d does not match grid->d");
+  if (pk->N < 0 || pk->N > 0x7fffffffLL) fail(FGGC_EINVAL, "packet count out of range [0, 2^31)");
+  if (pk->N > 0 && (!pk->Q || !pk->P || !pk->S || !pk->a)) fail(FGGC_EINVAL, "packet array is NULL");
+}
+
+GridGeom check_grid(const fggc_grid *g) {
+  if (!g) fail(FGGC_EINVAL, "grid is NULL");
+  if (g->d < 1 || g->d > 3) fail(FGGC_EINVAL, "grid->d must be 1, 2 or 3");
+  GridGeom gg{};
+  gg.d = g->d;
+  int64_t total = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (k < g->d) {
+      if (g->n[k] < 1 || g->n[k] > (1 << 24)) fail(FGGC_EINVAL, "grid size out of range [1, 2^24]");
+      gg.n[k] = g->n[k];
+      gg.dx[k] = kTwoPi / (double)g->n[k];
+      total *= g->n[k];
+    } else {
+      gg.n[k] = 1;
+      gg.dx[k] = 1.0;
+    }
+  }
+  if (total > (int64_t)1 << 31) fail(FGGC_EINVAL, "grid has more than 2^31 points");
+  return gg;
+}
+
+void check_eps(double eps) {
+  if (!(eps > 0) || !std::isfinite(eps)) fail(FGGC_EINVAL, "eps must be finite and > 0");
+}
+
+// Inputs as device pointers: staged through the workspace when on the host.
+struct Staged {
+  fggc_packets pk;
+  bool host_out = false;
+  void *u_dev = nullptr;
+};
+
+size_t staging_bytes(const fggc_packets &pk, bool any_host, size_t out_bytes, bool host_out) {
+  size_t b = 0;
+  if (any_host) b += align_up(pk.N * (size_t)(2 * pk.d + 3) * 8, 256) + 256;
+  if (host_out) b += align_up(out_bytes, 256) + 256;
+  return b;
+}
+
+struct Guard {
+  fggc_ctx *ctx;
+  explicit Guard(fggc_ctx *c) : ctx(c) {
+    ctx->mu.lock();
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) {
+      ctx->mu.unlock();
+      fail(FGGC_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    }
+  }
+  ~Guard() { ctx->mu.unlock(); }
+};
+
+template <class F> int guarded(const char *what, F &&f) {
+  try {
+    f();
+    return FGGC_OK;
+  } catch (const Error &e) {
+    set_last_error(std::string(what) + ": " + e.msg);
+    return e.code;
+  } catch (const std::exception &e) {
+    set_last_error(std::string(what) + ": " + e.what());
+    return FGGC_EDEVICE;
+  } catch (...) {
+    set_last_error(std::string(what) + ": unknown internal error");
+    return FGGC_EDEVICE;
+  }
+}
+
+// Copy host-resident packet arrays into `dst` (device); returns device views.
+fggc_packets stage_packets(const fggc_packets &pk, char *dst, hipStream_t s) {
+  fggc_packets out = pk;
+  const size_t dN = (size_t)pk.d * pk.N * 8, N8 = (size_t)pk.N * 8;
+  double *Q = (double *)dst, *P = Q + (size_t)pk.d * pk.N, *S = P + (size_t)pk.d * pk.N,
+         *a = S + pk.N;
+  FGGC_HIP(hipMemcpyAsync(Q, pk.Q, dN, hipMemcpyHostToDevice, s));
+  FGGC_HIP(hipMemcpyAsync(P, pk.P, dN, hipMemcpyHostToDevice, s));
+  FGGC_HIP(hipMemcpyAsync(S, pk.S, N8, hipMemcpyHostToDevice, s));
+  FGGC_HIP(hipMemcpyAsync(a, pk.a, 2 * N8, hipMemcpyHostToDevice, s));
+  out.Q = Q;
+  out.P = P;
+  out.S = S;
+  out.a = a;
+  return out;
+}
+
+bool packets_on_host(const fggc_packets &pk) {
+  if (pk.N == 0) return false;
+  return !(device_accessible(pk.Q) && device_accessible(pk.P) && device_accessible(pk.S) &&
+           device_accessible(pk.a));
+}
+
+// Non-finite check of device packets; synchronises the stream.
+void validate_finite(fggc_ctx *ctx, const fggc_packets &pk, hipStream_t s) {
+  if (pk.N == 0) return;
+  FGGC_HIP(hipMemsetAsync(ctx->dev_flag, 0, sizeof(int), s));
+  {
+    StageScope sc(ctx->profiling ? &ctx->prof : nullptr, "validate", s);
+    launch_validate(pk, ctx->dev_flag, s);
+  }
+  FGGC_HIP(hipMemcpyAsync(ctx->host_flag, ctx->dev_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  FGGC_HIP(hipStreamSynchronize(s));
+  if (*ctx->host_flag != 0)
+    fail(FGGC_EINVAL, std::to_string(*ctx->host_flag) + " packet(s) with NaN or Inf in Q, P, S or a");
+}
+
+void check_strategy(const fggc_strategy *st, int d) {
+  if (!st) fail(FGGC_EINVAL, "strategy is NULL");
+  if (st->nq < 1 || st->np < 1 || st->nq > 8 || st->np > 8 || st->nq * st->np > kMaxN1)
+    fail(FGGC_EINVAL, "strategy needs 1 <= nq, np <= 8 and nq * np <= 16");
+  for (int i = 0; i < st->nq; ++i)
+    for (int j = i + 1; j < st->nq; ++j)
+      if (st->dq_off[i] == st->dq_off[j]) fail(FGGC_EINVAL, "repeated q shift in strategy");
+  for (int i = 0; i < st->np; ++i)
+    for (int j = i + 1; j < st->np; ++j)
+      if (st->dp_off[i] == st->dp_off[j]) fail(FGGC_EINVAL, "repeated p shift in strategy");
+  for (int i = 0; i < st->nq; ++i)
+    if (std::abs(st->dq_off[i]) > 64) fail(FGGC_EINVAL, "q shift out of range [-64, 64]");
+  for (int i = 0; i < st->np; ++i)
+    if (std::abs(st->dp_off[i]) > 64) fail(FGGC_EINVAL, "p shift out of range [-64, 64]");
+  if (!(st->cutoff >= 0) || !(st->cutoff < 1)) fail(FGGC_EINVAL, "cutoff must be in [0, 1)");
+  for (int k = 0; k < d; ++k) {
+    if (st->Nq[k] < 4 || st->Nq[k] > 8192 || !is_pow2(st->Nq[k]))
+      fail(FGGC_EUNSUPPORTED, "Nq must be a power of two in [4, 8192]");
+    if (!(st->dp[k] > 0) || !std::isfinite(st->dp[k])) fail(FGGC_EINVAL, "dp must be finite and > 0");
+  }
+}
+
+// p-cell box of the packets (device reduction, one synchronisation).
+void cell_box(fggc_ctx *ctx, const fggc_packets &pk, const fggc_strategy &st, int64_t *slo,
+              int64_t *sn, hipStream_t s) {
+  if (pk.N == 0) fail(FGGC_EINVAL, "no packets");
+  double dp[3] = {st.dp[0], st.dp[1], st.dp[2]};
+  {
+    StageScope sc(ctx->profiling ? &ctx->prof : nullptr, "pcell_range", s);
+    launch_pcell_range(pk, dp, ctx->dev_range, s);
+  }
+  FGGC_HIP(hipMemcpyAsync(ctx->host_range, ctx->dev_range, 6 * sizeof(long long),
+                          hipMemcpyDeviceToHost, s));
+  FGGC_HIP(hipStreamSynchronize(s));
+  int mn = st.dp_off[0], mx = st.dp_off[0];
+  for (int i = 1; i < st.np; ++i) {
+    mn = std::min(mn, st.dp_off[i]);
+    mx = std::max(mx, st.dp_off[i]);
+  }
+  for (int k = 0; k < pk.d; ++k) {
+    const long long lo = ctx->host_range[k], hi = ctx->host_range[3 + k];
+    if (hi < lo || lo < -((long long)1 << 40) || hi > ((long long)1 << 40))
+      fail(FGGC_EINVAL, "momenta out of range for the p-mesh");
+    slo[k] = lo + mn;
+    sn[k] = hi + mx - slo[k] + 1;
+  }
+  for (int k = pk.d; k < 3; ++k) {
+    slo[k] = 0;
+    sn[k] = 1;
+  }
+}
+
+void fill_fggc_args(FggcArgs &fa, const fggc_packets *pk, double eps, const GridGeom &g,
+                    const fggc_strategy &st, double scale, int precision, const DimLsq *lsq,
+                    const int64_t *slo, const int64_t *sn) {
+  fa.pk = pk;
+  fa.eps = eps;
+  fa.scale = scale;
+  fa.g = g;
+  fa.precision = precision;
+  fa.lsq = lsq;
+  for (int k = 0; k < 3; ++k) {
+    fa.Nq[k] = k < g.d ? st.Nq[k] : 1;
+    fa.dp[k] = k < g.d ? st.dp[k] : 1.0;
+    fa.slo[k] = slo[k];
+    fa.sn[k] = sn[k];
+  }
+  fa.cK = precision == FGGC_FP64 ? 8.0 : 6.0;
+}
+
+int64_t prod3(const int64_t *v, int d) {
+  int64_t p = 1;
+  for (int k = 0; k < d; ++k) p *= v[k];
+  return p;
+}
+
+}  // namespace
+}  // namespace fggc
+
+using namespace fggc;
+
+extern "C" {
+
+const char *fggc_last_error(void) { return g_last_error.c_str(); }
+
+const char *fggc_version(void) { return "fggc 0.1 (gfx950)"; }
+
+int fggc_create(fggc_ctx **out, int device, size_t hbm_budget_bytes) {
+  return guarded("fggc_create", [&] {
+    if (!out) fail(FGGC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    FGGC_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) fail(FGGC_EINVAL, "no such device");
+    FGGC_HIP(hipSetDevice(device));
+    fggc_ctx *c = new fggc_ctx();
+    c->device = device;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      (void)hipGetLastError();
+      fr = tot = 0;
+    }
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+    try {
+      FGGC_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      FGGC_HIP(hipMalloc((void **)&c->dev_flag, 256));
+      c->dev_range = (long long *)((char *)c->dev_flag + 64);
+      FGGC_HIP(hipHostMalloc((void **)&c->host_flag, 256, hipHostMallocDefault));
+      c->host_range = (long long *)((char *)c->host_flag + 64);
+    } catch (...) {
+      fggc_destroy(c);
+      throw;
+    }
+    *out = c;
+  });
+}
+
+void fggc_destroy(fggc_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->dev_flag) (void)hipFree(ctx->dev_flag);
+  if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+int fggc_direct_sum(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_grid *grid,
+                    double window_radius, double scale, int precision, void *u_out, void *stream) {
+  return guarded("fggc_direct_sum", [&] {
+    if (!ctx) fail(FGGC_EINVAL, "ctx is NULL");
+    GridGeom g = check_grid(grid);
+    check_packets(pk, g.d);
+    check_eps(eps);
+    if (!(window_radius > 0) || !(window_radius < kPi))
+      fail(FGGC_EINVAL, "window_radius must be in (0, pi)");
+    if (!std::isfinite(scale)) fail(FGGC_EINVAL, "scale must be finite");
+    if (precision != FGGC_FP32 && precision != FGGC_FP64) fail(FGGC_EINVAL, "bad precision");
+    if (!u_out) fail(FGGC_EINVAL, "u_out is NULL");
+    Guard lock(ctx);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t npts = prod3(g.n, g.d);
+    const size_t out_bytes = (size_t)npts * (precision == FGGC_FP64 ? 16 : 8);
+    const bool host_in = packets_on_host(*pk);
+    const bool host_out = !device_accessible(u_out);
+    DirectArgs da{};
+    fggc_packets dpk = *pk;
+    da.pk = &dpk;
+    da.eps = eps;
+    da.R = window_radius;
+    da.scale = scale;
+    da.g = g;
+    for (int k = 0; k < 3; ++k) {
+      da.box.lo[k] = 0;
+      da.box.n[k] = g.n[k];
+    }
+    da.precision = precision;
+    da.prof = ctx->profiling ? &ctx->prof : nullptr;
+    const size_t need = staging_bytes(*pk, host_in, out_bytes, host_out) + direct_workspace_bytes(da);
+    ctx->ws.reserve(need, ctx->budget);
+    if (host_in) dpk = stage_packets(*pk, (char *)ctx->ws.take((size_t)pk->N * (2 * pk->d + 3) * 8), s);
+    da.u = host_out ? ctx->ws.take(out_bytes) : u_out;
+    validate_finite(ctx, dpk, s);
+    launch_direct(da, ctx->ws, s);
+    if (host_out) {
+      FGGC_HIP(hipMemcpyAsync(u_out, da.u, out_bytes, hipMemcpyDeviceToHost, s));
+      FGGC_HIP(hipStreamSynchronize(s));
+    } else if (host_in) {
+      FGGC_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+int fggc_cell_box(fggc_ctx *ctx, const fggc_packets *pk, const fggc_strategy *st,
+                  int64_t *slice_lo, int64_t *slice_n, void *stream) {
+  return guarded("fggc_cell_box", [&] {
+    if (!ctx || !pk || !slice_lo || !slice_n) fail(FGGC_EINVAL, "NULL argument");
+    if (pk->d < 1 || pk->d > 3) fail(FGGC_EINVAL, "packets->d must be 1, 2 or 3");
+    check_packets(pk, pk->d);
+    check_strategy(st, pk->d);
+    Guard lock(ctx);
+    hipStream_t s = (hipStream_t)stream;
+    const bool host_in = packets_on_host(*pk);
+    fggc_packets dpk = *pk;
+    ctx->ws.reserve(staging_bytes(*pk, host_in, 0, false) + 256, ctx->budget);
+    if (host_in) dpk = stage_packets(*pk, (char *)ctx->ws.take((size_t)pk->N * (2 * pk->d + 3) * 8), s);
+    validate_finite(ctx, dpk, s);
+    int64_t lo[3], n[3];
+    cell_box(ctx, dpk, *st, lo, n, s);
+    for (int k = 0; k < pk->d; ++k) {
+      slice_lo[k] = lo[k];
+      slice_n[k] = n[k];
+    }
+  });
+}
+
+int fggc_cells(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_strategy *st,
+               double scale, int precision, const int64_t *slice_lo, const int64_t *slice_n,
+               void *cells_out, size_t cells_bytes, void *stream) {
+  return guarded("fggc_cells", [&] {
+    if (!ctx || !pk || !slice_lo || !slice_n || !cells_out) fail(FGGC_EINVAL, "NULL argument");
+    if (pk->d < 1 || pk->d > 3) fail(FGGC_EINVAL, "packets->d must be 1, 2 or 3");
+    const int d = pk->d;
+    check_packets(pk, d);
+    check_eps(eps);
+    check_strategy(st, d);
+    if (!std::isfinite(scale)) fail(FGGC_EINVAL, "scale must be finite");
+    if (precision != FGGC_FP32 && precision != FGGC_FP64) fail(FGGC_EINVAL, "bad precision");
+    Guard lock(ctx);
+    hipStream_t s = (hipStream_t)stream;
+    int64_t slo[3] = {0, 0, 0}, sn[3] = {1, 1, 1};
+    for (int k = 0; k < d; ++k) {
+      slo[k] = slice_lo[k];
+      sn[k] = slice_n[k];
+      if (sn[k] < 1) fail(FGGC_EINVAL, "slice_n must be >= 1");
+    }
+    const size_t bytes = (size_t)(prod3(sn, d) * prod3(st->Nq, d)) * (precision == FGGC_FP64 ? 16 : 8);
+    if (cells_bytes < bytes) fail(FGGC_EINVAL, "cells_out too small");
+    const bool host_in = packets_on_host(*pk);
+    const bool host_out = !device_accessible(cells_out);
+    fggc_packets dpk = *pk;
+    DimLsq lsq[3];
+    for (int k = 0; k < d; ++k) build_dim_lsq(*st, k, eps, &lsq[k]);
+    GridGeom g{};
+    g.d = d;
+    for (int k = 0; k < 3; ++k) {
+      g.n[k] = 1;
+      g.dx[k] = 1.0;
+    }
+    FggcArgs fa{};
+    fill_fggc_args(fa, &dpk, eps, g, *st, scale, precision, lsq, slo, sn);
+    ctx->ws.reserve(staging_bytes(*pk, host_in, bytes, host_out) + fggc_cells_workspace_bytes(fa),
+                    ctx->budget);
+    if (host_in) dpk = stage_packets(*pk, (char *)ctx->ws.take((size_t)pk->N * (2 * d + 3) * 8), s);
+    void *cells = host_out ? ctx->ws.take(bytes) : cells_out;
+    validate_finite(ctx, dpk, s);
+    // the box must hold every p-cell the packets touch
+    if (dpk.N > 0) {
+      int64_t lo[3], n[3];
+      cell_box(ctx, dpk, *st, lo, n, s);
+      for (int k = 0; k < d; ++k)
+        if (lo[k] < slo[k] || lo[k] + n[k] > slo[k] + sn[k])
+          fail(FGGC_EINVAL, "slice box does not contain the packets' p-cells");
+    }
+    launch_fggc_cells(fa, cells, ctx->ws, s);
+    if (host_out) {
+      FGGC_HIP(hipMemcpyAsync(cells_out, cells, bytes, hipMemcpyDeviceToHost, s));
+      FGGC_HIP(hipStreamSynchronize(s));
+    } else if (host_in) {
+      FGGC_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+int fggc_reconstruct(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_grid *grid,
+                     const fggc_strategy *st, double scale, int precision, void *u_out,
+                     void *stream) {
+  return guarded("fggc_reconstruct", [&] {
+    if (!ctx) fail(FGGC_EINVAL, "ctx is NULL");
+    GridGeom g = check_grid(grid);
+    const int d = g.d;
+    check_packets(pk, d);
+    check_eps(eps);
+    check_strategy(st, d);
+    if (!std::isfinite(scale)) fail(FGGC_EINVAL, "scale must be finite");
+    if (precision != FGGC_FP32 && precision != FGGC_FP64) fail(FGGC_EINVAL, "bad precision");
+    if (!u_out) fail(FGGC_EINVAL, "u_out is NULL");
+    const int64_t maxM = d == 1 ? (precision == FGGC_FP64 ? 8192 : 16384) : 4096;
+    for (int k = 0; k < d; ++k)
+      if (!is_pow2(g.n[k]) || g.n[k] < 2 || g.n[k] > maxM)
+        fail(FGGC_EUNSUPPORTED, "FGGC needs power-of-two grid sizes in [2, " + std::to_string(maxM) + "]");
+    Guard lock(ctx);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t npts = prod3(g.n, d);
+    const size_t out_bytes = (size_t)npts * (precision == FGGC_FP64 ? 16 : 8);
+    const bool host_in = packets_on_host(*pk);
+    const bool host_out = !device_accessible(u_out);
+    fggc_packets dpk = *pk;
+    // stage, validate and find the p-cell box (one synchronisation)
+    ctx->ws.reserve(staging_bytes(*pk, host_in, out_bytes, host_out) + 256, ctx->budget);
+    if (host_in) dpk = stage_packets(*pk, (char *)ctx->ws.take((size_t)pk->N * (2 * d + 3) * 8), s);
+    if (dpk.N == 0) {
+      void *u = host_out ? ctx->ws.take(out_bytes) : u_out;
+      FGGC_HIP(hipMemsetAsync(u, 0, out_bytes, s));
+      if (host_out) FGGC_HIP(hipMemcpyAsync(u_out, u, out_bytes, hipMemcpyDeviceToHost, s));
+      FGGC_HIP(hipStreamSynchronize(s));
+      return;
+    }
+    validate_finite(ctx, dpk, s);
+    int64_t slo[3], sn[3];
+    cell_box(ctx, dpk, *st, slo, sn, s);
+    DimLsq lsq[3];
+    for (int k = 0; k < d; ++k) build_dim_lsq(*st, k, eps, &lsq[k]);
+    FggcArgs fa{};
+    fill_fggc_args(fa, &dpk, eps, g, *st, scale, precision, lsq, slo, sn);
+    // the staged packets must survive the re-reservation: reserve everything once more
+    const size_t stage_b = staging_bytes(*pk, host_in, out_bytes, host_out);
+    const size_t need = stage_b + fggc_workspace_bytes(fa);
+    if (need > ctx->ws.capacity()) {
+      if (need > ctx->budget)
+        fail(FGGC_EBUDGET, "FGGC needs " + std::to_string(need) + " bytes, budget is " +
+                               std::to_string(ctx->budget));
+      ctx->ws.reserve(need, ctx->budget);
+      if (host_in) dpk = stage_packets(*pk, (char *)ctx->ws.take((size_t)pk->N * (2 * d + 3) * 8), s);
+    } else {
+      ctx->ws.reset();
+      if (host_in) (void)ctx->ws.take((size_t)pk->N * (2 * d + 3) * 8);
+    }
+    fa.pk = &dpk;
+    fa.u = host_out ? ctx->ws.take(out_bytes) : u_out;
+    fa.prof = ctx->profiling ? &ctx->prof : nullptr;
+    launch_fggc(fa, ctx->ws, s);
+    if (host_out) {
+      FGGC_HIP(hipMemcpyAsync(u_out, fa.u, out_bytes, hipMemcpyDeviceToHost, s));
+      FGGC_HIP(hipStreamSynchronize(s));
+    } else if (host_in) {
+      FGGC_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+int fggc_profile(fggc_ctx *ctx, int enable) {
+  return guarded("fggc_profile", [&] {
+    if (!ctx) fail(FGGC_EINVAL, "ctx is NULL");
+    Guard lock(ctx);
+    ctx->profiling = enable != 0;
+    if (enable < 0 || enable > 1) fail(FGGC_EINVAL, "enable must be 0 or 1");
+    ctx->prof.reset();
+  });
+}
+
+int fggc_stage_time(fggc_ctx *ctx, const char *stage, double *total_ms, int64_t *count) {
+  return guarded("fggc_stage_time", [&] {
+    if (!ctx || !stage || !total_ms || !count) fail(FGGC_EINVAL, "NULL argument");
+    Guard lock(ctx);
+    ctx->prof.query(stage, total_ms, count);
+  });
+}
+
+int fggc_fft(fggc_ctx *ctx, int d, const int64_t *n, int64_t batch, int direction, int precision,
+             void *data, void *stream) {
+  return guarded("fggc_fft", [&] {
+    if (!ctx || !n || !data) fail(FGGC_EINVAL, "NULL argument");
+    if (d < 1 || d > 3) fail(FGGC_EINVAL, "d must be 1, 2 or 3");
+    if (batch < 0) fail(FGGC_EINVAL, "batch must be >= 0");
+    if (direction != -1 && direction != 1) fail(FGGC_EINVAL, "direction must be -1 or +1");
+    if (precision != FGGC_FP32 && precision != FGGC_FP64) fail(FGGC_EINVAL, "bad precision");
+    const int64_t maxn = precision == FGGC_FP64 ? 8192 : 16384;
+    for (int k = 0; k < d; ++k)
+      if (!is_pow2(n[k]) || n[k] < 2 || n[k] > maxn)
+        fail(FGGC_EUNSUPPORTED, "FFT sizes must be powers of two in [2, " + std::to_string(maxn) + "]");
+    Guard lock(ctx);
+    hipStream_t s = (hipStream_t)stream;
+    if (!device_accessible(data)) fail(FGGC_EINVAL, "fggc_fft needs device memory");
+    if (batch == 0) return;
+    ctx->ws.reserve(fft_workspace_bytes(d, n, precision), ctx->budget);
+    launch_fft(d, n, batch, direction, precision, data, ctx->ws, s,
+               ctx->profiling ? &ctx->prof : nullptr, "fft");
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,204 @@
+// Internal declarations shared by the libfggc sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fggc.h"
+
+namespace fggc {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 6.28318530717958647692;
+
+// Internal failure, converted to an fggc_status at the ABI boundary.
+struct Error {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg);
+void set_last_error(const std::string &msg);
+
+#define FGGC_HIP(x)                                                                      \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      ::fggc::fail(FGGC_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+// Bump allocator over one growable device buffer.  Growing synchronises the
+// device (old contents are not kept); a call reserves everything it needs up
+// front, then carves.
+class Workspace {
+ public:
+  ~Workspace();
+  void reserve(size_t bytes, size_t budget);  // ensure capacity (may reallocate)
+  void reset() { used_ = 0; }
+  void *take(size_t bytes);                   // 256-byte aligned slice
+  size_t capacity() const { return cap_; }
+
+ private:
+  char *base_ = nullptr;
+  size_t cap_ = 0, used_ = 0;
+};
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Optional per-stage timing: HIP events recorded around each stage on the
+// stream it is launched on, read back when queried.
+class Profiler {
+ public:
+  ~Profiler();
+  void start(const char *stage, hipStream_t s);  // record a start event
+  void stop(const char *stage, hipStream_t s);   // record the matching end event
+  // accumulated milliseconds and launch count of one stage (synchronises its events)
+  void query(const std::string &stage, double *ms, int64_t *count);
+  void reset();
+  std::vector<std::string> stages();
+
+ private:
+  struct Pending {
+    std::string stage;
+    hipEvent_t a, b;
+  };
+  struct Acc {
+    double ms = 0;
+    int64_t count = 0;
+  };
+  void drain();
+  std::mutex mu_;
+  std::vector<Pending> pending_;
+  std::vector<std::pair<std::string, Acc>> acc_;
+  std::vector<std::pair<std::string, hipEvent_t>> open_;
+};
+
+// RAII stage scope: no-op when prof is null.
+struct StageScope {
+  Profiler *p;
+  const char *name;
+  hipStream_t s;
+  StageScope(Profiler *p_, const char *n, hipStream_t s_) : p(p_), name(n), s(s_) {
+    if (p) p->start(name, s);
+  }
+  ~StageScope() {
+    if (p) p->stop(name, s);
+  }
+};
+
+// --------------------------------------------------------------------------
+// plan (host): per-dimension least-squares data of the FGGC correction
+// --------------------------------------------------------------------------
+
+constexpr int kMaxN1 = 16;  // largest one-dimensional basis (nq * np)
+
+// Eigenpairs of the eps-free Gram matrix (3.22) of one dimension, with the
+// reciprocal eigenvalues already cut: A~^+ = V diag(inv) V^H.
+struct DimLsq {
+  int n1;
+  int dq[kMaxN1], dp[kMaxN1];
+  double Cq, Cp;
+  double V[2 * kMaxN1 * kMaxN1];  // [row][col] complex, columns are eigenvectors
+  double inv[kMaxN1];             // 1/lambda or 0 when cut
+};
+
+// Hermitian eigen-decomposition of a complex n x n matrix (cyclic Jacobi on
+// the real symmetric 2n x 2n embedding, FP64).  evals ascending, evecs
+// [n][n] complex columns.
+void hermitian_eig(int n, const double *A, double *evals, double *evecs);
+void build_dim_lsq(const fggc_strategy &st, int dim, double eps, DimLsq *out);
+
+// --------------------------------------------------------------------------
+// device-side parameter blocks (passed by value to kernels)
+// --------------------------------------------------------------------------
+
+// Packet record for the direct sum, one per packet, sorted by spatial bin.
+struct alignas(16) DsRec {
+  int32_t mq[3];    // nearest grid index per dimension
+  int32_t pad;
+  double delta[3];  // Q - x_mq (minimum image), |delta| <= dx/2
+  double phi0;      // phase at x_mq in revolutions, frac((S - P.delta)/(2 pi eps) + arg(scale a)/(2 pi))
+  double omega[3];  // phase step per grid point in revolutions, frac(P_d / (eps n_d))
+  double lnamp;     // log |scale a|
+};
+static_assert(sizeof(DsRec) == 80, "DsRec layout");
+
+struct GridGeom {
+  int d;
+  int64_t n[3];
+  double dx[3];
+};
+
+struct Box {
+  int64_t lo[3], n[3];
+};
+
+// --------------------------------------------------------------------------
+// launchers (defined in the .hip files)
+// --------------------------------------------------------------------------
+
+// Count of non-finite entries of Q, P, S, a into *bad (device int).
+void launch_validate(const fggc_packets &pk, int *bad, hipStream_t s);
+
+// Direct sum.  Returns after enqueuing; `ws` supplies scratch.
+struct DirectArgs {
+  const fggc_packets *pk;
+  double eps, R, scale;
+  GridGeom g;
+  Box box;  // output points (row-major over the box)
+  int precision;
+  void *u;  // device output
+  Profiler *prof = nullptr;
+};
+size_t direct_workspace_bytes(const DirectArgs &a);
+void launch_direct(const DirectArgs &a, Workspace &ws, hipStream_t s);
+
+// FGGC.
+struct FggcArgs {
+  const fggc_packets *pk;
+  double eps, scale;
+  GridGeom g;
+  int precision;
+  const DimLsq *lsq;  // [d]
+  int64_t Nq[3];
+  double dp[3];
+  int64_t slo[3], sn[3];  // p-cell box
+  double cK;              // band half-width in units of 1/sqrt(eps)
+  void *u;                // device output
+  Profiler *prof = nullptr;
+};
+size_t fggc_workspace_bytes(const FggcArgs &a);
+void launch_fggc(const FggcArgs &a, Workspace &ws, hipStream_t s);
+// Only the cell array (eq. 2.25) into `cells` (device).
+void launch_fggc_cells(const FggcArgs &a, void *cells, Workspace &ws, hipStream_t s);
+size_t fggc_cells_workspace_bytes(const FggcArgs &a);
+
+// p-cell box reduction: mins/maxs of floor(P/dp) per dim into dev[0..2], dev[3..5].
+void launch_pcell_range(const fggc_packets &pk, const double *dp, long long *dev, hipStream_t s);
+
+// Batched in-place d-dimensional FFT (powers of two).
+size_t fft_workspace_bytes(int d, const int64_t *n, int precision);
+void launch_fft(int d, const int64_t *n, int64_t batch, int direction, int precision, void *data,
+                Workspace &ws, hipStream_t s, Profiler *prof = nullptr, const char *stage = "fft");
+
+}  // namespace fggc
+
+// The context behind the opaque ABI handle.
+struct fggc_ctx {
+  int device = 0;
+  size_t budget = 0;
+  hipStream_t stream = nullptr;
+  fggc::Workspace ws;
+  int *dev_flag = nullptr;       // device scratch for validation
+  long long *dev_range = nullptr;
+  int *host_flag = nullptr;      // pinned
+  long long *host_range = nullptr;
+  bool profiling = false;
+  fggc::Profiler prof;
+  std::mutex mu;
+};

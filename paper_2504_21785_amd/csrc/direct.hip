@@ -1,0 +1,589 @@
+// Windowed direct sum of eq. (2.10): every packet evaluated at every grid
+// point within its window, on gfx950.
+//
+// Pipeline (all on the caller's stream):
+//   1. ds_prep     per packet: nearest grid index and offset, the phase at that
+//                  point and its per-step increment (revolutions, FP64, reduced
+//                  mod 1), log|scale a|, and a spatial bin key;
+//   2. radix sort  (hipCUB, stable) of packets by bin, then a gather of the
+//                  records into bin order and the bin start offsets;
+//   3. ds_kernel   gather: a workgroup owns a tile of output points and walks
+//                  the packets of the bins its tile can see.  Packet records
+//                  are wave-uniform and are read into scalar registers through
+//                  the scalar cache; each lane owns four points and accumulates
+//                  their sums.  Per point: the Gaussian and the window test in
+//                  FP32 with v_exp_f32, the phase from FP64 (one FMA per
+//                  dimension and v_fract_f64), then v_sin_f32 / v_cos_f32 on
+//                  the reduced revolution count; FP32 partial sums of at most 32
+//                  packets are flushed into FP64 accumulators.  The FP64 variant
+//                  does the same arithmetic in FP64 (OCML exp, sincospi).
+//   4. ds_reduce   sum of the per-chunk partial grids, conversion to the
+//                  output precision.
+#include <hipcub/hipcub.hpp>
+
+#include "common.h"
+
+namespace fggc {
+namespace {
+
+constexpr int kBlock = 256;  // 4 waves
+constexpr int kFlush = 32;   // packets per FP32 partial sum
+
+__device__ __forceinline__ int64_t floordiv(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+__device__ __forceinline__ int64_t imod(int64_t a, int64_t m) {
+  int64_t r = a % m;
+  return r < 0 ? r + m : r;
+}
+
+struct PrepParams {
+  int d;
+  int64_t N;
+  const double *Q, *P, *S, *a;
+  double eps, scale;
+  int64_t n[3];
+  double dx[3];
+  int64_t binw[3], nbin[3];
+};
+
+__global__ void ds_prep_kernel(PrepParams p, DsRec *__restrict__ rec, uint32_t *__restrict__ key,
+                               uint32_t *__restrict__ idx) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= p.N) return;
+  DsRec r;
+  r.pad = 0;
+  double pdelta = 0.0;
+  uint32_t bin = 0;
+  for (int k = 0; k < 3; ++k) {
+    r.mq[k] = 0;
+    r.delta[k] = 0.0;
+    r.omega[k] = 0.0;
+  }
+  for (int k = 0; k < p.d; ++k) {
+    const double q = p.Q[k * p.N + j];
+    // position measured from x_0 = -pi, wrapped into [0, 2 pi)
+    const double t = (q + kPi) - kTwoPi * floor((q + kPi) / kTwoPi);
+    const double m = rint(t / p.dx[k]);
+    const double delta = fma(-m, p.dx[k], t);  // Q - x_m, |delta| <= dx/2
+    int64_t mi = (int64_t)m;
+    if (mi >= p.n[k]) mi -= p.n[k];
+    r.mq[k] = (int32_t)mi;
+    r.delta[k] = delta;
+    const double Pk = p.P[k * p.N + j];
+    pdelta = fma(Pk, delta, pdelta);
+    const double w = Pk / (p.eps * (double)p.n[k]);  // P dx / (2 pi eps)
+    r.omega[k] = w - floor(w);
+    bin = bin * (uint32_t)p.nbin[k] + (uint32_t)(mi / p.binw[k]);
+  }
+  const double are = p.scale * p.a[2 * j], aim = p.scale * p.a[2 * j + 1];
+  r.lnamp = log(hypot(are, aim));
+  const double ph = (p.S[j] - pdelta) / (kTwoPi * p.eps) + atan2(aim, are) * (1.0 / kTwoPi);
+  r.phi0 = ph - floor(ph);
+  rec[j] = r;
+  key[j] = bin;
+  idx[j] = (uint32_t)j;
+}
+
+__global__ void gather_rec_kernel(int64_t N, const uint32_t *__restrict__ idx,
+                                  const DsRec *__restrict__ in, DsRec *__restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N) out[i] = in[idx[i]];
+}
+
+// start[b] = first position whose key >= b (keys sorted), b in [0, nbins]
+__global__ void bin_start_kernel(int64_t N, const uint32_t *__restrict__ keys, int64_t nbins,
+                                 int64_t *__restrict__ start) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b > nbins) return;
+  int64_t lo = 0, hi = N;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)keys[mid] < b) lo = mid + 1;
+    else hi = mid;
+  }
+  start[b] = lo;
+}
+
+// Lane / sub-tile / wave layout of a workgroup tile for each dimension count.
+// Each lane owns 4 points (sub-tiles); a wave covers L*S points per
+// dimension, a workgroup (4 waves) L*S*V.
+template <int D> struct Shape;
+template <> struct Shape<1> {
+  static constexpr int L[3] = {64, 1, 1}, S[3] = {4, 1, 1}, V[3] = {4, 1, 1};
+};
+template <> struct Shape<2> {
+  static constexpr int L[3] = {8, 8, 1}, S[3] = {2, 2, 1}, V[3] = {2, 2, 1};
+};
+template <> struct Shape<3> {
+  static constexpr int L[3] = {4, 4, 4}, S[3] = {1, 2, 2}, V[3] = {4, 1, 1};
+};
+
+struct DsParams {
+  const DsRec *rec;        // sorted by bin
+  const int64_t *start;    // [nbins + 1]
+  int64_t n[3], binw[3], nbin[3];
+  int64_t box_lo[3], box_n[3];
+  int64_t ntile[3];        // tiles per dimension over the box
+  int64_t W[3];            // window half-width in grid steps per dimension
+  double dx[3];
+  double R2;               // window radius squared
+  double gauss;            // -1/(2 eps)
+  int nchunk;
+  int lanewrap;            // grid too small for a wave span: wrap every lane
+  double *partial;         // [nchunk][prod box_n] complex FP64
+};
+
+template <int D, bool F64>
+__global__ __launch_bounds__(kBlock) void ds_kernel(DsParams p) {
+  using Sh = Shape<D>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+  // tile and chunk of this workgroup
+  int64_t tile = blockIdx.x, torg[3] = {0, 0, 0};
+  for (int k = D - 1; k >= 0; --k) {
+    torg[k] = p.box_lo[k] + (tile % p.ntile[k]) * (Sh::L[k] * Sh::S[k] * Sh::V[k]);
+    tile /= p.ntile[k];
+  }
+  int lw[3], ll[3];
+  {
+    int w = wave, l = lane;
+    for (int k = D - 1; k >= 0; --k) {
+      lw[k] = w % Sh::V[k];
+      w /= Sh::V[k];
+      ll[k] = l % Sh::L[k];
+      l /= Sh::L[k];
+    }
+  }
+  int64_t worg[3] = {0, 0, 0};  // wave origin (grid index)
+  for (int k = 0; k < D; ++k) worg[k] = torg[k] + lw[k] * (Sh::L[k] * Sh::S[k]);
+
+  // per-lane offsets of the 4 owned points from the wave origin, and the
+  // (wave-uniform) offsets of the 4 sub-tiles
+  float offf[4][3];
+  double offd[4][3];
+  int subo[4][3];
+  for (int s = 0; s < 4; ++s) {
+    int ss = s;
+    for (int k = D - 1; k >= 0; --k) {
+      int sk = ss % Sh::S[k];
+      ss /= Sh::S[k];
+      subo[s][k] = sk * Sh::L[k];
+      int o = sk * Sh::L[k] + ll[k];
+      offf[s][k] = (float)o;
+      offd[s][k] = (double)o;
+    }
+  }
+  int nn[3], hh[3], Wi[3];
+  for (int k = 0; k < 3; ++k) {
+    nn[k] = (int)p.n[k];
+    hh[k] = nn[k] / 2;
+    Wi[k] = (int)p.W[k];
+  }
+
+  // bins visible from the tile: grid points [torg - W, torg + span - 1 + W]
+  // per dimension, taken modulo n, as at most two bin intervals
+  int64_t ia[3][2], ic[3][2], ilen[3][2], bcount[3];
+  int nint[3];
+  for (int k = 0; k < 3; ++k) {
+    nint[k] = 1;
+    ia[k][0] = ic[k][0] = 0;
+    ilen[k][0] = 1;
+    ilen[k][1] = 0;
+    bcount[k] = 1;
+  }
+  for (int k = 0; k < D; ++k) {
+    const int64_t span = Sh::L[k] * Sh::S[k] * Sh::V[k];
+    const int64_t lo = torg[k] - p.W[k], hi = torg[k] + span - 1 + p.W[k];
+    const int64_t nk = p.n[k], nb = p.nbin[k], bw = p.binw[k];
+    if (hi - lo + 1 >= nk) {
+      nint[k] = 1;
+      ia[k][0] = 0;
+      ic[k][0] = nb - 1;
+    } else {
+      const int64_t lm = imod(lo, nk), hm = imod(hi, nk);
+      if (lm <= hm) {
+        nint[k] = 1;
+        ia[k][0] = lm / bw;
+        ic[k][0] = hm / bw;
+      } else if (hm / bw + 1 >= lm / bw) {
+        nint[k] = 1;  // the two pieces touch: every bin
+        ia[k][0] = 0;
+        ic[k][0] = nb - 1;
+      } else {
+        nint[k] = 2;
+        ia[k][0] = lm / bw;
+        ic[k][0] = nb - 1;
+        ia[k][1] = 0;
+        ic[k][1] = hm / bw;
+      }
+    }
+    ilen[k][0] = ic[k][0] - ia[k][0] + 1;
+    ilen[k][1] = nint[k] == 2 ? ic[k][1] - ia[k][1] + 1 : 0;
+    bcount[k] = ilen[k][0] + ilen[k][1];
+  }
+  // visible bins form rows (all but the last dimension), each holding at most
+  // two contiguous runs in bin order; count packets, then take this chunk.
+  int64_t nrows = 1;
+  for (int k = 0; k < D - 1; ++k) nrows *= bcount[k];
+  const int kl = D - 1;
+  int64_t total = 0;
+  auto row_base = [&](int64_t row) {
+    int64_t rr = row, idx[3] = {0, 0, 0};
+    for (int k = D - 2; k >= 0; --k) {
+      const int64_t r = rr % bcount[k];
+      rr /= bcount[k];
+      idx[k] = r < ilen[k][0] ? ia[k][0] + r : ia[k][1] + (r - ilen[k][0]);
+    }
+    int64_t b = 0;
+    for (int k = 0; k < D - 1; ++k) b = b * p.nbin[k] + idx[k];
+    return b * p.nbin[kl];
+  };
+  for (int64_t row = 0; row < nrows; ++row) {
+    const int64_t base = row_base(row);
+    for (int run = 0; run < nint[kl]; ++run)
+      total += p.start[base + ic[kl][run] + 1] - p.start[base + ia[kl][run]];
+  }
+  const int64_t v0 = total * blockIdx.y / p.nchunk, v1 = total * (blockIdx.y + 1) / p.nchunk;
+
+  // accumulators
+  float a32r[4] = {0, 0, 0, 0}, a32i[4] = {0, 0, 0, 0};
+  double a64r[4] = {0, 0, 0, 0}, a64i[4] = {0, 0, 0, 0};
+  int pending = 0;
+
+  const float R2f = (float)p.R2;
+  const float gl2 = (float)(p.gauss * 1.4426950408889634);  // -log2(e) / (2 eps)
+  float dxf[3];
+  for (int k = 0; k < 3; ++k) dxf[k] = (float)p.dx[k];
+
+  int64_t vbase = 0;
+  for (int64_t row = 0; row < nrows && vbase < v1; ++row) {
+    const int64_t base = row_base(row);
+    for (int run = 0; run < nint[kl]; ++run) {
+      const int64_t ca = ia[kl][run], cb = ic[kl][run] + 1;
+      const int64_t sa = p.start[base + ca], sb = p.start[base + cb];
+      const int64_t len = sb - sa;
+      int64_t lo = v0 - vbase, hi = v1 - vbase;
+      if (lo < 0) lo = 0;
+      if (hi > len) hi = len;
+      for (int64_t v = lo; v < hi; ++v) {
+        const DsRec &r = p.rec[sa + v];
+        // displacement (in grid steps) of the wave origin from the packet, minimum image
+        int kb[3];
+        bool vis = true;
+        for (int k = 0; k < D; ++k) {
+          int kv = (int)(worg[k] - r.mq[k]);  // in (-n, n + span)
+          while (kv >= nn[k] - hh[k]) kv -= nn[k];
+          while (kv < -hh[k]) kv += nn[k];
+          kb[k] = kv;
+          const int span = Sh::L[k] * Sh::S[k];
+          vis = vis && (kv <= Wi[k]) && (kv + span - 1 >= -Wi[k]);
+        }
+        if (p.lanewrap) {
+          // small grids: a wave span can wrap around the torus and come back
+          // inside the window, so every lane takes its own minimum image
+          for (int s = 0; s < 4; ++s) {
+            double y2 = 0.0, th = r.phi0;
+            for (int k = 0; k < D; ++k) {
+              int kk = kb[k] + subo[s][k] + ll[k];
+              if (kk >= nn[k] - hh[k]) kk -= nn[k];
+              const double y = fma((double)kk, p.dx[k], -r.delta[k]);
+              y2 = fma(y, y, y2);
+              th = fma((double)kk, r.omega[k], th);
+            }
+            if (y2 <= p.R2) {
+              const double g = exp(fma(y2, p.gauss, r.lnamp));
+              double sn, cs;
+              sincospi(2.0 * __builtin_amdgcn_fract(th), &sn, &cs);
+              a64r[s] = fma(g, cs, a64r[s]);
+              a64i[s] = fma(g, sn, a64i[s]);
+            }
+          }
+          continue;
+        }
+        if (!vis) continue;
+        if (F64) {
+          double thb = r.phi0;
+          for (int k = 0; k < D; ++k) thb = fma((double)kb[k], r.omega[k], thb);
+          for (int s = 0; s < 4; ++s) {
+            bool sv = true;
+            for (int k = 0; k < D; ++k)
+              sv = sv && (kb[k] + subo[s][k] <= Wi[k]) && (kb[k] + subo[s][k] + Sh::L[k] - 1 >= -Wi[k]);
+            if (!sv) continue;
+            double y2 = 0.0, th = thb;
+            for (int k = 0; k < D; ++k) {
+              const double y = fma((double)kb[k] + offd[s][k], p.dx[k], -r.delta[k]);
+              y2 = fma(y, y, y2);
+              th = fma(offd[s][k], r.omega[k], th);
+            }
+            if (y2 <= p.R2) {
+              const double g = exp(fma(y2, p.gauss, r.lnamp));
+              double sn, cs;
+              sincospi(2.0 * __builtin_amdgcn_fract(th), &sn, &cs);
+              a64r[s] = fma(g, cs, a64r[s]);
+              a64i[s] = fma(g, sn, a64i[s]);
+            }
+          }
+        } else {
+          double thb = r.phi0;
+          float kbf[3], dlf[3];
+          for (int k = 0; k < D; ++k) {
+            thb = fma((double)kb[k], r.omega[k], thb);
+            kbf[k] = (float)kb[k];
+            dlf[k] = (float)r.delta[k];
+          }
+          const float la2 = (float)(r.lnamp * 1.4426950408889634);
+          for (int s = 0; s < 4; ++s) {
+            bool sv = true;
+            for (int k = 0; k < D; ++k)
+              sv = sv && (kb[k] + subo[s][k] <= Wi[k]) && (kb[k] + subo[s][k] + Sh::L[k] - 1 >= -Wi[k]);
+            if (!sv) continue;
+            float y2 = 0.0f;
+            double th = thb;
+            for (int k = 0; k < D; ++k) {
+              const float y = fmaf(kbf[k] + offf[s][k], dxf[k], -dlf[k]);
+              y2 = fmaf(y, y, y2);
+              th = fma(offd[s][k], r.omega[k], th);
+            }
+            float g = __builtin_amdgcn_exp2f(fmaf(y2, gl2, la2));
+            g = (y2 <= R2f) ? g : 0.0f;
+            const float rv = (float)__builtin_amdgcn_fract(th);
+            a32r[s] = fmaf(g, __builtin_amdgcn_cosf(rv), a32r[s]);
+            a32i[s] = fmaf(g, __builtin_amdgcn_sinf(rv), a32i[s]);
+          }
+          if (++pending == kFlush) {
+            pending = 0;
+            for (int s = 0; s < 4; ++s) {
+              a64r[s] += (double)a32r[s];
+              a64i[s] += (double)a32i[s];
+              a32r[s] = 0.0f;
+              a32i[s] = 0.0f;
+            }
+          }
+        }
+      }
+      vbase += len;
+    }
+  }
+  if (!F64) {
+    for (int s = 0; s < 4; ++s) {
+      a64r[s] += (double)a32r[s];
+      a64i[s] += (double)a32i[s];
+    }
+  }
+  // write this chunk's partial sums for the owned points inside the box
+  int64_t npts = 1;
+  for (int k = 0; k < D; ++k) npts *= p.box_n[k];
+  double *out = p.partial + 2 * (int64_t)blockIdx.y * npts;
+  for (int s = 0; s < 4; ++s) {
+    bool inside = true;
+    int64_t flat = 0;
+    for (int k = 0; k < D; ++k) {
+      const int64_t rel = worg[k] + (int64_t)offd[s][k] - p.box_lo[k];
+      inside = inside && rel < p.box_n[k];
+      flat = flat * p.box_n[k] + rel;
+    }
+    if (inside) {
+      out[2 * flat] = a64r[s];
+      out[2 * flat + 1] = a64i[s];
+    }
+  }
+}
+
+template <bool F64>
+__global__ void ds_reduce_kernel(int64_t npts, int nchunk, const double *__restrict__ partial,
+                                 void *__restrict__ u) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= npts) return;
+  double re = 0.0, im = 0.0;
+  for (int c = 0; c < nchunk; ++c) {
+    re += partial[2 * (c * npts + i)];
+    im += partial[2 * (c * npts + i) + 1];
+  }
+  if (F64) {
+    reinterpret_cast<double2 *>(u)[i] = make_double2(re, im);
+  } else {
+    reinterpret_cast<float2 *>(u)[i] = make_float2((float)re, (float)im);
+  }
+}
+
+__global__ void validate_kernel(int d, int64_t N, const double *__restrict__ Q,
+                                const double *__restrict__ P, const double *__restrict__ S,
+                                const double *__restrict__ a, int *bad) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  // finite, and positions / momenta small enough for exact integer cell indices
+  bool ok = isfinite(S[j]) && isfinite(a[2 * j]) && isfinite(a[2 * j + 1]);
+  for (int k = 0; k < d; ++k)
+    ok = ok && fabs(Q[k * N + j]) <= 1.0e9 && fabs(P[k * N + j]) <= 1.0e9;
+  if (!ok) atomicAdd(bad, 1);
+}
+
+// layout of one direct-sum call's workspace
+struct DsLayout {
+  int D;
+  int64_t span[3], binw[3], nbin[3], ntile[3], W[3];
+  int64_t nbins, ntiles, npts;
+  int nchunk;
+  size_t off_rec, off_rec2, off_keys, off_keys2, off_idx, off_idx2, off_start, off_part, off_tmp,
+      tmp_bytes, total;
+};
+
+DsLayout ds_layout(const DirectArgs &a) {
+  DsLayout L{};
+  const int D = a.g.d;
+  L.D = D;
+  static const int sp1[3] = {1024, 1, 1}, sp2[3] = {32, 32, 1}, sp3[3] = {16, 8, 8};
+  const int *sp = D == 1 ? sp1 : (D == 2 ? sp2 : sp3);
+  L.nbins = 1;
+  L.ntiles = 1;
+  L.npts = 1;
+  for (int k = 0; k < 3; ++k) {
+    L.span[k] = k < D ? sp[k] : 1;
+    L.binw[k] = k < D ? std::max<int64_t>(1, L.span[k] / 2) : 1;
+    L.nbin[k] = k < D ? (a.g.n[k] + L.binw[k] - 1) / L.binw[k] : 1;
+    L.ntile[k] = k < D ? (a.box.n[k] + L.span[k] - 1) / L.span[k] : 1;
+    L.W[k] = k < D ? (int64_t)std::floor(a.R / a.g.dx[k]) + 1 : 0;
+    L.nbins *= L.nbin[k];
+    L.ntiles *= L.ntile[k];
+    L.npts *= k < D ? a.box.n[k] : 1;
+  }
+  // chunks: aim for >= 2048 workgroups, and >= ~512 candidate packets per chunk
+  double cand = (double)a.pk->N;
+  for (int k = 0; k < D; ++k)
+    cand *= std::min(1.0, (double)(L.span[k] + 2 * L.W[k] + 2 * L.binw[k]) / (double)a.g.n[k]);
+  int nc = (int)std::ceil(2048.0 / (double)L.ntiles);
+  nc = std::min(nc, (int)std::max(1.0, cand / 512.0));
+  L.nchunk = std::max(1, std::min(nc, 64));
+  size_t tmp = 0;
+  {
+    uint32_t *k = nullptr, *v = nullptr;
+    hipcub::DoubleBuffer<uint32_t> kb(k, k), vb(v, v);
+    int bits = 1;
+    while (((int64_t)1 << bits) < L.nbins) ++bits;
+    FGGC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, kb, vb, (int)std::max<int64_t>(a.pk->N, 1),
+                                                0, bits));
+  }
+  const int64_t N = std::max<int64_t>(a.pk->N, 1);
+  size_t o = 0;
+  auto put = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  L.off_rec = put(N * sizeof(DsRec));
+  L.off_rec2 = put(N * sizeof(DsRec));
+  L.off_keys = put(N * 4);
+  L.off_keys2 = put(N * 4);
+  L.off_idx = put(N * 4);
+  L.off_idx2 = put(N * 4);
+  L.off_start = put((L.nbins + 1) * 8);
+  L.off_part = put((size_t)L.nchunk * L.npts * 16);
+  L.tmp_bytes = tmp;
+  L.off_tmp = put(tmp + 256);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+void launch_validate(const fggc_packets &pk, int *bad, hipStream_t s) {
+  if (pk.N == 0) return;
+  const int64_t nb = (pk.N + 255) / 256;
+  validate_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(pk.d, pk.N, pk.Q, pk.P, pk.S, pk.a, bad);
+  FGGC_HIP(hipGetLastError());
+}
+
+size_t direct_workspace_bytes(const DirectArgs &a) { return ds_layout(a).total; }
+
+void launch_direct(const DirectArgs &a, Workspace &ws, hipStream_t s) {
+  const DsLayout L = ds_layout(a);
+  const bool f64 = a.precision == FGGC_FP64;
+  char *base = (char *)ws.take(L.total);
+  DsRec *rec = (DsRec *)(base + L.off_rec), *rec2 = (DsRec *)(base + L.off_rec2);
+  uint32_t *keys = (uint32_t *)(base + L.off_keys), *keys2 = (uint32_t *)(base + L.off_keys2);
+  uint32_t *idx = (uint32_t *)(base + L.off_idx), *idx2 = (uint32_t *)(base + L.off_idx2);
+  int64_t *start = (int64_t *)(base + L.off_start);
+  double *part = (double *)(base + L.off_part);
+  const int64_t N = a.pk->N;
+  if (N > 0) {
+    PrepParams pp{};
+    pp.d = L.D;
+    pp.N = N;
+    pp.Q = a.pk->Q;
+    pp.P = a.pk->P;
+    pp.S = a.pk->S;
+    pp.a = a.pk->a;
+    pp.eps = a.eps;
+    pp.scale = a.scale;
+    for (int k = 0; k < 3; ++k) {
+      pp.n[k] = k < L.D ? a.g.n[k] : 1;
+      pp.dx[k] = k < L.D ? a.g.dx[k] : 1.0;
+      pp.binw[k] = L.binw[k];
+      pp.nbin[k] = L.nbin[k];
+    }
+    {
+      StageScope sc(a.prof, "ds_prep", s);
+      ds_prep_kernel<<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s>>>(pp, rec, keys, idx);
+      FGGC_HIP(hipGetLastError());
+    }
+    {
+    StageScope sc_sort(a.prof, "ds_sort", s);
+    hipcub::DoubleBuffer<uint32_t> kb(keys, keys2), vb(idx, idx2);
+    int bits = 1;
+    while (((int64_t)1 << bits) < L.nbins) ++bits;
+    size_t tmp = L.tmp_bytes;
+    FGGC_HIP(hipcub::DeviceRadixSort::SortPairs(base + L.off_tmp, tmp, kb, vb, (int)N, 0, bits, s));
+    gather_rec_kernel<<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s>>>(N, vb.Current(), rec, rec2);
+    FGGC_HIP(hipGetLastError());
+    bin_start_kernel<<<dim3((unsigned)((L.nbins + 1 + 255) / 256)), dim3(256), 0, s>>>(
+        N, kb.Current(), L.nbins, start);
+    FGGC_HIP(hipGetLastError());
+    }
+  }
+  if (N > 0) {
+    DsParams p{};
+    p.rec = rec2;
+    p.start = start;
+    for (int k = 0; k < 3; ++k) {
+      p.n[k] = k < L.D ? a.g.n[k] : 1;
+      p.binw[k] = L.binw[k];
+      p.nbin[k] = L.nbin[k];
+      p.box_lo[k] = k < L.D ? a.box.lo[k] : 0;
+      p.box_n[k] = k < L.D ? a.box.n[k] : 1;
+      p.ntile[k] = L.ntile[k];
+      p.W[k] = L.W[k];
+      p.dx[k] = k < L.D ? a.g.dx[k] : 1.0;
+    }
+    p.R2 = a.R * a.R;
+    p.gauss = -1.0 / (2.0 * a.eps);
+    p.nchunk = L.nchunk;
+    p.partial = part;
+    p.lanewrap = 0;
+    for (int k = 0; k < L.D; ++k)
+      if (a.g.n[k] < 2 * L.W[k] + L.span[k] + 2) p.lanewrap = 1;
+    dim3 grid((unsigned)L.ntiles, (unsigned)L.nchunk);
+    {
+    StageScope sc(a.prof, "ds_kernel", s);
+#define FGGC_DS(DD)                                                                    \
+  if (f64) ds_kernel<DD, true><<<grid, dim3(kBlock), 0, s>>>(p);                      \
+  else ds_kernel<DD, false><<<grid, dim3(kBlock), 0, s>>>(p);
+    if (L.D == 1) { FGGC_DS(1) }
+    else if (L.D == 2) { FGGC_DS(2) }
+    else { FGGC_DS(3) }
+#undef FGGC_DS
+    FGGC_HIP(hipGetLastError());
+    }
+    StageScope sr(a.prof, "ds_reduce", s);
+    if (f64) ds_reduce_kernel<true><<<dim3((unsigned)((L.npts + 255) / 256)), dim3(256), 0, s>>>(
+        L.npts, L.nchunk, part, a.u);
+    else ds_reduce_kernel<false><<<dim3((unsigned)((L.npts + 255) / 256)), dim3(256), 0, s>>>(
+        L.npts, L.nchunk, part, a.u);
+    FGGC_HIP(hipGetLastError());
+  } else {
+    FGGC_HIP(hipMemsetAsync(a.u, 0, (size_t)L.npts * (f64 ? 16 : 8), s));
+  }
+}
+
+}  // namespace fggc

@@ -1,0 +1,233 @@
+// Batched complex FFT of power-of-two sizes, in place, in LDS: Stockham
+// autosort passes of radix 4 (and one radix 2 when log2 n is odd), one
+// workgroup per group of lines along one axis of a row-major array.  A
+// d-dimensional transform is d such axis passes.  Twiddles come from a
+// table exp(-2 pi i k / n) computed in FP64 on the host (rounded once to the
+// working precision) and kept per device for the life of the process.
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "common.h"
+
+namespace fggc {
+namespace {
+
+template <typename T> struct Real;
+template <> struct Real<float2> { using type = float; };
+template <> struct Real<double2> { using type = double; };
+
+template <typename T> __device__ __forceinline__ T cmul(T a, T b) {
+  return T{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __device__ __forceinline__ T cadd(T a, T b) { return T{a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ T csub(T a, T b) { return T{a.x - b.x, a.y - b.y}; }
+
+constexpr int kMaxBfly = 8;  // radix-4 butterflies per thread per pass
+
+struct FftAxis {
+  int64_t n, inner, nlines;
+  int log2n, lines;  // lines per workgroup
+  int inverse;
+};
+
+template <typename T>
+__global__ __launch_bounds__(1024) void fft_axis_kernel(T *__restrict__ data, FftAxis a,
+                                                        const T *__restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *sm = reinterpret_cast<T *>(smem_raw);
+  const int64_t n = a.n;
+  const int L = a.lines;
+  const int64_t line0 = (int64_t)blockIdx.x * L;
+  const int64_t tot = (int64_t)L * n;
+  // load (coalesced: along the line when lines are contiguous, across lines otherwise)
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+    int64_t l, i;
+    if (a.inner == 1) {
+      l = e / n;
+      i = e - l * n;
+    } else {
+      i = e / L;
+      l = e - i * L;
+    }
+    const int64_t line = line0 + l;
+    if (line < a.nlines) {
+      const int64_t bo = line / a.inner, bi = line - bo * a.inner;
+      sm[l * n + i] = data[(bo * n + i) * a.inner + bi];
+    }
+  }
+  __syncthreads();
+  int64_t Ns = 1;
+  int rem = a.log2n;
+  while (rem > 0) {
+    const int R = rem >= 2 ? 4 : 2;
+    const int64_t nb = (int64_t)L * (n / R);  // butterflies in this pass
+    const int64_t stride = n / R;
+    T v[kMaxBfly][4];
+#pragma unroll
+    for (int c = 0; c < kMaxBfly; ++c) {
+      const int64_t b = threadIdx.x + (int64_t)c * blockDim.x;
+      if (b >= nb) break;
+      const int64_t l = b / stride, j = b - l * stride;
+      const int64_t k = j % Ns;
+      const T *src = sm + l * n;
+      for (int r = 0; r < R; ++r) v[c][r] = src[j + r * stride];
+      // twiddles exp(-+ 2 pi i r k / (Ns R)) = tw[r k n / (Ns R)]
+      const int64_t tstep = k * (n / (Ns * R));
+      for (int r = 1; r < R; ++r) {
+        T w = tw[r * tstep];
+        if (a.inverse) w.y = -w.y;
+        v[c][r] = cmul(v[c][r], w);
+      }
+      if (R == 4) {
+        const T s0 = cadd(v[c][0], v[c][2]), d0 = csub(v[c][0], v[c][2]);
+        const T s1 = cadd(v[c][1], v[c][3]), d1 = csub(v[c][1], v[c][3]);
+        // forward: multiply d1 by -i; inverse: by +i
+        const T jd1 = a.inverse ? T{-d1.y, d1.x} : T{d1.y, -d1.x};
+        v[c][0] = cadd(s0, s1);
+        v[c][2] = csub(s0, s1);
+        v[c][1] = cadd(d0, jd1);
+        v[c][3] = csub(d0, jd1);
+      } else {
+        const T x0 = v[c][0], x1 = v[c][1];
+        v[c][0] = cadd(x0, x1);
+        v[c][1] = csub(x0, x1);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kMaxBfly; ++c) {
+      const int64_t b = threadIdx.x + (int64_t)c * blockDim.x;
+      if (b >= nb) break;
+      const int64_t l = b / stride, j = b - l * stride;
+      const int64_t k = j % Ns;
+      const int64_t idxD = (j / Ns) * Ns * R + k;
+      T *dst = sm + l * n;
+      for (int r = 0; r < R; ++r) dst[idxD + r * Ns] = v[c][r];
+    }
+    __syncthreads();
+    Ns *= R;
+    rem -= R == 4 ? 2 : 1;
+  }
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+    int64_t l, i;
+    if (a.inner == 1) {
+      l = e / n;
+      i = e - l * n;
+    } else {
+      i = e / L;
+      l = e - i * L;
+    }
+    const int64_t line = line0 + l;
+    if (line < a.nlines) {
+      const int64_t bo = line / a.inner, bi = line - bo * a.inner;
+      data[(bo * n + i) * a.inner + bi] = sm[l * n + i];
+    }
+  }
+}
+
+// twiddle tables, per (device, n, precision), created on first use
+std::mutex g_tw_mu;
+std::map<std::tuple<int, int64_t, int>, void *> g_tw;
+
+const void *twiddles(int64_t n, int precision) {
+  int dev = 0;
+  FGGC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_tw_mu);
+  auto key = std::make_tuple(dev, n, precision);
+  auto it = g_tw.find(key);
+  if (it != g_tw.end()) return it->second;
+  void *p = nullptr;
+  const size_t es = precision == FGGC_FP64 ? 16 : 8;
+  FGGC_HIP(hipMalloc(&p, (size_t)n * es));
+  std::vector<double> h(2 * (size_t)n);
+  for (int64_t k = 0; k < n; ++k) {
+    // exp(-2 pi i k/n), evaluated in long double and rounded once
+    const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)n;
+    h[2 * k] = (double)cosl(ang);
+    h[2 * k + 1] = (double)sinl(ang);
+  }
+  if (precision == FGGC_FP64) {
+    FGGC_HIP(hipMemcpy(p, h.data(), (size_t)n * 16, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(2 * (size_t)n);
+    for (size_t i = 0; i < f.size(); ++i) f[i] = (float)h[i];
+    FGGC_HIP(hipMemcpy(p, f.data(), (size_t)n * 8, hipMemcpyHostToDevice));
+  }
+  g_tw[key] = p;
+  return p;
+}
+
+template <typename T>
+void launch_axis(T *data, int64_t n, int64_t inner, int64_t outer, int inverse, hipStream_t s) {
+  const int64_t elem = sizeof(T);
+  const int64_t lds_max = (elem == 8 ? 16384 : 8192);  // elements (128 KB)
+  int log2n = 0;
+  while (((int64_t)1 << log2n) < n) ++log2n;
+  const int64_t nlines = inner * outer;
+  int64_t L;
+  if (inner == 1) {
+    L = std::max<int64_t>(1, std::min<int64_t>(4096 / n, lds_max / n));
+  } else {
+    L = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(64, inner), lds_max / n));
+  }
+  L = std::min(L, nlines);
+  const int R = log2n >= 2 ? 4 : 2;
+  int64_t bfly = L * (n / R);
+  int threads = (int)std::min<int64_t>(1024, std::max<int64_t>(64, (bfly + 3) / 4));
+  threads = (threads + 63) / 64 * 64;
+  while ((bfly + threads - 1) / threads > kMaxBfly) {
+    // keep per-thread butterflies within the register budget
+    if (threads < 1024) threads = std::min(1024, threads * 2);
+    else {
+      L = std::max<int64_t>(1, L / 2);
+      bfly = L * (n / R);
+    }
+  }
+  FftAxis a;
+  a.n = n;
+  a.inner = inner;
+  a.nlines = nlines;
+  a.log2n = log2n;
+  a.lines = (int)L;
+  a.inverse = inverse;
+  const T *tw = (const T *)twiddles(n, elem == 8 ? FGGC_FP32 : FGGC_FP64);
+  const size_t shm = (size_t)L * n * elem;
+  const int64_t nblocks = (nlines + L - 1) / L;
+  fft_axis_kernel<T><<<dim3((unsigned)nblocks), dim3(threads), shm, s>>>(data, a, tw);
+  FGGC_HIP(hipGetLastError());
+}
+
+bool g_attr_set = false;
+std::mutex g_attr_mu;
+
+void ensure_attrs() {
+  std::lock_guard<std::mutex> lk(g_attr_mu);
+  if (g_attr_set) return;
+  FGGC_HIP(hipFuncSetAttribute((const void *)fft_axis_kernel<float2>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+  FGGC_HIP(hipFuncSetAttribute((const void *)fft_axis_kernel<double2>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+  g_attr_set = true;
+}
+
+}  // namespace
+
+size_t fft_workspace_bytes(int, const int64_t *, int) { return 256; }
+
+void launch_fft(int d, const int64_t *n, int64_t batch, int direction, int precision, void *data,
+                Workspace &, hipStream_t s, Profiler *prof, const char *stage) {
+  ensure_attrs();
+  StageScope sc(prof, stage, s);
+  const int inverse = direction > 0 ? 1 : 0;
+  for (int k = d - 1; k >= 0; --k) {
+    int64_t inner = 1, outer = batch;
+    for (int j = k + 1; j < d; ++j) inner *= n[j];
+    for (int j = 0; j < k; ++j) outer *= n[j];
+    if (precision == FGGC_FP64) launch_axis<double2>((double2 *)data, n[k], inner, outer, inverse, s);
+    else launch_axis<float2>((float2 *)data, n[k], inner, outer, inverse, s);
+  }
+}
+
+}  // namespace fggc

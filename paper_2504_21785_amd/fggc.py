@@ -1,0 +1,363 @@
+"""ctypes binding of libfggc (argument marshalling only).
+
+Every step of the reconstruction runs in the HIP library; this module only
+turns torch tensors (device memory and streams) or numpy arrays (host memory)
+into the pointers and sizes of the C ABI declared in include/fggc.h, with the
+same names.  It raises when the library has not been built -- there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfggc.so")
+
+FGGC_OK = 0
+FGGC_EINVAL = -1
+FGGC_ENOMEM = -2
+FGGC_EBUDGET = -3
+FGGC_EUNSUPPORTED = -4
+FGGC_EDEVICE = -5
+FGGC_ECANCELLED = -6
+FGGC_ETIMEOUT = -7
+FP32 = 0
+FP64 = 1
+
+_STATUS = {0: "FGGC_OK", -1: "FGGC_EINVAL", -2: "FGGC_ENOMEM", -3: "FGGC_EBUDGET",
+           -4: "FGGC_EUNSUPPORTED", -5: "FGGC_EDEVICE", -6: "FGGC_ECANCELLED", -7: "FGGC_ETIMEOUT"}
+
+
+class FggcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("n", ctypes.c_int64 * 3)]
+
+
+class Packets(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("N", ctypes.c_int64), ("Q", ctypes.c_void_p),
+                ("P", ctypes.c_void_p), ("S", ctypes.c_void_p), ("a", ctypes.c_void_p)]
+
+
+class Strategy(ctypes.Structure):
+    _fields_ = [("Nq", ctypes.c_int64 * 3), ("dp", ctypes.c_double * 3), ("nq", ctypes.c_int32),
+                ("np", ctypes.c_int32), ("dq_off", ctypes.c_int32 * 8),
+                ("dp_off", ctypes.c_int32 * 8), ("cutoff", ctypes.c_double)]
+
+    def describe(self) -> dict:
+        return {"Nq": list(self.Nq), "dp": list(self.dp), "dq_off": list(self.dq_off[:self.nq]),
+                "dp_off": list(self.dp_off[:self.np]), "cutoff": self.cutoff}
+
+
+_lib = None
+
+# (name, restype, argtypes) of every function in include/fggc.h
+_VP, _I, _D, _I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
+_SIGS = [
+    ("fggc_create", _I, [ctypes.POINTER(_VP), _I, ctypes.c_size_t]),
+    ("fggc_destroy", None, [_VP]),
+    ("fggc_last_error", ctypes.c_char_p, []),
+    ("fggc_version", ctypes.c_char_p, []),
+    ("fggc_direct_sum", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid), _D, _D, _I, _VP, _VP]),
+    ("fggc_reconstruct", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid),
+                              ctypes.POINTER(Strategy), _D, _I, _VP, _VP]),
+    ("fggc_default_strategy", _I, [_I, _D, ctypes.c_char_p, ctypes.POINTER(Strategy)]),
+    ("fggc_cell_box", _I, [_VP, ctypes.POINTER(Packets), ctypes.POINTER(Strategy),
+                           ctypes.POINTER(_I64), ctypes.POINTER(_I64), _VP]),
+    ("fggc_cells", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Strategy), _D, _I,
+                        ctypes.POINTER(_I64), ctypes.POINTER(_I64), _VP, ctypes.c_size_t, _VP]),
+    ("fggc_fft", _I, [_VP, _I, ctypes.POINTER(_I64), _I64, _I, _I, _VP, _VP]),
+    ("fggc_plan_gram", _I, [_I, ctypes.POINTER(ctypes.c_int32), _I, ctypes.POINTER(ctypes.c_int32),
+                            _D, _D, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    ("fggc_profile", _I, [_VP, _I]),
+    ("fggc_stage_time", _I, [_VP, ctypes.c_char_p, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
+    ("fggc_server_create", _I, [_VP, _I, ctypes.POINTER(_VP)]),
+    ("fggc_server_submit", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid),
+                                ctypes.POINTER(Strategy), _D, _I, _VP, ctypes.POINTER(_I64)]),
+    ("fggc_server_wait", _I, [_VP, _I64, _D]),
+    ("fggc_server_stats", _I, [_VP, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D),
+                               ctypes.POINTER(_I64)]),
+    ("fggc_server_destroy", None, [_VP]),
+]
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libfggc.so not found at {LIB_PATH}: build it with "
+                               "`python -m paper_2504_21785_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().fggc_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != FGGC_OK:
+        raise FggcError(rc, last_error())
+
+
+def default_strategy(d: int, eps: float, name: str = "Q4P2") -> Strategy:
+    st = Strategy()
+    _check(lib().fggc_default_strategy(d, eps, name.encode(), ctypes.byref(st)))
+    return st
+
+
+def make_strategy(d: int, Nq: Sequence[int], dp: Sequence[float], dq_off: Sequence[int],
+                  dp_off: Sequence[int], cutoff: float = 0.0) -> Strategy:
+    st = Strategy()
+    for k in range(3):
+        st.Nq[k] = int(Nq[k]) if k < d else 1
+        st.dp[k] = float(dp[k]) if k < d else 1.0
+    st.nq, st.np = len(dq_off), len(dp_off)
+    for i, v in enumerate(dq_off):
+        st.dq_off[i] = int(v)
+    for i, v in enumerate(dp_off):
+        st.dp_off[i] = int(v)
+    st.cutoff = cutoff
+    return st
+
+
+def plan_gram(dq_off, dp_off, Cq: float, Cp: float):
+    """Eigenpairs of the one-dimensional Gram matrix (3.22) used by the plan."""
+    dq = (ctypes.c_int32 * len(dq_off))(*dq_off)
+    dpv = (ctypes.c_int32 * len(dp_off))(*dp_off)
+    n1 = len(dq_off) * len(dp_off)
+    ev = np.zeros(n1)
+    V = np.zeros((n1, n1), dtype=np.complex128)
+    _check(lib().fggc_plan_gram(len(dq_off), dq, len(dp_off), dpv, Cq, Cp,
+                                ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                V.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return ev, V
+
+
+def _grid(d: int, M) -> Grid:
+    g = Grid()
+    g.d = d
+    M = list(M) if hasattr(M, "__len__") else [int(M)] * d
+    for k in range(3):
+        g.n[k] = int(M[k]) if k < d else 1
+    return g
+
+
+def _ptr(x) -> int:
+    """Address of a torch tensor (any device) or a numpy array (host)."""
+    if x is None:
+        return 0
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        if not x.flags.c_contiguous:
+            raise ValueError("arrays must be C-contiguous")
+        return x.ctypes.data
+    raise TypeError(f"unsupported buffer type {type(x)}")
+
+
+def _packets(Q, P, S, a) -> Packets:
+    pk = Packets()
+    d = Q.shape[0]
+    pk.d = d
+    pk.N = int(S.shape[0])
+    pk.Q, pk.P, pk.S, pk.a = _ptr(Q), _ptr(P), _ptr(S), _ptr(a)
+    return pk
+
+
+def _as_real_view(a):
+    """complex128 tensor/array -> same memory (interleaved re, im)."""
+    return a
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:
+            pass
+        return None
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class Context:
+    """A libfggc context on one HIP device (fggc_create / fggc_destroy)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().fggc_create(ctypes.byref(h), device, hbm_budget_bytes))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fggc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- reconstruction -----------------------------------------------------
+    def direct_sum(self, Q, P, S, a, eps: float, M, window_radius: float, scale: float = 1.0,
+                   precision: int = FP32, out=None, stream=None):
+        """fggc_direct_sum.  Q, P: [d][N] float64; S: [N] float64; a: [N] complex128.
+
+        Buffers are torch tensors (on the GPU: device path, stream-ordered on
+        the current stream) or numpy arrays (host path, synchronous).  Returns
+        `out` (allocated like Q when None), shape = grid.
+        """
+        d = Q.shape[0]
+        g = _grid(d, M)
+        out = self._alloc_out(Q, g, precision, out)
+        pk = _packets(Q, P, S, a)
+        _check(lib().fggc_direct_sum(self.h, ctypes.byref(pk), float(eps), ctypes.byref(g),
+                                     float(window_radius), float(scale), int(precision),
+                                     _ptr(out), _stream_ptr(stream) if _on_device(Q) else None))
+        return out
+
+    def reconstruct(self, Q, P, S, a, eps: float, M, strategy: Strategy, scale: float = 1.0,
+                    precision: int = FP32, out=None, stream=None):
+        """fggc_reconstruct (FGGC); same buffer conventions as direct_sum."""
+        d = Q.shape[0]
+        g = _grid(d, M)
+        out = self._alloc_out(Q, g, precision, out)
+        pk = _packets(Q, P, S, a)
+        _check(lib().fggc_reconstruct(self.h, ctypes.byref(pk), float(eps), ctypes.byref(g),
+                                      ctypes.byref(strategy), float(scale), int(precision),
+                                      _ptr(out), _stream_ptr(stream) if _on_device(Q) else None))
+        return out
+
+    def cell_box(self, Q, P, S, a, strategy: Strategy, stream=None):
+        d = Q.shape[0]
+        pk = _packets(Q, P, S, a)
+        lo = (ctypes.c_int64 * 3)()
+        n = (ctypes.c_int64 * 3)()
+        _check(lib().fggc_cell_box(self.h, ctypes.byref(pk), ctypes.byref(strategy), lo, n,
+                                   _stream_ptr(stream) if _on_device(Q) else None))
+        return np.array(lo[:d]), np.array(n[:d])
+
+    def cells(self, Q, P, S, a, eps: float, strategy: Strategy, scale: float = 1.0,
+              precision: int = FP32, box=None, stream=None):
+        """fggc_cells: the dense cell array of eq. (2.25) as a numpy array [slices][q]."""
+        d = Q.shape[0]
+        if box is None:
+            box = self.cell_box(Q, P, S, a, strategy, stream)
+        lo, n = box
+        nq = int(np.prod([strategy.Nq[k] for k in range(d)]))
+        ns = int(np.prod(n))
+        dt = np.complex128 if precision == FP64 else np.complex64
+        out = np.zeros((ns, nq), dtype=dt)
+        pk = _packets(Q, P, S, a)
+        lo_c = (ctypes.c_int64 * 3)(*[int(v) for v in lo])
+        n_c = (ctypes.c_int64 * 3)(*[int(v) for v in n])
+        _check(lib().fggc_cells(self.h, ctypes.byref(pk), float(eps), ctypes.byref(strategy),
+                                float(scale), int(precision), lo_c, n_c, out.ctypes.data,
+                                out.nbytes, _stream_ptr(stream) if _on_device(Q) else None))
+        return out, np.asarray(lo), np.asarray(n)
+
+    def fft(self, data, dims: Sequence[int], batch: int, direction: int, precision: int = FP32,
+            stream=None):
+        """fggc_fft in place on a torch complex tensor on the device."""
+        nd = (ctypes.c_int64 * 3)(*[int(v) for v in list(dims) + [1] * (3 - len(dims))])
+        _check(lib().fggc_fft(self.h, len(dims), nd, int(batch), int(direction), int(precision),
+                              _ptr(data), _stream_ptr(stream)))
+        return data
+
+    def profile(self, enable: bool):
+        """fggc_profile: start (True) or stop (False) per-stage event timing; resets totals."""
+        _check(lib().fggc_profile(self.h, 1 if enable else 0))
+
+    def stage_time(self, stage: str):
+        """fggc_stage_time: (total milliseconds, launches) recorded for one stage."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().fggc_stage_time(self.h, stage.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    @staticmethod
+    def _alloc_out(like, g: Grid, precision: int, out):
+        shape = tuple(g.n[k] for k in range(g.d))
+        if out is not None:
+            return out
+        if hasattr(like, "device"):
+            import torch
+            dt = torch.complex128 if precision == FP64 else torch.complex64
+            return torch.empty(shape, dtype=dt, device=like.device)
+        return np.empty(shape, dtype=np.complex128 if precision == FP64 else np.complex64)
+
+
+def _on_device(x) -> bool:
+    return hasattr(x, "is_cuda") and x.is_cuda
+
+
+class Server:
+    """fggc_server_*: continuous-batching reconstruction service on one context."""
+
+    def __init__(self, ctx: Context, n_streams: int = 4):
+        h = ctypes.c_void_p()
+        _check(lib().fggc_server_create(ctx.h, n_streams, ctypes.byref(h)))
+        self.h = h
+        self.ctx = ctx
+        self._keep = {}
+
+    def submit(self, Q, P, S, a, eps: float, M, strategy: Optional[Strategy] = None,
+               scale: float = 1.0, precision: int = FP32):
+        """Submit host (numpy) packets; returns (ticket, output array filled on completion)."""
+        d = Q.shape[0]
+        g = _grid(d, M)
+        out = np.zeros(tuple(g.n[k] for k in range(d)),
+                       dtype=np.complex128 if precision == FP64 else np.complex64)
+        pk = _packets(Q, P, S, a)
+        t = ctypes.c_int64()
+        _check(lib().fggc_server_submit(self.h, ctypes.byref(pk), float(eps), ctypes.byref(g),
+                                        ctypes.byref(strategy) if strategy is not None else None,
+                                        float(scale), int(precision), out.ctypes.data,
+                                        ctypes.byref(t)))
+        self._keep[t.value] = out
+        return t.value, out
+
+    def wait(self, ticket: int, timeout_s: float = -1.0) -> int:
+        rc = lib().fggc_server_wait(self.h, ticket, float(timeout_s))
+        if rc != FGGC_ETIMEOUT:
+            self._keep.pop(ticket, None)
+        return rc
+
+    def stats(self):
+        p50, p99, pps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().fggc_server_stats(self.h, ctypes.byref(p50), ctypes.byref(p99),
+                                       ctypes.byref(pps), ctypes.byref(n)))
+        return {"p50_s": p50.value, "p99_s": p99.value, "packets_per_s": pps.value,
+                "completed": n.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fggc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,162 @@
+"""Direct sum on the GPU (through the C ABI) against the FP64 CPU oracle.
+
+Bars: FP64 path rel-L2 <= 1e-12 (and max-abs <= 1e-12 of max |u|); FP32
+path rel-L2 <= 1e-6 (the FP32 path's stated tolerance).  Full-size workloads
+are compared on sampled grid points the oracle evaluates one by one.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2504_21785_amd import fggc as F  # noqa: E402
+from paper_2504_21785_amd import workloads as W  # noqa: E402
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = F.Context(0)
+    yield c
+    c.close()
+
+
+def dev(ps):
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    return t(ps.Q), t(ps.P), t(ps.S), t(ps.a)
+
+
+def rel(u, ref):
+    return float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+
+
+def random_set(seed, d, N, p_mean=0.5, p_std=0.3, edge=False):
+    rng = np.random.default_rng(seed)
+    Q = rng.uniform(-math.pi, math.pi, (d, N))
+    if edge:  # packets right at the periodic seam, on both sides
+        e = N // 8
+        Q[:, :e] = -math.pi + rng.uniform(-1e-9, 1e-9, (d, e))
+        Q[:, e: 2 * e] = math.pi - rng.uniform(0, 1e-3, (d, e))
+    P = p_mean + p_std * rng.standard_normal((d, N))
+    S = rng.uniform(0, 2 * math.pi, N)
+    a = (rng.standard_normal(N) + 1j * rng.standard_normal(N)) * 0.5
+    return Q, P, S, a
+
+
+def run_direct(ctx, Q, P, S, a, eps, M, R, prec, scale=1.0):
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    out = ctx.direct_sum(t(Q), t(P), t(S), t(a), eps, M, R, scale=scale, precision=prec)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().reshape(-1).astype(np.complex128)
+
+
+def test_cfg0_fp64_full_grid(ctx, orc):
+    ps = W.config(0)
+    log("cfg0 fp64", ps.N, ps.M)
+    u = run_direct(ctx, ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R, F.FP64)
+    ref = orc.direct_sum(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R)
+    e = rel(u, ref)
+    log("cfg0 fp64 rel-L2", e, "max-abs/max", np.abs(u - ref).max() / np.abs(ref).max())
+    assert e <= 1e-12
+    assert np.abs(u - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_cfg0_fp32_full_grid(ctx, orc):
+    ps = W.config(0)
+    u = run_direct(ctx, ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R, F.FP32)
+    ref = orc.direct_sum(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R)
+    e = rel(u, ref)
+    log("cfg0 fp32 rel-L2", e)
+    assert e <= 1e-6
+
+
+@pytest.mark.parametrize("prec,tol", [(F.FP64, 1e-12), (F.FP32, 1e-6)])
+@pytest.mark.parametrize("d,M,N,eps", [
+    (1, (1000,), 777, 1.0 / 64),        # ragged tile, several tiles
+    (1, (64,), 50, 1.0 / 16),           # grid smaller than a tile, window ~ grid
+    (1, (3000,), 5000, 1.0 / 1024),
+    (2, (96, 80), 1500, 1.0 / 256),     # non-square, ragged 32x32 tiles
+    (2, (130, 64), 900, 1.0 / 64),
+    (3, (40, 36, 32), 400, 1.0 / 128),  # ragged 16x8x8 tiles
+])
+def test_small_sets_with_seams(ctx, orc, prec, tol, d, M, N, eps):
+    Q, P, S, a = random_set(7 + N, d, N, edge=True)
+    R = 6 * math.sqrt(eps)
+    log("small", d, M, N, eps, prec)
+    u = run_direct(ctx, Q, P, S, a, eps, M, R, prec, scale=0.37)
+    ref = orc.direct_sum(Q, P, S, a, eps, M, R, scale=0.37)
+    e = rel(u, ref)
+    log("  rel-L2", e)
+    assert e <= tol
+
+
+def test_empty_and_single(ctx, orc):
+    Q = np.zeros((1, 0)); P = np.zeros((1, 0)); S = np.zeros(0); a = np.zeros(0, complex)
+    u = run_direct(ctx, Q, P, S, a, 1 / 64, (256,), 0.75, F.FP32)
+    assert np.all(u == 0)
+    # one packet centred on a grid point: symmetric, peak = |a|
+    M = 256
+    Q = np.array([[-math.pi + 100 * 2 * math.pi / M]])
+    u = run_direct(ctx, Q, np.zeros((1, 1)), np.zeros(1), np.ones(1, complex), 1 / 64, (M,), 0.75, F.FP64)
+    assert abs(u[100] - 1) < 1e-15
+    assert np.allclose(u[101:120], u[99:80:-1], atol=1e-13)
+
+
+def test_host_buffers(ctx, orc):
+    Q, P, S, a = random_set(3, 1, 300)
+    out = ctx.direct_sum(Q, P, S, a, 1 / 64, (512,), 0.75, precision=F.FP64)
+    ref = orc.direct_sum(Q, P, S, a, 1 / 64, (512,), 0.75)
+    assert rel(out, ref) <= 1e-12
+
+
+def test_invalid_inputs(ctx):
+    Q, P, S, a = random_set(4, 1, 64)
+    Qn = Q.copy()
+    Qn[0, 5] = np.nan
+    with pytest.raises(F.FggcError) as ei:
+        ctx.direct_sum(Qn, P, S, a, 1 / 64, (256,), 0.75)
+    assert ei.value.code == F.FGGC_EINVAL
+    for eps, R in [(0.0, 0.5), (-1.0, 0.5), (1 / 64, math.pi), (1 / 64, 0.0)]:
+        with pytest.raises(F.FggcError) as ei:
+            ctx.direct_sum(Q, P, S, a, eps, (256,), R)
+        assert ei.value.code == F.FGGC_EINVAL
+    with pytest.raises(F.FggcError):
+        ctx.direct_sum(Q, P, S, a, 1 / 64, (0,), 0.5)
+
+
+def sample_points(M, n, seed):
+    rng = np.random.default_rng(seed)
+    tot = int(np.prod(M))
+    return np.sort(rng.choice(tot, n, replace=False))
+
+
+def test_cfg1_fp32_full_size_sampled(ctx, orc):
+    ps = W.config(1)
+    log("cfg1 fp32 direct", ps.N, ps.M)
+    u = run_direct(ctx, ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R, F.FP32)
+    pts = sample_points(ps.M, 384, 1)
+    ref = orc.direct_sum(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R, pts=pts)
+    e = rel(u[pts], ref)
+    log("cfg1 fp32 sampled rel-L2", e)
+    assert e <= 1e-6
+
+
+def test_cfg2_fp32_full_size_sampled(ctx, orc):
+    ps = W.config(2)
+    log("cfg2 fp32 direct", ps.N, ps.M)
+    u = run_direct(ctx, ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R, F.FP32)
+    # sample where the wave lives (|q| small) and elsewhere
+    pts = sample_points(ps.M, 192, 2)
+    ref = orc.direct_sum(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R, pts=pts)
+    e = rel(u[pts], ref)
+    log("cfg2 fp32 sampled rel-L2", e)
+    assert e <= 1e-6
