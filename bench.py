@@ -134,7 +134,7 @@ def main():
         if do_direct:
             step_direct()
     torch.cuda.synchronize()
-    stage_names = ["validate", "pcell_range", "fggc_zero", "fggc_coef_scatter", "fggc_fft_q",
+    stage_names = ["prepass", "fggc_sort", "fggc_coef", "fggc_accum", "fggc_fft_q",
                    "fggc_band_table", "fggc_band_mac", "fggc_ifft", "ds_prep", "ds_sort",
                    "ds_kernel", "ds_reduce"]
     stages = {}
@@ -159,10 +159,14 @@ def main():
     nq = int(np.prod([st.Nq[i] for i in range(d)]))
     cells_b = slices * nq * 8
     mpts = int(np.prod(ps.M))
+    n1 = int(st.nq * st.np)
+    rec_b = 16 * ((8 * d + 15) // 16) + d * (4 if n1 <= 4 else (8 if n1 <= 8 else 16)) * 8
     per_launch_bytes = {
-        # packets in, the dense cell array written once (hardware atomics add in L2)
-        "fggc_coef_scatter": ps.N * ((2 * d + 1) * 8 + 16) + cells_b,
-        "fggc_zero": cells_b,
+        # packets in (through the sort order), one coefficient record out per packet
+        "fggc_coef": ps.N * ((2 * d + 1) * 8 + 16 + 4 + rec_b),
+        # records in, the dense cell array written once
+        "fggc_accum": ps.N * rec_b + cells_b,
+        "fggc_sort": ps.N * (2 * d * 8 + 16),
         "fggc_fft_q": 2 * cells_b,          # read and write the cell array
         "fggc_band_mac": cells_b + mpts * 8,  # read the spectra, write the grid spectrum
         "fggc_ifft": 2 * mpts * 8,

@@ -221,8 +221,8 @@ int fggc_plan_gram(int nq, const int32_t *dq_off, int np, const int32_t *dp_off,
  * Per-stage timing for benchmarks.  With enable = 1 every later call on the
  * context records HIP events around each of its stages (on the stream the
  * stage runs on); enable = 0 stops recording.  Either resets the totals.
- * Stages: "validate", "pcell_range", "ds_prep", "ds_sort", "ds_kernel",
- * "ds_reduce", "fggc_zero", "fggc_coef_scatter", "fggc_fft_q",
+ * Stages: "prepass", "ds_prep", "ds_sort", "ds_kernel",
+ * "ds_reduce", "fggc_sort", "fggc_coef", "fggc_accum", "fggc_fft_q",
  * "fggc_band_table", "fggc_band_mac", "fggc_ifft", "fft".
  */
 int fggc_profile(fggc_ctx *ctx, int enable);

@@ -247,18 +247,19 @@ bool packets_on_host(const fggc_packets &pk) {
            device_accessible(pk.a));
 }
 
-// Non-finite check of device packets; synchronises the stream.
-void validate_finite(fggc_ctx *ctx, const fggc_packets &pk, hipStream_t s) {
+// Packet pre-pass (validity and, with dp, the p-cell range); one synchronisation.
+void prepass(fggc_ctx *ctx, const fggc_packets &pk, const double *dp, hipStream_t s) {
   if (pk.N == 0) return;
-  FGGC_HIP(hipMemsetAsync(ctx->dev_flag, 0, sizeof(int), s));
+  long long *out = ctx->dev_scan + packet_scan_bytes() / 8;
   {
-    StageScope sc(ctx->profiling ? &ctx->prof : nullptr, "validate", s);
-    launch_validate(pk, ctx->dev_flag, s);
+    StageScope sc(ctx->profiling ? &ctx->prof : nullptr, "prepass", s);
+    launch_packet_scan(pk, dp, ctx->dev_scan, out, s);
   }
-  FGGC_HIP(hipMemcpyAsync(ctx->host_flag, ctx->dev_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  FGGC_HIP(hipMemcpyAsync(ctx->host_scan, out, 8 * sizeof(long long), hipMemcpyDeviceToHost, s));
   FGGC_HIP(hipStreamSynchronize(s));
-  if (*ctx->host_flag != 0)
-    fail(FGGC_EINVAL, std::to_string(*ctx->host_flag) + " packet(s) with NaN or Inf in Q, P, S or a");
+  if (ctx->host_scan[0] != 0)
+    fail(FGGC_EINVAL, std::to_string(ctx->host_scan[0]) +
+                          " packet(s) with NaN/Inf in Q, P, S or a, or |Q| or |P| above 1e9");
 }
 
 void check_strategy(const fggc_strategy *st, int d) {
@@ -276,6 +277,12 @@ void check_strategy(const fggc_strategy *st, int d) {
   for (int i = 0; i < st->np; ++i)
     if (std::abs(st->dp_off[i]) > 64) fail(FGGC_EINVAL, "p shift out of range [-64, 64]");
   if (!(st->cutoff >= 0) || !(st->cutoff < 1)) fail(FGGC_EINVAL, "cutoff must be in [0, 1)");
+  {
+    int a = st->dq_off[0], b = st->dq_off[0], c = st->dp_off[0], e = st->dp_off[0];
+    for (int i = 1; i < st->nq; ++i) { a = std::min(a, st->dq_off[i]); b = std::max(b, st->dq_off[i]); }
+    for (int i = 1; i < st->np; ++i) { c = std::min(c, st->dp_off[i]); e = std::max(e, st->dp_off[i]); }
+    if (b - a > 31 || e - c > 31) fail(FGGC_EINVAL, "shift sets must span at most 31 cells");
+  }
   for (int k = 0; k < d; ++k) {
     if (st->Nq[k] < 4 || st->Nq[k] > 8192 || !is_pow2(st->Nq[k]))
       fail(FGGC_EUNSUPPORTED, "Nq must be a power of two in [4, 8192]");
@@ -283,25 +290,17 @@ void check_strategy(const fggc_strategy *st, int d) {
   }
 }
 
-// p-cell box of the packets (device reduction, one synchronisation).
+// p-cell box of the packets (from the pre-pass, which must have run with dp).
 void cell_box(fggc_ctx *ctx, const fggc_packets &pk, const fggc_strategy &st, int64_t *slo,
-              int64_t *sn, hipStream_t s) {
+              int64_t *sn) {
   if (pk.N == 0) fail(FGGC_EINVAL, "no packets");
-  double dp[3] = {st.dp[0], st.dp[1], st.dp[2]};
-  {
-    StageScope sc(ctx->profiling ? &ctx->prof : nullptr, "pcell_range", s);
-    launch_pcell_range(pk, dp, ctx->dev_range, s);
-  }
-  FGGC_HIP(hipMemcpyAsync(ctx->host_range, ctx->dev_range, 6 * sizeof(long long),
-                          hipMemcpyDeviceToHost, s));
-  FGGC_HIP(hipStreamSynchronize(s));
   int mn = st.dp_off[0], mx = st.dp_off[0];
   for (int i = 1; i < st.np; ++i) {
     mn = std::min(mn, st.dp_off[i]);
     mx = std::max(mx, st.dp_off[i]);
   }
   for (int k = 0; k < pk.d; ++k) {
-    const long long lo = ctx->host_range[k], hi = ctx->host_range[3 + k];
+    const long long lo = ctx->host_scan[1 + k], hi = ctx->host_scan[4 + k];
     if (hi < lo || lo < -((long long)1 << 40) || hi > ((long long)1 << 40))
       fail(FGGC_EINVAL, "momenta out of range for the p-mesh");
     slo[k] = lo + mn;
@@ -366,10 +365,8 @@ int fggc_create(fggc_ctx **out, int device, size_t hbm_budget_bytes) {
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
     try {
       FGGC_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-      FGGC_HIP(hipMalloc((void **)&c->dev_flag, 256));
-      c->dev_range = (long long *)((char *)c->dev_flag + 64);
-      FGGC_HIP(hipHostMalloc((void **)&c->host_flag, 256, hipHostMallocDefault));
-      c->host_range = (long long *)((char *)c->host_flag + 64);
+      FGGC_HIP(hipMalloc((void **)&c->dev_scan, packet_scan_bytes() + 256));
+      FGGC_HIP(hipHostMalloc((void **)&c->host_scan, 256, hipHostMallocDefault));
     } catch (...) {
       fggc_destroy(c);
       throw;
@@ -382,8 +379,8 @@ void fggc_destroy(fggc_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  if (ctx->dev_flag) (void)hipFree(ctx->dev_flag);
-  if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
+  if (ctx->dev_scan) (void)hipFree(ctx->dev_scan);
+  if (ctx->host_scan) (void)hipHostFree(ctx->host_scan);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -423,7 +420,7 @@ int fggc_direct_sum(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fgg
     ctx->ws.reserve(need, ctx->budget);
     if (host_in) dpk = stage_packets(*pk, (char *)ctx->ws.take((size_t)pk->N * (2 * pk->d + 3) * 8), s);
     da.u = host_out ? ctx->ws.take(out_bytes) : u_out;
-    validate_finite(ctx, dpk, s);
+    prepass(ctx, dpk, nullptr, s);
     launch_direct(da, ctx->ws, s);
     if (host_out) {
       FGGC_HIP(hipMemcpyAsync(u_out, da.u, out_bytes, hipMemcpyDeviceToHost, s));
@@ -447,9 +444,9 @@ int fggc_cell_box(fggc_ctx *ctx, const fggc_packets *pk, const fggc_strategy *st
     fggc_packets dpk = *pk;
     ctx->ws.reserve(staging_bytes(*pk, host_in, 0, false) + 256, ctx->budget);
     if (host_in) dpk = stage_packets(*pk, (char *)ctx->ws.take((size_t)pk->N * (2 * pk->d + 3) * 8), s);
-    validate_finite(ctx, dpk, s);
+    prepass(ctx, dpk, st->dp, s);
     int64_t lo[3], n[3];
-    cell_box(ctx, dpk, *st, lo, n, s);
+    cell_box(ctx, dpk, *st, lo, n);
     for (int k = 0; k < pk->d; ++k) {
       slice_lo[k] = lo[k];
       slice_n[k] = n[k];
@@ -496,11 +493,11 @@ int fggc_cells(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_str
                     ctx->budget);
     if (host_in) dpk = stage_packets(*pk, (char *)ctx->ws.take((size_t)pk->N * (2 * d + 3) * 8), s);
     void *cells = host_out ? ctx->ws.take(bytes) : cells_out;
-    validate_finite(ctx, dpk, s);
+    prepass(ctx, dpk, st->dp, s);
     // the box must hold every p-cell the packets touch
     if (dpk.N > 0) {
       int64_t lo[3], n[3];
-      cell_box(ctx, dpk, *st, lo, n, s);
+      cell_box(ctx, dpk, *st, lo, n);
       for (int k = 0; k < d; ++k)
         if (lo[k] < slo[k] || lo[k] + n[k] > slo[k] + sn[k])
           fail(FGGC_EINVAL, "slice box does not contain the packets' p-cells");
@@ -549,9 +546,9 @@ int fggc_reconstruct(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fg
       FGGC_HIP(hipStreamSynchronize(s));
       return;
     }
-    validate_finite(ctx, dpk, s);
+    prepass(ctx, dpk, st->dp, s);
     int64_t slo[3], sn[3];
-    cell_box(ctx, dpk, *st, slo, sn, s);
+    cell_box(ctx, dpk, *st, slo, sn);
     DimLsq lsq[3];
     for (int k = 0; k < d; ++k) build_dim_lsq(*st, k, eps, &lsq[k]);
     FggcArgs fa{};
@@ -616,7 +613,7 @@ int fggc_fft(fggc_ctx *ctx, int d, const int64_t *n, int64_t batch, int directio
     hipStream_t s = (hipStream_t)stream;
     if (!device_accessible(data)) fail(FGGC_EINVAL, "fggc_fft needs device memory");
     if (batch == 0) return;
-    ctx->ws.reserve(fft_workspace_bytes(d, n, precision), ctx->budget);
+    ctx->ws.reserve(fft_workspace_bytes(d, n, precision, batch), ctx->budget);
     launch_fft(d, n, batch, direction, precision, data, ctx->ws, s,
                ctx->profiling ? &ctx->prof : nullptr, "fft");
   });

@@ -105,6 +105,7 @@ struct DimLsq {
   double Cq, Cp;
   double V[2 * kMaxN1 * kMaxN1];  // [row][col] complex, columns are eigenvectors
   double inv[kMaxN1];             // 1/lambda or 0 when cut
+  double D[2 * kMaxN1];           // exp(-i Cq Cp dq_k dp_k / 2), the constant phase of (3.23)
 };
 
 // Hermitian eigen-decomposition of a complex n x n matrix (cyclic Jacobi on
@@ -120,13 +121,15 @@ void build_dim_lsq(const fggc_strategy &st, int dim, double eps, DimLsq *out);
 // Packet record for the direct sum, one per packet, sorted by spatial bin.
 struct alignas(16) DsRec {
   int32_t mq[3];    // nearest grid index per dimension
-  int32_t pad;
+  float la2;        // log2 |scale a| (FP32 path)
   double delta[3];  // Q - x_mq (minimum image), |delta| <= dx/2
   double phi0;      // phase at x_mq in revolutions, frac((S - P.delta)/(2 pi eps) + arg(scale a)/(2 pi))
   double omega[3];  // phase step per grid point in revolutions, frac(P_d / (eps n_d))
   double lnamp;     // log |scale a|
+  float deltaf[3];  // delta rounded to FP32 (FP32 path)
+  int32_t pad;
 };
-static_assert(sizeof(DsRec) == 80, "DsRec layout");
+static_assert(sizeof(DsRec) == 96, "DsRec layout");
 
 struct GridGeom {
   int d;
@@ -142,8 +145,19 @@ struct Box {
 // launchers (defined in the .hip files)
 // --------------------------------------------------------------------------
 
-// Count of non-finite entries of Q, P, S, a into *bad (device int).
-void launch_validate(const fggc_packets &pk, int *bad, hipStream_t s);
+// Pre-pass over the packets: out[0] = number of packets with NaN/Inf or
+// |Q|, |P| > 1e9; out[1..3] / out[4..6] = min / max of floor(P/dp) per
+// dimension (when dp != nullptr).  `part` holds packet_scan_bytes().
+size_t packet_scan_bytes();
+void launch_packet_scan(const fggc_packets &pk, const double *dp, long long *part, long long *out,
+                        hipStream_t s);
+
+// Stable counting sort of indices 0..N-1 by keys[i] in [0, nbins): order[]
+// grouped by key, start[b] first position of key b (start[nbins] = N).
+// `scratch` holds bucket_sort_bytes(N, nbins); keys may be overwritten.
+size_t bucket_sort_bytes(int64_t N, int64_t nbins);
+void bucket_sort(uint32_t *keys, int64_t N, int64_t nbins, uint32_t *order, int64_t *start,
+                 void *scratch, hipStream_t s);
 
 // Direct sum.  Returns after enqueuing; `ws` supplies scratch.
 struct DirectArgs {
@@ -178,13 +192,14 @@ void launch_fggc(const FggcArgs &a, Workspace &ws, hipStream_t s);
 void launch_fggc_cells(const FggcArgs &a, void *cells, Workspace &ws, hipStream_t s);
 size_t fggc_cells_workspace_bytes(const FggcArgs &a);
 
-// p-cell box reduction: mins/maxs of floor(P/dp) per dim into dev[0..2], dev[3..5].
-void launch_pcell_range(const fggc_packets &pk, const double *dp, long long *dev, hipStream_t s);
 
 // Batched in-place d-dimensional FFT (powers of two).
-size_t fft_workspace_bytes(int d, const int64_t *n, int precision);
+size_t fft_workspace_bytes(int d, const int64_t *n, int precision, int64_t batch);
 void launch_fft(int d, const int64_t *n, int64_t batch, int direction, int precision, void *data,
                 Workspace &ws, hipStream_t s, Profiler *prof = nullptr, const char *stage = "fft");
+// One d-dimensional FFT from src to dst (src may be overwritten).
+void launch_fft_to(int d, const int64_t *n, int direction, int precision, void *src, void *dst,
+                   Workspace &ws, hipStream_t s, Profiler *prof = nullptr, const char *stage = "fft");
 
 }  // namespace fggc
 
@@ -194,10 +209,8 @@ struct fggc_ctx {
   size_t budget = 0;
   hipStream_t stream = nullptr;
   fggc::Workspace ws;
-  int *dev_flag = nullptr;       // device scratch for validation
-  long long *dev_range = nullptr;
-  int *host_flag = nullptr;      // pinned
-  long long *host_range = nullptr;
+  long long *dev_scan = nullptr;  // device scratch of the packet pre-pass (+ its 8 results)
+  long long *host_scan = nullptr; // pinned copy of the 8 results
   bool profiling = false;
   fggc::Profiler prof;
   std::mutex mu;

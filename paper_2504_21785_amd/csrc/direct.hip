@@ -5,8 +5,8 @@
 //   1. ds_prep     per packet: nearest grid index and offset, the phase at that
 //                  point and its per-step increment (revolutions, FP64, reduced
 //                  mod 1), log|scale a|, and a spatial bin key;
-//   2. radix sort  (hipCUB, stable) of packets by bin, then a gather of the
-//                  records into bin order and the bin start offsets;
+//   2. bucket sort (stable counting sort in LDS, sort.hip) of packets by bin,
+//                  then a gather of the records into bin order;
 //   3. ds_kernel   gather: a workgroup owns a tile of output points and walks
 //                  the packets of the bins its tile can see.  Packet records
 //                  are wave-uniform and are read into scalar registers through
@@ -19,8 +19,6 @@
 //                  does the same arithmetic in FP64 (OCML exp, sincospi).
 //   4. ds_reduce   sum of the per-chunk partial grids, conversion to the
 //                  output precision.
-#include <hipcub/hipcub.hpp>
-
 #include "common.h"
 
 namespace fggc {
@@ -48,12 +46,12 @@ struct PrepParams {
   int64_t binw[3], nbin[3];
 };
 
-__global__ void ds_prep_kernel(PrepParams p, DsRec *__restrict__ rec, uint32_t *__restrict__ key,
-                               uint32_t *__restrict__ idx) {
+__global__ void ds_prep_kernel(PrepParams p, DsRec *__restrict__ rec, uint32_t *__restrict__ key) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= p.N) return;
   DsRec r;
   r.pad = 0;
+  for (int k = 0; k < 3; ++k) r.deltaf[k] = 0.0f;
   double pdelta = 0.0;
   uint32_t bin = 0;
   for (int k = 0; k < 3; ++k) {
@@ -71,6 +69,7 @@ __global__ void ds_prep_kernel(PrepParams p, DsRec *__restrict__ rec, uint32_t *
     if (mi >= p.n[k]) mi -= p.n[k];
     r.mq[k] = (int32_t)mi;
     r.delta[k] = delta;
+    r.deltaf[k] = (float)delta;
     const double Pk = p.P[k * p.N + j];
     pdelta = fma(Pk, delta, pdelta);
     const double w = Pk / (p.eps * (double)p.n[k]);  // P dx / (2 pi eps)
@@ -79,31 +78,17 @@ __global__ void ds_prep_kernel(PrepParams p, DsRec *__restrict__ rec, uint32_t *
   }
   const double are = p.scale * p.a[2 * j], aim = p.scale * p.a[2 * j + 1];
   r.lnamp = log(hypot(are, aim));
+  r.la2 = (float)(r.lnamp * 1.4426950408889634);
   const double ph = (p.S[j] - pdelta) / (kTwoPi * p.eps) + atan2(aim, are) * (1.0 / kTwoPi);
   r.phi0 = ph - floor(ph);
   rec[j] = r;
   key[j] = bin;
-  idx[j] = (uint32_t)j;
 }
 
 __global__ void gather_rec_kernel(int64_t N, const uint32_t *__restrict__ idx,
                                   const DsRec *__restrict__ in, DsRec *__restrict__ out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < N) out[i] = in[idx[i]];
-}
-
-// start[b] = first position whose key >= b (keys sorted), b in [0, nbins]
-__global__ void bin_start_kernel(int64_t N, const uint32_t *__restrict__ keys, int64_t nbins,
-                                 int64_t *__restrict__ start) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b > nbins) return;
-  int64_t lo = 0, hi = N;
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)keys[mid] < b) lo = mid + 1;
-    else hi = mid;
-  }
-  start[b] = lo;
 }
 
 // Lane / sub-tile / wave layout of a workgroup tile for each dimension count.
@@ -138,7 +123,10 @@ struct DsParams {
 template <int D, bool F64>
 __global__ __launch_bounds__(kBlock) void ds_kernel(DsParams p) {
   using Sh = Shape<D>;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  // the wave index is uniform across the wave: keep it (and all that derives
+  // from it) in scalar registers so that window tests branch on the SALU
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
   // tile and chunk of this workgroup
   int64_t tile = blockIdx.x, torg[3] = {0, 0, 0};
@@ -267,18 +255,31 @@ __global__ __launch_bounds__(kBlock) void ds_kernel(DsParams p) {
       int64_t lo = v0 - vbase, hi = v1 - vbase;
       if (lo < 0) lo = 0;
       if (hi > len) hi = len;
+      if (lo >= hi) {
+        vbase += len;
+        continue;
+      }
+      // software pipeline: the next record is requested before this one is used
+      DsRec nxt = p.rec[sa + lo];
       for (int64_t v = lo; v < hi; ++v) {
-        const DsRec &r = p.rec[sa + v];
+        const DsRec r = nxt;
+        nxt = p.rec[sa + (v + 1 < hi ? v + 1 : v)];
         // displacement (in grid steps) of the wave origin from the packet, minimum image
         int kb[3];
         bool vis = true;
         for (int k = 0; k < D; ++k) {
           int kv = (int)(worg[k] - r.mq[k]);  // in (-n, n + span)
-          while (kv >= nn[k] - hh[k]) kv -= nn[k];
-          while (kv < -hh[k]) kv += nn[k];
+          if (p.lanewrap) {
+            while (kv >= nn[k] - hh[k]) kv -= nn[k];
+            while (kv < -hh[k]) kv += nn[k];
+          } else {
+            // grids at least twice (tile span + window) wide: one correction suffices
+            if (kv < -hh[k]) kv += nn[k];
+            else if (kv >= nn[k] - hh[k]) kv -= nn[k];
+          }
           kb[k] = kv;
           const int span = Sh::L[k] * Sh::S[k];
-          vis = vis && (kv <= Wi[k]) && (kv + span - 1 >= -Wi[k]);
+          vis = vis && (unsigned)(kv + span - 1 + Wi[k]) < (unsigned)(2 * Wi[k] + span);
         }
         if (p.lanewrap) {
           // small grids: a wave span can wrap around the torus and come back
@@ -303,13 +304,13 @@ __global__ __launch_bounds__(kBlock) void ds_kernel(DsParams p) {
           continue;
         }
         if (!vis) continue;
+        double thb = r.phi0;
+        for (int k = 0; k < D; ++k) thb = fma((double)kb[k], r.omega[k], thb);
         if (F64) {
-          double thb = r.phi0;
-          for (int k = 0; k < D; ++k) thb = fma((double)kb[k], r.omega[k], thb);
           for (int s = 0; s < 4; ++s) {
             bool sv = true;
             for (int k = 0; k < D; ++k)
-              sv = sv && (kb[k] + subo[s][k] <= Wi[k]) && (kb[k] + subo[s][k] + Sh::L[k] - 1 >= -Wi[k]);
+              sv = sv && (unsigned)(kb[k] + subo[s][k] + Sh::L[k] - 1 + Wi[k]) < (unsigned)(2 * Wi[k] + Sh::L[k]);
             if (!sv) continue;
             double y2 = 0.0, th = thb;
             for (int k = 0; k < D; ++k) {
@@ -326,27 +327,21 @@ __global__ __launch_bounds__(kBlock) void ds_kernel(DsParams p) {
             }
           }
         } else {
-          double thb = r.phi0;
-          float kbf[3], dlf[3];
-          for (int k = 0; k < D; ++k) {
-            thb = fma((double)kb[k], r.omega[k], thb);
-            kbf[k] = (float)kb[k];
-            dlf[k] = (float)r.delta[k];
-          }
-          const float la2 = (float)(r.lnamp * 1.4426950408889634);
+          float kbf[3];
+          for (int k = 0; k < D; ++k) kbf[k] = (float)kb[k];
           for (int s = 0; s < 4; ++s) {
             bool sv = true;
             for (int k = 0; k < D; ++k)
-              sv = sv && (kb[k] + subo[s][k] <= Wi[k]) && (kb[k] + subo[s][k] + Sh::L[k] - 1 >= -Wi[k]);
+              sv = sv && (unsigned)(kb[k] + subo[s][k] + Sh::L[k] - 1 + Wi[k]) < (unsigned)(2 * Wi[k] + Sh::L[k]);
             if (!sv) continue;
             float y2 = 0.0f;
             double th = thb;
             for (int k = 0; k < D; ++k) {
-              const float y = fmaf(kbf[k] + offf[s][k], dxf[k], -dlf[k]);
+              const float y = fmaf(kbf[k] + offf[s][k], dxf[k], -r.deltaf[k]);
               y2 = fmaf(y, y, y2);
               th = fma(offd[s][k], r.omega[k], th);
             }
-            float g = __builtin_amdgcn_exp2f(fmaf(y2, gl2, la2));
+            float g = __builtin_amdgcn_exp2f(fmaf(y2, gl2, r.la2));
             g = (y2 <= R2f) ? g : 0.0f;
             const float rv = (float)__builtin_amdgcn_fract(th);
             a32r[s] = fmaf(g, __builtin_amdgcn_cosf(rv), a32r[s]);
@@ -408,26 +403,13 @@ __global__ void ds_reduce_kernel(int64_t npts, int nchunk, const double *__restr
   }
 }
 
-__global__ void validate_kernel(int d, int64_t N, const double *__restrict__ Q,
-                                const double *__restrict__ P, const double *__restrict__ S,
-                                const double *__restrict__ a, int *bad) {
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  // finite, and positions / momenta small enough for exact integer cell indices
-  bool ok = isfinite(S[j]) && isfinite(a[2 * j]) && isfinite(a[2 * j + 1]);
-  for (int k = 0; k < d; ++k)
-    ok = ok && fabs(Q[k * N + j]) <= 1.0e9 && fabs(P[k * N + j]) <= 1.0e9;
-  if (!ok) atomicAdd(bad, 1);
-}
-
 // layout of one direct-sum call's workspace
 struct DsLayout {
   int D;
   int64_t span[3], binw[3], nbin[3], ntile[3], W[3];
   int64_t nbins, ntiles, npts;
   int nchunk;
-  size_t off_rec, off_rec2, off_keys, off_keys2, off_idx, off_idx2, off_start, off_part, off_tmp,
-      tmp_bytes, total;
+  size_t off_rec, off_rec2, off_keys, off_order, off_start, off_part, off_sort, total;
 };
 
 DsLayout ds_layout(const DirectArgs &a) {
@@ -453,18 +435,12 @@ DsLayout ds_layout(const DirectArgs &a) {
   double cand = (double)a.pk->N;
   for (int k = 0; k < D; ++k)
     cand *= std::min(1.0, (double)(L.span[k] + 2 * L.W[k] + 2 * L.binw[k]) / (double)a.g.n[k]);
-  int nc = (int)std::ceil(2048.0 / (double)L.ntiles);
-  nc = std::min(nc, (int)std::max(1.0, cand / 512.0));
-  L.nchunk = std::max(1, std::min(nc, 64));
-  size_t tmp = 0;
-  {
-    uint32_t *k = nullptr, *v = nullptr;
-    hipcub::DoubleBuffer<uint32_t> kb(k, k), vb(v, v);
-    int bits = 1;
-    while (((int64_t)1 << bits) < L.nbins) ++bits;
-    FGGC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, kb, vb, (int)std::max<int64_t>(a.pk->N, 1),
-                                                0, bits));
-  }
+  // chunks: aim for ~8 waves per SIMD, >= ~256 candidate packets per chunk, and
+  // a partial-sum buffer of at most ~32 MB
+  int nc = (int)std::ceil(8192.0 / (double)L.ntiles);
+  nc = std::min(nc, (int)std::max(1.0, cand / 256.0));
+  nc = std::min<int64_t>(nc, std::max<int64_t>(1, ((int64_t)32 << 20) / (L.npts * 16)));
+  L.nchunk = std::max(1, std::min(nc, 512));
   const int64_t N = std::max<int64_t>(a.pk->N, 1);
   size_t o = 0;
   auto put = [&](size_t bytes) {
@@ -475,25 +451,15 @@ DsLayout ds_layout(const DirectArgs &a) {
   L.off_rec = put(N * sizeof(DsRec));
   L.off_rec2 = put(N * sizeof(DsRec));
   L.off_keys = put(N * 4);
-  L.off_keys2 = put(N * 4);
-  L.off_idx = put(N * 4);
-  L.off_idx2 = put(N * 4);
+  L.off_order = put(N * 4);
   L.off_start = put((L.nbins + 1) * 8);
   L.off_part = put((size_t)L.nchunk * L.npts * 16);
-  L.tmp_bytes = tmp;
-  L.off_tmp = put(tmp + 256);
+  L.off_sort = put(bucket_sort_bytes(a.pk->N, L.nbins));
   L.total = o;
   return L;
 }
 
 }  // namespace
-
-void launch_validate(const fggc_packets &pk, int *bad, hipStream_t s) {
-  if (pk.N == 0) return;
-  const int64_t nb = (pk.N + 255) / 256;
-  validate_kernel<<<dim3((unsigned)nb), dim3(256), 0, s>>>(pk.d, pk.N, pk.Q, pk.P, pk.S, pk.a, bad);
-  FGGC_HIP(hipGetLastError());
-}
 
 size_t direct_workspace_bytes(const DirectArgs &a) { return ds_layout(a).total; }
 
@@ -502,8 +468,7 @@ void launch_direct(const DirectArgs &a, Workspace &ws, hipStream_t s) {
   const bool f64 = a.precision == FGGC_FP64;
   char *base = (char *)ws.take(L.total);
   DsRec *rec = (DsRec *)(base + L.off_rec), *rec2 = (DsRec *)(base + L.off_rec2);
-  uint32_t *keys = (uint32_t *)(base + L.off_keys), *keys2 = (uint32_t *)(base + L.off_keys2);
-  uint32_t *idx = (uint32_t *)(base + L.off_idx), *idx2 = (uint32_t *)(base + L.off_idx2);
+  uint32_t *keys = (uint32_t *)(base + L.off_keys), *order = (uint32_t *)(base + L.off_order);
   int64_t *start = (int64_t *)(base + L.off_start);
   double *part = (double *)(base + L.off_part);
   const int64_t N = a.pk->N;
@@ -525,22 +490,13 @@ void launch_direct(const DirectArgs &a, Workspace &ws, hipStream_t s) {
     }
     {
       StageScope sc(a.prof, "ds_prep", s);
-      ds_prep_kernel<<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s>>>(pp, rec, keys, idx);
+      ds_prep_kernel<<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s>>>(pp, rec, keys);
       FGGC_HIP(hipGetLastError());
     }
-    {
     StageScope sc_sort(a.prof, "ds_sort", s);
-    hipcub::DoubleBuffer<uint32_t> kb(keys, keys2), vb(idx, idx2);
-    int bits = 1;
-    while (((int64_t)1 << bits) < L.nbins) ++bits;
-    size_t tmp = L.tmp_bytes;
-    FGGC_HIP(hipcub::DeviceRadixSort::SortPairs(base + L.off_tmp, tmp, kb, vb, (int)N, 0, bits, s));
-    gather_rec_kernel<<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s>>>(N, vb.Current(), rec, rec2);
+    bucket_sort(keys, N, L.nbins, order, start, base + L.off_sort, s);
+    gather_rec_kernel<<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s>>>(N, order, rec, rec2);
     FGGC_HIP(hipGetLastError());
-    bin_start_kernel<<<dim3((unsigned)((L.nbins + 1 + 255) / 256)), dim3(256), 0, s>>>(
-        N, kb.Current(), L.nbins, start);
-    FGGC_HIP(hipGetLastError());
-    }
   }
   if (N > 0) {
     DsParams p{};
@@ -562,7 +518,7 @@ void launch_direct(const DirectArgs &a, Workspace &ws, hipStream_t s) {
     p.partial = part;
     p.lanewrap = 0;
     for (int k = 0; k < L.D; ++k)
-      if (a.g.n[k] < 2 * L.W[k] + L.span[k] + 2) p.lanewrap = 1;
+      if (a.g.n[k] < 2 * (L.W[k] + L.span[k]) + 2) p.lanewrap = 1;
     dim3 grid((unsigned)L.ntiles, (unsigned)L.nchunk);
     {
     StageScope sc(a.prof, "ds_kernel", s);

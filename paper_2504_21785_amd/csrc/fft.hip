@@ -30,11 +30,14 @@ struct FftAxis {
   int64_t n, inner, nlines;
   int log2n, lines;  // lines per workgroup
   int inverse;
+  int transpose_out;  // lines are contiguous rows: store element i of line l at dst[i * nlines + l]
+  int64_t nbig;       // > 0: multiply output i of line (bo, bi) by exp(-+ 2 pi i bi i / nbig)
 };
 
 template <typename T>
-__global__ __launch_bounds__(1024) void fft_axis_kernel(T *__restrict__ data, FftAxis a,
-                                                        const T *__restrict__ tw) {
+__global__ __launch_bounds__(1024) void fft_axis_kernel(const T *src, T *dst, FftAxis a,
+                                                        const T *__restrict__ tw,
+                                                        const T *__restrict__ twbig) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sm = reinterpret_cast<T *>(smem_raw);
   const int64_t n = a.n;
@@ -54,7 +57,7 @@ __global__ __launch_bounds__(1024) void fft_axis_kernel(T *__restrict__ data, Ff
     const int64_t line = line0 + l;
     if (line < a.nlines) {
       const int64_t bo = line / a.inner, bi = line - bo * a.inner;
-      sm[l * n + i] = data[(bo * n + i) * a.inner + bi];
+      sm[l * n + i] = src[(bo * n + i) * a.inner + bi];
     }
   }
   __syncthreads();
@@ -112,7 +115,7 @@ __global__ __launch_bounds__(1024) void fft_axis_kernel(T *__restrict__ data, Ff
   }
   for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
     int64_t l, i;
-    if (a.inner == 1) {
+    if (a.inner == 1 && !a.transpose_out) {
       l = e / n;
       i = e - l * n;
     } else {
@@ -122,7 +125,14 @@ __global__ __launch_bounds__(1024) void fft_axis_kernel(T *__restrict__ data, Ff
     const int64_t line = line0 + l;
     if (line < a.nlines) {
       const int64_t bo = line / a.inner, bi = line - bo * a.inner;
-      data[(bo * n + i) * a.inner + bi] = sm[l * n + i];
+      T v = sm[l * n + i];
+      if (a.nbig > 0) {  // four-step twiddle exp(-+ 2 pi i bi i / nbig)
+        T w = twbig[(bi * i) % a.nbig];
+        if (a.inverse) w.y = -w.y;
+        v = cmul(v, w);
+      }
+      if (a.transpose_out) dst[i * a.nlines + line] = v;
+      else dst[(bo * n + i) * a.inner + bi] = v;
     }
   }
 }
@@ -160,18 +170,23 @@ const void *twiddles(int64_t n, int precision) {
 }
 
 template <typename T>
-void launch_axis(T *data, int64_t n, int64_t inner, int64_t outer, int inverse, hipStream_t s) {
+void launch_axis(const T *src, T *dst, int64_t n, int64_t inner, int64_t outer, int inverse,
+                 hipStream_t s, int transpose_out = 0, int64_t nbig = 0) {
   const int64_t elem = sizeof(T);
   const int64_t lds_max = (elem == 8 ? 16384 : 8192);  // elements (128 KB)
   int log2n = 0;
   while (((int64_t)1 << log2n) < n) ++log2n;
   const int64_t nlines = inner * outer;
   int64_t L;
-  if (inner == 1) {
+  if (inner == 1 && !transpose_out) {
     L = std::max<int64_t>(1, std::min<int64_t>(4096 / n, lds_max / n));
+  } else if (inner == 1) {
+    L = std::max<int64_t>(1, std::min<int64_t>(64, lds_max / n));
   } else {
     L = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(64, inner), lds_max / n));
   }
+  // keep at least ~256 workgroups when there are enough lines
+  L = std::min(L, std::max<int64_t>(1, nlines / 256));
   L = std::min(L, nlines);
   const int R = log2n >= 2 ? 4 : 2;
   int64_t bfly = L * (n / R);
@@ -192,11 +207,38 @@ void launch_axis(T *data, int64_t n, int64_t inner, int64_t outer, int inverse, 
   a.log2n = log2n;
   a.lines = (int)L;
   a.inverse = inverse;
+  a.transpose_out = transpose_out;
+  a.nbig = nbig;
   const T *tw = (const T *)twiddles(n, elem == 8 ? FGGC_FP32 : FGGC_FP64);
+  const T *twb = nbig > 0 ? (const T *)twiddles(nbig, elem == 8 ? FGGC_FP32 : FGGC_FP64) : tw;
   const size_t shm = (size_t)L * n * elem;
   const int64_t nblocks = (nlines + L - 1) / L;
-  fft_axis_kernel<T><<<dim3((unsigned)nblocks), dim3(threads), shm, s>>>(data, a, tw);
+  fft_axis_kernel<T><<<dim3((unsigned)nblocks), dim3(threads), shm, s>>>(src, dst, a, tw, twb);
   FGGC_HIP(hipGetLastError());
+}
+
+// d-dimensional transform of one array, src -> dst (src may be dst; src is
+// overwritten when the four-step form is used).  One-dimensional sizes above
+// 4096 go through the four-step form: column FFTs of the n1 x n2 view with
+// the twiddles folded into their store, then row FFTs stored transposed.
+template <typename T>
+void fft_one(int d, const int64_t *n, int inverse, T *src, T *dst, hipStream_t s) {
+  if (d == 1 && n[0] > 4096) {
+    int lg = 0;
+    while (((int64_t)1 << lg) < n[0]) ++lg;
+    const int64_t n1 = (int64_t)1 << (lg / 2), n2 = n[0] / n1;
+    launch_axis<T>(src, src, n1, n2, 1, inverse, s, 0, n[0]);  // columns, twiddled
+    launch_axis<T>(src, dst, n2, 1, n1, inverse, s, 1, 0);     // rows, stored transposed
+    return;
+  }
+  const T *in = src;
+  for (int k = d - 1; k >= 0; --k) {
+    int64_t inner = 1, outer = 1;
+    for (int j = k + 1; j < d; ++j) inner *= n[j];
+    for (int j = 0; j < k; ++j) outer *= n[j];
+    launch_axis<T>(in, dst, n[k], inner, outer, inverse, s);
+    in = dst;
+  }
 }
 
 bool g_attr_set = false;
@@ -214,20 +256,46 @@ void ensure_attrs() {
 
 }  // namespace
 
-size_t fft_workspace_bytes(int, const int64_t *, int) { return 256; }
+
+size_t fft_workspace_bytes(int d, const int64_t *n, int precision, int64_t batch) {
+  if (d == 1 && n[0] > 4096 && batch > 0)
+    return (size_t)n[0] * (precision == FGGC_FP64 ? 16 : 8) + 256;
+  return 256;
+}
 
 void launch_fft(int d, const int64_t *n, int64_t batch, int direction, int precision, void *data,
-                Workspace &, hipStream_t s, Profiler *prof, const char *stage) {
+                Workspace &ws, hipStream_t s, Profiler *prof, const char *stage) {
   ensure_attrs();
   StageScope sc(prof, stage, s);
   const int inverse = direction > 0 ? 1 : 0;
+  const size_t es = precision == FGGC_FP64 ? 16 : 8;
+  if (d == 1 && n[0] > 4096) {
+    // four-step per array, through a scratch copy
+    char *tmp = (char *)ws.take((size_t)n[0] * es);
+    for (int64_t b = 0; b < batch; ++b) {
+      char *x = (char *)data + (size_t)b * n[0] * es;
+      FGGC_HIP(hipMemcpyAsync(tmp, x, (size_t)n[0] * es, hipMemcpyDeviceToDevice, s));
+      if (precision == FGGC_FP64) fft_one<double2>(1, n, inverse, (double2 *)tmp, (double2 *)x, s);
+      else fft_one<float2>(1, n, inverse, (float2 *)tmp, (float2 *)x, s);
+    }
+    return;
+  }
   for (int k = d - 1; k >= 0; --k) {
     int64_t inner = 1, outer = batch;
     for (int j = k + 1; j < d; ++j) inner *= n[j];
     for (int j = 0; j < k; ++j) outer *= n[j];
-    if (precision == FGGC_FP64) launch_axis<double2>((double2 *)data, n[k], inner, outer, inverse, s);
-    else launch_axis<float2>((float2 *)data, n[k], inner, outer, inverse, s);
+    if (precision == FGGC_FP64) launch_axis<double2>((double2 *)data, (double2 *)data, n[k], inner, outer, inverse, s);
+    else launch_axis<float2>((float2 *)data, (float2 *)data, n[k], inner, outer, inverse, s);
   }
+}
+
+void launch_fft_to(int d, const int64_t *n, int direction, int precision, void *src, void *dst,
+                   Workspace &, hipStream_t s, Profiler *prof, const char *stage) {
+  ensure_attrs();
+  StageScope sc(prof, stage, s);
+  const int inverse = direction > 0 ? 1 : 0;
+  if (precision == FGGC_FP64) fft_one<double2>(d, n, inverse, (double2 *)src, (double2 *)dst, s);
+  else fft_one<float2>(d, n, inverse, (float2 *)src, (float2 *)dst, s);
 }
 
 }  // namespace fggc

@@ -1,12 +1,17 @@
 // Frozen Gaussian grid-point correction on gfx950 (Section 2.3, Alg. 2).
 //
-//   coef_scatter  one thread per packet, FP64: int/frac split (3.6)-(3.7) per
-//                 dimension, right-hand side (3.23), least squares through the
-//                 plan's eigenpairs (c^ = V diag(1/lambda) V^H f~), conjugation
-//                 to the L2-best coefficients, shift (3.13), Kronecker product
-//                 over dimensions, times scale a exp(i S/eps); the contributions
-//                 are added into the dense cell array of eq. (2.25) with
-//                 hardware float atomics (FP32 or FP64 cells).
+//   fggc_key      per packet: its own cell (int parts of eq. 3.6) -> bin key
+//                 (p-cell major, q-tile minor); radix sort of the packets by bin.
+//   fggc_coef     one thread per packet, in bin order, FP64: frac parts (3.7),
+//                 right-hand side (3.23), least squares through the plan's
+//                 eigenpairs (c^ = V diag(1/lambda) V^H f~), conjugation to the
+//                 L2-best coefficients, shift (3.13); the per-dimension
+//                 coefficients (the first times scale a exp(i S/eps)) are
+//                 written as one record per packet.
+//   fggc_accum    owner-computes form of eq. (2.23)-(2.25): one workgroup per
+//                 (p-slice, q-tile) of the dense cell array accumulates, in LDS,
+//                 the Kronecker products of every packet of the bins that reach
+//                 it, then writes each of its cells once.
 //   fft over q    forward DFT of every p-slice of the cell array (fft.hip).
 //   band_mac      owner-computes over the grid spectrum: for each frequency
 //                 k' of the M-point grid, the sum over slices l and aliases
@@ -16,6 +21,8 @@
 //                 G(x; q, p_l) of eq. (2.16) with q = 0, truncated to
 //                 |k_d - p_l,d/eps| <= cK / sqrt(eps); accumulated in FP64.
 //   inverse fft   of the M^d spectrum gives eq. (2.24) on the grid.
+#include <hipcub/hipcub.hpp>
+
 #include <cmath>
 
 #include "common.h"
@@ -33,67 +40,33 @@ __device__ __forceinline__ void int_frac(double v, int64_t &i, double &f) {
   }
 }
 
-__global__ void range_init_kernel(long long *r) {
-  if (threadIdx.x < 3) {
-    r[threadIdx.x] = 0x7fffffffffffffffLL;
-    r[3 + threadIdx.x] = -0x7fffffffffffffffLL - 1;
-  }
+// unit complex number exp(2 pi i rev), argument reduced in revolutions first
+__device__ __forceinline__ void cis_rev(double rev, double &c, double &s) {
+  sincospi(2.0 * (rev - rint(rev)), &s, &c);
 }
 
-__global__ void pcell_range_kernel(int d, int64_t N, const double *__restrict__ P, double dp0,
-                                   double dp1, double dp2, long long *r) {
-  __shared__ long long smin[3][256], smax[3][256];
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const double dp[3] = {dp0, dp1, dp2};
-  for (int k = 0; k < 3; ++k) {
-    long long mn = 0x7fffffffffffffffLL, mx = -0x7fffffffffffffffLL - 1;
-    if (k < d && j < N) {
-      int64_t ip;
-      double t;
-      const double w = P[k * N + j] / dp[k];
-      if (isfinite(w) && fabs(w) < 9.0e15) {
-        int_frac(w, ip, t);
-        mn = mx = ip;
-      } else {  // poisons the range so that the host rejects the request
-        mn = -0x7fffffffffffffffLL - 1;
-        mx = 0x7fffffffffffffffLL;
-      }
-    }
-    smin[k][threadIdx.x] = mn;
-    smax[k][threadIdx.x] = mx;
+// (c + i s)^n for a small integer n (|z| = 1, so z^-1 = conj z)
+__device__ __forceinline__ void cis_pow(double c, double s, int n, double &pc, double &ps) {
+  double xr = 1.0, xi = 0.0;
+  const int m = n < 0 ? -n : n;
+  for (int k = 0; k < m; ++k) {
+    const double t = xr * c - xi * s;
+    xi = xr * s + xi * c;
+    xr = t;
   }
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st)
-      for (int k = 0; k < 3; ++k) {
-        smin[k][threadIdx.x] = min(smin[k][threadIdx.x], smin[k][threadIdx.x + st]);
-        smax[k][threadIdx.x] = max(smax[k][threadIdx.x], smax[k][threadIdx.x + st]);
-      }
-    __syncthreads();
-  }
-  if (threadIdx.x < d) {
-    atomicMin(&r[threadIdx.x], smin[threadIdx.x][0]);
-    atomicMax(&r[3 + threadIdx.x], smax[threadIdx.x][0]);
-  }
+  pc = xr;
+  ps = n < 0 ? -xi : xi;
 }
-
-template <typename T>
-__global__ void fill_zero_kernel(T *__restrict__ p, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = T{0, 0};
-}
-
-struct CoefParams {
-  int64_t N;
-  const double *Q, *P, *S, *a;
-  double eps, scale;
-  const DimLsq *lsq;  // [d], device copy of the plan
-  int64_t Nq[3], slo[3], sn[3];
-  double dq[3], dp[3];
-};
 
 // per-dimension least-squares coefficients c_k (after conjugation and shift)
+//
+// With CC = Cq Cp, the right-hand side (3.23) factors as
+//   f~_ab = gq_a gp_b E0 Es^dp_b Et^dq_a D_ab,
+//   gq_a = exp(-Cq^2 (dq_a - s)^2 / 4), gp_b = exp(-Cp^2 (dp_b - t)^2 / 4),
+//   E0 = exp(i CC s t / 2), Es = exp(i CC s / 2), Et = exp(-i CC t / 2),
+//   D_ab = exp(-i CC dq_a dp_b / 2)  (a constant of the plan),
+// and the shift of (3.13) as exp(-i CC (s - dq_a) ip) = F0 Fi^dq_a with
+//   F0 = exp(-i CC s ip), Fi = exp(i CC ip).
 template <int N1>
 __device__ __forceinline__ void dim_coeffs(const DimLsq &L, double Q, double P, double dq, double dp,
                                            int64_t &iq, int64_t &ip, double cre[N1], double cim[N1]) {
@@ -102,19 +75,35 @@ __device__ __forceinline__ void dim_coeffs(const DimLsq &L, double Q, double P, 
   int_frac(P / dp, ip, t);
   const double Cq = L.Cq, Cp = L.Cp, CC = Cq * Cp;
   const int n1 = L.n1;
+  constexpr double inv2pi = 1.0 / kTwoPi;
+  double e0c, e0s, esc, ess, etc_, ets, f0c, f0s, fic, fis;
+  cis_rev(0.5 * CC * s * t * inv2pi, e0c, e0s);
+  cis_rev(0.5 * CC * s * inv2pi, esc, ess);
+  cis_rev(-0.5 * CC * t * inv2pi, etc_, ets);
+  {
+    const double w = CC * inv2pi * (double)ip;  // CC ip in revolutions
+    cis_rev(w, fic, fis);
+    cis_rev(-s * w, f0c, f0s);
+  }
   double fre[N1], fim[N1];
 #pragma unroll
   for (int j = 0; j < N1; ++j) {
     fre[j] = 0.0;
     fim[j] = 0.0;
     if (j < n1) {
-      // eq. (3.23)
       const double a = (double)L.dq[j] - s, b = (double)L.dp[j] - t;
       const double mag = exp(-0.25 * (Cq * Cq * a * a + Cp * Cp * b * b));
-      double sn, cs;
-      sincos(0.5 * CC * (s - (double)L.dq[j]) * ((double)L.dp[j] + t), &sn, &cs);
-      fre[j] = mag * cs;
-      fim[j] = mag * sn;
+      double pr, pi, qr, qi;
+      cis_pow(esc, ess, L.dp[j], pr, pi);
+      cis_pow(etc_, ets, L.dq[j], qr, qi);
+      // E0 * Es^dp * Et^dq * D
+      double xr = e0c * pr - e0s * pi, xi = e0c * pi + e0s * pr;
+      double yr = xr * qr - xi * qi, yi = xr * qi + xi * qr;
+      const double dr = L.D[2 * j], di = L.D[2 * j + 1];
+      xr = yr * dr - yi * di;
+      xi = yr * di + yi * dr;
+      fre[j] = mag * xr;
+      fim[j] = mag * xi;
     }
   }
   // z = diag(inv) V^H f
@@ -124,8 +113,8 @@ __device__ __forceinline__ void dim_coeffs(const DimLsq &L, double Q, double P, 
     double yr = 0.0, yi = 0.0;
 #pragma unroll
     for (int j = 0; j < N1; ++j) {
-      const double vr = L.V[2 * (j * n1 + i)], vi = L.V[2 * (j * n1 + i) + 1];
       if (i < n1 && j < n1) {
+        const double vr = L.V[2 * (j * n1 + i)], vi = L.V[2 * (j * n1 + i) + 1];
         // conj(V_ji) * f_j
         yr = fma(vr, fre[j], fma(vi, fim[j], yr));
         yi = fma(vr, fim[j], fma(-vi, fre[j], yi));
@@ -135,41 +124,91 @@ __device__ __forceinline__ void dim_coeffs(const DimLsq &L, double Q, double P, 
     zre[i] = yr * w;
     zim[i] = yi * w;
   }
-  // c^ = V z ; c~ = conj(c^) ; c = c~ exp(-i Cq Cp (s - dq_j) ip)
+  // c^ = V z ; c~ = conj(c^) ; c = c~ F0 Fi^dq
 #pragma unroll
   for (int j = 0; j < N1; ++j) {
     double hr = 0.0, hi = 0.0;
 #pragma unroll
     for (int i = 0; i < N1; ++i) {
-      const double vr = L.V[2 * (j * n1 + i)], vi = L.V[2 * (j * n1 + i) + 1];
       if (i < n1 && j < n1) {
+        const double vr = L.V[2 * (j * n1 + i)], vi = L.V[2 * (j * n1 + i) + 1];
         hr = fma(vr, zre[i], fma(-vi, zim[i], hr));
         hi = fma(vr, zim[i], fma(vi, zre[i], hi));
       }
     }
     const double tr = hr, ti = -hi;  // conjugate
-    double sn = 0.0, cs = 1.0;
+    double cs = 1.0, sn = 0.0;
     if (j < n1) {
-      // phase -Cq Cp (s - dq_j) ip in revolutions, reduced before sin/cos
-      const double rev = -CC * (s - (double)L.dq[j]) * (double)ip * (1.0 / kTwoPi);
-      sincospi(2.0 * (rev - rint(rev)), &sn, &cs);
+      double pr, pi;
+      cis_pow(fic, fis, L.dq[j], pr, pi);
+      cs = f0c * pr - f0s * pi;
+      sn = f0c * pi + f0s * pr;
     }
     cre[j] = tr * cs - ti * sn;
     cim[j] = tr * sn + ti * cs;
   }
 }
 
-template <int D, int N1, bool F64>
-__global__ __launch_bounds__(256) void coef_scatter_kernel(CoefParams p, void *__restrict__ cells_v) {
+// Sort key of a packet: its own p-cell (relative to the box of packet p-cells)
+// major, its q-tile minor.  Packets of one key form one bin.
+struct KeyParams {
+  int64_t N;
+  const double *Q, *P;
+  int64_t Nq[3], pmin[3], npc[3], tile[3], ntq[3];
+  double dq[3], dp[3];
+};
+
+template <int D>
+__global__ void fggc_key_kernel(KeyParams p, uint32_t *__restrict__ key) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= p.N) return;
+  int64_t kp = 0, kq = 0;
+  for (int k = 0; k < D; ++k) {
+    int64_t iq, ip;
+    double s, t;
+    int_frac(p.Q[k * p.N + j] / p.dq[k], iq, s);
+    int_frac(p.P[k * p.N + j] / p.dp[k], ip, t);
+    const int64_t qi = (iq + p.Nq[k] / 2) & (p.Nq[k] - 1);
+    kp = kp * p.npc[k] + (ip - p.pmin[k]);
+    kq = kq * p.ntq[k] + qi / p.tile[k];
+  }
+  int64_t nqt = 1;
+  for (int k = 0; k < D; ++k) nqt *= p.ntq[k];
+  key[j] = (uint32_t)(kp * nqt + kq);
+}
+
+// Record of one packet in bin order: its q index and p-cell (relative) per
+// dimension, then the per-dimension least-squares coefficients c_d[a*np+b]
+// (after conjugation and shift), the first dimension's multiplied by
+// scale * a exp(i S / eps).
+template <int D> struct RecIdx { int32_t q[D], pc[D]; };
+template <int D> __host__ __device__ constexpr int rec_idx_bytes() { return 16 * ((8 * D + 15) / 16); }
+template <int D, int N1, typename T> __host__ __device__ constexpr int rec_bytes() {
+  return rec_idx_bytes<D>() + D * N1 * (int)sizeof(T);
+}
+
+struct CoefParams {
+  int64_t N;
+  const double *Q, *P, *S, *a;
+  double eps, scale;
+  const DimLsq *lsq;  // [d], device copy of the plan
+  int64_t Nq[3], pmin[3];
+  double dq[3], dp[3];
+};
+
+template <int D, int N1, typename T>
+__global__ __launch_bounds__(256) void fggc_coef_kernel(CoefParams p, const uint32_t *__restrict__ order,
+                                                        char *__restrict__ recs) {
+  using R = decltype(T{}.x);
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= p.N) return;
+  const int64_t j = order[i];
   double cre[D][N1], cim[D][N1];
   int64_t iq[D], ip[D];
 #pragma unroll
   for (int k = 0; k < D; ++k)
     dim_coeffs<N1>(p.lsq[k], p.Q[k * p.N + j], p.P[k * p.N + j], p.dq[k], p.dp[k], iq[k], ip[k],
                    cre[k], cim[k]);
-  // alpha = scale a exp(i S / eps), phase reduced in revolutions
   double sn, cs;
   {
     const double rev = p.S[j] / (kTwoPi * p.eps);
@@ -177,69 +216,217 @@ __global__ __launch_bounds__(256) void coef_scatter_kernel(CoefParams p, void *_
   }
   const double ar = p.scale * p.a[2 * j], ai = p.scale * p.a[2 * j + 1];
   const double alr = ar * cs - ai * sn, ali = ar * sn + ai * cs;
-  const int n1 = p.lsq[0].n1;
-  // strides of the cell array and this packet's base indices per dimension
-  int64_t nqt = 1, sstr[3] = {0, 0, 0}, qstr[3] = {0, 0, 0}, sbase[3] = {0, 0, 0}, qbase[3] = {0, 0, 0},
-          qmask[3] = {0, 0, 0};
-  {
-    int64_t ss = 1, qs = 1;
-    for (int k = D - 1; k >= 0; --k) {
-      sstr[k] = ss;
-      qstr[k] = qs;
-      ss *= p.sn[k];
-      qs *= p.Nq[k];
-      sbase[k] = ip[k] - p.slo[k];
-      qbase[k] = iq[k] + p.Nq[k] / 2;
-      qmask[k] = p.Nq[k] - 1;  // Nq is a power of two
-    }
-    nqt = qs;
+  char *r = recs + i * (int64_t)rec_bytes<D, N1, T>();
+  RecIdx<D> ri;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    ri.q[k] = (int32_t)((iq[k] + p.Nq[k] / 2) & (p.Nq[k] - 1));
+    ri.pc[k] = (int32_t)(ip[k] - p.pmin[k]);
   }
-  auto emit = [&](double vr, double vi, int64_t sl, int64_t qi) {
-    const int64_t cell = sl * nqt + qi;
-    if (F64) {
-      double *c = (double *)cells_v + 2 * cell;
-      atomicAdd(c, vr);
-      atomicAdd(c + 1, vi);
+  *reinterpret_cast<RecIdx<D> *>(r) = ri;
+  T *c = reinterpret_cast<T *>(r + rec_idx_bytes<D>());
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+      double xr = cre[k][m], xi = cim[k][m];
+      if (k == 0) {
+        const double nr = alr * xr - ali * xi;
+        xi = alr * xi + ali * xr;
+        xr = nr;
+      }
+      c[k * N1 + m] = T{(R)xr, (R)xi};
+    }
+}
+
+// Owner-computes accumulation of eq. (2.25): one workgroup per (p-slice,
+// q-tile) of the cell array holds its cells in LDS, adds the contributions of
+// every packet of the bins that can reach it, and writes each of its cells
+// exactly once (no zeroing pass, no global atomics).
+struct AccParams {
+  const char *recs;
+  const int64_t *start;
+  int64_t sn[3], npc[3], Nq[3], tile[3], ntq[3];
+  int nq, np;
+  int dq[8], dp[8];
+  int mindp, maxdp, mindq, maxdq;
+  int bofs[32];  // dp value - mindp -> index b, or -1
+};
+
+template <int D, int N1, typename T>
+__global__ __launch_bounds__(256) void fggc_accum_kernel(AccParams p, T *__restrict__ cells) {
+  using R = decltype(T{}.x);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R *lre = reinterpret_cast<R *>(smem_raw);
+  int64_t tcells = 1, nqt_all = 1, ncell_q = 1;
+  for (int k = 0; k < D; ++k) {
+    tcells *= p.tile[k];
+    nqt_all *= p.ntq[k];
+    ncell_q *= p.Nq[k];
+  }
+  R *lim = lre + tcells;
+  for (int64_t e = threadIdx.x; e < tcells; e += blockDim.x) {
+    lre[e] = 0;
+    lim[e] = 0;
+  }
+  // which slice and q-tile this workgroup owns
+  int64_t blk = blockIdx.x, tq[3] = {0, 0, 0}, sl[3] = {0, 0, 0};
+  for (int k = D - 1; k >= 0; --k) {
+    tq[k] = blk % p.ntq[k];
+    blk /= p.ntq[k];
+  }
+  for (int k = D - 1; k >= 0; --k) {
+    sl[k] = blk % p.sn[k];
+    blk /= p.sn[k];
+  }
+  // packet p-cells that reach slice sl: pc in [sl + mindp - maxdp, sl], clipped
+  int64_t pc0[3], pcn[3];
+  // packet q bins that reach the tile: q in [t T - maxdq, t T + T - 1 - mindq] mod Nq
+  int64_t ia[3][2], ic[3][2], ilen[3][2];
+  int nint[3];
+  for (int k = 0; k < 3; ++k) {
+    pc0[k] = 0;
+    pcn[k] = 1;
+    nint[k] = 1;
+    ia[k][0] = ic[k][0] = 0;
+    ilen[k][0] = 1;
+    ilen[k][1] = 0;
+  }
+  for (int k = 0; k < D; ++k) {
+    int64_t a = sl[k] + p.mindp - p.maxdp, b = sl[k];
+    if (a < 0) a = 0;
+    if (b > p.npc[k] - 1) b = p.npc[k] - 1;
+    pc0[k] = a;
+    pcn[k] = b - a + 1;  // may be <= 0: nothing reaches this slice
+    const int64_t nk = p.Nq[k], bw = p.tile[k], nb = p.ntq[k];
+    const int64_t lo = tq[k] * bw - p.maxdq, hi = tq[k] * bw + bw - 1 - p.mindq;
+    if (hi - lo + 1 >= nk) {
+      ia[k][0] = 0;
+      ic[k][0] = nb - 1;
     } else {
-      float *c = (float *)cells_v + 2 * cell;
-      atomicAdd(c, (float)vr);
-      atomicAdd(c + 1, (float)vi);
-    }
-  };
-  const DimLsq &L0 = p.lsq[0];
-#pragma unroll
-  for (int a0 = 0; a0 < N1; ++a0) {
-    if (a0 >= n1) break;
-    const double v0r = alr * cre[0][a0] - ali * cim[0][a0];
-    const double v0i = alr * cim[0][a0] + ali * cre[0][a0];
-    const int64_t s0 = (sbase[0] + L0.dp[a0]) * sstr[0];
-    const int64_t q0 = ((qbase[0] + L0.dq[a0]) & qmask[0]) * qstr[0];
-    if (D == 1) {
-      emit(v0r, v0i, s0, q0);
-      continue;
-    }
-    const DimLsq &L1 = p.lsq[D > 1 ? 1 : 0];
-#pragma unroll
-    for (int a1 = 0; a1 < N1; ++a1) {
-      if (a1 >= n1) break;
-      const double v1r = v0r * cre[D > 1 ? 1 : 0][a1] - v0i * cim[D > 1 ? 1 : 0][a1];
-      const double v1i = v0r * cim[D > 1 ? 1 : 0][a1] + v0i * cre[D > 1 ? 1 : 0][a1];
-      const int64_t s1 = s0 + (sbase[1] + L1.dp[a1]) * sstr[1];
-      const int64_t q1 = q0 + ((qbase[1] + L1.dq[a1]) & qmask[1]) * qstr[1];
-      if (D == 2) {
-        emit(v1r, v1i, s1, q1);
-        continue;
-      }
-      const DimLsq &L2 = p.lsq[D > 2 ? 2 : 0];
-#pragma unroll
-      for (int a2 = 0; a2 < N1; ++a2) {
-        if (a2 >= n1) break;
-        const double v2r = v1r * cre[D > 2 ? 2 : 0][a2] - v1i * cim[D > 2 ? 2 : 0][a2];
-        const double v2i = v1r * cim[D > 2 ? 2 : 0][a2] + v1i * cre[D > 2 ? 2 : 0][a2];
-        emit(v2r, v2i, s1 + (sbase[2] + L2.dp[a2]) * sstr[2],
-             q1 + ((qbase[2] + L2.dq[a2]) & qmask[2]) * qstr[2]);
+      const int64_t lm = ((lo % nk) + nk) % nk, hm = ((hi % nk) + nk) % nk;
+      if (lm <= hm) {
+        ia[k][0] = lm / bw;
+        ic[k][0] = hm / bw;
+      } else if (hm / bw + 1 >= lm / bw) {
+        ia[k][0] = 0;
+        ic[k][0] = nb - 1;
+      } else {
+        nint[k] = 2;
+        ia[k][0] = lm / bw;
+        ic[k][0] = nb - 1;
+        ia[k][1] = 0;
+        ic[k][1] = hm / bw;
       }
     }
+    ilen[k][0] = ic[k][0] - ia[k][0] + 1;
+    ilen[k][1] = nint[k] == 2 ? ic[k][1] - ia[k][1] + 1 : 0;
+  }
+  bool any = true;
+  for (int k = 0; k < D; ++k) any = any && pcn[k] > 0;
+  __syncthreads();
+  if (any) {
+    // enumerate packet p-cells x q-bin rows (all q dims but the last), runs in the last q dim
+    int64_t npcs = 1, nqrows = 1, qcnt[3];
+    for (int k = 0; k < D; ++k) {
+      npcs *= pcn[k];
+      qcnt[k] = ilen[k][0] + ilen[k][1];
+    }
+    for (int k = 0; k < D - 1; ++k) nqrows *= qcnt[k];
+    const int kl = D - 1;
+    constexpr int RB = rec_bytes<D, N1, T>();
+    for (int64_t pcv = 0; pcv < npcs; ++pcv) {
+      int64_t rem = pcv, pcf = 0, pcs[3];
+      for (int k = D - 1; k >= 0; --k) {
+        pcs[k] = pc0[k] + rem % pcn[k];
+        rem /= pcn[k];
+      }
+      for (int k = 0; k < D; ++k) pcf = pcf * p.npc[k] + pcs[k];
+      // the basis index b per dimension that lands this p-cell on the slice
+      // (slice = pc + dp - mindp, so dp - mindp = slice - pc)
+      int bsel[3];
+      for (int k = 0; k < D; ++k) bsel[k] = p.bofs[(int)(sl[k] - pcs[k])];
+      for (int64_t row = 0; row < nqrows; ++row) {
+        int64_t rr = row, qb = 0, qidx[3] = {0, 0, 0};
+        for (int k = D - 2; k >= 0; --k) {
+          const int64_t r0 = rr % qcnt[k];
+          rr /= qcnt[k];
+          qidx[k] = r0 < ilen[k][0] ? ia[k][0] + r0 : ia[k][1] + (r0 - ilen[k][0]);
+        }
+        for (int k = 0; k < D - 1; ++k) qb = qb * p.ntq[k] + qidx[k];
+        for (int run = 0; run < nint[kl]; ++run) {
+          const int64_t b0 = (pcf * nqt_all) + qb * p.ntq[kl] + ia[kl][run];
+          const int64_t b1 = (pcf * nqt_all) + qb * p.ntq[kl] + ic[kl][run] + 1;
+          const int64_t s0 = p.start[b0], s1 = p.start[b1];
+          for (int64_t r = s0 + threadIdx.x; r < s1; r += blockDim.x) {
+            const char *rec = p.recs + r * (int64_t)RB;
+            const RecIdx<D> ri = *reinterpret_cast<const RecIdx<D> *>(rec);
+            const T *c = reinterpret_cast<const T *>(rec + rec_idx_bytes<D>());
+            // local q offsets of this packet's neighbours inside the tile
+            int lq[3][8];
+            for (int k = 0; k < D; ++k)
+              for (int a = 0; a < 8; ++a) {
+                lq[k][a] = -1;
+                if (a < p.nq) {
+                  const int64_t qv = (ri.q[k] + p.dq[a] - tq[k] * p.tile[k] + 2 * p.Nq[k]) & (p.Nq[k] - 1);
+                  if (qv < p.tile[k]) lq[k][a] = (int)qv;
+                }
+              }
+            if (D == 1) {
+              for (int a0 = 0; a0 < p.nq; ++a0) {
+                if (lq[0][a0] < 0) continue;
+                const T v = c[a0 * p.np + bsel[0]];
+                atomicAdd(&lre[lq[0][a0]], v.x);
+                atomicAdd(&lim[lq[0][a0]], v.y);
+              }
+            } else if (D == 2) {
+              for (int a0 = 0; a0 < p.nq; ++a0) {
+                if (lq[0][a0] < 0) continue;
+                const T u = c[a0 * p.np + bsel[0]];
+                for (int a1 = 0; a1 < p.nq; ++a1) {
+                  if (lq[1][a1] < 0) continue;
+                  const T w = c[N1 + a1 * p.np + bsel[1]];
+                  const int64_t li = lq[0][a0] * p.tile[1] + lq[1][a1];
+                  atomicAdd(&lre[li], u.x * w.x - u.y * w.y);
+                  atomicAdd(&lim[li], u.x * w.y + u.y * w.x);
+                }
+              }
+            } else {
+              for (int a0 = 0; a0 < p.nq; ++a0) {
+                if (lq[0][a0] < 0) continue;
+                const T u = c[a0 * p.np + bsel[0]];
+                for (int a1 = 0; a1 < p.nq; ++a1) {
+                  if (lq[1][a1] < 0) continue;
+                  const T w1 = c[N1 + a1 * p.np + bsel[1]];
+                  const R ur = u.x * w1.x - u.y * w1.y, ui = u.x * w1.y + u.y * w1.x;
+                  for (int a2 = 0; a2 < p.nq; ++a2) {
+                    if (lq[2][a2] < 0) continue;
+                    const T w2 = c[2 * N1 + a2 * p.np + bsel[2]];
+                    const int64_t li = (lq[0][a0] * p.tile[1] + lq[1][a1]) * p.tile[2] + lq[2][a2];
+                    atomicAdd(&lre[li], ur * w2.x - ui * w2.y);
+                    atomicAdd(&lim[li], ur * w2.y + ui * w2.x);
+                  }
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // write the tile: every cell of the array is owned by exactly one workgroup
+  int64_t slf = 0;
+  for (int k = 0; k < D; ++k) slf = slf * p.sn[k] + sl[k];
+  T *dst = cells + slf * ncell_q;
+  for (int64_t e = threadIdx.x; e < tcells; e += blockDim.x) {
+    int64_t rem = e, q = 0, lo[3];
+    for (int k = D - 1; k >= 0; --k) {
+      lo[k] = rem % p.tile[k];
+      rem /= p.tile[k];
+    }
+    for (int k = 0; k < D; ++k) q = q * p.Nq[k] + tq[k] * p.tile[k] + lo[k];
+    dst[q] = T{lre[e], lim[e]};
   }
 }
 
@@ -378,37 +565,68 @@ __global__ __launch_bounds__(256) void band_mac_kernel(MacParams m, const T *__r
 }
 
 struct FggcLayout {
-  int64_t ncells, nslices, npts;
+  int d, N1, rec_b;
+  int64_t ncells, nslices, npts, nbins, tiles, ntq[3], tile[3], npc[3], pmin[3];
   int64_t nb[3], toff[3], koff[3], ntab, nkst;
-  size_t off_lsq, off_cells, off_gam, off_kst, total;
+  int mindp, maxdp, mindq, maxdq;
+  size_t off_lsq, off_keys, off_order, off_sort, off_start, off_recs, off_cells, off_gam, off_kst,
+      off_spec, total;
 };
+
+int n1_bucket(int n1) { return n1 <= 4 ? 4 : (n1 <= 8 ? 8 : 16); }
 
 FggcLayout fggc_layout(const FggcArgs &a) {
   FggcLayout L{};
   const int d = a.g.d;
-  const size_t es = a.precision == FGGC_FP64 ? 16 : 8;
+  L.d = d;
+  const bool f64 = a.precision == FGGC_FP64;
+  const size_t es = f64 ? 16 : 8;
+  const DimLsq &l0 = a.lsq[0];
+  L.N1 = n1_bucket(l0.n1);
+  L.rec_b = 16 * ((8 * d + 15) / 16) + d * L.N1 * (int)es;
+  L.mindp = L.maxdp = l0.dp[0];
+  L.mindq = L.maxdq = l0.dq[0];
+  for (int m = 1; m < l0.n1; ++m) {
+    L.mindp = std::min(L.mindp, l0.dp[m]);
+    L.maxdp = std::max(L.maxdp, l0.dp[m]);
+    L.mindq = std::min(L.mindq, l0.dq[m]);
+    L.maxdq = std::max(L.maxdq, l0.dq[m]);
+  }
+  static const int64_t deft[4] = {0, 32, 32, 16};
   L.nslices = 1;
   int64_t nqt = 1;
   L.npts = 1;
   L.ntab = 0;
   L.nkst = 0;
+  L.nbins = 1;
+  L.tiles = 1;
   for (int k = 0; k < 3; ++k) {
     if (k < d) {
       L.nslices *= a.sn[k];
       nqt *= a.Nq[k];
       L.npts *= a.g.n[k];
+      L.tile[k] = std::min<int64_t>(a.Nq[k], deft[d]);
+      L.ntq[k] = a.Nq[k] / L.tile[k];
+      L.pmin[k] = a.slo[k] - L.mindp;
+      L.npc[k] = a.sn[k] - (L.maxdp - L.mindp);
+      L.nbins *= L.npc[k] * L.ntq[k];
+      L.tiles *= a.sn[k] * L.ntq[k];
       L.nb[k] = (int64_t)std::floor(2.0 * a.cK / std::sqrt(a.eps)) + 2;
       L.toff[k] = L.ntab;
       L.koff[k] = L.nkst;
       L.ntab += a.sn[k] * L.nb[k];
       L.nkst += a.sn[k];
     } else {
+      L.tile[k] = L.ntq[k] = L.npc[k] = 1;
+      L.pmin[k] = 0;
       L.nb[k] = 1;
       L.toff[k] = 0;
       L.koff[k] = 0;
     }
   }
+  if (L.nbins >= ((int64_t)1 << 32)) fail(FGGC_EUNSUPPORTED, "too many packet bins");
   L.ncells = L.nslices * nqt;
+  const int64_t N = std::max<int64_t>(a.pk->N, 1);
   size_t o = 0;
   auto put = [&](size_t bytes) {
     size_t at = o;
@@ -416,43 +634,102 @@ FggcLayout fggc_layout(const FggcArgs &a) {
     return at;
   };
   L.off_lsq = put(3 * sizeof(DimLsq));
+  L.off_keys = put(N * 4);
+  L.off_order = put(N * 4);
+  L.off_sort = put(bucket_sort_bytes(a.pk->N, L.nbins));
+  L.off_start = put((size_t)(L.nbins + 1) * 8);
+  L.off_recs = put((size_t)N * L.rec_b);
   L.off_cells = put((size_t)L.ncells * es);
   L.off_gam = put((size_t)L.ntab * (es / 2));
   L.off_kst = put((size_t)L.nkst * 8 + 64);
+  L.off_spec = put((size_t)L.npts * es);  // grid spectrum (the inverse FFT writes u from it)
   L.total = o;
   return L;
 }
 
-template <int D, bool F64>
-void launch_coef(const CoefParams &cp, void *cells, int n1, hipStream_t s) {
-  const dim3 grid((unsigned)((cp.N + 255) / 256)), blk(256);
-  if (n1 <= 4) {
-    coef_scatter_kernel<D, 4, F64><<<grid, blk, 0, s>>>(cp, cells);
-  } else if (n1 <= 8) {
-    coef_scatter_kernel<D, 8, F64><<<grid, blk, 0, s>>>(cp, cells);
-  } else {
-    if constexpr (D < 3) coef_scatter_kernel<D, 16, F64><<<grid, blk, 0, s>>>(cp, cells);
-    else fail(FGGC_EUNSUPPORTED, "3D strategies need nq * np <= 8");
+template <int D, int N1, typename T>
+void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams &cp,
+                       const uint32_t *order, char *recs, const int64_t *start, T *cells,
+                       hipStream_t s) {
+  {
+    StageScope sc(a.prof, "fggc_coef", s);
+    fggc_coef_kernel<D, N1, T><<<dim3((unsigned)((cp.N + 255) / 256)), dim3(256), 0, s>>>(cp, order, recs);
+    FGGC_HIP(hipGetLastError());
   }
+  AccParams ap{};
+  ap.recs = recs;
+  ap.start = start;
+  const DimLsq &l0 = a.lsq[0];
+  for (int k = 0; k < 3; ++k) {
+    ap.sn[k] = a.sn[k];
+    ap.npc[k] = L.npc[k];
+    ap.Nq[k] = a.Nq[k];
+    ap.tile[k] = L.tile[k];
+    ap.ntq[k] = L.ntq[k];
+  }
+  // one-dimensional shift sets (basis index a * np + b)
+  int nq = 0, np = 0;
+  for (int m = 0; m < l0.n1; ++m) {
+    if (l0.dq[m] == l0.dq[0]) ++np;
+  }
+  nq = l0.n1 / np;
+  ap.nq = nq;
+  ap.np = np;
+  for (int i = 0; i < 8; ++i) {
+    ap.dq[i] = i < nq ? l0.dq[i * np] : 0;
+    ap.dp[i] = i < np ? l0.dp[i] : 0;
+  }
+  ap.mindp = L.mindp;
+  ap.maxdp = L.maxdp;
+  ap.mindq = L.mindq;
+  ap.maxdq = L.maxdq;
+  for (int i = 0; i < 32; ++i) ap.bofs[i] = -1;
+  for (int b = 0; b < np; ++b) ap.bofs[ap.dp[b] - L.mindp] = b;
+  int64_t tc = 1;
+  for (int k = 0; k < D; ++k) tc *= L.tile[k];
+  const size_t shm = 2 * (size_t)tc * sizeof(decltype(T{}.x));
+  StageScope sc(a.prof, "fggc_accum", s);
+  fggc_accum_kernel<D, N1, T><<<dim3((unsigned)L.tiles), dim3(256), shm, s>>>(ap, cells);
   FGGC_HIP(hipGetLastError());
 }
 
-// zero the cells and add every packet's contributions
-void cells_stage(const FggcArgs &a, const FggcLayout &L, void *cells, DimLsq *dlsq, hipStream_t s) {
+// sort packets into bins, compute their coefficients in bin order, and fill
+// the cell array of eq. (2.25) (every cell written once)
+void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells, hipStream_t s) {
   const int d = a.g.d;
   const bool f64 = a.precision == FGGC_FP64;
+  DimLsq *dlsq = (DimLsq *)(base + L.off_lsq);
   FGGC_HIP(hipMemcpyAsync(dlsq, a.lsq, d * sizeof(DimLsq), hipMemcpyHostToDevice, s));
+  const int64_t N = a.pk->N;
+  uint32_t *keys = (uint32_t *)(base + L.off_keys), *order = (uint32_t *)(base + L.off_order);
+  int64_t *start = (int64_t *)(base + L.off_start);
+  char *recs = base + L.off_recs;
   {
-    StageScope sc(a.prof, "fggc_zero", s);
-    const int64_t n = L.ncells;
-    const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
-    if (f64) fill_zero_kernel<double2><<<nb, 256, 0, s>>>((double2 *)cells, n);
-    else fill_zero_kernel<float2><<<nb, 256, 0, s>>>((float2 *)cells, n);
-    FGGC_HIP(hipGetLastError());
+    StageScope sc(a.prof, "fggc_sort", s);
+    if (N > 0) {
+      KeyParams kp{};
+      kp.N = N;
+      kp.Q = a.pk->Q;
+      kp.P = a.pk->P;
+      for (int k = 0; k < 3; ++k) {
+        kp.Nq[k] = a.Nq[k];
+        kp.pmin[k] = L.pmin[k];
+        kp.npc[k] = L.npc[k];
+        kp.tile[k] = L.tile[k];
+        kp.ntq[k] = L.ntq[k];
+        kp.dq[k] = kTwoPi / (double)a.Nq[k];
+        kp.dp[k] = a.dp[k];
+      }
+      const dim3 g((unsigned)((N + 255) / 256)), b(256);
+      if (d == 1) fggc_key_kernel<1><<<g, b, 0, s>>>(kp, keys);
+      else if (d == 2) fggc_key_kernel<2><<<g, b, 0, s>>>(kp, keys);
+      else fggc_key_kernel<3><<<g, b, 0, s>>>(kp, keys);
+      FGGC_HIP(hipGetLastError());
+    }
+    bucket_sort(keys, N, L.nbins, order, start, base + L.off_sort, s);
   }
-  if (a.pk->N == 0) return;
   CoefParams cp{};
-  cp.N = a.pk->N;
+  cp.N = N;
   cp.Q = a.pk->Q;
   cp.P = a.pk->P;
   cp.S = a.pk->S;
@@ -462,21 +739,27 @@ void cells_stage(const FggcArgs &a, const FggcLayout &L, void *cells, DimLsq *dl
   cp.lsq = dlsq;
   for (int k = 0; k < 3; ++k) {
     cp.Nq[k] = a.Nq[k];
-    cp.slo[k] = a.slo[k];
-    cp.sn[k] = a.sn[k];
+    cp.pmin[k] = L.pmin[k];
     cp.dq[k] = kTwoPi / (double)a.Nq[k];
     cp.dp[k] = a.dp[k];
   }
-  const int n1 = a.lsq[0].n1;
-  StageScope sc(a.prof, "fggc_coef_scatter", s);
-  if (d == 1) { if (f64) launch_coef<1, true>(cp, cells, n1, s); else launch_coef<1, false>(cp, cells, n1, s); }
-  else if (d == 2) { if (f64) launch_coef<2, true>(cp, cells, n1, s); else launch_coef<2, false>(cp, cells, n1, s); }
-  else { if (f64) launch_coef<3, true>(cp, cells, n1, s); else launch_coef<3, false>(cp, cells, n1, s); }
+#define FGGC_CA(DD, NN)                                                                           \
+  if (f64) launch_coef_accum<DD, NN, double2>(a, L, cp, order, recs, start, (double2 *)cells, s); \
+  else launch_coef_accum<DD, NN, float2>(a, L, cp, order, recs, start, (float2 *)cells, s);
+  if (d == 1) {
+    if (L.N1 == 4) { FGGC_CA(1, 4) } else if (L.N1 == 8) { FGGC_CA(1, 8) } else { FGGC_CA(1, 16) }
+  } else if (d == 2) {
+    if (L.N1 == 4) { FGGC_CA(2, 4) } else if (L.N1 == 8) { FGGC_CA(2, 8) } else { FGGC_CA(2, 16) }
+  } else {
+    if (L.N1 == 4) { FGGC_CA(3, 4) } else if (L.N1 == 8) { FGGC_CA(3, 8) }
+    else fail(FGGC_EUNSUPPORTED, "3D strategies need nq * np <= 8");
+  }
+#undef FGGC_CA
 }
 
 template <typename T, typename R>
 void finish_stage(const FggcArgs &a, const FggcLayout &L, T *cells, R *gam, int64_t *kst,
-                  Workspace &ws, hipStream_t s) {
+                  void *spec, Workspace &ws, hipStream_t s) {
   const int d = a.g.d;
   const int prec = a.precision;
   // F5: forward DFT over q of every p-slice
@@ -518,7 +801,7 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, T *cells, R *gam, int6
   }
   m.eps = a.eps;
   m.cK = a.cK;
-  T *U = (T *)a.u;
+  T *U = (T *)spec;
   const unsigned nblk = (unsigned)((L.npts + 255) / 256);
   {
   StageScope sc(a.prof, "fggc_band_mac", s);
@@ -527,20 +810,11 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, T *cells, R *gam, int6
   else band_mac_kernel<3, T, R><<<nblk, 256, 0, s>>>(m, cells, gam, kst, U);
   FGGC_HIP(hipGetLastError());
   }
-  // F7: inverse DFT of the grid spectrum
-  launch_fft(d, a.g.n, 1, +1, prec, U, ws, s, a.prof, "fggc_ifft");
+  // F7: inverse DFT of the grid spectrum into u
+  launch_fft_to(d, a.g.n, +1, prec, U, a.u, ws, s, a.prof, "fggc_ifft");
 }
 
 }  // namespace
-
-void launch_pcell_range(const fggc_packets &pk, const double *dp, long long *dev, hipStream_t s) {
-  range_init_kernel<<<1, 64, 0, s>>>(dev);
-  FGGC_HIP(hipGetLastError());
-  if (pk.N == 0) return;
-  pcell_range_kernel<<<dim3((unsigned)((pk.N + 255) / 256)), dim3(256), 0, s>>>(
-      pk.d, pk.N, pk.P, dp[0], pk.d > 1 ? dp[1] : 1.0, pk.d > 2 ? dp[2] : 1.0, dev);
-  FGGC_HIP(hipGetLastError());
-}
 
 size_t fggc_workspace_bytes(const FggcArgs &a) { return fggc_layout(a).total + 1024; }
 
@@ -551,22 +825,21 @@ size_t fggc_cells_workspace_bytes(const FggcArgs &a) {
 
 void launch_fggc_cells(const FggcArgs &a, void *cells, Workspace &ws, hipStream_t s) {
   FggcLayout L = fggc_layout(a);
-  DimLsq *dlsq = (DimLsq *)ws.take(3 * sizeof(DimLsq));
-  cells_stage(a, L, cells, dlsq, s);
+  char *base = (char *)ws.take(L.off_cells);
+  cells_stage(a, L, base, cells, s);
 }
 
 void launch_fggc(const FggcArgs &a, Workspace &ws, hipStream_t s) {
   FggcLayout L = fggc_layout(a);
   char *base = (char *)ws.take(L.total);
-  DimLsq *dlsq = (DimLsq *)(base + L.off_lsq);
   void *cells = base + L.off_cells;
-  cells_stage(a, L, cells, dlsq, s);
+  cells_stage(a, L, base, cells, s);
   if (a.precision == FGGC_FP64)
     finish_stage<double2, double>(a, L, (double2 *)cells, (double *)(base + L.off_gam),
-                                  (int64_t *)(base + L.off_kst), ws, s);
+                                  (int64_t *)(base + L.off_kst), base + L.off_spec, ws, s);
   else
     finish_stage<float2, float>(a, L, (float2 *)cells, (float *)(base + L.off_gam),
-                                (int64_t *)(base + L.off_kst), ws, s);
+                                (int64_t *)(base + L.off_kst), base + L.off_spec, ws, s);
 }
 
 }  // namespace fggc

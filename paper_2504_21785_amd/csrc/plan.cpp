@@ -128,6 +128,11 @@ void build_dim_lsq(const fggc_strategy &st, int dim, double eps, DimLsq *out) {
       out->V[2 * (i * n1 + k)] = (double)V[(size_t)i * n1 + k].real();
       out->V[2 * (i * n1 + k) + 1] = (double)V[(size_t)i * n1 + k].imag();
     }
+  for (int k = 0; k < n1; ++k) {
+    const long double ph = -Cq * Cp * (long double)out->dq[k] * (long double)out->dp[k] / 2;
+    out->D[2 * k] = (double)std::cos(ph);
+    out->D[2 * k + 1] = (double)std::sin(ph);
+  }
 }
 
 }  // namespace fggc
@@ -140,15 +145,7 @@ extern "C" int fggc_plan_gram(int nq, const int32_t *dq_off, int np, const int32
       fggc::set_last_error("fggc_plan_gram: invalid argument");
       return FGGC_EINVAL;
     }
-    fggc_strategy st;
-    std::memset(&st, 0, sizeof(st));
-    st.nq = nq;
-    st.np = np;
-    for (int i = 0; i < nq; ++i) st.dq_off[i] = dq_off[i];
-    for (int i = 0; i < np; ++i) st.dp_off[i] = dp_off[i];
-    // choose eps = 1 so that Nq and dp reproduce (Cq, Cp) exactly in long double
     const int n1 = nq * np;
-    std::vector<std::complex<double>> A((size_t)n1 * n1);
     int sq[fggc::kMaxN1], sp[fggc::kMaxN1];
     for (int a = 0; a < nq; ++a)
       for (int b = 0; b < np; ++b) {

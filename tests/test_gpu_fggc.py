@@ -46,7 +46,7 @@ def rel(u, ref):
 
 @pytest.mark.parametrize("prec,tol", [(F.FP64, 1e-13), (F.FP32, 1e-6)])
 @pytest.mark.parametrize("dims,batch", [((2,), 3), ((8,), 5), ((64,), 7), ((512,), 33),
-                                        ((2048,), 2), ((8192,), 1), ((16, 32), 3),
+                                        ((2048,), 2), ((8192,), 1), ((8192,), 3), ((16, 32), 3),
                                         ((256, 256), 2), ((8, 16, 4), 3), ((32, 32, 32), 2)])
 def test_fft_against_numpy(ctx, prec, tol, dims, batch):
     rng = np.random.default_rng(len(dims) * 100 + dims[0])
