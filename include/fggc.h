@@ -141,6 +141,16 @@ int fggc_direct_sum(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fgg
                     double window_radius, double scale, int precision, void *u_out, void *stream);
 
 /*
+ * The direct sum of fggc_direct_sum at the grid points of a box only:
+ * points m with box_lo[k] <= m_k < box_lo[k] + box_n[k] (0 <= box_lo,
+ * box_lo + box_n <= grid->n); u_out holds prod(box_n) values, row-major over
+ * the box.  Same arguments, precision and errors otherwise.
+ */
+int fggc_direct_sum_box(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_grid *grid,
+                        const int64_t *box_lo, const int64_t *box_n, double window_radius,
+                        double scale, int precision, void *u_out, void *stream);
+
+/*
  * FGGC reconstruction (Alg. 2 steps 3-4 with eq. 2.23-2.25):
  *   per packet and dimension, int/frac split (3.6)-(3.7), right-hand side
  *   (3.23), least squares against the precomputed Gram matrix (3.22) through

@@ -385,9 +385,11 @@ void fggc_destroy(fggc_ctx *ctx) {
   delete ctx;
 }
 
-int fggc_direct_sum(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_grid *grid,
-                    double window_radius, double scale, int precision, void *u_out, void *stream) {
-  return guarded("fggc_direct_sum", [&] {
+namespace {
+int direct_impl(const char *what, fggc_ctx *ctx, const fggc_packets *pk, double eps,
+                const fggc_grid *grid, const int64_t *box_lo, const int64_t *box_n,
+                double window_radius, double scale, int precision, void *u_out, void *stream) {
+  return guarded(what, [&] {
     if (!ctx) fail(FGGC_EINVAL, "ctx is NULL");
     GridGeom g = check_grid(grid);
     check_packets(pk, g.d);
@@ -397,9 +399,21 @@ int fggc_direct_sum(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fgg
     if (!std::isfinite(scale)) fail(FGGC_EINVAL, "scale must be finite");
     if (precision != FGGC_FP32 && precision != FGGC_FP64) fail(FGGC_EINVAL, "bad precision");
     if (!u_out) fail(FGGC_EINVAL, "u_out is NULL");
+    Box box{};
+    int64_t npts = 1;
+    for (int k = 0; k < 3; ++k) {
+      box.lo[k] = 0;
+      box.n[k] = g.n[k];
+      if (k < g.d && box_lo && box_n) {
+        if (box_lo[k] < 0 || box_n[k] < 1 || box_lo[k] + box_n[k] > g.n[k])
+          fail(FGGC_EINVAL, "box outside the grid");
+        box.lo[k] = box_lo[k];
+        box.n[k] = box_n[k];
+      }
+      if (k < g.d) npts *= box.n[k];
+    }
     Guard lock(ctx);
     hipStream_t s = (hipStream_t)stream;
-    const int64_t npts = prod3(g.n, g.d);
     const size_t out_bytes = (size_t)npts * (precision == FGGC_FP64 ? 16 : 8);
     const bool host_in = packets_on_host(*pk);
     const bool host_out = !device_accessible(u_out);
@@ -410,10 +424,7 @@ int fggc_direct_sum(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fgg
     da.R = window_radius;
     da.scale = scale;
     da.g = g;
-    for (int k = 0; k < 3; ++k) {
-      da.box.lo[k] = 0;
-      da.box.n[k] = g.n[k];
-    }
+    da.box = box;
     da.precision = precision;
     da.prof = ctx->profiling ? &ctx->prof : nullptr;
     const size_t need = staging_bytes(*pk, host_in, out_bytes, host_out) + direct_workspace_bytes(da);
@@ -429,6 +440,24 @@ int fggc_direct_sum(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fgg
       FGGC_HIP(hipStreamSynchronize(s));
     }
   });
+}
+}  // namespace
+
+int fggc_direct_sum(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_grid *grid,
+                    double window_radius, double scale, int precision, void *u_out, void *stream) {
+  return direct_impl("fggc_direct_sum", ctx, pk, eps, grid, nullptr, nullptr, window_radius, scale,
+                     precision, u_out, stream);
+}
+
+int fggc_direct_sum_box(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_grid *grid,
+                        const int64_t *box_lo, const int64_t *box_n, double window_radius,
+                        double scale, int precision, void *u_out, void *stream) {
+  if (!box_lo || !box_n) {
+    set_last_error("fggc_direct_sum_box: box is NULL");
+    return FGGC_EINVAL;
+  }
+  return direct_impl("fggc_direct_sum_box", ctx, pk, eps, grid, box_lo, box_n, window_radius, scale,
+                     precision, u_out, stream);
 }
 
 int fggc_cell_box(fggc_ctx *ctx, const fggc_packets *pk, const fggc_strategy *st,

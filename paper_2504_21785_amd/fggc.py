@@ -67,6 +67,8 @@ _SIGS = [
     ("fggc_last_error", ctypes.c_char_p, []),
     ("fggc_version", ctypes.c_char_p, []),
     ("fggc_direct_sum", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid), _D, _D, _I, _VP, _VP]),
+    ("fggc_direct_sum_box", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid),
+                                 ctypes.POINTER(_I64), ctypes.POINTER(_I64), _D, _D, _I, _VP, _VP]),
     ("fggc_reconstruct", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid),
                               ctypes.POINTER(Strategy), _D, _I, _VP, _VP]),
     ("fggc_default_strategy", _I, [_I, _D, ctypes.c_char_p, ctypes.POINTER(Strategy)]),
@@ -234,6 +236,22 @@ class Context:
         _check(lib().fggc_direct_sum(self.h, ctypes.byref(pk), float(eps), ctypes.byref(g),
                                      float(window_radius), float(scale), int(precision),
                                      _ptr(out), _stream_ptr(stream) if _on_device(Q) else None))
+        return out
+
+    def direct_sum_box(self, Q, P, S, a, eps: float, M, box_lo, box_n, window_radius: float,
+                       scale: float = 1.0, precision: int = FP32, out=None, stream=None):
+        """fggc_direct_sum_box: the direct sum at the points of a box of the grid."""
+        d = Q.shape[0]
+        g = _grid(d, M)
+        lo = (ctypes.c_int64 * 3)(*[int(v) for v in list(box_lo) + [0] * (3 - d)])
+        n = (ctypes.c_int64 * 3)(*[int(v) for v in list(box_n) + [1] * (3 - d)])
+        if out is None:
+            bg = _grid(d, list(box_n))
+            out = self._alloc_out(Q, bg, precision, None)
+        pk = _packets(Q, P, S, a)
+        _check(lib().fggc_direct_sum_box(self.h, ctypes.byref(pk), float(eps), ctypes.byref(g), lo, n,
+                                         float(window_radius), float(scale), int(precision),
+                                         _ptr(out), _stream_ptr(stream) if _on_device(Q) else None))
         return out
 
     def reconstruct(self, Q, P, S, a, eps: float, M, strategy: Strategy, scale: float = 1.0,
