@@ -63,6 +63,73 @@ def direct_slots_per_pair(d):
     return d + d + 1 + 2 + (d + 2) + 2 + 3 * 4
 
 
+def serving_bench(ctx, F, W, torch, n_pool, n_req, loads, n_streams):
+    """Serving stream: a pool of distinct requests of the stream's distribution
+    (device-resident), warmed so that each shape has run eagerly and been
+    captured; the capacity from a closed batch of n_req submissions; then
+    open-loop Poisson arrivals at each offered load (a fraction of that
+    capacity), reporting p50/p99 latency (submit to completion) and packets/s."""
+    log(f"serving: generating {n_pool} requests")
+    pool = []
+    for r in range(n_pool):
+        ps = W.serving_request(r)
+        st = F.default_strategy(ps.d, ps.eps, "Q4P2")
+        dev = tuple(torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (ps.Q, ps.P, ps.S, ps.a))
+        pool.append((ps, st, dev))
+    torch.cuda.synchronize()
+    srv = F.Server(ctx, n_streams)
+
+    def submit(i):
+        ps, st, dev = pool[i]
+        return srv.submit(*dev, ps.eps, ps.M, st)
+
+    def wait_all(tks):
+        for tk, _ in tks:
+            rc = srv.wait(tk, 300.0)
+            if rc != F.FGGC_OK:
+                raise RuntimeError(f"served request failed: {rc} {F.last_error()}")
+
+    try:
+        for _ in range(2):  # first sighting runs eagerly, the second captures its graph
+            wait_all([submit(i) for i in range(n_pool)])
+        rng = np.random.default_rng(W.BASE_SEED * 1000 + 4)
+        srv.reset_stats()
+        order = rng.integers(0, n_pool, n_req)
+        t0 = time.perf_counter()
+        wait_all([submit(int(i)) for i in order])
+        t_cap = time.perf_counter() - t0
+        cap = {"requests_per_s": n_req / t_cap,
+               "packets_per_s": float(sum(pool[int(i)][0].N for i in order)) / t_cap,
+               "graphs": srv.counters()}
+        log("serving capacity:", cap)
+        res = []
+        for rho in loads:
+            srv.reset_stats()
+            lam = rho * cap["requests_per_s"]
+            arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
+            order = rng.integers(0, n_pool, n_req)
+            tks = []
+            t0 = time.perf_counter()
+            for i in range(n_req):
+                while True:
+                    dt = arrivals[i] - (time.perf_counter() - t0)
+                    if dt <= 0:
+                        break
+                    time.sleep(min(dt, 0.002) if dt > 0.0005 else 0)
+                tks.append(submit(int(order[i])))
+            wait_all(tks)
+            s = srv.stats()
+            r = {"offered_load": rho, "offered_requests_per_s": lam, "requests": n_req,
+                 "p50_ms": s["p50_s"] * 1e3, "p99_ms": s["p99_s"] * 1e3,
+                 "packets_per_s": s["packets_per_s"], "graphs": srv.counters()}
+            log("serving load", rho, r)
+            res.append(r)
+    finally:
+        srv.close()
+    return {"workload": "cfg4: " + W.CONFIG_NAMES[4], "n_streams": n_streams, "pool_requests": n_pool,
+            "mean_packets": float(np.mean([p[0].N for p in pool])), "capacity": cap, "loads": res}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +138,15 @@ def main():
     ap.add_argument("--workload", default="cfg1", choices=sorted(WORKLOADS))
     ap.add_argument("--strategy", default=None, help="Q2P2, Q4P2, Q2P4 or Q4P4 (default Q4P2; Q2P2 in 3D)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream measurement")
+    ap.add_argument("--cpu-points", type=int, default=4096,
+                    help="grid points sampled by the oracle in 2D and 3D")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run a plain elementwise copy (read and write this many MiB) before timing, "
+                         "to scale HBM counters read under a profiler")
+    ap.add_argument("--serving-pool", type=int, default=48)
+    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-streams", type=int, default=4)
     ap.add_argument("--cpu-target-s", type=float, default=12.0,
                     help="approximate CPU seconds for the oracle sample")
     args = ap.parse_args()
@@ -108,6 +184,14 @@ def main():
         if do_direct:
             step_direct()
     torch.cuda.synchronize()
+
+    if args.calib_copy_mb > 0:
+        cx = torch.ones(args.calib_copy_mb << 18, dtype=torch.float32, device=dev)
+        cy = torch.empty_like(cx)
+        for _ in range(3):
+            torch.mul(cx, 2.0, out=cy)
+        torch.cuda.synchronize()
+        del cx, cy
 
     # ---- pass A: timed steps -------------------------------------------------
     torch.cuda.synchronize()
@@ -147,8 +231,10 @@ def main():
 
     # FGGC vs direct on the full workload (GPU outputs only)
     fvd = None
+    u_fggc = u_f.cpu().numpy()
+    u_direct = u_d.cpu().numpy() if do_direct else None
     if do_direct:
-        fvd = rel(u_f.cpu().numpy().astype(np.complex128), u_d.cpu().numpy().astype(np.complex128))
+        fvd = rel(u_fggc.astype(np.complex128), u_direct.astype(np.complex128))
         log(f"FGGC vs direct rel-L2 {fvd:.3e}")
 
     # ---- roofline of the dominant FGGC kernel --------------------------------
@@ -190,6 +276,11 @@ def main():
                            "pairs_per_s": pairs / (stages["ds_kernel"]["avg_ms"] * 1e-3)}
 
     # ---- CPU baseline: the oracle on a bounded sample -----------------------
+    # The oracle's FGGC cost is mostly per cell and per grid point, and its
+    # direct sum's per grid point, so the sample is all packets and a set of
+    # grid points: the whole grid in 1D (each run repeated until about
+    # cpu_target_s / 2 seconds have passed), a random sample of points in 2D and
+    # 3D, timed and scaled by (grid points / sampled points).
     cpu = None
     accuracy = {}
     if not args.no_cpu_baseline:
@@ -197,47 +288,65 @@ def main():
         oracle.build(force=False)
         cores = oracle.num_threads()
         sd = st.describe()
-        # calibrate the sample: a prefix of the packet list, full grid
-        ns = min(ps.N, 4096)
-        sub = lambda x: np.ascontiguousarray(x[..., :ns])
-        t0 = time.perf_counter()
-        oracle.fggc(sub(ps.Q), sub(ps.P), sub(ps.S), sub(ps.a), ps.eps, ps.M, sd["Nq"][:d],
-                    sd["dp"][:d], sd["dq_off"], sd["dp_off"])
-        t_small = time.perf_counter() - t0
-        ns = int(min(ps.N, max(4096, 4096 * args.cpu_target_s / 2 / max(t_small, 1e-3))))
-        sQ, sP, sS, sa = sub(ps.Q), sub(ps.P), sub(ps.S), sub(ps.a)
-        log(f"cpu baseline: {ns} packets, {cores} threads")
-        t0 = time.perf_counter()
-        ref_f = oracle.fggc(sQ, sP, sS, sa, ps.eps, ps.M, sd["Nq"][:d], sd["dp"][:d], sd["dq_off"],
-                            sd["dp_off"])
-        t_of = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        ref_d = oracle.direct_sum(sQ, sP, sS, sa, ps.eps, ps.M, ps.R) if do_direct else None
-        t_od = time.perf_counter() - t0
-        cpu = {"value": ns / t_of, "unit": "packets/s", "cores": cores, "kind": "oracle",
-               "sample": f"first {ns} packets of the workload, FP64 FGGC (cells + plain evaluation of "
-                         f"eq. 2.24 with window 8 sqrt(eps)) on the full grid",
-               "seconds": t_of}
-        if ref_d is not None:
-            cpu["direct_sum"] = {"value": ns / t_od, "unit": "packets/s", "seconds": t_od,
-                                 "sample": f"first {ns} packets, FP64 windowed direct sum, full grid"}
-        # the GPU on the same sample, against the oracle
-        sT = lambda x: t(x)
-        uf = ctx.reconstruct(sT(sQ), sT(sP), sT(sS), sT(sa), ps.eps, ps.M, st, precision=F.FP32)
-        torch.cuda.synchronize()
-        accuracy["fggc_fp32_vs_oracle_rel_l2"] = rel(uf.cpu().numpy().reshape(-1).astype(np.complex128), ref_f)
-        if ref_d is not None:
-            ud = ctx.direct_sum(sT(sQ), sT(sP), sT(sS), sT(sa), ps.eps, ps.M, ps.R, precision=F.FP32)
-            torch.cuda.synchronize()
-            accuracy["direct_fp32_vs_oracle_rel_l2"] = rel(ud.cpu().numpy().reshape(-1).astype(np.complex128), ref_d)
-        accuracy["sample_packets"] = ns
+        mpts = int(np.prod(ps.M))
+        if d == 1:
+            pts = None
+            npts = mpts
+        else:
+            rng = np.random.default_rng(11)
+            npts = min(mpts, args.cpu_points)
+            pts = np.unique(rng.integers(0, mpts, npts))
+            npts = len(pts)
+
+        def run_f():
+            return oracle.fggc(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, sd["Nq"][:d], sd["dp"][:d],
+                               sd["dq_off"], sd["dp_off"], pts=pts)
+
+        def run_d():
+            return oracle.direct_sum(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R, pts=pts)
+
+        def timed(fn):
+            n, t0 = 0, time.perf_counter()
+            while True:
+                out_ = fn()
+                n += 1
+                el = time.perf_counter() - t0
+                if el >= args.cpu_target_s / 2 or n >= 50:
+                    return out_, el / n, n
+
+        log(f"cpu baseline: {ps.N} packets, {npts} of {mpts} grid points, {cores} threads")
+        ref_f, t_of, n_f = timed(run_f)
+        scale_pts = mpts / npts
+        samp = "all packets, whole grid" if pts is None else \
+            f"all packets, {npts} random grid points of {mpts}, time scaled by {scale_pts:.4g}"
+        cpu = {"value": ps.N / (t_of * scale_pts), "unit": "packets/s", "cores": cores, "kind": "oracle",
+               "sample": f"FP64 FGGC oracle (cells, then plain evaluation of eq. 2.24 with window "
+                         f"8 sqrt(eps)): {samp}; mean of {n_f} runs",
+               "seconds_per_run": t_of}
+        ref_d = None
+        if do_direct:
+            ref_d, t_od, n_d = timed(run_d)
+            cpu["direct_sum"] = {"value": ps.N / (t_od * scale_pts), "unit": "packets/s",
+                                 "seconds_per_run": t_od,
+                                 "sample": f"FP64 windowed direct-sum oracle: {samp}; mean of {n_d} runs"}
+        # the GPU result of the timed workload against the oracle on the same points
+        pick = (lambda u: u.reshape(-1)) if pts is None else (lambda u: u.reshape(-1)[pts])
+        accuracy["fggc_fp32_vs_oracle_rel_l2"] = rel(pick(u_fggc).astype(np.complex128), ref_f)
+        if ref_d is not None and u_direct is not None:
+            accuracy["direct_fp32_vs_oracle_rel_l2"] = rel(pick(u_direct).astype(np.complex128), ref_d)
+        accuracy["oracle_points"] = npts
         log("accuracy:", accuracy)
     if fvd is not None:
         accuracy["fggc_vs_direct_rel_l2"] = fvd
 
+    serving = None
+    if not args.no_serving:
+        serving = serving_bench(ctx, F, W, torch, args.serving_pool, args.serving_requests, (0.5, 0.8),
+                                args.serving_streams)
+
     value = ps.N / (fggc_ms * 1e-3)
     out = {
-        "metric": "packets reconstructed/sec at rel-L2<=1e-6: FGGC vs direct sum",
+        "metric": "packets reconstructed/sec at rel-L2<=1e-6: FGGC vs direct sum; serving p50/p99",
         "value": value,
         "unit": "packets/s",
         "n_gpus": 1,
@@ -259,6 +368,7 @@ def main():
         "accuracy": accuracy,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
         "stages_ms": {k2: v["avg_ms"] for k2, v in stages.items()},
     }
     ctx.close()

@@ -249,28 +249,50 @@ typedef struct fggc_server fggc_server;
 typedef int64_t fggc_ticket;
 
 /*
- * A persistent scheduler on the context's device.  Submitted requests are
- * admitted in arrival order as soon as their memory estimate fits the
- * context's HBM budget and a slot is free; admitted requests run
- * concurrently on `n_streams` streams (1..8), each as a captured and cached
- * hipGraph of its shape.  A request whose estimate alone exceeds the
- * budget fails with FGGC_EBUDGET without blocking others.
+ * A persistent scheduler on the context's device (the serving mode of the
+ * reconstruction step; the paper states the single reconstruction, eq. 2.10
+ * and eq. 2.19, and this wraps it for a stream of independent requests).
+ * `n_streams` (1..8) executor slots each own a worker thread, a non-blocking
+ * stream and a workspace.  Queued requests are admitted in arrival order as
+ * soon as a slot is idle and the request's memory estimate fits the
+ * context's HBM budget (idle slots release memory when that makes it fit);
+ * admitted requests overlap on the device.  A slot runs a request's kernel
+ * pipeline eagerly the first time its shape is seen, captures it into a
+ * hipGraph the second time and replays that graph afterwards (up to 32
+ * graphs per slot, least recently used dropped).  Shapes repeat because the
+ * packet count is padded to a quarter-octave bucket (m 2^e, m in 4..8, at
+ * least 64) with zero-amplitude copies of packet 0, which add exactly
+ * nothing, and the p-cell box is widened to even cell indices.  The budget
+ * covers the slots' workspaces; synchronous calls on the same context
+ * during serving allocate outside it.
+ * Errors: FGGC_EINVAL (NULL out or ctx, n_streams out of range),
+ * FGGC_EDEVICE.
  */
 int fggc_server_create(fggc_ctx *ctx, int n_streams, fggc_server **out);
 
 /*
- * Enqueue a reconstruction.  Packet arrays are copied to the device before
- * submit returns (the caller may free them).  st == NULL selects the
- * direct sum with window 6 sqrt(eps); otherwise FGGC with *st.  u_out is
- * host memory of prod(grid->n) complex values, written before the ticket
- * completes.
+ * Enqueue a reconstruction and return its ticket.  st == NULL selects the
+ * direct sum with window radius 6 sqrt(eps); otherwise FGGC with *st.
+ * Packet arrays must be all host or all device memory.  Host packets are
+ * copied (and checked) before submit returns, so the caller may free them;
+ * device packets are checked by a small kernel at submit and read in place,
+ * so they must stay valid and unchanged until the ticket is waited for.
+ * u_out (host or device, prod(grid->n) complex values, complex64 for FP32,
+ * complex128 for FP64, row-major) is written before the ticket completes.
+ * The request's memory estimate is fixed here; a request whose estimate
+ * exceeds the budget fails at once with FGGC_EBUDGET and blocks nobody.
+ * N == 0 completes at once with u = 0.
+ * Errors: FGGC_EINVAL (bad arguments or packets, as for the synchronous
+ * calls; N > 2^30), FGGC_EUNSUPPORTED (grid sizes FGGC does not handle),
+ * FGGC_EBUDGET, FGGC_ECANCELLED (server shutting down), FGGC_EDEVICE.
  */
 int fggc_server_submit(fggc_server *srv, const fggc_packets *pk, double eps, const fggc_grid *grid,
                        const fggc_strategy *st, double scale, int precision, void *u_out,
                        fggc_ticket *ticket);
 
-/* Wait for a ticket; returns its final status, or FGGC_ETIMEOUT if
- * timeout_s (< 0: forever) elapsed first. */
+/* Wait for a ticket; returns its final status (and forgets the ticket), or
+ * FGGC_ETIMEOUT if timeout_s (< 0: forever) elapsed first (the ticket stays
+ * valid).  FGGC_EINVAL for an unknown or already-waited ticket. */
 int fggc_server_wait(fggc_server *srv, fggc_ticket ticket, double timeout_s);
 
 /* Latency percentiles (submit to completion, seconds) and throughput
@@ -278,6 +300,14 @@ int fggc_server_wait(fggc_server *srv, fggc_ticket ticket, double timeout_s);
  * completed requests. */
 int fggc_server_stats(fggc_server *srv, double *p50_s, double *p99_s, double *packets_per_s,
                       int64_t *completed);
+
+/* How the completed requests ran: eagerly (first sighting of a shape, or
+ * a shape that could not be captured), by capturing a new graph, or by
+ * replaying a cached one. */
+int fggc_server_counters(fggc_server *srv, int64_t *eager, int64_t *captured, int64_t *replayed);
+
+/* Clear the latency, throughput and graph counters (e.g. after a warm-up). */
+int fggc_server_reset_stats(fggc_server *srv);
 
 /* Stop the scheduler after the queued requests have finished; free it. */
 void fggc_server_destroy(fggc_server *srv);

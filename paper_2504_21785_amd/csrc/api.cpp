@@ -29,7 +29,8 @@ void Workspace::reserve(size_t bytes, size_t budget) {
     fail(FGGC_EBUDGET, "request needs " + std::to_string(bytes) + " bytes of workspace, budget is " +
                            std::to_string(budget));
   if (base_) {
-    FGGC_HIP(hipDeviceSynchronize());
+    if (has_stream_) FGGC_HIP(hipStreamSynchronize(stream_));
+    else FGGC_HIP(hipDeviceSynchronize());
     FGGC_HIP(hipFree(base_));
     base_ = nullptr;
     cap_ = 0;
@@ -45,6 +46,16 @@ void Workspace::reserve(size_t bytes, size_t budget) {
     }
   }
   cap_ = want;
+}
+
+void Workspace::release() {
+  used_ = 0;
+  if (!base_) return;
+  if (has_stream_) FGGC_HIP(hipStreamSynchronize(stream_));
+  else FGGC_HIP(hipDeviceSynchronize());
+  FGGC_HIP(hipFree(base_));
+  base_ = nullptr;
+  cap_ = 0;
 }
 
 void *Workspace::take(size_t bytes) {
@@ -133,8 +144,6 @@ std::vector<std::string> Profiler::stages() {
   return v;
 }
 
-namespace {
-
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // true when `p` can be dereferenced by kernels on the current device as is
@@ -208,21 +217,6 @@ struct Guard {
   ~Guard() { ctx->mu.unlock(); }
 };
 
-template <class F> int guarded(const char *what, F &&f) {
-  try {
-    f();
-    return FGGC_OK;
-  } catch (const Error &e) {
-    set_last_error(std::string(what) + ": " + e.msg);
-    return e.code;
-  } catch (const std::exception &e) {
-    set_last_error(std::string(what) + ": " + e.what());
-    return FGGC_EDEVICE;
-  } catch (...) {
-    set_last_error(std::string(what) + ": unknown internal error");
-    return FGGC_EDEVICE;
-  }
-}
 
 // Copy host-resident packet arrays into `dst` (device); returns device views.
 fggc_packets stage_packets(const fggc_packets &pk, char *dst, hipStream_t s) {
@@ -336,7 +330,6 @@ int64_t prod3(const int64_t *v, int d) {
   return p;
 }
 
-}  // namespace
 }  // namespace fggc
 
 using namespace fggc;
@@ -570,7 +563,7 @@ int fggc_reconstruct(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fg
     if (host_in) dpk = stage_packets(*pk, (char *)ctx->ws.take((size_t)pk->N * (2 * d + 3) * 8), s);
     if (dpk.N == 0) {
       void *u = host_out ? ctx->ws.take(out_bytes) : u_out;
-      FGGC_HIP(hipMemsetAsync(u, 0, out_bytes, s));
+      launch_zero(u, out_bytes, s);
       if (host_out) FGGC_HIP(hipMemcpyAsync(u_out, u, out_bytes, hipMemcpyDeviceToHost, s));
       FGGC_HIP(hipStreamSynchronize(s));
       return;

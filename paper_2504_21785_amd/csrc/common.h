@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <exception>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -40,12 +41,19 @@ class Workspace {
   ~Workspace();
   void reserve(size_t bytes, size_t budget);  // ensure capacity (may reallocate)
   void reset() { used_ = 0; }
+  void release();                             // free the memory (capacity 0)
+  size_t mark() const { return used_; }       // current take position
+  void rewind(size_t m) { used_ = m; }        // drop takes made after mark()
+  // stream whose completion is awaited before a reallocation (default: the device)
+  void set_stream(hipStream_t s) { stream_ = s; has_stream_ = true; }
   void *take(size_t bytes);                   // 256-byte aligned slice
   size_t capacity() const { return cap_; }
 
  private:
   char *base_ = nullptr;
   size_t cap_ = 0, used_ = 0;
+  hipStream_t stream_ = nullptr;
+  bool has_stream_ = false;
 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -152,6 +160,14 @@ size_t packet_scan_bytes();
 void launch_packet_scan(const fggc_packets &pk, const double *dp, long long *part, long long *out,
                         hipStream_t s);
 
+// Zero `bytes` (a multiple of 4) of device memory with a kernel (capturable
+// in a graph, unlike a memset node).
+void launch_zero(void *p, size_t bytes, hipStream_t s);
+// Fill slots [N, Npad) of SoA packet arrays sized Npad with zero-amplitude
+// copies of packet 0 (they add exactly nothing to any sum).
+void launch_pad_packets(int d, int64_t N, int64_t Npad, double *Q, double *P, double *S, double *a,
+                        hipStream_t s);
+
 // Stable counting sort of indices 0..N-1 by keys[i] in [0, nbins): order[]
 // grouped by key, start[b] first position of key b (start[nbins] = N).
 // `scratch` holds bucket_sort_bytes(N, nbins); keys may be overwritten.
@@ -200,6 +216,41 @@ void launch_fft(int d, const int64_t *n, int64_t batch, int direction, int preci
 // One d-dimensional FFT from src to dst (src may be overwritten).
 void launch_fft_to(int d, const int64_t *n, int direction, int precision, void *src, void *dst,
                    Workspace &ws, hipStream_t s, Profiler *prof = nullptr, const char *stage = "fft");
+
+// --------------------------------------------------------------------------
+// argument checks shared by the entry points (api.cpp)
+// --------------------------------------------------------------------------
+
+bool is_pow2(int64_t v);
+// true when `p` can be dereferenced by kernels on the current device as is
+bool device_accessible(const void *p);
+// true when any packet array is not device-accessible
+bool packets_on_host(const fggc_packets &pk);
+void check_packets(const fggc_packets *pk, int d);
+GridGeom check_grid(const fggc_grid *g);
+void check_eps(double eps);
+void check_strategy(const fggc_strategy *st, int d);
+void fill_fggc_args(FggcArgs &fa, const fggc_packets *pk, double eps, const GridGeom &g,
+                    const fggc_strategy &st, double scale, int precision, const DimLsq *lsq,
+                    const int64_t *slo, const int64_t *sn);
+int64_t prod3(const int64_t *v, int d);
+
+// Run f, turning exceptions into a status code and a thread-local message.
+template <class F> int guarded(const char *what, F &&f) {
+  try {
+    f();
+    return FGGC_OK;
+  } catch (const Error &e) {
+    set_last_error(std::string(what) + ": " + e.msg);
+    return e.code;
+  } catch (const std::exception &e) {
+    set_last_error(std::string(what) + ": " + e.what());
+    return FGGC_EDEVICE;
+  } catch (...) {
+    set_last_error(std::string(what) + ": unknown internal error");
+    return FGGC_EDEVICE;
+  }
+}
 
 }  // namespace fggc
 

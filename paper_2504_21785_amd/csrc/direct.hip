@@ -538,7 +538,7 @@ void launch_direct(const DirectArgs &a, Workspace &ws, hipStream_t s) {
         L.npts, L.nchunk, part, a.u);
     FGGC_HIP(hipGetLastError());
   } else {
-    FGGC_HIP(hipMemsetAsync(a.u, 0, (size_t)L.npts * (f64 ? 16 : 8), s));
+    launch_zero(a.u, (size_t)L.npts * (f64 ? 16 : 8), s);
   }
 }
 

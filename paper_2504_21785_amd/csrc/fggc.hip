@@ -169,7 +169,11 @@ __global__ void fggc_key_kernel(KeyParams p, uint32_t *__restrict__ key) {
     int_frac(p.Q[k * p.N + j] / p.dq[k], iq, s);
     int_frac(p.P[k * p.N + j] / p.dp[k], ip, t);
     const int64_t qi = (iq + p.Nq[k] / 2) & (p.Nq[k] - 1);
-    kp = kp * p.npc[k] + (ip - p.pmin[k]);
+    // the cell box comes from the same floor(P/dp), so this clamp never binds;
+    // it keeps every key inside [0, nbins) whatever the caller's box
+    int64_t pc = ip - p.pmin[k];
+    pc = pc < 0 ? 0 : (pc >= p.npc[k] ? p.npc[k] - 1 : pc);
+    kp = kp * p.npc[k] + pc;
     kq = kq * p.ntq[k] + qi / p.tile[k];
   }
   int64_t nqt = 1;

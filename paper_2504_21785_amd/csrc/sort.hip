@@ -284,7 +284,7 @@ void bucket_sort(uint32_t *keys, int64_t N, int64_t nbins, uint32_t *order, int6
       bucket_hist_kernel<<<dim3(sp.G), dim3(kSortBlock), shm, s>>>(keys, N, sp.chunk, nbins, sp.G, table);
       FGGC_HIP(hipGetLastError());
     } else {
-      FGGC_HIP(hipMemsetAsync(table, 0, (size_t)nbins * sp.G * 4, s));
+      launch_zero(table, (size_t)nbins * sp.G * 4, s);
     }
     size_t tmp = sp.tmp_bytes;
     FGGC_HIP(hipcub::DeviceScan::ExclusiveSum(base + sp.off_tmp, tmp, table, offs, (int)(nbins * sp.G), s));
@@ -311,6 +311,41 @@ void bucket_sort(uint32_t *keys, int64_t N, int64_t nbins, uint32_t *order, int6
   } else {
     radix_start_kernel<<<dim3((unsigned)((nbins + 1 + 255) / 256)), dim3(256), 0, s>>>(0, keys, nbins, start);
   }
+  FGGC_HIP(hipGetLastError());
+}
+
+__global__ void zero_kernel(uint32_t *__restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// zero-amplitude copies of packet 0 in slots [N, Npad) of SoA arrays sized Npad
+__global__ void pad_packets_kernel(int d, int64_t N, int64_t Npad, double *Q, double *P, double *S,
+                                   double *a) {
+  const int64_t j = N + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= Npad) return;
+  for (int k = 0; k < d; ++k) {
+    Q[k * Npad + j] = Q[k * Npad];
+    P[k * Npad + j] = P[k * Npad];
+  }
+  S[j] = S[0];
+  a[2 * j] = 0.0;
+  a[2 * j + 1] = 0.0;
+}
+
+void launch_zero(void *p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  if (bytes % 4) fail(FGGC_EDEVICE, "internal: launch_zero needs a multiple of 4 bytes");
+  const int64_t n = (int64_t)(bytes / 4);
+  const int64_t blocks = std::min<int64_t>(4096, (n + 255) / 256);
+  zero_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>((uint32_t *)p, n);
+  FGGC_HIP(hipGetLastError());
+}
+
+void launch_pad_packets(int d, int64_t N, int64_t Npad, double *Q, double *P, double *S, double *a,
+                        hipStream_t s) {
+  if (Npad <= N || N < 1) return;
+  pad_packets_kernel<<<dim3((unsigned)((Npad - N + 255) / 256)), dim3(256), 0, s>>>(d, N, Npad, Q, P, S, a);
   FGGC_HIP(hipGetLastError());
 }
 

@@ -87,6 +87,9 @@ _SIGS = [
     ("fggc_server_wait", _I, [_VP, _I64, _D]),
     ("fggc_server_stats", _I, [_VP, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D),
                                ctypes.POINTER(_I64)]),
+    ("fggc_server_counters", _I, [_VP, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                              ctypes.POINTER(_I64)]),
+    ("fggc_server_reset_stats", _I, [_VP]),
     ("fggc_server_destroy", None, [_VP]),
 ]
 
@@ -340,19 +343,30 @@ class Server:
         self._keep = {}
 
     def submit(self, Q, P, S, a, eps: float, M, strategy: Optional[Strategy] = None,
-               scale: float = 1.0, precision: int = FP32):
-        """Submit host (numpy) packets; returns (ticket, output array filled on completion)."""
+               scale: float = 1.0, precision: int = FP32, out=None):
+        """Submit packets (numpy arrays, or device tensors kept alive until wait);
+        returns (ticket, output) -- output is filled when the ticket completes.
+        out defaults to a numpy array for host packets and a device tensor otherwise."""
         d = Q.shape[0]
         g = _grid(d, M)
-        out = np.zeros(tuple(g.n[k] for k in range(d)),
-                       dtype=np.complex128 if precision == FP64 else np.complex64)
+        shape = tuple(g.n[k] for k in range(d))
+        if out is None:
+            if _on_device(Q):
+                import torch
+                out = torch.empty(shape, dtype=torch.complex128 if precision == FP64 else torch.complex64,
+                                  device=Q.device)
+            else:
+                out = np.zeros(shape, dtype=np.complex128 if precision == FP64 else np.complex64)
+        if _on_device(Q):
+            import torch
+            torch.cuda.current_stream().synchronize()  # packets must be written before submit
         pk = _packets(Q, P, S, a)
         t = ctypes.c_int64()
         _check(lib().fggc_server_submit(self.h, ctypes.byref(pk), float(eps), ctypes.byref(g),
                                         ctypes.byref(strategy) if strategy is not None else None,
-                                        float(scale), int(precision), out.ctypes.data,
+                                        float(scale), int(precision), _ptr(out),
                                         ctypes.byref(t)))
-        self._keep[t.value] = out
+        self._keep[t.value] = (out, Q, P, S, a)
         return t.value, out
 
     def wait(self, ticket: int, timeout_s: float = -1.0) -> int:
@@ -368,6 +382,14 @@ class Server:
                                        ctypes.byref(pps), ctypes.byref(n)))
         return {"p50_s": p50.value, "p99_s": p99.value, "packets_per_s": pps.value,
                 "completed": n.value}
+
+    def counters(self):
+        e, c, r = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().fggc_server_counters(self.h, ctypes.byref(e), ctypes.byref(c), ctypes.byref(r)))
+        return {"eager": e.value, "captured": c.value, "replayed": r.value}
+
+    def reset_stats(self):
+        _check(lib().fggc_server_reset_stats(self.h))
 
     def close(self):
         if getattr(self, "h", None):

@@ -1,0 +1,76 @@
+"""Summaries of rocprofv3 result databases (rocpd SQLite), as plain text.
+
+    python -m paper_2504_21785_amd.rocprof_summary kernels RUN_results.db
+        per kernel: calls, total and mean duration, share of GPU time
+    python -m paper_2504_21785_amd.rocprof_summary counter RUN_results.db COUNTER [--calib-mib M]
+        per kernel: mean counter value per dispatch; with --calib-mib, the
+        value of the plain elementwise copy kernel (reads and writes M MiB)
+        gives the factor that turns the counter's KiB into bytes
+
+Only reads the database; nothing here touches a GPU.
+"""
+import argparse
+import re
+import sqlite3
+import sys
+
+
+def short(name: str) -> str:
+    n = name.replace("(anonymous namespace)::", "").replace("fggc::", "")
+    n = re.sub(r"^void ", "", n)
+    n = re.sub(r"\(.*$", "", n)
+    return n[:90]
+
+
+def kernels(db):
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, count(*), sum(duration), avg(duration) from kernels "
+                     "group by name order by sum(duration) desc").fetchall()
+    tot = sum(r[2] for r in rows) or 1
+    out = [f"{'kernel':90s} {'calls':>6s} {'total_us':>12s} {'avg_us':>10s} {'pct':>6s}"]
+    for name, n, s, a in rows:
+        out.append(f"{short(name):90s} {n:6d} {s / 1e3:12.1f} {a / 1e3:10.2f} {100 * s / tot:6.2f}")
+    return "\n".join(out)
+
+
+def counter(db, name, calib_mib=None):
+    c = sqlite3.connect(db)
+    rows = c.execute("select kernel_name, dispatch_id, sum(value) from counters_collection "
+                     "where counter_name = ? group by kernel_name, dispatch_id", (name,)).fetchall()
+    per = {}
+    for k, _, v in rows:
+        per.setdefault(k, []).append(v)
+    factor = None
+    lines = []
+    if calib_mib:
+        cal = [sum(v) / len(v) for k, v in per.items() if "elementwise" in k]
+        if cal:
+            expect_kib = calib_mib * 1024.0
+            factor = expect_kib / max(cal)
+            lines.append(f"calibration: elementwise copy of {calib_mib} MiB reads {max(cal):.0f} KiB of "
+                         f"{name} per dispatch (expected {expect_kib:.0f}); factor {factor:.4f}")
+    lines.append(f"{'kernel':90s} {'dispatches':>10s} {'value/dispatch':>16s} {'x1024xfactor':>14s}")
+    for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        m = sum(v) / len(v)
+        b = m * 1024.0 * (factor if factor else 1.0)
+        lines.append(f"{short(k):90s} {len(v):10d} {m:16.1f} {b:14.4g}")
+    return "\n".join(lines)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["kernels", "counter"])
+    ap.add_argument("db")
+    ap.add_argument("name", nargs="?")
+    ap.add_argument("--calib-mib", type=float, default=None)
+    a = ap.parse_args(argv)
+    if a.what == "kernels":
+        print(kernels(a.db))
+    else:
+        if not a.name:
+            sys.exit("counter name required")
+        print(counter(a.db, a.name, a.calib_mib))
+
+
+if __name__ == "__main__":
+    main()

@@ -133,6 +133,8 @@ CONFIG_NAMES = {
     1: "1D FGGC vs direct sum, eps=1/1024, N=2^20 (1024x1024 (q,p)), M=16384, complex64",
     2: "2D FGGC vs direct sum, eps=1/256, N=2^22 (64^2 q x 32^2 p), M=1024^2, complex64",
     3: "3D FGGC, eps=1/128, N=2^24 (32^3 q x 8^3 p), M=256^3, complex64",
+    4: "serving stream: mixed 1D/2D requests, N log-uniform in 2^12..2^22, eps in {1/64,1/256,1/1024}, "
+       "M 2^10..2^14 (1D) or 256^2..1024^2 (2D), FGGC Q4P2, Poisson arrivals",
 }
 
 

@@ -1,0 +1,170 @@
+"""Serving (fggc_server_*) on the GPU through the C ABI.
+
+Each request's result from the server, submitted in a mix with others and
+repeated so that its pipeline runs eagerly, is captured into a graph and is
+replayed, must equal the same request run alone through the synchronous entry
+point, within the FP32 tolerance.  Requests follow the serving stream's
+distribution (mixed 1D/2D, eps, grid) with packet counts kept small here.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2504_21785_amd import fggc as F  # noqa: E402
+from paper_2504_21785_amd import workloads as W  # noqa: E402
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(u, ref):
+    n = np.linalg.norm(ref)
+    return float(np.linalg.norm(u - ref) / n) if n > 0 else float(np.linalg.norm(u))
+
+
+def small_requests(n_max=2 ** 17, count=8):
+    """The first `count` requests of the serving stream with N <= n_max,
+    covering both dimensions."""
+    out = []
+    for r in range(400):
+        u = W.uniform(W.BASE_SEED * 1000 + r, 10, 4)
+        N = int(math.floor(2.0 ** (12 + 10 * u[1])))
+        if N <= n_max:
+            out.append(W.serving_request(r))
+        if len(out) == count:
+            break
+    assert {p.d for p in out} == {1, 2}
+    return out
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = F.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def reqs():
+    return small_requests()
+
+
+def t(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def alone(ctx, ps, fggc=True):
+    st = F.default_strategy(ps.d, ps.eps, "Q4P2") if fggc else None
+    if fggc:
+        u = ctx.reconstruct(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, st, precision=F.FP32)
+    else:
+        u = ctx.direct_sum(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, 6 * math.sqrt(ps.eps), precision=F.FP32)
+    return np.asarray(u)
+
+
+def test_server_mix_equals_alone_host_inputs(ctx, reqs):
+    ref = [alone(ctx, ps) for ps in reqs]
+    srv = F.Server(ctx, n_streams=3)
+    try:
+        for rnd in range(3):  # eager, capture, replay
+            tickets = []
+            for ps in reqs:
+                st = F.default_strategy(ps.d, ps.eps, "Q4P2")
+                tickets.append(srv.submit(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, st))
+            for i, (tk, out) in enumerate(tickets):
+                rc = srv.wait(tk, 120.0)
+                assert rc == F.FGGC_OK, (i, rc, F.last_error())
+                e = rel(out, ref[i])
+                log(f"round {rnd} req {reqs[i].name} d={reqs[i].d} N={reqs[i].N} M={reqs[i].M} "
+                    f"eps={reqs[i].eps:.5f}: mix vs alone {e:.2e}")
+                assert e <= 1e-6
+        c = srv.counters()
+        log("counters", c, srv.stats())
+        assert c["captured"] >= 1 and c["replayed"] >= 1
+        assert c["eager"] + c["captured"] + c["replayed"] == 3 * len(reqs)
+        s = srv.stats()
+        assert s["completed"] == 3 * len(reqs) and s["p99_s"] >= s["p50_s"] > 0
+    finally:
+        srv.close()
+
+
+def test_server_device_inputs_and_direct(ctx, reqs):
+    srv = F.Server(ctx, n_streams=2)
+    try:
+        sub = reqs[:4]
+        dev = [(t(ps.Q), t(ps.P), t(ps.S), t(ps.a)) for ps in sub]
+        torch.cuda.synchronize()
+        tickets = []
+        for ps, (Q, P, S, a) in zip(sub, dev):
+            st = F.default_strategy(ps.d, ps.eps, "Q4P2")
+            tickets.append(("fggc", ps, srv.submit(Q, P, S, a, ps.eps, ps.M, st)))
+            tickets.append(("direct", ps, srv.submit(Q, P, S, a, ps.eps, ps.M, None)))
+        for kind, ps, (tk, out) in tickets:
+            rc = srv.wait(tk, 120.0)
+            assert rc == F.FGGC_OK, (kind, rc, F.last_error())
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            e = rel(got, alone(ctx, ps, fggc=(kind == "fggc")))
+            log(f"device {kind} {ps.name}: {e:.2e}")
+            assert e <= 1e-6
+    finally:
+        srv.close()
+
+
+def test_server_against_oracle(ctx, orc):
+    # a small 2D request with M = 256 < Nq = 512 (eps = 1/1024), sampled points
+    rng = np.random.default_rng(7)
+    N, eps = 3000, 1.0 / 1024
+    q = rng.uniform(-math.pi, math.pi, (2, N)) * 0.5
+    p = np.array([0.5, 0.3])[:, None] - 0.25 + 0.5 * rng.uniform(size=(2, N))
+    a = np.exp(-10 * np.sum(q * q, axis=0)) * np.exp(1j * rng.uniform(0, 2 * math.pi, N))
+    ps = W.PacketSet("srv2d", 2, eps, (256, 256), np.ascontiguousarray(W.wrap(q + 0.5 * p)),
+                     np.ascontiguousarray(p), rng.uniform(0, 2 * math.pi, N), a, 6 * math.sqrt(eps))
+    st = F.default_strategy(2, ps.eps, "Q4P2")
+    srv = F.Server(ctx, n_streams=1)
+    try:
+        tk, out = srv.submit(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, st)
+        assert srv.wait(tk, 120.0) == F.FGGC_OK, F.last_error()
+    finally:
+        srv.close()
+    sd = st.describe()
+    order = np.argsort(-np.abs(ps.a))[:40]
+    m = np.rint((ps.Q[:, order] + math.pi) / (2 * math.pi) * 256).astype(np.int64) % 256
+    pts = np.unique(np.ravel_multi_index((m[0], m[1]), (256, 256)))
+    ref = orc.fggc(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, sd["Nq"][:2], sd["dp"][:2], sd["dq_off"],
+                   sd["dp_off"], pts=pts)
+    e = rel(out.reshape(-1)[pts].astype(np.complex128), ref)
+    log("server 2D (M < Nq) vs oracle FGGC, sampled:", e)
+    assert e <= 1e-6
+
+
+def test_server_budget_and_timeout(ctx):
+    small = F.Context(0, hbm_budget_bytes=96 << 20)
+    srv = F.Server(small, n_streams=2)
+    try:
+        big = W.gen_mesh(2, 64, 32, 0.5, (0.5, 0.3), 1.0 / 256, 1024, seed=5)  # ~4M packets
+        st = F.default_strategy(2, big.eps, "Q4P2")
+        with pytest.raises(F.FggcError) as ei:
+            srv.submit(big.Q, big.P, big.S, big.a, big.eps, big.M, st)
+        assert ei.value.code == F.FGGC_EBUDGET
+        ps = W.gen_1d(64, 64, 1.0 / 256, 2048, seed=6)
+        st1 = F.default_strategy(1, ps.eps, "Q4P2")
+        tk, out = srv.submit(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, st1)
+        assert srv.wait(tk, 120.0) == F.FGGC_OK
+        assert rel(out, alone(ctx, ps)) <= 1e-6
+        assert srv.wait(tk, 1.0) == F.FGGC_EINVAL  # already waited
+        # empty request completes at once with zeros
+        e = np.zeros((1, 0))
+        tk, out = srv.submit(e, e, np.zeros(0), np.zeros(0, complex), ps.eps, ps.M, st1)
+        assert srv.wait(tk, 10.0) == F.FGGC_OK and not np.any(out)
+    finally:
+        srv.close()
+        small.close()
