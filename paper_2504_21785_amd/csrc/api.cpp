@@ -330,6 +330,96 @@ int64_t prod3(const int64_t *v, int d) {
   return p;
 }
 
+namespace {
+
+// The workspace is shared by the calls on a context: a call on a different
+// stream than the previous one makes its stream wait (on the device) for the
+// event recorded after the previous call's work.
+struct WsUse {
+  fggc_ctx *ctx;
+  hipStream_t s;
+  WsUse(fggc_ctx *c, hipStream_t st) : ctx(c), s(st) {
+    if (ctx->has_last && ctx->last_stream != s) FGGC_HIP(hipStreamWaitEvent(s, ctx->ws_event, 0));
+  }
+  ~WsUse() {
+    if (hipEventRecord(ctx->ws_event, s) == hipSuccess) {
+      ctx->last_stream = s;
+      ctx->has_last = true;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+};
+
+void clear_graphs(fggc_ctx *ctx) {
+  for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.second);
+  ctx->graphs.clear();
+}
+
+int64_t dbits(double x) {
+  int64_t b;
+  std::memcpy(&b, &x, 8);
+  return b;
+}
+
+constexpr size_t kCtxGraphs = 8;
+
+// Run `launch(stream)` on s, through a cached executable graph when the same
+// key (shape, buffers and workspace) has been seen before: the first sighting
+// runs eagerly, the second is captured on the context's capture stream, later
+// ones replay the graph.  A capture that fails falls back to eager runs for
+// that key.
+template <class F> void run_cached(fggc_ctx *ctx, std::vector<int64_t> key, hipStream_t s, F &&launch) {
+  if (ctx->graphs_ws != ctx->ws.base()) {
+    clear_graphs(ctx);
+    ctx->seen.clear();
+    ctx->graphs_ws = ctx->ws.base();
+  }
+  key.push_back((int64_t)(uintptr_t)ctx->ws.base());
+  key.push_back((int64_t)ctx->ws.capacity());
+  for (auto it = ctx->graphs.begin(); it != ctx->graphs.end(); ++it)
+    if (it->first == key) {
+      ctx->graphs.splice(ctx->graphs.begin(), ctx->graphs, it);
+      FGGC_HIP(hipGraphLaunch(ctx->graphs.front().second, s));
+      return;
+    }
+  if (ctx->seen.size() > 4096) ctx->seen.clear();
+  int &n = ctx->seen[key];
+  const size_t mark = ctx->ws.mark();
+  if (++n >= 2) {
+    hipStream_t cs = ctx->cap_stream;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      try {
+        launch(cs);
+      } catch (...) {
+        ok = false;
+      }
+      if (hipStreamEndCapture(cs, &graph) != hipSuccess) ok = false;
+      if (ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) ok = false;
+      if (graph) (void)hipGraphDestroy(graph);
+    }
+    if (ok) {
+      if (ctx->graphs.size() >= kCtxGraphs) {
+        (void)hipGraphExecDestroy(ctx->graphs.back().second);
+        ctx->graphs.pop_back();
+      }
+      ctx->graphs.emplace_front(key, exec);
+      FGGC_HIP(hipGraphLaunch(exec, s));
+      return;
+    }
+    (void)hipGetLastError();
+    if (exec) (void)hipGraphExecDestroy(exec);
+    n = -(1 << 30);
+    ctx->ws.rewind(mark);
+  }
+  launch(s);
+}
+
+}  // namespace
+
 }  // namespace fggc
 
 using namespace fggc;
@@ -358,6 +448,8 @@ int fggc_create(fggc_ctx **out, int device, size_t hbm_budget_bytes) {
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
     try {
       FGGC_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      FGGC_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      FGGC_HIP(hipEventCreateWithFlags(&c->ws_event, hipEventDisableTiming));
       FGGC_HIP(hipMalloc((void **)&c->dev_scan, packet_scan_bytes() + 256));
       FGGC_HIP(hipHostMalloc((void **)&c->host_scan, 256, hipHostMallocDefault));
     } catch (...) {
@@ -372,6 +464,12 @@ void fggc_destroy(fggc_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ws_event) {
+    (void)hipEventSynchronize(ctx->ws_event);
+    (void)hipEventDestroy(ctx->ws_event);
+  }
+  clear_graphs(ctx);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->dev_scan) (void)hipFree(ctx->dev_scan);
   if (ctx->host_scan) (void)hipHostFree(ctx->host_scan);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -407,6 +505,7 @@ int direct_impl(const char *what, fggc_ctx *ctx, const fggc_packets *pk, double 
     }
     Guard lock(ctx);
     hipStream_t s = (hipStream_t)stream;
+    WsUse wsu(ctx, s);
     const size_t out_bytes = (size_t)npts * (precision == FGGC_FP64 ? 16 : 8);
     const bool host_in = packets_on_host(*pk);
     const bool host_out = !device_accessible(u_out);
@@ -462,6 +561,7 @@ int fggc_cell_box(fggc_ctx *ctx, const fggc_packets *pk, const fggc_strategy *st
     check_strategy(st, pk->d);
     Guard lock(ctx);
     hipStream_t s = (hipStream_t)stream;
+    WsUse wsu(ctx, s);
     const bool host_in = packets_on_host(*pk);
     fggc_packets dpk = *pk;
     ctx->ws.reserve(staging_bytes(*pk, host_in, 0, false) + 256, ctx->budget);
@@ -490,6 +590,7 @@ int fggc_cells(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_str
     if (precision != FGGC_FP32 && precision != FGGC_FP64) fail(FGGC_EINVAL, "bad precision");
     Guard lock(ctx);
     hipStream_t s = (hipStream_t)stream;
+    WsUse wsu(ctx, s);
     int64_t slo[3] = {0, 0, 0}, sn[3] = {1, 1, 1};
     for (int k = 0; k < d; ++k) {
       slo[k] = slice_lo[k];
@@ -501,8 +602,8 @@ int fggc_cells(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_str
     const bool host_in = packets_on_host(*pk);
     const bool host_out = !device_accessible(cells_out);
     fggc_packets dpk = *pk;
-    DimLsq lsq[3];
-    for (int k = 0; k < d; ++k) build_dim_lsq(*st, k, eps, &lsq[k]);
+    const Plan plan = plan_for(*st, d, eps);
+    const DimLsq *lsq = plan.host;
     GridGeom g{};
     g.d = d;
     for (int k = 0; k < 3; ++k) {
@@ -511,6 +612,7 @@ int fggc_cells(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_str
     }
     FggcArgs fa{};
     fill_fggc_args(fa, &dpk, eps, g, *st, scale, precision, lsq, slo, sn);
+    fa.lsq_dev = plan.dev;
     ctx->ws.reserve(staging_bytes(*pk, host_in, bytes, host_out) + fggc_cells_workspace_bytes(fa),
                     ctx->budget);
     if (host_in) dpk = stage_packets(*pk, (char *)ctx->ws.take((size_t)pk->N * (2 * d + 3) * 8), s);
@@ -553,6 +655,7 @@ int fggc_reconstruct(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fg
         fail(FGGC_EUNSUPPORTED, "FGGC needs power-of-two grid sizes in [2, " + std::to_string(maxM) + "]");
     Guard lock(ctx);
     hipStream_t s = (hipStream_t)stream;
+    WsUse wsu(ctx, s);
     const int64_t npts = prod3(g.n, d);
     const size_t out_bytes = (size_t)npts * (precision == FGGC_FP64 ? 16 : 8);
     const bool host_in = packets_on_host(*pk);
@@ -571,10 +674,10 @@ int fggc_reconstruct(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fg
     prepass(ctx, dpk, st->dp, s);
     int64_t slo[3], sn[3];
     cell_box(ctx, dpk, *st, slo, sn);
-    DimLsq lsq[3];
-    for (int k = 0; k < d; ++k) build_dim_lsq(*st, k, eps, &lsq[k]);
+    const Plan plan = plan_for(*st, d, eps);
     FggcArgs fa{};
-    fill_fggc_args(fa, &dpk, eps, g, *st, scale, precision, lsq, slo, sn);
+    fill_fggc_args(fa, &dpk, eps, g, *st, scale, precision, plan.host, slo, sn);
+    fa.lsq_dev = plan.dev;
     // the staged packets must survive the re-reservation: reserve everything once more
     const size_t stage_b = staging_bytes(*pk, host_in, out_bytes, host_out);
     const size_t need = stage_b + fggc_workspace_bytes(fa);
@@ -591,7 +694,22 @@ int fggc_reconstruct(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fg
     fa.pk = &dpk;
     fa.u = host_out ? ctx->ws.take(out_bytes) : u_out;
     fa.prof = ctx->profiling ? &ctx->prof : nullptr;
-    launch_fggc(fa, ctx->ws, s);
+    if (!host_in && !host_out && !ctx->profiling && plan.dev) {
+      std::vector<int64_t> key = {1, d, precision, dpk.N, dbits(eps), dbits(scale),
+                                  (int64_t)(uintptr_t)dpk.Q, (int64_t)(uintptr_t)dpk.P,
+                                  (int64_t)(uintptr_t)dpk.S, (int64_t)(uintptr_t)dpk.a,
+                                  (int64_t)(uintptr_t)u_out, (int64_t)(uintptr_t)plan.dev};
+      for (int k = 0; k < 3; ++k) {
+        key.push_back(g.n[k]);
+        key.push_back(slo[k]);
+        key.push_back(sn[k]);
+        key.push_back(st->Nq[k]);
+        key.push_back(dbits(st->dp[k]));
+      }
+      run_cached(ctx, std::move(key), s, [&](hipStream_t ls) { launch_fggc(fa, ctx->ws, ls); });
+    } else {
+      launch_fggc(fa, ctx->ws, s);
+    }
     if (host_out) {
       FGGC_HIP(hipMemcpyAsync(u_out, fa.u, out_bytes, hipMemcpyDeviceToHost, s));
       FGGC_HIP(hipStreamSynchronize(s));
@@ -633,6 +751,7 @@ int fggc_fft(fggc_ctx *ctx, int d, const int64_t *n, int64_t batch, int directio
         fail(FGGC_EUNSUPPORTED, "FFT sizes must be powers of two in [2, " + std::to_string(maxn) + "]");
     Guard lock(ctx);
     hipStream_t s = (hipStream_t)stream;
+    WsUse wsu(ctx, s);
     if (!device_accessible(data)) fail(FGGC_EINVAL, "fggc_fft needs device memory");
     if (batch == 0) return;
     ctx->ws.reserve(fft_workspace_bytes(d, n, precision, batch), ctx->budget);

@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 #include <exception>
+#include <list>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -48,6 +50,7 @@ class Workspace {
   void set_stream(hipStream_t s) { stream_ = s; has_stream_ = true; }
   void *take(size_t bytes);                   // 256-byte aligned slice
   size_t capacity() const { return cap_; }
+  const void *base() const { return base_; }
 
  private:
   char *base_ = nullptr;
@@ -122,6 +125,15 @@ struct DimLsq {
 void hermitian_eig(int n, const double *A, double *evals, double *evecs);
 void build_dim_lsq(const fggc_strategy &st, int dim, double eps, DimLsq *out);
 
+// The plan of a (strategy, d, eps) on the current device: host copy and a
+// device copy uploaded once and kept for the life of the process (dev is null
+// when the cache is full; the caller then copies `host` itself).
+struct Plan {
+  DimLsq host[3];
+  const DimLsq *dev = nullptr;
+};
+Plan plan_for(const fggc_strategy &st, int d, double eps);
+
 // --------------------------------------------------------------------------
 // device-side parameter blocks (passed by value to kernels)
 // --------------------------------------------------------------------------
@@ -168,12 +180,15 @@ void launch_zero(void *p, size_t bytes, hipStream_t s);
 void launch_pad_packets(int d, int64_t N, int64_t Npad, double *Q, double *P, double *S, double *a,
                         hipStream_t s);
 
-// Stable counting sort of indices 0..N-1 by keys[i] in [0, nbins): order[]
-// grouped by key, start[b] first position of key b (start[nbins] = N).
-// `scratch` holds bucket_sort_bytes(N, nbins); keys may be overwritten.
-size_t bucket_sort_bytes(int64_t N, int64_t nbins);
-void bucket_sort(uint32_t *keys, int64_t N, int64_t nbins, uint32_t *order, int64_t *start,
-                 void *scratch, hipStream_t s);
+// Counting sort positions: for slot i with keys[i] in [0, nbins), pos[i] is
+// its position in key order; slots with keys[i] == kNoKey get kNoKey.
+// start[b] = first position of key b, start[nbins] = number of keyed slots.
+// The order of slots inside one key is unspecified.  `scratch` holds
+// bucket_positions_bytes(N, nbins).
+constexpr uint32_t kNoKey = 0xffffffffu;
+size_t bucket_positions_bytes(int64_t N, int64_t nbins);
+void bucket_positions(const uint32_t *keys, int64_t N, int64_t nbins, uint32_t *pos, int64_t *start,
+                      void *scratch, hipStream_t s);
 
 // Direct sum.  Returns after enqueuing; `ws` supplies scratch.
 struct DirectArgs {
@@ -194,7 +209,8 @@ struct FggcArgs {
   double eps, scale;
   GridGeom g;
   int precision;
-  const DimLsq *lsq;  // [d]
+  const DimLsq *lsq;  // [d], host
+  const DimLsq *lsq_dev = nullptr;  // [d], device copy when the plan is cached
   int64_t Nq[3];
   double dp[3];
   int64_t slo[3], sn[3];  // p-cell box
@@ -265,4 +281,14 @@ struct fggc_ctx {
   bool profiling = false;
   fggc::Profiler prof;
   std::mutex mu;
+  // the stream that last used the workspace and an event recorded after that
+  // use (a call on another stream waits for it)
+  hipStream_t last_stream = nullptr;
+  bool has_last = false;
+  hipEvent_t ws_event = nullptr;
+  // executable graphs of repeated device-resident reconstructions, most recent first
+  hipStream_t cap_stream = nullptr;
+  std::list<std::pair<std::vector<int64_t>, hipGraphExec_t>> graphs;
+  std::map<std::vector<int64_t>, int> seen;
+  const void *graphs_ws = nullptr;
 };

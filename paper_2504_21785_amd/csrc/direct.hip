@@ -2,11 +2,12 @@
 // point within its window, on gfx950.
 //
 // Pipeline (all on the caller's stream):
-//   1. ds_prep     per packet: nearest grid index and offset, the phase at that
-//                  point and its per-step increment (revolutions, FP64, reduced
-//                  mod 1), log|scale a|, and a spatial bin key;
-//   2. bucket sort (stable counting sort in LDS, sort.hip) of packets by bin,
-//                  then a gather of the records into bin order;
+//   1. ds_key      per packet: its spatial bin (from its nearest grid index);
+//   2. positions   counting sort of the bins (sort.hip), then ds_prep writes
+//                  each packet's record straight to its sorted position: the
+//                  nearest grid index and offset, the phase at that point and
+//                  its per-step increment (revolutions, FP64, reduced mod 1),
+//                  and log|scale a|;
 //   3. ds_kernel   gather: a workgroup owns a tile of output points and walks
 //                  the packets of the bins its tile can see.  Packet records
 //                  are wave-uniform and are read into scalar registers through
@@ -46,27 +47,44 @@ struct PrepParams {
   int64_t binw[3], nbin[3];
 };
 
-__global__ void ds_prep_kernel(PrepParams p, DsRec *__restrict__ rec, uint32_t *__restrict__ key) {
+// nearest grid index of coordinate q (position from x_0 = -pi wrapped into
+// [0, 2 pi)) and the offset Q - x_m, |offset| <= dx/2
+__device__ __forceinline__ int64_t nearest_index(double q, double dx, int64_t n, double &delta) {
+  const double t = (q + kPi) - kTwoPi * floor((q + kPi) / kTwoPi);
+  const double m = rint(t / dx);
+  delta = fma(-m, dx, t);
+  int64_t mi = (int64_t)m;
+  if (mi >= n) mi -= n;
+  return mi;
+}
+
+__global__ void ds_key_kernel(PrepParams p, uint32_t *__restrict__ key) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= p.N) return;
+  uint32_t bin = 0;
+  for (int k = 0; k < p.d; ++k) {
+    double delta;
+    const int64_t mi = nearest_index(p.Q[k * p.N + j], p.dx[k], p.n[k], delta);
+    bin = bin * (uint32_t)p.nbin[k] + (uint32_t)(mi / p.binw[k]);
+  }
+  key[j] = bin;
+}
+
+__global__ void ds_prep_kernel(PrepParams p, const uint32_t *__restrict__ pos, DsRec *__restrict__ rec) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= p.N) return;
   DsRec r;
   r.pad = 0;
-  for (int k = 0; k < 3; ++k) r.deltaf[k] = 0.0f;
-  double pdelta = 0.0;
-  uint32_t bin = 0;
   for (int k = 0; k < 3; ++k) {
+    r.deltaf[k] = 0.0f;
     r.mq[k] = 0;
     r.delta[k] = 0.0;
     r.omega[k] = 0.0;
   }
+  double pdelta = 0.0;
   for (int k = 0; k < p.d; ++k) {
-    const double q = p.Q[k * p.N + j];
-    // position measured from x_0 = -pi, wrapped into [0, 2 pi)
-    const double t = (q + kPi) - kTwoPi * floor((q + kPi) / kTwoPi);
-    const double m = rint(t / p.dx[k]);
-    const double delta = fma(-m, p.dx[k], t);  // Q - x_m, |delta| <= dx/2
-    int64_t mi = (int64_t)m;
-    if (mi >= p.n[k]) mi -= p.n[k];
+    double delta;
+    const int64_t mi = nearest_index(p.Q[k * p.N + j], p.dx[k], p.n[k], delta);
     r.mq[k] = (int32_t)mi;
     r.delta[k] = delta;
     r.deltaf[k] = (float)delta;
@@ -74,21 +92,13 @@ __global__ void ds_prep_kernel(PrepParams p, DsRec *__restrict__ rec, uint32_t *
     pdelta = fma(Pk, delta, pdelta);
     const double w = Pk / (p.eps * (double)p.n[k]);  // P dx / (2 pi eps)
     r.omega[k] = w - floor(w);
-    bin = bin * (uint32_t)p.nbin[k] + (uint32_t)(mi / p.binw[k]);
   }
   const double are = p.scale * p.a[2 * j], aim = p.scale * p.a[2 * j + 1];
   r.lnamp = log(hypot(are, aim));
   r.la2 = (float)(r.lnamp * 1.4426950408889634);
   const double ph = (p.S[j] - pdelta) / (kTwoPi * p.eps) + atan2(aim, are) * (1.0 / kTwoPi);
   r.phi0 = ph - floor(ph);
-  rec[j] = r;
-  key[j] = bin;
-}
-
-__global__ void gather_rec_kernel(int64_t N, const uint32_t *__restrict__ idx,
-                                  const DsRec *__restrict__ in, DsRec *__restrict__ out) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < N) out[i] = in[idx[i]];
+  rec[pos[j]] = r;
 }
 
 // Lane / sub-tile / wave layout of a workgroup tile for each dimension count.
@@ -409,7 +419,7 @@ struct DsLayout {
   int64_t span[3], binw[3], nbin[3], ntile[3], W[3];
   int64_t nbins, ntiles, npts;
   int nchunk;
-  size_t off_rec, off_rec2, off_keys, off_order, off_start, off_part, off_sort, total;
+  size_t off_rec, off_keys, off_pos, off_start, off_part, off_sort, total;
 };
 
 DsLayout ds_layout(const DirectArgs &a) {
@@ -449,12 +459,11 @@ DsLayout ds_layout(const DirectArgs &a) {
     return at;
   };
   L.off_rec = put(N * sizeof(DsRec));
-  L.off_rec2 = put(N * sizeof(DsRec));
   L.off_keys = put(N * 4);
-  L.off_order = put(N * 4);
+  L.off_pos = put(N * 4);
   L.off_start = put((L.nbins + 1) * 8);
   L.off_part = put((size_t)L.nchunk * L.npts * 16);
-  L.off_sort = put(bucket_sort_bytes(a.pk->N, L.nbins));
+  L.off_sort = put(bucket_positions_bytes(a.pk->N, L.nbins));
   L.total = o;
   return L;
 }
@@ -467,8 +476,8 @@ void launch_direct(const DirectArgs &a, Workspace &ws, hipStream_t s) {
   const DsLayout L = ds_layout(a);
   const bool f64 = a.precision == FGGC_FP64;
   char *base = (char *)ws.take(L.total);
-  DsRec *rec = (DsRec *)(base + L.off_rec), *rec2 = (DsRec *)(base + L.off_rec2);
-  uint32_t *keys = (uint32_t *)(base + L.off_keys), *order = (uint32_t *)(base + L.off_order);
+  DsRec *rec = (DsRec *)(base + L.off_rec);
+  uint32_t *keys = (uint32_t *)(base + L.off_keys), *pos = (uint32_t *)(base + L.off_pos);
   int64_t *start = (int64_t *)(base + L.off_start);
   double *part = (double *)(base + L.off_part);
   const int64_t N = a.pk->N;
@@ -488,19 +497,20 @@ void launch_direct(const DirectArgs &a, Workspace &ws, hipStream_t s) {
       pp.binw[k] = L.binw[k];
       pp.nbin[k] = L.nbin[k];
     }
+    const dim3 g((unsigned)((N + 255) / 256)), b(256);
     {
-      StageScope sc(a.prof, "ds_prep", s);
-      ds_prep_kernel<<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s>>>(pp, rec, keys);
+      StageScope sc_sort(a.prof, "ds_sort", s);
+      ds_key_kernel<<<g, b, 0, s>>>(pp, keys);
       FGGC_HIP(hipGetLastError());
+      bucket_positions(keys, N, L.nbins, pos, start, base + L.off_sort, s);
     }
-    StageScope sc_sort(a.prof, "ds_sort", s);
-    bucket_sort(keys, N, L.nbins, order, start, base + L.off_sort, s);
-    gather_rec_kernel<<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s>>>(N, order, rec, rec2);
+    StageScope sc(a.prof, "ds_prep", s);
+    ds_prep_kernel<<<g, b, 0, s>>>(pp, pos, rec);
     FGGC_HIP(hipGetLastError());
   }
   if (N > 0) {
     DsParams p{};
-    p.rec = rec2;
+    p.rec = rec;
     p.start = start;
     for (int k = 0; k < 3; ++k) {
       p.n[k] = k < L.D ? a.g.n[k] : 1;

@@ -1,17 +1,19 @@
 // Frozen Gaussian grid-point correction on gfx950 (Section 2.3, Alg. 2).
 //
-//   fggc_key      per packet: its own cell (int parts of eq. 3.6) -> bin key
-//                 (p-cell major, q-tile minor); radix sort of the packets by bin.
-//   fggc_coef     one thread per packet, in bin order, FP64: frac parts (3.7),
-//                 right-hand side (3.23), least squares through the plan's
-//                 eigenpairs (c^ = V diag(1/lambda) V^H f~), conjugation to the
-//                 L2-best coefficients, shift (3.13); the per-dimension
+//   fggc_key      per packet: its own cell (int parts of eq. 3.6) -> bin keys
+//                 (p-cell major, q-tile minor), one key slot per q-tile that
+//                 its shifted neighbours reach; counting-sort positions of the
+//                 slots (sort.hip).
+//   fggc_coef     one thread per packet, in packet order, FP64: frac parts
+//                 (3.7), right-hand side (3.23), least squares through the
+//                 plan's eigenpairs (c^ = V diag(1/lambda) V^H f~), conjugation
+//                 to the L2-best coefficients, shift (3.13); the per-dimension
 //                 coefficients (the first times scale a exp(i S/eps)) are
-//                 written as one record per packet.
+//                 written as one record at the sorted position of every slot.
 //   fggc_accum    owner-computes form of eq. (2.23)-(2.25): one workgroup per
-//                 (p-slice, q-tile) of the dense cell array accumulates, in LDS,
-//                 the Kronecker products of every packet of the bins that reach
-//                 it, then writes each of its cells once.
+//                 (window of p-slices, q-tile) of the dense cell array
+//                 accumulates, in LDS, the Kronecker products of the packets in
+//                 its tile's bins, then writes each of its cells once.
 //   fft over q    forward DFT of every p-slice of the cell array (fft.hip).
 //   band_mac      owner-computes over the grid spectrum: for each frequency
 //                 k' of the M-point grid, the sum over slices l and aliases
@@ -149,39 +151,66 @@ __device__ __forceinline__ void dim_coeffs(const DimLsq &L, double Q, double P, 
   }
 }
 
-// Sort key of a packet: its own p-cell (relative to the box of packet p-cells)
-// major, its q-tile minor.  Packets of one key form one bin.
+// Sort keys of a packet: its own p-cell (relative to the box of packet
+// p-cells) major, a q-tile minor -- one key slot for every q-tile its
+// neighbours [q + mindq, q + maxdq] reach (at most two per dimension, as a
+// tile is at least as wide as the shift set), so that a workgroup owning a
+// tile finds every packet that touches it in that tile's own bins.
 struct KeyParams {
   int64_t N;
   const double *Q, *P;
   int64_t Nq[3], pmin[3], npc[3], tile[3], ntq[3];
   double dq[3], dp[3];
+  int mindq, maxdq;
+  int ns;  // key slots per packet: 2^d with halo slots, 1 for the own tile only
 };
 
 template <int D>
 __global__ void fggc_key_kernel(KeyParams p, uint32_t *__restrict__ key) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= p.N) return;
-  int64_t kp = 0, kq = 0;
+  int64_t pcf = 0, nqt = 1, ta[3], tb[3];
   for (int k = 0; k < D; ++k) {
     int64_t iq, ip;
     double s, t;
     int_frac(p.Q[k * p.N + j] / p.dq[k], iq, s);
     int_frac(p.P[k * p.N + j] / p.dp[k], ip, t);
-    const int64_t qi = (iq + p.Nq[k] / 2) & (p.Nq[k] - 1);
+    const int64_t msk = p.Nq[k] - 1;
+    const int64_t qi = (iq + p.Nq[k] / 2) & msk;
     // the cell box comes from the same floor(P/dp), so this clamp never binds;
     // it keeps every key inside [0, nbins) whatever the caller's box
     int64_t pc = ip - p.pmin[k];
     pc = pc < 0 ? 0 : (pc >= p.npc[k] ? p.npc[k] - 1 : pc);
-    kp = kp * p.npc[k] + pc;
-    kq = kq * p.ntq[k] + qi / p.tile[k];
+    pcf = pcf * p.npc[k] + pc;
+    if (p.ns == 1) {
+      ta[k] = tb[k] = qi / p.tile[k];
+    } else {
+      ta[k] = ((qi + p.mindq) & msk) / p.tile[k];
+      tb[k] = ((qi + p.maxdq) & msk) / p.tile[k];
+    }
+    nqt *= p.ntq[k];
   }
-  int64_t nqt = 1;
-  for (int k = 0; k < D; ++k) nqt *= p.ntq[k];
-  key[j] = (uint32_t)(kp * nqt + kq);
+  if (p.ns == 1) {
+    int64_t tf = 0;
+    for (int k = 0; k < D; ++k) tf = tf * p.ntq[k] + ta[k];
+    key[j] = (uint32_t)(pcf * nqt + tf);
+    return;
+  }
+  constexpr int NS = 1 << D;
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+    bool ok = true;
+    int64_t tf = 0;
+    for (int k = 0; k < D; ++k) {
+      const int bit = (m >> k) & 1;
+      if (bit && tb[k] == ta[k]) ok = false;
+      tf = tf * p.ntq[k] + (bit ? tb[k] : ta[k]);
+    }
+    key[j * NS + m] = ok ? (uint32_t)(pcf * nqt + tf) : kNoKey;
+  }
 }
 
-// Record of one packet in bin order: its q index and p-cell (relative) per
+// Record of one packet (one per key slot, in bin order): its q index and p-cell (relative) per
 // dimension, then the per-dimension least-squares coefficients c_d[a*np+b]
 // (after conjugation and shift), the first dimension's multiplied by
 // scale * a exp(i S / eps).
@@ -192,6 +221,7 @@ template <int D, int N1, typename T> __host__ __device__ constexpr int rec_bytes
 }
 
 struct CoefParams {
+  int ns;  // key slots per packet
   int64_t N;
   const double *Q, *P, *S, *a;
   double eps, scale;
@@ -200,13 +230,14 @@ struct CoefParams {
   double dq[3], dp[3];
 };
 
+// One thread per packet, in packet order (coalesced reads); the record is
+// written to the sorted position of each of the packet's key slots.
 template <int D, int N1, typename T>
-__global__ __launch_bounds__(256) void fggc_coef_kernel(CoefParams p, const uint32_t *__restrict__ order,
+__global__ __launch_bounds__(256) void fggc_coef_kernel(CoefParams p, const uint32_t *__restrict__ pos,
                                                         char *__restrict__ recs) {
   using R = decltype(T{}.x);
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= p.N) return;
-  const int64_t j = order[i];
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= p.N) return;
   double cre[D][N1], cim[D][N1];
   int64_t iq[D], ip[D];
 #pragma unroll
@@ -220,15 +251,13 @@ __global__ __launch_bounds__(256) void fggc_coef_kernel(CoefParams p, const uint
   }
   const double ar = p.scale * p.a[2 * j], ai = p.scale * p.a[2 * j + 1];
   const double alr = ar * cs - ai * sn, ali = ar * sn + ai * cs;
-  char *r = recs + i * (int64_t)rec_bytes<D, N1, T>();
   RecIdx<D> ri;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     ri.q[k] = (int32_t)((iq[k] + p.Nq[k] / 2) & (p.Nq[k] - 1));
     ri.pc[k] = (int32_t)(ip[k] - p.pmin[k]);
   }
-  *reinterpret_cast<RecIdx<D> *>(r) = ri;
-  T *c = reinterpret_cast<T *>(r + rec_idx_bytes<D>());
+  T cv[D][N1];
 #pragma unroll
   for (int k = 0; k < D; ++k)
 #pragma unroll
@@ -239,176 +268,179 @@ __global__ __launch_bounds__(256) void fggc_coef_kernel(CoefParams p, const uint
         xi = alr * xi + ali * xr;
         xr = nr;
       }
-      c[k * N1 + m] = T{(R)xr, (R)xi};
+      cv[k][m] = T{(R)xr, (R)xi};
     }
+  constexpr int NS = 1 << D;
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+    if (m >= p.ns) break;
+    const uint32_t at = pos[j * p.ns + m];
+    if (at == kNoKey) continue;
+    char *r = recs + (int64_t)at * rec_bytes<D, N1, T>();
+    *reinterpret_cast<RecIdx<D> *>(r) = ri;
+    T *c = reinterpret_cast<T *>(r + rec_idx_bytes<D>());
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+      for (int n = 0; n < N1; ++n) c[k * N1 + n] = cv[k][n];
+  }
 }
 
-// Owner-computes accumulation of eq. (2.25): one workgroup per (p-slice,
-// q-tile) of the cell array holds its cells in LDS, adds the contributions of
-// every packet of the bins that can reach it, and writes each of its cells
-// exactly once (no zeroing pass, no global atomics).
+// Owner-computes accumulation of eq. (2.25): one workgroup per (window of
+// S slices per dimension, q-tile) of the cell array holds those cells in LDS,
+// adds the contributions of the packets in the bins of its own tile (halo
+// packets are binned into every tile they touch) for the p-cells that reach
+// its slices, and writes each of its cells exactly once (no zeroing pass, no
+// global atomics).
 struct AccParams {
   const char *recs;
   const int64_t *start;
-  int64_t sn[3], npc[3], Nq[3], tile[3], ntq[3];
+  int64_t sn[3], npc[3], Nq[3], tile[3], ntq[3], S[3], nsw[3];
   int nq, np;
   int dq[8], dp[8];
-  int mindp, maxdp, mindq, maxdq;
-  int bofs[32];  // dp value - mindp -> index b, or -1
+  int mindp, maxdp;
 };
 
 template <int D, int N1, typename T>
-__global__ __launch_bounds__(256) void fggc_accum_kernel(AccParams p, T *__restrict__ cells) {
+__global__ __launch_bounds__(256) void fggc_accum_generic_kernel(AccParams p, T *__restrict__ cells) {
   using R = decltype(T{}.x);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R *lre = reinterpret_cast<R *>(smem_raw);
-  int64_t tcells = 1, nqt_all = 1, ncell_q = 1;
+  int64_t tq_cells = 1, sw_cells = 1, nqt_all = 1, ncell_q = 1;
   for (int k = 0; k < D; ++k) {
-    tcells *= p.tile[k];
+    tq_cells *= p.tile[k];
+    sw_cells *= p.S[k];
     nqt_all *= p.ntq[k];
     ncell_q *= p.Nq[k];
   }
+  const int64_t tcells = tq_cells * sw_cells;
   R *lim = lre + tcells;
   for (int64_t e = threadIdx.x; e < tcells; e += blockDim.x) {
     lre[e] = 0;
     lim[e] = 0;
   }
-  // which slice and q-tile this workgroup owns
-  int64_t blk = blockIdx.x, tq[3] = {0, 0, 0}, sl[3] = {0, 0, 0};
+  // this workgroup's q-tile (minor) and slice window (major)
+  int64_t blk = blockIdx.x, tq[3] = {0, 0, 0}, w[3] = {0, 0, 0};
   for (int k = D - 1; k >= 0; --k) {
     tq[k] = blk % p.ntq[k];
     blk /= p.ntq[k];
   }
   for (int k = D - 1; k >= 0; --k) {
-    sl[k] = blk % p.sn[k];
-    blk /= p.sn[k];
+    w[k] = blk % p.nsw[k];
+    blk /= p.nsw[k];
   }
-  // packet p-cells that reach slice sl: pc in [sl + mindp - maxdp, sl], clipped
-  int64_t pc0[3], pcn[3];
-  // packet q bins that reach the tile: q in [t T - maxdq, t T + T - 1 - mindq] mod Nq
-  int64_t ia[3][2], ic[3][2], ilen[3][2];
-  int nint[3];
+  // slices [s0, s1) per dimension; packet p-cells reaching them: slice =
+  // pc + dp - mindp, so pc in [s0 - (maxdp - mindp), s1 - 1]
+  int64_t s0[3], s1[3], pc0[3], pcn[3];
+  bool any = true;
   for (int k = 0; k < 3; ++k) {
+    s0[k] = 0;
+    s1[k] = 1;
     pc0[k] = 0;
     pcn[k] = 1;
-    nint[k] = 1;
-    ia[k][0] = ic[k][0] = 0;
-    ilen[k][0] = 1;
-    ilen[k][1] = 0;
   }
   for (int k = 0; k < D; ++k) {
-    int64_t a = sl[k] + p.mindp - p.maxdp, b = sl[k];
+    s0[k] = w[k] * p.S[k];
+    s1[k] = min(s0[k] + p.S[k], p.sn[k]);
+    int64_t a = s0[k] - (p.maxdp - p.mindp), b = s1[k] - 1;
     if (a < 0) a = 0;
     if (b > p.npc[k] - 1) b = p.npc[k] - 1;
     pc0[k] = a;
-    pcn[k] = b - a + 1;  // may be <= 0: nothing reaches this slice
-    const int64_t nk = p.Nq[k], bw = p.tile[k], nb = p.ntq[k];
-    const int64_t lo = tq[k] * bw - p.maxdq, hi = tq[k] * bw + bw - 1 - p.mindq;
-    if (hi - lo + 1 >= nk) {
-      ia[k][0] = 0;
-      ic[k][0] = nb - 1;
-    } else {
-      const int64_t lm = ((lo % nk) + nk) % nk, hm = ((hi % nk) + nk) % nk;
-      if (lm <= hm) {
-        ia[k][0] = lm / bw;
-        ic[k][0] = hm / bw;
-      } else if (hm / bw + 1 >= lm / bw) {
-        ia[k][0] = 0;
-        ic[k][0] = nb - 1;
-      } else {
-        nint[k] = 2;
-        ia[k][0] = lm / bw;
-        ic[k][0] = nb - 1;
-        ia[k][1] = 0;
-        ic[k][1] = hm / bw;
-      }
-    }
-    ilen[k][0] = ic[k][0] - ia[k][0] + 1;
-    ilen[k][1] = nint[k] == 2 ? ic[k][1] - ia[k][1] + 1 : 0;
+    pcn[k] = b - a + 1;
+    any = any && pcn[k] > 0;
   }
-  bool any = true;
-  for (int k = 0; k < D; ++k) any = any && pcn[k] > 0;
+  int64_t tflat = 0;
+  for (int k = 0; k < D; ++k) tflat = tflat * p.ntq[k] + tq[k];
   __syncthreads();
   if (any) {
-    // enumerate packet p-cells x q-bin rows (all q dims but the last), runs in the last q dim
-    int64_t npcs = 1, nqrows = 1, qcnt[3];
-    for (int k = 0; k < D; ++k) {
-      npcs *= pcn[k];
-      qcnt[k] = ilen[k][0] + ilen[k][1];
-    }
-    for (int k = 0; k < D - 1; ++k) nqrows *= qcnt[k];
-    const int kl = D - 1;
+    int64_t npcs = 1;
+    for (int k = 0; k < D; ++k) npcs *= pcn[k];
     constexpr int RB = rec_bytes<D, N1, T>();
     for (int64_t pcv = 0; pcv < npcs; ++pcv) {
-      int64_t rem = pcv, pcf = 0, pcs[3];
+      int64_t rem = pcv, pcf = 0, pcs[3] = {0, 0, 0};
       for (int k = D - 1; k >= 0; --k) {
         pcs[k] = pc0[k] + rem % pcn[k];
         rem /= pcn[k];
       }
       for (int k = 0; k < D; ++k) pcf = pcf * p.npc[k] + pcs[k];
-      // the basis index b per dimension that lands this p-cell on the slice
-      // (slice = pc + dp - mindp, so dp - mindp = slice - pc)
-      int bsel[3];
-      for (int k = 0; k < D; ++k) bsel[k] = p.bofs[(int)(sl[k] - pcs[k])];
-      for (int64_t row = 0; row < nqrows; ++row) {
-        int64_t rr = row, qb = 0, qidx[3] = {0, 0, 0};
-        for (int k = D - 2; k >= 0; --k) {
-          const int64_t r0 = rr % qcnt[k];
-          rr /= qcnt[k];
-          qidx[k] = r0 < ilen[k][0] ? ia[k][0] + r0 : ia[k][1] + (r0 - ilen[k][0]);
+      // local slice of basis index b in each dimension, or -1 outside the window
+      int ls[3][8];
+      for (int k = 0; k < D; ++k)
+        for (int b = 0; b < 8; ++b) {
+          ls[k][b] = -1;
+          if (b < p.np) {
+            const int64_t sl = pcs[k] + p.dp[b] - p.mindp;
+            if (sl >= s0[k] && sl < s1[k]) ls[k][b] = (int)(sl - s0[k]);
+          }
         }
-        for (int k = 0; k < D - 1; ++k) qb = qb * p.ntq[k] + qidx[k];
-        for (int run = 0; run < nint[kl]; ++run) {
-          const int64_t b0 = (pcf * nqt_all) + qb * p.ntq[kl] + ia[kl][run];
-          const int64_t b1 = (pcf * nqt_all) + qb * p.ntq[kl] + ic[kl][run] + 1;
-          const int64_t s0 = p.start[b0], s1 = p.start[b1];
-          for (int64_t r = s0 + threadIdx.x; r < s1; r += blockDim.x) {
-            const char *rec = p.recs + r * (int64_t)RB;
-            const RecIdx<D> ri = *reinterpret_cast<const RecIdx<D> *>(rec);
-            const T *c = reinterpret_cast<const T *>(rec + rec_idx_bytes<D>());
-            // local q offsets of this packet's neighbours inside the tile
-            int lq[3][8];
-            for (int k = 0; k < D; ++k)
-              for (int a = 0; a < 8; ++a) {
-                lq[k][a] = -1;
-                if (a < p.nq) {
-                  const int64_t qv = (ri.q[k] + p.dq[a] - tq[k] * p.tile[k] + 2 * p.Nq[k]) & (p.Nq[k] - 1);
-                  if (qv < p.tile[k]) lq[k][a] = (int)qv;
-                }
-              }
-            if (D == 1) {
+      const int64_t bin = pcf * nqt_all + tflat;
+      const int64_t r0 = p.start[bin], r1 = p.start[bin + 1];
+      for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        const char *rec = p.recs + r * (int64_t)RB;
+        const RecIdx<D> ri = *reinterpret_cast<const RecIdx<D> *>(rec);
+        const T *c = reinterpret_cast<const T *>(rec + rec_idx_bytes<D>());
+        // local q offsets of this packet's neighbours inside the tile, or -1
+        int lq[3][8];
+        for (int k = 0; k < D; ++k)
+          for (int a = 0; a < 8; ++a) {
+            lq[k][a] = -1;
+            if (a < p.nq) {
+              const int64_t qv = (ri.q[k] + p.dq[a] - tq[k] * p.tile[k]) & (p.Nq[k] - 1);
+              if (qv < p.tile[k]) lq[k][a] = (int)qv;
+            }
+          }
+        if (D == 1) {
+          for (int b0 = 0; b0 < p.np; ++b0) {
+            if (ls[0][b0] < 0) continue;
+            const int64_t sb = ls[0][b0] * p.tile[0];
+            for (int a0 = 0; a0 < p.nq; ++a0) {
+              if (lq[0][a0] < 0) continue;
+              const T v = c[a0 * p.np + b0];
+              atomicAdd(&lre[sb + lq[0][a0]], v.x);
+              atomicAdd(&lim[sb + lq[0][a0]], v.y);
+            }
+          }
+        } else if (D == 2) {
+          for (int b0 = 0; b0 < p.np; ++b0) {
+            if (ls[0][b0] < 0) continue;
+            for (int b1 = 0; b1 < p.np; ++b1) {
+              if (ls[1][b1] < 0) continue;
+              const int64_t sb = (ls[0][b0] * p.S[1] + ls[1][b1]) * tq_cells;
               for (int a0 = 0; a0 < p.nq; ++a0) {
                 if (lq[0][a0] < 0) continue;
-                const T v = c[a0 * p.np + bsel[0]];
-                atomicAdd(&lre[lq[0][a0]], v.x);
-                atomicAdd(&lim[lq[0][a0]], v.y);
-              }
-            } else if (D == 2) {
-              for (int a0 = 0; a0 < p.nq; ++a0) {
-                if (lq[0][a0] < 0) continue;
-                const T u = c[a0 * p.np + bsel[0]];
+                const T u = c[a0 * p.np + b0];
                 for (int a1 = 0; a1 < p.nq; ++a1) {
                   if (lq[1][a1] < 0) continue;
-                  const T w = c[N1 + a1 * p.np + bsel[1]];
-                  const int64_t li = lq[0][a0] * p.tile[1] + lq[1][a1];
-                  atomicAdd(&lre[li], u.x * w.x - u.y * w.y);
-                  atomicAdd(&lim[li], u.x * w.y + u.y * w.x);
+                  const T v = c[N1 + a1 * p.np + b1];
+                  const int64_t li = sb + lq[0][a0] * p.tile[1] + lq[1][a1];
+                  atomicAdd(&lre[li], u.x * v.x - u.y * v.y);
+                  atomicAdd(&lim[li], u.x * v.y + u.y * v.x);
                 }
               }
-            } else {
-              for (int a0 = 0; a0 < p.nq; ++a0) {
-                if (lq[0][a0] < 0) continue;
-                const T u = c[a0 * p.np + bsel[0]];
-                for (int a1 = 0; a1 < p.nq; ++a1) {
-                  if (lq[1][a1] < 0) continue;
-                  const T w1 = c[N1 + a1 * p.np + bsel[1]];
-                  const R ur = u.x * w1.x - u.y * w1.y, ui = u.x * w1.y + u.y * w1.x;
-                  for (int a2 = 0; a2 < p.nq; ++a2) {
-                    if (lq[2][a2] < 0) continue;
-                    const T w2 = c[2 * N1 + a2 * p.np + bsel[2]];
-                    const int64_t li = (lq[0][a0] * p.tile[1] + lq[1][a1]) * p.tile[2] + lq[2][a2];
-                    atomicAdd(&lre[li], ur * w2.x - ui * w2.y);
-                    atomicAdd(&lim[li], ur * w2.y + ui * w2.x);
+            }
+          }
+        } else {
+          for (int b0 = 0; b0 < p.np; ++b0) {
+            if (ls[0][b0] < 0) continue;
+            for (int b1 = 0; b1 < p.np; ++b1) {
+              if (ls[1][b1] < 0) continue;
+              for (int b2 = 0; b2 < p.np; ++b2) {
+                if (ls[2][b2] < 0) continue;
+                const int64_t sb = ((ls[0][b0] * p.S[1] + ls[1][b1]) * p.S[2] + ls[2][b2]) * tq_cells;
+                for (int a0 = 0; a0 < p.nq; ++a0) {
+                  if (lq[0][a0] < 0) continue;
+                  const T u = c[a0 * p.np + b0];
+                  for (int a1 = 0; a1 < p.nq; ++a1) {
+                    if (lq[1][a1] < 0) continue;
+                    const T v1 = c[N1 + a1 * p.np + b1];
+                    const R ur = u.x * v1.x - u.y * v1.y, ui = u.x * v1.y + u.y * v1.x;
+                    for (int a2 = 0; a2 < p.nq; ++a2) {
+                      if (lq[2][a2] < 0) continue;
+                      const T v2 = c[2 * N1 + a2 * p.np + b2];
+                      const int64_t li = sb + (lq[0][a0] * p.tile[1] + lq[1][a1]) * p.tile[2] + lq[2][a2];
+                      atomicAdd(&lre[li], ur * v2.x - ui * v2.y);
+                      atomicAdd(&lim[li], ur * v2.y + ui * v2.x);
+                    }
                   }
                 }
               }
@@ -419,19 +451,542 @@ __global__ __launch_bounds__(256) void fggc_accum_kernel(AccParams p, T *__restr
     }
   }
   __syncthreads();
-  // write the tile: every cell of the array is owned by exactly one workgroup
+  // write the window: every cell of the array is owned by exactly one workgroup
+  for (int64_t e = threadIdx.x; e < tcells; e += blockDim.x) {
+    int64_t rem = e, lqv[3] = {0, 0, 0}, lsv[3] = {0, 0, 0};
+    for (int k = D - 1; k >= 0; --k) {
+      lqv[k] = rem % p.tile[k];
+      rem /= p.tile[k];
+    }
+    for (int k = D - 1; k >= 0; --k) {
+      lsv[k] = rem % p.S[k];
+      rem /= p.S[k];
+    }
+    bool in = true;
+    int64_t slf = 0, q = 0;
+    for (int k = 0; k < D; ++k) {
+      const int64_t sl = s0[k] + lsv[k];
+      in = in && sl < s1[k];
+      slf = slf * p.sn[k] + sl;
+      q = q * p.Nq[k] + tq[k] * p.tile[k] + lqv[k];
+    }
+    if (in) cells[slf * ncell_q + q] = T{lre[e], lim[e]};
+  }
+}
+
+// The same accumulation with the shift-set sizes fixed at compile time (the
+// tensor strategies Q2P2, Q4P2, Q2P4, Q4P4): every loop over shifts is
+// unrolled, each record is loaded once with 16-byte loads into registers, and
+// the records of all the workgroup's bins form one index space, so that every
+// lane has work and the loads of two records are in flight together.
+constexpr int kMaxBinsPerPass = 64;
+
+template <int D, int NQ, int NP, typename T>
+__device__ __forceinline__ void add_record(const uint4 *__restrict__ src, const AccParams &p,
+                                           const int *s0, const int *sw, const int *tq0,
+                                           int tile1, int tile2, int tq_cells,
+                                           decltype(T{}.x) *lre, decltype(T{}.x) *lim) {
+  using R = decltype(T{}.x);
+  constexpr int N1 = NQ * NP;
+  constexpr int RB = rec_bytes<D, N1, T>();
+  constexpr int NV = RB / 16;
+  uint4 raw[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) raw[v] = src[v];
+  const RecIdx<D> ri = *reinterpret_cast<const RecIdx<D> *>(raw);
+  const T *c = reinterpret_cast<const T *>(reinterpret_cast<const char *>(raw) + rec_idx_bytes<D>());
+  int lq[D][NQ], ls[D][NP];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const int msk = (int)p.Nq[k] - 1, tl = (int)p.tile[k];
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) {
+      const int qv = (ri.q[k] + p.dq[a] - tq0[k]) & msk;
+      lq[k][a] = qv < tl ? qv : -1;
+    }
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      const int sl = ri.pc[k] + p.dp[b] - p.mindp - s0[k];
+      ls[k][b] = (sl >= 0 && sl < sw[k]) ? sl : -1;
+    }
+  }
+  if constexpr (D == 1) {
+#pragma unroll
+    for (int b = 0; b < NP; ++b)
+#pragma unroll
+      for (int a = 0; a < NQ; ++a)
+        if (ls[0][b] >= 0 && lq[0][a] >= 0) {
+          const int li = ls[0][b] * (int)p.tile[0] + lq[0][a];
+          const T v = c[a * NP + b];
+          atomicAdd(&lre[li], v.x);
+          atomicAdd(&lim[li], v.y);
+        }
+  } else if constexpr (D == 2) {
+#pragma unroll
+    for (int b0 = 0; b0 < NP; ++b0)
+#pragma unroll
+      for (int b1 = 0; b1 < NP; ++b1) {
+        if (ls[0][b0] < 0 || ls[1][b1] < 0) continue;
+        const int sb = (ls[0][b0] * (int)p.S[1] + ls[1][b1]) * tq_cells;
+#pragma unroll
+        for (int a0 = 0; a0 < NQ; ++a0) {
+          const T u = c[a0 * NP + b0];
+#pragma unroll
+          for (int a1 = 0; a1 < NQ; ++a1)
+            if (lq[0][a0] >= 0 && lq[1][a1] >= 0) {
+              const T v = c[N1 + a1 * NP + b1];
+              const int li = sb + lq[0][a0] * tile1 + lq[1][a1];
+              atomicAdd(&lre[li], u.x * v.x - u.y * v.y);
+              atomicAdd(&lim[li], u.x * v.y + u.y * v.x);
+            }
+        }
+      }
+  } else {
+#pragma unroll
+    for (int b0 = 0; b0 < NP; ++b0)
+#pragma unroll
+      for (int b1 = 0; b1 < NP; ++b1)
+#pragma unroll
+        for (int b2 = 0; b2 < NP; ++b2) {
+          if (ls[0][b0] < 0 || ls[1][b1] < 0 || ls[2][b2] < 0) continue;
+          const int sb = ((ls[0][b0] * (int)p.S[1] + ls[1][b1]) * (int)p.S[2] + ls[2][b2]) * tq_cells;
+#pragma unroll
+          for (int a0 = 0; a0 < NQ; ++a0) {
+            const T u = c[a0 * NP + b0];
+#pragma unroll
+            for (int a1 = 0; a1 < NQ; ++a1) {
+              const T v1 = c[N1 + a1 * NP + b1];
+              const R ur = u.x * v1.x - u.y * v1.y, ui = u.x * v1.y + u.y * v1.x;
+#pragma unroll
+              for (int a2 = 0; a2 < NQ; ++a2)
+                if (lq[0][a0] >= 0 && lq[1][a1] >= 0 && lq[2][a2] >= 0) {
+                  const T v2 = c[2 * N1 + a2 * NP + b2];
+                  const int li = sb + (lq[0][a0] * tile1 + lq[1][a1]) * tile2 + lq[2][a2];
+                  atomicAdd(&lre[li], ur * v2.x - ui * v2.y);
+                  atomicAdd(&lim[li], ur * v2.y + ui * v2.x);
+                }
+            }
+          }
+        }
+  }
+}
+
+template <int D, int NQ, int NP, typename T>
+__global__ __launch_bounds__(256) void fggc_accum_kernel(AccParams p, T *__restrict__ cells) {
+  using R = decltype(T{}.x);
+  constexpr int RB = rec_bytes<D, NQ * NP, T>();
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int64_t s_r0[kMaxBinsPerPass], s_pre[kMaxBinsPerPass + 1];
+  R *lre = reinterpret_cast<R *>(smem_raw);
+  int tq_cells = 1, sw_cells = 1;
+  int64_t nqt_all = 1, ncell_q = 1;
+  for (int k = 0; k < D; ++k) {
+    tq_cells *= (int)p.tile[k];
+    sw_cells *= (int)p.S[k];
+    nqt_all *= p.ntq[k];
+    ncell_q *= p.Nq[k];
+  }
+  const int tcells = tq_cells * sw_cells;
+  R *lim = lre + tcells;
+  for (int e = threadIdx.x; e < tcells; e += blockDim.x) {
+    lre[e] = 0;
+    lim[e] = 0;
+  }
+  int64_t blk = blockIdx.x;
+  int tq[3] = {0, 0, 0}, s0[3] = {0, 0, 0}, sw[3] = {1, 1, 1}, tq0[3] = {0, 0, 0};
+  int64_t w[3] = {0, 0, 0}, pc0[3] = {0, 0, 0}, pcn[3] = {1, 1, 1};
+  for (int k = D - 1; k >= 0; --k) {
+    tq[k] = (int)(blk % p.ntq[k]);
+    blk /= p.ntq[k];
+  }
+  for (int k = D - 1; k >= 0; --k) {
+    w[k] = blk % p.nsw[k];
+    blk /= p.nsw[k];
+  }
+  bool any = true;
+  for (int k = 0; k < D; ++k) {
+    s0[k] = (int)(w[k] * p.S[k]);
+    sw[k] = (int)min(p.S[k], p.sn[k] - s0[k]);
+    tq0[k] = tq[k] * (int)p.tile[k];
+    int64_t a = s0[k] - (p.maxdp - p.mindp), b = s0[k] + sw[k] - 1;
+    if (a < 0) a = 0;
+    if (b > p.npc[k] - 1) b = p.npc[k] - 1;
+    pc0[k] = a;
+    pcn[k] = b - a + 1;
+    any = any && pcn[k] > 0;
+  }
+  int64_t tflat = 0;
+  for (int k = 0; k < D; ++k) tflat = tflat * p.ntq[k] + tq[k];
+  const int tile1 = D > 1 ? (int)p.tile[1] : 1, tile2 = D > 2 ? (int)p.tile[2] : 1;
+  int64_t npcs = 1;
+  for (int k = 0; k < D; ++k) npcs *= pcn[k];
+  if (!any) npcs = 0;
+  __syncthreads();
+  for (int64_t bb = 0; bb < npcs; bb += kMaxBinsPerPass) {
+    const int nb = (int)min<int64_t>(kMaxBinsPerPass, npcs - bb);
+    if ((int)threadIdx.x < nb) {
+      int64_t rem = bb + threadIdx.x, pcf = 0, pcs[3] = {0, 0, 0};
+      for (int k = D - 1; k >= 0; --k) {
+        pcs[k] = pc0[k] + rem % pcn[k];
+        rem /= pcn[k];
+      }
+      for (int k = 0; k < D; ++k) pcf = pcf * p.npc[k] + pcs[k];
+      const int64_t bin = pcf * nqt_all + tflat;
+      s_r0[threadIdx.x] = p.start[bin];
+      s_pre[threadIdx.x + 1] = p.start[bin + 1] - p.start[bin];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_pre[0] = 0;
+      for (int i = 1; i <= nb; ++i) s_pre[i] += s_pre[i - 1];
+    }
+    __syncthreads();
+    const int64_t total = s_pre[nb];
+    // consecutive records of a bin often come from one packet-mesh point and
+    // hit the same cells: spread the lanes of a wave over the bin with a
+    // stride coprime to the record count, so that their LDS atomics rarely
+    // collide on one address
+    int64_t stride = 1;
+    if (total > 64) {
+      const int64_t cand[6] = {97, 89, 83, 79, 73, 71};
+      for (int c = 0; c < 6; ++c) {
+        int64_t x = total, y = cand[c];
+        while (y) {
+          const int64_t t = x % y;
+          x = y;
+          y = t;
+        }
+        if (x == 1) {
+          stride = cand[c];
+          break;
+        }
+      }
+    }
+    auto rec_of = [&](int64_t i0) {
+      const int64_t i = (i0 * stride) % total;
+      int lo = 0, hi = nb - 1;  // last bin with s_pre[bin] <= i
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] <= i) lo = mid;
+        else hi = mid - 1;
+      }
+      return reinterpret_cast<const uint4 *>(p.recs + (s_r0[lo] + (i - s_pre[lo])) * (int64_t)RB);
+    };
+    for (int64_t i = threadIdx.x; i < total; i += 2 * (int64_t)blockDim.x) {
+      const int64_t i2 = i + blockDim.x;
+      const uint4 *ra = rec_of(i);
+      const uint4 *rb = i2 < total ? rec_of(i2) : ra;
+      add_record<D, NQ, NP, T>(ra, p, s0, sw, tq0, tile1, tile2, tq_cells, lre, lim);
+      if (i2 < total) add_record<D, NQ, NP, T>(rb, p, s0, sw, tq0, tile1, tile2, tq_cells, lre, lim);
+    }
+    __syncthreads();
+  }
+  // write the window: every cell of the array is owned by exactly one workgroup
+  for (int e = threadIdx.x; e < tcells; e += blockDim.x) {
+    int rem = e, lqv[3] = {0, 0, 0}, lsv[3] = {0, 0, 0};
+    for (int k = D - 1; k >= 0; --k) {
+      lqv[k] = rem % (int)p.tile[k];
+      rem /= (int)p.tile[k];
+    }
+    for (int k = D - 1; k >= 0; --k) {
+      lsv[k] = rem % (int)p.S[k];
+      rem /= (int)p.S[k];
+    }
+    bool in = true;
+    int64_t slf = 0, q = 0;
+    for (int k = 0; k < D; ++k) {
+      in = in && lsv[k] < sw[k];
+      slf = slf * p.sn[k] + s0[k] + lsv[k];
+      q = q * p.Nq[k] + tq0[k] + lqv[k];
+    }
+    if (in) cells[slf * ncell_q + q] = T{lre[e], lim[e]};
+  }
+}
+
+// Accumulation without atomics (d = 1, 2): one wave per (slice, q-tile); the
+// tile lives in LDS as interleaved complex values and is updated with plain
+// read-modify-writes.  Two lanes can hit the same cell in one instruction only
+// when their records share (p-cell, q-cell); before adding, lanes claim an LDS
+// hash slot of that key and only the lane that holds its slot adds in this
+// pass, the others in later passes -- so each pass writes distinct cells.
+constexpr int kHashSlots = 256;
+
+template <int D, int NQ, int NP, typename T>
+__global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__restrict__ cells) {
+  using R = decltype(T{}.x);
+  constexpr int N1 = NQ * NP;
+  constexpr int RB = rec_bytes<D, N1, T>();
+  constexpr int NV = RB / 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int64_t s_r0[kMaxBinsPerPass], s_pre[kMaxBinsPerPass + 1];
+  __shared__ int s_claim[kHashSlots];
+  T *tile = reinterpret_cast<T *>(smem_raw);
+  const int lane = threadIdx.x;
+  int tq_cells = 1;
+  int64_t nqt_all = 1, ncell_q = 1;
+  for (int k = 0; k < D; ++k) {
+    tq_cells *= (int)p.tile[k];
+    nqt_all *= p.ntq[k];
+    ncell_q *= p.Nq[k];
+  }
+  for (int e = lane; e < tq_cells; e += 64) tile[e] = T{0, 0};
+  int64_t blk = blockIdx.x;
+  int tq0[3] = {0, 0, 0}, tq[3] = {0, 0, 0};
+  int64_t sl[3] = {0, 0, 0}, pc0[3] = {0, 0, 0}, pcn[3] = {1, 1, 1};
+  for (int k = D - 1; k >= 0; --k) {
+    tq[k] = (int)(blk % p.ntq[k]);
+    blk /= p.ntq[k];
+  }
+  for (int k = D - 1; k >= 0; --k) {
+    sl[k] = blk % p.sn[k];
+    blk /= p.sn[k];
+  }
+  bool any = true;
+  for (int k = 0; k < D; ++k) {
+    tq0[k] = tq[k] * (int)p.tile[k];
+    int64_t a = sl[k] - (p.maxdp - p.mindp), b = sl[k];
+    if (a < 0) a = 0;
+    if (b > p.npc[k] - 1) b = p.npc[k] - 1;
+    pc0[k] = a;
+    pcn[k] = b - a + 1;
+    any = any && pcn[k] > 0;
+  }
+  int64_t tflat = 0;
+  for (int k = 0; k < D; ++k) tflat = tflat * p.ntq[k] + tq[k];
+  int64_t npcs = 1;
+  for (int k = 0; k < D; ++k) npcs *= pcn[k];
+  if (!any) npcs = 0;
+  const int tile1 = D > 1 ? (int)p.tile[1] : 1;
+  __syncthreads();
+  for (int64_t bb = 0; bb < npcs; bb += kMaxBinsPerPass) {
+    const int nb = (int)min<int64_t>(kMaxBinsPerPass, npcs - bb);
+    for (int t = lane; t < nb; t += 64) {
+      int64_t rem = bb + t, pcf = 0, pcs[3] = {0, 0, 0};
+      for (int k = D - 1; k >= 0; --k) {
+        pcs[k] = pc0[k] + rem % pcn[k];
+        rem /= pcn[k];
+      }
+      for (int k = 0; k < D; ++k) pcf = pcf * p.npc[k] + pcs[k];
+      const int64_t bin = pcf * nqt_all + tflat;
+      s_r0[t] = p.start[bin];
+      s_pre[t + 1] = p.start[bin + 1] - p.start[bin];
+    }
+    __syncthreads();
+    if (lane == 0) {
+      s_pre[0] = 0;
+      for (int i = 1; i <= nb; ++i) s_pre[i] += s_pre[i - 1];
+    }
+    __syncthreads();
+    const int64_t total = s_pre[nb];
+    for (int64_t base = 0; base < total; base += 64) {
+      const int64_t i = base + lane;
+      const bool valid = i < total;
+      uint4 raw[NV];
+      if (valid) {
+        int lo = 0, hi = nb - 1;  // last bin with s_pre[bin] <= i
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pre[mid] <= i) lo = mid;
+          else hi = mid - 1;
+        }
+        const uint4 *src = reinterpret_cast<const uint4 *>(p.recs + (s_r0[lo] + (i - s_pre[lo])) * (int64_t)RB);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) raw[v] = src[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) raw[v] = make_uint4(0, 0, 0, 0);
+      }
+      const RecIdx<D> ri = *reinterpret_cast<const RecIdx<D> *>(raw);
+      const T *c = reinterpret_cast<const T *>(reinterpret_cast<const char *>(raw) + rec_idx_bytes<D>());
+      int lq[D][NQ];
+      bool okb[D][NP];
+      uint32_t h = 0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const int msk = (int)p.Nq[k] - 1, tl = (int)p.tile[k];
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) {
+          const int qv = (ri.q[k] + p.dq[a] - tq0[k]) & msk;
+          lq[k][a] = qv < tl ? qv : -1;
+        }
+#pragma unroll
+        for (int b = 0; b < NP; ++b) okb[k][b] = (int64_t)ri.pc[k] + p.dp[b] - p.mindp == sl[k];
+        h = h * 0x9E3779B1u + (uint32_t)ri.q[k] * 0x85EBCA77u + (uint32_t)ri.pc[k] * 0xC2B2AE3Du;
+      }
+      h = (h ^ (h >> 15)) & (kHashSlots - 1);
+      // passes: the loop condition is wave-uniform; the barriers (a single
+      // wave here) order the claims and the cell updates between lanes
+      volatile int *claim = s_claim;
+      bool todo = valid;
+      while (__ballot(todo)) {
+        if (todo) claim[h] = lane;
+        __syncthreads();
+        const bool win = todo && claim[h] == lane;
+        if (win) {
+          todo = false;
+          if constexpr (D == 1) {
+#pragma unroll
+            for (int b = 0; b < NP; ++b) {
+              if (!okb[0][b]) continue;
+#pragma unroll
+              for (int a = 0; a < NQ; ++a) {
+                if (lq[0][a] < 0) continue;
+                const T v = c[a * NP + b];
+                T o = tile[lq[0][a]];
+                o.x += v.x;
+                o.y += v.y;
+                tile[lq[0][a]] = o;
+              }
+            }
+          } else {
+#pragma unroll
+            for (int b0 = 0; b0 < NP; ++b0)
+#pragma unroll
+              for (int b1 = 0; b1 < NP; ++b1) {
+                if (!okb[0][b0] || !okb[1][b1]) continue;
+#pragma unroll
+                for (int a0 = 0; a0 < NQ; ++a0) {
+                  if (lq[0][a0] < 0) continue;
+                  const T u = c[a0 * NP + b0];
+#pragma unroll
+                  for (int a1 = 0; a1 < NQ; ++a1) {
+                    if (lq[1][a1] < 0) continue;
+                    const T v = c[N1 + a1 * NP + b1];
+                    const int li = lq[0][a0] * tile1 + lq[1][a1];
+                    T o = tile[li];
+                    o.x += u.x * v.x - u.y * v.y;
+                    o.y += u.x * v.y + u.y * v.x;
+                    tile[li] = o;
+                  }
+                }
+              }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+  }
   int64_t slf = 0;
   for (int k = 0; k < D; ++k) slf = slf * p.sn[k] + sl[k];
   T *dst = cells + slf * ncell_q;
-  for (int64_t e = threadIdx.x; e < tcells; e += blockDim.x) {
-    int64_t rem = e, q = 0, lo[3];
+  for (int e = lane; e < tq_cells; e += 64) {
+    int rem = e, q = 0, lqv[3] = {0, 0, 0};
     for (int k = D - 1; k >= 0; --k) {
-      lo[k] = rem % p.tile[k];
-      rem /= p.tile[k];
+      lqv[k] = rem % (int)p.tile[k];
+      rem /= (int)p.tile[k];
     }
-    for (int k = 0; k < D; ++k) q = q * p.Nq[k] + tq[k] * p.tile[k] + lo[k];
-    dst[q] = T{lre[e], lim[e]};
+    int64_t qf = 0;
+    for (int k = 0; k < D; ++k) qf = qf * p.Nq[k] + tq0[k] + lqv[k];
+    (void)q;
+    dst[qf] = tile[e];
   }
+}
+
+// One dimension, without atomics.  Packets of one (p-cell, q-cell) add to
+// the same cells with the same shifts, so their coefficient vectors can be
+// summed first:
+//   aggregate  one workgroup per bin (p-cell, q-tile); thread (q-cell, m)
+//              owns A[p-cell][q-cell][m] and adds c[m] of every record of the
+//              bin that sits in its q-cell (records are read by all threads:
+//              broadcast loads); deterministic;
+//   stencil    cells[s][q] = sum over b, a of A[s + mindp - dp_b][q - dq_a][a np + b]
+//              (eq. 2.25 with the shifts applied on the aggregated vectors).
+struct Agg1Params {
+  const char *recs;
+  const int64_t *start;
+  int64_t Nq, tile, ntq, npc;
+};
+
+// 4 waves split the bin's records; within a wave, lane l owns coefficient
+// m = l % N1 of the q-cells l / N1 + (64 / N1) j (j < N1 / 2) of the 32-cell
+// tile; the four partial tiles are summed through LDS at the end.
+template <int N1, typename T>
+__global__ __launch_bounds__(256) void fggc_agg1_kernel(Agg1Params p, T *__restrict__ A) {
+  using R = decltype(T{}.x);
+  constexpr int RB = rec_bytes<1, N1, T>();
+  constexpr int K = N1 / 2, STEP = 64 / N1, U = 8;
+  __shared__ T part[4][32 * N1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane % N1, q0 = lane / N1;
+  const int64_t bin = blockIdx.x;
+  const int64_t pc = bin / p.ntq, t = bin - pc * p.ntq;
+  const int tbase = (int)(t * p.tile);
+  const int64_t r0 = p.start[bin], r1 = p.start[bin + 1], n = r1 - r0;
+  const int64_t ra = r0 + (n * w) / 4, rb = r0 + (n * (w + 1)) / 4;
+  R ar[K], ai[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) ar[j] = ai[j] = 0;
+  int64_t r = ra;
+  for (; r + U <= rb; r += U) {
+    int qq[U];
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const char *rec = p.recs + (r + u) * (int64_t)RB;
+      qq[u] = *reinterpret_cast<const int32_t *>(rec) - tbase - q0;
+      v[u] = reinterpret_cast<const T *>(rec + rec_idx_bytes<1>())[m];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        if (qq[u] == STEP * j) {
+          ar[j] += v[u].x;
+          ai[j] += v[u].y;
+        }
+  }
+  for (; r < rb; ++r) {
+    const char *rec = p.recs + r * (int64_t)RB;
+    const int qq = *reinterpret_cast<const int32_t *>(rec) - tbase - q0;
+    const T v = reinterpret_cast<const T *>(rec + rec_idx_bytes<1>())[m];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      if (qq == STEP * j) {
+        ar[j] += v.x;
+        ai[j] += v.y;
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) part[w][(q0 + STEP * j) * N1 + m] = T{ar[j], ai[j]};
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * N1; e += 256) {
+    const int ql = e / N1;
+    T sum = part[0][e];
+#pragma unroll
+    for (int x = 1; x < 4; ++x) {
+      sum.x += part[x][e].x;
+      sum.y += part[x][e].y;
+    }
+    if (ql < p.tile) A[(pc * p.Nq + tbase + ql) * N1 + (e % N1)] = sum;
+  }
+}
+
+struct Stencil1Params {
+  int64_t Nq, sn, npc;
+  int n1, nq, np, mindp;
+  int dq[8], dp[8];
+};
+
+template <typename T>
+__global__ void fggc_stencil1_kernel(Stencil1Params p, const T *__restrict__ A, int n1s,
+                                     T *__restrict__ cells) {
+  using R = decltype(T{}.x);
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= p.sn * p.Nq) return;
+  const int64_t sl = e / p.Nq, q = e - sl * p.Nq;
+  R ar = 0, ai = 0;
+  for (int b = 0; b < p.np; ++b) {
+    const int64_t pc = sl + p.mindp - p.dp[b];
+    if (pc < 0 || pc >= p.npc) continue;
+    for (int a = 0; a < p.nq; ++a) {
+      const int64_t qs = (q - p.dq[a]) & (p.Nq - 1);
+      const T v = A[(pc * p.Nq + qs) * n1s + a * p.np + b];
+      ar += v.x;
+      ai += v.y;
+    }
+  }
+  cells[e] = T{ar, ai};
 }
 
 // Band tables per dimension: for slice index l (p = (slo + l) dp) the first
@@ -569,11 +1124,12 @@ __global__ __launch_bounds__(256) void band_mac_kernel(MacParams m, const T *__r
 }
 
 struct FggcLayout {
-  int d, N1, rec_b;
-  int64_t ncells, nslices, npts, nbins, tiles, ntq[3], tile[3], npc[3], pmin[3];
+  int d, N1, rec_b, ns;
+  bool agg1;  // one dimension: aggregate + stencil instead of tile accumulation
+  int64_t ncells, nslices, npts, nbins, nslots, tiles, ntq[3], tile[3], npc[3], pmin[3], S[3], nsw[3];
   int64_t nb[3], toff[3], koff[3], ntab, nkst;
   int mindp, maxdp, mindq, maxdq;
-  size_t off_lsq, off_keys, off_order, off_sort, off_start, off_recs, off_cells, off_gam, off_kst,
+  size_t off_lsq, off_keys, off_pos, off_sort, off_start, off_recs, off_agg, off_cells, off_gam, off_kst,
       off_spec, total;
 };
 
@@ -596,7 +1152,11 @@ FggcLayout fggc_layout(const FggcArgs &a) {
     L.mindq = std::min(L.mindq, l0.dq[m]);
     L.maxdq = std::max(L.maxdq, l0.dq[m]);
   }
-  static const int64_t deft[4] = {0, 32, 32, 16};
+  // q-tile and slice window of one accumulation workgroup: the LDS holds
+  // S^d * tile^d cells; a tile is at least as wide as the q-shift set
+  static const int64_t deft[4] = {0, 32, 32, 16}, defs[4] = {0, 1, 1, 1};
+  int64_t tmin = 1;
+  while (tmin < L.maxdq - L.mindq + 1) tmin *= 2;
   L.nslices = 1;
   int64_t nqt = 1;
   L.npts = 1;
@@ -609,19 +1169,24 @@ FggcLayout fggc_layout(const FggcArgs &a) {
       L.nslices *= a.sn[k];
       nqt *= a.Nq[k];
       L.npts *= a.g.n[k];
-      L.tile[k] = std::min<int64_t>(a.Nq[k], deft[d]);
+      // one dimension aggregates by own q-cell (no halo): tiles of exactly 32
+      // cells, the width of the aggregation workgroup
+      L.tile[k] = d == 1 ? std::min<int64_t>(a.Nq[k], 32)
+                         : std::min<int64_t>(a.Nq[k], std::max<int64_t>(deft[d], tmin));
       L.ntq[k] = a.Nq[k] / L.tile[k];
       L.pmin[k] = a.slo[k] - L.mindp;
       L.npc[k] = a.sn[k] - (L.maxdp - L.mindp);
+      L.S[k] = std::min<int64_t>(defs[d], a.sn[k]);
+      L.nsw[k] = (a.sn[k] + L.S[k] - 1) / L.S[k];
       L.nbins *= L.npc[k] * L.ntq[k];
-      L.tiles *= a.sn[k] * L.ntq[k];
+      L.tiles *= L.nsw[k] * L.ntq[k];
       L.nb[k] = (int64_t)std::floor(2.0 * a.cK / std::sqrt(a.eps)) + 2;
       L.toff[k] = L.ntab;
       L.koff[k] = L.nkst;
       L.ntab += a.sn[k] * L.nb[k];
       L.nkst += a.sn[k];
     } else {
-      L.tile[k] = L.ntq[k] = L.npc[k] = 1;
+      L.tile[k] = L.ntq[k] = L.npc[k] = L.S[k] = L.nsw[k] = 1;
       L.pmin[k] = 0;
       L.nb[k] = 1;
       L.toff[k] = 0;
@@ -630,7 +1195,12 @@ FggcLayout fggc_layout(const FggcArgs &a) {
   }
   if (L.nbins >= ((int64_t)1 << 32)) fail(FGGC_EUNSUPPORTED, "too many packet bins");
   L.ncells = L.nslices * nqt;
+  if (L.tiles >= ((int64_t)1 << 31)) fail(FGGC_EUNSUPPORTED, "too many accumulation workgroups");
   const int64_t N = std::max<int64_t>(a.pk->N, 1);
+  L.agg1 = d == 1;
+  L.ns = L.agg1 ? 1 : (1 << d);  // key slots per packet: own tile, or 2^d with halo tiles
+  L.nslots = a.pk->N * L.ns;
+  const int64_t NS = std::max<int64_t>(L.nslots, 1);
   size_t o = 0;
   auto put = [&](size_t bytes) {
     size_t at = o;
@@ -638,11 +1208,13 @@ FggcLayout fggc_layout(const FggcArgs &a) {
     return at;
   };
   L.off_lsq = put(3 * sizeof(DimLsq));
-  L.off_keys = put(N * 4);
-  L.off_order = put(N * 4);
-  L.off_sort = put(bucket_sort_bytes(a.pk->N, L.nbins));
+  L.off_keys = put(NS * 4);
+  L.off_pos = put(NS * 4);
+  L.off_sort = put(bucket_positions_bytes(L.nslots, L.nbins));
   L.off_start = put((size_t)(L.nbins + 1) * 8);
-  L.off_recs = put((size_t)N * L.rec_b);
+  L.off_recs = put((size_t)NS * L.rec_b);  // at most one record per slot
+  L.off_agg = put(L.agg1 ? (size_t)L.npc[0] * a.Nq[0] * L.N1 * es : 0);
+  (void)N;
   L.off_cells = put((size_t)L.ncells * es);
   L.off_gam = put((size_t)L.ntab * (es / 2));
   L.off_kst = put((size_t)L.nkst * 8 + 64);
@@ -653,11 +1225,11 @@ FggcLayout fggc_layout(const FggcArgs &a) {
 
 template <int D, int N1, typename T>
 void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams &cp,
-                       const uint32_t *order, char *recs, const int64_t *start, T *cells,
+                       const uint32_t *pos, char *recs, const int64_t *start, void *agg, T *cells,
                        hipStream_t s) {
-  {
+  if (cp.N > 0) {
     StageScope sc(a.prof, "fggc_coef", s);
-    fggc_coef_kernel<D, N1, T><<<dim3((unsigned)((cp.N + 255) / 256)), dim3(256), 0, s>>>(cp, order, recs);
+    fggc_coef_kernel<D, N1, T><<<dim3((unsigned)((cp.N + 255) / 256)), dim3(256), 0, s>>>(cp, pos, recs);
     FGGC_HIP(hipGetLastError());
   }
   AccParams ap{};
@@ -670,6 +1242,8 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
     ap.Nq[k] = a.Nq[k];
     ap.tile[k] = L.tile[k];
     ap.ntq[k] = L.ntq[k];
+    ap.S[k] = L.S[k];
+    ap.nsw[k] = L.nsw[k];
   }
   // one-dimensional shift sets (basis index a * np + b)
   int nq = 0, np = 0;
@@ -685,27 +1259,93 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
   }
   ap.mindp = L.mindp;
   ap.maxdp = L.maxdp;
-  ap.mindq = L.mindq;
-  ap.maxdq = L.maxdq;
-  for (int i = 0; i < 32; ++i) ap.bofs[i] = -1;
-  for (int b = 0; b < np; ++b) ap.bofs[ap.dp[b] - L.mindp] = b;
+  if (L.agg1) {
+    StageScope sc(a.prof, "fggc_accum", s);
+    T *A = reinterpret_cast<T *>(agg);
+    Agg1Params gp{};
+    gp.recs = recs;
+    gp.start = start;
+    gp.Nq = a.Nq[0];
+    gp.tile = L.tile[0];
+    gp.ntq = L.ntq[0];
+    gp.npc = L.npc[0];
+    const dim3 gg((unsigned)L.nbins), gb(256);
+    fggc_agg1_kernel<N1, T><<<gg, gb, 0, s>>>(gp, A);
+    FGGC_HIP(hipGetLastError());
+    Stencil1Params sp{};
+    sp.Nq = a.Nq[0];
+    sp.sn = a.sn[0];
+    sp.npc = L.npc[0];
+    sp.n1 = l0.n1;
+    sp.nq = nq;
+    sp.np = np;
+    sp.mindp = L.mindp;
+    for (int i = 0; i < 8; ++i) {
+      sp.dq[i] = ap.dq[i];
+      sp.dp[i] = ap.dp[i];
+    }
+    const int64_t ncl = a.sn[0] * a.Nq[0];
+    fggc_stencil1_kernel<T><<<dim3((unsigned)((ncl + 255) / 256)), dim3(256), 0, s>>>(sp, A, N1, cells);
+    FGGC_HIP(hipGetLastError());
+    return;
+  }
   int64_t tc = 1;
-  for (int k = 0; k < D; ++k) tc *= L.tile[k];
+  for (int k = 0; k < D; ++k) tc *= L.tile[k] * L.S[k];
   const size_t shm = 2 * (size_t)tc * sizeof(decltype(T{}.x));
+  if (shm > 65536) fail(FGGC_EUNSUPPORTED, "accumulation tile exceeds 64 KB of LDS");
   StageScope sc(a.prof, "fggc_accum", s);
-  fggc_accum_kernel<D, N1, T><<<dim3((unsigned)L.tiles), dim3(256), shm, s>>>(ap, cells);
+  const dim3 grid((unsigned)L.tiles), blk(256);
+  const bool wave = D <= 2 && L.S[0] == 1 && (D < 2 || L.S[1] == 1);
+  if (wave) {
+    const size_t wshm = (size_t)(tc)*sizeof(T);
+    const dim3 wblk(64);
+    if (N1 == 4 && nq == 2 && np == 2) {
+      fggc_accum_wave_kernel<D, 2, 2, T><<<grid, wblk, wshm, s>>>(ap, cells);
+      FGGC_HIP(hipGetLastError());
+      return;
+    }
+    if (N1 == 8 && nq == 4 && np == 2) {
+      fggc_accum_wave_kernel<D, 4, 2, T><<<grid, wblk, wshm, s>>>(ap, cells);
+      FGGC_HIP(hipGetLastError());
+      return;
+    }
+    if (N1 == 8 && nq == 2 && np == 4) {
+      fggc_accum_wave_kernel<D, 2, 4, T><<<grid, wblk, wshm, s>>>(ap, cells);
+      FGGC_HIP(hipGetLastError());
+      return;
+    }
+    if (N1 == 16 && nq == 4 && np == 4) {
+      fggc_accum_wave_kernel<D, 4, 4, T><<<grid, wblk, wshm, s>>>(ap, cells);
+      FGGC_HIP(hipGetLastError());
+      return;
+    }
+  }
+  if (N1 == 4 && nq == 2 && np == 2)
+    fggc_accum_kernel<D, 2, 2, T><<<grid, blk, shm, s>>>(ap, cells);
+  else if (N1 == 8 && nq == 4 && np == 2)
+    fggc_accum_kernel<D, 4, 2, T><<<grid, blk, shm, s>>>(ap, cells);
+  else if (N1 == 8 && nq == 2 && np == 4)
+    fggc_accum_kernel<D, 2, 4, T><<<grid, blk, shm, s>>>(ap, cells);
+  else if (N1 == 16 && nq == 4 && np == 4 && D < 3)
+    fggc_accum_kernel<D, 4, 4, T><<<grid, blk, shm, s>>>(ap, cells);
+  else
+    fggc_accum_generic_kernel<D, N1, T><<<grid, blk, shm, s>>>(ap, cells);
   FGGC_HIP(hipGetLastError());
 }
 
-// sort packets into bins, compute their coefficients in bin order, and fill
+// bin the packets' key slots, compute their coefficients into bin order, and fill
 // the cell array of eq. (2.25) (every cell written once)
 void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells, hipStream_t s) {
   const int d = a.g.d;
   const bool f64 = a.precision == FGGC_FP64;
-  DimLsq *dlsq = (DimLsq *)(base + L.off_lsq);
-  FGGC_HIP(hipMemcpyAsync(dlsq, a.lsq, d * sizeof(DimLsq), hipMemcpyHostToDevice, s));
+  const DimLsq *dlsq = a.lsq_dev;
+  if (!dlsq) {
+    DimLsq *tmp = (DimLsq *)(base + L.off_lsq);
+    FGGC_HIP(hipMemcpyAsync(tmp, a.lsq, d * sizeof(DimLsq), hipMemcpyHostToDevice, s));
+    dlsq = tmp;
+  }
   const int64_t N = a.pk->N;
-  uint32_t *keys = (uint32_t *)(base + L.off_keys), *order = (uint32_t *)(base + L.off_order);
+  uint32_t *keys = (uint32_t *)(base + L.off_keys), *pos = (uint32_t *)(base + L.off_pos);
   int64_t *start = (int64_t *)(base + L.off_start);
   char *recs = base + L.off_recs;
   {
@@ -724,15 +1364,19 @@ void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells
         kp.dq[k] = kTwoPi / (double)a.Nq[k];
         kp.dp[k] = a.dp[k];
       }
+      kp.mindq = L.mindq;
+      kp.maxdq = L.maxdq;
+      kp.ns = L.ns;
       const dim3 g((unsigned)((N + 255) / 256)), b(256);
       if (d == 1) fggc_key_kernel<1><<<g, b, 0, s>>>(kp, keys);
       else if (d == 2) fggc_key_kernel<2><<<g, b, 0, s>>>(kp, keys);
       else fggc_key_kernel<3><<<g, b, 0, s>>>(kp, keys);
       FGGC_HIP(hipGetLastError());
     }
-    bucket_sort(keys, N, L.nbins, order, start, base + L.off_sort, s);
+    bucket_positions(keys, L.nslots, L.nbins, pos, start, base + L.off_sort, s);
   }
   CoefParams cp{};
+  cp.ns = L.ns;
   cp.N = N;
   cp.Q = a.pk->Q;
   cp.P = a.pk->P;
@@ -748,8 +1392,8 @@ void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells
     cp.dp[k] = a.dp[k];
   }
 #define FGGC_CA(DD, NN)                                                                           \
-  if (f64) launch_coef_accum<DD, NN, double2>(a, L, cp, order, recs, start, (double2 *)cells, s); \
-  else launch_coef_accum<DD, NN, float2>(a, L, cp, order, recs, start, (float2 *)cells, s);
+  if (f64) launch_coef_accum<DD, NN, double2>(a, L, cp, pos, recs, start, base + L.off_agg, (double2 *)cells, s); \
+  else launch_coef_accum<DD, NN, float2>(a, L, cp, pos, recs, start, base + L.off_agg, (float2 *)cells, s);
   if (d == 1) {
     if (L.N1 == 4) { FGGC_CA(1, 4) } else if (L.N1 == 8) { FGGC_CA(1, 8) } else { FGGC_CA(1, 16) }
   } else if (d == 2) {

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <memory>
 #include <string>
 
 #include "common.h"
@@ -133,6 +134,55 @@ void build_dim_lsq(const fggc_strategy &st, int dim, double eps, DimLsq *out) {
     out->D[2 * k] = (double)std::cos(ph);
     out->D[2 * k + 1] = (double)std::sin(ph);
   }
+}
+
+namespace {
+struct PlanEntry {
+  int device, d;
+  double eps;
+  fggc_strategy st;
+  Plan plan;
+};
+std::mutex g_plan_mu;
+std::vector<std::unique_ptr<PlanEntry>> g_plans;
+constexpr size_t kMaxPlans = 1024;
+
+bool same_strategy(const fggc_strategy &a, const fggc_strategy &b, int d) {
+  if (a.nq != b.nq || a.np != b.np || a.cutoff != b.cutoff) return false;
+  for (int k = 0; k < d; ++k)
+    if (a.Nq[k] != b.Nq[k] || a.dp[k] != b.dp[k]) return false;
+  for (int i = 0; i < a.nq; ++i)
+    if (a.dq_off[i] != b.dq_off[i]) return false;
+  for (int i = 0; i < a.np; ++i)
+    if (a.dp_off[i] != b.dp_off[i]) return false;
+  return true;
+}
+}  // namespace
+
+Plan plan_for(const fggc_strategy &st, int d, double eps) {
+  int dev = 0;
+  FGGC_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (auto &e : g_plans)
+      if (e->device == dev && e->d == d && e->eps == eps && same_strategy(e->st, st, d)) return e->plan;
+  }
+  Plan pl{};
+  for (int k = 0; k < d; ++k) build_dim_lsq(st, k, eps, &pl.host[k]);
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  if (g_plans.size() >= kMaxPlans) return pl;  // callers copy the host plan themselves
+  DimLsq *dv = nullptr;
+  FGGC_HIP(hipMalloc((void **)&dv, 3 * sizeof(DimLsq)));
+  FGGC_HIP(hipMemcpy(dv, pl.host, 3 * sizeof(DimLsq), hipMemcpyHostToDevice));
+  pl.dev = dv;  // kept for the life of the process (graphs may refer to it)
+  auto e = std::make_unique<PlanEntry>();
+  e->device = dev;
+  e->d = d;
+  e->eps = eps;
+  e->st = st;
+  e->plan = pl;
+  g_plans.push_back(std::move(e));
+  return pl;
 }
 
 }  // namespace fggc

@@ -302,8 +302,12 @@ void fggc_server::run(Slot *sl, Request &r) {
   FggcArgs fa{};
   DirectArgs da{};
   if (r.use_fggc) {
-    for (int k = 0; k < d; ++k) build_dim_lsq(r.st, k, r.eps, &sl->lsq[k]);
+    const Plan plan = plan_for(r.st, d, r.eps);
+    // the host plan lives in the slot's pinned copy: a captured graph's
+    // memcpy node reads it there when the device plan is not cached
+    std::memcpy(sl->lsq, plan.host, sizeof(plan.host));
     fill_fggc_args(fa, &dpk, r.eps, r.g, r.st, r.scale, r.precision, sl->lsq, r.slo, r.sn);
+    fa.lsq_dev = plan.dev;
     fa.u = u;
   } else {
     da.pk = &dpk;
@@ -572,9 +576,8 @@ int fggc_server_submit(fggc_server *srv, const fggc_packets *pk, double eps, con
       shape.d = d;
       shape.N = r->Npad;
       FggcArgs fa{};
-      DimLsq plan[3];  // the layout reads the shift sets from the plan
-      for (int k = 0; k < d; ++k) build_dim_lsq(*st, k, eps, &plan[k]);
-      fill_fggc_args(fa, &shape, eps, g, *st, scale, precision, plan, r->slo, r->sn);
+      const Plan plan = plan_for(*st, d, eps);  // the layout reads the shift sets from the plan
+      fill_fggc_args(fa, &shape, eps, g, *st, scale, precision, plan.host, r->slo, r->sn);
       need += fggc_workspace_bytes(fa);
     } else if (r->N > 0) {
       fggc_packets shape{};

@@ -1,18 +1,20 @@
-// Stable bucket (counting) sort of packet indices by a small integer key, and
-// the pre-pass reduction over the packets.
+// Counting sort of key slots by a small integer key, and the pre-pass
+// reduction over the packets.
 //
-// bucket_sort: order[] lists packet indices grouped by ascending key, stable
-// (within a key, by index); start[b] is the first position of key b,
-// start[nbins] = N.  For nbins <= kMaxLdsBins:
-//   hist    each workgroup counts the keys of its contiguous chunk in LDS and
-//           writes the counts bin-major into table[bin * G + group];
-//   scan    exclusive prefix sum of the table (hipCUB device scan): the offset
-//           of every (bin, group) run, and start[] from its first column;
-//   place   each workgroup sorts its chunk's (key, local index) words in LDS
-//           with a bitonic network and places every element at the offset of
-//           its (key, group) run plus its rank among equal keys, so equal keys
-//           keep their index order.
-// Larger key ranges fall back to a stable hipCUB radix sort of (key, index).
+// bucket_positions: for every slot i with keys[i] in [0, nbins), pos[i] is its
+// position in key order (slots with kNoKey get kNoKey); start[b] is the first
+// position of key b and start[nbins] the number of keyed slots.  Producers then
+// write each slot's record straight to its position (no permutation array and
+// no gather).  For nbins <= kMaxLdsBins:
+//   rank    each workgroup counts the keys of its contiguous chunk with LDS
+//           atomics, keeping each slot's returned count as its rank inside
+//           (key, chunk), and writes the counts bin-major into
+//           table[bin * G + chunk];
+//   scan    exclusive prefix sum of the table (hipCUB device scan);
+//   pos     pos[i] = offset of (key, chunk) + rank; start[] from the table.
+// The order of slots inside a key follows the LDS atomics (unspecified).
+// Larger key ranges use a hipCUB radix sort of (key, slot) pairs and scatter
+// the sorted ranks back to the slots.
 //
 // packet_scan: per packet, NaN/Inf and magnitude checks, and per dimension the
 // range of floor(P/dp); a two-level reduction (per-workgroup results, then one
@@ -29,78 +31,57 @@ namespace {
 constexpr int64_t kMaxLdsBins = 32768;
 constexpr int kSortBlock = 1024;
 
-__global__ __launch_bounds__(kSortBlock) void bucket_hist_kernel(const uint32_t *__restrict__ keys, int64_t N,
+__global__ __launch_bounds__(kSortBlock) void bucket_rank_kernel(const uint32_t *__restrict__ keys, int64_t N,
                                                                 int64_t chunk, int64_t nbins, int G,
-                                                                uint32_t *__restrict__ table) {
+                                                                uint32_t *__restrict__ table,
+                                                                uint32_t *__restrict__ rank) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   uint32_t *cnt = reinterpret_cast<uint32_t *>(smem_raw);
   for (int64_t b = threadIdx.x; b < nbins; b += blockDim.x) cnt[b] = 0;
   __syncthreads();
   const int64_t lo = blockIdx.x * chunk, hi = min(N, lo + chunk);
-  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&cnt[keys[i]], 1u);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const uint32_t k = keys[i];
+    if (k != kNoKey) rank[i] = atomicAdd(&cnt[k], 1u);
+  }
   __syncthreads();
   for (int64_t b = threadIdx.x; b < nbins; b += blockDim.x) table[b * G + blockIdx.x] = cnt[b];
 }
 
-__global__ void bucket_start_kernel(const uint32_t *__restrict__ offs, int64_t nbins, int G, int64_t N,
-                                    int64_t *__restrict__ start) {
+__global__ void bucket_pos_kernel(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ rank,
+                                  int64_t N, int64_t chunk, int G, const uint32_t *__restrict__ offs,
+                                  uint32_t *__restrict__ pos) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const uint32_t k = keys[i];
+  pos[i] = k == kNoKey ? kNoKey : offs[(int64_t)k * G + i / chunk] + rank[i];
+}
+
+__global__ void bucket_start_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ table,
+                                    int64_t nbins, int G, int64_t *__restrict__ start) {
   const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (b < nbins) start[b] = offs[b * G];
-  if (b == nbins) start[b] = N;
-}
-
-// Each workgroup sorts its chunk's (key << lbits | local index) words in LDS
-// with a bitonic network; an element's rank among equal keys of the chunk is
-// its sorted position minus the first position of its key.  Deterministic,
-// and stable by index.
-__global__ __launch_bounds__(kSortBlock) void bucket_place_kernel(const uint32_t *__restrict__ keys, int64_t N,
-                                                                 int64_t chunk, int lbits, int G,
-                                                                 const uint32_t *__restrict__ offs,
-                                                                 uint32_t *__restrict__ order) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  uint32_t *a = reinterpret_cast<uint32_t *>(smem_raw);
-  const int C = 1 << lbits;  // chunk rounded up to a power of two
-  const int64_t lo = blockIdx.x * chunk, hi = min(N, lo + chunk);
-  for (int i = threadIdx.x; i < C; i += blockDim.x) {
-    const int64_t gi = lo + i;
-    a[i] = gi < hi ? ((keys[gi] << lbits) | (uint32_t)i) : 0xffffffffu;
-  }
-  __syncthreads();
-  for (int k = 2; k <= C; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < C; i += blockDim.x) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const uint32_t x = a[i], y = a[ixj];
-          const bool up = (i & k) == 0;
-          if ((x > y) == up) {
-            a[i] = y;
-            a[ixj] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  const int n = (int)(hi - lo);
-  for (int p = threadIdx.x; p < n; p += blockDim.x) {
-    const uint32_t v = a[p];
-    const uint32_t key = v >> lbits, li = v & ((1u << lbits) - 1);
-    // first sorted position of this key
-    int l = 0, r = p;
-    const uint32_t kv = key << lbits;
-    while (l < r) {
-      const int m = (l + r) >> 1;
-      if (a[m] < kv) l = m + 1;
-      else r = m;
-    }
-    order[offs[(int64_t)key * G + blockIdx.x] + (p - l)] = (uint32_t)(lo + li);
+  if (b == nbins) {
+    const int64_t last = nbins * G - 1;
+    start[b] = (int64_t)offs[last] + table[last];
   }
 }
 
-__global__ void iota_kernel(uint32_t *__restrict__ v, int64_t N) {
+// radix path: keys with kNoKey sort last (as nbins)
+__global__ void radix_prep_kernel(const uint32_t *__restrict__ keys, int64_t N, int64_t nbins,
+                                  uint32_t *__restrict__ k, uint32_t *__restrict__ v) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < N) v[i] = (uint32_t)i;
+  if (i >= N) return;
+  const uint32_t x = keys[i];
+  k[i] = x == kNoKey ? (uint32_t)nbins : x;
+  v[i] = (uint32_t)i;
+}
+
+__global__ void radix_pos_kernel(const uint32_t *__restrict__ sk, const uint32_t *__restrict__ sv,
+                                 int64_t N, int64_t nbins, uint32_t *__restrict__ pos) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  pos[sv[i]] = sk[i] == (uint32_t)nbins ? kNoKey : (uint32_t)i;
 }
 
 // packet pre-pass ---------------------------------------------------------
@@ -192,16 +173,16 @@ constexpr int kScanBlocks = 1024;
 
 struct SortPlan {
   bool lds;
-  int G, lbits;
+  int G;
   int64_t chunk;
   int bits;
-  size_t off_table, off_offs, off_tmp, tmp_bytes, off_k2, off_i1, off_i2, total;
+  size_t off_table, off_offs, off_rank, off_tmp, tmp_bytes, off_k1, off_k2, off_v1, off_v2, total;
 };
 
 SortPlan sort_plan(int64_t N, int64_t nbins) {
   SortPlan sp{};
   const int64_t Nn = std::max<int64_t>(N, 1);
-  sp.lds = nbins <= kMaxLdsBins && N <= ((int64_t)1 << 22);
+  sp.lds = nbins <= kMaxLdsBins;
   size_t o = 0;
   auto put = [&](size_t b) {
     size_t at = o;
@@ -209,22 +190,18 @@ SortPlan sort_plan(int64_t N, int64_t nbins) {
     return at;
   };
   if (sp.lds) {
-    // chunks of at most 2^14 elements (LDS bitonic sort); key and local index share 32 bits
-    sp.lbits = 12;
-    while (((int64_t)1 << sp.lbits) * 1024 < Nn && sp.lbits < 14) ++sp.lbits;
-    sp.chunk = (int64_t)1 << sp.lbits;
+    // chunks of >= 2048 slots, at most 1024 of them, and a table of at most ~2^22 entries
+    int64_t G = std::min<int64_t>(1024, (Nn + 2047) / 2048);
+    G = std::max<int64_t>(1, std::min<int64_t>(G, ((int64_t)1 << 22) / std::max<int64_t>(nbins, 1)));
+    sp.chunk = (Nn + G - 1) / G;
     sp.G = (int)((Nn + sp.chunk - 1) / sp.chunk);
-    int kb = 1;
-    while (((int64_t)1 << kb) < nbins) ++kb;
-    if (kb + sp.lbits > 31) sp.lds = false;  // padding (all ones) sorts after every entry
-  }
-  if (sp.lds) {
     const int64_t tn = nbins * sp.G;
     size_t tmp = 0;
     FGGC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, (uint32_t *)nullptr, (uint32_t *)nullptr, (int)tn));
     sp.tmp_bytes = tmp;
     sp.off_table = put(tn * 4);
     sp.off_offs = put(tn * 4);
+    sp.off_rank = put(Nn * 4);
     sp.off_tmp = put(tmp + 256);
   } else {
     sp.bits = 1;
@@ -234,9 +211,10 @@ SortPlan sort_plan(int64_t N, int64_t nbins) {
     hipcub::DoubleBuffer<uint32_t> kb(kk, kk), vb(vv, vv);
     FGGC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, kb, vb, (int)Nn, 0, sp.bits));
     sp.tmp_bytes = tmp;
+    sp.off_k1 = put(Nn * 4);
     sp.off_k2 = put(Nn * 4);
-    sp.off_i1 = put(Nn * 4);
-    sp.off_i2 = put(Nn * 4);
+    sp.off_v1 = put(Nn * 4);
+    sp.off_v2 = put(Nn * 4);
     sp.off_tmp = put(tmp + 256);
   }
   sp.total = o;
@@ -261,55 +239,58 @@ std::mutex g_sort_mu;
 
 }  // namespace
 
-size_t bucket_sort_bytes(int64_t N, int64_t nbins) { return sort_plan(N, nbins).total + 256; }
+size_t bucket_positions_bytes(int64_t N, int64_t nbins) { return sort_plan(N, nbins).total + 256; }
 
-void bucket_sort(uint32_t *keys, int64_t N, int64_t nbins, uint32_t *order, int64_t *start,
-                 void *scratch, hipStream_t s) {
+void bucket_positions(const uint32_t *keys, int64_t N, int64_t nbins, uint32_t *pos, int64_t *start,
+                      void *scratch, hipStream_t s) {
+  if (N >= ((int64_t)1 << 31)) fail(FGGC_EUNSUPPORTED, "more than 2^31 sort slots");
+  if (nbins >= ((int64_t)1 << 31)) fail(FGGC_EUNSUPPORTED, "more than 2^31 sort keys");
   const SortPlan sp = sort_plan(N, nbins);
   char *base = (char *)scratch;
   {
     std::lock_guard<std::mutex> lk(g_sort_mu);
     if (!g_sort_attr) {
-      FGGC_HIP(hipFuncSetAttribute((const void *)bucket_hist_kernel,
+      FGGC_HIP(hipFuncSetAttribute((const void *)bucket_rank_kernel,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxLdsBins * 4)));
-      FGGC_HIP(hipFuncSetAttribute((const void *)bucket_place_kernel,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
       g_sort_attr = true;
     }
   }
+  const unsigned gN = (unsigned)((std::max<int64_t>(N, 1) + 255) / 256);
   if (sp.lds) {
-    uint32_t *table = (uint32_t *)(base + sp.off_table), *offs = (uint32_t *)(base + sp.off_offs);
-    const size_t shm = (size_t)nbins * 4;
+    uint32_t *table = (uint32_t *)(base + sp.off_table), *offs = (uint32_t *)(base + sp.off_offs),
+             *rank = (uint32_t *)(base + sp.off_rank);
     if (N > 0) {
-      bucket_hist_kernel<<<dim3(sp.G), dim3(kSortBlock), shm, s>>>(keys, N, sp.chunk, nbins, sp.G, table);
+      bucket_rank_kernel<<<dim3(sp.G), dim3(kSortBlock), (size_t)nbins * 4, s>>>(keys, N, sp.chunk, nbins,
+                                                                                sp.G, table, rank);
       FGGC_HIP(hipGetLastError());
     } else {
       launch_zero(table, (size_t)nbins * sp.G * 4, s);
     }
     size_t tmp = sp.tmp_bytes;
     FGGC_HIP(hipcub::DeviceScan::ExclusiveSum(base + sp.off_tmp, tmp, table, offs, (int)(nbins * sp.G), s));
-    bucket_start_kernel<<<dim3((unsigned)((nbins + 1 + 255) / 256)), dim3(256), 0, s>>>(offs, nbins, sp.G, N, start);
+    bucket_start_kernel<<<dim3((unsigned)((nbins + 1 + 255) / 256)), dim3(256), 0, s>>>(offs, table, nbins,
+                                                                                      sp.G, start);
     FGGC_HIP(hipGetLastError());
     if (N > 0) {
-      const size_t shp = ((size_t)1 << sp.lbits) * 4;
-      bucket_place_kernel<<<dim3(sp.G), dim3(kSortBlock), shp, s>>>(keys, N, sp.chunk, sp.lbits, sp.G, offs, order);
+      bucket_pos_kernel<<<dim3(gN), dim3(256), 0, s>>>(keys, rank, N, sp.chunk, sp.G, offs, pos);
       FGGC_HIP(hipGetLastError());
     }
     return;
   }
-  // wide key range: stable radix sort of (key, index)
-  uint32_t *k2 = (uint32_t *)(base + sp.off_k2), *i1 = (uint32_t *)(base + sp.off_i1),
-           *i2 = (uint32_t *)(base + sp.off_i2);
+  uint32_t *k1 = (uint32_t *)(base + sp.off_k1), *k2 = (uint32_t *)(base + sp.off_k2),
+           *v1 = (uint32_t *)(base + sp.off_v1), *v2 = (uint32_t *)(base + sp.off_v2);
   if (N > 0) {
-    iota_kernel<<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s>>>(i1, N);
+    radix_prep_kernel<<<dim3(gN), dim3(256), 0, s>>>(keys, N, nbins, k1, v1);
     FGGC_HIP(hipGetLastError());
-    hipcub::DoubleBuffer<uint32_t> kb(keys, k2), vb(i1, i2);
+    hipcub::DoubleBuffer<uint32_t> kb(k1, k2), vb(v1, v2);
     size_t tmp = sp.tmp_bytes;
     FGGC_HIP(hipcub::DeviceRadixSort::SortPairs(base + sp.off_tmp, tmp, kb, vb, (int)N, 0, sp.bits, s));
-    FGGC_HIP(hipMemcpyAsync(order, vb.Current(), (size_t)N * 4, hipMemcpyDeviceToDevice, s));
-    radix_start_kernel<<<dim3((unsigned)((nbins + 1 + 255) / 256)), dim3(256), 0, s>>>(N, kb.Current(), nbins, start);
+    radix_pos_kernel<<<dim3(gN), dim3(256), 0, s>>>(kb.Current(), vb.Current(), N, nbins, pos);
+    FGGC_HIP(hipGetLastError());
+    radix_start_kernel<<<dim3((unsigned)((nbins + 1 + 255) / 256)), dim3(256), 0, s>>>(N, kb.Current(), nbins,
+                                                                                     start);
   } else {
-    radix_start_kernel<<<dim3((unsigned)((nbins + 1 + 255) / 256)), dim3(256), 0, s>>>(0, keys, nbins, start);
+    radix_start_kernel<<<dim3((unsigned)((nbins + 1 + 255) / 256)), dim3(256), 0, s>>>(0, k1, nbins, start);
   }
   FGGC_HIP(hipGetLastError());
 }

@@ -169,3 +169,58 @@ def test_fggc_vs_direct_cfg1(ctx):
     e = rel(uf.cpu().numpy(), ud.cpu().numpy())
     log("cfg1 fggc vs direct", e)
     assert e < 2e-6
+
+
+def test_repeated_calls_replay_graph_with_live_data(ctx, orc):
+    # Device-resident calls with the same buffers run eagerly, are captured,
+    # then replayed from a cached graph: every run must read the buffers as
+    # they are at that call (a replay after an in-place update sees the update).
+    ps = small_1d(21, N=3000, eps=1.0 / 256, M=2048)
+    st = F.default_strategy(1, ps.eps, "Q4P2")
+    Q, P, S, a = t(ps.Q), t(ps.P), t(ps.S), t(ps.a)
+    u = torch.empty(ps.M, dtype=torch.complex64, device="cuda")
+    sd = st.describe()
+    ref = orc.fggc(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, sd["Nq"][:1], sd["dp"][:1], sd["dq_off"],
+                   sd["dp_off"])
+    outs = []
+    for i in range(4):
+        ctx.reconstruct(Q, P, S, a, ps.eps, ps.M, st, precision=F.FP32, out=u)
+        torch.cuda.synchronize()
+        outs.append(u.cpu().numpy().copy())
+        log(f"call {i}: vs oracle {rel(outs[-1], ref):.2e}")
+        assert rel(outs[-1], ref) <= 1e-6
+    a.mul_(2.0)  # the same buffers, new values
+    torch.cuda.synchronize()
+    ctx.reconstruct(Q, P, S, a, ps.eps, ps.M, st, precision=F.FP32, out=u)
+    torch.cuda.synchronize()
+    e = rel(u.cpu().numpy(), 2 * ref)
+    log(f"replay after in-place update: {e:.2e}")
+    assert e <= 1e-6
+
+
+def test_calls_on_two_streams_are_ordered(ctx, orc):
+    # one context, two streams: the second call's stream waits for the first
+    # call's use of the shared workspace
+    ps1 = small_1d(31, N=2500, eps=1.0 / 256, M=2048)
+    ps2 = small_1d(32, N=4000, eps=1.0 / 64, M=1024)
+    st1 = F.default_strategy(1, ps1.eps, "Q4P2")
+    st2 = F.default_strategy(1, ps2.eps, "Q2P2")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    d1 = [t(x) for x in (ps1.Q, ps1.P, ps1.S, ps1.a)]
+    d2 = [t(x) for x in (ps2.Q, ps2.P, ps2.S, ps2.a)]
+    torch.cuda.synchronize()
+    u1 = torch.empty(ps1.M, dtype=torch.complex64, device="cuda")
+    u2 = torch.empty(ps2.M, dtype=torch.complex64, device="cuda")
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            ctx.reconstruct(*d1, ps1.eps, ps1.M, st1, precision=F.FP32, out=u1, stream=s1)
+        with torch.cuda.stream(s2):
+            ctx.direct_sum(*d2, ps2.eps, ps2.M, ps2.R, precision=F.FP32, out=u2, stream=s2)
+    torch.cuda.synchronize()
+    sd = st1.describe()
+    r1 = orc.fggc(ps1.Q, ps1.P, ps1.S, ps1.a, ps1.eps, ps1.M, sd["Nq"][:1], sd["dp"][:1], sd["dq_off"],
+                  sd["dp_off"])
+    r2 = orc.direct_sum(ps2.Q, ps2.P, ps2.S, ps2.a, ps2.eps, ps2.M, ps2.R)
+    e1, e2 = rel(u1.cpu().numpy(), r1), rel(u2.cpu().numpy(), r2)
+    log(f"two streams: fggc {e1:.2e}, direct {e2:.2e}")
+    assert e1 <= 1e-6 and e2 <= 1e-6
