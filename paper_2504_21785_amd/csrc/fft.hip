@@ -27,63 +27,70 @@ template <typename T> __device__ __forceinline__ T csub(T a, T b) { return T{a.x
 constexpr int kMaxBfly = 8;  // radix-4 butterflies per thread per pass
 
 struct FftAxis {
-  int64_t n, inner, nlines;
-  int log2n, lines;  // lines per workgroup
+  int64_t nlines;
+  int log2n, log2L;   // line length and lines per workgroup (powers of two)
+  int log2inner;      // lines of one axis are 2^log2inner apart (inner stride)
   int inverse;
   int transpose_out;  // lines are contiguous rows: store element i of line l at dst[i * nlines + l]
-  int64_t nbig;       // > 0: multiply output i of line (bo, bi) by exp(-+ 2 pi i bi i / nbig)
+  int log2big;        // > 0: multiply output i of line (bo, bi) by exp(-+ 2 pi i bi i / 2^log2big)
 };
 
+// All index arithmetic on powers of two (shifts and masks, 32-bit inside the
+// workgroup, 64-bit only for global offsets).
 template <typename T>
 __global__ __launch_bounds__(1024) void fft_axis_kernel(const T *src, T *dst, FftAxis a,
                                                         const T *__restrict__ tw,
                                                         const T *__restrict__ twbig) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sm = reinterpret_cast<T *>(smem_raw);
-  const int64_t n = a.n;
-  const int L = a.lines;
-  const int64_t line0 = (int64_t)blockIdx.x * L;
-  const int64_t tot = (int64_t)L * n;
+  const int lg = a.log2n, lgL = a.log2L, lgin = a.log2inner;
+  const int n = 1 << lg, L = 1 << lgL;
+  const int64_t inner_mask = ((int64_t)1 << lgin) - 1;
+  const int64_t line0 = (int64_t)blockIdx.x << lgL;
+  const int tot = L << lg;
   // load (coalesced: along the line when lines are contiguous, across lines otherwise)
-  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
-    int64_t l, i;
-    if (a.inner == 1) {
-      l = e / n;
-      i = e - l * n;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    int l, i;
+    if (lgin == 0) {
+      l = e >> lg;
+      i = e & (n - 1);
     } else {
-      i = e / L;
-      l = e - i * L;
+      i = e >> lgL;
+      l = e & (L - 1);
     }
     const int64_t line = line0 + l;
     if (line < a.nlines) {
-      const int64_t bo = line / a.inner, bi = line - bo * a.inner;
-      sm[l * n + i] = src[(bo * n + i) * a.inner + bi];
+      const int64_t bo = line >> lgin, bi = line & inner_mask;
+      sm[(l << lg) + i] = src[((((bo << lg) + i)) << lgin) + bi];
     }
   }
   __syncthreads();
-  int64_t Ns = 1;
-  int rem = a.log2n;
+  int lgNs = 0;
+  int rem = lg;
   while (rem > 0) {
-    const int R = rem >= 2 ? 4 : 2;
-    const int64_t nb = (int64_t)L * (n / R);  // butterflies in this pass
-    const int64_t stride = n / R;
+    const int lgR = rem >= 2 ? 2 : 1;
+    const int lgstride = lg - lgR;
+    const int stride = 1 << lgstride, Ns = 1 << lgNs;
+    const int nb = L << lgstride;  // butterflies in this pass
+    const int tshift = lg - lgNs - lgR;  // twiddle step n / (Ns R) = 2^tshift
     T v[kMaxBfly][4];
 #pragma unroll
     for (int c = 0; c < kMaxBfly; ++c) {
-      const int64_t b = threadIdx.x + (int64_t)c * blockDim.x;
+      const int b = threadIdx.x + c * (int)blockDim.x;
       if (b >= nb) break;
-      const int64_t l = b / stride, j = b - l * stride;
-      const int64_t k = j % Ns;
-      const T *src = sm + l * n;
-      for (int r = 0; r < R; ++r) v[c][r] = src[j + r * stride];
-      // twiddles exp(-+ 2 pi i r k / (Ns R)) = tw[r k n / (Ns R)]
-      const int64_t tstep = k * (n / (Ns * R));
-      for (int r = 1; r < R; ++r) {
-        T w = tw[r * tstep];
-        if (a.inverse) w.y = -w.y;
-        v[c][r] = cmul(v[c][r], w);
-      }
-      if (R == 4) {
+      const int l = b >> lgstride, j = b & (stride - 1);
+      const int k = j & (Ns - 1);
+      const T *sp = sm + (l << lg);
+      const int tstep = k << tshift;
+      if (lgR == 2) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[c][r] = sp[j + r * stride];
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+          T w = tw[r * tstep];
+          if (a.inverse) w.y = -w.y;
+          v[c][r] = cmul(v[c][r], w);
+        }
         const T s0 = cadd(v[c][0], v[c][2]), d0 = csub(v[c][0], v[c][2]);
         const T s1 = cadd(v[c][1], v[c][3]), d1 = csub(v[c][1], v[c][3]);
         // forward: multiply d1 by -i; inverse: by +i
@@ -93,6 +100,11 @@ __global__ __launch_bounds__(1024) void fft_axis_kernel(const T *src, T *dst, Ff
         v[c][1] = cadd(d0, jd1);
         v[c][3] = csub(d0, jd1);
       } else {
+        v[c][0] = sp[j];
+        v[c][1] = sp[j + stride];
+        T w = tw[tstep];
+        if (a.inverse) w.y = -w.y;
+        v[c][1] = cmul(v[c][1], w);
         const T x0 = v[c][0], x1 = v[c][1];
         v[c][0] = cadd(x0, x1);
         v[c][1] = csub(x0, x1);
@@ -101,38 +113,45 @@ __global__ __launch_bounds__(1024) void fft_axis_kernel(const T *src, T *dst, Ff
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < kMaxBfly; ++c) {
-      const int64_t b = threadIdx.x + (int64_t)c * blockDim.x;
+      const int b = threadIdx.x + c * (int)blockDim.x;
       if (b >= nb) break;
-      const int64_t l = b / stride, j = b - l * stride;
-      const int64_t k = j % Ns;
-      const int64_t idxD = (j / Ns) * Ns * R + k;
-      T *dst = sm + l * n;
-      for (int r = 0; r < R; ++r) dst[idxD + r * Ns] = v[c][r];
+      const int l = b >> lgstride, j = b & (stride - 1);
+      const int k = j & (Ns - 1);
+      const int idxD = ((j >> lgNs) << (lgNs + lgR)) + k;
+      T *dp = sm + (l << lg);
+      if (lgR == 2) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dp[idxD + r * Ns] = v[c][r];
+      } else {
+        dp[idxD] = v[c][0];
+        dp[idxD + Ns] = v[c][1];
+      }
     }
     __syncthreads();
-    Ns *= R;
-    rem -= R == 4 ? 2 : 1;
+    lgNs += lgR;
+    rem -= lgR;
   }
-  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
-    int64_t l, i;
-    if (a.inner == 1 && !a.transpose_out) {
-      l = e / n;
-      i = e - l * n;
+  const int bigmask = (1 << a.log2big) - 1;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    int l, i;
+    if (lgin == 0 && !a.transpose_out) {
+      l = e >> lg;
+      i = e & (n - 1);
     } else {
-      i = e / L;
-      l = e - i * L;
+      i = e >> lgL;
+      l = e & (L - 1);
     }
     const int64_t line = line0 + l;
     if (line < a.nlines) {
-      const int64_t bo = line / a.inner, bi = line - bo * a.inner;
-      T v = sm[l * n + i];
-      if (a.nbig > 0) {  // four-step twiddle exp(-+ 2 pi i bi i / nbig)
-        T w = twbig[(bi * i) % a.nbig];
+      const int64_t bo = line >> lgin, bi = line & inner_mask;
+      T v = sm[(l << lg) + i];
+      if (a.log2big > 0) {  // four-step twiddle exp(-+ 2 pi i bi i / nbig)
+        T w = twbig[((int)bi * i) & bigmask];
         if (a.inverse) w.y = -w.y;
         v = cmul(v, w);
       }
-      if (a.transpose_out) dst[i * a.nlines + line] = v;
-      else dst[(bo * n + i) * a.inner + bi] = v;
+      if (a.transpose_out) dst[(int64_t)i * a.nlines + line] = v;
+      else dst[((((bo << lg) + i)) << lgin) + bi] = v;
     }
   }
 }
@@ -188,6 +207,9 @@ void launch_axis(const T *src, T *dst, int64_t n, int64_t inner, int64_t outer, 
   // keep at least ~256 workgroups when there are enough lines
   L = std::min(L, std::max<int64_t>(1, nlines / 256));
   L = std::min(L, nlines);
+  int lgL = 0;
+  while (((int64_t)2 << lgL) <= L) ++lgL;  // lines per workgroup: a power of two
+  L = (int64_t)1 << lgL;
   const int R = log2n >= 2 ? 4 : 2;
   int64_t bfly = L * (n / R);
   int threads = (int)std::min<int64_t>(1024, std::max<int64_t>(64, (bfly + 3) / 4));
@@ -196,19 +218,26 @@ void launch_axis(const T *src, T *dst, int64_t n, int64_t inner, int64_t outer, 
     // keep per-thread butterflies within the register budget
     if (threads < 1024) threads = std::min(1024, threads * 2);
     else {
-      L = std::max<int64_t>(1, L / 2);
+      --lgL;
+      L = (int64_t)1 << lgL;
       bfly = L * (n / R);
     }
   }
+  int lgin = 0;
+  while (((int64_t)1 << lgin) < inner) ++lgin;
+  if (((int64_t)1 << lgin) != inner) fail(FGGC_EDEVICE, "internal: FFT inner stride must be a power of two");
+  int lgbig = 0;
+  if (nbig > 0) {
+    while (((int64_t)1 << lgbig) < nbig) ++lgbig;
+  }
   FftAxis a;
-  a.n = n;
-  a.inner = inner;
   a.nlines = nlines;
   a.log2n = log2n;
-  a.lines = (int)L;
+  a.log2L = lgL;
+  a.log2inner = lgin;
   a.inverse = inverse;
   a.transpose_out = transpose_out;
-  a.nbig = nbig;
+  a.log2big = lgbig;
   const T *tw = (const T *)twiddles(n, elem == 8 ? FGGC_FP32 : FGGC_FP64);
   const T *twb = nbig > 0 ? (const T *)twiddles(nbig, elem == 8 ? FGGC_FP32 : FGGC_FP64) : tw;
   const size_t shm = (size_t)L * n * elem;

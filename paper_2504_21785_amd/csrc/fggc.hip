@@ -151,6 +151,88 @@ __device__ __forceinline__ void dim_coeffs(const DimLsq &L, double Q, double P, 
   }
 }
 
+// The same with the shift-set sizes fixed (basis j = a NP + b): the Gaussian
+// factor splits as gq_a gp_b, and the powers Es^dp_b, Et^dq_a, Fi^dq_a are
+// formed once per shift instead of once per basis function.
+template <int NQ, int NP>
+__device__ __forceinline__ void dim_coeffs_exact(const DimLsq &L, double Q, double P, double dq, double dp,
+                                                 int64_t &iq, int64_t &ip, double *cre, double *cim) {
+  constexpr int N1 = NQ * NP;
+  double s, t;
+  int_frac(Q / dq, iq, s);
+  int_frac(P / dp, ip, t);
+  const double Cq = L.Cq, Cp = L.Cp, CC = Cq * Cp;
+  constexpr double inv2pi = 1.0 / kTwoPi;
+  double e0c, e0s, esc, ess, etc_, ets, f0c, f0s, fic, fis;
+  cis_rev(0.5 * CC * s * t * inv2pi, e0c, e0s);
+  cis_rev(0.5 * CC * s * inv2pi, esc, ess);
+  cis_rev(-0.5 * CC * t * inv2pi, etc_, ets);
+  {
+    const double w = CC * inv2pi * (double)ip;  // CC ip in revolutions
+    cis_rev(w, fic, fis);
+    cis_rev(-s * w, f0c, f0s);
+  }
+  double gq[NQ], qr[NQ], qi[NQ], hr[NQ], hi[NQ];
+#pragma unroll
+  for (int a = 0; a < NQ; ++a) {
+    const int dqa = L.dq[a * NP];
+    const double x = (double)dqa - s;
+    gq[a] = exp(-0.25 * Cq * Cq * x * x);
+    cis_pow(etc_, ets, dqa, qr[a], qi[a]);
+    cis_pow(fic, fis, dqa, hr[a], hi[a]);
+  }
+  double gp[NP], pr[NP], pi[NP];
+#pragma unroll
+  for (int b = 0; b < NP; ++b) {
+    const int dpb = L.dp[b];
+    const double x = (double)dpb - t;
+    gp[b] = exp(-0.25 * Cp * Cp * x * x);
+    cis_pow(esc, ess, dpb, pr[b], pi[b]);
+  }
+  double fre[N1], fim[N1];
+#pragma unroll
+  for (int a = 0; a < NQ; ++a)
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      const int j = a * NP + b;
+      // E0 * Es^dp * Et^dq * D, times gq gp
+      double xr = e0c * pr[b] - e0s * pi[b], xi = e0c * pi[b] + e0s * pr[b];
+      const double yr = xr * qr[a] - xi * qi[a], yi = xr * qi[a] + xi * qr[a];
+      const double dr = L.D[2 * j], di = L.D[2 * j + 1];
+      const double mag = gq[a] * gp[b];
+      fre[j] = mag * (yr * dr - yi * di);
+      fim[j] = mag * (yr * di + yi * dr);
+    }
+  double zre[N1], zim[N1];
+#pragma unroll
+  for (int i = 0; i < N1; ++i) {
+    double yr = 0.0, yi = 0.0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      const double vr = L.V[2 * (j * N1 + i)], vi = L.V[2 * (j * N1 + i) + 1];
+      yr = fma(vr, fre[j], fma(vi, fim[j], yr));
+      yi = fma(vr, fim[j], fma(-vi, fre[j], yi));
+    }
+    zre[i] = yr * L.inv[i];
+    zim[i] = yi * L.inv[i];
+  }
+#pragma unroll
+  for (int j = 0; j < N1; ++j) {
+    double gr = 0.0, gi = 0.0;
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+      const double vr = L.V[2 * (j * N1 + i)], vi = L.V[2 * (j * N1 + i) + 1];
+      gr = fma(vr, zre[i], fma(-vi, zim[i], gr));
+      gi = fma(vr, zim[i], fma(vi, zre[i], gi));
+    }
+    const double tr = gr, ti = -gi;  // conjugate
+    const int a = j / NP;
+    const double cs = f0c * hr[a] - f0s * hi[a], sn = f0c * hi[a] + f0s * hr[a];
+    cre[j] = tr * cs - ti * sn;
+    cim[j] = tr * sn + ti * cs;
+  }
+}
+
 // Sort keys of a packet: its own p-cell (relative to the box of packet
 // p-cells) major, a q-tile minor -- one key slot for every q-tile its
 // neighbours [q + mindq, q + maxdq] reach (at most two per dimension, as a
@@ -232,7 +314,7 @@ struct CoefParams {
 
 // One thread per packet, in packet order (coalesced reads); the record is
 // written to the sorted position of each of the packet's key slots.
-template <int D, int N1, typename T>
+template <int D, int N1, int NQ, int NP, typename T>
 __global__ __launch_bounds__(256) void fggc_coef_kernel(CoefParams p, const uint32_t *__restrict__ pos,
                                                         char *__restrict__ recs) {
   using R = decltype(T{}.x);
@@ -241,9 +323,15 @@ __global__ __launch_bounds__(256) void fggc_coef_kernel(CoefParams p, const uint
   double cre[D][N1], cim[D][N1];
   int64_t iq[D], ip[D];
 #pragma unroll
-  for (int k = 0; k < D; ++k)
-    dim_coeffs<N1>(p.lsq[k], p.Q[k * p.N + j], p.P[k * p.N + j], p.dq[k], p.dp[k], iq[k], ip[k],
-                   cre[k], cim[k]);
+  for (int k = 0; k < D; ++k) {
+    if constexpr (NQ > 0) {
+      dim_coeffs_exact<NQ, NP>(p.lsq[k], p.Q[k * p.N + j], p.P[k * p.N + j], p.dq[k], p.dp[k], iq[k],
+                               ip[k], cre[k], cim[k]);
+    } else {
+      dim_coeffs<N1>(p.lsq[k], p.Q[k * p.N + j], p.P[k * p.N + j], p.dq[k], p.dp[k], iq[k], ip[k],
+                     cre[k], cim[k]);
+    }
+  }
   double sn, cs;
   {
     const double rev = p.S[j] / (kTwoPi * p.eps);
@@ -905,7 +993,7 @@ template <int N1, typename T>
 __global__ __launch_bounds__(256) void fggc_agg1_kernel(Agg1Params p, T *__restrict__ A) {
   using R = decltype(T{}.x);
   constexpr int RB = rec_bytes<1, N1, T>();
-  constexpr int K = N1 / 2, STEP = 64 / N1, U = 8;
+  constexpr int K = N1 / 2, STEP = 64 / N1, U = 16;
   __shared__ T part[4][32 * N1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m = lane % N1, q0 = lane / N1;
@@ -1123,6 +1211,49 @@ __global__ __launch_bounds__(256) void band_mac_kernel(MacParams m, const T *__r
   U[e] = T{(R)accr, (R)acci};
 }
 
+// One dimension: eight lanes per frequency split the slice loop, then a
+// shuffle reduction (FP64) -- eight times the waves of the plain kernel.
+template <typename T, typename R>
+__global__ __launch_bounds__(256) void band_mac1_kernel(MacParams m, const T *__restrict__ F,
+                                                         const R *__restrict__ gam,
+                                                         const int64_t *__restrict__ kst,
+                                                         T *__restrict__ U) {
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t e = id >> 3;
+  const int g = (int)(id & 7);
+  const bool live = e < m.M[0];
+  double accr = 0.0, acci = 0.0;
+  if (live) {
+    const double se = sqrt(m.eps);
+    const int64_t a = m.kmin[0] - e, b = m.kmax[0] - e, M = m.M[0];
+    const int64_t j0 = a >= 0 ? (a + M - 1) / M : -((-a) / M);
+    const int64_t j1 = b >= 0 ? b / M : -((-b + M - 1) / M);
+    for (int64_t ja = j0; ja <= j1; ++ja) {
+      const int64_t k0 = e + ja * M;
+      const double pk = m.eps * (double)k0;
+      int64_t la = (int64_t)floor((pk - m.cK * se) * m.inv_dp[0]) - m.slo[0] - 1;
+      int64_t lb = (int64_t)ceil((pk + m.cK * se) * m.inv_dp[0]) - m.slo[0] + 1;
+      if (la < 0) la = 0;
+      if (lb > m.sn[0] - 1) lb = m.sn[0] - 1;
+      const int64_t q0 = ((k0 % m.Nq[0]) + m.Nq[0]) % m.Nq[0];
+      for (int64_t l0 = la + g; l0 <= lb; l0 += 8) {
+        const int64_t i0 = k0 - kst[m.koff[0] + l0];
+        if (i0 < 0 || i0 >= m.nb[0]) continue;
+        const double g0 = (double)gam[m.toff[0] + l0 * m.nb[0] + i0];
+        const T f = F[l0 * m.Nq[0] + q0];
+        accr = fma(g0, (double)f.x, accr);
+        acci = fma(g0, (double)f.y, acci);
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) {
+    accr += __shfl_xor(accr, o);
+    acci += __shfl_xor(acci, o);
+  }
+  if (live && g == 0) U[e] = T{(R)accr, (R)acci};
+}
+
 struct FggcLayout {
   int d, N1, rec_b, ns;
   bool agg1;  // one dimension: aggregate + stencil instead of tile accumulation
@@ -1227,9 +1358,19 @@ template <int D, int N1, typename T>
 void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams &cp,
                        const uint32_t *pos, char *recs, const int64_t *start, void *agg, T *cells,
                        hipStream_t s) {
+  const DimLsq &c0 = a.lsq[0];
+  int cnp = 0;
+  for (int m = 0; m < c0.n1; ++m)
+    if (c0.dq[m] == c0.dq[0]) ++cnp;
+  const int cnq = c0.n1 / cnp;
   if (cp.N > 0) {
     StageScope sc(a.prof, "fggc_coef", s);
-    fggc_coef_kernel<D, N1, T><<<dim3((unsigned)((cp.N + 255) / 256)), dim3(256), 0, s>>>(cp, pos, recs);
+    const dim3 g((unsigned)((cp.N + 255) / 256)), b(256);
+    if (N1 == 4 && cnq == 2 && cnp == 2) fggc_coef_kernel<D, N1, 2, 2, T><<<g, b, 0, s>>>(cp, pos, recs);
+    else if (N1 == 8 && cnq == 4 && cnp == 2) fggc_coef_kernel<D, N1, 4, 2, T><<<g, b, 0, s>>>(cp, pos, recs);
+    else if (N1 == 8 && cnq == 2 && cnp == 4) fggc_coef_kernel<D, N1, 2, 4, T><<<g, b, 0, s>>>(cp, pos, recs);
+    else if (N1 == 16 && cnq == 4 && cnp == 4) fggc_coef_kernel<D, N1, 4, 4, T><<<g, b, 0, s>>>(cp, pos, recs);
+    else fggc_coef_kernel<D, N1, 0, 0, T><<<g, b, 0, s>>>(cp, pos, recs);
     FGGC_HIP(hipGetLastError());
   }
   AccParams ap{};
@@ -1453,7 +1594,8 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, T *cells, R *gam, int6
   const unsigned nblk = (unsigned)((L.npts + 255) / 256);
   {
   StageScope sc(a.prof, "fggc_band_mac", s);
-  if (d == 1) band_mac_kernel<1, T, R><<<nblk, 256, 0, s>>>(m, cells, gam, kst, U);
+  if (d == 1)
+    band_mac1_kernel<T, R><<<(unsigned)((8 * L.npts + 255) / 256), 256, 0, s>>>(m, cells, gam, kst, U);
   else if (d == 2) band_mac_kernel<2, T, R><<<nblk, 256, 0, s>>>(m, cells, gam, kst, U);
   else band_mac_kernel<3, T, R><<<nblk, 256, 0, s>>>(m, cells, gam, kst, U);
   FGGC_HIP(hipGetLastError());

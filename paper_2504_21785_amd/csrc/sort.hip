@@ -190,8 +190,8 @@ SortPlan sort_plan(int64_t N, int64_t nbins) {
     return at;
   };
   if (sp.lds) {
-    // chunks of >= 2048 slots, at most 1024 of them, and a table of at most ~2^22 entries
-    int64_t G = std::min<int64_t>(1024, (Nn + 2047) / 2048);
+    // chunks of >= 8192 slots, at most 1024 of them, and a table of at most ~2^22 entries
+    int64_t G = std::min<int64_t>(1024, (Nn + 8191) / 8192);
     G = std::max<int64_t>(1, std::min<int64_t>(G, ((int64_t)1 << 22) / std::max<int64_t>(nbins, 1)));
     sp.chunk = (Nn + G - 1) / G;
     sp.G = (int)((Nn + sp.chunk - 1) / sp.chunk);
