@@ -26,6 +26,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_T = 78.6  # FP64 vector TFLOP/s
 # VALU issue slots: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one non-packed op per lane per cycle)
 VALU_SLOT_PEAK_T = 256 * 64 * 2.4e9 / 1e12
 
@@ -35,6 +36,25 @@ WORKLOADS = {
     "cfg2": 2,
     "cfg3": 3,
 }
+
+
+def measured_traffic(workload, stage):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) of a stage, from the
+    committed counter run of this workload -- None when there is none or when the
+    kernel sources have changed since the counters were taken."""
+    from paper_2504_21785_amd import rocprof_summary as RS
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha256") != RS.source_digest():
+        return None
+    st = t.get("stages", {}).get(stage)
+    if not st or "fetch_size_bytes" not in st or "write_size_bytes" not in st:
+        return None
+    return st["fetch_size_bytes"] + st["write_size_bytes"]
 
 
 def log(*a):
@@ -246,23 +266,29 @@ def main():
     cells_b = slices * nq * 8
     mpts = int(np.prod(ps.M))
     n1 = int(st.nq * st.np)
-    rec_b = 16 * ((8 * d + 15) // 16) + d * (4 if n1 <= 4 else (8 if n1 <= 8 else 16)) * 8
-    per_launch_bytes = {
-        # packets in (through the sort order), one coefficient record out per packet
-        "fggc_coef": ps.N * ((2 * d + 1) * 8 + 16 + 4 + rec_b),
+    n1b = 4 if n1 <= 4 else (8 if n1 <= 8 else 16)
+    rec_b = 16 * ((8 * d + 15) // 16) + d * n1b * 8
+    ns = 1 if d == 1 else 2 ** d
+    # (bound, amount per launch, unit of the amount, peak in that unit per second)
+    per_launch = {
+        # FP64: two complex n1 x n1 mat-vecs per dimension, rhs and shift, Kronecker weights
+        "fggc_coef": ("alu", ps.N * (d * (16 * n1 * n1 + 60 * n1) + 6 * n1 ** d) / 1e12,
+                      "TFLOP/s", FP64_PEAK_T),
         # records in, the dense cell array written once
-        "fggc_accum": ps.N * rec_b + cells_b,
-        "fggc_sort": ps.N * (2 * d * 8 + 16),
-        "fggc_fft_q": 2 * cells_b,          # read and write the cell array
-        "fggc_band_mac": cells_b + mpts * 8,  # read the spectra, write the grid spectrum
-        "fggc_ifft": 2 * mpts * 8,
-        "fggc_band_table": 0,
+        "fggc_accum": ("hbm", (ps.N * rec_b + cells_b) / 1e9, "GB/s", HBM_PEAK_GBS),
+        # packets' Q and P in; keys, ranks and positions
+        "fggc_sort": ("hbm", ps.N * (2 * d * 8 + 12 * ns) / 1e9, "GB/s", HBM_PEAK_GBS),
+        "fggc_fft_q": ("hbm", 2 * cells_b / 1e9, "GB/s", HBM_PEAK_GBS),
+        "fggc_band_mac": ("hbm", (cells_b + mpts * 8) / 1e9, "GB/s", HBM_PEAK_GBS),
+        "fggc_ifft": ("hbm", 2 * mpts * 8 / 1e9, "GB/s", HBM_PEAK_GBS),
+        "fggc_band_table": ("hbm", 0.0, "GB/s", HBM_PEAK_GBS),
     }
+    bound, amount, unit, peak = per_launch.get(dom, ("hbm", 0.0, "GB/s", HBM_PEAK_GBS))
     dom_ms = stages[dom]["avg_ms"]
-    achieved = per_launch_bytes.get(dom, 0) / (dom_ms * 1e-3) / 1e9
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "alg_bytes_per_launch": per_launch_bytes.get(dom, 0), "avg_launch_ms": dom_ms}
+    achieved = amount / (dom_ms * 1e-3)
+    roofline = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": measured_traffic(args.workload, dom),
+                "algorithmic_per_launch": amount, "avg_launch_ms": dom_ms}
     direct_roofline = None
     if do_direct and "ds_kernel" in stages:
         pairs = ps.N * (math.pi * ps.R ** 2 / np.prod([2 * math.pi / m for m in ps.M]) if d == 2

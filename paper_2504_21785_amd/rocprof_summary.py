@@ -6,13 +6,43 @@
         per kernel: mean counter value per dispatch; with --calib-mib, the
         value of the plain elementwise copy kernel (reads and writes M MiB)
         gives the factor that turns the counter's KiB into bytes
+    python -m paper_2504_21785_amd.rocprof_summary traffic FETCH.db WRITE.db --calib-mib M
+            --workload W --command CMD --out FILE.json
+        HBM bytes per launch of each FGGC stage (FETCH_SIZE + WRITE_SIZE,
+        calibrated), stamped with the digest of the kernel sources
 
 Only reads the database; nothing here touches a GPU.
 """
 import argparse
+import hashlib
+import json
+import os
 import re
 import sqlite3
 import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+# stage name -> kernel-name fragments (the kernels that make up the stage)
+STAGE_KERNELS = {
+    "fggc_coef": ["fggc_coef_kernel"],
+    "fggc_accum": ["fggc_agg1_kernel", "fggc_stencil1_kernel", "fggc_accum_wave_kernel",
+                   "fggc_accum_kernel", "fggc_accum_generic_kernel"],
+    "fggc_sort": ["fggc_key_kernel", "bucket_rank_kernel", "bucket_pos_kernel", "bucket_start_kernel"],
+    "fggc_band_mac": ["band_mac"],
+    "ds_kernel": ["ds_kernel"],
+}
+
+
+def source_digest() -> str:
+    """SHA-256 over the kernel sources (csrc/*.hip, *.h, *.cpp), in name order."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
 
 
 def short(name: str) -> str:
@@ -57,15 +87,53 @@ def counter(db, name, calib_mib=None):
     return "\n".join(lines)
 
 
+def per_dispatch(db, name):
+    c = sqlite3.connect(db)
+    rows = c.execute("select kernel_name, dispatch_id, sum(value) from counters_collection "
+                     "where counter_name = ? group by kernel_name, dispatch_id", (name,)).fetchall()
+    per = {}
+    for k, _, v in rows:
+        per.setdefault(k, []).append(v)
+    return {k: sum(v) / len(v) for k, v in per.items()}
+
+
+def traffic(fetch_db, write_db, calib_mib, workload, command):
+    out = {"workload": workload, "command": command, "source_sha256": source_digest(),
+           "calibration_mib": calib_mib, "stages": {}}
+    for cname, db in (("FETCH_SIZE", fetch_db), ("WRITE_SIZE", write_db)):
+        per = per_dispatch(db, cname)
+        cal = [v for k, v in per.items() if "elementwise" in k]
+        factor = calib_mib * 1024.0 / max(cal) if cal else 1.0
+        out[cname.lower() + "_factor"] = factor
+        for stage, frags in STAGE_KERNELS.items():
+            ks = [k for k in per if any(f in k for f in frags)]
+            if not ks:
+                continue
+            b = sum(per[k] for k in ks) * 1024.0 * factor
+            out["stages"].setdefault(stage, {})[cname.lower() + "_bytes"] = b
+            out["stages"][stage]["kernels"] = sorted(short(k) for k in ks)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["kernels", "counter"])
+    ap.add_argument("what", choices=["kernels", "counter", "traffic"])
     ap.add_argument("db")
     ap.add_argument("name", nargs="?")
     ap.add_argument("--calib-mib", type=float, default=None)
+    ap.add_argument("--workload", default="cfg1")
+    ap.add_argument("--command", default="")
+    ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     if a.what == "kernels":
         print(kernels(a.db))
+    elif a.what == "traffic":
+        t = traffic(a.db, a.name, a.calib_mib or 256.0, a.workload, a.command)
+        text = json.dumps(t, indent=1)
+        if a.out:
+            with open(a.out, "w") as f:
+                f.write(text + "\n")
+        print(text)
     else:
         if not a.name:
             sys.exit("counter name required")
