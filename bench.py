@@ -181,6 +181,7 @@ def main():
 
     k = WORKLOADS[args.workload]
     ps = W.config(k)
+    log(f"generated {args.workload}: {ps.N} packets")
     d = ps.d
     sname = args.strategy or ("Q2P2" if d == 3 else "Q4P2")
     st = F.default_strategy(d, ps.eps, sname)
@@ -199,11 +200,12 @@ def main():
         ctx.direct_sum(Q, P, S, a, ps.eps, ps.M, ps.R, precision=F.FP32, out=u_d)
 
     log(f"workload {args.workload}: d={d} N={ps.N} M={ps.M} eps={ps.eps} strategy={sname}")
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step_fggc()
         if do_direct:
             step_direct()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1} of {args.warmup} done")
 
     if args.calib_copy_mb > 0:
         cx = torch.ones(args.calib_copy_mb << 18, dtype=torch.float32, device=dev)
@@ -238,6 +240,7 @@ def main():
         if do_direct:
             step_direct()
     torch.cuda.synchronize()
+    log("profiled pass done")
     stage_names = ["prepass", "fggc_sort", "fggc_coef", "fggc_accum", "fggc_fft_q",
                    "fggc_band_table", "fggc_band_mac", "fggc_ifft", "ds_prep", "ds_sort",
                    "ds_kernel", "ds_reduce"]

@@ -694,7 +694,7 @@ int fggc_reconstruct(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fg
     fa.pk = &dpk;
     fa.u = host_out ? ctx->ws.take(out_bytes) : u_out;
     fa.prof = ctx->profiling ? &ctx->prof : nullptr;
-    if (!host_in && !host_out && !ctx->profiling && plan.dev) {
+    if (!host_in && !host_out && !ctx->profiling && plan.dev && fggc_graph_safe(fa)) {
       std::vector<int64_t> key = {1, d, precision, dpk.N, dbits(eps), dbits(scale),
                                   (int64_t)(uintptr_t)dpk.Q, (int64_t)(uintptr_t)dpk.P,
                                   (int64_t)(uintptr_t)dpk.S, (int64_t)(uintptr_t)dpk.a,

@@ -187,6 +187,8 @@ void launch_pad_packets(int d, int64_t N, int64_t Npad, double *Q, double *P, do
 // bucket_positions_bytes(N, nbins).
 constexpr uint32_t kNoKey = 0xffffffffu;
 size_t bucket_positions_bytes(int64_t N, int64_t nbins);
+// True when the sort's launches may be captured into a graph and replayed.
+bool bucket_positions_graph_safe(int64_t N, int64_t nbins);
 void bucket_positions(const uint32_t *keys, int64_t N, int64_t nbins, uint32_t *pos, int64_t *start,
                       void *scratch, hipStream_t s);
 
@@ -201,6 +203,8 @@ struct DirectArgs {
   Profiler *prof = nullptr;
 };
 size_t direct_workspace_bytes(const DirectArgs &a);
+// True when launch_direct's launches may be captured into a graph and replayed.
+bool direct_graph_safe(const DirectArgs &a);
 void launch_direct(const DirectArgs &a, Workspace &ws, hipStream_t s);
 
 // FGGC.
@@ -219,6 +223,8 @@ struct FggcArgs {
   Profiler *prof = nullptr;
 };
 size_t fggc_workspace_bytes(const FggcArgs &a);
+// True when launch_fggc's launches may be captured into a graph and replayed.
+bool fggc_graph_safe(const FggcArgs &a);
 void launch_fggc(const FggcArgs &a, Workspace &ws, hipStream_t s);
 // Only the cell array (eq. 2.25) into `cells` (device).
 void launch_fggc_cells(const FggcArgs &a, void *cells, Workspace &ws, hipStream_t s);

@@ -472,6 +472,11 @@ DsLayout ds_layout(const DirectArgs &a) {
 
 size_t direct_workspace_bytes(const DirectArgs &a) { return ds_layout(a).total; }
 
+bool direct_graph_safe(const DirectArgs &a) {
+  const DsLayout L = ds_layout(a);
+  return bucket_positions_graph_safe(a.pk->N, L.nbins);
+}
+
 void launch_direct(const DirectArgs &a, Workspace &ws, hipStream_t s) {
   const DsLayout L = ds_layout(a);
   const bool f64 = a.precision == FGGC_FP64;

@@ -1608,6 +1608,11 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, T *cells, R *gam, int6
 
 size_t fggc_workspace_bytes(const FggcArgs &a) { return fggc_layout(a).total + 1024; }
 
+bool fggc_graph_safe(const FggcArgs &a) {
+  const FggcLayout L = fggc_layout(a);
+  return bucket_positions_graph_safe(L.nslots, L.nbins);
+}
+
 size_t fggc_cells_workspace_bytes(const FggcArgs &a) {
   FggcLayout L = fggc_layout(a);
   return L.off_cells + 1024;

@@ -337,7 +337,12 @@ void fggc_server::run(Slot *sl, Request &r) {
   auto it = sl->graphs.begin();
   for (; it != sl->graphs.end(); ++it)
     if (!(it->first < key) && !(key < it->first)) break;
-  if (it != sl->graphs.end()) {
+  const bool graph_ok = r.use_fggc ? fggc_graph_safe(fa) : direct_graph_safe(da);
+  if (!graph_ok) {
+    enqueue();
+    std::lock_guard<std::mutex> lk(mu);
+    n_eager += 1;
+  } else if (it != sl->graphs.end()) {
     sl->graphs.splice(sl->graphs.begin(), sl->graphs, it);
     FGGC_HIP(hipGraphLaunch(sl->graphs.front().second, s));
     std::lock_guard<std::mutex> lk(mu);

@@ -241,6 +241,11 @@ std::mutex g_sort_mu;
 
 size_t bucket_positions_bytes(int64_t N, int64_t nbins) { return sort_plan(N, nbins).total + 256; }
 
+// The radix path runs the library's onesweep sort, which resets its lookback
+// states and histogram with memsets and its ordered block counter from the
+// host on the stream: none of that may be replayed from a captured graph.
+bool bucket_positions_graph_safe(int64_t N, int64_t nbins) { return sort_plan(N, nbins).lds; }
+
 void bucket_positions(const uint32_t *keys, int64_t N, int64_t nbins, uint32_t *pos, int64_t *start,
                       void *scratch, hipStream_t s) {
   if (N >= ((int64_t)1 << 31)) fail(FGGC_EUNSUPPORTED, "more than 2^31 sort slots");

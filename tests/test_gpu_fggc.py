@@ -224,3 +224,24 @@ def test_calls_on_two_streams_are_ordered(ctx, orc):
     e1, e2 = rel(u1.cpu().numpy(), r1), rel(u2.cpu().numpy(), r2)
     log(f"two streams: fggc {e1:.2e}, direct {e2:.2e}")
     assert e1 <= 1e-6 and e2 <= 1e-6
+
+
+def test_repeated_3d_calls_on_radix_sort_path(ctx, orc):
+    # A 3D layout with more than 2^15 bins sorts through the library radix
+    # sort, whose stream memsets must not be replayed from a graph: repeated
+    # calls with the same buffers run eagerly each time and must agree.
+    ps = W.gen_mesh(3, 8, 3, 0.5, (0.5, 0.3, 0.3), 1.0 / 64, 64, seed=9)
+    st = F.default_strategy(3, ps.eps, "Q2P2")
+    Q, P, S, a = t(ps.Q), t(ps.P), t(ps.S), t(ps.a)
+    u = torch.empty(ps.M, dtype=torch.complex64, device="cuda")
+    pts = heavy_points(ps, 40, 10, 4)
+    sd = st.describe()
+    ref = orc.fggc(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, sd["Nq"][:3], sd["dp"][:3], sd["dq_off"],
+                   sd["dp_off"], pts=pts)
+    for i in range(3):
+        log(f"3d radix-path call {i}")
+        ctx.reconstruct(Q, P, S, a, ps.eps, ps.M, st, precision=F.FP32, out=u)
+        torch.cuda.synchronize()
+        e = rel(u.cpu().numpy().reshape(-1)[pts].astype(np.complex128), ref)
+        log(f"  vs oracle {e:.2e}")
+        assert e <= 1e-6
