@@ -242,8 +242,8 @@ def main():
     torch.cuda.synchronize()
     log("profiled pass done")
     stage_names = ["prepass", "fggc_sort", "fggc_coef", "fggc_accum", "fggc_fft_q",
-                   "fggc_band_table", "fggc_band_mac", "fggc_ifft", "ds_prep", "ds_sort",
-                   "ds_kernel", "ds_reduce"]
+                   "fggc_band_table", "fggc_band_mac", "fggc_contract", "fggc_ifft", "ds_prep",
+                   "ds_sort", "ds_kernel", "ds_reduce"]
     stages = {}
     for sn in stage_names:
         ms, cnt = ctx.stage_time(sn)
@@ -283,6 +283,8 @@ def main():
         "fggc_sort": ("hbm", ps.N * (2 * d * 8 + 12 * ns) / 1e9, "GB/s", HBM_PEAK_GBS),
         "fggc_fft_q": ("hbm", 2 * cells_b / 1e9, "GB/s", HBM_PEAK_GBS),
         "fggc_band_mac": ("hbm", (cells_b + mpts * 8) / 1e9, "GB/s", HBM_PEAK_GBS),
+        # separable finish (d >= 2): read the cell array, write the grid spectrum
+        "fggc_contract": ("hbm", (cells_b + mpts * 8) / 1e9, "GB/s", HBM_PEAK_GBS),
         "fggc_ifft": ("hbm", 2 * mpts * 8 / 1e9, "GB/s", HBM_PEAK_GBS),
         "fggc_band_table": ("hbm", 0.0, "GB/s", HBM_PEAK_GBS),
     }

@@ -231,6 +231,9 @@ void launch_fggc_cells(const FggcArgs &a, void *cells, Workspace &ws, hipStream_
 size_t fggc_cells_workspace_bytes(const FggcArgs &a);
 
 
+// Device table exp(-2 pi i k / n), k < n, in the working precision (cached).
+const void *fft_twiddles(int64_t n, int precision);
+
 // Batched in-place d-dimensional FFT (powers of two).
 size_t fft_workspace_bytes(int d, const int64_t *n, int precision, int64_t batch);
 void launch_fft(int d, const int64_t *n, int64_t batch, int direction, int precision, void *data,

@@ -10,21 +10,10 @@
 #include <tuple>
 
 #include "common.h"
+#include "lds_fft.h"
 
 namespace fggc {
 namespace {
-
-template <typename T> struct Real;
-template <> struct Real<float2> { using type = float; };
-template <> struct Real<double2> { using type = double; };
-
-template <typename T> __device__ __forceinline__ T cmul(T a, T b) {
-  return T{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-template <typename T> __device__ __forceinline__ T cadd(T a, T b) { return T{a.x + b.x, a.y + b.y}; }
-template <typename T> __device__ __forceinline__ T csub(T a, T b) { return T{a.x - b.x, a.y - b.y}; }
-
-constexpr int kMaxBfly = 8;  // radix-4 butterflies per thread per pass
 
 struct FftAxis {
   int64_t nlines;
@@ -65,72 +54,7 @@ __global__ __launch_bounds__(1024) void fft_axis_kernel(const T *src, T *dst, Ff
     }
   }
   __syncthreads();
-  int lgNs = 0;
-  int rem = lg;
-  while (rem > 0) {
-    const int lgR = rem >= 2 ? 2 : 1;
-    const int lgstride = lg - lgR;
-    const int stride = 1 << lgstride, Ns = 1 << lgNs;
-    const int nb = L << lgstride;  // butterflies in this pass
-    const int tshift = lg - lgNs - lgR;  // twiddle step n / (Ns R) = 2^tshift
-    T v[kMaxBfly][4];
-#pragma unroll
-    for (int c = 0; c < kMaxBfly; ++c) {
-      const int b = threadIdx.x + c * (int)blockDim.x;
-      if (b >= nb) break;
-      const int l = b >> lgstride, j = b & (stride - 1);
-      const int k = j & (Ns - 1);
-      const T *sp = sm + (l << lg);
-      const int tstep = k << tshift;
-      if (lgR == 2) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[c][r] = sp[j + r * stride];
-#pragma unroll
-        for (int r = 1; r < 4; ++r) {
-          T w = tw[r * tstep];
-          if (a.inverse) w.y = -w.y;
-          v[c][r] = cmul(v[c][r], w);
-        }
-        const T s0 = cadd(v[c][0], v[c][2]), d0 = csub(v[c][0], v[c][2]);
-        const T s1 = cadd(v[c][1], v[c][3]), d1 = csub(v[c][1], v[c][3]);
-        // forward: multiply d1 by -i; inverse: by +i
-        const T jd1 = a.inverse ? T{-d1.y, d1.x} : T{d1.y, -d1.x};
-        v[c][0] = cadd(s0, s1);
-        v[c][2] = csub(s0, s1);
-        v[c][1] = cadd(d0, jd1);
-        v[c][3] = csub(d0, jd1);
-      } else {
-        v[c][0] = sp[j];
-        v[c][1] = sp[j + stride];
-        T w = tw[tstep];
-        if (a.inverse) w.y = -w.y;
-        v[c][1] = cmul(v[c][1], w);
-        const T x0 = v[c][0], x1 = v[c][1];
-        v[c][0] = cadd(x0, x1);
-        v[c][1] = csub(x0, x1);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < kMaxBfly; ++c) {
-      const int b = threadIdx.x + c * (int)blockDim.x;
-      if (b >= nb) break;
-      const int l = b >> lgstride, j = b & (stride - 1);
-      const int k = j & (Ns - 1);
-      const int idxD = ((j >> lgNs) << (lgNs + lgR)) + k;
-      T *dp = sm + (l << lg);
-      if (lgR == 2) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) dp[idxD + r * Ns] = v[c][r];
-      } else {
-        dp[idxD] = v[c][0];
-        dp[idxD + Ns] = v[c][1];
-      }
-    }
-    __syncthreads();
-    lgNs += lgR;
-    rem -= lgR;
-  }
+  lds_fft_rows<T>(sm, lg, L, n, a.inverse, tw);
   const int bigmask = (1 << a.log2big) - 1;
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     int l, i;
@@ -285,6 +209,7 @@ void ensure_attrs() {
 
 }  // namespace
 
+const void *fft_twiddles(int64_t n, int precision) { return twiddles(n, precision); }
 
 size_t fft_workspace_bytes(int d, const int64_t *n, int precision, int64_t batch) {
   if (d == 1 && n[0] > 4096 && batch > 0)

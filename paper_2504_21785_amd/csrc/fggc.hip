@@ -28,6 +28,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "lds_fft.h"
 
 namespace fggc {
 namespace {
@@ -1254,6 +1255,101 @@ __global__ __launch_bounds__(256) void band_mac1_kernel(MacParams m, const T *__
   if (live && g == 0) U[e] = T{(R)accr, (R)acci};
 }
 
+// Separable Fourier finish (d >= 2).  The band weight gamma_l(k) and the DFT
+// both factor over dimensions, so the sum over slices l and cells i of
+// eq. (2.24) in Fourier space is a product of one-dimensional operators
+//   K_k(k'; l, i) = sum_j gamma_{l,k}(k' + j M_k) exp(-2 pi i (k' + j M_k) i / Nq_k)
+// applied one dimension at a time, last dimension first.  A pass reads the
+// array as [O][L][A][N][B] (L slices and N q-cells of dimension k), FFTs each
+// (slice, b) row over q in LDS, folds the slices into the M grid frequencies
+// with the band weights (FP64 accumulation) and writes [O][A][M][B].
+struct ContractParams {
+  int64_t O, L, A, B, M;
+  int lgN, W, Lc, R;  // W: b values per workgroup; Lc: slices per LDS chunk; R: outputs per thread
+  int MS;             // workgroups sharing one line group, each with M / MS of the frequencies
+  int64_t nb, toff, koff, slo, kmin, kmax;
+  double eps, cK, inv_dp;
+};
+
+
+template <typename T, typename R>
+__global__ __launch_bounds__(256) void fft_contract_kernel(ContractParams p, const T *__restrict__ X,
+                                                           T *__restrict__ Y, const R *__restrict__ gam,
+                                                           const int64_t *__restrict__ kst,
+                                                           const T *__restrict__ tw) {
+  using RR = decltype(T{}.x);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *sm = reinterpret_cast<T *>(smem_raw);
+  const int N = 1 << p.lgN, W = p.W, M = (int)p.M;
+  const int64_t nbc = p.B / W;
+  int64_t g = blockIdx.x;
+  const int mg = (int)(g % p.MS);
+  g /= p.MS;
+  const int64_t bc = g % nbc;
+  g /= nbc;
+  const int64_t a = g % p.A, o = g / p.A;
+  const int64_t b0 = bc * W;
+  const int Mg = M / p.MS, k0g = mg * Mg;  // this workgroup's frequencies [k0g, k0g + Mg)
+  const int nout = Mg * W;
+  const int nb = (int)p.nb;
+  // LDS: rows of the chunk, one accumulator per output ([w][k]), band rows
+  T *acc = sm + (size_t)p.Lc * N * W;
+  R *bg = reinterpret_cast<R *>(acc + nout);
+  int *bk = reinterpret_cast<int *>(bg + (size_t)p.Lc * nb);
+  for (int e = threadIdx.x; e < nout; e += blockDim.x) acc[e] = T{0, 0};
+  const double se = sqrt(p.eps);
+  const int kmin = (int)p.kmin, kmax = (int)p.kmax, slo = (int)p.slo;
+  for (int lc0 = 0; lc0 < (int)p.L; lc0 += p.Lc) {
+    const int lcn = min(p.Lc, (int)p.L - lc0);
+    const int tot = lcn * N * W;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+      const int w = e % W, rest = e / W;
+      const int n = rest & (N - 1), l = rest >> p.lgN;
+      sm[(l * W + w) * N + n] = X[(((o * p.L + lc0 + l) * p.A + a) * N + n) * p.B + b0 + w];
+    }
+    for (int e = threadIdx.x; e < lcn * nb; e += blockDim.x) bg[e] = gam[p.toff + (int64_t)lc0 * nb + e];
+    for (int e = threadIdx.x; e < lcn; e += blockDim.x) bk[e] = (int)kst[p.koff + lc0 + e];
+    __syncthreads();
+    lds_fft_rows<T>(sm, p.lgN, lcn * W, N, 0, tw);
+    for (int e = threadIdx.x; e < nout; e += blockDim.x) {
+      const int kp = k0g + e % Mg, w = e / Mg;
+      // aliases kk = kp + j M inside [kmin, kmax]
+      const int lo = kmin - kp, hi = kmax - kp;
+      const int j0 = lo >= 0 ? (lo + M - 1) / M : -((-lo) / M);
+      const int j1 = hi >= 0 ? hi / M : -((-hi + M - 1) / M);
+      double xr = 0.0, xi = 0.0;
+      for (int j = j0; j <= j1; ++j) {
+        const int kk = kp + j * M;
+        const double pk = p.eps * (double)kk;
+        int la = (int)floor((pk - p.cK * se) * p.inv_dp) - slo - 1;
+        int lb = (int)ceil((pk + p.cK * se) * p.inv_dp) - slo + 1;
+        la = max(la, lc0);
+        lb = min(lb, lc0 + lcn - 1);
+        const int q = kk & (N - 1);
+        for (int l = la; l <= lb; ++l) {
+          const int ll = l - lc0;
+          const int i0 = kk - bk[ll];
+          if (i0 < 0 || i0 >= nb) continue;
+          const double gv = (double)bg[ll * nb + i0];
+          const T v = sm[(ll * W + w) * N + q];
+          xr = fma(gv, (double)v.x, xr);
+          xi = fma(gv, (double)v.y, xi);
+        }
+      }
+      T c = acc[e];
+      c.x += (RR)xr;
+      c.y += (RR)xi;
+      acc[e] = c;
+    }
+    __syncthreads();
+  }
+  // write coalesced along b
+  for (int e = threadIdx.x; e < nout; e += blockDim.x) {
+    const int kl = e / W, w = e % W;
+    Y[((o * p.A + a) * p.M + k0g + kl) * p.B + b0 + w] = acc[w * Mg + kl];
+  }
+}
+
 struct FggcLayout {
   int d, N1, rec_b, ns;
   bool agg1;  // one dimension: aggregate + stencil instead of tile accumulation
@@ -1261,7 +1357,7 @@ struct FggcLayout {
   int64_t nb[3], toff[3], koff[3], ntab, nkst;
   int mindp, maxdp, mindq, maxdq;
   size_t off_lsq, off_keys, off_pos, off_sort, off_start, off_recs, off_agg, off_cells, off_gam, off_kst,
-      off_spec, total;
+      off_spec, off_x1, off_x2, total;
 };
 
 int n1_bucket(int n1) { return n1 <= 4 ? 4 : (n1 <= 8 ? 8 : 16); }
@@ -1350,6 +1446,19 @@ FggcLayout fggc_layout(const FggcArgs &a) {
   L.off_gam = put((size_t)L.ntab * (es / 2));
   L.off_kst = put((size_t)L.nkst * 8 + 64);
   L.off_spec = put((size_t)L.npts * es);  // grid spectrum (the inverse FFT writes u from it)
+  // separable finish (d >= 2): outputs of the passes over the last and the
+  // middle dimension, [l_<k][i_<k][grid frequencies of dims >= k]
+  L.off_x1 = L.off_x2 = 0;
+  if (d >= 2) {
+    auto pass_out = [&](int k) {
+      size_t v = 1;
+      for (int j = 0; j < k; ++j) v *= (size_t)a.sn[j] * (size_t)a.Nq[j];
+      for (int j = k; j < d; ++j) v *= (size_t)a.g.n[j];
+      return v;
+    };
+    L.off_x1 = put(pass_out(d - 1) * es);
+    if (d == 3) L.off_x2 = put(pass_out(1) * es);
+  }
   L.total = o;
   return L;
 }
@@ -1546,13 +1655,86 @@ void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells
 #undef FGGC_CA
 }
 
+bool g_contract_attr = false;
+std::mutex g_contract_mu;
+
+// One separable pass over dimension k (see fft_contract_kernel).
 template <typename T, typename R>
-void finish_stage(const FggcArgs &a, const FggcLayout &L, T *cells, R *gam, int64_t *kst,
+void launch_contract(const FggcArgs &a, const FggcLayout &L, int k, const T *in, T *out, const R *gam,
+                     const int64_t *kst, const MacParams &m, hipStream_t s) {
+  {
+    std::lock_guard<std::mutex> lk(g_contract_mu);
+    if (!g_contract_attr) {
+      FGGC_HIP(hipFuncSetAttribute((const void *)fft_contract_kernel<float2, float>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+      FGGC_HIP(hipFuncSetAttribute((const void *)fft_contract_kernel<double2, double>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+      g_contract_attr = true;
+    }
+  }
+  const int d = a.g.d;
+  ContractParams p{};
+  p.O = 1;
+  p.A = 1;
+  p.B = 1;
+  for (int j = 0; j < k; ++j) {
+    p.O *= a.sn[j];
+    p.A *= a.Nq[j];
+  }
+  for (int j = k + 1; j < d; ++j) p.B *= a.g.n[j];
+  p.L = a.sn[k];
+  p.M = a.g.n[k];
+  int lgN = 0;
+  while (((int64_t)1 << lgN) < a.Nq[k]) ++lgN;
+  p.lgN = lgN;
+  const int64_t N = a.Nq[k];
+  const size_t es = sizeof(T);
+  // b values per workgroup: coalesced runs along b, at most 4096 outputs per workgroup
+  int64_t W = 1;
+  while (W * 2 <= std::min<int64_t>(16, p.B) && W * 2 * p.M <= 4096) W *= 2;
+  // LDS chunk: rows * N elements within the butterfly budget of lds_fft_rows
+  // for 256 threads, counting the radix-2 pass of an odd log2 N
+  // (rows * N / 2 <= 256 * kMaxBfly)
+  const int64_t elems = 256 * kMaxBfly * 2;
+  while (W > 1 && N * W > elems) W /= 2;
+  if (N * W > elems) fail(FGGC_EUNSUPPORTED, "q-mesh too long for the separable finish");
+  p.W = (int)W;
+  p.Lc = (int)std::max<int64_t>(1, std::min<int64_t>(p.L, elems / (N * W)));
+  // split the frequencies of a line group over several workgroups when there
+  // are few line groups (each recomputes the group's FFTs)
+  const int64_t groups = p.O * p.A * (p.B / W);
+  int MS = 1;
+  while (groups * MS < 1024 && MS * 2 <= 16 && (p.M / (MS * 2)) * W >= 256) MS *= 2;
+  p.MS = MS;
+  p.R = 0;
+  p.nb = L.nb[k];
+  p.toff = L.toff[k];
+  p.koff = L.koff[k];
+  p.slo = a.slo[k];
+  p.kmin = m.kmin[k];
+  p.kmax = m.kmax[k];
+  p.eps = a.eps;
+  p.cK = a.cK;
+  p.inv_dp = 1.0 / a.dp[k];
+  const size_t rows_b = ((size_t)p.Lc * N * W + (size_t)(p.M / MS) * W) * es;
+  const size_t band_b = (size_t)p.Lc * p.nb * sizeof(R) + (size_t)p.Lc * 4;
+  const size_t shm = rows_b + band_b + 16;
+  if (shm > 131072) fail(FGGC_EUNSUPPORTED, "separable finish needs more than 128 KB of LDS");
+  const int64_t blocks = groups * MS;
+  if (blocks >= ((int64_t)1 << 31)) fail(FGGC_EUNSUPPORTED, "too many workgroups for the separable finish");
+  const T *tw = (const T *)fft_twiddles(N, a.precision);
+  fft_contract_kernel<T, R><<<dim3((unsigned)blocks), dim3(256), shm, s>>>(p, in, out, gam, kst, tw);
+  FGGC_HIP(hipGetLastError());
+}
+
+template <typename T, typename R>
+void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, R *gam, int64_t *kst,
                   void *spec, Workspace &ws, hipStream_t s) {
   const int d = a.g.d;
   const int prec = a.precision;
-  // F5: forward DFT over q of every p-slice
-  launch_fft(d, a.Nq, L.nslices, -1, prec, cells, ws, s, a.prof, "fggc_fft_q");
+  // F5: forward DFT over q of every p-slice (one dimension; higher dimensions
+  // fold the DFT into the separable passes below)
+  if (d == 1) launch_fft(d, a.Nq, L.nslices, -1, prec, cells, ws, s, a.prof, "fggc_fft_q");
   // band tables
   BandParams bp{};
   bp.d = d;
@@ -1592,7 +1774,17 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, T *cells, R *gam, int6
   m.cK = a.cK;
   T *U = (T *)spec;
   const unsigned nblk = (unsigned)((L.npts + 255) / 256);
-  {
+  if (d >= 2) {
+    // F5 + F6 as d separable passes, last dimension first, into the spectrum
+    StageScope sc(a.prof, "fggc_contract", s);
+    T *x1 = (T *)(base + L.off_x1), *x2 = (T *)(base + L.off_x2);
+    const T *in = cells;
+    for (int k = d - 1; k >= 0; --k) {
+      T *out = k == 0 ? U : (k == d - 1 ? x1 : x2);
+      launch_contract<T, R>(a, L, k, in, out, gam, kst, m, s);
+      in = out;
+    }
+  } else {
   StageScope sc(a.prof, "fggc_band_mac", s);
   if (d == 1)
     band_mac1_kernel<T, R><<<(unsigned)((8 * L.npts + 255) / 256), 256, 0, s>>>(m, cells, gam, kst, U);
@@ -1630,10 +1822,10 @@ void launch_fggc(const FggcArgs &a, Workspace &ws, hipStream_t s) {
   void *cells = base + L.off_cells;
   cells_stage(a, L, base, cells, s);
   if (a.precision == FGGC_FP64)
-    finish_stage<double2, double>(a, L, (double2 *)cells, (double *)(base + L.off_gam),
+    finish_stage<double2, double>(a, L, base, (double2 *)cells, (double *)(base + L.off_gam),
                                   (int64_t *)(base + L.off_kst), base + L.off_spec, ws, s);
   else
-    finish_stage<float2, float>(a, L, (float2 *)cells, (float *)(base + L.off_gam),
+    finish_stage<float2, float>(a, L, base, (float2 *)cells, (float *)(base + L.off_gam),
                                 (int64_t *)(base + L.off_kst), base + L.off_spec, ws, s);
 }
 
