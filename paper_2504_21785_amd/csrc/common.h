@@ -110,7 +110,7 @@ constexpr int kMaxN1 = 16;  // largest one-dimensional basis (nq * np)
 
 // Eigenpairs of the eps-free Gram matrix (3.22) of one dimension, with the
 // reciprocal eigenvalues already cut: A~^+ = V diag(inv) V^H.
-struct DimLsq {
+struct alignas(16) DimLsq {
   int n1;
   int dq[kMaxN1], dp[kMaxN1];
   double Cq, Cp;
@@ -137,6 +137,8 @@ Plan plan_for(const fggc_strategy &st, int d, double eps);
 // --------------------------------------------------------------------------
 // device-side parameter blocks (passed by value to kernels)
 // --------------------------------------------------------------------------
+
+static_assert(sizeof(DimLsq) % 16 == 0, "DimLsq is copied in 16-byte units");
 
 // Packet record for the direct sum, one per packet, sorted by spatial bin.
 struct alignas(16) DsRec {

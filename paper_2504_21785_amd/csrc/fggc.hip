@@ -319,18 +319,33 @@ template <int D, int N1, int NQ, int NP, typename T>
 __global__ __launch_bounds__(256) void fggc_coef_kernel(CoefParams p, const uint32_t *__restrict__ pos,
                                                         char *__restrict__ recs) {
   using R = decltype(T{}.x);
+  // one dimension: the plan is staged in LDS and read as broadcasts instead of
+  // held in scalar registers (which the eigenvector matrix overflows); with
+  // more dimensions the scalar path measured faster
+  __shared__ DimLsq sl[1];
+  if constexpr (D == 1) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(p.lsq);
+    uint4 *dst = reinterpret_cast<uint4 *>(sl);
+    for (int e = threadIdx.x; e < (int)(sizeof(DimLsq) / 16); e += blockDim.x) dst[e] = src[e];
+    __syncthreads();
+  }
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= p.N) return;
   double cre[D][N1], cim[D][N1];
   int64_t iq[D], ip[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) {
+    const double qv = p.Q[k * p.N + j], pv = p.P[k * p.N + j];
     if constexpr (NQ > 0) {
-      dim_coeffs_exact<NQ, NP>(p.lsq[k], p.Q[k * p.N + j], p.P[k * p.N + j], p.dq[k], p.dp[k], iq[k],
-                               ip[k], cre[k], cim[k]);
+      if constexpr (D == 1)
+        dim_coeffs_exact<NQ, NP>(sl[0], qv, pv, p.dq[k], p.dp[k], iq[k], ip[k], cre[k], cim[k]);
+      else
+        dim_coeffs_exact<NQ, NP>(p.lsq[k], qv, pv, p.dq[k], p.dp[k], iq[k], ip[k], cre[k], cim[k]);
     } else {
-      dim_coeffs<N1>(p.lsq[k], p.Q[k * p.N + j], p.P[k * p.N + j], p.dq[k], p.dp[k], iq[k], ip[k],
-                     cre[k], cim[k]);
+      if constexpr (D == 1)
+        dim_coeffs<N1>(sl[0], qv, pv, p.dq[k], p.dp[k], iq[k], ip[k], cre[k], cim[k]);
+      else
+        dim_coeffs<N1>(p.lsq[k], qv, pv, p.dq[k], p.dp[k], iq[k], ip[k], cre[k], cim[k]);
     }
   }
   double sn, cs;
@@ -987,22 +1002,24 @@ struct Agg1Params {
   int64_t Nq, tile, ntq, npc;
 };
 
-// 4 waves split the bin's records; within a wave, lane l owns coefficient
-// m = l % N1 of the q-cells l / N1 + (64 / N1) j (j < N1 / 2) of the 32-cell
-// tile; the four partial tiles are summed through LDS at the end.
+// Eight waves split the bin's records; within a wave, lane l owns
+// coefficient m = l % N1 of the q-cells l / N1 + (64 / N1) j (j < N1 / 2) of
+// the 32-cell tile; the partial tiles are summed through LDS at the end.
+constexpr int kAggWaves = 8;
+
 template <int N1, typename T>
-__global__ __launch_bounds__(256) void fggc_agg1_kernel(Agg1Params p, T *__restrict__ A) {
+__global__ __launch_bounds__(64 * kAggWaves) void fggc_agg1_kernel(Agg1Params p, T *__restrict__ A) {
   using R = decltype(T{}.x);
   constexpr int RB = rec_bytes<1, N1, T>();
   constexpr int K = N1 / 2, STEP = 64 / N1, U = 16;
-  __shared__ T part[4][32 * N1];
+  __shared__ T part[kAggWaves][32 * N1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m = lane % N1, q0 = lane / N1;
   const int64_t bin = blockIdx.x;
   const int64_t pc = bin / p.ntq, t = bin - pc * p.ntq;
   const int tbase = (int)(t * p.tile);
   const int64_t r0 = p.start[bin], r1 = p.start[bin + 1], n = r1 - r0;
-  const int64_t ra = r0 + (n * w) / 4, rb = r0 + (n * (w + 1)) / 4;
+  const int64_t ra = r0 + (n * w) / kAggWaves, rb = r0 + (n * (w + 1)) / kAggWaves;
   R ar[K], ai[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) ar[j] = ai[j] = 0;
@@ -1039,11 +1056,11 @@ __global__ __launch_bounds__(256) void fggc_agg1_kernel(Agg1Params p, T *__restr
 #pragma unroll
   for (int j = 0; j < K; ++j) part[w][(q0 + STEP * j) * N1 + m] = T{ar[j], ai[j]};
   __syncthreads();
-  for (int e = threadIdx.x; e < 32 * N1; e += 256) {
+  for (int e = threadIdx.x; e < 32 * N1; e += blockDim.x) {
     const int ql = e / N1;
     T sum = part[0][e];
 #pragma unroll
-    for (int x = 1; x < 4; ++x) {
+    for (int x = 1; x < kAggWaves; ++x) {
       sum.x += part[x][e].x;
       sum.y += part[x][e].y;
     }
@@ -1519,7 +1536,7 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
     gp.tile = L.tile[0];
     gp.ntq = L.ntq[0];
     gp.npc = L.npc[0];
-    const dim3 gg((unsigned)L.nbins), gb(256);
+    const dim3 gg((unsigned)L.nbins), gb(64 * kAggWaves);
     fggc_agg1_kernel<N1, T><<<gg, gb, 0, s>>>(gp, A);
     FGGC_HIP(hipGetLastError());
     Stencil1Params sp{};

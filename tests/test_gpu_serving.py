@@ -2,7 +2,7 @@
 
 Each request's result from the server, submitted in a mix with others and
 repeated so that its pipeline runs eagerly, is captured into a graph and is
-replayed, must equal the same request run alone through the synchronous entry
+replayed (per slot), must equal the same request run alone through the synchronous entry
 point, within the FP32 tolerance.  Requests follow the serving stream's
 distribution (mixed 1D/2D, eps, grid) with packet counts kept small here.
 """
@@ -73,8 +73,13 @@ def alone(ctx, ps, fggc=True):
 def test_server_mix_equals_alone_host_inputs(ctx, reqs):
     ref = [alone(ctx, ps) for ps in reqs]
     srv = F.Server(ctx, n_streams=3)
+    # a shape runs eagerly on its first sighting and is captured on its second;
+    # a graph belongs to the slot that captured it, so a repeat may land on a
+    # slot that captures it anew -- at most once per (shape, slot): with 8
+    # shapes and 3 slots, 6 rounds leave at least 48 - 8 - 24 replays
+    rounds = 6
     try:
-        for rnd in range(3):  # eager, capture, replay
+        for rnd in range(rounds):
             tickets = []
             for ps in reqs:
                 st = F.default_strategy(ps.d, ps.eps, "Q4P2")
@@ -89,9 +94,9 @@ def test_server_mix_equals_alone_host_inputs(ctx, reqs):
         c = srv.counters()
         log("counters", c, srv.stats())
         assert c["captured"] >= 1 and c["replayed"] >= 1
-        assert c["eager"] + c["captured"] + c["replayed"] == 3 * len(reqs)
+        assert c["eager"] + c["captured"] + c["replayed"] == rounds * len(reqs)
         s = srv.stats()
-        assert s["completed"] == 3 * len(reqs) and s["p99_s"] >= s["p50_s"] > 0
+        assert s["completed"] == rounds * len(reqs) and s["p99_s"] >= s["p50_s"] > 0
     finally:
         srv.close()
 
