@@ -191,6 +191,24 @@ constexpr uint32_t kNoKey = 0xffffffffu;
 size_t bucket_positions_bytes(int64_t N, int64_t nbins);
 // True when the sort's launches may be captured into a graph and replayed.
 bool bucket_positions_graph_safe(int64_t N, int64_t nbins);
+
+// The LDS counting sort in pieces, for callers that compute their keys in
+// their own counting kernel: slots are counted in G chunks of `chunk` slots (a
+// multiple of `unit`); the caller's kernel writes table[bin * G + chunk], each
+// slot's rank inside (bin, chunk) and its key; count_scan turns the table into
+// offsets and start[]; count_positions gives each slot its position.
+// Only for lds == true (nbins <= 2^15).
+struct CountPlan {
+  bool lds;
+  int G;
+  int64_t chunk;
+  size_t off_table, off_offs, off_rank, off_tmp, tmp_bytes, bytes;  // in the scratch area
+};
+CountPlan count_plan(int64_t N, int64_t nbins, int unit);
+void count_scan(const CountPlan &c, int64_t nbins, char *scratch, int64_t *start, hipStream_t s);
+// pos[i] = offs[keys[i] * G + i / chunk] + rank[i] (kNoKey for kNoKey slots)
+void count_positions(const CountPlan &c, const uint32_t *keys, int64_t N, char *scratch, uint32_t *pos,
+                     hipStream_t s);
 void bucket_positions(const uint32_t *keys, int64_t N, int64_t nbins, uint32_t *pos, int64_t *start,
                       void *scratch, hipStream_t s);
 

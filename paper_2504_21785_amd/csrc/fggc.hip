@@ -248,10 +248,11 @@ struct KeyParams {
   int ns;  // key slots per packet: 2^d with halo slots, 1 for the own tile only
 };
 
+// The key slots of packet j (kNoKey for unused halo slots).  The rank kernel,
+// the key kernel and the coefficient kernel all call this, so their keys agree
+// bit for bit.
 template <int D>
-__global__ void fggc_key_kernel(KeyParams p, uint32_t *__restrict__ key) {
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= p.N) return;
+__device__ __forceinline__ void packet_keys(const KeyParams &p, int64_t j, uint32_t *key) {
   int64_t pcf = 0, nqt = 1, ta[3], tb[3];
   for (int k = 0; k < D; ++k) {
     int64_t iq, ip;
@@ -276,7 +277,7 @@ __global__ void fggc_key_kernel(KeyParams p, uint32_t *__restrict__ key) {
   if (p.ns == 1) {
     int64_t tf = 0;
     for (int k = 0; k < D; ++k) tf = tf * p.ntq[k] + ta[k];
-    key[j] = (uint32_t)(pcf * nqt + tf);
+    key[0] = (uint32_t)(pcf * nqt + tf);
     return;
   }
   constexpr int NS = 1 << D;
@@ -289,8 +290,43 @@ __global__ void fggc_key_kernel(KeyParams p, uint32_t *__restrict__ key) {
       if (bit && tb[k] == ta[k]) ok = false;
       tf = tf * p.ntq[k] + (bit ? tb[k] : ta[k]);
     }
-    key[j * NS + m] = ok ? (uint32_t)(pcf * nqt + tf) : kNoKey;
+    key[m] = ok ? (uint32_t)(pcf * nqt + tf) : kNoKey;
   }
+}
+
+template <int D>
+__global__ void fggc_key_kernel(KeyParams p, uint32_t *__restrict__ key) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= p.N) return;
+  uint32_t k[1 << D];
+  packet_keys<D>(p, j, k);
+  for (int m = 0; m < p.ns; ++m) key[j * p.ns + m] = k[m];
+}
+
+// Counting pass of the LDS counting sort with the keys computed in place:
+// workgroup g counts the key slots of its chunk of packets in LDS, keeping
+// each slot's returned count as its rank inside (key, chunk), writes the
+// counts bin-major into table[bin * G + g] and the keys for the position pass.
+template <int D>
+__global__ __launch_bounds__(1024) void fggc_rank_kernel(KeyParams p, int64_t chunk, int64_t nbins, int G,
+                                                         uint32_t *__restrict__ table,
+                                                         uint32_t *__restrict__ rank,
+                                                         uint32_t *__restrict__ keys) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  uint32_t *cnt = reinterpret_cast<uint32_t *>(smem_raw);
+  for (int64_t b = threadIdx.x; b < nbins; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  const int64_t j0 = blockIdx.x * chunk / p.ns, j1 = min(p.N, (blockIdx.x + 1) * chunk / p.ns);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    uint32_t k[1 << D];
+    packet_keys<D>(p, j, k);
+    for (int m = 0; m < p.ns; ++m) {
+      keys[j * p.ns + m] = k[m];
+      if (k[m] != kNoKey) rank[j * p.ns + m] = atomicAdd(&cnt[k[m]], 1u);
+    }
+  }
+  __syncthreads();
+  for (int64_t b = threadIdx.x; b < nbins; b += blockDim.x) table[b * G + blockIdx.x] = cnt[b];
 }
 
 // Record of one packet (one per key slot, in bin order): its q index and p-cell (relative) per
@@ -1107,27 +1143,35 @@ struct BandParams {
   int64_t koff[3];  // offset of each dimension's kstart table (entries)
 };
 
+// First frequency of slice l's band, and gamma at frequency k = k0 + i
+// (0 outside the truncated band); used by the table kernel and inline.
+__device__ __forceinline__ int64_t band_start(double p, double eps, double cK) {
+  return (int64_t)ceil(p / eps - cK / sqrt(eps));
+}
+__device__ __forceinline__ double band_gamma(double p, int64_t k, double eps, double cK) {
+  const double cst = sqrt(kTwoPi * eps) / kTwoPi;
+  const double dk = eps * (double)k - p;  // eps (k - p/eps)
+  const double ex = -dk * dk / (2.0 * eps);
+  return (ex >= -0.5 * cK * cK * (1.0 + 1e-12)) ? cst * exp(ex) : 0.0;
+}
+
 template <typename R>
 __global__ void band_table_kernel(BandParams b, R *__restrict__ gam, int64_t *__restrict__ kst) {
   const int k = blockIdx.y;
   if (k >= b.d) return;
   const int64_t total = b.sn[k] * b.nb[k];
-  const double se = sqrt(b.eps);
-  const double cst = sqrt(kTwoPi * b.eps) / kTwoPi;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t l = e / b.nb[k], i = e - l * b.nb[k];
     const double p = (double)(b.slo[k] + l) * b.dp[k];
-    const int64_t k0 = (int64_t)ceil(p / b.eps - b.cK / se);
-    const double dk = b.eps * (double)(k0 + i) - p;  // eps (k - p/eps)
-    const double ex = -dk * dk / (2.0 * b.eps);
-    const double v = (ex >= -0.5 * b.cK * b.cK * (1.0 + 1e-12)) ? cst * exp(ex) : 0.0;
-    gam[b.toff[k] + e] = (R)v;
+    const int64_t k0 = band_start(p, b.eps, b.cK);
+    gam[b.toff[k] + e] = (R)band_gamma(p, k0 + i, b.eps, b.cK);
     if (i == 0) kst[b.koff[k] + l] = k0;
   }
 }
 
 struct MacParams {
+  double dp[3];
   int64_t M[3], Nq[3], sn[3], nb[3], toff[3], koff[3];
   int64_t kmin[3], kmax[3];  // union of the bands per dimension
   double lo_c[3], inv_dp[3], eps, cK;  // l range helpers
@@ -1255,9 +1299,11 @@ __global__ __launch_bounds__(256) void band_mac1_kernel(MacParams m, const T *__
       if (lb > m.sn[0] - 1) lb = m.sn[0] - 1;
       const int64_t q0 = ((k0 % m.Nq[0]) + m.Nq[0]) % m.Nq[0];
       for (int64_t l0 = la + g; l0 <= lb; l0 += 8) {
-        const int64_t i0 = k0 - kst[m.koff[0] + l0];
+        // gamma evaluated in place, exactly as the band table would hold it
+        const double p = (double)(m.slo[0] + l0) * m.dp[0];
+        const int64_t i0 = k0 - band_start(p, m.eps, m.cK);
         if (i0 < 0 || i0 >= m.nb[0]) continue;
-        const double g0 = (double)gam[m.toff[0] + l0 * m.nb[0] + i0];
+        const double g0 = (double)(R)band_gamma(p, k0, m.eps, m.cK);
         const T f = F[l0 * m.Nq[0] + q0];
         accr = fma(g0, (double)f.x, accr);
         acci = fma(g0, (double)f.y, acci);
@@ -1454,7 +1500,7 @@ FggcLayout fggc_layout(const FggcArgs &a) {
   L.off_lsq = put(3 * sizeof(DimLsq));
   L.off_keys = put(NS * 4);
   L.off_pos = put(NS * 4);
-  L.off_sort = put(bucket_positions_bytes(L.nslots, L.nbins));
+  L.off_sort = put(std::max(bucket_positions_bytes(L.nslots, L.nbins), count_plan(L.nslots, L.nbins, L.ns).bytes));
   L.off_start = put((size_t)(L.nbins + 1) * 8);
   L.off_recs = put((size_t)NS * L.rec_b);  // at most one record per slot
   L.off_agg = put(L.agg1 ? (size_t)L.npc[0] * a.Nq[0] * L.N1 * es : 0);
@@ -1600,6 +1646,9 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
   FGGC_HIP(hipGetLastError());
 }
 
+bool g_rank_attr = false;
+std::mutex g_rank_mu;
+
 // bin the packets' key slots, compute their coefficients into bin order, and fill
 // the cell array of eq. (2.25) (every cell written once)
 void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells, hipStream_t s) {
@@ -1615,32 +1664,61 @@ void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells
   uint32_t *keys = (uint32_t *)(base + L.off_keys), *pos = (uint32_t *)(base + L.off_pos);
   int64_t *start = (int64_t *)(base + L.off_start);
   char *recs = base + L.off_recs;
+  KeyParams kp{};
+  kp.N = N;
+  kp.Q = a.pk->Q;
+  kp.P = a.pk->P;
+  for (int k = 0; k < 3; ++k) {
+    kp.Nq[k] = a.Nq[k];
+    kp.pmin[k] = L.pmin[k];
+    kp.npc[k] = L.npc[k];
+    kp.tile[k] = L.tile[k];
+    kp.ntq[k] = L.ntq[k];
+    kp.dq[k] = kTwoPi / (double)a.Nq[k];
+    kp.dp[k] = a.dp[k];
+  }
+  kp.mindq = L.mindq;
+  kp.maxdq = L.maxdq;
+  kp.ns = L.ns;
+  const CountPlan cpn = count_plan(L.nslots, L.nbins, L.ns);
+  uint32_t *rank = (uint32_t *)(base + L.off_sort + cpn.off_rank);
+  {
+    std::lock_guard<std::mutex> lk(g_rank_mu);
+    if (!g_rank_attr) {
+      FGGC_HIP(hipFuncSetAttribute((const void *)fggc_rank_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+      FGGC_HIP(hipFuncSetAttribute((const void *)fggc_rank_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+      FGGC_HIP(hipFuncSetAttribute((const void *)fggc_rank_kernel<3>, hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+      g_rank_attr = true;
+    }
+  }
   {
     StageScope sc(a.prof, "fggc_sort", s);
-    if (N > 0) {
-      KeyParams kp{};
-      kp.N = N;
-      kp.Q = a.pk->Q;
-      kp.P = a.pk->P;
-      for (int k = 0; k < 3; ++k) {
-        kp.Nq[k] = a.Nq[k];
-        kp.pmin[k] = L.pmin[k];
-        kp.npc[k] = L.npc[k];
-        kp.tile[k] = L.tile[k];
-        kp.ntq[k] = L.ntq[k];
-        kp.dq[k] = kTwoPi / (double)a.Nq[k];
-        kp.dp[k] = a.dp[k];
+    if (cpn.lds) {
+      // keys computed in place: ranks here, positions in the coefficient kernel
+      char *sc_base = base + L.off_sort;
+      uint32_t *table = (uint32_t *)(sc_base + cpn.off_table);
+      if (N > 0) {
+        const dim3 g((unsigned)cpn.G), b(1024);
+        const size_t shm = (size_t)L.nbins * 4;
+        if (d == 1) fggc_rank_kernel<1><<<g, b, shm, s>>>(kp, cpn.chunk, L.nbins, cpn.G, table, rank, keys);
+        else if (d == 2) fggc_rank_kernel<2><<<g, b, shm, s>>>(kp, cpn.chunk, L.nbins, cpn.G, table, rank, keys);
+        else fggc_rank_kernel<3><<<g, b, shm, s>>>(kp, cpn.chunk, L.nbins, cpn.G, table, rank, keys);
+        FGGC_HIP(hipGetLastError());
+      } else {
+        launch_zero(table, (size_t)L.nbins * cpn.G * 4, s);
       }
-      kp.mindq = L.mindq;
-      kp.maxdq = L.maxdq;
-      kp.ns = L.ns;
+      count_scan(cpn, L.nbins, sc_base, start, s);
+      if (N > 0) count_positions(cpn, keys, L.nslots, sc_base, pos, s);
+    } else if (N > 0) {
       const dim3 g((unsigned)((N + 255) / 256)), b(256);
       if (d == 1) fggc_key_kernel<1><<<g, b, 0, s>>>(kp, keys);
       else if (d == 2) fggc_key_kernel<2><<<g, b, 0, s>>>(kp, keys);
       else fggc_key_kernel<3><<<g, b, 0, s>>>(kp, keys);
       FGGC_HIP(hipGetLastError());
+      bucket_positions(keys, L.nslots, L.nbins, pos, start, base + L.off_sort, s);
+    } else {
+      bucket_positions(keys, L.nslots, L.nbins, pos, start, base + L.off_sort, s);
     }
-    bucket_positions(keys, L.nslots, L.nbins, pos, start, base + L.off_sort, s);
   }
   CoefParams cp{};
   cp.ns = L.ns;
@@ -1765,7 +1843,7 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, 
     bp.toff[k] = L.toff[k];
     bp.koff[k] = L.koff[k];
   }
-  {
+  if (d >= 2) {  // one dimension evaluates gamma in place
     StageScope sc(a.prof, "fggc_band_table", s);
     band_table_kernel<R><<<dim3(64, (unsigned)d), dim3(256), 0, s>>>(bp, gam, kst);
     FGGC_HIP(hipGetLastError());
@@ -1781,6 +1859,7 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, 
     m.toff[k] = L.toff[k];
     m.koff[k] = L.koff[k];
     m.slo[k] = a.slo[k];
+    m.dp[k] = a.dp[k];
     m.inv_dp[k] = 1.0 / a.dp[k];
     if (k < d) {
       m.kmin[k] = (int64_t)std::floor((double)a.slo[k] * a.dp[k] / a.eps - a.cK / se) - 1;

@@ -179,7 +179,7 @@ struct SortPlan {
   size_t off_table, off_offs, off_rank, off_tmp, tmp_bytes, off_k1, off_k2, off_v1, off_v2, total;
 };
 
-SortPlan sort_plan(int64_t N, int64_t nbins) {
+SortPlan sort_plan(int64_t N, int64_t nbins, int unit = 1) {
   SortPlan sp{};
   const int64_t Nn = std::max<int64_t>(N, 1);
   sp.lds = nbins <= kMaxLdsBins;
@@ -194,6 +194,7 @@ SortPlan sort_plan(int64_t N, int64_t nbins) {
     int64_t G = std::min<int64_t>(1024, (Nn + 8191) / 8192);
     G = std::max<int64_t>(1, std::min<int64_t>(G, ((int64_t)1 << 22) / std::max<int64_t>(nbins, 1)));
     sp.chunk = (Nn + G - 1) / G;
+    sp.chunk = (sp.chunk + unit - 1) / unit * unit;  // whole packets per chunk
     sp.G = (int)((Nn + sp.chunk - 1) / sp.chunk);
     const int64_t tn = nbins * sp.G;
     size_t tmp = 0;
@@ -240,6 +241,37 @@ std::mutex g_sort_mu;
 }  // namespace
 
 size_t bucket_positions_bytes(int64_t N, int64_t nbins) { return sort_plan(N, nbins).total + 256; }
+
+CountPlan count_plan(int64_t N, int64_t nbins, int unit) {
+  const SortPlan sp = sort_plan(N, nbins, unit);
+  CountPlan c{};
+  c.lds = sp.lds;
+  c.G = sp.G;
+  c.chunk = sp.chunk;
+  c.off_table = sp.off_table;
+  c.off_offs = sp.off_offs;
+  c.off_rank = sp.off_rank;
+  c.off_tmp = sp.off_tmp;
+  c.tmp_bytes = sp.tmp_bytes;
+  c.bytes = sp.total + 256;
+  return c;
+}
+
+void count_positions(const CountPlan &c, const uint32_t *keys, int64_t N, char *scratch, uint32_t *pos,
+                     hipStream_t s) {
+  const uint32_t *rank = (const uint32_t *)(scratch + c.off_rank), *offs = (const uint32_t *)(scratch + c.off_offs);
+  bucket_pos_kernel<<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s>>>(keys, rank, N, c.chunk, c.G, offs, pos);
+  FGGC_HIP(hipGetLastError());
+}
+
+void count_scan(const CountPlan &c, int64_t nbins, char *scratch, int64_t *start, hipStream_t s) {
+  uint32_t *table = (uint32_t *)(scratch + c.off_table), *offs = (uint32_t *)(scratch + c.off_offs);
+  size_t tmp = c.tmp_bytes;
+  FGGC_HIP(hipcub::DeviceScan::ExclusiveSum(scratch + c.off_tmp, tmp, table, offs, (int)(nbins * c.G), s));
+  bucket_start_kernel<<<dim3((unsigned)((nbins + 1 + 255) / 256)), dim3(256), 0, s>>>(offs, table, nbins,
+                                                                                    c.G, start);
+  FGGC_HIP(hipGetLastError());
+}
 
 // The radix path runs the library's onesweep sort, which resets its lookback
 // states and histogram with memsets and its ordered block counter from the
