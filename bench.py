@@ -242,7 +242,7 @@ def main():
     torch.cuda.synchronize()
     log("profiled pass done")
     stage_names = ["prepass", "fggc_sort", "fggc_coef", "fggc_accum", "fggc_fft_q",
-                   "fggc_band_table", "fggc_band_mac", "fggc_contract", "fggc_ifft", "ds_prep",
+                   "fggc_band_mac", "fggc_contract", "fggc_ifft", "ds_prep",
                    "ds_sort", "ds_kernel", "ds_reduce"]
     stages = {}
     for sn in stage_names:
@@ -286,7 +286,6 @@ def main():
         # separable finish (d >= 2): read the cell array, write the grid spectrum
         "fggc_contract": ("hbm", (cells_b + mpts * 8) / 1e9, "GB/s", HBM_PEAK_GBS),
         "fggc_ifft": ("hbm", 2 * mpts * 8 / 1e9, "GB/s", HBM_PEAK_GBS),
-        "fggc_band_table": ("hbm", 0.0, "GB/s", HBM_PEAK_GBS),
     }
     bound, amount, unit, peak = per_launch.get(dom, ("hbm", 0.0, "GB/s", HBM_PEAK_GBS))
     dom_ms = stages[dom]["avg_ms"]

@@ -110,13 +110,26 @@ constexpr int kMaxN1 = 16;  // largest one-dimensional basis (nq * np)
 
 // Eigenpairs of the eps-free Gram matrix (3.22) of one dimension, with the
 // reciprocal eigenvalues already cut: A~^+ = V diag(inv) V^H.
+// Column of counting chunk g in the bin-major count table [bin][column]:
+// workgroups are dealt to the eight XCDs in turn, so mapping the chunks of one
+// XCD to adjacent columns keeps each cache line of the table written from one
+// L2.  Any bijection is correct: it only orders the chunks inside a bin.
+__host__ __device__ inline int64_t chunk_column(int64_t g, int G) {
+  return (G & 7) ? g : (g & 7) * (G >> 3) + (g >> 3);
+}
+
 struct alignas(16) DimLsq {
   int n1;
+  int dq0, dp0;  // smallest q and p shifts
   int dq[kMaxN1], dp[kMaxN1];
   double Cq, Cp;
+  double inv[kMaxN1];    // 1/lambda or 0 when cut
+  double D[2 * kMaxN1];  // exp(-i Cq Cp dq_k dp_k / 2), the constant phase of (3.23)
+  // D_k exp(-(Cq^2 (dq_k - dq0)^2 + Cp^2 (dp_k - dp0)^2) / 4): the constant
+  // part of the right-hand side once the Gaussian factor is split about the
+  // smallest shifts
+  double DK[2 * kMaxN1];
   double V[2 * kMaxN1 * kMaxN1];  // [row][col] complex, columns are eigenvectors
-  double inv[kMaxN1];             // 1/lambda or 0 when cut
-  double D[2 * kMaxN1];           // exp(-i Cq Cp dq_k dp_k / 2), the constant phase of (3.23)
 };
 
 // Hermitian eigen-decomposition of a complex n x n matrix (cyclic Jacobi on
@@ -194,21 +207,22 @@ bool bucket_positions_graph_safe(int64_t N, int64_t nbins);
 
 // The LDS counting sort in pieces, for callers that compute their keys in
 // their own counting kernel: slots are counted in G chunks of `chunk` slots (a
-// multiple of `unit`); the caller's kernel writes table[bin * G + chunk], each
+// multiple of `unit`); the caller's kernel writes table[bin * G + chunk_column(chunk)], each
 // slot's rank inside (bin, chunk) and its key; count_scan turns the table into
-// offsets and start[]; count_positions gives each slot its position.
+// offsets inside each bin and start[]; count_positions gives each slot its position.
 // Only for lds == true (nbins <= 2^15).
 struct CountPlan {
   bool lds;
   int G;
   int64_t chunk;
-  size_t off_table, off_offs, off_rank, off_tmp, tmp_bytes, bytes;  // in the scratch area
+  size_t off_table, off_offs, off_rank, off_rowsum, bytes;  // in the scratch area
 };
 CountPlan count_plan(int64_t N, int64_t nbins, int unit);
 void count_scan(const CountPlan &c, int64_t nbins, char *scratch, int64_t *start, hipStream_t s);
-// pos[i] = offs[keys[i] * G + i / chunk] + rank[i] (kNoKey for kNoKey slots)
-void count_positions(const CountPlan &c, const uint32_t *keys, int64_t N, char *scratch, uint32_t *pos,
-                     hipStream_t s);
+// pos[i] = start[keys[i]] + offs[keys[i] * G + chunk_column(i / chunk)] + rank[i]
+// (kNoKey for kNoKey slots)
+void count_positions(const CountPlan &c, const uint32_t *keys, int64_t N, char *scratch, const int64_t *start,
+                     uint32_t *pos, hipStream_t s);
 void bucket_positions(const uint32_t *keys, int64_t N, int64_t nbins, uint32_t *pos, int64_t *start,
                       void *scratch, hipStream_t s);
 

@@ -130,7 +130,10 @@ struct DsParams {
   double *partial;         // [nchunk][prod box_n] complex FP64
 };
 
-template <int D, bool F64>
+// WRAP: grids too small for a wave's span, where every lane takes its own
+// minimum image (a separate instantiation keeps that path's registers out of
+// the common one)
+template <int D, bool F64, bool WRAP>
 __global__ __launch_bounds__(kBlock) void ds_kernel(DsParams p) {
   using Sh = Shape<D>;
   const int lane = threadIdx.x & 63;
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void ds_kernel(DsParams p) {
         bool vis = true;
         for (int k = 0; k < D; ++k) {
           int kv = (int)(worg[k] - r.mq[k]);  // in (-n, n + span)
-          if (p.lanewrap) {
+          if constexpr (WRAP) {
             while (kv >= nn[k] - hh[k]) kv -= nn[k];
             while (kv < -hh[k]) kv += nn[k];
           } else {
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void ds_kernel(DsParams p) {
           const int span = Sh::L[k] * Sh::S[k];
           vis = vis && (unsigned)(kv + span - 1 + Wi[k]) < (unsigned)(2 * Wi[k] + span);
         }
-        if (p.lanewrap) {
+        if constexpr (WRAP) {
           // small grids: a wave span can wrap around the torus and come back
           // inside the window, so every lane takes its own minimum image
           for (int s = 0; s < 4; ++s) {
@@ -538,8 +541,10 @@ void launch_direct(const DirectArgs &a, Workspace &ws, hipStream_t s) {
     {
     StageScope sc(a.prof, "ds_kernel", s);
 #define FGGC_DS(DD)                                                                    \
-  if (f64) ds_kernel<DD, true><<<grid, dim3(kBlock), 0, s>>>(p);                      \
-  else ds_kernel<DD, false><<<grid, dim3(kBlock), 0, s>>>(p);
+  if (f64 && p.lanewrap) ds_kernel<DD, true, true><<<grid, dim3(kBlock), 0, s>>>(p);  \
+  else if (f64) ds_kernel<DD, true, false><<<grid, dim3(kBlock), 0, s>>>(p);         \
+  else if (p.lanewrap) ds_kernel<DD, false, true><<<grid, dim3(kBlock), 0, s>>>(p);  \
+  else ds_kernel<DD, false, false><<<grid, dim3(kBlock), 0, s>>>(p);
     if (L.D == 1) { FGGC_DS(1) }
     else if (L.D == 2) { FGGC_DS(2) }
     else { FGGC_DS(3) }

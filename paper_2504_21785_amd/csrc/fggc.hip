@@ -152,85 +152,154 @@ __device__ __forceinline__ void dim_coeffs(const DimLsq &L, double Q, double P, 
   }
 }
 
-// The same with the shift-set sizes fixed (basis j = a NP + b): the Gaussian
-// factor splits as gq_a gp_b, and the powers Es^dp_b, Et^dq_a, Fi^dq_a are
-// formed once per shift instead of once per basis function.
-template <int NQ, int NP>
-__device__ __forceinline__ void dim_coeffs_exact(const DimLsq &L, double Q, double P, double dq, double dp,
-                                                 int64_t &iq, int64_t &ip, double *cre, double *cim) {
+// The same with the shift-set sizes fixed (basis j = a NP + b), up to a factor
+// that every basis function of the packet shares.  With CC = Cq Cp, the
+// smallest shifts dq0, dp0, x0 = dq0 - s, y0 = dp0 - t and the offsets
+// Eq_a = dq_a - dq0, Ep_b = dp_b - dp0 (whole numbers >= 0), the Gaussian
+// factor of (3.23) splits about (x0, y0) and the right-hand side becomes
+//   f~_ab = W uq^Eq_a up^Ep_b DK_ab,
+//   uq = exp(-Cq^2 x0 / 2) exp(-i CC t / 2),  up = exp(-Cp^2 y0 / 2) exp(i CC s / 2),
+//   DK_ab = D_ab exp(-(Cq^2 Eq_a^2 + Cp^2 Ep_b^2) / 4)   (a plan constant),
+//   W = exp(-(Cq^2 x0^2 + Cp^2 y0^2) / 4) exp(i CC (s t + s dp0 - t dq0) / 2),
+// and the shift of (3.13) is exp(-i CC (s - dq0) ip) Fi^Eq_a with Fi = exp(i CC ip).
+// The solve is linear and c~ = conj(c^), so W leaves it as conj(W); that and
+// exp(-i CC (s - dq0) ip) are gathered, over all dimensions, into the one
+// per-packet factor that common_factor() returns (log-magnitude and phase in
+// revolutions).  What is left is computed here:
+//   z = diag(inv) V^H g,  g_ab = uq^Eq_a up^Ep_b DK_ab;  c_ab = conj(V z)_ab Fi^Eq_a  (x alpha).
+__device__ __forceinline__ void common_factor(const DimLsq &L, double s, double t, int64_t ip, double &lg,
+                                              double &rev) {
+  const double Cq = L.Cq, Cp = L.Cp, CC = Cq * Cp;
+  const double x0 = (double)L.dq0 - s, y0 = (double)L.dp0 - t;
+  lg -= 0.25 * (Cq * Cq * x0 * x0 + Cp * Cp * y0 * y0);
+  rev -= CC * (0.5 * (s * t + s * (double)L.dp0 - t * (double)L.dq0) - x0 * (double)ip) * (1.0 / kTwoPi);
+}
+
+// A compiler fence between rows of a matrix product: loads are neither
+// merged nor moved across it, and the running sums passed in are complete
+// before it, so each row's loads and arithmetic stay together.
+template <int N>
+__device__ __forceinline__ void row_fence(double (&xr)[N], double (&xi)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) asm volatile("" : "+v"(xr[i]), "+v"(xi[i]));
+  asm volatile("" ::: "memory");
+}
+__device__ __forceinline__ void row_fence(double &xr, double &xi) {
+  asm volatile("" : "+v"(xr), "+v"(xi)::"memory");
+}
+
+// z^n for a small whole n >= 0 (uniform across the wave)
+__device__ __forceinline__ void cpow(double zr, double zi, int n, double &pr, double &pi) {
+  double xr = 1.0, xi = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double t = xr * zr - xi * zi;
+    xi = xr * zi + xi * zr;
+    xr = t;
+  }
+  pr = xr;
+  pi = xi;
+}
+
+template <int NQ, int NP, typename T>
+__device__ __forceinline__ void dim_coeffs_exact(const DimLsq &L, double s, double t, int64_t ip, bool first,
+                                                 double alr, double ali, T *cv) {
+  using R = decltype(T{}.x);
   constexpr int N1 = NQ * NP;
-  double s, t;
-  int_frac(Q / dq, iq, s);
-  int_frac(P / dp, ip, t);
   const double Cq = L.Cq, Cp = L.Cp, CC = Cq * Cp;
   constexpr double inv2pi = 1.0 / kTwoPi;
-  double e0c, e0s, esc, ess, etc_, ets, f0c, f0s, fic, fis;
-  cis_rev(0.5 * CC * s * t * inv2pi, e0c, e0s);
-  cis_rev(0.5 * CC * s * inv2pi, esc, ess);
-  cis_rev(-0.5 * CC * t * inv2pi, etc_, ets);
+  double uqr, uqi, upr, upi, fir, fii;
   {
-    const double w = CC * inv2pi * (double)ip;  // CC ip in revolutions
-    cis_rev(w, fic, fis);
-    cis_rev(-s * w, f0c, f0s);
+    double c, sn;
+    cis_rev(-0.5 * CC * t * inv2pi, c, sn);
+    const double m = exp(-0.5 * Cq * Cq * ((double)L.dq0 - s));
+    uqr = m * c;
+    uqi = m * sn;
+    cis_rev(0.5 * CC * s * inv2pi, c, sn);
+    const double mp = exp(-0.5 * Cp * Cp * ((double)L.dp0 - t));
+    upr = mp * c;
+    upi = mp * sn;
+    cis_rev(CC * inv2pi * (double)ip, fir, fii);
   }
-  double gq[NQ], qr[NQ], qi[NQ], hr[NQ], hi[NQ];
+  double ppr[NP], ppi[NP];
+#pragma unroll
+  for (int b = 0; b < NP; ++b) cpow(upr, upi, L.dp[b] - L.dp0, ppr[b], ppi[b]);
+  // z = diag(inv) V^H g, accumulated one basis function at a time (g_j is
+  // never stored); uq^Eq_a is kept as a running power over a
+  double zr[N1], zi[N1];
+#pragma unroll
+  for (int i = 0; i < N1; ++i) zr[i] = zi[i] = 0.0;
+  double pqr = 1.0, pqi = 0.0;
+  int ea = 0;
 #pragma unroll
   for (int a = 0; a < NQ; ++a) {
-    const int dqa = L.dq[a * NP];
-    const double x = (double)dqa - s;
-    gq[a] = exp(-0.25 * Cq * Cq * x * x);
-    cis_pow(etc_, ets, dqa, qr[a], qi[a]);
-    cis_pow(fic, fis, dqa, hr[a], hi[a]);
-  }
-  double gp[NP], pr[NP], pi[NP];
-#pragma unroll
-  for (int b = 0; b < NP; ++b) {
-    const int dpb = L.dp[b];
-    const double x = (double)dpb - t;
-    gp[b] = exp(-0.25 * Cp * Cp * x * x);
-    cis_pow(esc, ess, dpb, pr[b], pi[b]);
-  }
-  double fre[N1], fim[N1];
-#pragma unroll
-  for (int a = 0; a < NQ; ++a)
+    {
+      double xr, xi;
+      const int e = L.dq[a * NP] - L.dq0;
+      cpow(uqr, uqi, e - ea, xr, xi);
+      const double nr = pqr * xr - pqi * xi;
+      pqi = pqr * xi + pqi * xr;
+      pqr = nr;
+      ea = e;
+    }
 #pragma unroll
     for (int b = 0; b < NP; ++b) {
       const int j = a * NP + b;
-      // E0 * Es^dp * Et^dq * D, times gq gp
-      double xr = e0c * pr[b] - e0s * pi[b], xi = e0c * pi[b] + e0s * pr[b];
-      const double yr = xr * qr[a] - xi * qi[a], yi = xr * qi[a] + xi * qr[a];
-      const double dr = L.D[2 * j], di = L.D[2 * j + 1];
-      const double mag = gq[a] * gp[b];
-      fre[j] = mag * (yr * dr - yi * di);
-      fim[j] = mag * (yr * di + yi * dr);
-    }
-  double zre[N1], zim[N1];
+      const double hr = pqr * ppr[b] - pqi * ppi[b], hi = pqr * ppi[b] + pqi * ppr[b];
+      const double kr = L.DK[2 * j], ki = L.DK[2 * j + 1];
+      const double gr = hr * kr - hi * ki, gi = hr * ki + hi * kr;
+      // one row of V at a time: the compiler would otherwise load all of V
+      // at once (and keep it for the second product), at a cost in occupancy
+      row_fence(zr, zi);
 #pragma unroll
-  for (int i = 0; i < N1; ++i) {
-    double yr = 0.0, yi = 0.0;
-#pragma unroll
-    for (int j = 0; j < N1; ++j) {
-      const double vr = L.V[2 * (j * N1 + i)], vi = L.V[2 * (j * N1 + i) + 1];
-      yr = fma(vr, fre[j], fma(vi, fim[j], yr));
-      yi = fma(vr, fim[j], fma(-vi, fre[j], yi));
+      for (int i = 0; i < N1; ++i) {
+        const double vr = L.V[2 * (j * N1 + i)], vi = L.V[2 * (j * N1 + i) + 1];
+        // conj(V_ji) g_j
+        zr[i] = fma(vr, gr, fma(vi, gi, zr[i]));
+        zi[i] = fma(vr, gi, fma(-vi, gr, zi[i]));
+      }
     }
-    zre[i] = yr * L.inv[i];
-    zim[i] = yi * L.inv[i];
   }
 #pragma unroll
-  for (int j = 0; j < N1; ++j) {
-    double gr = 0.0, gi = 0.0;
+  for (int i = 0; i < N1; ++i) {
+    zr[i] *= L.inv[i];
+    zi[i] *= L.inv[i];
+  }
+  // c = conj(V z) Fi^Eq_a, Fi^Eq_a again as a running power over a
+  pqr = 1.0;
+  pqi = 0.0;
+  ea = 0;
 #pragma unroll
-    for (int i = 0; i < N1; ++i) {
-      const double vr = L.V[2 * (j * N1 + i)], vi = L.V[2 * (j * N1 + i) + 1];
-      gr = fma(vr, zre[i], fma(-vi, zim[i], gr));
-      gi = fma(vr, zim[i], fma(vi, zre[i], gi));
+  for (int a = 0; a < NQ; ++a) {
+    {
+      double xr, xi;
+      const int e = L.dq[a * NP] - L.dq0;
+      cpow(fir, fii, e - ea, xr, xi);
+      const double nr = pqr * xr - pqi * xi;
+      pqi = pqr * xi + pqi * xr;
+      pqr = nr;
+      ea = e;
     }
-    const double tr = gr, ti = -gi;  // conjugate
-    const int a = j / NP;
-    const double cs = f0c * hr[a] - f0s * hi[a], sn = f0c * hi[a] + f0s * hr[a];
-    cre[j] = tr * cs - ti * sn;
-    cim[j] = tr * sn + ti * cs;
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      const int j = a * NP + b;
+      double gr = 0.0, gi = 0.0;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) {
+        const double vr = L.V[2 * (j * N1 + i)], vi = L.V[2 * (j * N1 + i) + 1];
+        gr = fma(vr, zr[i], fma(-vi, zi[i], gr));
+        gi = fma(vr, zi[i], fma(vi, zr[i], gi));
+        if (N1 > 4 && i == N1 / 2 - 1) row_fence(gr, gi);  // half a row of V in flight
+      }
+      row_fence(gr, gi);
+      // conj(g) Fi^Eq_a
+      double xr = gr * pqr + gi * pqi, xi = gr * pqi - gi * pqr;
+      if (first) {
+        const double nr = alr * xr - ali * xi;
+        xi = alr * xi + ali * xr;
+        xr = nr;
+      }
+      cv[j] = T{(R)xr, (R)xi};
+    }
   }
 }
 
@@ -306,7 +375,8 @@ __global__ void fggc_key_kernel(KeyParams p, uint32_t *__restrict__ key) {
 // Counting pass of the LDS counting sort with the keys computed in place:
 // workgroup g counts the key slots of its chunk of packets in LDS, keeping
 // each slot's returned count as its rank inside (key, chunk), writes the
-// counts bin-major into table[bin * G + g] and the keys for the position pass.
+// counts bin-major into table[bin * G + chunk_column(g)] and the keys for the
+// position pass.
 template <int D>
 __global__ __launch_bounds__(1024) void fggc_rank_kernel(KeyParams p, int64_t chunk, int64_t nbins, int G,
                                                          uint32_t *__restrict__ table,
@@ -317,16 +387,29 @@ __global__ __launch_bounds__(1024) void fggc_rank_kernel(KeyParams p, int64_t ch
   for (int64_t b = threadIdx.x; b < nbins; b += blockDim.x) cnt[b] = 0;
   __syncthreads();
   const int64_t j0 = blockIdx.x * chunk / p.ns, j1 = min(p.N, (blockIdx.x + 1) * chunk / p.ns);
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
-    uint32_t k[1 << D];
-    packet_keys<D>(p, j, k);
-    for (int m = 0; m < p.ns; ++m) {
-      keys[j * p.ns + m] = k[m];
-      if (k[m] != kNoKey) rank[j * p.ns + m] = atomicAdd(&cnt[k[m]], 1u);
+  // U packets per thread and pass: their loads and key arithmetic are
+  // independent, so they overlap instead of forming one latency chain
+  constexpr int U = 4;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += U * (int64_t)blockDim.x) {
+    uint32_t k[U][1 << D];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t ju = j + u * (int64_t)blockDim.x;
+      if (ju < j1) packet_keys<D>(p, ju, k[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t ju = j + u * (int64_t)blockDim.x;
+      if (ju >= j1) break;
+      for (int m = 0; m < p.ns; ++m) {
+        keys[ju * p.ns + m] = k[u][m];
+        if (k[u][m] != kNoKey) rank[ju * p.ns + m] = atomicAdd(&cnt[k[u][m]], 1u);
+      }
     }
   }
   __syncthreads();
-  for (int64_t b = threadIdx.x; b < nbins; b += blockDim.x) table[b * G + blockIdx.x] = cnt[b];
+  const int64_t col = chunk_column(blockIdx.x, G);
+  for (int64_t b = threadIdx.x; b < nbins; b += blockDim.x) table[b * G + col] = cnt[b];
 }
 
 // Record of one packet (one per key slot, in bin order): its q index and p-cell (relative) per
@@ -343,7 +426,7 @@ struct CoefParams {
   int ns;  // key slots per packet
   int64_t N;
   const double *Q, *P, *S, *a;
-  double eps, scale;
+  double inv_2pi_eps, scale;  // 1 / (2 pi eps): S in revolutions
   const DimLsq *lsq;  // [d], device copy of the plan
   int64_t Nq[3], pmin[3];
   double dq[3], dp[3];
@@ -352,78 +435,95 @@ struct CoefParams {
 // One thread per packet, in packet order (coalesced reads); the record is
 // written to the sorted position of each of the packet's key slots.
 template <int D, int N1, int NQ, int NP, typename T>
-__global__ __launch_bounds__(256) void fggc_coef_kernel(CoefParams p, const uint32_t *__restrict__ pos,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 1 && N1 <= 8 && NQ > 0 ? 4 : 1))) void fggc_coef_kernel(CoefParams p, const uint32_t *__restrict__ pos,
                                                         char *__restrict__ recs) {
   using R = decltype(T{}.x);
-  // one dimension: the plan is staged in LDS and read as broadcasts instead of
-  // held in scalar registers (which the eigenvector matrix overflows); with
-  // more dimensions the scalar path measured faster
-  __shared__ DimLsq sl[1];
-  if constexpr (D == 1) {
+  // the plan is staged in LDS and read as broadcasts, a row of V at a time,
+  // rather than through scalar registers (which V overflows)
+  __shared__ DimLsq sl[D];
+  {
     const uint4 *src = reinterpret_cast<const uint4 *>(p.lsq);
     uint4 *dst = reinterpret_cast<uint4 *>(sl);
-    for (int e = threadIdx.x; e < (int)(sizeof(DimLsq) / 16); e += blockDim.x) dst[e] = src[e];
+    for (int e = threadIdx.x; e < (int)(D * sizeof(DimLsq) / 16); e += blockDim.x) dst[e] = src[e];
     __syncthreads();
   }
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= p.N) return;
-  double cre[D][N1], cim[D][N1];
-  int64_t iq[D], ip[D];
+  constexpr int NS = 1 << D;
+  constexpr int RB = rec_bytes<D, N1, T>();
+  // the record of every key slot of the packet (kNoKey: none)
+  uint32_t at[NS];
 #pragma unroll
-  for (int k = 0; k < D; ++k) {
-    const double qv = p.Q[k * p.N + j], pv = p.P[k * p.N + j];
-    if constexpr (NQ > 0) {
-      if constexpr (D == 1)
-        dim_coeffs_exact<NQ, NP>(sl[0], qv, pv, p.dq[k], p.dp[k], iq[k], ip[k], cre[k], cim[k]);
-      else
-        dim_coeffs_exact<NQ, NP>(p.lsq[k], qv, pv, p.dq[k], p.dp[k], iq[k], ip[k], cre[k], cim[k]);
-    } else {
-      if constexpr (D == 1)
-        dim_coeffs<N1>(sl[0], qv, pv, p.dq[k], p.dp[k], iq[k], ip[k], cre[k], cim[k]);
-      else
-        dim_coeffs<N1>(p.lsq[k], qv, pv, p.dq[k], p.dp[k], iq[k], ip[k], cre[k], cim[k]);
+  for (int m = 0; m < NS; ++m) at[m] = m < p.ns ? pos[j * p.ns + m] : kNoKey;
+  auto put_coeffs = [&](int k, const T *cv) {
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+      if (at[m] == kNoKey) continue;
+      T *c = reinterpret_cast<T *>(recs + (int64_t)at[m] * RB + rec_idx_bytes<D>()) + k * N1;
+#pragma unroll
+      for (int n = 0; n < N1; ++n) c[n] = cv[n];
+    }
+  };
+  int64_t iq[D], ip[D];
+  if constexpr (NQ > 0) {
+    // every dimension's cell first: the per-packet factor spans them
+    double s[D], t[D];
+    double lg = 0.0, rev = p.S[j] * p.inv_2pi_eps;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      int_frac(p.Q[k * p.N + j] / p.dq[k], iq[k], s[k]);
+      int_frac(p.P[k * p.N + j] / p.dp[k], ip[k], t[k]);
+      common_factor(sl[k], s[k], t[k], ip[k], lg, rev);
+    }
+    double cs, sn;
+    cis_rev(rev, cs, sn);
+    const double m = p.scale * exp(lg);
+    const double ar = m * p.a[2 * j], ai = m * p.a[2 * j + 1];
+    const double alr = ar * cs - ai * sn, ali = ar * sn + ai * cs;
+    // each dimension's coefficients go out as soon as they are known, so
+    // that only one dimension's are held at a time
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T cv[N1];
+      dim_coeffs_exact<NQ, NP, T>(sl[k], s[k], t[k], ip[k], k == 0, alr, ali, cv);
+      put_coeffs(k, cv);
+    }
+  } else {
+    double cre[D][N1], cim[D][N1];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double qv = p.Q[k * p.N + j], pv = p.P[k * p.N + j];
+      dim_coeffs<N1>(sl[k], qv, pv, p.dq[k], p.dp[k], iq[k], ip[k], cre[k], cim[k]);
+    }
+    double sn, cs;
+    cis_rev(p.S[j] * p.inv_2pi_eps, cs, sn);
+    const double ar = p.scale * p.a[2 * j], ai = p.scale * p.a[2 * j + 1];
+    const double alr = ar * cs - ai * sn, ali = ar * sn + ai * cs;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      T cv[N1];
+#pragma unroll
+      for (int n = 0; n < N1; ++n) {
+        double xr = cre[k][n], xi = cim[k][n];
+        if (k == 0) {
+          const double nr = alr * xr - ali * xi;
+          xi = alr * xi + ali * xr;
+          xr = nr;
+        }
+        cv[n] = T{(R)xr, (R)xi};
+      }
+      put_coeffs(k, cv);
     }
   }
-  double sn, cs;
-  {
-    const double rev = p.S[j] / (kTwoPi * p.eps);
-    sincospi(2.0 * (rev - rint(rev)), &sn, &cs);
-  }
-  const double ar = p.scale * p.a[2 * j], ai = p.scale * p.a[2 * j + 1];
-  const double alr = ar * cs - ai * sn, ali = ar * sn + ai * cs;
   RecIdx<D> ri;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     ri.q[k] = (int32_t)((iq[k] + p.Nq[k] / 2) & (p.Nq[k] - 1));
     ri.pc[k] = (int32_t)(ip[k] - p.pmin[k]);
   }
-  T cv[D][N1];
 #pragma unroll
-  for (int k = 0; k < D; ++k)
-#pragma unroll
-    for (int m = 0; m < N1; ++m) {
-      double xr = cre[k][m], xi = cim[k][m];
-      if (k == 0) {
-        const double nr = alr * xr - ali * xi;
-        xi = alr * xi + ali * xr;
-        xr = nr;
-      }
-      cv[k][m] = T{(R)xr, (R)xi};
-    }
-  constexpr int NS = 1 << D;
-#pragma unroll
-  for (int m = 0; m < NS; ++m) {
-    if (m >= p.ns) break;
-    const uint32_t at = pos[j * p.ns + m];
-    if (at == kNoKey) continue;
-    char *r = recs + (int64_t)at * rec_bytes<D, N1, T>();
-    *reinterpret_cast<RecIdx<D> *>(r) = ri;
-    T *c = reinterpret_cast<T *>(r + rec_idx_bytes<D>());
-#pragma unroll
-    for (int k = 0; k < D; ++k)
-#pragma unroll
-      for (int n = 0; n < N1; ++n) c[k * N1 + n] = cv[k][n];
-  }
+  for (int m = 0; m < NS; ++m)
+    if (at[m] != kNoKey) *reinterpret_cast<RecIdx<D> *>(recs + (int64_t)at[m] * RB) = ri;
 }
 
 // Owner-computes accumulation of eq. (2.25): one workgroup per (window of
@@ -1023,84 +1123,109 @@ __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__r
   }
 }
 
-// One dimension, without atomics.  Packets of one (p-cell, q-cell) add to
-// the same cells with the same shifts, so their coefficient vectors can be
+// One dimension, without float atomics.  Packets of one (p-cell, q-cell) add
+// to the same cells with the same shifts, so their coefficient vectors can be
 // summed first:
-//   aggregate  one workgroup per bin (p-cell, q-tile); thread (q-cell, m)
-//              owns A[p-cell][q-cell][m] and adds c[m] of every record of the
-//              bin that sits in its q-cell (records are read by all threads:
-//              broadcast loads); deterministic;
+//   aggregate  one workgroup per bin (p-cell, q-tile).
+//              The bin's records pass through LDS in chunks; an LDS counting
+//              sort (integer atomics) groups each chunk by q-cell, and thread
+//              (q-cell, m) adds coefficient m of its q-cell's records into a
+//              register, so A[p-cell][q-cell][m] is written once;
 //   stencil    cells[s][q] = sum over b, a of A[s + mindp - dp_b][q - dq_a][a np + b]
 //              (eq. 2.25 with the shifts applied on the aggregated vectors).
+// The order of the terms inside a q-cell follows the sort (unspecified), so
+// the sums may differ from call to call at the rounding level.
 struct Agg1Params {
   const char *recs;
   const int64_t *start;
   int64_t Nq, tile, ntq, npc;
 };
 
-// Eight waves split the bin's records; within a wave, lane l owns
-// coefficient m = l % N1 of the q-cells l / N1 + (64 / N1) j (j < N1 / 2) of
-// the 32-cell tile; the partial tiles are summed through LDS at the end.
-constexpr int kAggWaves = 8;
+constexpr int kAggThreads = 256;
+// q-cells per one-dimensional bin (the sort's q-tile): fewer, larger bins make
+// the counting sort cheaper, more bins give the aggregate more workgroups
+constexpr int kAgg1Tile = 32;
 
-template <int N1, typename T>
-__global__ __launch_bounds__(64 * kAggWaves) void fggc_agg1_kernel(Agg1Params p, T *__restrict__ A) {
+// records per LDS chunk: up to 256, at most ~40 KB
+template <int RB> __host__ __device__ constexpr int agg1_chunk() {
+  return RB * 256 <= 40960 ? 256 : (RB * 128 <= 40960 ? 128 : 64);
+}
+
+template <int N1, typename T, int TILE>
+__global__ __launch_bounds__(kAggThreads) void fggc_agg1_kernel(Agg1Params p, T *__restrict__ A) {
   using R = decltype(T{}.x);
   constexpr int RB = rec_bytes<1, N1, T>();
-  constexpr int K = N1 / 2, STEP = 64 / N1, U = 16;
-  __shared__ T part[kAggWaves][32 * N1];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m = lane % N1, q0 = lane / N1;
+  static_assert(RB % 16 == 0 && rec_idx_bytes<1>() == 16, "records are whole 16-byte words");
+  constexpr int W = RB / 16, CH = agg1_chunk<RB>();
+  constexpr int PAIRS = TILE * N1, PER = (PAIRS + kAggThreads - 1) / kAggThreads;
+  static_assert(CH <= kAggThreads, "one record per thread and chunk");
+  static_assert(TILE <= 128 && kAggThreads >= TILE, "at most two waves scan the histogram");
+  __shared__ uint4 rs[CH * W];
+  __shared__ int hist[TILE], incl[TILE];
+  __shared__ uint16_t perm[CH];
+  const int tid = threadIdx.x;
   const int64_t bin = blockIdx.x;
   const int64_t pc = bin / p.ntq, t = bin - pc * p.ntq;
   const int tbase = (int)(t * p.tile);
-  const int64_t r0 = p.start[bin], r1 = p.start[bin + 1], n = r1 - r0;
-  const int64_t ra = r0 + (n * w) / kAggWaves, rb = r0 + (n * (w + 1)) / kAggWaves;
-  R ar[K], ai[K];
+  const int64_t r0 = p.start[bin], r1 = p.start[bin + 1];
+  const uint4 *src = reinterpret_cast<const uint4 *>(p.recs);
+  R accr[PER], acci[PER];
 #pragma unroll
-  for (int j = 0; j < K; ++j) ar[j] = ai[j] = 0;
-  int64_t r = ra;
-  for (; r + U <= rb; r += U) {
-    int qq[U];
-    T v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const char *rec = p.recs + (r + u) * (int64_t)RB;
-      qq[u] = *reinterpret_cast<const int32_t *>(rec) - tbase - q0;
-      v[u] = reinterpret_cast<const T *>(rec + rec_idx_bytes<1>())[m];
+  for (int i = 0; i < PER; ++i) accr[i] = acci[i] = 0;
+  if (tid < TILE) hist[tid] = 0;
+  for (int64_t c0 = r0; c0 < r1; c0 += CH) {
+    const int cnt = (int)min<int64_t>(CH, r1 - c0);
+    for (int w = tid; w < cnt * W; w += kAggThreads) rs[w] = src[c0 * W + w];
+    __syncthreads();
+    int ql = 0, rk = 0;
+    if (tid < cnt) {
+      // the record's q-cell lies in this bin's tile by construction of the
+      // keys; the clamp only keeps the LDS indexes in range
+      ql = reinterpret_cast<const int32_t *>(&rs[tid * W])[0] - tbase;
+      ql = ql < 0 ? 0 : (ql >= TILE ? TILE - 1 : ql);
+      rk = atomicAdd(&hist[ql], 1);
     }
+    __syncthreads();
+    if (tid < TILE) {  // inclusive scan within each wave
+      int v = hist[tid];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int j = 0; j < K; ++j)
-        if (qq[u] == STEP * j) {
-          ar[j] += v[u].x;
-          ai[j] += v[u].y;
-        }
-  }
-  for (; r < rb; ++r) {
-    const char *rec = p.recs + r * (int64_t)RB;
-    const int qq = *reinterpret_cast<const int32_t *>(rec) - tbase - q0;
-    const T v = reinterpret_cast<const T *>(rec + rec_idx_bytes<1>())[m];
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-      if (qq == STEP * j) {
-        ar[j] += v.x;
-        ai[j] += v.y;
+      for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(v, d, 64);
+        if ((tid & 63) >= d) v += u;
       }
+      incl[tid] = v;
+    }
+    __syncthreads();
+    // first position of q-cell q in the chunk's grouped order
+    auto first = [&](int q) {
+      if constexpr (TILE > 64) return incl[q] - hist[q] + (q >= 64 ? incl[63] : 0);
+      else return incl[q] - hist[q];
+    };
+    if (tid < cnt) perm[first(ql) + rk] = (uint16_t)tid;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * kAggThreads;
+      if (e < PAIRS) {
+        const int q = e / N1, m = e - (e / N1) * N1;
+        const int b = first(q), n = hist[q];
+        for (int k = 0; k < n; ++k) {
+          const T v = reinterpret_cast<const T *>(&rs[perm[b + k] * W + 1])[m];
+          accr[i] += v.x;
+          acci[i] += v.y;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < TILE) hist[tid] = 0;
   }
 #pragma unroll
-  for (int j = 0; j < K; ++j) part[w][(q0 + STEP * j) * N1 + m] = T{ar[j], ai[j]};
-  __syncthreads();
-  for (int e = threadIdx.x; e < 32 * N1; e += blockDim.x) {
-    const int ql = e / N1;
-    T sum = part[0][e];
-#pragma unroll
-    for (int x = 1; x < kAggWaves; ++x) {
-      sum.x += part[x][e].x;
-      sum.y += part[x][e].y;
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * kAggThreads;
+    if (e < PAIRS) {
+      const int q = e / N1, m = e - (e / N1) * N1;
+      if (q < p.tile) A[(pc * p.Nq + tbase + q) * N1 + m] = T{accr[i], acci[i]};
     }
-    if (ql < p.tile) A[(pc * p.Nq + tbase + ql) * N1 + (e % N1)] = sum;
   }
 }
 
@@ -1131,20 +1256,8 @@ __global__ void fggc_stencil1_kernel(Stencil1Params p, const T *__restrict__ A, 
   cells[e] = T{ar, ai};
 }
 
-// Band tables per dimension: for slice index l (p = (slo + l) dp) the first
-// frequency kstart of its band and gamma values for kstart .. kstart + nb - 1.
-struct BandParams {
-  int d;
-  double eps, cK;
-  int64_t slo[3], sn[3];
-  double dp[3];
-  int64_t nb[3];    // table width per dimension
-  int64_t toff[3];  // offset of each dimension's gamma table (entries)
-  int64_t koff[3];  // offset of each dimension's kstart table (entries)
-};
-
-// First frequency of slice l's band, and gamma at frequency k = k0 + i
-// (0 outside the truncated band); used by the table kernel and inline.
+// First frequency of slice l's band, and gamma at frequency k (0 outside the
+// truncated band).
 __device__ __forceinline__ int64_t band_start(double p, double eps, double cK) {
   return (int64_t)ceil(p / eps - cK / sqrt(eps));
 }
@@ -1155,130 +1268,18 @@ __device__ __forceinline__ double band_gamma(double p, int64_t k, double eps, do
   return (ex >= -0.5 * cK * cK * (1.0 + 1e-12)) ? cst * exp(ex) : 0.0;
 }
 
-template <typename R>
-__global__ void band_table_kernel(BandParams b, R *__restrict__ gam, int64_t *__restrict__ kst) {
-  const int k = blockIdx.y;
-  if (k >= b.d) return;
-  const int64_t total = b.sn[k] * b.nb[k];
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t l = e / b.nb[k], i = e - l * b.nb[k];
-    const double p = (double)(b.slo[k] + l) * b.dp[k];
-    const int64_t k0 = band_start(p, b.eps, b.cK);
-    gam[b.toff[k] + e] = (R)band_gamma(p, k0 + i, b.eps, b.cK);
-    if (i == 0) kst[b.koff[k] + l] = k0;
-  }
-}
-
 struct MacParams {
   double dp[3];
-  int64_t M[3], Nq[3], sn[3], nb[3], toff[3], koff[3];
+  int64_t M[3], Nq[3], sn[3], nb[3];
   int64_t kmin[3], kmax[3];  // union of the bands per dimension
   double lo_c[3], inv_dp[3], eps, cK;  // l range helpers
   int64_t slo[3];
 };
 
-template <int D, typename T, typename R>
-__global__ __launch_bounds__(256) void band_mac_kernel(MacParams m, const T *__restrict__ F,
-                                                       const R *__restrict__ gam,
-                                                       const int64_t *__restrict__ kst,
-                                                       T *__restrict__ U) {
-  int64_t npts = 1;
-  for (int k = 0; k < D; ++k) npts *= m.M[k];
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= npts) return;
-  int64_t kp[3] = {0, 0, 0};
-  {
-    int64_t rem = e;
-    for (int k = D - 1; k >= 0; --k) {
-      kp[k] = rem % m.M[k];
-      rem /= m.M[k];
-    }
-  }
-  int64_t nqt = 1;
-  for (int k = 0; k < D; ++k) nqt *= m.Nq[k];
-  const double se = sqrt(m.eps);
-  // per dimension: the aliases k = k' + jM that can lie in some band, and for
-  // each the slice range whose band holds it
-  double accr = 0.0, acci = 0.0;
-  int64_t j0[3], j1[3];
-  for (int k = 0; k < D; ++k) {
-    // smallest j with k' + jM >= kmin, largest with k' + jM <= kmax
-    int64_t a = m.kmin[k] - kp[k], b = m.kmax[k] - kp[k];
-    j0[k] = a >= 0 ? (a + m.M[k] - 1) / m.M[k] : -((-a) / m.M[k]);
-    j1[k] = b >= 0 ? b / m.M[k] : -((-b + m.M[k] - 1) / m.M[k]);
-  }
-  auto lrange = [&](int k, int64_t kk, int64_t &la, int64_t &lb) {
-    // slices whose band [kst, kst + nb) holds kk; start from the real-valued estimate
-    const double pk = m.eps * (double)kk;
-    int64_t a = (int64_t)floor((pk - m.cK * se) * m.inv_dp[k]) - m.slo[k] - 1;
-    int64_t b = (int64_t)ceil((pk + m.cK * se) * m.inv_dp[k]) - m.slo[k] + 1;
-    if (a < 0) a = 0;
-    if (b > m.sn[k] - 1) b = m.sn[k] - 1;
-    la = a;
-    lb = b;
-  };
-  const int64_t ts0 = m.koff[0], ts1 = m.koff[1], ts2 = m.koff[2];
-  for (int64_t ja = j0[0]; ja <= j1[0]; ++ja) {
-    const int64_t k0 = kp[0] + ja * m.M[0];
-    int64_t la0, lb0;
-    lrange(0, k0, la0, lb0);
-    const int64_t q0 = ((k0 % m.Nq[0]) + m.Nq[0]) % m.Nq[0];
-    for (int64_t l0 = la0; l0 <= lb0; ++l0) {
-      const int64_t i0 = k0 - kst[ts0 + l0];
-      if (i0 < 0 || i0 >= m.nb[0]) continue;
-      const double g0 = (double)gam[m.toff[0] + l0 * m.nb[0] + i0];
-      if (g0 == 0.0) continue;
-      if (D == 1) {
-        const T f = F[l0 * nqt + q0];
-        accr = fma(g0, (double)f.x, accr);
-        acci = fma(g0, (double)f.y, acci);
-        continue;
-      }
-      for (int64_t jb = j0[1]; jb <= j1[1]; ++jb) {
-        const int64_t k1 = kp[1] + jb * m.M[1];
-        int64_t la1, lb1;
-        lrange(1, k1, la1, lb1);
-        const int64_t q1 = ((k1 % m.Nq[1]) + m.Nq[1]) % m.Nq[1];
-        for (int64_t l1 = la1; l1 <= lb1; ++l1) {
-          const int64_t i1 = k1 - kst[ts1 + l1];
-          if (i1 < 0 || i1 >= m.nb[1]) continue;
-          const double g01 = g0 * (double)gam[m.toff[1] + l1 * m.nb[1] + i1];
-          if (g01 == 0.0) continue;
-          if (D == 2) {
-            const T f = F[(l0 * m.sn[1] + l1) * nqt + q0 * m.Nq[1] + q1];
-            accr = fma(g01, (double)f.x, accr);
-            acci = fma(g01, (double)f.y, acci);
-            continue;
-          }
-          for (int64_t jc = j0[2]; jc <= j1[2]; ++jc) {
-            const int64_t k2 = kp[2] + jc * m.M[2];
-            int64_t la2, lb2;
-            lrange(2, k2, la2, lb2);
-            const int64_t q2 = ((k2 % m.Nq[2]) + m.Nq[2]) % m.Nq[2];
-            for (int64_t l2 = la2; l2 <= lb2; ++l2) {
-              const int64_t i2 = k2 - kst[ts2 + l2];
-              if (i2 < 0 || i2 >= m.nb[2]) continue;
-              const double g = g01 * (double)gam[m.toff[2] + l2 * m.nb[2] + i2];
-              const T f = F[((l0 * m.sn[1] + l1) * m.sn[2] + l2) * nqt +
-                            (q0 * m.Nq[1] + q1) * m.Nq[2] + q2];
-              accr = fma(g, (double)f.x, accr);
-              acci = fma(g, (double)f.y, acci);
-            }
-          }
-        }
-      }
-    }
-  }
-  U[e] = T{(R)accr, (R)acci};
-}
-
 // One dimension: eight lanes per frequency split the slice loop, then a
 // shuffle reduction (FP64) -- eight times the waves of the plain kernel.
 template <typename T, typename R>
 __global__ __launch_bounds__(256) void band_mac1_kernel(MacParams m, const T *__restrict__ F,
-                                                         const R *__restrict__ gam,
-                                                         const int64_t *__restrict__ kst,
                                                          T *__restrict__ U) {
   const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t e = id >> 3;
@@ -1299,7 +1300,7 @@ __global__ __launch_bounds__(256) void band_mac1_kernel(MacParams m, const T *__
       if (lb > m.sn[0] - 1) lb = m.sn[0] - 1;
       const int64_t q0 = ((k0 % m.Nq[0]) + m.Nq[0]) % m.Nq[0];
       for (int64_t l0 = la + g; l0 <= lb; l0 += 8) {
-        // gamma evaluated in place, exactly as the band table would hold it
+        // gamma evaluated in place, rounded to the record precision
         const double p = (double)(m.slo[0] + l0) * m.dp[0];
         const int64_t i0 = k0 - band_start(p, m.eps, m.cK);
         if (i0 < 0 || i0 >= m.nb[0]) continue;
@@ -1328,88 +1329,110 @@ __global__ __launch_bounds__(256) void band_mac1_kernel(MacParams m, const T *__
 // with the band weights (FP64 accumulation) and writes [O][A][M][B].
 struct ContractParams {
   int64_t O, L, A, B, M;
-  int lgN, W, Lc, R;  // W: b values per workgroup; Lc: slices per LDS chunk; R: outputs per thread
-  int MS;             // workgroups sharing one line group, each with M / MS of the frequencies
-  int64_t nb, toff, koff, slo, kmin, kmax;
-  double eps, cK, inv_dp;
+  int lgN, lgWA, lgW;  // q-line length; lines of consecutive a and of consecutive b per workgroup
+  int Lc;              // slices per LDS chunk
+  int MS;              // workgroups sharing one line group, each with a share of the frequencies
+  int64_t kmin, kmax;  // union of the slices' bands (grid frequencies before aliasing)
+  int64_t slo;
+  double eps, dp, cK;
 };
 
+constexpr int kContractOut = 8;  // outputs per thread (256 threads, 2048 per workgroup)
 
+// One pass of the separable finish over dimension k of the cell array (or of
+// the previous pass's output), viewed as X[O][L][A][N][B]:
+//   Y[o][a][k'][b] = sum_l sum_{kk = k' (mod M)} gamma_l(kk) F_{o,l,a,b}[kk mod N],
+// F the length-N DFT over n of X[o][l][a][.][b] and gamma_l the band of slice
+// l in this dimension (eq. 2.24 factors over dimensions; kk runs over the
+// truncated band |kk - p_l/eps| <= cK/sqrt(eps)).  A workgroup loads chunks of
+// Lc slices of its 2^lgWA x 2^lgW lines into LDS, transforms them there and
+// adds each slice's band into per-thread FP64 sums of its outputs; gamma is
+// evaluated in place.  Frequencies no band reaches are written as zeros.
 template <typename T, typename R>
 __global__ __launch_bounds__(256) void fft_contract_kernel(ContractParams p, const T *__restrict__ X,
-                                                           T *__restrict__ Y, const R *__restrict__ gam,
-                                                           const int64_t *__restrict__ kst,
-                                                           const T *__restrict__ tw) {
+                                                           T *__restrict__ Y, const T *__restrict__ tw) {
   using RR = decltype(T{}.x);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *sm = reinterpret_cast<T *>(smem_raw);
-  const int N = 1 << p.lgN, W = p.W, M = (int)p.M;
-  const int64_t nbc = p.B / W;
+  const int lgN = p.lgN, N = 1 << lgN, WA = 1 << p.lgWA, W = 1 << p.lgW, P = WA * W;
+  const int M = (int)p.M;
+  const int64_t nbc = p.B >> p.lgW, nac = p.A >> p.lgWA;
   int64_t g = blockIdx.x;
   const int mg = (int)(g % p.MS);
   g /= p.MS;
   const int64_t bc = g % nbc;
   g /= nbc;
-  const int64_t a = g % p.A, o = g / p.A;
-  const int64_t b0 = bc * W;
-  const int Mg = M / p.MS, k0g = mg * Mg;  // this workgroup's frequencies [k0g, k0g + Mg)
-  const int nout = Mg * W;
-  const int nb = (int)p.nb;
-  // LDS: rows of the chunk, one accumulator per output ([w][k]), band rows
-  T *acc = sm + (size_t)p.Lc * N * W;
-  R *bg = reinterpret_cast<R *>(acc + nout);
-  int *bk = reinterpret_cast<int *>(bg + (size_t)p.Lc * nb);
-  for (int e = threadIdx.x; e < nout; e += blockDim.x) acc[e] = T{0, 0};
-  const double se = sqrt(p.eps);
-  const int kmin = (int)p.kmin, kmax = (int)p.kmax, slo = (int)p.slo;
+  const int64_t ac = g % nac, o = g / nac;
+  const int64_t b0 = bc << p.lgW, a0 = ac << p.lgWA;
+  // frequencies in band order t = (k' - kmin) mod M: the first nact reach a
+  // band; this workgroup takes t in [t0, t0 + Mg)
+  const int nact = (int)min<int64_t>(M, p.kmax - p.kmin + 1);
+  const int Mg = M / p.MS, t0 = mg * Mg;
+  const int na = max(0, min(Mg, nact - t0));  // active frequencies of this workgroup
+  const int nown = na * P;
+  const int kmod = (int)(((p.kmin % M) + M) % M);
+  double accr[kContractOut], acci[kContractOut];
+#pragma unroll
+  for (int c = 0; c < kContractOut; ++c) accr[c] = acci[c] = 0.0;
+  const double cst = sqrt(kTwoPi * p.eps) / kTwoPi, cut = -0.5 * p.cK * p.cK * (1.0 + 1e-12);
+  const double inv2e = 1.0 / (2.0 * p.eps);
   for (int lc0 = 0; lc0 < (int)p.L; lc0 += p.Lc) {
     const int lcn = min(p.Lc, (int)p.L - lc0);
-    const int tot = lcn * N * W;
+    // rows [l][wa][w] of N, loaded with b fastest, then n, then a
+    const int tot = lcn * P * N;
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-      const int w = e % W, rest = e / W;
-      const int n = rest & (N - 1), l = rest >> p.lgN;
-      sm[(l * W + w) * N + n] = X[(((o * p.L + lc0 + l) * p.A + a) * N + n) * p.B + b0 + w];
+      const int w = e & (W - 1), n = (e >> p.lgW) & (N - 1), rest = e >> (p.lgW + lgN);
+      const int wa = rest & (WA - 1), l = rest >> p.lgWA;
+      const int row = (((l << p.lgWA) + wa) << p.lgW) + w;
+      sm[(row << lgN) + n] = X[((((o * p.L + lc0 + l) * p.A + a0 + wa) << lgN) + n) * p.B + b0 + w];
     }
-    for (int e = threadIdx.x; e < lcn * nb; e += blockDim.x) bg[e] = gam[p.toff + (int64_t)lc0 * nb + e];
-    for (int e = threadIdx.x; e < lcn; e += blockDim.x) bk[e] = (int)kst[p.koff + lc0 + e];
     __syncthreads();
-    lds_fft_rows<T>(sm, p.lgN, lcn * W, N, 0, tw);
-    for (int e = threadIdx.x; e < nout; e += blockDim.x) {
-      const int kp = k0g + e % Mg, w = e / Mg;
-      // aliases kk = kp + j M inside [kmin, kmax]
-      const int lo = kmin - kp, hi = kmax - kp;
-      const int j0 = lo >= 0 ? (lo + M - 1) / M : -((-lo) / M);
-      const int j1 = hi >= 0 ? hi / M : -((-hi + M - 1) / M);
+    lds_fft_rows<T>(sm, lgN, lcn * P, N, 0, tw);
+#pragma unroll
+    for (int c = 0; c < kContractOut; ++c) {
+      const int e = threadIdx.x + c * (int)blockDim.x;
+      if (e >= nown) break;
+      // e = (wa, t, w) with w fastest (coalesced along b), then t
+      const int w = e & (W - 1), rest = e >> p.lgW;
+      const int t = rest % na, wa = rest / na;
+      const T *rows = sm + ((wa << p.lgW) + w) * N;  // slice l at rows + l * P * N
       double xr = 0.0, xi = 0.0;
-      for (int j = j0; j <= j1; ++j) {
-        const int kk = kp + j * M;
-        const double pk = p.eps * (double)kk;
-        int la = (int)floor((pk - p.cK * se) * p.inv_dp) - slo - 1;
-        int lb = (int)ceil((pk + p.cK * se) * p.inv_dp) - slo + 1;
-        la = max(la, lc0);
-        lb = min(lb, lc0 + lcn - 1);
-        const int q = kk & (N - 1);
-        for (int l = la; l <= lb; ++l) {
-          const int ll = l - lc0;
-          const int i0 = kk - bk[ll];
-          if (i0 < 0 || i0 >= nb) continue;
-          const double gv = (double)bg[ll * nb + i0];
-          const T v = sm[(ll * W + w) * N + q];
+      for (int64_t kk = p.kmin + t0 + t; kk <= p.kmax; kk += M) {
+        const T *fq = rows + (int)(kk & (N - 1));
+        const double dk0 = p.eps * (double)kk - (double)(p.slo + lc0) * p.dp;
+        for (int l = 0; l < lcn; ++l) {
+          const double dk = dk0 - (double)l * p.dp;  // eps (kk - p_l / eps)
+          const double ex = -dk * dk * inv2e;
+          if (ex < cut) continue;
+          double gv;
+          if constexpr (sizeof(R) == 4) gv = (double)(float)(cst * (double)__expf((float)ex));
+          else gv = cst * exp(ex);
+          const T v = fq[l * P * N];
           xr = fma(gv, (double)v.x, xr);
           xi = fma(gv, (double)v.y, xi);
         }
       }
-      T c = acc[e];
-      c.x += (RR)xr;
-      c.y += (RR)xi;
-      acc[e] = c;
+      accr[c] += xr;
+      acci[c] += xi;
     }
     __syncthreads();
   }
-  // write coalesced along b
-  for (int e = threadIdx.x; e < nout; e += blockDim.x) {
-    const int kl = e / W, w = e % W;
-    Y[((o * p.A + a) * p.M + k0g + kl) * p.B + b0 + w] = acc[w * Mg + kl];
+#pragma unroll
+  for (int c = 0; c < kContractOut; ++c) {
+    const int e = threadIdx.x + c * (int)blockDim.x;
+    if (e >= nown) break;
+    const int w = e & (W - 1), rest = e >> p.lgW;
+    const int t = rest % na, wa = rest / na;
+    const int kp = (kmod + t0 + t) % M;
+    Y[((o * p.A + a0 + wa) * p.M + kp) * p.B + b0 + w] = T{(RR)accr[c], (RR)acci[c]};
+  }
+  // frequencies of this workgroup's share that no band reaches
+  const int nz = (Mg - na) * P;
+  for (int e = threadIdx.x; e < nz; e += blockDim.x) {
+    const int w = e & (W - 1), rest = e >> p.lgW;
+    const int t = na + rest % (Mg - na), wa = rest / (Mg - na);
+    const int kp = (kmod + t0 + t) % M;
+    Y[((o * p.A + a0 + wa) * p.M + kp) * p.B + b0 + w] = T{0, 0};
   }
 }
 
@@ -1417,9 +1440,9 @@ struct FggcLayout {
   int d, N1, rec_b, ns;
   bool agg1;  // one dimension: aggregate + stencil instead of tile accumulation
   int64_t ncells, nslices, npts, nbins, nslots, tiles, ntq[3], tile[3], npc[3], pmin[3], S[3], nsw[3];
-  int64_t nb[3], toff[3], koff[3], ntab, nkst;
+  int64_t nb[3];
   int mindp, maxdp, mindq, maxdq;
-  size_t off_lsq, off_keys, off_pos, off_sort, off_start, off_recs, off_agg, off_cells, off_gam, off_kst,
+  size_t off_lsq, off_keys, off_pos, off_sort, off_start, off_recs, off_agg, off_cells,
       off_spec, off_x1, off_x2, total;
 };
 
@@ -1450,8 +1473,6 @@ FggcLayout fggc_layout(const FggcArgs &a) {
   L.nslices = 1;
   int64_t nqt = 1;
   L.npts = 1;
-  L.ntab = 0;
-  L.nkst = 0;
   L.nbins = 1;
   L.tiles = 1;
   for (int k = 0; k < 3; ++k) {
@@ -1461,7 +1482,7 @@ FggcLayout fggc_layout(const FggcArgs &a) {
       L.npts *= a.g.n[k];
       // one dimension aggregates by own q-cell (no halo): tiles of exactly 32
       // cells, the width of the aggregation workgroup
-      L.tile[k] = d == 1 ? std::min<int64_t>(a.Nq[k], 32)
+      L.tile[k] = d == 1 ? std::min<int64_t>(a.Nq[k], kAgg1Tile)
                          : std::min<int64_t>(a.Nq[k], std::max<int64_t>(deft[d], tmin));
       L.ntq[k] = a.Nq[k] / L.tile[k];
       L.pmin[k] = a.slo[k] - L.mindp;
@@ -1471,16 +1492,10 @@ FggcLayout fggc_layout(const FggcArgs &a) {
       L.nbins *= L.npc[k] * L.ntq[k];
       L.tiles *= L.nsw[k] * L.ntq[k];
       L.nb[k] = (int64_t)std::floor(2.0 * a.cK / std::sqrt(a.eps)) + 2;
-      L.toff[k] = L.ntab;
-      L.koff[k] = L.nkst;
-      L.ntab += a.sn[k] * L.nb[k];
-      L.nkst += a.sn[k];
     } else {
       L.tile[k] = L.ntq[k] = L.npc[k] = L.S[k] = L.nsw[k] = 1;
       L.pmin[k] = 0;
       L.nb[k] = 1;
-      L.toff[k] = 0;
-      L.koff[k] = 0;
     }
   }
   if (L.nbins >= ((int64_t)1 << 32)) fail(FGGC_EUNSUPPORTED, "too many packet bins");
@@ -1506,8 +1521,6 @@ FggcLayout fggc_layout(const FggcArgs &a) {
   L.off_agg = put(L.agg1 ? (size_t)L.npc[0] * a.Nq[0] * L.N1 * es : 0);
   (void)N;
   L.off_cells = put((size_t)L.ncells * es);
-  L.off_gam = put((size_t)L.ntab * (es / 2));
-  L.off_kst = put((size_t)L.nkst * 8 + 64);
   L.off_spec = put((size_t)L.npts * es);  // grid spectrum (the inverse FFT writes u from it)
   // separable finish (d >= 2): outputs of the passes over the last and the
   // middle dimension, [l_<k][i_<k][grid frequencies of dims >= k]
@@ -1582,8 +1595,8 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
     gp.tile = L.tile[0];
     gp.ntq = L.ntq[0];
     gp.npc = L.npc[0];
-    const dim3 gg((unsigned)L.nbins), gb(64 * kAggWaves);
-    fggc_agg1_kernel<N1, T><<<gg, gb, 0, s>>>(gp, A);
+    const dim3 gg((unsigned)L.nbins), gb(kAggThreads);
+    fggc_agg1_kernel<N1, T, kAgg1Tile><<<gg, gb, 0, s>>>(gp, A);
     FGGC_HIP(hipGetLastError());
     Stencil1Params sp{};
     sp.Nq = a.Nq[0];
@@ -1708,7 +1721,7 @@ void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells
         launch_zero(table, (size_t)L.nbins * cpn.G * 4, s);
       }
       count_scan(cpn, L.nbins, sc_base, start, s);
-      if (N > 0) count_positions(cpn, keys, L.nslots, sc_base, pos, s);
+      if (N > 0) count_positions(cpn, keys, L.nslots, sc_base, start, pos, s);
     } else if (N > 0) {
       const dim3 g((unsigned)((N + 255) / 256)), b(256);
       if (d == 1) fggc_key_kernel<1><<<g, b, 0, s>>>(kp, keys);
@@ -1727,7 +1740,7 @@ void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells
   cp.P = a.pk->P;
   cp.S = a.pk->S;
   cp.a = a.pk->a;
-  cp.eps = a.eps;
+  cp.inv_2pi_eps = 1.0 / (kTwoPi * a.eps);
   cp.scale = a.scale;
   cp.lsq = dlsq;
   for (int k = 0; k < 3; ++k) {
@@ -1755,15 +1768,14 @@ std::mutex g_contract_mu;
 
 // One separable pass over dimension k (see fft_contract_kernel).
 template <typename T, typename R>
-void launch_contract(const FggcArgs &a, const FggcLayout &L, int k, const T *in, T *out, const R *gam,
-                     const int64_t *kst, const MacParams &m, hipStream_t s) {
+void launch_contract(const FggcArgs &a, int k, const T *in, T *out, const MacParams &m, hipStream_t s) {
   {
     std::lock_guard<std::mutex> lk(g_contract_mu);
     if (!g_contract_attr) {
       FGGC_HIP(hipFuncSetAttribute((const void *)fft_contract_kernel<float2, float>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
       FGGC_HIP(hipFuncSetAttribute((const void *)fft_contract_kernel<double2, double>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
       g_contract_attr = true;
     }
   }
@@ -1779,76 +1791,59 @@ void launch_contract(const FggcArgs &a, const FggcLayout &L, int k, const T *in,
   for (int j = k + 1; j < d; ++j) p.B *= a.g.n[j];
   p.L = a.sn[k];
   p.M = a.g.n[k];
-  int lgN = 0;
-  while (((int64_t)1 << lgN) < a.Nq[k]) ++lgN;
-  p.lgN = lgN;
   const int64_t N = a.Nq[k];
-  const size_t es = sizeof(T);
-  // b values per workgroup: coalesced runs along b, at most 4096 outputs per workgroup
-  int64_t W = 1;
-  while (W * 2 <= std::min<int64_t>(16, p.B) && W * 2 * p.M <= 4096) W *= 2;
-  // LDS chunk: rows * N elements within the butterfly budget of lds_fft_rows
-  // for 256 threads, counting the radix-2 pass of an odd log2 N
-  // (rows * N / 2 <= 256 * kMaxBfly)
-  const int64_t elems = 256 * kMaxBfly * 2;
-  while (W > 1 && N * W > elems) W /= 2;
-  if (N * W > elems) fail(FGGC_EUNSUPPORTED, "q-mesh too long for the separable finish");
-  p.W = (int)W;
-  p.Lc = (int)std::max<int64_t>(1, std::min<int64_t>(p.L, elems / (N * W)));
-  // split the frequencies of a line group over several workgroups when there
-  // are few line groups (each recomputes the group's FFTs)
-  const int64_t groups = p.O * p.A * (p.B / W);
+  int lgN = 0;
+  while (((int64_t)1 << lgN) < N) ++lgN;
+  p.lgN = lgN;
+  // lines per workgroup: runs of up to 4 consecutive b (contiguous in memory),
+  // or, when b is a single line, up to 16 consecutive a (whole rows of N);
+  // a chunk holds at most 4096 elements (the butterfly budget of
+  // lds_fft_rows for 256 threads, counting the radix-2 pass of an odd log2 N)
+  constexpr int64_t kElems = 256 * kMaxBfly * 2;
+  if (N > kElems) fail(FGGC_EUNSUPPORTED, "q-mesh too long for the separable finish");
+  int lgW = 0, lgWA = 0;
+  while ((2 << lgW) <= std::min<int64_t>(4, p.B) && (N << (lgW + 1)) <= kElems) ++lgW;
+  if (p.B == 1)
+    while ((2 << lgWA) <= std::min<int64_t>(16, p.A) && (N << (lgWA + 1)) <= 1024 &&
+           (p.M << (lgWA + 1)) <= 256 * kContractOut)
+      ++lgWA;
+  p.lgW = lgW;
+  p.lgWA = lgWA;
+  const int64_t P = (int64_t)1 << (lgW + lgWA);
+  if (p.B % (1 << lgW) || p.A % (1 << lgWA)) fail(FGGC_EUNSUPPORTED, "separable finish: uneven line packing");
+  p.Lc = (int)std::max<int64_t>(1, std::min<int64_t>(p.L, kElems / (N * P)));
+  // frequencies split over MS workgroups: at most 256 * kContractOut outputs
+  // each, and more splits (each redoing the group's DFTs) when there are
+  // few line groups
+  const int64_t groups = p.O * (p.A / (1 << lgWA)) * (p.B / (1 << lgW));
   int MS = 1;
-  while (groups * MS < 1024 && MS * 2 <= 16 && (p.M / (MS * 2)) * W >= 256) MS *= 2;
+  while ((p.M / MS) * P > 256 * kContractOut) MS *= 2;
+  while (groups * MS < 1024 && MS * 2 <= 16 && (p.M / (MS * 2)) * P >= 256) MS *= 2;
+  if (p.M % MS) fail(FGGC_EUNSUPPORTED, "separable finish: uneven frequency split");
   p.MS = MS;
-  p.R = 0;
-  p.nb = L.nb[k];
-  p.toff = L.toff[k];
-  p.koff = L.koff[k];
-  p.slo = a.slo[k];
   p.kmin = m.kmin[k];
   p.kmax = m.kmax[k];
+  p.slo = a.slo[k];
   p.eps = a.eps;
+  p.dp = a.dp[k];
   p.cK = a.cK;
-  p.inv_dp = 1.0 / a.dp[k];
-  const size_t rows_b = ((size_t)p.Lc * N * W + (size_t)(p.M / MS) * W) * es;
-  const size_t band_b = (size_t)p.Lc * p.nb * sizeof(R) + (size_t)p.Lc * 4;
-  const size_t shm = rows_b + band_b + 16;
-  if (shm > 131072) fail(FGGC_EUNSUPPORTED, "separable finish needs more than 128 KB of LDS");
+  const size_t shm = (size_t)p.Lc * N * P * sizeof(T) + 16;
   const int64_t blocks = groups * MS;
   if (blocks >= ((int64_t)1 << 31)) fail(FGGC_EUNSUPPORTED, "too many workgroups for the separable finish");
   const T *tw = (const T *)fft_twiddles(N, a.precision);
-  fft_contract_kernel<T, R><<<dim3((unsigned)blocks), dim3(256), shm, s>>>(p, in, out, gam, kst, tw);
+  fft_contract_kernel<T, R><<<dim3((unsigned)blocks), dim3(256), shm, s>>>(p, in, out, tw);
   FGGC_HIP(hipGetLastError());
 }
 
 template <typename T, typename R>
-void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, R *gam, int64_t *kst,
-                  void *spec, Workspace &ws, hipStream_t s) {
+void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, void *spec, Workspace &ws,
+                  hipStream_t s) {
   const int d = a.g.d;
   const int prec = a.precision;
   // F5: forward DFT over q of every p-slice (one dimension; higher dimensions
   // fold the DFT into the separable passes below)
   if (d == 1) launch_fft(d, a.Nq, L.nslices, -1, prec, cells, ws, s, a.prof, "fggc_fft_q");
-  // band tables
-  BandParams bp{};
-  bp.d = d;
-  bp.eps = a.eps;
-  bp.cK = a.cK;
-  for (int k = 0; k < 3; ++k) {
-    bp.slo[k] = a.slo[k];
-    bp.sn[k] = a.sn[k];
-    bp.dp[k] = a.dp[k];
-    bp.nb[k] = L.nb[k];
-    bp.toff[k] = L.toff[k];
-    bp.koff[k] = L.koff[k];
-  }
-  if (d >= 2) {  // one dimension evaluates gamma in place
-    StageScope sc(a.prof, "fggc_band_table", s);
-    band_table_kernel<R><<<dim3(64, (unsigned)d), dim3(256), 0, s>>>(bp, gam, kst);
-    FGGC_HIP(hipGetLastError());
-  }
-  // F6: band multiply-accumulate into the grid spectrum (written into u)
+  // F6: band multiply-accumulate into the grid spectrum (gamma evaluated in place)
   MacParams m{};
   const double se = std::sqrt(a.eps);
   for (int k = 0; k < 3; ++k) {
@@ -1856,8 +1851,6 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, 
     m.Nq[k] = k < d ? a.Nq[k] : 1;
     m.sn[k] = a.sn[k];
     m.nb[k] = L.nb[k];
-    m.toff[k] = L.toff[k];
-    m.koff[k] = L.koff[k];
     m.slo[k] = a.slo[k];
     m.dp[k] = a.dp[k];
     m.inv_dp[k] = 1.0 / a.dp[k];
@@ -1869,7 +1862,6 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, 
   m.eps = a.eps;
   m.cK = a.cK;
   T *U = (T *)spec;
-  const unsigned nblk = (unsigned)((L.npts + 255) / 256);
   if (d >= 2) {
     // F5 + F6 as d separable passes, last dimension first, into the spectrum
     StageScope sc(a.prof, "fggc_contract", s);
@@ -1877,16 +1869,13 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, 
     const T *in = cells;
     for (int k = d - 1; k >= 0; --k) {
       T *out = k == 0 ? U : (k == d - 1 ? x1 : x2);
-      launch_contract<T, R>(a, L, k, in, out, gam, kst, m, s);
+      launch_contract<T, R>(a, k, in, out, m, s);
       in = out;
     }
   } else {
-  StageScope sc(a.prof, "fggc_band_mac", s);
-  if (d == 1)
-    band_mac1_kernel<T, R><<<(unsigned)((8 * L.npts + 255) / 256), 256, 0, s>>>(m, cells, gam, kst, U);
-  else if (d == 2) band_mac_kernel<2, T, R><<<nblk, 256, 0, s>>>(m, cells, gam, kst, U);
-  else band_mac_kernel<3, T, R><<<nblk, 256, 0, s>>>(m, cells, gam, kst, U);
-  FGGC_HIP(hipGetLastError());
+    StageScope sc(a.prof, "fggc_band_mac", s);
+    band_mac1_kernel<T, R><<<(unsigned)((8 * L.npts + 255) / 256), 256, 0, s>>>(m, cells, U);
+    FGGC_HIP(hipGetLastError());
   }
   // F7: inverse DFT of the grid spectrum into u
   launch_fft_to(d, a.g.n, +1, prec, U, a.u, ws, s, a.prof, "fggc_ifft");
@@ -1918,11 +1907,9 @@ void launch_fggc(const FggcArgs &a, Workspace &ws, hipStream_t s) {
   void *cells = base + L.off_cells;
   cells_stage(a, L, base, cells, s);
   if (a.precision == FGGC_FP64)
-    finish_stage<double2, double>(a, L, base, (double2 *)cells, (double *)(base + L.off_gam),
-                                  (int64_t *)(base + L.off_kst), base + L.off_spec, ws, s);
+    finish_stage<double2, double>(a, L, base, (double2 *)cells, base + L.off_spec, ws, s);
   else
-    finish_stage<float2, float>(a, L, base, (float2 *)cells, (float *)(base + L.off_gam),
-                                (int64_t *)(base + L.off_kst), base + L.off_spec, ws, s);
+    finish_stage<float2, float>(a, L, base, (float2 *)cells, base + L.off_spec, ws, s);
 }
 
 }  // namespace fggc

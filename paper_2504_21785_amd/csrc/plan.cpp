@@ -3,6 +3,7 @@
 // step 0: the pseudo-inverse is precomputed once per mesh and neighbour
 // strategy, here as eigenpairs so that it is applied as V diag(1/lambda) V^H
 // and never formed as an explicit matrix).
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -129,10 +130,16 @@ void build_dim_lsq(const fggc_strategy &st, int dim, double eps, DimLsq *out) {
       out->V[2 * (i * n1 + k)] = (double)V[(size_t)i * n1 + k].real();
       out->V[2 * (i * n1 + k) + 1] = (double)V[(size_t)i * n1 + k].imag();
     }
+  out->dq0 = *std::min_element(st.dq_off, st.dq_off + st.nq);
+  out->dp0 = *std::min_element(st.dp_off, st.dp_off + st.np);
   for (int k = 0; k < n1; ++k) {
     const long double ph = -Cq * Cp * (long double)out->dq[k] * (long double)out->dp[k] / 2;
     out->D[2 * k] = (double)std::cos(ph);
     out->D[2 * k + 1] = (double)std::sin(ph);
+    const long double eq = out->dq[k] - out->dq0, ep = out->dp[k] - out->dp0;
+    const long double g = std::exp(-(Cq * Cq * eq * eq + Cp * Cp * ep * ep) / 4);
+    out->DK[2 * k] = (double)(g * std::cos(ph));
+    out->DK[2 * k + 1] = (double)(g * std::sin(ph));
   }
 }
 

@@ -9,9 +9,10 @@
 //   rank    each workgroup counts the keys of its contiguous chunk with LDS
 //           atomics, keeping each slot's returned count as its rank inside
 //           (key, chunk), and writes the counts bin-major into
-//           table[bin * G + chunk];
-//   scan    exclusive prefix sum of the table (hipCUB device scan);
-//   pos     pos[i] = offset of (key, chunk) + rank; start[] from the table.
+//           table[bin * G + chunk_column(chunk)];
+//   scan    a wave per bin turns its row into offsets inside the bin and a
+//           bin total; one workgroup scans the totals into start[];
+//   pos     pos[i] = start[key] + offset of (key, chunk) + rank.
 // The order of slots inside a key follows the LDS atomics (unspecified).
 // Larger key ranges use a hipCUB radix sort of (key, slot) pairs and scatter
 // the sorted ranks back to the slots.
@@ -45,26 +46,79 @@ __global__ __launch_bounds__(kSortBlock) void bucket_rank_kernel(const uint32_t 
     if (k != kNoKey) rank[i] = atomicAdd(&cnt[k], 1u);
   }
   __syncthreads();
-  for (int64_t b = threadIdx.x; b < nbins; b += blockDim.x) table[b * G + blockIdx.x] = cnt[b];
+  const int64_t col = chunk_column(blockIdx.x, G);
+  for (int64_t b = threadIdx.x; b < nbins; b += blockDim.x) table[b * G + col] = cnt[b];
 }
 
 __global__ void bucket_pos_kernel(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ rank,
                                   int64_t N, int64_t chunk, int G, const uint32_t *__restrict__ offs,
-                                  uint32_t *__restrict__ pos) {
+                                  const int64_t *__restrict__ start, uint32_t *__restrict__ pos) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= N) return;
   const uint32_t k = keys[i];
-  pos[i] = k == kNoKey ? kNoKey : offs[(int64_t)k * G + i / chunk] + rank[i];
+  pos[i] = k == kNoKey ? kNoKey
+                       : (uint32_t)start[k] + offs[(int64_t)k * G + chunk_column(i / chunk, G)] + rank[i];
 }
 
-__global__ void bucket_start_kernel(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ table,
-                                    int64_t nbins, int G, int64_t *__restrict__ start) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b < nbins) start[b] = offs[b * G];
-  if (b == nbins) {
-    const int64_t last = nbins * G - 1;
-    start[b] = (int64_t)offs[last] + table[last];
+// Scan of the count table in two steps.  Row step: one wave per bin turns
+// its row of G chunk counts into offsets inside the bin and writes the bin's
+// total.
+constexpr int kRowMax = 16;  // counts per lane: G <= 64 * kRowMax
+__global__ __launch_bounds__(256) void count_rowscan_kernel(const uint32_t *__restrict__ table, int64_t nbins,
+                                                            int G, uint32_t *__restrict__ offs,
+                                                            uint32_t *__restrict__ rowsum) {
+  const int lane = threadIdx.x & 63;
+  const int64_t b = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  if (b >= nbins) return;  // b is the same for the whole wave
+  const int per = (G + 63) / 64, c0 = lane * per;
+  const uint32_t *row = table + b * G;
+  uint32_t v[kRowMax], sum = 0;
+#pragma unroll
+  for (int i = 0; i < kRowMax; ++i) {
+    v[i] = (i < per && c0 + i < G) ? row[c0 + i] : 0u;
+    sum += v[i];
   }
+  uint32_t incl = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t u = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += u;
+  }
+  uint32_t run = incl - sum;
+  uint32_t *orow = offs + b * G;
+#pragma unroll
+  for (int i = 0; i < kRowMax; ++i) {
+    if (i < per && c0 + i < G) orow[c0 + i] = run;
+    run += v[i];
+  }
+  if (lane == 63) rowsum[b] = incl;
+}
+
+// Bin step: one workgroup scans the bin totals into start[0 .. nbins].
+__global__ __launch_bounds__(1024) void count_binscan_kernel(const uint32_t *__restrict__ rowsum, int64_t nbins,
+                                                             int64_t *__restrict__ start) {
+  __shared__ int64_t wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t per = (nbins + 1023) / 1024, b0 = tid * per;
+  int64_t sum = 0;
+  for (int64_t i = 0; i < per; ++i)
+    if (b0 + i < nbins) sum += rowsum[b0 + i];
+  int64_t incl = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t u = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += u;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int64_t run = incl - sum;
+  for (int j = 0; j < w; ++j) run += wsum[j];
+  for (int64_t i = 0; i < per; ++i)
+    if (b0 + i < nbins) {
+      start[b0 + i] = run;
+      run += rowsum[b0 + i];
+    }
+  if (tid == 1023) start[nbins] = run;
 }
 
 // radix path: keys with kNoKey sort last (as nbins)
@@ -102,50 +156,54 @@ __device__ __forceinline__ int64_t floor_cell(double v) {
   return i;
 }
 
+// Reduction of the seven scan values {bad, min0..2, max0..2} over a
+// workgroup of 256: shuffles within each wave, then the four wave results.
+__device__ __forceinline__ void reduce_scan7(long long v[7], long long *__restrict__ dst) {
+  __shared__ long long red[4][7];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v[0] += __shfl_xor(v[0], o);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      v[1 + k] = min(v[1 + k], __shfl_xor(v[1 + k], o));
+      v[4 + k] = max(v[4 + k], __shfl_xor(v[4 + k], o));
+    }
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int t = 0; t < 7; ++t) red[w][t] = v[t];
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const int t = threadIdx.x;
+    long long r = red[0][t];
+    for (int x = 1; x < 4; ++x) r = t == 0 ? r + red[x][t] : (t < 4 ? min(r, red[x][t]) : max(r, red[x][t]));
+    dst[t] = r;
+  }
+}
+
 // out[block] = {bad, min0, min1, min2, max0, max1, max2, pad}
 __global__ __launch_bounds__(256) void packet_scan_kernel(ScanParams p, long long *__restrict__ out) {
-  __shared__ long long red[7][256];
-  long long bad = 0, mn[3], mx[3];
-  for (int k = 0; k < 3; ++k) {
-    mn[k] = LLONG_MAX;
-    mx[k] = LLONG_MIN;
-  }
+  long long v[7] = {0, LLONG_MAX, LLONG_MAX, LLONG_MAX, LLONG_MIN, LLONG_MIN, LLONG_MIN};
   const int64_t lo = blockIdx.x * p.per_block, hi = min(p.N, lo + p.per_block);
   for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
-    bool ok = isfinite(p.S[j]) && isfinite(p.a[2 * j]) && isfinite(p.a[2 * j + 1]);
+    const double2 aj = reinterpret_cast<const double2 *>(p.a)[j];
+    bool ok = isfinite(p.S[j]) && isfinite(aj.x) && isfinite(aj.y);
     for (int k = 0; k < p.d; ++k) {
       const double q = p.Q[k * p.N + j], pv = p.P[k * p.N + j];
       ok = ok && fabs(q) <= 1.0e9 && fabs(pv) <= 1.0e9;
       if (p.want_range && fabs(pv) <= 1.0e9) {
-        const int64_t c = floor_cell(pv / p.dp[k]);
-        mn[k] = min(mn[k], (long long)c);
-        mx[k] = max(mx[k], (long long)c);
+        const long long c = (long long)floor_cell(pv / p.dp[k]);
+        v[1 + k] = min(v[1 + k], c);
+        v[4 + k] = max(v[4 + k], c);
       }
     }
-    if (!ok) ++bad;
+    if (!ok) ++v[0];
   }
-  red[0][threadIdx.x] = bad;
-  for (int k = 0; k < 3; ++k) {
-    red[1 + k][threadIdx.x] = mn[k];
-    red[4 + k][threadIdx.x] = mx[k];
-  }
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + st];
-      for (int k = 0; k < 3; ++k) {
-        red[1 + k][threadIdx.x] = min(red[1 + k][threadIdx.x], red[1 + k][threadIdx.x + st]);
-        red[4 + k][threadIdx.x] = max(red[4 + k][threadIdx.x], red[4 + k][threadIdx.x + st]);
-      }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < 7) out[blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
+  reduce_scan7(v, out + blockIdx.x * 8);
 }
 
 __global__ __launch_bounds__(256) void packet_scan_final_kernel(const long long *__restrict__ part, int nb,
                                                                 long long *__restrict__ out) {
-  __shared__ long long red[7][256];
   long long v[7] = {0, LLONG_MAX, LLONG_MAX, LLONG_MAX, LLONG_MIN, LLONG_MIN, LLONG_MIN};
   for (int b = threadIdx.x; b < nb; b += blockDim.x) {
     v[0] += part[b * 8];
@@ -154,19 +212,7 @@ __global__ __launch_bounds__(256) void packet_scan_final_kernel(const long long 
       v[4 + k] = max(v[4 + k], part[b * 8 + 4 + k]);
     }
   }
-  for (int t = 0; t < 7; ++t) red[t][threadIdx.x] = v[t];
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + st];
-      for (int k = 0; k < 3; ++k) {
-        red[1 + k][threadIdx.x] = min(red[1 + k][threadIdx.x], red[1 + k][threadIdx.x + st]);
-        red[4 + k][threadIdx.x] = max(red[4 + k][threadIdx.x], red[4 + k][threadIdx.x + st]);
-      }
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < 7) out[threadIdx.x] = red[threadIdx.x][0];
+  reduce_scan7(v, out);
 }
 
 constexpr int kScanBlocks = 1024;
@@ -190,20 +236,20 @@ SortPlan sort_plan(int64_t N, int64_t nbins, int unit = 1) {
     return at;
   };
   if (sp.lds) {
-    // chunks of >= 8192 slots, at most 1024 of them, and a table of at most ~2^22 entries
-    int64_t G = std::min<int64_t>(1024, (Nn + 8191) / 8192);
+    // chunks of >= 8192 slots, at most 1024 of them (the row scan's limit),
+    // and a table of at most ~2^22 entries: every (bin, chunk) count is a
+    // separate write, so fewer, larger chunks keep the table cheap
+    int64_t G = std::min<int64_t>(64 * kRowMax, (Nn + 8191) / 8192);
     G = std::max<int64_t>(1, std::min<int64_t>(G, ((int64_t)1 << 22) / std::max<int64_t>(nbins, 1)));
+    if (G >= 8) G &= ~(int64_t)7;  // whole XCD rounds (chunk_column)
     sp.chunk = (Nn + G - 1) / G;
     sp.chunk = (sp.chunk + unit - 1) / unit * unit;  // whole packets per chunk
     sp.G = (int)((Nn + sp.chunk - 1) / sp.chunk);
     const int64_t tn = nbins * sp.G;
-    size_t tmp = 0;
-    FGGC_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp, (uint32_t *)nullptr, (uint32_t *)nullptr, (int)tn));
-    sp.tmp_bytes = tmp;
     sp.off_table = put(tn * 4);
     sp.off_offs = put(tn * 4);
     sp.off_rank = put(Nn * 4);
-    sp.off_tmp = put(tmp + 256);
+    sp.off_tmp = put(nbins * 4);  // bin totals
   } else {
     sp.bits = 1;
     while (((int64_t)1 << sp.bits) < nbins + 1) ++sp.bits;
@@ -251,25 +297,26 @@ CountPlan count_plan(int64_t N, int64_t nbins, int unit) {
   c.off_table = sp.off_table;
   c.off_offs = sp.off_offs;
   c.off_rank = sp.off_rank;
-  c.off_tmp = sp.off_tmp;
-  c.tmp_bytes = sp.tmp_bytes;
+  c.off_rowsum = sp.off_tmp;
   c.bytes = sp.total + 256;
   return c;
 }
 
-void count_positions(const CountPlan &c, const uint32_t *keys, int64_t N, char *scratch, uint32_t *pos,
-                     hipStream_t s) {
+void count_positions(const CountPlan &c, const uint32_t *keys, int64_t N, char *scratch, const int64_t *start,
+                     uint32_t *pos, hipStream_t s) {
   const uint32_t *rank = (const uint32_t *)(scratch + c.off_rank), *offs = (const uint32_t *)(scratch + c.off_offs);
-  bucket_pos_kernel<<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s>>>(keys, rank, N, c.chunk, c.G, offs, pos);
+  bucket_pos_kernel<<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s>>>(keys, rank, N, c.chunk, c.G, offs,
+                                                                            start, pos);
   FGGC_HIP(hipGetLastError());
 }
 
 void count_scan(const CountPlan &c, int64_t nbins, char *scratch, int64_t *start, hipStream_t s) {
-  uint32_t *table = (uint32_t *)(scratch + c.off_table), *offs = (uint32_t *)(scratch + c.off_offs);
-  size_t tmp = c.tmp_bytes;
-  FGGC_HIP(hipcub::DeviceScan::ExclusiveSum(scratch + c.off_tmp, tmp, table, offs, (int)(nbins * c.G), s));
-  bucket_start_kernel<<<dim3((unsigned)((nbins + 1 + 255) / 256)), dim3(256), 0, s>>>(offs, table, nbins,
-                                                                                    c.G, start);
+  uint32_t *table = (uint32_t *)(scratch + c.off_table), *offs = (uint32_t *)(scratch + c.off_offs),
+           *rowsum = (uint32_t *)(scratch + c.off_rowsum);
+  count_rowscan_kernel<<<dim3((unsigned)((nbins * 64 + 255) / 256)), dim3(256), 0, s>>>(table, nbins, c.G, offs,
+                                                                                      rowsum);
+  FGGC_HIP(hipGetLastError());
+  count_binscan_kernel<<<dim3(1), dim3(1024), 0, s>>>(rowsum, nbins, start);
   FGGC_HIP(hipGetLastError());
 }
 
@@ -303,13 +350,14 @@ void bucket_positions(const uint32_t *keys, int64_t N, int64_t nbins, uint32_t *
     } else {
       launch_zero(table, (size_t)nbins * sp.G * 4, s);
     }
-    size_t tmp = sp.tmp_bytes;
-    FGGC_HIP(hipcub::DeviceScan::ExclusiveSum(base + sp.off_tmp, tmp, table, offs, (int)(nbins * sp.G), s));
-    bucket_start_kernel<<<dim3((unsigned)((nbins + 1 + 255) / 256)), dim3(256), 0, s>>>(offs, table, nbins,
-                                                                                      sp.G, start);
+    uint32_t *rowsum = (uint32_t *)(base + sp.off_tmp);
+    count_rowscan_kernel<<<dim3((unsigned)((nbins * 64 + 255) / 256)), dim3(256), 0, s>>>(table, nbins, sp.G,
+                                                                                        offs, rowsum);
+    FGGC_HIP(hipGetLastError());
+    count_binscan_kernel<<<dim3(1), dim3(1024), 0, s>>>(rowsum, nbins, start);
     FGGC_HIP(hipGetLastError());
     if (N > 0) {
-      bucket_pos_kernel<<<dim3(gN), dim3(256), 0, s>>>(keys, rank, N, sp.chunk, sp.G, offs, pos);
+      bucket_pos_kernel<<<dim3(gN), dim3(256), 0, s>>>(keys, rank, N, sp.chunk, sp.G, offs, start, pos);
       FGGC_HIP(hipGetLastError());
     }
     return;

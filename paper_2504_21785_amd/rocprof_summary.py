@@ -28,8 +28,11 @@ STAGE_KERNELS = {
     "fggc_coef": ["fggc_coef_kernel"],
     "fggc_accum": ["fggc_agg1_kernel", "fggc_stencil1_kernel", "fggc_accum_wave_kernel",
                    "fggc_accum_kernel", "fggc_accum_generic_kernel"],
-    "fggc_sort": ["fggc_key_kernel", "bucket_rank_kernel", "bucket_pos_kernel", "bucket_start_kernel"],
+    # bucket_pos_kernel also serves the direct sum's sort; its dispatches count here
+    "fggc_sort": ["fggc_key_kernel", "fggc_rank_kernel", "count_rowscan_kernel", "count_binscan_kernel",
+                  "bucket_pos_kernel"],
     "fggc_band_mac": ["band_mac"],
+    "fggc_contract": ["fft_contract_kernel"],
     "ds_kernel": ["ds_kernel"],
 }
 
