@@ -1139,6 +1139,7 @@ struct Agg1Params {
   const char *recs;
   const int64_t *start;
   int64_t Nq, tile, ntq, npc;
+  int splits;  // workgroups per bin, each with its share of the records and its own copy of A
 };
 
 constexpr int kAggThreads = 256;
@@ -1164,11 +1165,14 @@ __global__ __launch_bounds__(kAggThreads) void fggc_agg1_kernel(Agg1Params p, T 
   __shared__ int hist[TILE], incl[TILE];
   __shared__ uint16_t perm[CH];
   const int tid = threadIdx.x;
-  const int64_t bin = blockIdx.x;
+  const int64_t bin = blockIdx.x / p.splits;
+  const int sp = (int)(blockIdx.x - bin * p.splits);
   const int64_t pc = bin / p.ntq, t = bin - pc * p.ntq;
   const int tbase = (int)(t * p.tile);
-  const int64_t r0 = p.start[bin], r1 = p.start[bin + 1];
+  const int64_t b0 = p.start[bin], nrec = p.start[bin + 1] - b0;
+  const int64_t r0 = b0 + nrec * sp / p.splits, r1 = b0 + nrec * (sp + 1) / p.splits;
   const uint4 *src = reinterpret_cast<const uint4 *>(p.recs);
+  A += (int64_t)sp * p.npc * p.Nq * N1;
   R accr[PER], acci[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) accr[i] = acci[i] = 0;
@@ -1233,6 +1237,7 @@ struct Stencil1Params {
   int64_t Nq, sn, npc;
   int n1, nq, np, mindp;
   int dq[8], dp[8];
+  int splits;  // copies of A to add
 };
 
 template <typename T>
@@ -1248,9 +1253,11 @@ __global__ void fggc_stencil1_kernel(Stencil1Params p, const T *__restrict__ A, 
     if (pc < 0 || pc >= p.npc) continue;
     for (int a = 0; a < p.nq; ++a) {
       const int64_t qs = (q - p.dq[a]) & (p.Nq - 1);
-      const T v = A[(pc * p.Nq + qs) * n1s + a * p.np + b];
-      ar += v.x;
-      ai += v.y;
+      for (int c = 0; c < p.splits; ++c) {
+        const T v = A[((c * p.npc + pc) * p.Nq + qs) * n1s + a * p.np + b];
+        ar += v.x;
+        ai += v.y;
+      }
     }
   }
   cells[e] = T{ar, ai};
@@ -1439,6 +1446,7 @@ __global__ __launch_bounds__(256) void fft_contract_kernel(ContractParams p, con
 struct FggcLayout {
   int d, N1, rec_b, ns;
   bool agg1;  // one dimension: aggregate + stencil instead of tile accumulation
+  int agg_splits;  // one dimension: workgroups (and copies of the aggregate) per bin
   int64_t ncells, nslices, npts, nbins, nslots, tiles, ntq[3], tile[3], npc[3], pmin[3], S[3], nsw[3];
   int64_t nb[3];
   int mindp, maxdp, mindq, maxdq;
@@ -1518,7 +1526,14 @@ FggcLayout fggc_layout(const FggcArgs &a) {
   L.off_sort = put(std::max(bucket_positions_bytes(L.nslots, L.nbins), count_plan(L.nslots, L.nbins, L.ns).bytes));
   L.off_start = put((size_t)(L.nbins + 1) * 8);
   L.off_recs = put((size_t)NS * L.rec_b);  // at most one record per slot
-  L.off_agg = put(L.agg1 ? (size_t)L.npc[0] * a.Nq[0] * L.N1 * es : 0);
+  // few, crowded bins (a coarse mesh) get several workgroups each, ~2048
+  // records apiece, each adding into its own copy of the aggregate
+  L.agg_splits = 1;
+  if (L.agg1) {
+    const int64_t per_bin = a.pk->N / std::max<int64_t>(L.nbins, 1);
+    L.agg_splits = (int)std::min<int64_t>(32, std::max<int64_t>(1, (per_bin + 2047) / 2048));
+  }
+  L.off_agg = put(L.agg1 ? (size_t)L.agg_splits * L.npc[0] * a.Nq[0] * L.N1 * es : 0);
   (void)N;
   L.off_cells = put((size_t)L.ncells * es);
   L.off_spec = put((size_t)L.npts * es);  // grid spectrum (the inverse FFT writes u from it)
@@ -1595,7 +1610,8 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
     gp.tile = L.tile[0];
     gp.ntq = L.ntq[0];
     gp.npc = L.npc[0];
-    const dim3 gg((unsigned)L.nbins), gb(kAggThreads);
+    gp.splits = L.agg_splits;
+    const dim3 gg((unsigned)(L.nbins * L.agg_splits)), gb(kAggThreads);
     fggc_agg1_kernel<N1, T, kAgg1Tile><<<gg, gb, 0, s>>>(gp, A);
     FGGC_HIP(hipGetLastError());
     Stencil1Params sp{};
@@ -1606,6 +1622,7 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
     sp.nq = nq;
     sp.np = np;
     sp.mindp = L.mindp;
+    sp.splits = L.agg_splits;
     for (int i = 0; i < 8; ++i) {
       sp.dq[i] = ap.dq[i];
       sp.dp[i] = ap.dp[i];

@@ -139,6 +139,19 @@ def heavy_points(ps, n_heavy, n_rand, seed):
     return np.unique(pts)
 
 
+@pytest.mark.parametrize("prec,tol", [(F.FP32, 1e-6), (F.FP64, 1e-10)])
+def test_reconstruct_1d_crowded_bins(ctx, orc, prec, tol):
+    # a coarse mesh (eps = 1/64: 128 q-cells, 4 q-tiles) with 655360 packets
+    # puts several thousand records in each bin, so that the one-dimensional
+    # aggregate splits bins over several workgroups and copies of A
+    ps = W.gen_1d(1024, 640, 1.0 / 64, 1024, seed=21)
+    pts = heavy_points(ps, 48, 16, 2)
+    u, ref = fggc_case(ctx, orc, ps, "Q4P2", prec, pts=pts)
+    e = rel(u, ref)
+    log("fggc 1d crowded bins", prec, e)
+    assert e <= tol
+
+
 @pytest.mark.parametrize("prec,name,tol", [(F.FP64, "Q2P2", 1e-12), (F.FP32, "Q4P2", 1e-6)])
 def test_reconstruct_2d_small(ctx, orc, prec, name, tol):
     ps = W.gen_mesh(2, 16, 6, 0.5, (0.5, 0.3), 1.0 / 256, 128, seed=5)
