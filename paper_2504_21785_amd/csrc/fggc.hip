@@ -535,6 +535,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 1 && N
 struct AccParams {
   const char *recs;
   const int64_t *start;
+  // two dimensions: per (slice, q-tile) emptiness; an empty tile is not
+  // written (null: every tile is written)
+  uint8_t *empty;
   int64_t sn[3], npc[3], Nq[3], tile[3], ntq[3], S[3], nsw[3];
   int nq, np;
   int dq[8], dp[8];
@@ -998,6 +1001,7 @@ __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__r
   if (!any) npcs = 0;
   const int tile1 = D > 1 ? (int)p.tile[1] : 1;
   __syncthreads();
+  bool any_rec = false;
   for (int64_t bb = 0; bb < npcs; bb += kMaxBinsPerPass) {
     const int nb = (int)min<int64_t>(kMaxBinsPerPass, npcs - bb);
     for (int t = lane; t < nb; t += 64) {
@@ -1018,6 +1022,7 @@ __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__r
     }
     __syncthreads();
     const int64_t total = s_pre[nb];
+    any_rec = any_rec || total > 0;
     for (int64_t base = 0; base < total; base += 64) {
       const int64_t i = base + lane;
       const bool valid = i < total;
@@ -1109,6 +1114,10 @@ __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__r
   }
   int64_t slf = 0;
   for (int k = 0; k < D; ++k) slf = slf * p.sn[k] + sl[k];
+  if (p.empty) {  // an empty tile is only marked (the finish reads it as zeros)
+    if (lane == 0) p.empty[slf * nqt_all + tflat] = any_rec ? 0 : 1;
+    if (!any_rec) return;
+  }
   T *dst = cells + slf * ncell_q;
   for (int e = lane; e < tq_cells; e += 64) {
     int rem = e, q = 0, lqv[3] = {0, 0, 0};
@@ -1342,9 +1351,17 @@ struct ContractParams {
   int64_t kmin, kmax;  // union of the slices' bands (grid frequencies before aliasing)
   int64_t slo;
   double eps, dp, cK;
+  // two dimensions, pass over the cells: per (slice, q-tile) emptiness; an
+  // empty tile was not written and reads as zeros (null: read everything)
+  const uint8_t *empty;
+  int64_t ntq0, ntq1;
+  int lgt0, lgt1;  // log2 of the q-tile sizes
 };
 
-constexpr int kContractOut = 8;  // outputs per thread (256 threads, 2048 per workgroup)
+constexpr int kContractThreads = 512;
+constexpr int kContractBfly = 4;  // butterflies per thread and FFT pass
+constexpr int kContractOut = 4;   // outputs per thread (2048 per workgroup)
+constexpr int kContractFlags = 4096;  // (row, q-tile) emptiness flags of one chunk (<= 4096 / tile)
 
 // One pass of the separable finish over dimension k of the cell array (or of
 // the previous pass's output), viewed as X[O][L][A][N][B]:
@@ -1356,10 +1373,11 @@ constexpr int kContractOut = 8;  // outputs per thread (256 threads, 2048 per wo
 // adds each slice's band into per-thread FP64 sums of its outputs; gamma is
 // evaluated in place.  Frequencies no band reaches are written as zeros.
 template <typename T, typename R>
-__global__ __launch_bounds__(256) void fft_contract_kernel(ContractParams p, const T *__restrict__ X,
+__global__ __launch_bounds__(kContractThreads) void fft_contract_kernel(ContractParams p, const T *__restrict__ X,
                                                            T *__restrict__ Y, const T *__restrict__ tw) {
   using RR = decltype(T{}.x);
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ uint8_t s_empty[kContractFlags];
   T *sm = reinterpret_cast<T *>(smem_raw);
   const int lgN = p.lgN, N = 1 << lgN, WA = 1 << p.lgWA, W = 1 << p.lgW, P = WA * W;
   const int M = (int)p.M;
@@ -1387,14 +1405,31 @@ __global__ __launch_bounds__(256) void fft_contract_kernel(ContractParams p, con
     const int lcn = min(p.Lc, (int)p.L - lc0);
     // rows [l][wa][w] of N, loaded with b fastest, then n, then a
     const int tot = lcn * P * N;
+    if (p.empty) {
+      // the chunk's (row, q1-tile) emptiness into LDS (rows [l][wa]; one b),
+      // and a chunk of empty tiles adds nothing: skip it
+      const int nf = lcn * WA * (int)p.ntq1;
+      int any = 0;
+      for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+        const int t1 = f % (int)p.ntq1, r = f / (int)p.ntq1;
+        const int wa = r & (WA - 1), l = r >> p.lgWA;
+        const int64_t slf = o * p.L + lc0 + l;  // cells of [slice][q0 = a][q1 = n]
+        const uint8_t e = p.empty[(slf * p.ntq0 + ((a0 + wa) >> p.lgt0)) * p.ntq1 + t1];
+        s_empty[f] = e;
+        any |= e == 0;
+      }
+      if (!__syncthreads_or(any)) continue;
+    }
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
       const int w = e & (W - 1), n = (e >> p.lgW) & (N - 1), rest = e >> (p.lgW + lgN);
       const int wa = rest & (WA - 1), l = rest >> p.lgWA;
       const int row = (((l << p.lgWA) + wa) << p.lgW) + w;
-      sm[(row << lgN) + n] = X[((((o * p.L + lc0 + l) * p.A + a0 + wa) << lgN) + n) * p.B + b0 + w];
+      const bool full = !p.empty || !s_empty[((l << p.lgWA) + wa) * (int)p.ntq1 + (n >> p.lgt1)];
+      sm[(row << lgN) + n] =
+          full ? X[((((o * p.L + lc0 + l) * p.A + a0 + wa) << lgN) + n) * p.B + b0 + w] : T{0, 0};
     }
     __syncthreads();
-    lds_fft_rows<T>(sm, lgN, lcn * P, N, 0, tw);
+    lds_fft_rows<T, kContractBfly>(sm, lgN, lcn * P, N, 0, tw);
 #pragma unroll
     for (int c = 0; c < kContractOut; ++c) {
       const int e = threadIdx.x + c * (int)blockDim.x;
@@ -1450,7 +1485,7 @@ struct FggcLayout {
   int64_t ncells, nslices, npts, nbins, nslots, tiles, ntq[3], tile[3], npc[3], pmin[3], S[3], nsw[3];
   int64_t nb[3];
   int mindp, maxdp, mindq, maxdq;
-  size_t off_lsq, off_keys, off_pos, off_sort, off_start, off_recs, off_agg, off_cells,
+  size_t off_lsq, off_keys, off_pos, off_sort, off_start, off_recs, off_agg, off_cells, off_occ,
       off_spec, off_x1, off_x2, total;
 };
 
@@ -1536,6 +1571,9 @@ FggcLayout fggc_layout(const FggcArgs &a) {
   L.off_agg = put(L.agg1 ? (size_t)L.agg_splits * L.npc[0] * a.Nq[0] * L.N1 * es : 0);
   (void)N;
   L.off_cells = put((size_t)L.ncells * es);
+  // after the cells: the cells-only entry point (whose cells are the
+  // caller's) writes every tile and takes no occupancy map
+  L.off_occ = put(d == 2 ? (size_t)L.nslices * L.ntq[0] * L.ntq[1] : 0);  // empty-tile map
   L.off_spec = put((size_t)L.npts * es);  // grid spectrum (the inverse FFT writes u from it)
   // separable finish (d >= 2): outputs of the passes over the last and the
   // middle dimension, [l_<k][i_<k][grid frequencies of dims >= k]
@@ -1557,7 +1595,7 @@ FggcLayout fggc_layout(const FggcArgs &a) {
 template <int D, int N1, typename T>
 void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams &cp,
                        const uint32_t *pos, char *recs, const int64_t *start, void *agg, T *cells,
-                       hipStream_t s) {
+                       uint8_t *occ, hipStream_t s) {
   const DimLsq &c0 = a.lsq[0];
   int cnp = 0;
   for (int m = 0; m < c0.n1; ++m)
@@ -1576,6 +1614,7 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
   AccParams ap{};
   ap.recs = recs;
   ap.start = start;
+  ap.empty = nullptr;
   const DimLsq &l0 = a.lsq[0];
   for (int k = 0; k < 3; ++k) {
     ap.sn[k] = a.sn[k];
@@ -1638,7 +1677,12 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
   if (shm > 65536) fail(FGGC_EUNSUPPORTED, "accumulation tile exceeds 64 KB of LDS");
   StageScope sc(a.prof, "fggc_accum", s);
   const dim3 grid((unsigned)L.tiles), blk(256);
-  const bool wave = D <= 2 && L.S[0] == 1 && (D < 2 || L.S[1] == 1);
+  const bool wave = D <= 2 && L.S[0] == 1 && (D < 2 || L.S[1] == 1) && N1 == nq * np &&
+                    ((nq == 2 && np == 2) || (nq == 4 && np == 2) || (nq == 2 && np == 4) || (nq == 4 && np == 4));
+  if (D == 2 && occ) {
+    if (wave) ap.empty = occ;  // the one-wave kernel marks every (slice, tile)
+    else launch_zero(occ, (size_t)L.nslices * L.ntq[0] * L.ntq[1], s);  // no tile is skipped
+  }
   if (wave) {
     const size_t wshm = (size_t)(tc)*sizeof(T);
     const dim3 wblk(64);
@@ -1681,7 +1725,8 @@ std::mutex g_rank_mu;
 
 // bin the packets' key slots, compute their coefficients into bin order, and fill
 // the cell array of eq. (2.25) (every cell written once)
-void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells, hipStream_t s) {
+void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells, uint8_t *occ,
+                 hipStream_t s) {
   const int d = a.g.d;
   const bool f64 = a.precision == FGGC_FP64;
   const DimLsq *dlsq = a.lsq_dev;
@@ -1767,8 +1812,8 @@ void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells
     cp.dp[k] = a.dp[k];
   }
 #define FGGC_CA(DD, NN)                                                                           \
-  if (f64) launch_coef_accum<DD, NN, double2>(a, L, cp, pos, recs, start, base + L.off_agg, (double2 *)cells, s); \
-  else launch_coef_accum<DD, NN, float2>(a, L, cp, pos, recs, start, base + L.off_agg, (float2 *)cells, s);
+  if (f64) launch_coef_accum<DD, NN, double2>(a, L, cp, pos, recs, start, base + L.off_agg, (double2 *)cells, occ, s); \
+  else launch_coef_accum<DD, NN, float2>(a, L, cp, pos, recs, start, base + L.off_agg, (float2 *)cells, occ, s);
   if (d == 1) {
     if (L.N1 == 4) { FGGC_CA(1, 4) } else if (L.N1 == 8) { FGGC_CA(1, 8) } else { FGGC_CA(1, 16) }
   } else if (d == 2) {
@@ -1785,7 +1830,8 @@ std::mutex g_contract_mu;
 
 // One separable pass over dimension k (see fft_contract_kernel).
 template <typename T, typename R>
-void launch_contract(const FggcArgs &a, int k, const T *in, T *out, const MacParams &m, hipStream_t s) {
+void launch_contract(const FggcArgs &a, const FggcLayout &L, int k, const T *in, T *out, const uint8_t *occ,
+                     const MacParams &m, hipStream_t s) {
   {
     std::lock_guard<std::mutex> lk(g_contract_mu);
     if (!g_contract_attr) {
@@ -1815,27 +1861,28 @@ void launch_contract(const FggcArgs &a, int k, const T *in, T *out, const MacPar
   // lines per workgroup: runs of up to 4 consecutive b (contiguous in memory),
   // or, when b is a single line, up to 16 consecutive a (whole rows of N);
   // a chunk holds at most 4096 elements (the butterfly budget of
-  // lds_fft_rows for 256 threads, counting the radix-2 pass of an odd log2 N)
-  constexpr int64_t kElems = 256 * kMaxBfly * 2;
+  // lds_fft_rows for kContractThreads threads, counting the radix-2 pass of
+  // an odd log2 N)
+  constexpr int64_t kElems = kContractThreads * kContractBfly * 2;
   if (N > kElems) fail(FGGC_EUNSUPPORTED, "q-mesh too long for the separable finish");
   int lgW = 0, lgWA = 0;
   while ((2 << lgW) <= std::min<int64_t>(4, p.B) && (N << (lgW + 1)) <= kElems) ++lgW;
   if (p.B == 1)
     while ((2 << lgWA) <= std::min<int64_t>(16, p.A) && (N << (lgWA + 1)) <= 1024 &&
-           (p.M << (lgWA + 1)) <= 256 * kContractOut)
+           (p.M << (lgWA + 1)) <= kContractThreads * kContractOut)
       ++lgWA;
   p.lgW = lgW;
   p.lgWA = lgWA;
   const int64_t P = (int64_t)1 << (lgW + lgWA);
   if (p.B % (1 << lgW) || p.A % (1 << lgWA)) fail(FGGC_EUNSUPPORTED, "separable finish: uneven line packing");
   p.Lc = (int)std::max<int64_t>(1, std::min<int64_t>(p.L, kElems / (N * P)));
-  // frequencies split over MS workgroups: at most 256 * kContractOut outputs
+  // frequencies split over MS workgroups: at most 2048 outputs
   // each, and more splits (each redoing the group's DFTs) when there are
   // few line groups
   const int64_t groups = p.O * (p.A / (1 << lgWA)) * (p.B / (1 << lgW));
   int MS = 1;
-  while ((p.M / MS) * P > 256 * kContractOut) MS *= 2;
-  while (groups * MS < 1024 && MS * 2 <= 16 && (p.M / (MS * 2)) * P >= 256) MS *= 2;
+  while ((p.M / MS) * P > kContractThreads * kContractOut) MS *= 2;
+  while (groups * MS < 1024 && MS * 2 <= 16 && (p.M / (MS * 2)) * P >= kContractThreads) MS *= 2;
   if (p.M % MS) fail(FGGC_EUNSUPPORTED, "separable finish: uneven frequency split");
   p.MS = MS;
   p.kmin = m.kmin[k];
@@ -1844,17 +1891,27 @@ void launch_contract(const FggcArgs &a, int k, const T *in, T *out, const MacPar
   p.eps = a.eps;
   p.dp = a.dp[k];
   p.cK = a.cK;
+  p.empty = (d == 2 && k == 1) ? occ : nullptr;
+  // a chunk holds at most 4096 / N rows of N / tile q1-tiles (the accumulate
+  // has already skipped the empty tiles, so the map must be honoured)
+  if (p.empty && (int64_t)p.Lc * (1 << lgWA) * L.ntq[1] > kContractFlags)
+    fail(FGGC_EUNSUPPORTED, "separable finish: too many tile flags per chunk");
+  p.ntq0 = L.ntq[0];
+  p.ntq1 = L.ntq[1];
+  p.lgt0 = p.lgt1 = 0;
+  while (((int64_t)1 << p.lgt0) < L.tile[0]) ++p.lgt0;
+  while (((int64_t)1 << p.lgt1) < L.tile[1]) ++p.lgt1;
   const size_t shm = (size_t)p.Lc * N * P * sizeof(T) + 16;
   const int64_t blocks = groups * MS;
   if (blocks >= ((int64_t)1 << 31)) fail(FGGC_EUNSUPPORTED, "too many workgroups for the separable finish");
   const T *tw = (const T *)fft_twiddles(N, a.precision);
-  fft_contract_kernel<T, R><<<dim3((unsigned)blocks), dim3(256), shm, s>>>(p, in, out, tw);
+  fft_contract_kernel<T, R><<<dim3((unsigned)blocks), dim3(kContractThreads), shm, s>>>(p, in, out, tw);
   FGGC_HIP(hipGetLastError());
 }
 
 template <typename T, typename R>
-void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, void *spec, Workspace &ws,
-                  hipStream_t s) {
+void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, const uint8_t *occ,
+                  void *spec, Workspace &ws, hipStream_t s) {
   const int d = a.g.d;
   const int prec = a.precision;
   // F5: forward DFT over q of every p-slice (one dimension; higher dimensions
@@ -1886,7 +1943,7 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, 
     const T *in = cells;
     for (int k = d - 1; k >= 0; --k) {
       T *out = k == 0 ? U : (k == d - 1 ? x1 : x2);
-      launch_contract<T, R>(a, k, in, out, m, s);
+      launch_contract<T, R>(a, L, k, in, out, k == d - 1 ? occ : nullptr, m, s);
       in = out;
     }
   } else {
@@ -1915,18 +1972,19 @@ size_t fggc_cells_workspace_bytes(const FggcArgs &a) {
 void launch_fggc_cells(const FggcArgs &a, void *cells, Workspace &ws, hipStream_t s) {
   FggcLayout L = fggc_layout(a);
   char *base = (char *)ws.take(L.off_cells);
-  cells_stage(a, L, base, cells, s);
+  cells_stage(a, L, base, cells, nullptr, s);
 }
 
 void launch_fggc(const FggcArgs &a, Workspace &ws, hipStream_t s) {
   FggcLayout L = fggc_layout(a);
   char *base = (char *)ws.take(L.total);
   void *cells = base + L.off_cells;
-  cells_stage(a, L, base, cells, s);
+  uint8_t *occ = a.g.d == 2 ? (uint8_t *)(base + L.off_occ) : nullptr;
+  cells_stage(a, L, base, cells, occ, s);
   if (a.precision == FGGC_FP64)
-    finish_stage<double2, double>(a, L, base, (double2 *)cells, base + L.off_spec, ws, s);
+    finish_stage<double2, double>(a, L, base, (double2 *)cells, occ, base + L.off_spec, ws, s);
   else
-    finish_stage<float2, float>(a, L, base, (float2 *)cells, base + L.off_spec, ws, s);
+    finish_stage<float2, float>(a, L, base, (float2 *)cells, occ, base + L.off_spec, ws, s);
 }
 
 }  // namespace fggc

@@ -17,9 +17,10 @@ template <typename T> __device__ __forceinline__ T csub(T a, T b) { return T{a.x
 
 constexpr int kMaxBfly = 8;  // radix-4 butterflies per thread per pass
 
-// Rows: nrows * 2^(lg-2) <= blockDim * kMaxBfly is required (radix-4 passes).
+// Rows: nrows * 2^(lg-2) <= blockDim * MB is required (radix-4 passes), and
+// nrows * 2^(lg-1) <= blockDim * MB when lg is odd (the radix-2 pass).
 // tw[k] = exp(-2 pi i k / n); inverse = 1 conjugates the twiddles.
-template <typename T>
+template <typename T, int MB = kMaxBfly>
 __device__ __forceinline__ void lds_fft_rows(T *sm, int lg, int nrows, int rowstride, int inverse,
                                              const T *__restrict__ tw) {
   int lgNs = 0;
@@ -30,9 +31,9 @@ __device__ __forceinline__ void lds_fft_rows(T *sm, int lg, int nrows, int rowst
     const int stride = 1 << lgstride, Ns = 1 << lgNs;
     const int nb = nrows << lgstride;  // butterflies in this pass
     const int tshift = lg - lgNs - lgR;
-    T v[kMaxBfly][4];
+    T v[MB][4];
 #pragma unroll
-    for (int c = 0; c < kMaxBfly; ++c) {
+    for (int c = 0; c < MB; ++c) {
       const int b = threadIdx.x + c * (int)blockDim.x;
       if (b >= nb) break;
       const int l = b >> lgstride, j = b & (stride - 1);
@@ -69,7 +70,7 @@ __device__ __forceinline__ void lds_fft_rows(T *sm, int lg, int nrows, int rowst
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < kMaxBfly; ++c) {
+    for (int c = 0; c < MB; ++c) {
       const int b = threadIdx.x + c * (int)blockDim.x;
       if (b >= nb) break;
       const int l = b >> lgstride, j = b & (stride - 1);

@@ -182,22 +182,44 @@ __device__ __forceinline__ void reduce_scan7(long long v[7], long long *__restri
 }
 
 // out[block] = {bad, min0, min1, min2, max0, max1, max2, pad}
+template <int D>
 __global__ __launch_bounds__(256) void packet_scan_kernel(ScanParams p, long long *__restrict__ out) {
   long long v[7] = {0, LLONG_MAX, LLONG_MAX, LLONG_MAX, LLONG_MIN, LLONG_MIN, LLONG_MIN};
   const int64_t lo = blockIdx.x * p.per_block, hi = min(p.N, lo + p.per_block);
-  for (int64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
-    const double2 aj = reinterpret_cast<const double2 *>(p.a)[j];
-    bool ok = isfinite(p.S[j]) && isfinite(aj.x) && isfinite(aj.y);
-    for (int k = 0; k < p.d; ++k) {
-      const double q = p.Q[k * p.N + j], pv = p.P[k * p.N + j];
-      ok = ok && fabs(q) <= 1.0e9 && fabs(pv) <= 1.0e9;
-      if (p.want_range && fabs(pv) <= 1.0e9) {
-        const long long c = (long long)floor_cell(pv / p.dp[k]);
-        v[1 + k] = min(v[1 + k], c);
-        v[4 + k] = max(v[4 + k], c);
+  // U packets per thread and pass, so that their loads are in flight together
+  constexpr int U = 4;
+  for (int64_t j0 = lo + threadIdx.x; j0 < hi; j0 += U * (int64_t)blockDim.x) {
+    double sv[U], ar[U], ai[U], qv[U][D], pv[U][D];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + u * (int64_t)blockDim.x;
+      if (j >= hi) break;
+      const double2 aj = reinterpret_cast<const double2 *>(p.a)[j];
+      sv[u] = p.S[j];
+      ar[u] = aj.x;
+      ai[u] = aj.y;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        qv[u][k] = p.Q[k * p.N + j];
+        pv[u][k] = p.P[k * p.N + j];
       }
     }
-    if (!ok) ++v[0];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + u * (int64_t)blockDim.x;
+      if (j >= hi) break;
+      bool ok = isfinite(sv[u]) && isfinite(ar[u]) && isfinite(ai[u]);
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        ok = ok && fabs(qv[u][k]) <= 1.0e9 && fabs(pv[u][k]) <= 1.0e9;
+        if (p.want_range && fabs(pv[u][k]) <= 1.0e9) {
+          const long long c = (long long)floor_cell(pv[u][k] / p.dp[k]);
+          v[1 + k] = min(v[1 + k], c);
+          v[4 + k] = max(v[4 + k], c);
+        }
+      }
+      if (!ok) ++v[0];
+    }
   }
   reduce_scan7(v, out + blockIdx.x * 8);
 }
@@ -431,7 +453,9 @@ void launch_packet_scan(const fggc_packets &pk, const double *dp, long long *par
   const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kScanBlocks, (pk.N + 1023) / 1024));
   p.per_block = (pk.N + nb - 1) / nb;
   if (p.per_block < 1) p.per_block = 1;
-  packet_scan_kernel<<<dim3(nb), dim3(256), 0, s>>>(p, part);
+  if (pk.d == 1) packet_scan_kernel<1><<<dim3(nb), dim3(256), 0, s>>>(p, part);
+  else if (pk.d == 2) packet_scan_kernel<2><<<dim3(nb), dim3(256), 0, s>>>(p, part);
+  else packet_scan_kernel<3><<<dim3(nb), dim3(256), 0, s>>>(p, part);
   FGGC_HIP(hipGetLastError());
   packet_scan_final_kernel<<<dim3(1), dim3(256), 0, s>>>(part, nb, out);
   FGGC_HIP(hipGetLastError());
