@@ -188,6 +188,28 @@ __device__ __forceinline__ void row_fence(double &xr, double &xi) {
   asm volatile("" : "+v"(xr), "+v"(xi)::"memory");
 }
 
+// exp(i th) for |th| <= 0.5 from the Taylor series of cos and sin (through
+// th^14 and th^15; the first omitted terms are below 3e-18 and 2e-19)
+__device__ __forceinline__ void cis_small(double th, double &c, double &s) {
+  const double x = th * th;
+  double pc = 1.0 / 87178291200.0;           // 1/14!
+  pc = fma(pc, -x, 1.0 / 479001600.0);       // 1/12!
+  pc = fma(pc, -x, 1.0 / 3628800.0);         // 1/10!
+  pc = fma(pc, -x, 1.0 / 40320.0);           // 1/8!
+  pc = fma(pc, -x, 1.0 / 720.0);             // 1/6!
+  pc = fma(pc, -x, 1.0 / 24.0);              // 1/4!
+  pc = fma(pc, -x, 0.5);                     // 1/2!
+  c = fma(pc, -x, 1.0);
+  double ps = 1.0 / 1307674368000.0;         // 1/15!
+  ps = fma(ps, -x, 1.0 / 6227020800.0);      // 1/13!
+  ps = fma(ps, -x, 1.0 / 39916800.0);        // 1/11!
+  ps = fma(ps, -x, 1.0 / 362880.0);          // 1/9!
+  ps = fma(ps, -x, 1.0 / 5040.0);            // 1/7!
+  ps = fma(ps, -x, 1.0 / 120.0);             // 1/5!
+  ps = fma(ps, -x, 1.0 / 6.0);               // 1/3!
+  s = th * fma(ps, -x, 1.0);
+}
+
 // z^n for a small whole n >= 0 (uniform across the wave)
 __device__ __forceinline__ void cpow(double zr, double zi, int n, double &pr, double &pi) {
   double xr = 1.0, xi = 0.0;
@@ -209,12 +231,16 @@ __device__ __forceinline__ void dim_coeffs_exact(const DimLsq &L, double s, doub
   constexpr double inv2pi = 1.0 / kTwoPi;
   double uqr, uqi, upr, upi, fir, fii;
   {
+    // the angles CC t / 2 and CC s / 2 stay below CC / 2 (s, t in [0, 1))
+    const bool small = CC <= 1.0;
     double c, sn;
-    cis_rev(-0.5 * CC * t * inv2pi, c, sn);
+    if (small) cis_small(-0.5 * CC * t, c, sn);
+    else cis_rev(-0.5 * CC * t * inv2pi, c, sn);
     const double m = exp(-0.5 * Cq * Cq * ((double)L.dq0 - s));
     uqr = m * c;
     uqi = m * sn;
-    cis_rev(0.5 * CC * s * inv2pi, c, sn);
+    if (small) cis_small(0.5 * CC * s, c, sn);
+    else cis_rev(0.5 * CC * s * inv2pi, c, sn);
     const double mp = exp(-0.5 * Cp * Cp * ((double)L.dp0 - t));
     upr = mp * c;
     upi = mp * sn;
@@ -1250,12 +1276,9 @@ struct Stencil1Params {
 };
 
 template <typename T>
-__global__ void fggc_stencil1_kernel(Stencil1Params p, const T *__restrict__ A, int n1s,
-                                     T *__restrict__ cells) {
+__device__ __forceinline__ T stencil1_cell(const Stencil1Params &p, const T *__restrict__ A, int n1s,
+                                           int64_t sl, int64_t q) {
   using R = decltype(T{}.x);
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= p.sn * p.Nq) return;
-  const int64_t sl = e / p.Nq, q = e - sl * p.Nq;
   R ar = 0, ai = 0;
   for (int b = 0; b < p.np; ++b) {
     const int64_t pc = sl + p.mindp - p.dp[b];
@@ -1269,7 +1292,34 @@ __global__ void fggc_stencil1_kernel(Stencil1Params p, const T *__restrict__ A, 
       }
     }
   }
-  cells[e] = T{ar, ai};
+  return T{ar, ai};
+}
+
+template <typename T>
+__global__ void fggc_stencil1_kernel(Stencil1Params p, const T *__restrict__ A, int n1s,
+                                     T *__restrict__ cells) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= p.sn * p.Nq) return;
+  const int64_t sl = e / p.Nq;
+  cells[e] = stencil1_cell(p, A, n1s, sl, e - sl * p.Nq);
+}
+
+// The stencil and the forward DFT over q of one slice per workgroup (eq. 2.25,
+// then the first step of the Fourier finish): the slice's cells are built in
+// LDS, transformed there and written once as their spectrum.
+template <typename T>
+__global__ __launch_bounds__(256) void fggc_stencil_fft1_kernel(Stencil1Params p, const T *__restrict__ A,
+                                                                int n1s, int lgN, const T *__restrict__ tw,
+                                                                T *__restrict__ spec) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *row = reinterpret_cast<T *>(smem_raw);
+  const int64_t sl = blockIdx.x;
+  const int N = 1 << lgN;
+  for (int q = threadIdx.x; q < N; q += blockDim.x) row[q] = stencil1_cell(p, A, n1s, sl, q);
+  __syncthreads();
+  lds_fft_rows<T>(row, lgN, 1, N, 0, tw);
+  T *dst = spec + sl * N;
+  for (int q = threadIdx.x; q < N; q += blockDim.x) dst[q] = row[q];
 }
 
 // First frequency of slice l's band, and gamma at frequency k (0 outside the
@@ -1478,6 +1528,10 @@ __global__ __launch_bounds__(kContractThreads) void fft_contract_kernel(Contract
   }
 }
 
+// One dimension: the aggregate's stencil writes each slice's q-spectrum
+// directly (fggc_stencil_fft1_kernel, one slice per workgroup in LDS).
+bool fft1_fused(const FggcArgs &a) { return a.g.d == 1 && a.Nq[0] <= 4096; }
+
 struct FggcLayout {
   int d, N1, rec_b, ns;
   bool agg1;  // one dimension: aggregate + stencil instead of tile accumulation
@@ -1595,7 +1649,7 @@ FggcLayout fggc_layout(const FggcArgs &a) {
 template <int D, int N1, typename T>
 void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams &cp,
                        const uint32_t *pos, char *recs, const int64_t *start, void *agg, T *cells,
-                       uint8_t *occ, hipStream_t s) {
+                       uint8_t *occ, bool spectra, hipStream_t s) {
   const DimLsq &c0 = a.lsq[0];
   int cnp = 0;
   for (int m = 0; m < c0.n1; ++m)
@@ -1667,7 +1721,17 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
       sp.dp[i] = ap.dp[i];
     }
     const int64_t ncl = a.sn[0] * a.Nq[0];
-    fggc_stencil1_kernel<T><<<dim3((unsigned)((ncl + 255) / 256)), dim3(256), 0, s>>>(sp, A, N1, cells);
+    if (spectra && fft1_fused(a)) {
+      // cells straight into their q-spectra (the finish skips its q-DFT)
+      int lgN = 0;
+      while (((int64_t)1 << lgN) < a.Nq[0]) ++lgN;
+      // 256 threads: N <= 4096 keeps the FFT within 8 butterflies per thread
+      const T *tw = (const T *)fft_twiddles(a.Nq[0], a.precision);
+      fggc_stencil_fft1_kernel<T><<<dim3((unsigned)a.sn[0]), dim3(256), a.Nq[0] * sizeof(T), s>>>(sp, A, N1, lgN,
+                                                                                                 tw, cells);
+    } else {
+      fggc_stencil1_kernel<T><<<dim3((unsigned)((ncl + 255) / 256)), dim3(256), 0, s>>>(sp, A, N1, cells);
+    }
     FGGC_HIP(hipGetLastError());
     return;
   }
@@ -1726,7 +1790,7 @@ std::mutex g_rank_mu;
 // bin the packets' key slots, compute their coefficients into bin order, and fill
 // the cell array of eq. (2.25) (every cell written once)
 void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells, uint8_t *occ,
-                 hipStream_t s) {
+                 bool spectra, hipStream_t s) {
   const int d = a.g.d;
   const bool f64 = a.precision == FGGC_FP64;
   const DimLsq *dlsq = a.lsq_dev;
@@ -1812,8 +1876,8 @@ void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells
     cp.dp[k] = a.dp[k];
   }
 #define FGGC_CA(DD, NN)                                                                           \
-  if (f64) launch_coef_accum<DD, NN, double2>(a, L, cp, pos, recs, start, base + L.off_agg, (double2 *)cells, occ, s); \
-  else launch_coef_accum<DD, NN, float2>(a, L, cp, pos, recs, start, base + L.off_agg, (float2 *)cells, occ, s);
+  if (f64) launch_coef_accum<DD, NN, double2>(a, L, cp, pos, recs, start, base + L.off_agg, (double2 *)cells, occ, spectra, s); \
+  else launch_coef_accum<DD, NN, float2>(a, L, cp, pos, recs, start, base + L.off_agg, (float2 *)cells, occ, spectra, s);
   if (d == 1) {
     if (L.N1 == 4) { FGGC_CA(1, 4) } else if (L.N1 == 8) { FGGC_CA(1, 8) } else { FGGC_CA(1, 16) }
   } else if (d == 2) {
@@ -1916,7 +1980,7 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, 
   const int prec = a.precision;
   // F5: forward DFT over q of every p-slice (one dimension; higher dimensions
   // fold the DFT into the separable passes below)
-  if (d == 1) launch_fft(d, a.Nq, L.nslices, -1, prec, cells, ws, s, a.prof, "fggc_fft_q");
+  if (d == 1 && !fft1_fused(a)) launch_fft(d, a.Nq, L.nslices, -1, prec, cells, ws, s, a.prof, "fggc_fft_q");
   // F6: band multiply-accumulate into the grid spectrum (gamma evaluated in place)
   MacParams m{};
   const double se = std::sqrt(a.eps);
@@ -1972,7 +2036,7 @@ size_t fggc_cells_workspace_bytes(const FggcArgs &a) {
 void launch_fggc_cells(const FggcArgs &a, void *cells, Workspace &ws, hipStream_t s) {
   FggcLayout L = fggc_layout(a);
   char *base = (char *)ws.take(L.off_cells);
-  cells_stage(a, L, base, cells, nullptr, s);
+  cells_stage(a, L, base, cells, nullptr, false, s);
 }
 
 void launch_fggc(const FggcArgs &a, Workspace &ws, hipStream_t s) {
@@ -1980,7 +2044,7 @@ void launch_fggc(const FggcArgs &a, Workspace &ws, hipStream_t s) {
   char *base = (char *)ws.take(L.total);
   void *cells = base + L.off_cells;
   uint8_t *occ = a.g.d == 2 ? (uint8_t *)(base + L.off_occ) : nullptr;
-  cells_stage(a, L, base, cells, occ, s);
+  cells_stage(a, L, base, cells, occ, true, s);
   if (a.precision == FGGC_FP64)
     finish_stage<double2, double>(a, L, base, (double2 *)cells, occ, base + L.off_spec, ws, s);
   else
