@@ -139,6 +139,27 @@ def heavy_points(ps, n_heavy, n_rand, seed):
     return np.unique(pts)
 
 
+def test_reconstruct_1d_wide_shifts(ctx, orc):
+    # a coarse strategy with Cq Cp > 1 (Nq = 32 and dp = 2 sqrt(eps) at
+    # eps = 1/64): the right-hand side's phases take the general path of the
+    # coefficient kernel instead of the small-angle series
+    ps = small_1d(13, N=3000)
+    eps = ps.eps
+    cq = 2 * math.pi / 32 / math.sqrt(eps)
+    cp = 2.0
+    assert cq * cp > 1.0
+    st = F.make_strategy(1, [32], [cp * math.sqrt(eps)], [0, 1], [0, 1])
+    u = ctx.reconstruct(t(ps.Q), t(ps.P), t(ps.S), t(ps.a), eps, ps.M, st, precision=F.FP64)
+    torch.cuda.synchronize()
+    u = u.cpu().numpy().reshape(-1)
+    sd = st.describe()
+    ref = orc.fggc(ps.Q, ps.P, ps.S, ps.a, eps, ps.M, sd["Nq"][:1], sd["dp"][:1], sd["dq_off"],
+                   sd["dp_off"])
+    e = rel(u, ref)
+    log("fggc 1d wide shifts (Cq Cp = %.2f)" % (cq * cp), e)
+    assert e <= 1e-12
+
+
 @pytest.mark.parametrize("prec,tol", [(F.FP32, 1e-6), (F.FP64, 1e-10)])
 def test_reconstruct_1d_crowded_bins(ctx, orc, prec, tol):
     # a coarse mesh (eps = 1/64: 128 q-cells, 4 q-tiles) with 655360 packets
