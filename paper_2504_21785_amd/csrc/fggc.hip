@@ -972,7 +972,7 @@ __global__ __launch_bounds__(256) void fggc_accum_kernel(AccParams p, T *__restr
   }
 }
 
-// Accumulation without atomics (d = 1, 2): one wave per (slice, q-tile); the
+// Accumulation without atomics (d = 2, 3): one wave per (slice, q-tile); the
 // tile lives in LDS as interleaved complex values and is updated with plain
 // read-modify-writes.  Two lanes can hit the same cell in one instruction only
 // when their records share (p-cell, q-cell); before adding, lanes claim an LDS
@@ -1025,7 +1025,7 @@ __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__r
   int64_t npcs = 1;
   for (int k = 0; k < D; ++k) npcs *= pcn[k];
   if (!any) npcs = 0;
-  const int tile1 = D > 1 ? (int)p.tile[1] : 1;
+  const int tile1 = D > 1 ? (int)p.tile[1] : 1, tile2 = D > 2 ? (int)p.tile[2] : 1;
   __syncthreads();
   bool any_rec = false;
   for (int64_t bb = 0; bb < npcs; bb += kMaxBinsPerPass) {
@@ -1109,7 +1109,7 @@ __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__r
                 tile[lq[0][a]] = o;
               }
             }
-          } else {
+          } else if constexpr (D == 2) {
 #pragma unroll
             for (int b0 = 0; b0 < NP; ++b0)
 #pragma unroll
@@ -1131,6 +1131,36 @@ __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__r
                   }
                 }
               }
+          } else {
+#pragma unroll
+            for (int b0 = 0; b0 < NP; ++b0)
+#pragma unroll
+              for (int b1 = 0; b1 < NP; ++b1)
+#pragma unroll
+                for (int b2 = 0; b2 < NP; ++b2) {
+                  if (!okb[0][b0] || !okb[1][b1] || !okb[2][b2]) continue;
+#pragma unroll
+                  for (int a0 = 0; a0 < NQ; ++a0) {
+                    if (lq[0][a0] < 0) continue;
+                    const T u = c[a0 * NP + b0];
+#pragma unroll
+                    for (int a1 = 0; a1 < NQ; ++a1) {
+                      if (lq[1][a1] < 0) continue;
+                      const T v = c[N1 + a1 * NP + b1];
+                      const T uv = T{u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x};
+#pragma unroll
+                      for (int a2 = 0; a2 < NQ; ++a2) {
+                        if (lq[2][a2] < 0) continue;
+                        const T w = c[2 * N1 + a2 * NP + b2];
+                        const int li = (lq[0][a0] * tile1 + lq[1][a1]) * tile2 + lq[2][a2];
+                        T o = tile[li];
+                        o.x += uv.x * w.x - uv.y * w.y;
+                        o.y += uv.x * w.y + uv.y * w.x;
+                        tile[li] = o;
+                      }
+                    }
+                  }
+                }
           }
         }
         __syncthreads();
@@ -1646,6 +1676,9 @@ FggcLayout fggc_layout(const FggcArgs &a) {
   return L;
 }
 
+bool g_wave3_attr = false;
+std::mutex g_wave3_mu;
+
 template <int D, int N1, typename T>
 void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams &cp,
                        const uint32_t *pos, char *recs, const int64_t *start, void *agg, T *cells,
@@ -1741,8 +1774,19 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
   if (shm > 65536) fail(FGGC_EUNSUPPORTED, "accumulation tile exceeds 64 KB of LDS");
   StageScope sc(a.prof, "fggc_accum", s);
   const dim3 grid((unsigned)L.tiles), blk(256);
-  const bool wave = D <= 2 && L.S[0] == 1 && (D < 2 || L.S[1] == 1) && N1 == nq * np &&
-                    ((nq == 2 && np == 2) || (nq == 4 && np == 2) || (nq == 2 && np == 4) || (nq == 4 && np == 4));
+  const bool wave = L.S[0] == 1 && (D < 2 || L.S[1] == 1) && (D < 3 || L.S[2] == 1) && N1 == nq * np &&
+                    ((nq == 2 && np == 2) || (nq == 4 && np == 2) || (nq == 2 && np == 4) || (nq == 4 && np == 4)) &&
+                    tc * sizeof(T) <= 65536 && (D < 3 || N1 == 4);  // 3D: Q2P2 (larger sets unroll too far)
+  if (wave && D == 3) {
+    std::lock_guard<std::mutex> lk(g_wave3_mu);
+    if (!g_wave3_attr) {
+      const void *ks[] = {(const void *)fggc_accum_wave_kernel<3, 2, 2, float2>,
+                          (const void *)fggc_accum_wave_kernel<3, 2, 2, double2>};
+      for (const void *kf : ks)
+        FGGC_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
+      g_wave3_attr = true;
+    }
+  }
   if (D == 2 && occ) {
     if (wave) ap.empty = occ;  // the one-wave kernel marks every (slice, tile)
     else launch_zero(occ, (size_t)L.nslices * L.ntq[0] * L.ntq[1], s);  // no tile is skipped
@@ -1755,18 +1799,18 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
       FGGC_HIP(hipGetLastError());
       return;
     }
-    if (N1 == 8 && nq == 4 && np == 2) {
-      fggc_accum_wave_kernel<D, 4, 2, T><<<grid, wblk, wshm, s>>>(ap, cells);
+    if (D < 3 && N1 == 8 && nq == 4 && np == 2) {
+      fggc_accum_wave_kernel<(D < 3 ? D : 2), 4, 2, T><<<grid, wblk, wshm, s>>>(ap, cells);
       FGGC_HIP(hipGetLastError());
       return;
     }
-    if (N1 == 8 && nq == 2 && np == 4) {
-      fggc_accum_wave_kernel<D, 2, 4, T><<<grid, wblk, wshm, s>>>(ap, cells);
+    if (D < 3 && N1 == 8 && nq == 2 && np == 4) {
+      fggc_accum_wave_kernel<(D < 3 ? D : 2), 2, 4, T><<<grid, wblk, wshm, s>>>(ap, cells);
       FGGC_HIP(hipGetLastError());
       return;
     }
-    if (N1 == 16 && nq == 4 && np == 4) {
-      fggc_accum_wave_kernel<D, 4, 4, T><<<grid, wblk, wshm, s>>>(ap, cells);
+    if (D < 3 && N1 == 16 && nq == 4 && np == 4) {
+      fggc_accum_wave_kernel<(D < 3 ? D : 2), 4, 4, T><<<grid, wblk, wshm, s>>>(ap, cells);
       FGGC_HIP(hipGetLastError());
       return;
     }
