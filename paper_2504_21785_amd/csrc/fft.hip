@@ -37,6 +37,8 @@ __global__ __launch_bounds__(1024) void fft_axis_kernel(const T *src, T *dst, Ff
   const int64_t inner_mask = ((int64_t)1 << lgin) - 1;
   const int64_t line0 = (int64_t)blockIdx.x << lgL;
   const int tot = L << lg;
+  T *stw = sm + tot;  // the twiddles, staged in LDS
+  for (int i = threadIdx.x; i < n; i += blockDim.x) stw[i] = tw[i];
   // load (coalesced: along the line when lines are contiguous, across lines otherwise)
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     int l, i;
@@ -54,7 +56,7 @@ __global__ __launch_bounds__(1024) void fft_axis_kernel(const T *src, T *dst, Ff
     }
   }
   __syncthreads();
-  lds_fft_rows<T>(sm, lg, L, n, a.inverse, tw);
+  lds_fft_rows<T>(sm, lg, L, n, a.inverse, stw);
   const int bigmask = (1 << a.log2big) - 1;
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     int l, i;
@@ -121,12 +123,13 @@ void launch_axis(const T *src, T *dst, int64_t n, int64_t inner, int64_t outer, 
   while (((int64_t)1 << log2n) < n) ++log2n;
   const int64_t nlines = inner * outer;
   int64_t L;
+  const int64_t lds_rows = std::max<int64_t>(n, lds_max - n);  // the twiddles take n of it
   if (inner == 1 && !transpose_out) {
-    L = std::max<int64_t>(1, std::min<int64_t>(4096 / n, lds_max / n));
+    L = std::max<int64_t>(1, std::min<int64_t>(4096 / n, lds_rows / n));
   } else if (inner == 1) {
-    L = std::max<int64_t>(1, std::min<int64_t>(64, lds_max / n));
+    L = std::max<int64_t>(1, std::min<int64_t>(64, lds_rows / n));
   } else {
-    L = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(64, inner), lds_max / n));
+    L = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(64, inner), lds_rows / n));
   }
   // keep at least ~256 workgroups when there are enough lines
   L = std::min(L, std::max<int64_t>(1, nlines / 256));
@@ -164,7 +167,7 @@ void launch_axis(const T *src, T *dst, int64_t n, int64_t inner, int64_t outer, 
   a.log2big = lgbig;
   const T *tw = (const T *)twiddles(n, elem == 8 ? FGGC_FP32 : FGGC_FP64);
   const T *twb = nbig > 0 ? (const T *)twiddles(nbig, elem == 8 ? FGGC_FP32 : FGGC_FP64) : tw;
-  const size_t shm = (size_t)L * n * elem;
+  const size_t shm = (size_t)(L + 1) * n * elem;  // rows, then twiddles
   const int64_t nblocks = (nlines + L - 1) / L;
   fft_axis_kernel<T><<<dim3((unsigned)nblocks), dim3(threads), shm, s>>>(src, dst, a, tw, twb);
   FGGC_HIP(hipGetLastError());

@@ -1345,9 +1345,13 @@ __global__ __launch_bounds__(256) void fggc_stencil_fft1_kernel(Stencil1Params p
   T *row = reinterpret_cast<T *>(smem_raw);
   const int64_t sl = blockIdx.x;
   const int N = 1 << lgN;
-  for (int q = threadIdx.x; q < N; q += blockDim.x) row[q] = stencil1_cell(p, A, n1s, sl, q);
+  T *stw = row + N;  // the twiddles, staged in LDS
+  for (int q = threadIdx.x; q < N; q += blockDim.x) {
+    row[q] = stencil1_cell(p, A, n1s, sl, q);
+    stw[q] = tw[q];
+  }
   __syncthreads();
-  lds_fft_rows<T>(row, lgN, 1, N, 0, tw);
+  lds_fft_rows<T>(row, lgN, 1, N, 0, stw);
   T *dst = spec + sl * N;
   for (int q = threadIdx.x; q < N; q += blockDim.x) dst[q] = row[q];
 }
@@ -1462,6 +1466,8 @@ __global__ __launch_bounds__(kContractThreads) void fft_contract_kernel(Contract
   const int lgN = p.lgN, N = 1 << lgN, WA = 1 << p.lgWA, W = 1 << p.lgW, P = WA * W;
   const int M = (int)p.M;
   const int64_t nbc = p.B >> p.lgW, nac = p.A >> p.lgWA;
+  T *stw = sm + (size_t)p.Lc * P * N;  // the twiddles, staged in LDS
+  for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = tw[i];
   int64_t g = blockIdx.x;
   const int mg = (int)(g % p.MS);
   g /= p.MS;
@@ -1509,7 +1515,7 @@ __global__ __launch_bounds__(kContractThreads) void fft_contract_kernel(Contract
           full ? X[((((o * p.L + lc0 + l) * p.A + a0 + wa) << lgN) + n) * p.B + b0 + w] : T{0, 0};
     }
     __syncthreads();
-    lds_fft_rows<T, kContractBfly>(sm, lgN, lcn * P, N, 0, tw);
+    lds_fft_rows<T, kContractBfly>(sm, lgN, lcn * P, N, 0, stw);
 #pragma unroll
     for (int c = 0; c < kContractOut; ++c) {
       const int e = threadIdx.x + c * (int)blockDim.x;
@@ -1679,6 +1685,8 @@ FggcLayout fggc_layout(const FggcArgs &a) {
 bool g_wave3_attr = false;
 std::mutex g_wave3_mu;
 
+bool g_sfft_attr = false;
+std::mutex g_sfft_mu;
 template <int D, int N1, typename T>
 void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams &cp,
                        const uint32_t *pos, char *recs, const int64_t *start, void *agg, T *cells,
@@ -1760,8 +1768,18 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
       while (((int64_t)1 << lgN) < a.Nq[0]) ++lgN;
       // 256 threads: N <= 4096 keeps the FFT within 8 butterflies per thread
       const T *tw = (const T *)fft_twiddles(a.Nq[0], a.precision);
-      fggc_stencil_fft1_kernel<T><<<dim3((unsigned)a.sn[0]), dim3(256), a.Nq[0] * sizeof(T), s>>>(sp, A, N1, lgN,
-                                                                                                 tw, cells);
+      {
+        std::lock_guard<std::mutex> lk(g_sfft_mu);
+        if (!g_sfft_attr) {
+          FGGC_HIP(hipFuncSetAttribute((const void *)fggc_stencil_fft1_kernel<float2>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+          FGGC_HIP(hipFuncSetAttribute((const void *)fggc_stencil_fft1_kernel<double2>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+          g_sfft_attr = true;
+        }
+      }
+      fggc_stencil_fft1_kernel<T><<<dim3((unsigned)a.sn[0]), dim3(256), 2 * a.Nq[0] * sizeof(T), s>>>(
+          sp, A, N1, lgN, tw, cells);
     } else {
       fggc_stencil1_kernel<T><<<dim3((unsigned)((ncl + 255) / 256)), dim3(256), 0, s>>>(sp, A, N1, cells);
     }
@@ -1944,9 +1962,9 @@ void launch_contract(const FggcArgs &a, const FggcLayout &L, int k, const T *in,
     std::lock_guard<std::mutex> lk(g_contract_mu);
     if (!g_contract_attr) {
       FGGC_HIP(hipFuncSetAttribute((const void *)fft_contract_kernel<float2, float>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
       FGGC_HIP(hipFuncSetAttribute((const void *)fft_contract_kernel<double2, double>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 65536));
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
       g_contract_attr = true;
     }
   }
@@ -2009,7 +2027,7 @@ void launch_contract(const FggcArgs &a, const FggcLayout &L, int k, const T *in,
   p.lgt0 = p.lgt1 = 0;
   while (((int64_t)1 << p.lgt0) < L.tile[0]) ++p.lgt0;
   while (((int64_t)1 << p.lgt1) < L.tile[1]) ++p.lgt1;
-  const size_t shm = (size_t)p.Lc * N * P * sizeof(T) + 16;
+  const size_t shm = (size_t)(p.Lc * P + 1) * N * sizeof(T) + 16;  // rows, then twiddles
   const int64_t blocks = groups * MS;
   if (blocks >= ((int64_t)1 << 31)) fail(FGGC_EUNSUPPORTED, "too many workgroups for the separable finish");
   const T *tw = (const T *)fft_twiddles(N, a.precision);
