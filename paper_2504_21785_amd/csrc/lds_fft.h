@@ -1,7 +1,8 @@
-// In-place complex DFT of rows held in LDS (Stockham autosort, radix 4 and
-// one radix 2 when log2 n is odd), shared by the batched FFT and the
-// separable Fourier finish.  Rows of length n = 2^lg are `rowstride` apart;
-// all threads of the workgroup take part and synchronise.
+// In-place complex DFT of rows held in LDS (Stockham autosort: radix-8 and
+// radix-4 passes for FP32, radix 4 and one radix 2 when log2 n is odd for
+// FP64), shared by the batched FFT and the separable Fourier finish.  Rows of
+// length n = 2^lg are `rowstride` apart; all threads of the workgroup take part
+// and synchronise.
 #ifndef FGGC_LDS_FFT_H
 #define FGGC_LDS_FFT_H
 
@@ -15,7 +16,7 @@ template <typename T> __device__ __forceinline__ T cmul(T a, T b) {
 template <typename T> __device__ __forceinline__ T cadd(T a, T b) { return T{a.x + b.x, a.y + b.y}; }
 template <typename T> __device__ __forceinline__ T csub(T a, T b) { return T{a.x - b.x, a.y - b.y}; }
 
-constexpr int kMaxBfly = 8;  // radix-4 butterflies per thread per pass
+constexpr int kMaxBfly = 8;  // radix-4 butterflies per thread per pass (radix 8: half)
 
 // x * (-i) (forward) or x * (+i) (inverse)
 template <typename T> __device__ __forceinline__ T rot_quarter(T x, int inverse) {
