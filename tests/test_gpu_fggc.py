@@ -5,7 +5,10 @@
   well conditioned, so the coefficients themselves are comparable);
 - the whole reconstruction against the oracle's plain evaluation of (2.24):
   FP64 with Q2P2 at 1e-12; FP64 with Q4P2 at the conditioning floor of the
-  least-squares solve; FP32 at 1e-6.
+  least-squares solve; FP32 at 1e-6;
+- every neighbour strategy of the M_LSA tables (Q2P2, Q4P2, Q2P4, Q4P4) on
+  three meshes in 1D, and the four-shift p-sets in 2D, FP64 at a tolerance
+  derived from the conditioning of the solve and FP32 at 1e-6.
 """
 import math
 import sys
@@ -171,6 +174,79 @@ def test_reconstruct_1d_crowded_bins(ctx, orc, prec, tol):
     e = rel(u, ref)
     log("fggc 1d crowded bins", prec, e)
     assert e <= tol
+
+
+STRATEGIES = {"Q2P2": (Q2, Q2), "Q4P2": (Q4, Q2), "Q2P4": (Q2, Q4), "Q4P4": (Q4, Q4)}
+
+
+def strategy_cutoff_and_tol(name, Cq, Cp):
+    """Eigenvalue cutoff and FP64 tolerance for a neighbour strategy (Sec. 3.1).
+
+    Exact least squares where the Gram matrix (3.22) has kappa < 1e12; above
+    that the paper's reading of a truncated pseudo-inverse (eigenvalues below
+    1e-10 of the largest dropped), on both sides.  Two rounding terms, with
+    kappa the ratio of the largest to the smallest kept eigenvalue and
+    |c|_1 = O(1):
+    - the library's FP64 solve moves c by ~kappa u along the eigenvectors of
+      the smallest kept eigenvalue, which changes u by at most
+      sqrt(lambda_min) kappa u |c| = sqrt(lambda_max kappa) u (u = 1.1e-16,
+      a factor 2 of margin);
+    - the oracle's truncated solve forms the pseudo-inverse explicitly in long
+      double: its entries, of size 1/lambda_min, carry a rounding error of
+      ~u_ld kappa relative that spreads over every direction (u_ld = 5.4e-20).
+    """
+    ev, _ = F.plan_gram(*STRATEGIES[name], Cq, Cp)
+    lmax = float(ev.max())
+    kappa = lmax / ev.min() if ev.min() > 0 else math.inf
+    cutoff = 0.0 if kappa < 1e12 else 1e-10
+    kept = ev[ev > cutoff * lmax] if cutoff > 0 else ev
+    kappa_eff = lmax / float(kept.min())
+    oracle_term = 5.4e-20 * kappa_eff if cutoff > 0 else 0.0
+    return cutoff, max(1e-12, 2.2e-16 * math.sqrt(lmax * kappa_eff), oracle_term)
+
+
+@pytest.mark.parametrize("C", [math.pi / 4, math.pi / 8, math.pi / 16], ids=["pi/4", "pi/8", "pi/16"])
+@pytest.mark.parametrize("name", ["Q2P2", "Q4P2", "Q2P4", "Q4P4"])
+def test_reconstruct_1d_strategies(ctx, orc, name, C):
+    # every neighbour strategy of the M_LSA tables at Cq = Cp = C (eps = 1/64:
+    # Nq = 64, 128, 256), FP64 against the oracle with the same cutoff, and
+    # FP32 at the FP32 bound
+    ps = small_1d(14, N=3000)
+    eps = ps.eps
+    Nq = int(round(2 * math.pi / (C * math.sqrt(eps))))
+    dq_off, dp_off = STRATEGIES[name]
+    cutoff, tol = strategy_cutoff_and_tol(name, C, C)
+    st = F.make_strategy(1, [Nq], [C * math.sqrt(eps)], dq_off, dp_off, cutoff=cutoff)
+    ref = orc.fggc(ps.Q, ps.P, ps.S, ps.a, eps, ps.M, [Nq], [C * math.sqrt(eps)], dq_off, dp_off,
+                   rcond=cutoff)
+    for prec, bound in ((F.FP64, tol), (F.FP32, 1e-6)):
+        u = ctx.reconstruct(t(ps.Q), t(ps.P), t(ps.S), t(ps.a), eps, ps.M, st, precision=prec)
+        torch.cuda.synchronize()
+        e = rel(u.cpu().numpy().reshape(-1).astype(np.complex128), ref)
+        log("fggc 1d", name, "C = %.4f" % C, "cutoff", cutoff, prec, e, "bound", bound)
+        assert e <= bound
+
+
+@pytest.mark.parametrize("name", ["Q2P4", "Q4P4"])
+def test_reconstruct_2d_strategies(ctx, orc, name):
+    # the p-shift sets of four (n1 = 8 and 16, n1^2 = 64 and 256 coefficients
+    # per packet) in 2D at the default mesh (C = pi/8)
+    ps = W.gen_mesh(2, 16, 6, 0.5, (0.5, 0.3), 1.0 / 256, 128, seed=6)
+    pts = heavy_points(ps, 150, 50, 3)
+    st0 = F.default_strategy(2, ps.eps, name)
+    Cq = 2 * math.pi / st0.Nq[0] / math.sqrt(ps.eps)
+    Cp = st0.dp[0] / math.sqrt(ps.eps)
+    cutoff, tol = strategy_cutoff_and_tol(name, Cq, Cp)
+    sd = st0.describe()
+    st = F.make_strategy(2, sd["Nq"][:2], sd["dp"][:2], sd["dq_off"], sd["dp_off"], cutoff=cutoff)
+    ref = orc.fggc(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, sd["Nq"][:2], sd["dp"][:2], sd["dq_off"],
+                   sd["dp_off"], rcond=cutoff, pts=pts)
+    for prec, bound in ((F.FP64, 2 * tol), (F.FP32, 1e-6)):
+        u = ctx.reconstruct(t(ps.Q), t(ps.P), t(ps.S), t(ps.a), ps.eps, ps.M, st, precision=prec)
+        torch.cuda.synchronize()
+        e = rel(u.cpu().numpy().reshape(-1).astype(np.complex128)[pts], ref)
+        log("fggc 2d", name, "cutoff", cutoff, prec, e, "bound", bound)
+        assert e <= bound
 
 
 @pytest.mark.parametrize("prec,name,tol", [(F.FP64, "Q2P2", 1e-12), (F.FP32, "Q4P2", 1e-6)])
