@@ -66,18 +66,23 @@ def _check(rc, what):
         raise ValueError(f"{what} failed with code {rc}")
 
 
-def direct_sum(Q, P, S, a, eps, M, R, scale=1.0, pts=None):
-    """Windowed direct sum of eq. (2.10) at grid points `pts` (flat indices; None = all)."""
+def direct_sum(Q, P, S, a, eps, M, R, scale=1.0, pts=None, window="ball"):
+    """Windowed direct sum of eq. (2.10) at grid points `pts` (flat indices; None = all).
+
+    window: "ball" (|y| <= R) or "box" (every |y_k| <= R).
+    """
     Q = _f64(Q); P = _f64(P); S = _f64(S); a = _cplx(a)
     d, N = Q.shape
     M = _i64(M)
     pts_a = None if pts is None else _i64(pts)
     npts = int(np.prod(M)) if pts_a is None else pts_a.size
     u = np.zeros(npts, dtype=np.complex128)
-    rc = _load().oracle_direct_sum(ctypes.c_int(d), ctypes.c_int64(N), _p(Q), _p(P), _p(S), _p(a),
-                                   ctypes.c_double(eps), _p(M), ctypes.c_double(R),
-                                   ctypes.c_double(scale), ctypes.c_int64(npts), _p(pts_a), _p(u))
-    _check(rc, "oracle_direct_sum")
+    if window not in ("ball", "box"):
+        raise ValueError(f"unknown window {window!r}")
+    fn = _load().oracle_direct_sum if window == "ball" else _load().oracle_direct_sum_boxwin
+    rc = fn(ctypes.c_int(d), ctypes.c_int64(N), _p(Q), _p(P), _p(S), _p(a), ctypes.c_double(eps),
+            _p(M), ctypes.c_double(R), ctypes.c_double(scale), ctypes.c_int64(npts), _p(pts_a), _p(u))
+    _check(rc, "oracle_direct_sum" if window == "ball" else "oracle_direct_sum_boxwin")
     return u
 
 

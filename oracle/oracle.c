@@ -11,6 +11,8 @@
  *   oracle_direct_sum        the discrete reconstruction sum, eq. (2.10) and
  *                            eq. (2.19), on the periodic grid [-pi,pi)^d,
  *                            minimum image, Euclidean window |y| <= R.
+ *   oracle_direct_sum_boxwin the same sum with a box window: every component
+ *                            of the minimum image satisfies |y_k| <= R.
  *   oracle_direct_bruteforce the same sum with no window, over all periodic
  *                            images n in [-nimg,nimg]^d (for tiny inputs).
  *   oracle_inner             packet inner product, eq. (2.17).
@@ -127,9 +129,9 @@ static double complex packet_term(int d, const double *y, double Pj[3], double S
  * so that a point only visits the 3^d bins around its own; every candidate is
  * still tested against the window exactly.
  */
-int oracle_direct_sum(int d, int64_t N, const double *Q, const double *P, const double *S,
-                      const double *a, double eps, const int64_t *M, double R, double scale,
-                      int64_t npts, const int64_t *pts, double *u) {
+static int direct_sum_window(int d, int64_t N, const double *Q, const double *P, const double *S,
+                             const double *a, double eps, const int64_t *M, double R, double scale,
+                             int64_t npts, const int64_t *pts, double *u, int box) {
   if (d < 1 || d > 3 || N < 0 || !(eps > 0) || !(R > 0) || !(R < M_PI)) return -1;
   int64_t total = 1;
   for (int k = 0; k < d; ++k) {
@@ -197,13 +199,14 @@ int oracle_direct_sum(int d, int64_t N, const double *Q, const double *P, const 
       }
       for (int64_t t = start[b]; t < start[b + 1]; ++t) {
         int64_t j = order[t];
-        double y[3], r2 = 0.0, Pj[3] = {0, 0, 0};
+        double y[3], r2 = 0.0, ymax = 0.0, Pj[3] = {0, 0, 0};
         for (int k = 0; k < d; ++k) {
           y[k] = wrap_pi(x[k] - Q[k * N + j]);
           r2 += y[k] * y[k];
+          ymax = fmax(ymax, fabs(y[k]));
           Pj[k] = P[k * N + j];
         }
-        if (r2 > R * R) continue;
+        if (box ? ymax > R : r2 > R * R) continue;
         acc += packet_term(d, y, Pj, S[j], a[2 * j] + I * a[2 * j + 1], eps);
       }
     }
@@ -213,6 +216,23 @@ int oracle_direct_sum(int d, int64_t N, const double *Q, const double *P, const 
   }
   free(start); free(order); free(binof);
   return 0;
+}
+
+int oracle_direct_sum(int d, int64_t N, const double *Q, const double *P, const double *S,
+                      const double *a, double eps, const int64_t *M, double R, double scale,
+                      int64_t npts, const int64_t *pts, double *u) {
+  return direct_sum_window(d, N, Q, P, S, a, eps, M, R, scale, npts, pts, u, 0);
+}
+
+/*
+ * The sum of oracle_direct_sum with the window max_k |y_k| <= R (a box of
+ * half-width R about the packet centre) instead of the ball |y| <= R.  The
+ * box contains the ball, so this sum drops less of each packet's tail.
+ */
+int oracle_direct_sum_boxwin(int d, int64_t N, const double *Q, const double *P, const double *S,
+                             const double *a, double eps, const int64_t *M, double R, double scale,
+                             int64_t npts, const int64_t *pts, double *u) {
+  return direct_sum_window(d, N, Q, P, S, a, eps, M, R, scale, npts, pts, u, 1);
 }
 
 /*

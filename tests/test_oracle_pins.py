@@ -263,6 +263,35 @@ def test_direct_sum_against_bruteforce(orc, d, M):
     assert np.array_equal(orc.direct_sum(Q, P, S, a, eps, Mv, 6 * math.sqrt(eps), 0.7, pts=pts), u6[pts])
 
 
+def test_direct_sum_box_window_against_definition(orc):
+    """The box-window sum (every |y_k| <= R) against its definition, written out
+    as plain loops over packets and points on a tiny 2D grid.  eps and R are
+    large enough that the corners of the box (outside the ball of radius R)
+    carry weight, so the window's shape is seen."""
+    rng = np.random.default_rng(41)
+    eps, R, M = 0.5, 1.3, (8, 6)
+    Q, P, S, a = random_set(rng, 2, 7)
+    ref = np.zeros(M, dtype=complex)
+    for m0 in range(M[0]):
+        for m1 in range(M[1]):
+            x = (-math.pi + 2 * math.pi * m0 / M[0], -math.pi + 2 * math.pi * m1 / M[1])
+            for j in range(Q.shape[1]):
+                y = [(x[k] - Q[k, j] + math.pi) % (2 * math.pi) - math.pi for k in range(2)]
+                if max(abs(y[0]), abs(y[1])) > R:
+                    continue
+                ph = (S[j] + P[0, j] * y[0] + P[1, j] * y[1]) / eps
+                ref[m0, m1] += 0.9 * a[j] * np.exp(1j * ph - (y[0] ** 2 + y[1] ** 2) / (2 * eps))
+    ub = orc.direct_sum(Q, P, S, a, eps, M, R, scale=0.9, window="box")
+    assert np.linalg.norm(ub - ref.ravel()) <= 1e-13 * np.linalg.norm(ref)
+    # the ball drops the corners: a visible difference here
+    uc = orc.direct_sum(Q, P, S, a, eps, M, R, scale=0.9)
+    assert np.linalg.norm(uc - ub) > 1e-3 * np.linalg.norm(ub)
+    # in one dimension the box is the ball
+    Q1, P1, S1, a1 = random_set(rng, 1, 9)
+    assert np.array_equal(orc.direct_sum(Q1, P1, S1, a1, 1 / 16, [64], 0.9, window="box"),
+                          orc.direct_sum(Q1, P1, S1, a1, 1 / 16, [64], 0.9))
+
+
 def test_direct_sum_single_packet_on_grid_is_symmetric(orc):
     eps, M = 1.0 / 64, 256
     m0 = 100
