@@ -27,6 +27,7 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_T = 78.6  # FP64 vector TFLOP/s
+FP32_MFMA_PEAK_T = 157.3  # dense FP32 matrix-core TFLOP/s
 # VALU issue slots: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one non-packed op per lane per cycle)
 VALU_SLOT_PEAK_T = 256 * 64 * 2.4e9 / 1e12
 
@@ -233,6 +234,39 @@ def main():
         direct_ms = (time.perf_counter() - t0) * 1e3 / args.steps
         log(f"direct: {direct_ms:.4f} ms/step")
 
+    # the separable (box-window, matrix-core) direct sum: 2D only
+    sep = None
+    if d == 2:
+        u_s = torch.empty(ps.M, dtype=torch.complex64, device=dev)
+
+        def step_sep():
+            ctx.direct_sum_separable(Q, P, S, a, ps.eps, ps.M, ps.R, out=u_s)
+
+        for _ in range(max(1, args.warmup)):
+            step_sep()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step_sep()
+        torch.cuda.synchronize()
+        sep_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ctx.profile(True)
+        for _ in range(args.steps):
+            step_sep()
+        torch.cuda.synchronize()
+        kms, kcnt = ctx.stage_time("ds_kernel")
+        ctx.profile(False)
+        kms = kms / max(kcnt, 1)
+        # algorithmic work: one complex multiply-add (8 flops) per (packet, point)
+        # pair inside the box window
+        pairs = ps.N * np.prod([2 * ps.R / (2 * math.pi / m) for m in ps.M])
+        ach = pairs * 8 / (kms * 1e-3) / 1e12
+        sep = {"value": ps.N / (sep_ms * 1e-3), "ms_per_step": sep_ms, "window": "box, half-width R",
+               "roofline": {"kernel": "ds_sep2_kernel", "bound": "mfma", "achieved": ach,
+                            "peak": FP32_MFMA_PEAK_T, "unit": "TFLOP/s", "frac": ach / FP32_MFMA_PEAK_T,
+                            "pairs_per_launch": float(pairs), "avg_launch_ms": kms}}
+        log(f"separable direct: {sep_ms:.4f} ms/step, kernel {kms:.4f} ms")
+
     # ---- pass B: per-stage HIP events ---------------------------------------
     ctx.profile(True)
     for _ in range(args.steps):
@@ -259,6 +293,11 @@ def main():
     if do_direct:
         fvd = rel(u_fggc.astype(np.complex128), u_direct.astype(np.complex128))
         log(f"FGGC vs direct rel-L2 {fvd:.3e}")
+    if sep is not None:
+        u_sep = u_s.cpu().numpy().astype(np.complex128)
+        sep["rel_l2_vs_direct"] = rel(u_sep, u_direct.astype(np.complex128))
+        sep["fggc_rel_l2_vs_it"] = rel(u_fggc.astype(np.complex128), u_sep)
+        sep["speedup_fggc_vs_it"] = sep["ms_per_step"] / fggc_ms
 
     # ---- roofline of the dominant FGGC kernel --------------------------------
     lo, n = ctx.cell_box(Q, P, S, a, st)
@@ -395,6 +434,7 @@ def main():
                                                       "ms_per_step": direct_ms,
                                                       "roofline": direct_roofline},
         "speedup_vs_direct": None if direct_ms is None else direct_ms / fggc_ms,
+        "direct_sum_separable": sep,
         "accuracy": accuracy,
         "roofline": roofline,
         "cpu_baseline": cpu,

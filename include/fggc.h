@@ -151,6 +151,25 @@ int fggc_direct_sum_box(fggc_ctx *ctx, const fggc_packets *pk, double eps, const
                         double scale, int precision, void *u_out, void *stream);
 
 /*
+ * The direct sum of eq. (2.10) with a box window, evaluated as a matrix
+ * product (d = 2, FP32 only):
+ *   u_m = scale * sum_j a_j exp(i (S_j + P_j.y)/eps - |y|^2/(2 eps)) * [|y_0| <= h] [|y_1| <= h],
+ *   y = minimum image of x_m - Q_j, h = window_half_width.
+ * Under this window every term is a product of a factor of m_0 and a factor
+ * of m_1, so a tile of u is a sum over packets of outer products: the call
+ * evaluates it on the matrix cores.  The box contains the ball of radius h,
+ * so the result differs from fggc_direct_sum's at the same h only by terms
+ * smaller than exp(-h^2/(2 eps)) relative (about 1.5e-8 at h = 6 sqrt(eps)).
+ * Arguments, layout, ownership and staging as in fggc_direct_sum; u_out holds
+ * the whole grid as complex64.  Errors: FGGC_EINVAL as fggc_direct_sum;
+ * FGGC_EUNSUPPORTED when d != 2, precision != FGGC_FP32 or an axis exceeds
+ * 2^20 points.
+ */
+int fggc_direct_sum_separable(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_grid *grid,
+                              double window_half_width, double scale, int precision, void *u_out,
+                              void *stream);
+
+/*
  * FGGC reconstruction (Alg. 2 steps 3-4 with eq. 2.23-2.25):
  *   per packet and dimension, int/frac split (3.6)-(3.7), right-hand side
  *   (3.23), least squares against the precomputed Gram matrix (3.22) through

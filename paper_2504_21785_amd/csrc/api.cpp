@@ -479,7 +479,8 @@ void fggc_destroy(fggc_ctx *ctx) {
 namespace {
 int direct_impl(const char *what, fggc_ctx *ctx, const fggc_packets *pk, double eps,
                 const fggc_grid *grid, const int64_t *box_lo, const int64_t *box_n,
-                double window_radius, double scale, int precision, void *u_out, void *stream) {
+                double window_radius, double scale, int precision, void *u_out, void *stream,
+                int box_window = 0) {
   return guarded(what, [&] {
     if (!ctx) fail(FGGC_EINVAL, "ctx is NULL");
     GridGeom g = check_grid(grid);
@@ -490,6 +491,11 @@ int direct_impl(const char *what, fggc_ctx *ctx, const fggc_packets *pk, double 
     if (!std::isfinite(scale)) fail(FGGC_EINVAL, "scale must be finite");
     if (precision != FGGC_FP32 && precision != FGGC_FP64) fail(FGGC_EINVAL, "bad precision");
     if (!u_out) fail(FGGC_EINVAL, "u_out is NULL");
+    if (box_window) {
+      if (g.d != 2) fail(FGGC_EUNSUPPORTED, "the separable direct sum is two-dimensional (d = 2)");
+      if (precision != FGGC_FP32) fail(FGGC_EUNSUPPORTED, "the separable direct sum computes in FP32");
+      if (g.n[0] > (1 << 20) || g.n[1] > (1 << 20)) fail(FGGC_EUNSUPPORTED, "grid axes above 2^20 points");
+    }
     Box box{};
     int64_t npts = 1;
     for (int k = 0; k < 3; ++k) {
@@ -518,6 +524,7 @@ int direct_impl(const char *what, fggc_ctx *ctx, const fggc_packets *pk, double 
     da.g = g;
     da.box = box;
     da.precision = precision;
+    da.box_window = box_window;
     da.prof = ctx->profiling ? &ctx->prof : nullptr;
     const size_t need = staging_bytes(*pk, host_in, out_bytes, host_out) + direct_workspace_bytes(da);
     ctx->ws.reserve(need, ctx->budget);
@@ -550,6 +557,13 @@ int fggc_direct_sum_box(fggc_ctx *ctx, const fggc_packets *pk, double eps, const
   }
   return direct_impl("fggc_direct_sum_box", ctx, pk, eps, grid, box_lo, box_n, window_radius, scale,
                      precision, u_out, stream);
+}
+
+int fggc_direct_sum_separable(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_grid *grid,
+                              double window_half_width, double scale, int precision, void *u_out,
+                              void *stream) {
+  return direct_impl("fggc_direct_sum_separable", ctx, pk, eps, grid, nullptr, nullptr, window_half_width,
+                     scale, precision, u_out, stream, 1);
 }
 
 int fggc_cell_box(fggc_ctx *ctx, const fggc_packets *pk, const fggc_strategy *st,

@@ -233,6 +233,7 @@ struct DirectArgs {
   GridGeom g;
   Box box;  // output points (row-major over the box)
   int precision;
+  int box_window = 0;  // 1: window |y_k| <= R per dimension, separable evaluation (d = 2, FP32)
   void *u;  // device output
   Profiler *prof = nullptr;
 };

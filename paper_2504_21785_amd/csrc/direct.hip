@@ -399,6 +399,197 @@ __global__ __launch_bounds__(kBlock) void ds_kernel(DsParams p) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Separable direct sum on the matrix cores (box window, d = 2, FP32).
+//
+// With the window |y_k| <= R taken per dimension, a packet's term at grid
+// point (m_0, m_1) factors: it is A_j(m_0) B_j(m_1) with
+//   A_j(m_0) = |scale a_j| e^{-y_0^2/(2 eps)} e^{2 pi i (phi0_j + k_0 omega_0j)} [|y_0| <= R],
+//   B_j(m_1) = e^{-y_1^2/(2 eps)} e^{2 pi i k_1 omega_1j} [|y_1| <= R],
+// k_d the minimum-image grid offset of m_d from the packet's nearest grid
+// index and y_d = k_d dx_d - delta_d.  A 32 x 32 tile of u is then
+// sum_j A_j B_j^T: a product of a 32 x J and a J x 32 complex matrix over the
+// J packets that reach the tile.  One wave owns a tile.  The packets of the
+// visible bins are tested 64 at a time (one per lane) and the visible ones
+// are taken in pairs: lane l evaluates A of packet l/32 at row l%32 and B of
+// packet l/32 at column l%32, which is the operand layout of
+// v_mfma_f32_32x32x2_f32 (K = 2), and four MFMAs add the complex product.
+// FP32 sums over 16 pairs are flushed into FP64 accumulators.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kSepTile = 32;
+constexpr int kSepFlush = 16;  // packet pairs per FP32 partial sum
+
+struct SepParams {
+  const DsRec *rec;      // sorted by bin
+  const int64_t *start;  // [nbins + 1]
+  int64_t n[2], binw[2], nbin[2], ntile[2];
+  int W[2];              // window half-width in grid steps, rounded up
+  float dxf[2], Rf, gl2;  // gl2 = -log2(e) / (2 eps)
+  int nchunk;
+  int allvis;            // grid too small for the interval visibility test
+  double *partial;       // [nchunk][n0 n1] complex FP64
+};
+
+__device__ __forceinline__ int min_image(int k, int n) {
+  const int h = n >> 1;
+  return k >= n - h ? k - n : (k < -h ? k + n : k);
+}
+
+__global__ __launch_bounds__(64) void ds_sep2_kernel(SepParams p) {
+  const int lane = threadIdx.x;
+  const int row = lane & 31;
+  const int64_t torg0 = ((int64_t)blockIdx.x / p.ntile[1]) * kSepTile;
+  const int64_t torg1 = ((int64_t)blockIdx.x % p.ntile[1]) * kSepTile;
+  const int64_t torg[2] = {torg0, torg1};
+  const int n0 = (int)p.n[0], n1 = (int)p.n[1];
+
+  // bins visible from the tile: grid points [torg - W, torg + 31 + W] per
+  // dimension, modulo n, as at most two bin intervals
+  int64_t ia[2][2], ic[2][2], ilen[2][2], bcount[2];
+  int nint[2];
+  for (int k = 0; k < 2; ++k) {
+    const int64_t lo = torg[k] - p.W[k], hi = torg[k] + kSepTile - 1 + p.W[k];
+    const int64_t nk = p.n[k], nb = p.nbin[k], bw = p.binw[k];
+    ia[k][1] = ic[k][1] = 0;
+    if (hi - lo + 1 >= nk) {
+      nint[k] = 1;
+      ia[k][0] = 0;
+      ic[k][0] = nb - 1;
+    } else {
+      const int64_t lm = imod(lo, nk), hm = imod(hi, nk);
+      if (lm <= hm) {
+        nint[k] = 1;
+        ia[k][0] = lm / bw;
+        ic[k][0] = hm / bw;
+      } else if (hm / bw + 1 >= lm / bw) {
+        nint[k] = 1;
+        ia[k][0] = 0;
+        ic[k][0] = nb - 1;
+      } else {
+        nint[k] = 2;
+        ia[k][0] = lm / bw;
+        ic[k][0] = nb - 1;
+        ia[k][1] = 0;
+        ic[k][1] = hm / bw;
+      }
+    }
+    ilen[k][0] = ic[k][0] - ia[k][0] + 1;
+    ilen[k][1] = nint[k] == 2 ? ic[k][1] - ia[k][1] + 1 : 0;
+    bcount[k] = ilen[k][0] + ilen[k][1];
+  }
+  auto row_base = [&](int64_t r) {
+    const int64_t b0 = r < ilen[0][0] ? ia[0][0] + r : ia[0][1] + (r - ilen[0][0]);
+    return b0 * p.nbin[1];
+  };
+  int64_t total = 0;
+  for (int64_t r = 0; r < bcount[0]; ++r) {
+    const int64_t base = row_base(r);
+    for (int run = 0; run < nint[1]; ++run)
+      total += p.start[base + ic[1][run] + 1] - p.start[base + ia[1][run]];
+  }
+  const int64_t v0 = total * blockIdx.y / p.nchunk, v1 = total * (blockIdx.y + 1) / p.nchunk;
+
+  f32x16 cr, ci;
+  for (int r = 0; r < 16; ++r) cr[r] = ci[r] = 0.0f;
+  double sr[16], si[16];
+  for (int r = 0; r < 16; ++r) sr[r] = si[r] = 0.0;
+  int pend = 0;
+  const int m0 = (int)torg0 + row, m1 = (int)torg1 + row;  // this lane's row (A) and column (B)
+
+  int64_t vbase = 0;
+  for (int64_t rr = 0; rr < bcount[0] && vbase < v1; ++rr) {
+    const int64_t base = row_base(rr);
+    for (int run = 0; run < nint[1]; ++run) {
+      const int64_t sa = p.start[base + ia[1][run]], sb = p.start[base + ic[1][run] + 1];
+      const int64_t len = sb - sa;
+      int64_t lo = v0 - vbase, hi = v1 - vbase;
+      if (lo < 0) lo = 0;
+      if (hi > len) hi = len;
+      vbase += len;
+      for (int64_t b = lo; b < hi; b += 64) {
+        // one candidate record per lane, and whether its window reaches the tile
+        const int64_t v = b + lane;
+        int mq0 = 0, mq1 = 0;
+        float la2 = 0.0f, d0 = 0.0f, d1 = 0.0f;
+        double om0 = 0.0, om1 = 0.0, ph = 0.0;
+        bool vis = false;
+        if (v < hi) {
+          const DsRec &r = p.rec[sa + v];
+          mq0 = r.mq[0];
+          mq1 = r.mq[1];
+          la2 = r.la2;
+          d0 = r.deltaf[0];
+          d1 = r.deltaf[1];
+          om0 = r.omega[0];
+          om1 = r.omega[1];
+          ph = r.phi0;
+          const int kv0 = min_image((int)torg0 - mq0, n0), kv1 = min_image((int)torg1 - mq1, n1);
+          vis = p.allvis || (kv0 + kSepTile - 1 >= -p.W[0] && kv0 <= p.W[0] && kv1 + kSepTile - 1 >= -p.W[1] &&
+                             kv1 <= p.W[1]);
+        }
+        uint64_t mask = __ballot(vis);
+        while (mask) {
+          const int j0 = __builtin_ctzll(mask);
+          mask &= mask - 1;
+          int j1 = -1;
+          if (mask) {
+            j1 = __builtin_ctzll(mask);
+            mask &= mask - 1;
+          }
+          const bool live = lane < 32 || j1 >= 0;
+          const int src = lane < 32 || j1 < 0 ? j0 : j1;
+          const int smq0 = __shfl(mq0, src), smq1 = __shfl(mq1, src);
+          const float sla2 = __shfl(la2, src), sd0 = __shfl(d0, src), sd1 = __shfl(d1, src);
+          const double som0 = __shfl(om0, src), som1 = __shfl(om1, src), sph = __shfl(ph, src);
+          // A at row m0 (carries the amplitude and the packet's phase)
+          const int k0 = min_image(m0 - smq0, n0);
+          const float y0 = fmaf((float)k0, p.dxf[0], -sd0);
+          float g0 = __builtin_amdgcn_exp2f(fmaf(y0 * y0, p.gl2, sla2));
+          g0 = (live && fabsf(y0) <= p.Rf) ? g0 : 0.0f;
+          const float r0 = (float)__builtin_amdgcn_fract(fma((double)k0, som0, sph));
+          const float ar = g0 * __builtin_amdgcn_cosf(r0), ai = g0 * __builtin_amdgcn_sinf(r0);
+          // B at column m1
+          const int k1 = min_image(m1 - smq1, n1);
+          const float y1 = fmaf((float)k1, p.dxf[1], -sd1);
+          float g1 = __builtin_amdgcn_exp2f(y1 * y1 * p.gl2);
+          g1 = (live && fabsf(y1) <= p.Rf) ? g1 : 0.0f;
+          const float r1 = (float)__builtin_amdgcn_fract((double)k1 * som1);
+          const float br = g1 * __builtin_amdgcn_cosf(r1), bi = g1 * __builtin_amdgcn_sinf(r1);
+          cr = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, ci, 0, 0, 0);
+          if (++pend == kSepFlush) {
+            pend = 0;
+            for (int r = 0; r < 16; ++r) {
+              sr[r] += (double)cr[r];
+              si[r] += (double)ci[r];
+              cr[r] = ci[r] = 0.0f;
+            }
+          }
+        }
+      }
+    }
+  }
+  for (int r = 0; r < 16; ++r) {
+    sr[r] += (double)cr[r];
+    si[r] += (double)ci[r];
+  }
+  // result layout of the 32x32 MFMA: lane l, register r holds row
+  // 8 (r / 4) + 4 (l / 32) + r % 4 and column l % 32
+  double *out = p.partial + 2 * (int64_t)blockIdx.y * p.n[0] * p.n[1];
+  const int64_t col = torg1 + (lane & 31);
+  for (int r = 0; r < 16; ++r) {
+    const int64_t m = torg0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    if (m < p.n[0] && col < p.n[1]) {
+      const int64_t flat = m * p.n[1] + col;
+      out[2 * flat] = sr[r];
+      out[2 * flat + 1] = si[r];
+    }
+  }
+}
+
 template <bool F64>
 __global__ void ds_reduce_kernel(int64_t npts, int nchunk, const double *__restrict__ partial,
                                  void *__restrict__ u) {
@@ -449,10 +640,13 @@ DsLayout ds_layout(const DirectArgs &a) {
   for (int k = 0; k < D; ++k)
     cand *= std::min(1.0, (double)(L.span[k] + 2 * L.W[k] + 2 * L.binw[k]) / (double)a.g.n[k]);
   // chunks: aim for ~8 waves per SIMD, >= ~256 candidate packets per chunk, and
-  // a partial-sum buffer of at most ~32 MB
-  int nc = (int)std::ceil(8192.0 / (double)L.ntiles);
-  nc = std::min(nc, (int)std::max(1.0, cand / 256.0));
-  nc = std::min<int64_t>(nc, std::max<int64_t>(1, ((int64_t)32 << 20) / (L.npts * 16)));
+  // a partial-sum buffer of at most ~32 MB.  The separable kernel runs one
+  // wave per workgroup and wants ~16 per SIMD to overlap its matrix-core and
+  // vector work: 16384 workgroups, a buffer of up to ~256 MB.
+  const bool sep = a.box_window != 0;
+  int nc = (int)std::ceil((sep ? 16384.0 : 8192.0) / (double)L.ntiles);
+  nc = std::min(nc, (int)std::max(1.0, cand / (sep ? 128.0 : 256.0)));
+  nc = std::min<int64_t>(nc, std::max<int64_t>(1, ((int64_t)(sep ? 256 : 32) << 20) / (L.npts * 16)));
   L.nchunk = std::max(1, std::min(nc, 512));
   const int64_t N = std::max<int64_t>(a.pk->N, 1);
   size_t o = 0;
@@ -516,7 +710,33 @@ void launch_direct(const DirectArgs &a, Workspace &ws, hipStream_t s) {
     ds_prep_kernel<<<g, b, 0, s>>>(pp, pos, rec);
     FGGC_HIP(hipGetLastError());
   }
-  if (N > 0) {
+  if (N > 0 && a.box_window) {
+    SepParams p{};
+    p.rec = rec;
+    p.start = start;
+    for (int k = 0; k < 2; ++k) {
+      p.n[k] = a.g.n[k];
+      p.binw[k] = L.binw[k];
+      p.nbin[k] = L.nbin[k];
+      p.ntile[k] = L.ntile[k];
+      p.W[k] = (int)L.W[k];
+      p.dxf[k] = (float)a.g.dx[k];
+      if (a.g.n[k] < 2 * (L.W[k] + kSepTile) + 2) p.allvis = 1;
+    }
+    p.Rf = (float)a.R;
+    p.gl2 = (float)(-1.4426950408889634 / (2.0 * a.eps));
+    p.nchunk = L.nchunk;
+    p.partial = part;
+    {
+      StageScope sc(a.prof, "ds_kernel", s);
+      ds_sep2_kernel<<<dim3((unsigned)L.ntiles, (unsigned)L.nchunk), dim3(64), 0, s>>>(p);
+      FGGC_HIP(hipGetLastError());
+    }
+    StageScope sr(a.prof, "ds_reduce", s);
+    ds_reduce_kernel<false><<<dim3((unsigned)((L.npts + 255) / 256)), dim3(256), 0, s>>>(L.npts, L.nchunk,
+                                                                                        part, a.u);
+    FGGC_HIP(hipGetLastError());
+  } else if (N > 0) {
     DsParams p{};
     p.rec = rec;
     p.start = start;

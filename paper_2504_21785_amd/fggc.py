@@ -69,6 +69,8 @@ _SIGS = [
     ("fggc_direct_sum", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid), _D, _D, _I, _VP, _VP]),
     ("fggc_direct_sum_box", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid),
                                  ctypes.POINTER(_I64), ctypes.POINTER(_I64), _D, _D, _I, _VP, _VP]),
+    ("fggc_direct_sum_separable", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid), _D, _D, _I,
+                                       _VP, _VP]),
     ("fggc_reconstruct", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid),
                               ctypes.POINTER(Strategy), _D, _I, _VP, _VP]),
     ("fggc_default_strategy", _I, [_I, _D, ctypes.c_char_p, ctypes.POINTER(Strategy)]),
@@ -255,6 +257,18 @@ class Context:
         _check(lib().fggc_direct_sum_box(self.h, ctypes.byref(pk), float(eps), ctypes.byref(g), lo, n,
                                          float(window_radius), float(scale), int(precision),
                                          _ptr(out), _stream_ptr(stream) if _on_device(Q) else None))
+        return out
+
+    def direct_sum_separable(self, Q, P, S, a, eps: float, M, window_half_width: float, scale: float = 1.0,
+                             precision: int = FP32, out=None, stream=None):
+        """fggc_direct_sum_separable: the box-window direct sum on the matrix cores (d = 2, FP32)."""
+        d = Q.shape[0]
+        g = _grid(d, M)
+        out = self._alloc_out(Q, g, precision, out)
+        pk = _packets(Q, P, S, a)
+        _check(lib().fggc_direct_sum_separable(self.h, ctypes.byref(pk), float(eps), ctypes.byref(g),
+                                               float(window_half_width), float(scale), int(precision),
+                                               _ptr(out), _stream_ptr(stream) if _on_device(Q) else None))
         return out
 
     def reconstruct(self, Q, P, S, a, eps: float, M, strategy: Strategy, scale: float = 1.0,
