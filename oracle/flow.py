@@ -1,0 +1,90 @@
+"""Plain FP64 oracle for the packet flow of eq. (2.3)-(2.6), in numpy.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, never by the product
+package.  It shares no code with the HIP path.
+
+The flow of one packet, after Sec. 2.1:
+- (2.3) dQ/dt = P;  (2.4) dP/dt = -grad V(Q);  (2.5) dS/dt = |P|^2/2 - V(Q);
+- (2.6) dA/dt = (A/2) tr(Z^{-1} dZ/dt), with Z = dz(Q + iP) and dz = d_q - i d_p.
+
+Z needs the derivatives of the flow with respect to its starting point
+(q, p).  Differentiating (2.3)-(2.4) along dz gives the variational system
+    d(dz Q)/dt = dz P,   d(dz P)/dt = -Hess V(Q) dz Q,
+started at dz Q = I, dz P = -i I (so Z(0) = 2 I).  This is a reading: the
+paper defines Z through the flow and leaves these equations implicit.
+
+The potential family covers the paper's examples:
+    V(x) = c0 + sum_k w_k x_k^2 / 2 + c1 sum_k cos(kappa x_k) + c2 exp(c3 |x|^2).
+
+The time stepping is the classical fourth-order Runge-Kutta scheme (the
+paper's choice, Sec. 4), written plainly: four stage derivatives k1..k4 and
+y + dt (k1 + 2 k2 + 2 k3 + k4) / 6.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def potential(c0=0.0, w=(0.0, 0.0, 0.0), c1=0.0, kappa=0.0, c2=0.0, c3=0.0) -> dict:
+    return {"c0": float(c0), "w": tuple(float(x) for x in (list(w) + [0.0, 0.0, 0.0])[:3]),
+            "c1": float(c1), "kappa": float(kappa), "c2": float(c2), "c3": float(c3)}
+
+
+def v_grad_hess(V: dict, Q: np.ndarray):
+    """V, grad V and Hess V at Q ([d][N]); returns ([N], [d][N], [d][d][N])."""
+    d, N = Q.shape
+    w = np.array(V["w"][:d])[:, None]
+    r2 = np.sum(Q * Q, axis=0)
+    E = V["c2"] * np.exp(V["c3"] * r2)
+    kap = V["kappa"]
+    val = V["c0"] + 0.5 * np.sum(w * Q * Q, axis=0) + V["c1"] * np.sum(np.cos(kap * Q), axis=0) + E
+    grad = w * Q - V["c1"] * kap * np.sin(kap * Q) + 2 * V["c3"] * Q * E[None, :]
+    hess = np.zeros((d, d, N))
+    for k in range(d):
+        hess[k, k] = V["w"][k] - V["c1"] * kap * kap * np.cos(kap * Q[k]) + 2 * V["c3"] * E
+        for m in range(d):
+            hess[k, m] += 4 * V["c3"] ** 2 * Q[k] * Q[m] * E
+    return val, grad, hess
+
+
+def _rhs(V, Q, P, S, A, JQ, JP):
+    """Time derivatives of (Q, P, S, A, JQ, JP); JQ, JP are [d][d][N] complex."""
+    val, grad, hess = v_grad_hess(V, Q)
+    dQ = P
+    dP = -grad
+    dS = 0.5 * np.sum(P * P, axis=0) - val
+    dJQ = JP
+    dJP = -np.einsum("kmn,mln->kln", hess, JQ)
+    Z = JQ + 1j * JP
+    dZ = dJQ + 1j * dJP
+    # tr(Z^{-1} dZ) per packet
+    Zt = np.moveaxis(Z, -1, 0)
+    dZt = np.moveaxis(dZ, -1, 0)
+    tr = np.trace(np.linalg.solve(Zt, dZt), axis1=1, axis2=2)
+    dA = 0.5 * A * tr
+    return dQ, dP, dS, dA, dJQ, dJP
+
+
+def propagate(Q, P, S, A, V: dict, dt: float, nsteps: int, JQ=None, JP=None):
+    """RK4 for (2.3)-(2.6) from (Q, P, S, A) at t = 0 over nsteps steps of dt.
+
+    Q, P: [d][N]; S: [N]; A: [N] complex.  JQ, JP default to I and -i I.
+    Returns (Q, P, S, A, JQ, JP) at t = nsteps dt.
+    """
+    Q = np.array(Q, dtype=np.float64)
+    P = np.array(P, dtype=np.float64)
+    S = np.array(S, dtype=np.float64)
+    A = np.array(A, dtype=np.complex128)
+    d, N = Q.shape
+    if JQ is None:
+        JQ = np.repeat(np.eye(d, dtype=np.complex128)[:, :, None], N, axis=2)
+    if JP is None:
+        JP = -1j * np.repeat(np.eye(d, dtype=np.complex128)[:, :, None], N, axis=2)
+    y = [Q, P, S, A, np.array(JQ, dtype=np.complex128), np.array(JP, dtype=np.complex128)]
+    for _ in range(int(nsteps)):
+        k1 = _rhs(V, *y)
+        k2 = _rhs(V, *[a + 0.5 * dt * b for a, b in zip(y, k1)])
+        k3 = _rhs(V, *[a + 0.5 * dt * b for a, b in zip(y, k2)])
+        k4 = _rhs(V, *[a + dt * b for a, b in zip(y, k3)])
+        y = [a + dt / 6.0 * (b1 + 2 * b2 + 2 * b3 + b4) for a, b1, b2, b3, b4 in zip(y, k1, k2, k3, k4)]
+    return tuple(y)

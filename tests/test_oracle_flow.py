@@ -1,0 +1,124 @@
+"""Pins of the flow oracle (eq. 2.3-2.6, RK4) against closed forms and invariants.
+
+- V = 0: Q = q + t p, S = t |p|^2 / 2, Z = (2 - i t) I and A = A0 (1 - i t/2)^{d/2}.
+- Harmonic V = sum_k w_k x_k^2 / 2: the closed-form flow, action and
+  Z_k = 2 cos(w t) - i (w + 1/w) sin(w t) per dimension (w = sqrt(w_k)).
+- The paper's cosine and exponential potentials: energy |P|^2/2 + V(Q) is
+  conserved, the real Jacobian of (q, p) -> (Q, P) is symplectic, and
+  A^2 / A0^2 = det Z / det Z(0) (eq. 2.6 integrates to this).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import flow
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def start(d, N, seed, q_scale=0.8):
+    rng = np.random.default_rng(seed)
+    q = rng.uniform(-q_scale, q_scale, (d, N))
+    p = 1.0 + 0.5 * rng.standard_normal((d, N))
+    A0 = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    return q, p, A0
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_free_flow_closed_form(d):
+    q, p, A0 = start(d, 50, 1)
+    t, n = 0.8, 400
+    Q, P, S, A, JQ, JP = flow.propagate(q, p, np.zeros(50), A0, flow.potential(), t / n, n)
+    assert rel(Q, q + t * p) < 1e-13
+    assert rel(P, p) == 0.0
+    assert rel(S, t * np.sum(p * p, axis=0) / 2) < 1e-13
+    assert rel(A, A0 * (1 - 0.5j * t) ** (d / 2)) < 1e-12
+    eye = np.eye(d)[:, :, None]
+    assert rel(JQ, (1 - 1j * t) * eye + 0 * JQ) < 1e-13
+    assert rel(JP, -1j * eye + 0 * JP) < 1e-13
+
+
+def test_harmonic_closed_form():
+    d, N = 2, 40
+    q, p, A0 = start(d, N, 2)
+    wk = np.array([1.0, 2.25])
+    om = np.sqrt(wk)[:, None]
+    t, n = 0.8, 800
+    Q, P, S, A, JQ, JP = flow.propagate(q, p, np.zeros(N), A0, flow.potential(w=wk), t / n, n)
+    c, s = np.cos(om * t), np.sin(om * t)
+    assert rel(Q, q * c + p / om * s) < 1e-12
+    assert rel(P, p * c - q * om * s) < 1e-12
+    S_ex = np.sum((p * p - om * om * q * q) * np.sin(2 * om * t) / (4 * om) - p * q * s * s, axis=0)
+    assert rel(S, S_ex) < 1e-11
+    Zk = 2 * c - 1j * (om + 1 / om) * s  # [d][1]
+    assert rel(A, A0 * np.prod(np.sqrt(Zk / 2), axis=0)) < 1e-11
+    Z = JQ + 1j * JP
+    for k in range(d):
+        assert np.allclose(Z[k, k], Zk[k, 0], rtol=1e-11, atol=0)
+        assert np.allclose(Z[k, 1 - k], 0.0, atol=1e-14)
+
+
+def real_jacobian(JQ, JP):
+    """[[dQ/dq, dQ/dp], [dP/dq, dP/dp]] from dz = d_q - i d_p of real maps."""
+    return np.block([[JQ.real.transpose(2, 0, 1), -JQ.imag.transpose(2, 0, 1)],
+                     [JP.real.transpose(2, 0, 1), -JP.imag.transpose(2, 0, 1)]])
+
+
+@pytest.mark.parametrize("d,V", [
+    (1, flow.potential(c0=1.0, c1=-1.0, kappa=math.pi)),          # 1 - cos(pi x)
+    # Example 2's V1 read as 1 - exp(-(x^2 + y^2)): the printed exp(+(x^2 + y^2))
+    # pushes packets out to infinity in finite time
+    (2, flow.potential(c0=1.0, c2=-1.0, c3=-1.0)),
+    (2, flow.potential(c0=0.3, w=(0.5, 2.0), c1=0.2, kappa=2.0, c2=0.4, c3=-1.5)),
+])
+def test_invariants(d, V):
+    N = 30
+    q, p, A0 = start(d, N, 3 + d, q_scale=0.6)
+    t, n = 0.8, 800
+    Q, P, S, A, JQ, JP = flow.propagate(q, p, np.zeros(N), A0, V, t / n, n)
+    H0 = 0.5 * np.sum(p * p, axis=0) + flow.v_grad_hess(V, q)[0]
+    H1 = 0.5 * np.sum(P * P, axis=0) + flow.v_grad_hess(V, Q)[0]
+    assert np.max(abs(H1 - H0) / (1 + abs(H0))) < 1e-9
+    # the motion is not trivial
+    assert np.max(abs(P - p)) > 0.05
+    Mj = real_jacobian(JQ, JP)
+    Om = np.block([[np.zeros((d, d)), np.eye(d)], [-np.eye(d), np.zeros((d, d))]])
+    assert np.max(abs(np.einsum("nji,jk,nkl->nil", Mj, Om, Mj) - Om)) < 1e-9
+    Z = (JQ + 1j * JP).transpose(2, 0, 1)
+    detZ = np.linalg.det(Z)
+    assert rel(A * A, A0 * A0 * detZ / 2 ** d) < 1e-9
+
+
+def test_planted_errors_fail():
+    """A wrong sign in the force or a missing 1/2 in (2.6) breaks the pins above."""
+    V = flow.potential(c0=1.0, c1=-1.0, kappa=math.pi)
+    q, p, A0 = start(1, 20, 9, q_scale=0.6)
+    good = flow.propagate(q, p, np.zeros(20), A0, V, 1e-3, 800)
+    orig = flow._rhs
+
+    def bad_force(V_, Q, P, S, A, JQ, JP):
+        r = list(orig(V_, Q, P, S, A, JQ, JP))
+        r[1] = -r[1]
+        return tuple(r)
+
+    def bad_amp(V_, Q, P, S, A, JQ, JP):
+        r = list(orig(V_, Q, P, S, A, JQ, JP))
+        r[3] = 2 * r[3]
+        return tuple(r)
+
+    try:
+        flow._rhs = bad_force
+        Q, P = flow.propagate(q, p, np.zeros(20), A0, V, 1e-3, 800)[:2]
+        H0 = 0.5 * p * p + flow.v_grad_hess(V, q)[0]
+        H1 = 0.5 * P * P + flow.v_grad_hess(V, Q)[0]
+        assert np.max(abs(H1 - H0)) > 1e-3
+        flow._rhs = bad_amp
+        A, JQ, JP = flow.propagate(q, p, np.zeros(20), A0, V, 1e-3, 800)[3:]
+        detZ = (JQ + 1j * JP)[0, 0]
+        assert rel(A * A, A0 * A0 * detZ / 2) > 1e-3
+    finally:
+        flow._rhs = orig
+    assert rel(good[0], q) > 0.1
