@@ -170,6 +170,40 @@ int fggc_direct_sum_separable(fggc_ctx *ctx, const fggc_packets *pk, double eps,
                               void *stream);
 
 /*
+ * Potential of the packet flow:
+ *   V(x) = c0 + sum_k w[k] x_k^2 / 2 + c1 sum_k cos(kappa x_k) + c2 exp(c3 |x|^2).
+ * The paper's examples (Sec. 4) are members: 1 - cos(pi x) (c0 = 1, c1 = -1,
+ * kappa = pi), |x|^2 / 2 (w = 1) and 1 - exp(-|x|^2) (c0 = 1, c2 = -1, c3 = -1).
+ */
+typedef struct {
+  double c0;
+  double w[3];
+  double c1, kappa;
+  double c2, c3;
+} fggc_potential;
+
+/*
+ * Propagate N packets along the Hamiltonian flow of eq. (2.3)-(2.6) for
+ * nsteps steps of the classical fourth-order Runge-Kutta scheme with step dt
+ * (the paper's time integrator, Sec. 4), in FP64, one thread per packet.
+ *   Q, P: [d][N] in/out; S: [N] in/out; a: [N] complex128 in/out (the
+ *   amplitude A of (2.6)).  Q is not wrapped into [-pi, pi): the flow is on
+ *   R^d, and the reconstruction calls take Q modulo 2 pi.
+ *   jac: NULL, or [N][2][d][d] complex128 in/out holding dz Q then dz P
+ *   (dz = d_q - i d_p, row-major), the Jacobians whose combination
+ *   Z = dz Q + i dz P enters (2.6).  With NULL every packet starts from
+ *   dz Q = I, dz P = -i I, i.e. from its initial point (q, p) of (2.3)-(2.4),
+ *   and the Jacobians are not returned; pass jac to continue a flow across
+ *   several calls.
+ * Buffers may be device or host memory (host buffers are staged and the call
+ * completes before it returns).  Errors: FGGC_EINVAL for d outside 1..3,
+ * N < 0, nsteps < 0, a NULL array with N > 0, a non-finite dt or potential
+ * coefficient.
+ */
+int fggc_propagate(fggc_ctx *ctx, int32_t d, int64_t N, double *Q, double *P, double *S, double *a,
+                   double *jac, const fggc_potential *V, double dt, int64_t nsteps, void *stream);
+
+/*
  * FGGC reconstruction (Alg. 2 steps 3-4 with eq. 2.23-2.25):
  *   per packet and dimension, int/frac split (3.6)-(3.7), right-hand side
  *   (3.23), least squares against the precomputed Gram matrix (3.22) through

@@ -566,6 +566,44 @@ int fggc_direct_sum_separable(fggc_ctx *ctx, const fggc_packets *pk, double eps,
                      scale, precision, u_out, stream, 1);
 }
 
+int fggc_propagate(fggc_ctx *ctx, int32_t d, int64_t N, double *Q, double *P, double *S, double *a,
+                   double *jac, const fggc_potential *V, double dt, int64_t nsteps, void *stream) {
+  return guarded("fggc_propagate", [&] {
+    if (!ctx || !V) fail(FGGC_EINVAL, "NULL argument");
+    if (d < 1 || d > 3) fail(FGGC_EINVAL, "d must be 1, 2 or 3");
+    if (N < 0 || N > 0x7fffffffLL) fail(FGGC_EINVAL, "packet count out of range [0, 2^31)");
+    if (nsteps < 0) fail(FGGC_EINVAL, "nsteps must be >= 0");
+    if (N > 0 && (!Q || !P || !S || !a)) fail(FGGC_EINVAL, "packet array is NULL");
+    if (!std::isfinite(dt)) fail(FGGC_EINVAL, "dt must be finite");
+    const double coef[] = {V->c0, V->w[0], V->w[1], V->w[2], V->c1, V->kappa, V->c2, V->c3};
+    for (double c : coef)
+      if (!std::isfinite(c)) fail(FGGC_EINVAL, "potential coefficients must be finite");
+    if (N == 0 || nsteps == 0) return;
+    Guard lock(ctx);
+    hipStream_t s = (hipStream_t)stream;
+    WsUse wsu(ctx, s);
+    const size_t dN = (size_t)d * N * 8, N8 = (size_t)N * 8, jb = jac ? (size_t)N * 4 * d * d * 8 : 0;
+    const bool host = !(device_accessible(Q) && device_accessible(P) && device_accessible(S) &&
+                        device_accessible(a) && (!jac || device_accessible(jac)));
+    if (!host) {
+      launch_propagate(d, N, Q, P, S, a, jac, *V, dt, nsteps, s);
+      return;
+    }
+    ctx->ws.reserve(2 * dN + 3 * N8 + jb + 5 * 256, ctx->budget);
+    double *dQ = (double *)ctx->ws.take(dN), *dP = (double *)ctx->ws.take(dN);
+    double *dS = (double *)ctx->ws.take(N8), *da = (double *)ctx->ws.take(2 * N8);
+    double *dj = jac ? (double *)ctx->ws.take(jb) : nullptr;
+    struct Arr { double *host, *dev; size_t bytes; } arrs[] = {
+        {Q, dQ, dN}, {P, dP, dN}, {S, dS, N8}, {a, da, 2 * N8}, {jac, dj, jb}};
+    for (const Arr &x : arrs)
+      if (x.bytes) FGGC_HIP(hipMemcpyAsync(x.dev, x.host, x.bytes, hipMemcpyDefault, s));
+    launch_propagate(d, N, dQ, dP, dS, da, dj, *V, dt, nsteps, s);
+    for (const Arr &x : arrs)
+      if (x.bytes) FGGC_HIP(hipMemcpyAsync(x.host, x.dev, x.bytes, hipMemcpyDefault, s));
+    FGGC_HIP(hipStreamSynchronize(s));
+  });
+}
+
 int fggc_cell_box(fggc_ctx *ctx, const fggc_packets *pk, const fggc_strategy *st,
                   int64_t *slice_lo, int64_t *slice_n, void *stream) {
   return guarded("fggc_cell_box", [&] {

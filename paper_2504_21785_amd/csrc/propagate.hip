@@ -1,0 +1,233 @@
+// Packet flow of eq. (2.3)-(2.6) on gfx950: one thread per packet, FP64,
+// classical fourth-order Runge-Kutta.
+//
+// State of a packet: Q and P (d each), S, A (complex) and the Jacobians
+// JQ = dz Q and JP = dz P (d x d complex, dz = d_q - i d_p) whose combination
+// Z = JQ + i JP enters (2.6).  Differentiating (2.3)-(2.4) along dz gives
+//   dJQ/dt = JP,   dJP/dt = -Hess V(Q) JQ,
+// and (2.6) reads dA/dt = (A/2) tr(Z^{-1} dZ/dt) with dZ/dt = JP - i Hess V(Q) JQ.
+// The potential family is
+//   V(x) = c0 + sum_k w_k x_k^2 / 2 + c1 sum_k cos(kappa x_k) + c2 exp(c3 |x|^2),
+// with its gradient and Hessian in closed form.
+//
+// The state lives in registers as NV doubles; a step keeps the state, the
+// running RK4 sum, the stage point and one stage derivative.
+#include "common.h"
+
+namespace fggc {
+namespace {
+
+template <int D> struct FlowLayout {
+  static constexpr int kQ = 0, kP = D, kS = 2 * D, kA = 2 * D + 1, kJQ = 2 * D + 3, kJP = kJQ + 2 * D * D;
+  static constexpr int NV = kJP + 2 * D * D;
+};
+
+struct PropParams {
+  int64_t N;
+  double *Q, *P, *S, *a;  // [d][N], [d][N], [N], [N] complex
+  double *jac;            // [N][2][d][d] complex or null
+  fggc_potential V;
+  double dt;
+  int64_t nsteps;
+};
+
+// d/dt of the state y, written to k
+template <int D>
+__device__ __forceinline__ void flow_rhs(const double *y, const fggc_potential &V, double *k) {
+  using L = FlowLayout<D>;
+  const double *q = y + L::kQ, *p = y + L::kP;
+  double r2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) r2 = fma(q[i], q[i], r2);
+  const double E = V.c2 != 0.0 ? V.c2 * exp(V.c3 * r2) : 0.0;
+  double val = V.c0 + E, g[D], hd[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double sn = 0.0, cs = 0.0;
+    if (V.c1 != 0.0) sincos(V.kappa * q[i], &sn, &cs);
+    val += 0.5 * V.w[i] * q[i] * q[i] + V.c1 * cs;
+    g[i] = V.w[i] * q[i] - V.c1 * V.kappa * sn + 2.0 * V.c3 * q[i] * E;
+    hd[i] = V.w[i] - V.c1 * V.kappa * V.kappa * cs + 2.0 * V.c3 * E;
+  }
+  double H[D][D];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int m = 0; m < D; ++m) H[i][m] = (i == m ? hd[i] : 0.0) + 4.0 * V.c3 * V.c3 * q[i] * q[m] * E;
+
+  double ps = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    k[L::kQ + i] = p[i];
+    k[L::kP + i] = -g[i];
+    ps = fma(p[i], p[i], ps);
+  }
+  k[L::kS] = 0.5 * ps - val;
+  // dJQ = JP; dJP = -H JQ (complex entries as (re, im) pairs, row-major)
+  const double *jq = y + L::kJQ, *jp = y + L::kJP;
+#pragma unroll
+  for (int e = 0; e < 2 * D * D; ++e) k[L::kJQ + e] = jp[e];
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int l = 0; l < D; ++l) {
+        re = fma(-H[i][l], jq[2 * (l * D + m)], re);
+        im = fma(-H[i][l], jq[2 * (l * D + m) + 1], im);
+      }
+      k[L::kJP + 2 * (i * D + m)] = re;
+      k[L::kJP + 2 * (i * D + m) + 1] = im;
+    }
+  // Z = JQ + i JP and dZ = dJQ + i dJP
+  double zr[D * D], zi[D * D], wr[D * D], wi[D * D];
+#pragma unroll
+  for (int e = 0; e < D * D; ++e) {
+    zr[e] = jq[2 * e] - jp[2 * e + 1];
+    zi[e] = jq[2 * e + 1] + jp[2 * e];
+    wr[e] = k[L::kJQ + 2 * e] - k[L::kJP + 2 * e + 1];
+    wi[e] = k[L::kJQ + 2 * e + 1] + k[L::kJP + 2 * e];
+  }
+  // tr(Z^{-1} dZ) = tr(adj(Z) dZ) / det Z
+  double cr[D * D], ci[D * D], detr, deti;  // cofactor matrix C (adj = C^T)
+  if constexpr (D == 1) {
+    cr[0] = 1.0;
+    ci[0] = 0.0;
+    detr = zr[0];
+    deti = zi[0];
+  } else if constexpr (D == 2) {
+    cr[0] = zr[3]; ci[0] = zi[3];
+    cr[1] = -zr[2]; ci[1] = -zi[2];
+    cr[2] = -zr[1]; ci[2] = -zi[1];
+    cr[3] = zr[0]; ci[3] = zi[0];
+    detr = zr[0] * zr[3] - zi[0] * zi[3] - (zr[1] * zr[2] - zi[1] * zi[2]);
+    deti = zr[0] * zi[3] + zi[0] * zr[3] - (zr[1] * zi[2] + zi[1] * zr[2]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, m1 = (m + 1) % 3, m2 = (m + 2) % 3;
+        // C_im = z[i1][m1] z[i2][m2] - z[i1][m2] z[i2][m1]
+        const double ar = zr[i1 * 3 + m1], ai = zi[i1 * 3 + m1], br = zr[i2 * 3 + m2], bi = zi[i2 * 3 + m2];
+        const double cr2 = zr[i1 * 3 + m2], ci2 = zi[i1 * 3 + m2], dr = zr[i2 * 3 + m1], di = zi[i2 * 3 + m1];
+        cr[i * 3 + m] = ar * br - ai * bi - (cr2 * dr - ci2 * di);
+        ci[i * 3 + m] = ar * bi + ai * br - (cr2 * di + ci2 * dr);
+      }
+    detr = deti = 0.0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      detr += zr[m] * cr[m] - zi[m] * ci[m];
+      deti += zr[m] * ci[m] + zi[m] * cr[m];
+    }
+  }
+  // tr(adj(Z) dZ) = sum_{i,m} C_mi dZ_mi
+  double tr = 0.0, ti = 0.0;
+#pragma unroll
+  for (int e = 0; e < D * D; ++e) {
+    tr += cr[e] * wr[e] - ci[e] * wi[e];
+    ti += cr[e] * wi[e] + ci[e] * wr[e];
+  }
+  const double dd = detr * detr + deti * deti;
+  const double qr = (tr * detr + ti * deti) / dd, qi = (ti * detr - tr * deti) / dd;
+  const double ar = y[L::kA], ai = y[L::kA + 1];
+  k[L::kA] = 0.5 * (ar * qr - ai * qi);
+  k[L::kA + 1] = 0.5 * (ar * qi + ai * qr);
+}
+
+template <int D>
+__global__ __launch_bounds__(D < 3 ? 256 : 64) void propagate_kernel(PropParams p) {
+  using L = FlowLayout<D>;
+  constexpr int NV = L::NV;
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= p.N) return;
+  double y[NV];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    y[L::kQ + i] = p.Q[i * p.N + j];
+    y[L::kP + i] = p.P[i * p.N + j];
+  }
+  y[L::kS] = p.S[j];
+  y[L::kA] = p.a[2 * j];
+  y[L::kA + 1] = p.a[2 * j + 1];
+  if (p.jac) {
+    const double *src = p.jac + (size_t)j * 4 * D * D;
+#pragma unroll
+    for (int e = 0; e < 4 * D * D; ++e) y[L::kJQ + e] = src[e];
+  } else {
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        y[L::kJQ + 2 * (i * D + m)] = i == m ? 1.0 : 0.0;
+        y[L::kJQ + 2 * (i * D + m) + 1] = 0.0;
+        y[L::kJP + 2 * (i * D + m)] = 0.0;
+        y[L::kJP + 2 * (i * D + m) + 1] = i == m ? -1.0 : 0.0;
+      }
+  }
+  const fggc_potential V = p.V;
+  const double h = p.dt, h2 = 0.5 * p.dt, h3 = p.dt / 3.0, h6 = p.dt / 6.0;
+  for (int64_t n = 0; n < p.nsteps; ++n) {
+    double acc[NV], st[NV], k[NV];
+    flow_rhs<D>(y, V, k);
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      acc[e] = fma(h6, k[e], y[e]);
+      st[e] = fma(h2, k[e], y[e]);
+    }
+    flow_rhs<D>(st, V, k);
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      acc[e] = fma(h3, k[e], acc[e]);
+      st[e] = fma(h2, k[e], y[e]);
+    }
+    flow_rhs<D>(st, V, k);
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      acc[e] = fma(h3, k[e], acc[e]);
+      st[e] = fma(h, k[e], y[e]);
+    }
+    flow_rhs<D>(st, V, k);
+#pragma unroll
+    for (int e = 0; e < NV; ++e) y[e] = fma(h6, k[e], acc[e]);
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    p.Q[i * p.N + j] = y[L::kQ + i];
+    p.P[i * p.N + j] = y[L::kP + i];
+  }
+  p.S[j] = y[L::kS];
+  p.a[2 * j] = y[L::kA];
+  p.a[2 * j + 1] = y[L::kA + 1];
+  if (p.jac) {
+    double *dst = p.jac + (size_t)j * 4 * D * D;
+#pragma unroll
+    for (int e = 0; e < 4 * D * D; ++e) dst[e] = y[L::kJQ + e];
+  }
+}
+
+}  // namespace
+
+void launch_propagate(int d, int64_t N, double *Q, double *P, double *S, double *a, double *jac,
+                      const fggc_potential &V, double dt, int64_t nsteps, hipStream_t s) {
+  if (N == 0) return;
+  PropParams p{};
+  p.N = N;
+  p.Q = Q;
+  p.P = P;
+  p.S = S;
+  p.a = a;
+  p.jac = jac;
+  p.V = V;
+  p.dt = dt;
+  p.nsteps = nsteps;
+  const int blk = d < 3 ? 256 : 64;
+  const dim3 g((unsigned)((N + blk - 1) / blk)), b(blk);
+  if (d == 1) propagate_kernel<1><<<g, b, 0, s>>>(p);
+  else if (d == 2) propagate_kernel<2><<<g, b, 0, s>>>(p);
+  else propagate_kernel<3><<<g, b, 0, s>>>(p);
+  FGGC_HIP(hipGetLastError());
+}
+
+}  // namespace fggc

@@ -57,6 +57,20 @@ class Strategy(ctypes.Structure):
                 "dp_off": list(self.dp_off[:self.np]), "cutoff": self.cutoff}
 
 
+class Potential(ctypes.Structure):
+    """V(x) = c0 + sum_k w_k x_k^2 / 2 + c1 sum_k cos(kappa x_k) + c2 exp(c3 |x|^2)."""
+    _fields_ = [("c0", ctypes.c_double), ("w", ctypes.c_double * 3), ("c1", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("c2", ctypes.c_double), ("c3", ctypes.c_double)]
+
+
+def potential(c0=0.0, w=(0.0, 0.0, 0.0), c1=0.0, kappa=0.0, c2=0.0, c3=0.0) -> Potential:
+    V = Potential()
+    V.c0, V.c1, V.kappa, V.c2, V.c3 = float(c0), float(c1), float(kappa), float(c2), float(c3)
+    for k, v in enumerate((list(w) + [0.0, 0.0, 0.0])[:3]):
+        V.w[k] = float(v)
+    return V
+
+
 _lib = None
 
 # (name, restype, argtypes) of every function in include/fggc.h
@@ -73,6 +87,8 @@ _SIGS = [
                                        _VP, _VP]),
     ("fggc_reconstruct", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid),
                               ctypes.POINTER(Strategy), _D, _I, _VP, _VP]),
+    ("fggc_propagate", _I, [_VP, ctypes.c_int32, _I64, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(Potential), _D,
+                            _I64, _VP]),
     ("fggc_default_strategy", _I, [_I, _D, ctypes.c_char_p, ctypes.POINTER(Strategy)]),
     ("fggc_cell_box", _I, [_VP, ctypes.POINTER(Packets), ctypes.POINTER(Strategy),
                            ctypes.POINTER(_I64), ctypes.POINTER(_I64), _VP]),
@@ -270,6 +286,24 @@ class Context:
                                                float(window_half_width), float(scale), int(precision),
                                                _ptr(out), _stream_ptr(stream) if _on_device(Q) else None))
         return out
+
+    def propagate(self, Q, P, S, a, V: Potential, dt: float, nsteps: int, jac=None, stream=None):
+        """fggc_propagate: RK4 for eq. (2.3)-(2.6), in place on Q, P, S, a (and jac).
+
+        Q, P: [d][N] float64; S: [N] float64; a: [N] complex128; jac: None or
+        [N][2][d][d] complex128.  Torch tensors on the GPU run stream-ordered;
+        numpy arrays are staged (synchronous).
+        """
+        d, N = int(Q.shape[0]), int(Q.shape[1])
+        for x in (Q, P, S, a) + ((jac,) if jac is not None else ()):
+            if hasattr(x, "is_contiguous") and not x.is_contiguous():
+                raise ValueError("propagate works in place: arrays must be contiguous")
+            if isinstance(x, np.ndarray) and not x.flags["C_CONTIGUOUS"]:
+                raise ValueError("propagate works in place: arrays must be contiguous")
+        _check(lib().fggc_propagate(self.h, d, N, _ptr(Q), _ptr(P), _ptr(S), _ptr(a),
+                                    _ptr(jac) if jac is not None else None, ctypes.byref(V), float(dt),
+                                    int(nsteps), _stream_ptr(stream) if _on_device(Q) else None))
+        return Q, P, S, a
 
     def reconstruct(self, Q, P, S, a, eps: float, M, strategy: Strategy, scale: float = 1.0,
                     precision: int = FP32, out=None, stream=None):
