@@ -1,4 +1,5 @@
-"""Plain FP64 oracle for the packet flow of eq. (2.3)-(2.6), in numpy.
+"""Plain FP64 oracle for the steps either side of the reconstruction, in numpy:
+the initial decomposition (2.7) and the packet flow of eq. (2.3)-(2.6).
 
 TEST INFRASTRUCTURE ONLY: imported by the test suite, never by the product
 package.  It shares no code with the HIP path.
@@ -88,3 +89,30 @@ def propagate(Q, P, S, A, V: dict, dt: float, nsteps: int, JQ=None, JP=None):
         k4 = _rhs(V, *[a + dt * b for a, b in zip(y, k3)])
         y = [a + dt / 6.0 * (b1 + 2 * b2 + 2 * b3 + b4) for a, b1, b2, b3, b4 in zip(y, k1, k2, k3, k4)]
     return tuple(y)
+
+
+def decompose(u0, eps, M, R, q, p):
+    """A(0, q, p) = 2^{d/2} u0^(q, p) of eq. (2.6)-(2.7) by quadrature on the grid.
+
+    u0^(q, p) = int u0(y) exp(-i p.(y - q)/eps - |y - q|^2/(2 eps)) dy, with u0
+    sampled on the periodic grid x_m = -pi + m 2 pi / M (row-major, [prod M]),
+    y - q taken as the minimum image and the integrand kept for |y - q| <= R
+    (the window of the direct sum); weight prod_k 2 pi / M_k.  q, p: [d][N].
+    """
+    M = [int(m) for m in np.atleast_1d(M)]
+    d = len(M)
+    axes = [-np.pi + 2 * np.pi * np.arange(m) / m for m in M]
+    X = np.stack([g.ravel() for g in np.meshgrid(*axes, indexing="ij")])  # [d][npts]
+    u = np.asarray(u0, dtype=np.complex128).ravel()
+    w = np.prod([2 * np.pi / m for m in M])
+    q = np.asarray(q, dtype=np.float64).reshape(d, -1)
+    p = np.asarray(p, dtype=np.float64).reshape(d, -1)
+    out = np.zeros(q.shape[1], dtype=np.complex128)
+    for j in range(q.shape[1]):
+        y = X - q[:, j:j + 1]
+        y = y - 2 * np.pi * np.floor((y + np.pi) / (2 * np.pi))
+        r2 = np.sum(y * y, axis=0)
+        keep = r2 <= R * R
+        ph = -np.sum(p[:, j:j + 1] * y[:, keep], axis=0) / eps
+        out[j] = np.sum(u[keep] * np.exp(1j * ph - r2[keep] / (2 * eps))) * w
+    return 2 ** (d / 2) * out

@@ -122,3 +122,56 @@ def test_planted_errors_fail():
     finally:
         flow._rhs = orig
     assert rel(good[0], q) > 0.1
+
+
+# --------------------------------------------------------------------------
+# initial decomposition (2.7)
+# --------------------------------------------------------------------------
+
+def gaussian_transform(alpha, beta, eps, q, p):
+    """u0^ of u0 = exp(-alpha y^2 + i beta y) in closed form (one dimension):
+    int exp(-a y^2 + b y + c) dy = sqrt(pi / a) exp(b^2 / (4 a) + c)."""
+    a = alpha + 1 / (2 * eps)
+    b = 1j * beta - 1j * p / eps + q / eps
+    c = 1j * p * q / eps - q * q / (2 * eps)
+    return np.sqrt(np.pi / a) * np.exp(b * b / (4 * a) + c)
+
+
+def test_decomposition_gaussian_closed_form():
+    eps, M, alpha, beta = 1 / 64, 2048, 32.0, 64.0
+    x = -math.pi + 2 * math.pi * np.arange(M) / M
+    u0 = np.exp(-alpha * x * x + 1j * beta * x)
+    rng = np.random.default_rng(4)
+    q = rng.uniform(-0.4, 0.4, (1, 40))
+    p = 1.0 + 0.3 * rng.standard_normal((1, 40))
+    A = flow.decompose(u0, eps, [M], 8 * math.sqrt(eps), q, p)
+    ref = math.sqrt(2) * gaussian_transform(alpha, beta, eps, q[0], p[0])
+    assert rel(A, ref) < 1e-12
+    # 2D: a product Gaussian decomposes into the product of 1D transforms (2^{d/2} = 2)
+    M2 = 256
+    x2 = -math.pi + 2 * math.pi * np.arange(M2) / M2
+    eps2 = 1 / 16
+    g1 = np.exp(-8.0 * x2 * x2 + 4j * x2)
+    g2 = np.exp(-6.0 * x2 * x2 - 2j * x2)
+    u2 = np.outer(g1, g2)
+    q2 = rng.uniform(-0.3, 0.3, (2, 12))
+    p2 = rng.uniform(-1, 1, (2, 12))
+    A2 = flow.decompose(u2, eps2, [M2, M2], 3.0, q2, p2)
+    ref2 = 2 * gaussian_transform(8.0, 4.0, eps2, q2[0], p2[0]) * gaussian_transform(6.0, -2.0, eps2, q2[1], p2[1])
+    assert rel(A2, ref2) < 1e-10
+
+
+def test_decomposition_reproduces_u0(orc):
+    """Prop. 1 (eq. 2.9): the packets of (2.7) on the mesh dq = sqrt(eps)/2,
+    dp = pi sqrt(eps)/8 sum back to u0 with weight (dq dp)/(2 pi eps)^{3/2}."""
+    eps, M = 1 / 64, 1024
+    x = -math.pi + 2 * math.pi * np.arange(M) / M
+    u0 = (64 / math.pi) ** 0.25 * np.exp(-32 * x * x + 1j * x / eps)
+    dq, dp = math.sqrt(eps) / 2, math.pi * math.sqrt(eps) / 8
+    qs = np.arange(-1.0, 1.0 + 1e-12, dq)
+    ps_ = 1.0 + np.arange(-1.0, 1.0 + 1e-12, dp)
+    qq, pp = [g.ravel()[None, :] for g in np.meshgrid(qs, ps_, indexing="ij")]
+    A = flow.decompose(u0, eps, [M], 8 * math.sqrt(eps), qq, pp)
+    scale = dq * dp / (2 * math.pi * eps) ** 1.5
+    u = orc.direct_sum(qq, pp, np.zeros(qq.shape[1]), A, eps, [M], 6 * math.sqrt(eps), scale)
+    assert rel(u, u0) < 1e-7
