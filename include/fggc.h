@@ -170,6 +170,22 @@ int fggc_direct_sum_separable(fggc_ctx *ctx, const fggc_packets *pk, double eps,
                               void *stream);
 
 /*
+ * Initial decomposition, eq. (2.6)-(2.7): for each of N phase-space points
+ * (q_j, p_j),
+ *   A_j = 2^{d/2} sum_m u0(x_m) exp(-i p_j.y / eps - |y|^2 / (2 eps)) prod_k (2 pi / n_k),
+ * y = minimum image of x_m - q_j, over the grid points with |y| <= window_radius
+ * (the quadrature of u0^ on the grid; the Gaussian bounds the dropped tail
+ * by exp(-R^2 / (2 eps))).  u0: the grid's values, complex128, row-major;
+ * q, p: [d][N] FP64; A_out: [N] complex128, the amplitudes A(0, q, p) that
+ * start the flow (fggc_propagate) and, with the weight
+ * (dq dp)^d / (2 pi eps)^{3d/2}, reproduce u0 through eq. (2.9).
+ * Buffers may be device or host memory.  FP64.  Errors: FGGC_EINVAL for a
+ * bad grid, eps <= 0, window_radius outside (0, pi), N < 0 or a NULL array.
+ */
+int fggc_decompose(fggc_ctx *ctx, const fggc_grid *grid, const double *u0, double eps, double window_radius,
+                   int64_t N, const double *q, const double *p, double *A_out, void *stream);
+
+/*
  * Potential of the packet flow:
  *   V(x) = c0 + sum_k w[k] x_k^2 / 2 + c1 sum_k cos(kappa x_k) + c2 exp(c3 |x|^2).
  * The paper's examples (Sec. 4) are members: 1 - cos(pi x) (c0 = 1, c1 = -1,

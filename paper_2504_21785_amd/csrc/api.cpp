@@ -566,6 +566,41 @@ int fggc_direct_sum_separable(fggc_ctx *ctx, const fggc_packets *pk, double eps,
                      scale, precision, u_out, stream, 1);
 }
 
+int fggc_decompose(fggc_ctx *ctx, const fggc_grid *grid, const double *u0, double eps, double window_radius,
+                   int64_t N, const double *q, const double *p, double *A_out, void *stream) {
+  return guarded("fggc_decompose", [&] {
+    if (!ctx) fail(FGGC_EINVAL, "ctx is NULL");
+    GridGeom g = check_grid(grid);
+    check_eps(eps);
+    if (!(window_radius > 0) || !(window_radius < kPi)) fail(FGGC_EINVAL, "window_radius must be in (0, pi)");
+    if (N < 0 || N > 0x7fffffffLL) fail(FGGC_EINVAL, "packet count out of range [0, 2^31)");
+    if (!u0) fail(FGGC_EINVAL, "u0 is NULL");
+    if (N > 0 && (!q || !p || !A_out)) fail(FGGC_EINVAL, "packet array is NULL");
+    if (N == 0) return;
+    Guard lock(ctx);
+    hipStream_t s = (hipStream_t)stream;
+    WsUse wsu(ctx, s);
+    int64_t npts = 1;
+    for (int k = 0; k < g.d; ++k) npts *= g.n[k];
+    const size_t ub = (size_t)npts * 16, qb = (size_t)g.d * N * 8, ab = (size_t)N * 16;
+    const bool host = !(device_accessible(u0) && device_accessible(q) && device_accessible(p) &&
+                        device_accessible(A_out));
+    if (!host) {
+      launch_decompose(g.d, g.n, u0, eps, window_radius, N, q, p, A_out, s);
+      return;
+    }
+    ctx->ws.reserve(ub + 2 * qb + ab + 4 * 256, ctx->budget);
+    double *du = (double *)ctx->ws.take(ub), *dq = (double *)ctx->ws.take(qb), *dp = (double *)ctx->ws.take(qb);
+    double *da = (double *)ctx->ws.take(ab);
+    FGGC_HIP(hipMemcpyAsync(du, u0, ub, hipMemcpyDefault, s));
+    FGGC_HIP(hipMemcpyAsync(dq, q, qb, hipMemcpyDefault, s));
+    FGGC_HIP(hipMemcpyAsync(dp, p, qb, hipMemcpyDefault, s));
+    launch_decompose(g.d, g.n, du, eps, window_radius, N, dq, dp, da, s);
+    FGGC_HIP(hipMemcpyAsync(A_out, da, ab, hipMemcpyDefault, s));
+    FGGC_HIP(hipStreamSynchronize(s));
+  });
+}
+
 int fggc_propagate(fggc_ctx *ctx, int32_t d, int64_t N, double *Q, double *P, double *S, double *a,
                    double *jac, const fggc_potential *V, double dt, int64_t nsteps, void *stream) {
   return guarded("fggc_propagate", [&] {

@@ -227,6 +227,9 @@ void bucket_positions(const uint32_t *keys, int64_t N, int64_t nbins, uint32_t *
                       void *scratch, hipStream_t s);
 
 // Direct sum.  Returns after enqueuing; `ws` supplies scratch.
+// Initial decomposition (2.7) by windowed quadrature; device pointers, stream-ordered.
+void launch_decompose(int d, const int64_t *n, const double *u0, double eps, double R, int64_t N,
+                      const double *q, const double *p, double *A, hipStream_t s);
 // Packet flow (RK4 for eq. 2.3-2.6); device pointers, stream-ordered.
 void launch_propagate(int d, int64_t N, double *Q, double *P, double *S, double *a, double *jac,
                       const fggc_potential &V, double dt, int64_t nsteps, hipStream_t s);

@@ -1,5 +1,8 @@
-// Packet flow of eq. (2.3)-(2.6) on gfx950: one thread per packet, FP64,
-// classical fourth-order Runge-Kutta.
+// The steps either side of the reconstruction, on gfx950:
+//   - the initial decomposition (2.7): A(0, q, p) = 2^{d/2} u0^(q, p) by
+//     windowed quadrature on the grid, one wave per packet;
+//   - the packet flow of eq. (2.3)-(2.6): one thread per packet, FP64,
+//     classical fourth-order Runge-Kutta.
 //
 // State of a packet: Q and P (d each), S, A (complex) and the Jacobians
 // JQ = dz Q and JP = dz P (d x d complex, dz = d_q - i d_p) whose combination
@@ -207,7 +210,105 @@ __global__ __launch_bounds__(D < 3 ? 256 : 64) void propagate_kernel(PropParams 
   }
 }
 
+struct DecParams {
+  int d;
+  int64_t N;
+  int64_t n[3];
+  double dx[3];
+  int64_t W[3];   // window half-width in grid steps
+  double R2, inv2eps, inveps, wscale;  // wscale = 2^{d/2} prod dx
+  const double *u0;  // grid, complex, row-major
+  const double *q, *p;
+  double *A;
+};
+
+// u0^(q, p) = sum over grid points m with |y| <= R of
+//   u0(x_m) exp(-i p.y / eps - |y|^2 / (2 eps)) prod dx,  y = minimum image of x_m - q,
+// the lanes of a wave striding over the box of grid points around q.
+__global__ __launch_bounds__(256) void decompose_kernel(DecParams p) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= p.N) return;  // uniform per wave
+  double qk[3] = {0, 0, 0}, pk[3] = {0, 0, 0};
+  int64_t start[3] = {0, 0, 0}, side[3] = {1, 1, 1}, total = 1;
+  for (int k = 0; k < p.d; ++k) {
+    qk[k] = p.q[k * p.N + j];
+    pk[k] = p.p[k * p.N + j];
+    const double t = (qk[k] + kPi) - kTwoPi * floor((qk[k] + kPi) / kTwoPi);
+    int64_t c = (int64_t)rint(t / p.dx[k]);
+    if (c >= p.n[k]) c -= p.n[k];
+    if (2 * p.W[k] + 1 >= p.n[k]) {
+      start[k] = 0;
+      side[k] = p.n[k];
+    } else {
+      start[k] = c - p.W[k];
+      if (start[k] < 0) start[k] += p.n[k];
+      side[k] = 2 * p.W[k] + 1;
+    }
+    total *= side[k];
+  }
+  double ar = 0.0, ai = 0.0;
+  for (int64_t e = lane; e < total; e += 64) {
+    int64_t rem = e, flat = 0;
+    double r2 = 0.0, th = 0.0;
+    int64_t mk[3] = {0, 0, 0};
+    for (int k = p.d - 1; k >= 0; --k) {
+      int64_t m = start[k] + rem % side[k];
+      rem /= side[k];
+      if (m >= p.n[k]) m -= p.n[k];
+      mk[k] = m;
+    }
+    for (int k = 0; k < p.d; ++k) {
+      double y = (-kPi + (double)mk[k] * p.dx[k]) - qk[k];
+      y -= kTwoPi * floor((y + kPi) / kTwoPi);
+      r2 = fma(y, y, r2);
+      th = fma(-pk[k], y, th);
+      flat = flat * p.n[k] + mk[k];
+    }
+    if (r2 <= p.R2) {
+      const double g = exp(-r2 * p.inv2eps);
+      double sn, cs;
+      sincos(th * p.inveps, &sn, &cs);
+      const double ur = p.u0[2 * flat], ui = p.u0[2 * flat + 1];
+      ar = fma(g, ur * cs - ui * sn, ar);
+      ai = fma(g, ur * sn + ui * cs, ai);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ar += __shfl_xor(ar, off);
+    ai += __shfl_xor(ai, off);
+  }
+  if (lane == 0) {
+    p.A[2 * j] = p.wscale * ar;
+    p.A[2 * j + 1] = p.wscale * ai;
+  }
+}
+
 }  // namespace
+
+void launch_decompose(int d, const int64_t *n, const double *u0, double eps, double R, int64_t N,
+                      const double *q, const double *pm, double *A, hipStream_t s) {
+  if (N == 0) return;
+  DecParams p{};
+  p.d = d;
+  p.N = N;
+  p.wscale = std::pow(2.0, 0.5 * d);
+  for (int k = 0; k < 3; ++k) {
+    p.n[k] = k < d ? n[k] : 1;
+    p.dx[k] = k < d ? kTwoPi / (double)n[k] : 1.0;
+    p.W[k] = k < d ? (int64_t)std::floor(R / p.dx[k]) + 1 : 0;
+    if (k < d) p.wscale *= p.dx[k];
+  }
+  p.R2 = R * R;
+  p.inv2eps = 1.0 / (2.0 * eps);
+  p.inveps = 1.0 / eps;
+  p.u0 = u0;
+  p.q = q;
+  p.p = pm;
+  p.A = A;
+  decompose_kernel<<<dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s>>>(p);
+  FGGC_HIP(hipGetLastError());
+}
 
 void launch_propagate(int d, int64_t N, double *Q, double *P, double *S, double *a, double *jac,
                       const fggc_potential &V, double dt, int64_t nsteps, hipStream_t s) {

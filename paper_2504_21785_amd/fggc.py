@@ -87,6 +87,7 @@ _SIGS = [
                                        _VP, _VP]),
     ("fggc_reconstruct", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid),
                               ctypes.POINTER(Strategy), _D, _I, _VP, _VP]),
+    ("fggc_decompose", _I, [_VP, ctypes.POINTER(Grid), _VP, _D, _D, _I64, _VP, _VP, _VP, _VP]),
     ("fggc_propagate", _I, [_VP, ctypes.c_int32, _I64, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(Potential), _D,
                             _I64, _VP]),
     ("fggc_default_strategy", _I, [_I, _D, ctypes.c_char_p, ctypes.POINTER(Strategy)]),
@@ -285,6 +286,24 @@ class Context:
         _check(lib().fggc_direct_sum_separable(self.h, ctypes.byref(pk), float(eps), ctypes.byref(g),
                                                float(window_half_width), float(scale), int(precision),
                                                _ptr(out), _stream_ptr(stream) if _on_device(Q) else None))
+        return out
+
+    def decompose(self, u0, eps: float, M, window_radius: float, q, p, out=None, stream=None):
+        """fggc_decompose: A(0, q, p) of eq. (2.7) for the [d][N] points (q, p) from u0 on the grid.
+
+        u0: complex128 grid values (torch on the GPU, or numpy).  Returns A
+        ([N] complex128, allocated like q when out is None).
+        """
+        d, N = int(q.shape[0]), int(q.shape[1])
+        g = _grid(d, M)
+        if out is None:
+            if hasattr(q, "device"):
+                import torch
+                out = torch.empty(N, dtype=torch.complex128, device=q.device)
+            else:
+                out = np.empty(N, dtype=np.complex128)
+        _check(lib().fggc_decompose(self.h, ctypes.byref(g), _ptr(u0), float(eps), float(window_radius), N,
+                                    _ptr(q), _ptr(p), _ptr(out), _stream_ptr(stream) if _on_device(q) else None))
         return out
 
     def propagate(self, Q, P, S, a, V: Potential, dt: float, nsteps: int, jac=None, stream=None):

@@ -1,9 +1,12 @@
-"""Packet flow (eq. 2.3-2.6, RK4) on the GPU against the flow oracle.
+"""The steps either side of the reconstruction on the GPU, against the oracle.
 
-Both integrate the same ODEs with the same RK4 steps in FP64, so they agree
-to rounding: rel-L2 <= 1e-11 on Q, P, S, A and the Jacobians, over the
-paper's potentials (1D cosine, 2D Gaussian well, 3D harmonic) and a mixed
-one, from initial packets and from a given Jacobian state.
+- Packet flow (eq. 2.3-2.6, RK4): both sides integrate the same ODEs with the
+  same steps in FP64, so they agree to rounding (rel-L2 <= 1e-11 on Q, P, S,
+  A and the Jacobians) over the paper's potentials (1D cosine, 2D Gaussian
+  well, 3D harmonic) and mixed ones.
+- Initial decomposition (2.7): the same windowed quadrature, <= 1e-12.
+- The whole chain u0 -> (2.7) -> flow -> FGGC / direct sum, against the oracle
+  chain and a split-step spectral reference written for the tests.
 """
 import math
 import sys
@@ -141,3 +144,82 @@ def test_host_buffers_and_errors(ctx):
     with pytest.raises(F.FggcError) as ei:
         ctx.propagate(q.copy(), p.copy(), S0.copy(), A0.copy(), F.potential(c1=math.inf), 1e-3, 10)
     assert ei.value.code == F.FGGC_EINVAL
+
+
+# --------------------------------------------------------------------------
+# initial decomposition (2.7) and the whole chain on the GPU
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d,M,eps,N", [(1, (1024,), 1 / 64, 500), (1, (4096,), 1 / 1024, 300),
+                                       (2, (128, 96), 1 / 64, 200)])
+def test_decompose_matches_oracle(ctx, d, M, eps, N):
+    rng = np.random.default_rng(21 + d)
+    axes = [-math.pi + 2 * math.pi * np.arange(m) / m for m in M]
+    X = np.meshgrid(*axes, indexing="ij")
+    r2 = sum(x * x for x in X)
+    u0 = (np.exp(-20 * r2 + 1j * sum(X) / eps) * (1 + 0.3 * np.cos(3 * X[0]))).astype(np.complex128)
+    q = rng.uniform(-0.6, 0.6, (d, N))
+    p = 1.0 + 0.4 * rng.standard_normal((d, N))
+    R = 6 * math.sqrt(eps)
+    A = ctx.decompose(torch.from_numpy(u0.ravel().copy()).cuda(), eps, M, R,
+                      torch.from_numpy(q).cuda(), torch.from_numpy(p).cuda())
+    torch.cuda.synchronize()
+    ref = flow.decompose(u0.ravel(), eps, list(M), R, q, p)
+    e = rel(A.cpu().numpy(), ref)
+    log("decompose", d, M, eps, e)
+    assert e <= 1e-12
+    # host buffers
+    Ah = ctx.decompose(u0.ravel().copy(), eps, M, R, q, p)
+    assert rel(Ah, ref) <= 1e-12
+
+
+def test_chain_on_gpu_matches_spectral_reference(ctx, orc):
+    """u0 -> decomposition -> RK4 flow -> FGGC, all through the library:
+    for the harmonic potential the FGA is exact and the chain meets the
+    split-step solution; for Example 1's 1 - cos(pi x) the chain's FGA sum
+    equals the oracle chain's, and FGGC (Q4P2) differs from it at the LSA level."""
+    eps, M, T, n = 1 / 64, 2048, 0.5, 500
+    x = -math.pi + 2 * math.pi * np.arange(M) / M
+    u0 = (64 / math.pi) ** 0.25 * np.exp(-32 * x * x + 1j * x / eps)
+    dq, dp = math.sqrt(eps) / 2, math.pi * math.sqrt(eps) / 8
+    qs = np.arange(-0.8, 0.8 + 1e-12, dq)
+    ps_ = 1.0 + np.arange(-1.2, 1.2 + 1e-12, dp)
+    qq, pp = [g.ravel()[None, :] for g in np.meshgrid(qs, ps_, indexing="ij")]
+    scale = dq * dp / (2 * math.pi * eps) ** 1.5
+    st = F.default_strategy(1, eps, "Q4P2")
+    for name, kw, Vx in (("harmonic", dict(w=(1.0,)), 0.5 * x * x),
+                         ("cos", dict(c0=1.0, c1=-1.0, kappa=math.pi), 1 - np.cos(math.pi * x))):
+        Qd = torch.from_numpy(qq.copy()).cuda()
+        Pd = torch.from_numpy(pp.copy()).cuda()
+        A = ctx.decompose(torch.from_numpy(u0.copy()).cuda(), eps, (M,), 8 * math.sqrt(eps), Qd, Pd)
+        Sd = torch.zeros(qq.shape[1], dtype=torch.float64, device="cuda")
+        ctx.propagate(Qd, Pd, Sd, A, F.potential(**kw), T / n, n)
+        uf = ctx.reconstruct(Qd, Pd, Sd, A, eps, (M,), st, scale=scale, precision=F.FP64)
+        ud = ctx.direct_sum(Qd, Pd, Sd, A, eps, (M,), 6 * math.sqrt(eps), scale=scale, precision=F.FP64)
+        torch.cuda.synchronize()
+        uf, ud = uf.cpu().numpy(), ud.cpu().numpy()
+        ref = split_step_1d(u0, Vx, eps, T, 4000)
+        # the oracle chain on the same inputs
+        A0 = flow.decompose(u0, eps, [M], 8 * math.sqrt(eps), qq, pp)
+        Qo, Po, So, Ao, _, _ = flow.propagate(qq, pp, np.zeros(qq.shape[1]), A0, flow.potential(**kw), T / n, n)
+        uo = orc.direct_sum(Qo, Po, So, Ao, eps, [M], 6 * math.sqrt(eps), scale)
+        e_par, e_lsa, e_ref = rel(ud, uo), rel(uf, ud), rel(ud, ref)
+        log("chain", name, "FGA gpu vs oracle", e_par, "FGGC vs FGA", e_lsa, "FGA vs split-step", e_ref)
+        assert e_par <= 1e-11
+        assert e_lsa <= 1e-6
+        if name == "harmonic":
+            assert e_ref <= 5e-7
+            assert rel(uf, ref) <= 1e-6
+
+
+def split_step_1d(u0, Vx, eps, T, nsteps):
+    """Strang splitting of i eps u_t = -eps^2/2 u_xx + V u (test reference)."""
+    M = u0.size
+    k = np.fft.fftfreq(M, d=1.0 / M)
+    dt = T / nsteps
+    half = np.exp(-1j * Vx * dt / (2 * eps))
+    kin = np.exp(-1j * eps * k * k * dt / 2)
+    u = u0.copy()
+    for _ in range(nsteps):
+        u = half * np.fft.ifft(kin * np.fft.fft(half * u))
+    return u

@@ -175,3 +175,57 @@ def test_decomposition_reproduces_u0(orc):
     scale = dq * dp / (2 * math.pi * eps) ** 1.5
     u = orc.direct_sum(qq, pp, np.zeros(qq.shape[1]), A, eps, [M], 6 * math.sqrt(eps), scale)
     assert rel(u, u0) < 1e-7
+
+
+# --------------------------------------------------------------------------
+# the whole FGA chain (2.7) -> (2.3)-(2.6) -> (2.10) against a spectral reference
+# --------------------------------------------------------------------------
+
+def split_step(u0, Vx, eps, T, nsteps):
+    """Strang splitting of i eps u_t = -eps^2/2 u_xx + V u on the periodic grid
+    (a reference written for these tests; second order in dt, spectral in x)."""
+    M = u0.size
+    k = np.fft.fftfreq(M, d=1.0 / M)
+    dt = T / nsteps
+    half = np.exp(-1j * Vx * dt / (2 * eps))
+    kin = np.exp(-1j * eps * k * k * dt / 2)
+    u = u0.copy()
+    for _ in range(nsteps):
+        u = half * np.fft.ifft(kin * np.fft.fft(half * u))
+    return u
+
+
+def fga_chain(orc, eps, M, V, T, n):
+    """Example 1's initial wave, decomposed on dq = sqrt(eps)/2, dp = pi sqrt(eps)/8,
+    carried by RK4 and summed by the direct sum (R = 6 sqrt(eps))."""
+    x = -math.pi + 2 * math.pi * np.arange(M) / M
+    u0 = (64 / math.pi) ** 0.25 * np.exp(-32 * x * x + 1j * x / eps)
+    dq, dp = math.sqrt(eps) / 2, math.pi * math.sqrt(eps) / 8
+    qs = np.arange(-0.8, 0.8 + 1e-12, dq)
+    ps_ = 1.0 + np.arange(-1.2, 1.2 + 1e-12, dp)
+    qq, pp = [g.ravel()[None, :] for g in np.meshgrid(qs, ps_, indexing="ij")]
+    A = flow.decompose(u0, eps, [M], 8 * math.sqrt(eps), qq, pp)
+    Q, P, S, At, _, _ = flow.propagate(qq, pp, np.zeros(qq.shape[1]), A, V, T / n, n)
+    scale = dq * dp / (2 * math.pi * eps) ** 1.5
+    return x, u0, orc.direct_sum(Q, P, S, At, eps, [M], 6 * math.sqrt(eps), scale)
+
+
+def test_fga_chain_exact_for_harmonic_potential(orc):
+    """For a quadratic potential the FGA is exact: the chain meets the spectral
+    solution to the reference's own time-step error."""
+    eps, M, T = 1 / 64, 2048, 0.5
+    x, u0, u = fga_chain(orc, eps, M, flow.potential(w=(1.0,)), T, 500)
+    ref = split_step(u0, 0.5 * x * x, eps, T, 4000)
+    assert rel(u, ref) < 5e-7
+
+
+def test_fga_chain_first_order_in_eps(orc):
+    """Example 1's potential 1 - cos(pi x): the FGA error is first order in eps
+    (a factor ~4 per factor 4 in eps), far above the discretisation errors."""
+    V = flow.potential(c0=1.0, c1=-1.0, kappa=math.pi)
+    errs = []
+    for eps, M in ((1 / 64, 2048), (1 / 256, 4096)):
+        x, u0, u = fga_chain(orc, eps, M, V, 0.5, 500)
+        errs.append(rel(u, split_step(u0, 1 - np.cos(math.pi * x), eps, 0.5, 4000)))
+    assert 3e-3 < errs[0] < 3e-2
+    assert 2.5 < errs[0] / errs[1] < 6
