@@ -17,6 +17,10 @@
  *                     on on-grid packets (eq. 2.20-2.22, 3.9-3.13, 3.22-3.23),
  *                     the coefficients are summed per phase-space cell
  *                     (eq. 2.25) and eq. (2.24) is evaluated with FFTs.
+ * fggc_direct_sum_separable evaluates the direct sum under a box window as a
+ * product of matrices on the matrix cores (2D).  The steps around the
+ * reconstruction are here too: fggc_decompose (initial packets, eq. 2.7) and
+ * fggc_propagate (the packet flow, eq. 2.3-2.6).
  *
  * Conventions shared by every call
  *   - Domain [-pi, pi)^d, periodic; grid x_m = -pi + m * 2 pi / n per
