@@ -116,3 +116,43 @@ def decompose(u0, eps, M, R, q, p):
         ph = -np.sum(p[:, j:j + 1] * y[:, keep], axis=0) / eps
         out[j] = np.sum(u[keep] * np.exp(1j * ph - r2[keep] / (2 * eps))) * w
     return 2 ** (d / 2) * out
+
+
+def multistep(orc, u0, eps, M, qm, pm, V: dict, dt: float, steps: int, runs: int, Nq, dp, dq_off, dp_off,
+              R_dec: float, prune: float = 1e-12, rcond: float = 0.0):
+    """Multi-step FGGC (Alg. 3): `runs` times (Step 1) decompose the current u on
+    the fixed mesh (qm, pm) ([d][Nm]), (Step 2) evolve over steps * dt the mesh
+    points not learned yet and keep what the flow maps them to, (Step 3)
+    reconstruct u by FGGC (eq. 2.23-2.25) with the oracle's plain evaluation.
+
+    The flow is linear in A, so a learned point is stored as its final
+    (Q, P, S) and the ratio A(T_evo) / A(0) (the flow of A(0) = 1).  Mesh
+    points whose |A(0)| is below prune * max are dropped in that run.
+    Returns the final u ([prod M]) and the number of points evolved per run.
+    """
+    M = [int(m) for m in np.atleast_1d(M)]
+    d = len(M)
+    qm = np.asarray(qm, dtype=np.float64).reshape(d, -1)
+    pm = np.asarray(pm, dtype=np.float64).reshape(d, -1)
+    Nm = qm.shape[1]
+    learned = np.zeros(Nm, dtype=bool)
+    Qf, Pf = np.zeros((d, Nm)), np.zeros((d, Nm))
+    Sf, ratio = np.zeros(Nm), np.zeros(Nm, dtype=np.complex128)
+    dq = 2 * np.pi / np.asarray(Nq, dtype=np.float64)
+    scale = float(np.prod(dq * np.asarray(dp, dtype=np.float64))) / (2 * np.pi * eps) ** (1.5 * d)
+    u = np.asarray(u0, dtype=np.complex128).ravel()
+    evolved = []
+    for _ in range(int(runs)):
+        A0 = decompose(u, eps, M, R_dec, qm, pm)
+        keep = np.abs(A0) > prune * np.abs(A0).max()
+        new = np.flatnonzero(keep & ~learned)
+        if new.size:
+            Q, P, S, A, _, _ = propagate(qm[:, new], pm[:, new], np.zeros(new.size),
+                                         np.ones(new.size, dtype=np.complex128), V, dt, steps)
+            Qf[:, new], Pf[:, new], Sf[new], ratio[new] = Q, P, S, A
+            learned[new] = True
+        evolved.append(int(new.size))
+        k = np.flatnonzero(keep)
+        u = orc.fggc(Qf[:, k], Pf[:, k], Sf[k], A0[k] * ratio[k], eps, M, Nq, dp, dq_off, dp_off,
+                     rcond=rcond, scale=scale)
+    return u, evolved

@@ -229,3 +229,46 @@ def test_fga_chain_first_order_in_eps(orc):
         errs.append(rel(u, split_step(u0, 1 - np.cos(math.pi * x), eps, 0.5, 4000)))
     assert 3e-3 < errs[0] < 3e-2
     assert 2.5 < errs[0] / errs[1] < 6
+
+
+# --------------------------------------------------------------------------
+# multi-step FGGC (Alg. 3)
+# --------------------------------------------------------------------------
+
+def multistep_setup():
+    eps, M, Nq = 1 / 64, 512, 128
+    x = -math.pi + 2 * math.pi * np.arange(M) / M
+    u0 = (64 / math.pi) ** 0.25 * np.exp(-32 * x * x + 1j * x / eps)
+    dq, dp = 2 * math.pi / Nq, math.pi * math.sqrt(eps) / 8
+    qs = -math.pi + dq * np.arange(Nq)
+    qs = qs[(qs > -1.0) & (qs < 1.8)]
+    ps_ = dp * np.arange(int(np.floor(-0.3 / dp)), int(np.ceil(2.3 / dp)) + 1)
+    qm, pm = [g.ravel()[None, :] for g in np.meshgrid(qs, ps_, indexing="ij")]
+    return eps, M, Nq, dp, x, u0, qm, pm
+
+
+def test_multistep_exact_for_harmonic_and_learns(orc):
+    """Alg. 3 on the harmonic potential: every run's FGA is exact, so the
+    composed result meets the spectral solution whatever the number of runs;
+    later runs evolve only the mesh points not learned before."""
+    eps, M, Nq, dp, x, u0, qm, pm = multistep_setup()
+    ref = split_step(u0, 0.5 * x * x, eps, 0.5, 4000)
+    for runs in (2, 4):
+        u, ev = flow.multistep(orc, u0, eps, [M], qm, pm, flow.potential(w=(1.0,)), 1e-3, 500 // runs, runs,
+                               [Nq], [dp], [-1, 0, 1, 2], [0, 1], 8 * math.sqrt(eps))
+        assert rel(u, ref) < 2e-7
+        assert all(e < 0.3 * ev[0] for e in ev[1:])
+
+
+def test_multistep_error_accumulates_mildly(orc):
+    """Example 1's potential: restarting the FGA at T/2 keeps the error of the
+    same order (the paper reports growth by a small factor)."""
+    eps, M, Nq, dp, x, u0, qm, pm = multistep_setup()
+    V = flow.potential(c0=1.0, c1=-1.0, kappa=math.pi)
+    ref = split_step(u0, 1 - np.cos(math.pi * x), eps, 0.5, 4000)
+    errs = []
+    for runs in (1, 2):
+        u, _ = flow.multistep(orc, u0, eps, [M], qm, pm, V, 1e-3, 500 // runs, runs, [Nq], [dp],
+                              [-1, 0, 1, 2], [0, 1], 8 * math.sqrt(eps))
+        errs.append(rel(u, ref))
+    assert 3e-3 < errs[0] < errs[1] < 3 * errs[0]
