@@ -1,0 +1,69 @@
+"""Multi-step FGGC (Alg. 3) on the GPU, through libfggc.
+
+T_final = T_multi * T_evo.  Each run
+- decomposes the current u on a fixed (q, p) mesh (fggc_decompose, eq. 2.7),
+- evolves over T_evo only the mesh points that no earlier run has seen
+  (fggc_propagate, eq. 2.3-2.6) and keeps what the flow maps them to,
+- and reconstructs u by FGGC (fggc_reconstruct).
+
+The flow is linear in A, so what a mesh point "learns" is its final
+(Q, P, S) and the ratio A(T_evo) / A(0), obtained by evolving A(0) = 1; a
+later run reuses it with its own A(0).  Mesh points whose |A(0)| is below
+`prune` times the largest are skipped in that run.
+
+This module only sequences library calls: the masks, gathers and the
+element-wise product A(0) * ratio are torch bookkeeping on device memory.
+"""
+import math
+
+from paper_2504_21785_amd import fggc as F
+
+
+class MultiStep:
+    def __init__(self, ctx, eps: float, M, qm, pm, V, dt: float, steps: int, strategy,
+                 R_dec: float = None, prune: float = 1e-12, precision: int = F.FP64):
+        import torch
+        self.torch = torch
+        self.ctx, self.eps, self.M = ctx, float(eps), tuple(int(m) for m in M)
+        self.d = len(self.M)
+        self.qm, self.pm = qm.contiguous(), pm.contiguous()  # [d][Nm] float64 on the GPU
+        self.V, self.dt, self.steps, self.st = V, float(dt), int(steps), strategy
+        self.R_dec = 8 * math.sqrt(eps) if R_dec is None else float(R_dec)
+        self.prune, self.precision = float(prune), precision
+        Nm = self.qm.shape[1]
+        dev = self.qm.device
+        self.learned = torch.zeros(Nm, dtype=torch.bool, device=dev)
+        self.Qf = torch.zeros_like(self.qm)
+        self.Pf = torch.zeros_like(self.pm)
+        self.Sf = torch.zeros(Nm, dtype=torch.float64, device=dev)
+        self.ratio = torch.zeros(Nm, dtype=torch.complex128, device=dev)
+        dq = [2 * math.pi / strategy.Nq[k] for k in range(self.d)]
+        self.scale = math.prod(dq[k] * strategy.dp[k] for k in range(self.d)) / (2 * math.pi * eps) ** (1.5 * self.d)
+        self.evolved = []
+
+    def run(self, u, runs: int):
+        """Carry u ([prod M] or grid-shaped complex tensor) over `runs` runs of T_evo."""
+        torch = self.torch
+        for _ in range(int(runs)):
+            u64 = u.reshape(-1).to(torch.complex128).contiguous()
+            A0 = self.ctx.decompose(u64, self.eps, self.M, self.R_dec, self.qm, self.pm)
+            mag = A0.abs()
+            keep = mag > self.prune * mag.max()
+            new = torch.nonzero(keep & ~self.learned).squeeze(1)
+            if new.numel():
+                Q = self.qm[:, new].contiguous()
+                P = self.pm[:, new].contiguous()
+                S = torch.zeros(new.numel(), dtype=torch.float64, device=Q.device)
+                A = torch.ones(new.numel(), dtype=torch.complex128, device=Q.device)
+                self.ctx.propagate(Q, P, S, A, self.V, self.dt, self.steps)
+                self.Qf[:, new] = Q
+                self.Pf[:, new] = P
+                self.Sf[new] = S
+                self.ratio[new] = A
+                self.learned[new] = True
+            self.evolved.append(int(new.numel()))
+            k = torch.nonzero(keep).squeeze(1)
+            u = self.ctx.reconstruct(self.Qf[:, k].contiguous(), self.Pf[:, k].contiguous(), self.Sf[k].contiguous(),
+                                     (A0[k] * self.ratio[k]).contiguous(), self.eps, self.M, self.st,
+                                     scale=self.scale, precision=self.precision)
+        return u
