@@ -14,7 +14,11 @@ the same solution: the wave stays far from the boundary up to T = 0.8), on a
 power-of-two grid with dx <= eps.  Packets whose |A(0)| is below 1e-12 of
 the largest are dropped before the flow.
 
+Examples 4 (1D, eps = 1/4096, T = 0.8) and 5 (2D, eps = 1/64, T = 1.6) run
+multi-step FGGC (Alg. 3, Q2P2) with the steps split into T_multi runs.
+
 Usage: python -m paper_2504_21785_amd.examples --example 1 --eps 64,256,1024
+       python -m paper_2504_21785_amd.examples --example 4 --potential V1
 Everything runs through libfggc; torch only holds device memory.
 """
 import argparse
@@ -114,15 +118,91 @@ def run(example: int, inv_eps: int, potential: str, T: float, dt: float, precisi
             **{k: round(v, 6) for k, v in times.items()}, "fggc_vs_fga_rel_l2": lsa}
 
 
+def run_multi(example: int, inv_eps: int, potential: str, T: float, dt: float, splits, precision: str,
+              prune: float = 1e-12, p_min: float = -1.0, p_max: float = 2.3):
+    """Examples 4 (1D) and 5 (2D): multi-step FGGC with Q2P2 over T_multi runs of T / T_multi.
+    Reported per split: time per stage, mesh points evolved, and the rel-L2
+    difference from the single-run result (the error the runs accumulate)."""
+    import torch
+    from paper_2504_21785_amd import fggc as F
+    from paper_2504_21785_amd.multistep import MultiStep
+
+    eps = 1.0 / inv_eps
+    d = 1 if example == 4 else 2
+    n = 1 << int(math.ceil(math.log2(2 * math.pi / eps)))
+    n = min(n, 4096 if d == 2 else (8192 if precision == "fp64" else 16384))
+    if 1.5 / eps >= n / 2:
+        raise ValueError(f"eps = 1/{inv_eps}: momenta up to 1.5 need a grid above {n} points per axis")
+    M = (n,) * d
+    dev = torch.device("cuda:0")
+    axes = [torch.arange(n, dtype=torch.float64, device=dev) * (2 * math.pi / n) - math.pi for _ in range(d)]
+    X = torch.meshgrid(*axes, indexing="ij")
+    u0 = (64 / math.pi) ** (d / 4) * torch.exp(-32 * sum(x * x for x in X) + 1j * sum(X) / eps)
+    if potential == "V1":
+        V = F.potential(c0=1.0, c1=-1.0, kappa=math.pi) if d == 1 else F.potential(c0=1.0, c2=-1.0, c3=-1.0)
+    else:
+        V = F.potential(w=(1.0,) * d)
+    st = F.default_strategy(d, eps, "Q2P2")
+    Nq, dp = int(st.Nq[0]), float(st.dp[0])
+    # the FGGC mesh over the region of phase space the wave visits: q in (-1, 1.8),
+    # p in (p_min, p_max); in Example 4's cosine well the wave reflects after
+    # about a quarter period (t ~ 0.5), so its momenta reach -1
+    q1 = -math.pi + (2 * math.pi / Nq) * torch.arange(Nq, dtype=torch.float64, device=dev)
+    q1 = q1[(q1 > -1.0) & (q1 < 1.8)]
+    p1 = dp * torch.arange(math.floor(p_min / dp), math.ceil(p_max / dp) + 1, dtype=torch.float64, device=dev)
+    qg = torch.stack([g.reshape(-1) for g in torch.meshgrid(*([q1] * d), indexing="ij")])
+    pg = torch.stack([g.reshape(-1) for g in torch.meshgrid(*([p1] * d), indexing="ij")])
+    qm = qg.repeat_interleave(pg.shape[1], dim=1).contiguous()
+    pm = pg.repeat(1, qg.shape[1]).contiguous()
+    prec = F.FP64 if precision == "fp64" else F.FP32
+    nsteps = int(round(T / dt))
+    ctx = F.Context(0)
+    MultiStep(ctx, eps, M, qm, pm, V, dt, nsteps, st, precision=prec, prune=prune).run(u0, 1)  # warm-up
+    out, base = [], None
+    for runs in splits:
+        ms = MultiStep(ctx, eps, M, qm, pm, V, dt, nsteps // runs, st, precision=prec, prune=prune)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = ms.run(u0, runs)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        u = u.reshape(-1).to(torch.complex128)
+        if base is None:
+            base = u
+        diff = float(torch.linalg.vector_norm(u - base) / torch.linalg.vector_norm(base))
+        out.append({"example": example, "potential": potential, "eps": f"1/{inv_eps}", "grid": list(M),
+                    "mesh_points": int(qm.shape[1]), "split": f"{nsteps // runs}x{runs}", "seconds": round(secs, 4),
+                    "evolved": ms.evolved, "rel_l2_vs_single_run": diff, "precision": precision})
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--example", type=int, default=1, choices=[1, 2])
+    ap.add_argument("--example", type=int, default=1, choices=[1, 2, 4, 5],
+                    help="1, 2: single run; 4 (1D), 5 (2D): multi-step FGGC")
+    ap.add_argument("--splits", default="1,2,4,8,16,32", help="values of T_multi (examples 4 and 5)")
+    ap.add_argument("--prune", type=float, default=None,
+                    help="drop mesh points with |A(0)| below this times the largest (default 1e-12 FP64, 1e-6 FP32)")
+    ap.add_argument("--p-min", type=float, default=None, help="lower end of the mesh in p (default -1.6 in example 4, -1.0 in 5)")
+    ap.add_argument("--p-max", type=float, default=2.3, help="upper end of the mesh in p (examples 4 and 5)")
     ap.add_argument("--eps", default=None, help="values of 1/eps (default 64,256,1024 in 1D; 64,256 in 2D)")
     ap.add_argument("--potential", default="V2", choices=["V1", "V2"], help="Example 2's potential")
     ap.add_argument("--T", type=float, default=0.8)
     ap.add_argument("--dt", type=float, default=1e-4)
     ap.add_argument("--precision", default="fp64", choices=["fp32", "fp64"])
     args = ap.parse_args()
+    if args.example in (4, 5):
+        ie = int(args.eps or ("4096" if args.example == 4 else "64"))
+        T = args.T if args.example == 4 else (1.6 if args.T == 0.8 else args.T)
+        prec = args.precision if args.example == 5 or ie <= 1024 else "fp32"
+        log(f"example {args.example}, eps = 1/{ie}, T = {T}, {prec}")
+        prune = args.prune if args.prune is not None else (1e-12 if prec == "fp64" else 1e-6)
+        for rec in run_multi(args.example, ie, args.potential, T, args.dt, [int(v) for v in args.splits.split(",")],
+                             prec, prune, args.p_min if args.p_min is not None else (-1.6 if args.example == 4 else -1.0),
+                             args.p_max):
+            print(json.dumps(rec), flush=True)
+        return
     eps_list = args.eps or ("64,256,1024" if args.example == 1 else "64,256")
     for ie in (int(v) for v in eps_list.split(",")):
         log(f"example {args.example}, eps = 1/{ie}")
