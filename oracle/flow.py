@@ -91,13 +91,14 @@ def propagate(Q, P, S, A, V: dict, dt: float, nsteps: int, JQ=None, JP=None):
     return tuple(y)
 
 
-def decompose(u0, eps, M, R, q, p):
+def decompose(u0, eps, M, R, q, p, window="ball"):
     """A(0, q, p) = 2^{d/2} u0^(q, p) of eq. (2.6)-(2.7) by quadrature on the grid.
 
     u0^(q, p) = int u0(y) exp(-i p.(y - q)/eps - |y - q|^2/(2 eps)) dy, with u0
     sampled on the periodic grid x_m = -pi + m 2 pi / M (row-major, [prod M]),
     y - q taken as the minimum image and the integrand kept for |y - q| <= R
-    (the window of the direct sum); weight prod_k 2 pi / M_k.  q, p: [d][N].
+    (window "ball", that of the direct sum) or for every |y_k - q_k| <= R
+    (window "box"); weight prod_k 2 pi / M_k.  q, p: [d][N].
     """
     M = [int(m) for m in np.atleast_1d(M)]
     d = len(M)
@@ -112,7 +113,7 @@ def decompose(u0, eps, M, R, q, p):
         y = X - q[:, j:j + 1]
         y = y - 2 * np.pi * np.floor((y + np.pi) / (2 * np.pi))
         r2 = np.sum(y * y, axis=0)
-        keep = r2 <= R * R
+        keep = r2 <= R * R if window == "ball" else np.all(np.abs(y) <= R, axis=0)
         ph = -np.sum(p[:, j:j + 1] * y[:, keep], axis=0) / eps
         out[j] = np.sum(u[keep] * np.exp(1j * ph - r2[keep] / (2 * eps))) * w
     return 2 ** (d / 2) * out

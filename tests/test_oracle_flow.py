@@ -272,3 +272,20 @@ def test_multistep_error_accumulates_mildly(orc):
                               [-1, 0, 1, 2], [0, 1], 8 * math.sqrt(eps))
         errs.append(rel(u, ref))
     assert 3e-3 < errs[0] < errs[1] < 3 * errs[0]
+
+
+def test_decomposition_box_window():
+    """The box window keeps every point of the ball and the corners beyond it:
+    against the closed form both are exact once R is large (8 sqrt(eps)); with
+    a small R they differ, the box being closer to the untruncated transform."""
+    eps, M = 1 / 16, 256
+    x2 = -math.pi + 2 * math.pi * np.arange(M) / M
+    u2 = np.outer(np.exp(-8.0 * x2 * x2 + 4j * x2), np.exp(-6.0 * x2 * x2 - 2j * x2))
+    rng = np.random.default_rng(6)
+    q = rng.uniform(-0.3, 0.3, (2, 10))
+    p = rng.uniform(-1, 1, (2, 10))
+    exact = 2 * gaussian_transform(8.0, 4.0, eps, q[0], p[0]) * gaussian_transform(6.0, -2.0, eps, q[1], p[1])
+    assert rel(flow.decompose(u2, eps, [M, M], 3.0, q, p, window="box"), exact) < 1e-10
+    eb = rel(flow.decompose(u2, eps, [M, M], 0.4, q, p, window="box"), exact)
+    ec = rel(flow.decompose(u2, eps, [M, M], 0.4, q, p), exact)
+    assert 0 < eb < ec
