@@ -190,6 +190,29 @@ int fggc_decompose(fggc_ctx *ctx, const fggc_grid *grid, const double *u0, doubl
                    int64_t N, const double *q, const double *p, double *A_out, void *stream);
 
 /*
+ * The initial decomposition (2.7) on a product mesh whose q-points are grid
+ * points, with a box window (every |y_k| <= window_half_width):
+ *   q_k = -pi + (q_lo[k] + i) 2 pi / Nq[k], i < q_n[k];  p_k = (p_lo[k] + j) dp[k], j < p_n[k].
+ * Because q sits on a grid point, the offsets y = x_m - q are the same for
+ * every q, the kernel factors over dimensions, and for each q the values
+ * over all p are E_0 W_q E_1^T: products of the window W_q of u0 with two
+ * fixed phase matrices, evaluated as batched FP64 complex GEMMs on the matrix
+ * cores.  The box contains the ball of fggc_decompose's window, so the two
+ * differ only by terms below exp(-R^2/(2 eps)) relative.
+ * u0: grid values, complex128, row-major.  A_out: [prod q_n][prod p_n]
+ * complex128, q-index major and p-index minor, each row-major over the
+ * dimensions (the order of packets listed q-major for fggc_decompose).
+ * d = 1 or 2.  Buffers may be device or host memory.  Errors: FGGC_EINVAL
+ * when a grid size is not a multiple of Nq, a q range leaves [0, Nq), a p
+ * range is empty, dp <= 0, eps <= 0, the window is wider than the grid or
+ * outside (0, pi); FGGC_EUNSUPPORTED for d = 3; FGGC_EDEVICE when the GEMM
+ * library fails.
+ */
+int fggc_decompose_mesh(fggc_ctx *ctx, const fggc_grid *grid, const double *u0, double eps,
+                        double window_half_width, const int64_t *Nq, const int64_t *q_lo, const int64_t *q_n,
+                        const double *dp, const int64_t *p_lo, const int64_t *p_n, double *A_out, void *stream);
+
+/*
  * Potential of the packet flow:
  *   V(x) = c0 + sum_k w[k] x_k^2 / 2 + c1 sum_k cos(kappa x_k) + c2 exp(c3 |x|^2).
  * The paper's examples (Sec. 4) are members: 1 - cos(pi x) (c0 = 1, c1 = -1,

@@ -469,6 +469,7 @@ void fggc_destroy(fggc_ctx *ctx) {
     (void)hipEventDestroy(ctx->ws_event);
   }
   clear_graphs(ctx);
+  fggc::destroy_blas(ctx->blas);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->dev_scan) (void)hipFree(ctx->dev_scan);
   if (ctx->host_scan) (void)hipHostFree(ctx->host_scan);
@@ -598,6 +599,51 @@ int fggc_decompose(fggc_ctx *ctx, const fggc_grid *grid, const double *u0, doubl
     launch_decompose(g.d, g.n, du, eps, window_radius, N, dq, dp, da, s);
     FGGC_HIP(hipMemcpyAsync(A_out, da, ab, hipMemcpyDefault, s));
     FGGC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int fggc_decompose_mesh(fggc_ctx *ctx, const fggc_grid *grid, const double *u0, double eps,
+                        double window_half_width, const int64_t *Nq, const int64_t *q_lo, const int64_t *q_n,
+                        const double *dp, const int64_t *p_lo, const int64_t *p_n, double *A_out, void *stream) {
+  return guarded("fggc_decompose_mesh", [&] {
+    if (!ctx || !u0 || !Nq || !q_lo || !q_n || !dp || !p_lo || !p_n || !A_out) fail(FGGC_EINVAL, "NULL argument");
+    GridGeom g = check_grid(grid);
+    if (g.d > 2) fail(FGGC_EUNSUPPORTED, "the mesh decomposition is one- or two-dimensional");
+    check_eps(eps);
+    const double R = window_half_width;
+    if (!(R > 0) || !(R < kPi)) fail(FGGC_EINVAL, "window_half_width must be in (0, pi)");
+    int64_t nq = 1, np = 1;
+    for (int k = 0; k < g.d; ++k) {
+      if (Nq[k] < 1 || g.n[k] % Nq[k] != 0) fail(FGGC_EINVAL, "grid size must be a multiple of Nq (q on grid points)");
+      if (q_n[k] < 1 || q_lo[k] < 0 || q_lo[k] + q_n[k] > Nq[k]) fail(FGGC_EINVAL, "q range outside [0, Nq)");
+      if (p_n[k] < 1 || !(dp[k] > 0) || !std::isfinite(dp[k])) fail(FGGC_EINVAL, "bad p range or dp");
+      if (2 * (int64_t)std::floor(R / (kTwoPi / (double)g.n[k])) + 1 > g.n[k])
+        fail(FGGC_EINVAL, "window wider than the grid");
+      nq *= q_n[k];
+      np *= p_n[k];
+    }
+    if (nq * np > 0x7fffffffLL) fail(FGGC_EINVAL, "mesh larger than 2^31 points");
+    Guard lock(ctx);
+    hipStream_t s = (hipStream_t)stream;
+    WsUse wsu(ctx, s);
+    int64_t npts = 1;
+    for (int k = 0; k < g.d; ++k) npts *= g.n[k];
+    const size_t ub = (size_t)npts * 16, ab = (size_t)nq * np * 16;
+    const bool host = !(device_accessible(u0) && device_accessible(A_out));
+    const size_t need = decompose_mesh_bytes(g.d, g.n, R, q_n, p_n) + (host ? ub + ab + 2 * 256 : 0);
+    ctx->ws.reserve(need, ctx->budget);
+    const double *du = u0;
+    double *da = A_out;
+    if (host) {
+      du = (const double *)ctx->ws.take(ub);
+      da = (double *)ctx->ws.take(ab);
+      FGGC_HIP(hipMemcpyAsync((void *)du, u0, ub, hipMemcpyDefault, s));
+    }
+    decompose_mesh(&ctx->blas, g.d, g.n, du, eps, R, Nq, q_lo, q_n, dp, p_lo, p_n, da, ctx->ws, s);
+    if (host) {
+      FGGC_HIP(hipMemcpyAsync(A_out, da, ab, hipMemcpyDefault, s));
+      FGGC_HIP(hipStreamSynchronize(s));
+    }
   });
 }
 

@@ -230,6 +230,14 @@ void bucket_positions(const uint32_t *keys, int64_t N, int64_t nbins, uint32_t *
 // Initial decomposition (2.7) by windowed quadrature; device pointers, stream-ordered.
 void launch_decompose(int d, const int64_t *n, const double *u0, double eps, double R, int64_t N,
                       const double *q, const double *p, double *A, hipStream_t s);
+// Decomposition (2.7) on a product mesh with q on grid points, by batched ZGEMMs
+// (rocBLAS handle created in *blas on first use); device pointers; ws must hold
+// decompose_mesh_bytes().
+size_t decompose_mesh_bytes(int d, const int64_t *n, double R, const int64_t *q_n, const int64_t *p_n);
+void decompose_mesh(void **blas, int d, const int64_t *n, const double *u0, double eps, double R, const int64_t *Nq,
+                    const int64_t *q_lo, const int64_t *q_n, const double *dp, const int64_t *p_lo,
+                    const int64_t *p_n, double *A, Workspace &ws, hipStream_t s);
+void destroy_blas(void *blas);
 // Packet flow (RK4 for eq. 2.3-2.6); device pointers, stream-ordered.
 void launch_propagate(int d, int64_t N, double *Q, double *P, double *S, double *a, double *jac,
                       const fggc_potential &V, double dt, int64_t nsteps, hipStream_t s);
@@ -342,4 +350,5 @@ struct fggc_ctx {
   std::list<std::pair<std::vector<int64_t>, hipGraphExec_t>> graphs;
   std::map<std::vector<int64_t>, int> seen;
   const void *graphs_ws = nullptr;
+  void *blas = nullptr;  // rocBLAS handle of the mesh decomposition, created on first use
 };

@@ -15,6 +15,8 @@
 //
 // The state lives in registers as NV doubles; a step keeps the state, the
 // running RK4 sum, the stage point and one stage derivative.
+#include <rocblas/rocblas.h>
+
 #include "common.h"
 
 namespace fggc {
@@ -310,6 +312,44 @@ void launch_decompose(int d, const int64_t *n, const double *u0, double eps, dou
   FGGC_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------
+// Decomposition on a product mesh whose q-points are grid points: with the
+// window |y_k| <= R per dimension the kernel of (2.7) factors, and for q on
+// grid point c the offsets y = (m - c) dx are the same for every q.  Per
+// dimension, E_k[j][o] = sqrt(2) dx_k exp(-(o dx_k)^2 / (2 eps) - i p_j o dx_k / eps),
+// o = -W..W, so that for each q
+//   A(q, .) = E_0 W_q E_1^T,   W_q = the (2W_0+1) x (2W_1+1) window of u0 about q,
+// two complex matrix products (FP64) per q, done as strided-batched ZGEMMs
+// (rocBLAS) over a periodically padded copy of u0.
+namespace {
+
+// E for one dimension; col_major_pj: element (j, o) at j + o * pn, else at o + j * L
+__global__ void phase_matrix_kernel(double2 *E, int pn, int L, int W, double dx, double eps, double p0, double dp,
+                                    double wscale, int col_major_pj) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= pn * L) return;
+  const int j = t % pn, o = t / pn;
+  const double y = (double)(o - W) * dx, pj = p0 + (double)j * dp;
+  double sn, cs;
+  sincos(-pj * y / eps, &sn, &cs);
+  const double g = wscale * exp(-y * y / (2.0 * eps));
+  E[col_major_pj ? (size_t)j + (size_t)o * pn : (size_t)o + (size_t)j * L] = make_double2(g * cs, g * sn);
+}
+
+// U_pad[a][b] = u0[(a - W0) mod n0][(b - W1) mod n1]
+__global__ void pad_periodic_kernel(const double2 *u0, double2 *up, int64_t n0, int64_t n1, int64_t W0, int64_t W1) {
+  const int64_t cols = n1 + 2 * W1, total = (n0 + 2 * W0) * cols;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int64_t a = t / cols, b = t % cols;
+  int64_t r = (a - W0) % n0, c = (b - W1) % n1;
+  if (r < 0) r += n0;
+  if (c < 0) c += n1;
+  up[t] = u0[r * n1 + c];
+}
+
+}  // namespace
+
 void launch_propagate(int d, int64_t N, double *Q, double *P, double *S, double *a, double *jac,
                       const fggc_potential &V, double dt, int64_t nsteps, hipStream_t s) {
   if (N == 0) return;
@@ -329,6 +369,105 @@ void launch_propagate(int d, int64_t N, double *Q, double *P, double *S, double 
   else if (d == 2) propagate_kernel<2><<<g, b, 0, s>>>(p);
   else propagate_kernel<3><<<g, b, 0, s>>>(p);
   FGGC_HIP(hipGetLastError());
+}
+
+}  // namespace fggc
+
+namespace fggc {
+
+size_t decompose_mesh_bytes(int d, const int64_t *n, double R, const int64_t *q_n, const int64_t *p_n) {
+  int64_t W[2] = {0, 0}, L[2] = {1, 1};
+  for (int k = 0; k < d; ++k) {
+    W[k] = (int64_t)std::floor(R / (kTwoPi / (double)n[k]));
+    L[k] = 2 * W[k] + 1;
+  }
+  const int64_t pad = (n[0] + 2 * W[0]) * (d == 2 ? n[1] + 2 * W[1] : 1);
+  const int64_t pn1 = d == 2 ? p_n[1] : 1, qn1 = d == 2 ? q_n[1] : 1;
+  return (size_t)pad * 16 + (size_t)p_n[0] * L[0] * 16 + (size_t)pn1 * L[1] * 16 +
+         (d == 2 ? (size_t)qn1 * pn1 * L[0] * 16 : 0) + 4 * 256;
+}
+
+void decompose_mesh(void **blas, int d, const int64_t *n, const double *u0, double eps, double R, const int64_t *Nq,
+                    const int64_t *q_lo, const int64_t *q_n, const double *dp, const int64_t *p_lo,
+                    const int64_t *p_n, double *A, Workspace &ws, hipStream_t s) {
+  if (!*blas) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) fail(FGGC_EDEVICE, "rocblas_create_handle failed");
+    *blas = (void *)h;
+  }
+  rocblas_handle h = (rocblas_handle)*blas;
+  if (rocblas_set_stream(h, s) != rocblas_status_success) fail(FGGC_EDEVICE, "rocblas_set_stream failed");
+  int64_t W[2] = {0, 0}, L[2] = {1, 1}, st[2] = {1, 1};
+  double dx[2] = {1, 1};
+  for (int k = 0; k < d; ++k) {
+    dx[k] = kTwoPi / (double)n[k];
+    W[k] = (int64_t)std::floor(R / dx[k]);
+    L[k] = 2 * W[k] + 1;
+    st[k] = n[k] / Nq[k];
+  }
+  const int64_t n1 = d == 2 ? n[1] : 1;
+  const int64_t pad_rows = n[0] + 2 * W[0], pad_cols = d == 2 ? n1 + 2 * W[1] : 1;
+  // workspace: padded u0, E per dimension, and one q-row of intermediate products
+  const int64_t pn0 = p_n[0], pn1 = d == 2 ? p_n[1] : 1, qn1 = d == 2 ? q_n[1] : 1;
+  const size_t b_up = (size_t)pad_rows * pad_cols * 16, b_e0 = (size_t)pn0 * L[0] * 16,
+               b_e1 = (size_t)pn1 * L[1] * 16, b_t = d == 2 ? (size_t)qn1 * pn1 * L[0] * 16 : 0;
+  // the caller reserved decompose_mesh_bytes() in ws
+  double2 *up = (double2 *)ws.take(b_up), *E0 = (double2 *)ws.take(b_e0), *E1 = (double2 *)ws.take(b_e1);
+  double2 *T = d == 2 ? (double2 *)ws.take(b_t) : nullptr;
+  const int64_t tot = pad_rows * pad_cols;
+  if (d == 1) {
+    pad_periodic_kernel<<<dim3((unsigned)((tot + 255) / 256)), 256, 0, s>>>((const double2 *)u0, up, n[0], 1, W[0], 0);
+  } else {
+    pad_periodic_kernel<<<dim3((unsigned)((tot + 255) / 256)), 256, 0, s>>>((const double2 *)u0, up, n[0], n1, W[0],
+                                                                              W[1]);
+  }
+  FGGC_HIP(hipGetLastError());
+  const double w2 = std::sqrt(2.0);
+  // dimension 0: 1D uses (j, o) column-major (pn x L); 2D uses E0^T column-major (L0 x pn0)
+  phase_matrix_kernel<<<dim3((unsigned)((pn0 * L[0] + 255) / 256)), 256, 0, s>>>(
+      E0, (int)pn0, (int)L[0], (int)W[0], dx[0], eps, (double)p_lo[0] * dp[0], dp[0], w2 * dx[0], d == 1);
+  FGGC_HIP(hipGetLastError());
+  if (d == 2) {
+    phase_matrix_kernel<<<dim3((unsigned)((pn1 * L[1] + 255) / 256)), 256, 0, s>>>(
+        E1, (int)pn1, (int)L[1], (int)W[1], dx[1], eps, (double)p_lo[1] * dp[1], dp[1], w2 * dx[1], 1);
+    FGGC_HIP(hipGetLastError());
+  }
+  const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+  auto check = [](rocblas_status r) {
+    if (r != rocblas_status_success) fail(FGGC_EDEVICE, std::string("rocBLAS ZGEMM failed: ") + rocblas_status_to_string(r));
+  };
+  double2 *out = (double2 *)A;
+  if (d == 1) {
+    // A(q_i, .) = E (pn x L) . u_pad[c_i .. c_i + L), c_i = (q_lo + i) st: one batch over q
+    const double2 *b0 = up + q_lo[0] * st[0];
+    check(rocblas_zgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)pn0, 1,
+                                        (rocblas_int)L[0], &one, (const rocblas_double_complex *)E0, (rocblas_int)pn0,
+                                        0, (const rocblas_double_complex *)b0, (rocblas_int)L[0], st[0], &zero,
+                                        (rocblas_double_complex *)out, (rocblas_int)pn0, pn0, (rocblas_int)q_n[0]));
+    return;
+  }
+  // 2D, one q-row i0 at a time (column-major views of row-major arrays):
+  //   T_i1^T (pn1 x L0) = E1 (pn1 x L1) . W_q^T (L1 x L0),  W_q^T at up + c0 * pad_cols + c1, ld pad_cols
+  //   A_q^T  (pn1 x pn0) = T_i1^T . E0^T (L0 x pn0)
+  for (int64_t i0 = 0; i0 < q_n[0]; ++i0) {
+    const int64_t c0 = (q_lo[0] + i0) * st[0];
+    const double2 *bq = up + c0 * pad_cols + q_lo[1] * st[1];
+    check(rocblas_zgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)pn1,
+                                        (rocblas_int)L[0], (rocblas_int)L[1], &one,
+                                        (const rocblas_double_complex *)E1, (rocblas_int)pn1, 0,
+                                        (const rocblas_double_complex *)bq, (rocblas_int)pad_cols, st[1], &zero,
+                                        (rocblas_double_complex *)T, (rocblas_int)pn1, pn1 * L[0], (rocblas_int)qn1));
+    check(rocblas_zgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)pn1,
+                                        (rocblas_int)pn0, (rocblas_int)L[0], &one, (const rocblas_double_complex *)T,
+                                        (rocblas_int)pn1, pn1 * L[0], (const rocblas_double_complex *)E0,
+                                        (rocblas_int)L[0], 0, &zero,
+                                        (rocblas_double_complex *)(out + i0 * qn1 * pn0 * pn1), (rocblas_int)pn1,
+                                        pn0 * pn1, (rocblas_int)qn1));
+  }
+}
+
+void destroy_blas(void *blas) {
+  if (blas) (void)rocblas_destroy_handle((rocblas_handle)blas);
 }
 
 }  // namespace fggc

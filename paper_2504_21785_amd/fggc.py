@@ -88,6 +88,9 @@ _SIGS = [
     ("fggc_reconstruct", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid),
                               ctypes.POINTER(Strategy), _D, _I, _VP, _VP]),
     ("fggc_decompose", _I, [_VP, ctypes.POINTER(Grid), _VP, _D, _D, _I64, _VP, _VP, _VP, _VP]),
+    ("fggc_decompose_mesh", _I, [_VP, ctypes.POINTER(Grid), _VP, _D, _D, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                                 ctypes.POINTER(_I64), ctypes.POINTER(_D), ctypes.POINTER(_I64),
+                                 ctypes.POINTER(_I64), _VP, _VP]),
     ("fggc_propagate", _I, [_VP, ctypes.c_int32, _I64, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(Potential), _D,
                             _I64, _VP]),
     ("fggc_default_strategy", _I, [_I, _D, ctypes.c_char_p, ctypes.POINTER(Strategy)]),
@@ -304,6 +307,30 @@ class Context:
                 out = np.empty(N, dtype=np.complex128)
         _check(lib().fggc_decompose(self.h, ctypes.byref(g), _ptr(u0), float(eps), float(window_radius), N,
                                     _ptr(q), _ptr(p), _ptr(out), _stream_ptr(stream) if _on_device(q) else None))
+        return out
+
+    def decompose_mesh(self, u0, eps: float, M, window_half_width: float, Nq, q_lo, q_n, dp, p_lo, p_n,
+                       out=None, stream=None):
+        """fggc_decompose_mesh: A(0, q, p) of eq. (2.7) on the product mesh
+        q_k = -pi + (q_lo[k] + i) 2 pi / Nq[k], p_k = (p_lo[k] + j) dp[k] (box window).
+
+        Returns [prod q_n * prod p_n] complex128, q-major (allocated like u0 when out is None).
+        """
+        M = list(M) if hasattr(M, "__len__") else [int(M)]
+        d = len(M)
+        g = _grid(d, M)
+        arr = lambda v, t: (t * 3)(*[(float(x) if t is _D else int(x)) for x in (list(v) + [0] * (3 - d))])
+        total = int(np.prod(list(q_n))) * int(np.prod(list(p_n)))
+        if out is None:
+            if hasattr(u0, "device"):
+                import torch
+                out = torch.empty(total, dtype=torch.complex128, device=u0.device)
+            else:
+                out = np.empty(total, dtype=np.complex128)
+        _check(lib().fggc_decompose_mesh(self.h, ctypes.byref(g), _ptr(u0), float(eps), float(window_half_width),
+                                         arr(Nq, _I64), arr(q_lo, _I64), arr(q_n, _I64), arr(dp, _D), arr(p_lo, _I64),
+                                         arr(p_n, _I64), _ptr(out),
+                                         _stream_ptr(stream) if _on_device(u0) else None))
         return out
 
     def propagate(self, Q, P, S, a, V: Potential, dt: float, nsteps: int, jac=None, stream=None):

@@ -223,3 +223,52 @@ def split_step_1d(u0, Vx, eps, T, nsteps):
     for _ in range(nsteps):
         u = half * np.fft.ifft(kin * np.fft.fft(half * u))
     return u
+
+
+@pytest.mark.parametrize("M,Nq,eps,q_n,p_n", [((1024,), (128,), 1 / 64, (40,), (23,)),
+                                              ((256, 128), (64, 32), 1 / 64, (8, 4), (6, 5)),
+                                              ((512, 512), (128, 128), 1 / 256, (4, 5), (5, 4))])
+def test_decompose_mesh_matches_oracle(ctx, M, Nq, eps, q_n, p_n):
+    """The GEMM form of (2.7) on a mesh with q on grid points, against the
+    oracle's quadrature with the same box window on the same (q, p) list."""
+    d = len(M)
+    axes = [-math.pi + 2 * math.pi * np.arange(m) / m for m in M]
+    X = np.meshgrid(*axes, indexing="ij")
+    u0 = (np.exp(-20 * sum(x * x for x in X) + 1j * sum(X) / eps) * (1 + 0.3 * np.cos(3 * X[0]))).astype(np.complex128)
+    dp = [math.pi * math.sqrt(eps) / 8] * d
+    q_lo = [Nq[k] // 2 - q_n[k] // 2 for k in range(d)]
+    p_lo = [int(round(1.0 / dp[k])) - p_n[k] // 2 for k in range(d)]  # about the momentum of u0
+    R = 8 * math.sqrt(eps)
+    A = ctx.decompose_mesh(torch.from_numpy(u0.ravel().copy()).cuda(), eps, M, R, Nq, q_lo, q_n, dp, p_lo, p_n)
+    torch.cuda.synchronize()
+    qs = [-math.pi + (q_lo[k] + np.arange(q_n[k])) * 2 * math.pi / Nq[k] for k in range(d)]
+    ps = [(p_lo[k] + np.arange(p_n[k])) * dp[k] for k in range(d)]
+    qg = np.stack([g.ravel() for g in np.meshgrid(*qs, indexing="ij")])
+    pg = np.stack([g.ravel() for g in np.meshgrid(*ps, indexing="ij")])
+    qm = np.repeat(qg, pg.shape[1], axis=1)
+    pm = np.tile(pg, (1, qg.shape[1]))
+    ref = flow.decompose(u0.ravel(), eps, list(M), R, qm, pm, window="box")
+    e = rel(A.cpu().numpy(), ref)
+    log("decompose_mesh", M, Nq, eps, e)
+    assert e <= 1e-12
+    Ah = ctx.decompose_mesh(u0.ravel().copy(), eps, M, R, Nq, q_lo, q_n, dp, p_lo, p_n)
+    assert rel(Ah, ref) <= 1e-12
+    # the ball-window quadrature differs by terms below exp(-32)
+    Ab = ctx.decompose(torch.from_numpy(u0.ravel().copy()).cuda(), eps, M, R, torch.from_numpy(qm).cuda(),
+                       torch.from_numpy(pm).cuda())
+    assert rel(Ab.cpu().numpy(), ref) <= 1e-12
+
+
+def test_decompose_mesh_errors(ctx):
+    u0 = np.zeros(256, dtype=np.complex128)
+    for kw in (dict(Nq=(100,)), dict(q_lo=(-1,)), dict(q_n=(200,)), dict(p_n=(0,)), dict(R=math.pi)):
+        args = dict(Nq=(128,), q_lo=(0,), q_n=(4,), p_n=(3,), R=0.5)
+        args.update(kw)
+        with pytest.raises(F.FggcError) as ei:
+            ctx.decompose_mesh(u0, 1 / 64, (256,), args["R"], args["Nq"], args["q_lo"], args["q_n"], (0.05,), (0,),
+                               args["p_n"])
+        assert ei.value.code == F.FGGC_EINVAL
+    with pytest.raises(F.FggcError) as ei:
+        ctx.decompose_mesh(np.zeros(8 ** 3, dtype=np.complex128), 1 / 64, (8, 8, 8), 0.5, (8, 8, 8), (0, 0, 0),
+                           (2, 2, 2), (0.1,) * 3, (0, 0, 0), (2, 2, 2))
+    assert ei.value.code == F.FGGC_EUNSUPPORTED
