@@ -1,7 +1,8 @@
 """The paper's Examples 1 and 2 (Sec. 4) end to end on the GPU.
 
-u0 -> initial decomposition (2.7) on the (q, p) mesh dq = sqrt(eps)/2,
-dp = pi sqrt(eps)/8 -> RK4 flow (2.3)-(2.6) to T = 0.8 with dt = 1e-4 ->
+u0 -> initial decomposition (2.7) on the FGGC mesh (q on grid points,
+dq = 2 pi / Nq ~ sqrt(eps)/2, dp = pi sqrt(eps)/8; batched GEMMs) -> RK4 flow
+(2.3)-(2.6) to T = 0.8 with dt = 1e-4 ->
 reconstruction by FGGC (Q4P2) and by the direct sum (the FGA).  Printed per
 eps: packets kept, the time of each stage, and the FGGC-vs-FGA rel-L2 (the
 paper's "LSA error").
@@ -54,15 +55,18 @@ def run(example: int, inv_eps: int, potential: str, T: float, dt: float, precisi
         V = F.potential(c0=1.0, c2=-1.0, c3=-1.0)
     else:
         V = F.potential(w=(1.0, 1.0))
-    # (q, p) mesh over the support of u0 (|x| < 0.8) and of its transform in p:
-    # per dimension |u0^| ~ exp(-(p - 1)^2 / (2 eps + 128 eps^2)), below 1e-12
-    # of its peak outside |p - 1| = sqrt(27.7 (2 eps + 128 eps^2))
-    dq, dp = math.sqrt(eps) / 2, math.pi * math.sqrt(eps) / 8
-    ph = math.sqrt(27.7 * (2 * eps + 128 * eps * eps)) + 2 * dp
-    q1 = torch.arange(-0.8, 0.8 + 1e-12, dq, dtype=torch.float64, device=dev)
-    p1 = 1.0 + torch.arange(-ph, ph + 1e-12, dp, dtype=torch.float64, device=dev)
+    # the FGGC mesh (q on grid points, dq = 2 pi / Nq, dp = pi sqrt(eps) / 8) over the
+    # support of u0 (|x| < 0.8) and of its transform in p: per dimension
+    # |u0^| ~ exp(-(p - 1)^2 / (2 eps + 128 eps^2)), below 1e-12 of its peak
+    # outside |p - 1| = sqrt(27.7 (2 eps + 128 eps^2))
     ctx = F.Context(0)
     st = F.default_strategy(d, eps, "Q4P2")
+    Nq, dp = int(st.Nq[0]), float(st.dp[0])
+    dq = 2 * math.pi / Nq
+    ph = math.sqrt(27.7 * (2 * eps + 128 * eps * eps)) + 2 * dp
+    qi = [i for i in range(Nq) if abs(-math.pi + i * dq) < 0.8]
+    j0, j1 = math.floor((1.0 - ph) / dp), math.ceil((1.0 + ph) / dp)
+    mesh = ([Nq] * d, [qi[0]] * d, [len(qi)] * d, [dp] * d, [j0] * d, [j1 - j0 + 1] * d)
     scale = (dq * dp) ** d / (2 * math.pi * eps) ** (1.5 * d)
     prec = F.FP64 if precision == "fp64" else F.FP32
     times = {}
@@ -71,31 +75,19 @@ def run(example: int, inv_eps: int, potential: str, T: float, dt: float, precisi
         torch.cuda.synchronize()
         times[name] = time.perf_counter() - t0
 
-    # decomposition in chunks of q-rows (the full mesh of a small eps in 2D is large)
+    u0f = u0.reshape(-1).contiguous()
+    ctx.decompose_mesh(u0f, eps, M, 8 * math.sqrt(eps), *mesh)  # warm-up (library and GEMM kernels)
     t0 = time.perf_counter()
-    keepQ, keepP, keepA = [], [], []
-    amax = 0.0
-    qs = torch.meshgrid(*([q1] * d), indexing="ij")
-    qs = torch.stack([g.reshape(-1) for g in qs])
-    ps = torch.meshgrid(*([p1] * d), indexing="ij")
-    ps = torch.stack([g.reshape(-1) for g in ps])
-    chunk = max(1, (1 << 24) // ps.shape[1])
-    parts = []
-    for i in range(0, qs.shape[1], chunk):
-        qq = qs[:, i:i + chunk].repeat_interleave(ps.shape[1], dim=1).contiguous()
-        pp = ps.repeat(1, min(chunk, qs.shape[1] - i)).contiguous()
-        A = ctx.decompose(u0.reshape(-1).contiguous(), eps, M, 8 * math.sqrt(eps), qq, pp)
-        amax = max(amax, float(A.abs().max()))
-        parts.append((qq, pp, A))
-    for qq, pp, A in parts:
-        k = A.abs() > 1e-12 * amax
-        keepQ.append(qq[:, k])
-        keepP.append(pp[:, k])
-        keepA.append(A[k])
-    Q = torch.cat(keepQ, dim=1).contiguous()
-    P = torch.cat(keepP, dim=1).contiguous()
-    A = torch.cat(keepA).contiguous()
-    del parts
+    A = ctx.decompose_mesh(u0f, eps, M, 8 * math.sqrt(eps), *mesh)
+    q1 = -math.pi + dq * torch.arange(qi[0], qi[-1] + 1, dtype=torch.float64, device=dev)
+    p1 = dp * torch.arange(j0, j1 + 1, dtype=torch.float64, device=dev)
+    qg = torch.stack([g.reshape(-1) for g in torch.meshgrid(*([q1] * d), indexing="ij")])
+    pg = torch.stack([g.reshape(-1) for g in torch.meshgrid(*([p1] * d), indexing="ij")])
+    mag = A.abs()
+    idx = torch.nonzero(mag > 1e-12 * mag.max()).squeeze(1)
+    Q = qg[:, idx // pg.shape[1]].contiguous()
+    P = pg[:, idx % pg.shape[1]].contiguous()
+    A = A[idx].contiguous()
     tick("decompose_s", t0)
     N = A.shape[0]
     S = torch.zeros(N, dtype=torch.float64, device=dev)
@@ -147,9 +139,11 @@ def run_multi(example: int, inv_eps: int, potential: str, T: float, dt: float, s
     # the FGGC mesh over the region of phase space the wave visits: q in (-1, 1.8),
     # p in (p_min, p_max); in Example 4's cosine well the wave reflects after
     # about a quarter period (t ~ 0.5), so its momenta reach -1
-    q1 = -math.pi + (2 * math.pi / Nq) * torch.arange(Nq, dtype=torch.float64, device=dev)
-    q1 = q1[(q1 > -1.0) & (q1 < 1.8)]
-    p1 = dp * torch.arange(math.floor(p_min / dp), math.ceil(p_max / dp) + 1, dtype=torch.float64, device=dev)
+    qi = [i for i in range(Nq) if -1.0 < -math.pi + 2 * math.pi * i / Nq < 1.8]
+    q1 = -math.pi + (2 * math.pi / Nq) * torch.arange(qi[0], qi[-1] + 1, dtype=torch.float64, device=dev)
+    j0, j1 = math.floor(p_min / dp), math.ceil(p_max / dp)
+    p1 = dp * torch.arange(j0, j1 + 1, dtype=torch.float64, device=dev)
+    mesh = ([Nq] * d, [qi[0]] * d, [len(qi)] * d, [dp] * d, [j0] * d, [j1 - j0 + 1] * d)
     qg = torch.stack([g.reshape(-1) for g in torch.meshgrid(*([q1] * d), indexing="ij")])
     pg = torch.stack([g.reshape(-1) for g in torch.meshgrid(*([p1] * d), indexing="ij")])
     qm = qg.repeat_interleave(pg.shape[1], dim=1).contiguous()
@@ -157,10 +151,10 @@ def run_multi(example: int, inv_eps: int, potential: str, T: float, dt: float, s
     prec = F.FP64 if precision == "fp64" else F.FP32
     nsteps = int(round(T / dt))
     ctx = F.Context(0)
-    MultiStep(ctx, eps, M, qm, pm, V, dt, nsteps, st, precision=prec, prune=prune).run(u0, 1)  # warm-up
+    MultiStep(ctx, eps, M, qm, pm, V, dt, nsteps, st, precision=prec, prune=prune, mesh=mesh).run(u0, 1)  # warm-up
     out, base = [], None
     for runs in splits:
-        ms = MultiStep(ctx, eps, M, qm, pm, V, dt, nsteps // runs, st, precision=prec, prune=prune)
+        ms = MultiStep(ctx, eps, M, qm, pm, V, dt, nsteps // runs, st, precision=prec, prune=prune, mesh=mesh)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         u = ms.run(u0, runs)

@@ -1,7 +1,8 @@
 """Multi-step FGGC (Alg. 3) on the GPU, through libfggc.
 
 T_final = T_multi * T_evo.  Each run
-- decomposes the current u on a fixed (q, p) mesh (fggc_decompose, eq. 2.7),
+- decomposes the current u on a fixed (q, p) mesh (fggc_decompose, or
+  fggc_decompose_mesh for a product mesh on grid points, eq. 2.7),
 - evolves over T_evo only the mesh points that no earlier run has seen
   (fggc_propagate, eq. 2.3-2.6) and keeps what the flow maps them to,
 - and reconstructs u by FGGC (fggc_reconstruct).
@@ -21,7 +22,10 @@ from paper_2504_21785_amd import fggc as F
 
 class MultiStep:
     def __init__(self, ctx, eps: float, M, qm, pm, V, dt: float, steps: int, strategy,
-                 R_dec: float = None, prune: float = 1e-12, precision: int = F.FP64):
+                 R_dec: float = None, prune: float = 1e-12, precision: int = F.FP64, mesh=None):
+        """mesh: None, or (Nq, q_lo, q_n, dp, p_lo, p_n) when (qm, pm) is that product
+        mesh listed q-major with q on grid points; the decomposition then runs as
+        batched GEMMs (fggc_decompose_mesh, box window)."""
         import torch
         self.torch = torch
         self.ctx, self.eps, self.M = ctx, float(eps), tuple(int(m) for m in M)
@@ -29,7 +33,7 @@ class MultiStep:
         self.qm, self.pm = qm.contiguous(), pm.contiguous()  # [d][Nm] float64 on the GPU
         self.V, self.dt, self.steps, self.st = V, float(dt), int(steps), strategy
         self.R_dec = 8 * math.sqrt(eps) if R_dec is None else float(R_dec)
-        self.prune, self.precision = float(prune), precision
+        self.prune, self.precision, self.mesh = float(prune), precision, mesh
         Nm = self.qm.shape[1]
         dev = self.qm.device
         self.learned = torch.zeros(Nm, dtype=torch.bool, device=dev)
@@ -46,7 +50,10 @@ class MultiStep:
         torch = self.torch
         for _ in range(int(runs)):
             u64 = u.reshape(-1).to(torch.complex128).contiguous()
-            A0 = self.ctx.decompose(u64, self.eps, self.M, self.R_dec, self.qm, self.pm)
+            if self.mesh is not None:
+                A0 = self.ctx.decompose_mesh(u64, self.eps, self.M, self.R_dec, *self.mesh)
+            else:
+                A0 = self.ctx.decompose(u64, self.eps, self.M, self.R_dec, self.qm, self.pm)
             mag = A0.abs()
             keep = mag > self.prune * mag.max()
             new = torch.nonzero(keep & ~self.learned).squeeze(1)
