@@ -213,6 +213,28 @@ int fggc_decompose_mesh(fggc_ctx *ctx, const fggc_grid *grid, const double *u0, 
                         const double *dp, const int64_t *p_lo, const int64_t *p_n, double *A_out, void *stream);
 
 /*
+ * The seeded synthetic workloads (configurations 0-3):
+ *   0: 1D, eps = 1/64, N = 256 x 256 (q, p), grid 1024;
+ *   1: 1D, eps = 1/1024, N = 1024 x 1024, grid 16384;
+ *   2: 2D, eps = 1/256, N = 64^2 q x 32^2 p, grid 1024^2;
+ *   3: 3D, eps = 1/128, N = 32^3 q x 8^3 p, grid 256^3.
+ * Packets start on a (q, p) mesh (q uniform over [-pi, pi)^d; p random in
+ * 1D, an endpoint-inclusive mesh in 2D/3D), are carried by free flow
+ * (eq. 2.3-2.4 with V = 0) to t = 0.5, and carry a uniform random action and
+ * a Gaussian-in-q amplitude with a uniform random phase; random numbers are
+ * SplitMix64 counter streams (the package's Python generator draws the same
+ * values).  The window radius of the direct sum is 6 sqrt(eps).
+ * fggc_config_info returns the sizes (any output pointer may be NULL).
+ * fggc_gen_config fills caller-allocated host arrays out->Q, out->P
+ * ([d][N]), out->S ([N]) and out->a ([N] complex128), written through the
+ * pointers of `out`; out->d and out->N must equal the configuration's.
+ * seed = 0 selects the default seed of the configuration.  Host only, no
+ * GPU call.  Errors: FGGC_EINVAL for an unknown config_id or a mismatching out.
+ */
+int fggc_config_info(int config_id, int32_t *d, int64_t *N, double *eps, fggc_grid *grid, double *window_radius);
+int fggc_gen_config(int config_id, uint64_t seed, fggc_packets *out);
+
+/*
  * Potential of the packet flow:
  *   V(x) = c0 + sum_k w[k] x_k^2 / 2 + c1 sum_k cos(kappa x_k) + c2 exp(c3 |x|^2).
  * The paper's examples (Sec. 4) are members: 1 - cos(pi x) (c0 = 1, c1 = -1,

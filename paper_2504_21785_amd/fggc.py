@@ -94,6 +94,9 @@ _SIGS = [
     ("fggc_propagate", _I, [_VP, ctypes.c_int32, _I64, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(Potential), _D,
                             _I64, _VP]),
     ("fggc_default_strategy", _I, [_I, _D, ctypes.c_char_p, ctypes.POINTER(Strategy)]),
+    ("fggc_config_info", _I, [_I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_I64), ctypes.POINTER(_D),
+                              ctypes.POINTER(Grid), ctypes.POINTER(_D)]),
+    ("fggc_gen_config", _I, [_I, ctypes.c_uint64, ctypes.POINTER(Packets)]),
     ("fggc_cell_box", _I, [_VP, ctypes.POINTER(Packets), ctypes.POINTER(Strategy),
                            ctypes.POINTER(_I64), ctypes.POINTER(_I64), _VP]),
     ("fggc_cells", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Strategy), _D, _I,
@@ -145,6 +148,28 @@ def default_strategy(d: int, eps: float, name: str = "Q4P2") -> Strategy:
     st = Strategy()
     _check(lib().fggc_default_strategy(d, eps, name.encode(), ctypes.byref(st)))
     return st
+
+
+def config_info(config_id: int) -> dict:
+    """fggc_config_info: d, N, eps, grid and window radius of a synthetic workload (0-3)."""
+    d, N, eps, R = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    g = Grid()
+    _check(lib().fggc_config_info(int(config_id), ctypes.byref(d), ctypes.byref(N), ctypes.byref(eps),
+                                  ctypes.byref(g), ctypes.byref(R)))
+    return {"d": d.value, "N": N.value, "eps": eps.value, "M": tuple(g.n[:d.value]), "R": R.value}
+
+
+def gen_config(config_id: int, seed: int = 0):
+    """fggc_gen_config: the workload's packets as numpy arrays (Q, P [d][N], S [N], a [N] complex)."""
+    info = config_info(config_id)
+    d, N = info["d"], info["N"]
+    Q, P = np.empty((d, N)), np.empty((d, N))
+    S, a = np.empty(N), np.empty(N, dtype=np.complex128)
+    pk = Packets()
+    pk.d, pk.N = d, N
+    pk.Q, pk.P, pk.S, pk.a = Q.ctypes.data, P.ctypes.data, S.ctypes.data, a.ctypes.data
+    _check(lib().fggc_gen_config(int(config_id), ctypes.c_uint64(seed), ctypes.byref(pk)))
+    return Q, P, S, a
 
 
 def make_strategy(d: int, Nq: Sequence[int], dp: Sequence[float], dq_off: Sequence[int],

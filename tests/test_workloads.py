@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+import pytest
 
 from paper_2504_21785_amd import workloads as w
 
@@ -48,3 +49,26 @@ def test_serving_requests_cover_the_mix():
         assert 2 ** 12 <= req.N < 2 ** 22
         assert req.Q.shape == (req.d, req.N)
     assert ds == {1, 2} and len(epss) == 3
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_native_generator_matches(k):
+    """fggc_gen_config (C ABI, host) draws the same packets as the Python generator:
+    uniform-derived values bit for bit, Box-Muller normals to the last ulp or two
+    (the two sides call different cos / log1p implementations)."""
+    from paper_2504_21785_amd import fggc as F
+    ps = w.config(k)
+    info = F.config_info(k)
+    assert (info["d"], info["N"], info["M"]) == (ps.d, ps.N, tuple(ps.M))
+    assert info["eps"] == ps.eps and abs(info["R"] - ps.R) <= 1e-15
+    Q, P, S, a = F.gen_config(k)
+    assert np.array_equal(S, ps.S)
+    if k >= 2:  # mesh momenta: no normals involved
+        assert np.array_equal(P, ps.P) and np.array_equal(Q, ps.Q)
+    assert np.max(np.abs(P - ps.P)) <= 4e-16 * np.max(np.abs(ps.P))
+    assert np.max(np.abs(Q - ps.Q)) <= 1e-15
+    assert np.max(np.abs(a - ps.a)) <= 1e-15
+    # another seed gives other values, and the same ones on both sides
+    Q2, _, S2, _ = F.gen_config(k, seed=12345)
+    assert not np.array_equal(S2, S)
+    assert np.array_equal(S2, w.config(k, seed=12345).S)
