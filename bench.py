@@ -392,6 +392,19 @@ def main():
                "sample": f"FP64 FGGC oracle (cells, then plain evaluation of eq. 2.24 with window "
                          f"8 sqrt(eps)): {samp}; mean of {n_f} runs",
                "seconds_per_run": t_of}
+        # one thread, one run: what a single core of the box does
+        prev = oracle.set_threads(1)
+        t0 = time.perf_counter()
+        run_f()
+        cpu["single_thread"] = {"value": ps.N / ((time.perf_counter() - t0) * scale_pts), "unit": "packets/s",
+                                "cores": 1, "sample": f"the same FGGC oracle sample, one run on one thread"}
+        oracle.set_threads(prev)
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu["host_cpu"] = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+        except OSError:
+            cpu["host_cpu"] = None
+        cpu["host_threads"] = os.cpu_count()
         ref_d = None
         if do_direct:
             ref_d, t_od, n_d = timed(run_d)

@@ -57,6 +57,11 @@ def _cplx(x):
     return np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
 
 
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops; returns the previous count."""
+    return int(_load().oracle_set_threads(ctypes.c_int(int(n))))
+
+
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
 

@@ -103,6 +103,13 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Threads of the oracle's parallel loops (n >= 1); returns the previous count. */
+int oracle_set_threads(int n) {
+  const int prev = omp_get_max_threads();
+  if (n >= 1) omp_set_num_threads(n);
+  return prev;
+}
+
 /* ------------------------------------------------------------------------ */
 /* direct sum, eq. (2.10) / (2.19)                                          */
 /* ------------------------------------------------------------------------ */
