@@ -26,7 +26,7 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 # stage name -> kernel-name fragments (the kernels that make up the stage)
 STAGE_KERNELS = {
     "fggc_coef": ["fggc_coef_kernel"],
-    "fggc_accum": ["fggc_agg1_kernel", "fggc_stencil1_kernel", "fggc_accum_wave_kernel",
+    "fggc_accum": ["fggc_agg1_kernel", "fggc_stencil1_kernel", "fggc_stencil_fft1_kernel", "fggc_accum_wave_kernel",
                    "fggc_accum_kernel", "fggc_accum_generic_kernel"],
     # bucket_pos_kernel also serves the direct sum's sort; its dispatches count here
     "fggc_sort": ["fggc_key_kernel", "fggc_rank_kernel", "count_rowscan_kernel", "count_binscan_kernel",
@@ -34,6 +34,7 @@ STAGE_KERNELS = {
     "fggc_band_mac": ["band_mac"],
     "fggc_contract": ["fft_contract_kernel"],
     "ds_kernel": ["ds_kernel"],
+    "ds_sep2": ["ds_sep2_kernel"],
 }
 
 

@@ -268,6 +268,34 @@ def test_reconstruct_3d_small(ctx, orc):
     assert e <= 1e-12
 
 
+def test_cells_3d_match_oracle_and_sub_box(ctx, orc):
+    """3D Q2P2 cells (the atomic scatter) against the oracle's cells of eq. (2.25);
+    a caller-chosen box that cuts the packets' p-cells is refused."""
+    # eps = 1/16: 64^3 q-cells per slice and ~5 slices per axis (~0.5 GB of FP64 cells)
+    ps = W.gen_mesh(3, 8, 3, 0.3, (0.5, 0.3, 0.3), 1.0 / 16, 64, seed=12)
+    st = F.default_strategy(3, ps.eps, "Q2P2")
+    lo0, n0 = ctx.cell_box(t(ps.Q), t(ps.P), t(ps.S), t(ps.a), st)
+    assert np.prod(np.asarray(n0) + 2) * np.prod(list(st.Nq)[:3]) * 16 < 2e9
+    sd = st.describe()
+    args = (t(ps.Q), t(ps.P), t(ps.S), t(ps.a), ps.eps, st)
+    cells, lo, n = ctx.cells(*args, scale=0.5, precision=F.FP64)
+    ref, slo, sn = orc.fggc_cells(ps.Q, ps.P, ps.S, ps.a, ps.eps, sd["Nq"][:3], sd["dp"][:3], sd["dq_off"],
+                                  sd["dp_off"], scale=0.5)
+    assert list(lo) == list(slo) and list(n) == list(sn)
+    e = rel(cells.reshape(-1), ref.reshape(-1))
+    log("cells 3d rel", e)
+    assert e <= 1e-10
+    assert min(n) >= 3
+    with pytest.raises(F.FggcError) as ei:
+        ctx.cells(*args, scale=0.5, precision=F.FP64, box=(np.asarray(lo) + 1, np.asarray(n) - 2))
+    assert ei.value.code == F.FGGC_EINVAL
+    # a larger box holds the same cells, surrounded by zeros
+    big, _, _ = ctx.cells(*args, scale=0.5, precision=F.FP64, box=(np.asarray(lo) - 1, np.asarray(n) + 2))
+    inner = big.reshape(*[int(v) + 2 for v in n], -1)[1:-1, 1:-1, 1:-1].reshape(cells.shape)
+    assert np.max(np.abs(inner - cells)) <= 1e-13 * np.max(np.abs(cells))
+    assert np.count_nonzero(big) == np.count_nonzero(cells)
+
+
 def test_fggc_vs_direct_cfg1(ctx):
     """FGGC and the direct sum agree at the LSA level (Q4P2 ~ 3e-7 at C = pi/8)."""
     ps = W.config(1)
