@@ -376,11 +376,11 @@ typedef int64_t fggc_ticket;
  * context's HBM budget (idle slots release memory when that makes it fit);
  * admitted requests overlap on the device.  A slot runs a request's kernel
  * pipeline eagerly the first time its shape is seen, captures it into a
- * hipGraph the second time and replays that graph afterwards (up to 32
+ * hipGraph the second time and replays that graph afterwards (up to 128
  * graphs per slot, least recently used dropped).  Shapes repeat because the
  * packet count is padded to a quarter-octave bucket (m 2^e, m in 4..8, at
- * least 64) with zero-amplitude copies of packet 0, which add exactly
- * nothing, and the p-cell box is widened to even cell indices.  The budget
+ * least 64) with zero-amplitude copies of packets 0, 1, 2, ..., which add
+ * exactly nothing, and the p-cell box is widened to even cell indices.  The budget
  * covers the slots' workspaces; synchronous calls on the same context
  * during serving allocate outside it.
  * Errors: FGGC_EINVAL (NULL out or ctx, n_streams out of range),

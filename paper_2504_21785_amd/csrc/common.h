@@ -191,7 +191,7 @@ void launch_packet_scan(const fggc_packets &pk, const double *dp, long long *par
 // in a graph, unlike a memset node).
 void launch_zero(void *p, size_t bytes, hipStream_t s);
 // Fill slots [N, Npad) of SoA packet arrays sized Npad with zero-amplitude
-// copies of packet 0 (they add exactly nothing to any sum).
+// copies of packets 0, 1, 2, ... (they add exactly nothing to any sum).
 void launch_pad_packets(int d, int64_t N, int64_t Npad, double *Q, double *P, double *S, double *a,
                         hipStream_t s);
 

@@ -103,7 +103,10 @@ struct fggc_server;
 namespace fggc {
 namespace {
 
-constexpr int kMaxGraphs = 32;  // cached executable graphs per slot
+// cached executable graphs per slot: a slot may serve every shape of a stream
+// (the scheduler reuses the smallest slot that fits), and an LRU smaller than
+// the set of shapes in rotation misses on every request
+constexpr int kMaxGraphs = 128;
 
 struct Slot {
   int idx = 0;

@@ -407,16 +407,20 @@ __global__ void zero_kernel(uint32_t *__restrict__ p, int64_t n) {
     p[i] = 0u;
 }
 
-// zero-amplitude copies of packet 0 in slots [N, Npad) of SoA arrays sized Npad
+// Slots [N, Npad) of SoA arrays sized Npad get zero-amplitude copies of
+// packets 0, 1, 2, ... (cyclically).  The copies sit where the real packets
+// are, so no cell receives more than a few of them; copies of a single
+// packet would pile into one cell and serialise the accumulation of its bin.
 __global__ void pad_packets_kernel(int d, int64_t N, int64_t Npad, double *Q, double *P, double *S,
                                    double *a) {
   const int64_t j = N + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= Npad) return;
+  const int64_t src = (j - N) % N;
   for (int k = 0; k < d; ++k) {
-    Q[k * Npad + j] = Q[k * Npad];
-    P[k * Npad + j] = P[k * Npad];
+    Q[k * Npad + j] = Q[k * Npad + src];
+    P[k * Npad + j] = P[k * Npad + src];
   }
-  S[j] = S[0];
+  S[j] = S[src];
   a[2 * j] = 0.0;
   a[2 * j + 1] = 0.0;
 }
