@@ -173,3 +173,61 @@ def test_server_budget_and_timeout(ctx):
     finally:
         srv.close()
         small.close()
+
+
+def test_server_tiny_requests_padding(ctx):
+    # N below the smallest bucket (64) or just above a bucket edge: the
+    # zero-amplitude padding copies wrap around the real packets several times
+    srv = F.Server(ctx, n_streams=2)
+    try:
+        for d in (1, 2):
+            for N in (1, 5, 37, 65, 300):
+                base = W.serving_request(0 if d == 1 else 1)
+                assert base.d == d
+                sel = np.sort(np.argsort(-np.abs(base.a))[:N])  # packets that matter in FP32
+                ps = W.PacketSet(f"tiny{d}_{N}", d, base.eps, base.M, np.ascontiguousarray(base.Q[:, sel]),
+                                 np.ascontiguousarray(base.P[:, sel]), np.ascontiguousarray(base.S[sel]),
+                                 np.ascontiguousarray(base.a[sel]), base.R)
+                ref = alone(ctx, ps)
+                st = F.default_strategy(d, ps.eps, "Q4P2")
+                for rep in range(3):  # eager, captured, replayed
+                    tk, out = srv.submit(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, st)
+                    assert srv.wait(tk, 120.0) == F.FGGC_OK, F.last_error()
+                    e = rel(out, ref)
+                    log(f"tiny d={d} N={N} rep {rep}: server vs alone {e:.2e}")
+                    assert e <= 1e-6
+    finally:
+        srv.close()
+
+
+def test_server_padding_keeps_cells_balanced(ctx):
+    # A 2D request at eps = 1/1024 (radix-sorted, so it runs eagerly every
+    # time) padded by ~17% to its bucket.  Copies of a single packet would
+    # crowd one cell, whose bin one wave accumulates alone; the server then
+    # took over ten times the synchronous call.  Loose bound: 4x + 10 ms.
+    import time
+    ps = W.serving_request(11)
+    assert ps.d == 2 and ps.eps == 1.0 / 1024
+    st = F.default_strategy(2, ps.eps, "Q4P2")
+    dev = (t(ps.Q), t(ps.P), t(ps.S), t(ps.a))
+    torch.cuda.synchronize()
+    ctx.reconstruct(*dev, ps.eps, ps.M, st)
+    torch.cuda.synchronize()
+    t_sync = 1e9
+    for _ in range(3):
+        t0 = time.perf_counter()
+        ctx.reconstruct(*dev, ps.eps, ps.M, st)
+        torch.cuda.synchronize()
+        t_sync = min(t_sync, time.perf_counter() - t0)
+    srv = F.Server(ctx, n_streams=1)
+    try:
+        t_srv = 1e9
+        for _ in range(3):
+            t0 = time.perf_counter()
+            tk, _ = srv.submit(*dev, ps.eps, ps.M, st)
+            assert srv.wait(tk, 120.0) == F.FGGC_OK, F.last_error()
+            t_srv = min(t_srv, time.perf_counter() - t0)
+    finally:
+        srv.close()
+    log(f"N={ps.N}: server {t_srv * 1e3:.2f} ms, synchronous {t_sync * 1e3:.2f} ms")
+    assert t_srv <= 4 * t_sync + 0.010
