@@ -130,7 +130,14 @@ struct alignas(16) DimLsq {
   // smallest shifts
   double DK[2 * kMaxN1];
   double V[2 * kMaxN1 * kMaxN1];  // [row][col] complex, columns are eigenvectors
+  // W[j][i] = inv_i conj(V[j][i]) DK_j: the first product of the solve with
+  // the right-hand side's constant factor and 1/lambda folded in, so that
+  // z = diag(inv) V^H (DK .* h) is one product W^T h per packet.  The second
+  // product V z stays separate (the pseudo-inverse is never formed).
+  double W[2 * kMaxN1 * kMaxN1];
 };
+static_assert(offsetof(DimLsq, V) % 16 == 0 && offsetof(DimLsq, W) % 16 == 0,
+              "the plan is staged in 16-byte units");
 
 // Hermitian eigen-decomposition of a complex n x n matrix (cyclic Jacobi on
 // the real symmetric 2n x 2n embedding, FP64).  evals ascending, evecs

@@ -249,8 +249,8 @@ __device__ __forceinline__ void dim_coeffs_exact(const DimLsq &L, double s, doub
   double ppr[NP], ppi[NP];
 #pragma unroll
   for (int b = 0; b < NP; ++b) cpow(upr, upi, L.dp[b] - L.dp0, ppr[b], ppi[b]);
-  // z = diag(inv) V^H g, accumulated one basis function at a time (g_j is
-  // never stored); uq^Eq_a is kept as a running power over a
+  // z = diag(inv) V^H (DK .* h) = W^T h, accumulated one basis function at a
+  // time (h_j is never stored); uq^Eq_a is kept as a running power over a
   double zr[N1], zi[N1];
 #pragma unroll
   for (int i = 0; i < N1; ++i) zr[i] = zi[i] = 0.0;
@@ -271,24 +271,17 @@ __device__ __forceinline__ void dim_coeffs_exact(const DimLsq &L, double s, doub
     for (int b = 0; b < NP; ++b) {
       const int j = a * NP + b;
       const double hr = pqr * ppr[b] - pqi * ppi[b], hi = pqr * ppi[b] + pqi * ppr[b];
-      const double kr = L.DK[2 * j], ki = L.DK[2 * j + 1];
-      const double gr = hr * kr - hi * ki, gi = hr * ki + hi * kr;
-      // one row of V at a time: the compiler would otherwise load all of V
-      // at once (and keep it for the second product), at a cost in occupancy
+      // one row of W at a time: the compiler would otherwise load all of it
+      // at once, at a cost in occupancy
       row_fence(zr, zi);
 #pragma unroll
       for (int i = 0; i < N1; ++i) {
-        const double vr = L.V[2 * (j * N1 + i)], vi = L.V[2 * (j * N1 + i) + 1];
-        // conj(V_ji) g_j
-        zr[i] = fma(vr, gr, fma(vi, gi, zr[i]));
-        zi[i] = fma(vr, gi, fma(-vi, gr, zi[i]));
+        const double wr = L.W[2 * (j * N1 + i)], wi = L.W[2 * (j * N1 + i) + 1];
+        // W_ji h_j
+        zr[i] = fma(wr, hr, fma(-wi, hi, zr[i]));
+        zi[i] = fma(wr, hi, fma(wi, hr, zi[i]));
       }
     }
-  }
-#pragma unroll
-  for (int i = 0; i < N1; ++i) {
-    zr[i] *= L.inv[i];
-    zi[i] *= L.inv[i];
   }
   // c = conj(V z) Fi^Eq_a, Fi^Eq_a again as a running power over a
   pqr = 1.0;
@@ -468,9 +461,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 1 && N
   // rather than through scalar registers (which V overflows)
   __shared__ DimLsq sl[D];
   {
-    const uint4 *src = reinterpret_cast<const uint4 *>(p.lsq);
-    uint4 *dst = reinterpret_cast<uint4 *>(sl);
-    for (int e = threadIdx.x; e < (int)(D * sizeof(DimLsq) / 16); e += blockDim.x) dst[e] = src[e];
+    // per dimension: the fields before V, and the n1 x n1 corners of V and W
+    // in use (both are stored with row stride n1)
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const uint4 *src = reinterpret_cast<const uint4 *>(p.lsq + k);
+      uint4 *dst = reinterpret_cast<uint4 *>(sl + k);
+      const int n1 = p.lsq[k].n1;
+      const int nv = (int)(offsetof(DimLsq, V) / 16) + n1 * n1, w0 = (int)(offsetof(DimLsq, W) / 16);
+      for (int e = threadIdx.x; e < nv + n1 * n1; e += blockDim.x) {
+        const int at = e < nv ? e : w0 + (e - nv);
+        dst[at] = src[at];
+      }
+    }
     __syncthreads();
   }
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;

@@ -140,6 +140,13 @@ void build_dim_lsq(const fggc_strategy &st, int dim, double eps, DimLsq *out) {
     const long double g = std::exp(-(Cq * Cq * eq * eq + Cp * Cp * ep * ep) / 4);
     out->DK[2 * k] = (double)(g * std::cos(ph));
     out->DK[2 * k + 1] = (double)(g * std::sin(ph));
+    const cld dk = g * cld(std::cos(ph), std::sin(ph));
+    for (int i = 0; i < n1; ++i) {
+      const long double iv = w[i] > cut ? 1 / w[i] : 0.0L;
+      const cld x = iv * std::conj(V[(size_t)k * n1 + i]) * dk;
+      out->W[2 * (k * n1 + i)] = (double)x.real();
+      out->W[2 * (k * n1 + i) + 1] = (double)x.imag();
+    }
   }
 }
 
