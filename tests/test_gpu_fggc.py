@@ -383,3 +383,55 @@ def test_repeated_3d_calls_on_radix_sort_path(ctx, orc):
         e = rel(u.cpu().numpy().reshape(-1)[pts].astype(np.complex128), ref)
         log(f"  vs oracle {e:.2e}")
         assert e <= 1e-6
+
+
+def edge_packets(d, eps, st, seed):
+    """Packets on the q- and p-mesh points of strategy `st` (s = t = 0 up to the
+    rounding of Q / dq), at -pi and just below pi (the periodic seam), at
+    negative momenta, and one at a random point."""
+    rng = np.random.default_rng(seed)
+    sd = st.describe()
+    dq = [2 * math.pi / sd["Nq"][k] for k in range(d)]
+    dp = [sd["dp"][k] for k in range(d)]
+    Qs, Ps = [], []
+    for i in (-(sd["Nq"][0] // 2), -3, 0, 5, sd["Nq"][0] // 2 - 1):
+        for l in (-7, -1, 0, 2, 9):
+            Qs.append([-math.pi + (i + sd["Nq"][0] // 2) * dq[k] for k in range(d)])
+            Ps.append([l * dp[k] for k in range(d)])
+    Qs.append([-math.pi] * d)
+    Ps.append([-0.3] * d)
+    Qs.append([math.pi - 1e-12] * d)
+    Ps.append([0.45] * d)
+    Qs.append(list(rng.uniform(-math.pi, math.pi, d)))
+    Ps.append(list(rng.uniform(-0.5, 0.5, d)))
+    Q = np.ascontiguousarray(np.array(Qs).T)
+    P = np.ascontiguousarray(np.array(Ps).T)
+    N = Q.shape[1]
+    S = rng.uniform(0, 2 * math.pi, N)
+    a = rng.normal(size=N) + 1j * rng.normal(size=N)
+    return Q, P, S, a
+
+
+@pytest.mark.parametrize("d,M", [(1, 512), (2, 64)])
+@pytest.mark.parametrize("prec,tol", [(F.FP64, 1e-12), (F.FP32, 1e-6)])
+def test_reconstruct_edge_cases(ctx, orc, d, M, prec, tol):
+    eps = 1.0 / 64
+    st = F.default_strategy(d, eps, "Q2P2")
+    sd = st.describe()
+    grid = (M,) * d
+    # no packets: zeros
+    e0 = np.zeros((d, 0))
+    u = ctx.reconstruct(t(e0), t(e0), t(np.zeros(0)), t(np.zeros(0, complex)), eps, grid, st, precision=prec)
+    torch.cuda.synchronize()
+    assert u.shape[-1] == M and not torch.any(u != 0)
+    Q, P, S, a = edge_packets(d, eps, st, seed=20 + d)
+    for sel in (slice(0, 1), slice(-1, None), slice(None)):  # a single packet, another one, all
+        q, p, s_, a_ = (np.ascontiguousarray(Q[:, sel]), np.ascontiguousarray(P[:, sel]),
+                        np.ascontiguousarray(S[sel]), np.ascontiguousarray(a[sel]))
+        u = ctx.reconstruct(t(q), t(p), t(s_), t(a_), eps, grid, st, precision=prec)
+        torch.cuda.synchronize()
+        u = u.cpu().numpy().reshape(-1).astype(np.complex128)
+        ref = orc.fggc(q, p, s_, a_, eps, grid, sd["Nq"][:d], sd["dp"][:d], sd["dq_off"], sd["dp_off"])
+        e = rel(u, ref)
+        log(f"edge d={d} prec={prec} N={q.shape[1]}: {e:.2e}")
+        assert e <= tol
