@@ -224,9 +224,49 @@ def eval_cells(cells, slo, sn, Nq, dp, eps, M, Ro, pts=None):
     return u
 
 
-def fggc(Q, P, S, a, eps, M, Nq, dp, dq_off, dp_off, rcond=0.0, scale=1.0, Ro=None, pts=None):
-    """Whole FGGC reconstruction: cells (eq. 2.25) then eq. (2.24) over cells, window Ro = 8 sqrt(eps)."""
+def fggc_points(Q, P, S, a, eps, M, Nq, dp, dq_off, dp_off, pts, rcond=0.0, scale=1.0, Ro=None,
+                max_bytes=4e9):
+    """FGGC at grid points `pts` keeping only the cells within Ro of them (no dense cell array).
+
+    The same scatter (eq. 2.23-2.25) and the same plain evaluation of eq. (2.24)
+    as fggc_cells + eval_cells; points are processed in batches whose kept cells
+    fit in max_bytes."""
     if Ro is None:
         Ro = 8.0 * np.sqrt(eps)
+    Q = _f64(Q); P = _f64(P); S = _f64(S); a = _cplx(a)
+    d, N = Q.shape
+    Nq = _i64(np.broadcast_to(Nq, (d,))); dp = _f64(np.broadcast_to(dp, (d,)))
+    dq_off = np.ascontiguousarray(np.asarray(dq_off, dtype=np.int32))
+    dp_off = np.ascontiguousarray(np.asarray(dp_off, dtype=np.int32))
+    M = _i64(M)
+    pts_a = _i64(pts)
+    u = np.zeros(pts_a.size, dtype=np.complex128)
+    if pts_a.size == 0:
+        return u
+    if N == 0:
+        return u
+    lo, hi = pcell_bounds(P, dp)
+    slo = _i64(lo + dp_off.min())
+    sn = _i64(hi + dp_off.max() - slo + 1)
+    rc = _load().oracle_fggc_points(ctypes.c_int(d), ctypes.c_int64(N), _p(Q), _p(P), _p(S), _p(a),
+                                    ctypes.c_double(eps), _p(Nq), _p(dp), ctypes.c_int(dq_off.size),
+                                    _p(dq_off), ctypes.c_int(dp_off.size), _p(dp_off),
+                                    ctypes.c_double(rcond), ctypes.c_double(scale), _p(slo), _p(sn), _p(M),
+                                    ctypes.c_double(Ro), ctypes.c_int64(pts_a.size), _p(pts_a),
+                                    ctypes.c_double(max_bytes), _p(u))
+    _check(rc, "oracle_fggc_points")
+    return u
+
+
+def fggc(Q, P, S, a, eps, M, Nq, dp, dq_off, dp_off, rcond=0.0, scale=1.0, Ro=None, pts=None,
+         sparse=None):
+    """Whole FGGC reconstruction: cells (eq. 2.25) then eq. (2.24) over cells, window Ro = 8 sqrt(eps).
+
+    With grid points `pts`, only the cells within Ro of them are kept (fggc_points)
+    unless sparse=False, which builds the dense cell array as for the whole grid."""
+    if Ro is None:
+        Ro = 8.0 * np.sqrt(eps)
+    if pts is not None and sparse is not False:
+        return fggc_points(Q, P, S, a, eps, M, Nq, dp, dq_off, dp_off, pts, rcond, scale, Ro)
     cells, slo, sn = fggc_cells(Q, P, S, a, eps, Nq, dp, dq_off, dp_off, rcond, scale)
     return eval_cells(cells, slo, sn, Nq, dp, eps, M, Ro, pts)

@@ -30,6 +30,9 @@
  *                            and the scatter of eq. (2.23)-(2.25).
  *   oracle_eval_cells        eq. (2.24) evaluated plainly over the cells
  *                            (no FFT), minimum image, window |y| <= Ro.
+ *   oracle_fggc_points       the two above at a list of grid points, keeping
+ *                            only the cells within Ro of those points (for
+ *                            grids whose dense cell array does not fit).
  *
  * Readings of the paper taken here (each is pinned by a test):
  *   - Conjugation.  With <g,h> = int g conj(h) (eq. 2.14), A_jk = <psi_j,psi_k>
@@ -619,29 +622,40 @@ int oracle_pcell_bounds(int d, int64_t N, const double *P, const double *dpm, in
 }
 
 /*
- * Dense cell array A~(q_i, p_l) of eq. (2.25) (times `scale`):
- *   cells[l][i] += scale * a_j exp(i S_j/eps) c_j^(k)
- * for every packet j and neighbour k (eq. 2.23).  The strategy is the tensor
- * product over dimensions of the one-dimensional shift set
- * {(dq_off[a], dp_off[b])}, a < nq, b < np (basis index a*np + b), with
- * dq = 2 pi / Nq[k] and dp = dpm[k] per dimension.
- * slo[d] / sn[d] give the box of p-cells stored: slice l (row-major over the
- * box) holds p-cells slo + l; q index i (row-major, last dim fastest) holds
- * q = -pi + i dq.  cells is [prod sn][prod Nq] complex and is ADDED to.
+ * Where a cell (slice sl, q index qi) is stored.  Dense: every cell, at
+ * sl * nstore + qi (nstore = all q indices).  Sparse: only the q indices
+ * listed in qmap (qmap[qi] >= 0, a compact q slot), q-major at
+ * qmap[qi] * nstore + sl (nstore = slices); a contribution to any other q is
+ * not stored.  The arithmetic of each stored cell is the same in both.
  */
-int oracle_fggc_cells(int d, int64_t N, const double *Q, const double *P, const double *S,
-                      const double *a, double eps, const int64_t *Nq, const double *dpm, int nq,
-                      const int *dq_off, int np, const int *dp_off, double rcond, double scale,
-                      const int64_t *slo, const int64_t *sn, double *cells) {
+typedef struct {
+  const int64_t *qmap; /* NULL: dense */
+  int64_t nstore;
+} cellstore_t;
+
+static int64_t cell_slot(const cellstore_t *cs, int64_t sl, int64_t qi) {
+  if (!cs->qmap) return sl * cs->nstore + qi;
+  const int64_t k = cs->qmap[qi];
+  return k < 0 ? -1 : k * cs->nstore + sl;
+}
+
+/*
+ * The scatter of eq. (2.23)-(2.25) over every packet:
+ *   cell(ip + dp_K, iq + dq_K) += scale * a_j exp(i S_j/eps) c_j^(K).
+ * In the sparse form a packet none of whose neighbours is stored adds nothing,
+ * so its coefficients are not formed.
+ */
+static int fggc_scatter(int d, int64_t N, const double *Q, const double *P, const double *S,
+                        const double *a, double eps, const int64_t *Nq, const double *dpm, int nq,
+                        const int *dq_off, int np, const int *dp_off, double rcond, double scale,
+                        const int64_t *slo, const int64_t *sn, const cellstore_t *cs, double *cells) {
   if (d < 1 || d > 3 || N < 0 || !(eps > 0) || nq < 1 || np < 1 || nq * np > MAXN1) return -1;
   int n1 = nq * np;
   double Cq[3], Cp[3];
-  int64_t nqt = 1;
   for (int k = 0; k < d; ++k) {
     if (Nq[k] < 2 || Nq[k] % 2 || !(dpm[k] > 0) || sn[k] < 1) return -1;
     Cq[k] = (TWO_PI / (double)Nq[k]) / sqrt(eps);
     Cp[k] = dpm[k] / sqrt(eps);
-    nqt *= Nq[k];
   }
   /* per-dimension shift lists and precomputed solver (Alg. 2, step 0) */
   int sq[MAXN1], sp[MAXN1];
@@ -661,24 +675,44 @@ int oracle_fggc_cells(int d, int64_t N, const double *Q, const double *P, const 
       return -3;
     }
   }
-  int64_t nK = 1;
-  for (int k = 0; k < d; ++k) nK *= n1;
+  int64_t nK = 1, nqK = 1;
+  for (int k = 0; k < d; ++k) {
+    nK *= n1;
+    nqK *= nq;
+  }
   int err = 0;
 
 #pragma omp parallel for schedule(dynamic, 256)
   for (int64_t j = 0; j < N; ++j) {
     cld c1[3][MAXN1];
     int64_t iq[3], ip[3];
+    double s[3], t[3];
     for (int k = 0; k < d; ++k) {
-      double s, t;
-      int_frac(Q[k * N + j] / (TWO_PI / (double)Nq[k]), &iq[k], &s);
-      int_frac(P[k * N + j] / dpm[k], &ip[k], &t);
+      int_frac(Q[k * N + j] / (TWO_PI / (double)Nq[k]), &iq[k], &s[k]);
+      int_frac(P[k * N + j] / dpm[k], &ip[k], &t[k]);
+    }
+    if (cs->qmap) {
+      /* is any of the packet's q neighbours stored? */
+      int any = 0;
+      for (int64_t K = 0; K < nqK && !any; ++K) {
+        int64_t rem = K, qi = 0;
+        int kk[3];
+        for (int k = d - 1; k >= 0; --k) {
+          kk[k] = (int)(rem % nq);
+          rem /= nq;
+        }
+        for (int k = 0; k < d; ++k) qi = qi * Nq[k] + imod(iq[k] + dq_off[kk[k]] + Nq[k] / 2, Nq[k]);
+        any = cs->qmap[qi] >= 0;
+      }
+      if (!any) continue;
+    }
+    for (int k = 0; k < d; ++k) {
       cld f[MAXN1], ch[MAXN1];
-      for (int i = 0; i < n1; ++i) f[i] = rhs_entry(1, &sq[i], &sp[i], &s, &t, &Cq[k], &Cp[k]);
+      for (int i = 0; i < n1; ++i) f[i] = rhs_entry(1, &sq[i], &sp[i], &s[k], &t[k], &Cq[k], &Cp[k]);
       solver_apply(&sv[k], f, ch);
       for (int i = 0; i < n1; ++i) {
         /* c~ = conj(A~^+ f~), then the shift of eq. (3.13) */
-        long double ph = -(long double)Cq[k] * Cp[k] * ((long double)s - sq[i]) * (long double)ip[k];
+        long double ph = -(long double)Cq[k] * Cp[k] * ((long double)s[k] - sq[i]) * (long double)ip[k];
         c1[k][i] = conjl(ch[i]) * cexpl(I * ph);
       }
     }
@@ -706,8 +740,10 @@ int oracle_fggc_cells(int d, int64_t N, const double *Q, const double *P, const 
         err = 1;
         continue;
       }
+      const int64_t at = cell_slot(cs, sl, qi);
+      if (at < 0) continue;
       double complex v = alpha * (double complex)coef;
-      double *cell = cells + 2 * (sl * nqt + qi);
+      double *cell = cells + 2 * at;
 #pragma omp atomic
       cell[0] += creal(v);
 #pragma omp atomic
@@ -720,6 +756,191 @@ int oracle_fggc_cells(int d, int64_t N, const double *Q, const double *P, const 
 }
 
 /*
+ * Dense cell array A~(q_i, p_l) of eq. (2.25) (times `scale`):
+ *   cells[l][i] += scale * a_j exp(i S_j/eps) c_j^(k)
+ * for every packet j and neighbour k (eq. 2.23).  The strategy is the tensor
+ * product over dimensions of the one-dimensional shift set
+ * {(dq_off[a], dp_off[b])}, a < nq, b < np (basis index a*np + b), with
+ * dq = 2 pi / Nq[k] and dp = dpm[k] per dimension.
+ * slo[d] / sn[d] give the box of p-cells stored: slice l (row-major over the
+ * box) holds p-cells slo + l; q index i (row-major, last dim fastest) holds
+ * q = -pi + i dq.  cells is [prod sn][prod Nq] complex and is ADDED to.
+ */
+int oracle_fggc_cells(int d, int64_t N, const double *Q, const double *P, const double *S,
+                      const double *a, double eps, const int64_t *Nq, const double *dpm, int nq,
+                      const int *dq_off, int np, const int *dp_off, double rcond, double scale,
+                      const int64_t *slo, const int64_t *sn, double *cells) {
+  if (d < 1 || d > 3) return -1;
+  cellstore_t cs = {NULL, 1};
+  for (int k = 0; k < d; ++k) cs.nstore *= Nq[k];
+  return fggc_scatter(d, N, Q, P, S, a, eps, Nq, dpm, nq, dq_off, np, dp_off, rcond, scale, slo, sn, &cs,
+                      cells);
+}
+
+/*
+ * The q indices a grid point x sees: per dimension the indices within reach
+ * of x +- Ro (each visited once), minimum image y = wrap(x - q_i), and only
+ * those with |y| <= Ro.  Calls back with (flat q index, y) in row-major order.
+ */
+typedef void (*ball_fn)(void *ctx, int64_t qi, const double *y);
+
+static void visit_ball(int d, const double *x, const int64_t *Nq, double Ro, ball_fn fn, void *ctx) {
+  int64_t i0[3] = {0, 0, 0}, ni[3] = {1, 1, 1};
+  for (int k = 0; k < d; ++k) {
+    double dqk = TWO_PI / (double)Nq[k];
+    int64_t lo = (int64_t)floor((x[k] - Ro + M_PI) / dqk) - 1;
+    int64_t hi = (int64_t)ceil((x[k] + Ro + M_PI) / dqk) + 1;
+    if (hi - lo + 1 >= Nq[k]) {
+      i0[k] = 0;
+      ni[k] = Nq[k];
+    } else {
+      i0[k] = lo;
+      ni[k] = hi - lo + 1;
+    }
+  }
+  int64_t nbox = 1;
+  for (int k = 0; k < d; ++k) nbox *= ni[k];
+  for (int64_t bq = 0; bq < nbox; ++bq) {
+    int64_t rem = bq, qi = 0;
+    double y[3] = {0, 0, 0}, r2 = 0;
+    int64_t idx[3];
+    for (int k = d - 1; k >= 0; --k) {
+      idx[k] = imod(i0[k] + rem % ni[k], Nq[k]);
+      rem /= ni[k];
+    }
+    for (int k = 0; k < d; ++k) {
+      double qv = -M_PI + (double)idx[k] * (TWO_PI / (double)Nq[k]);
+      y[k] = wrap_pi(x[k] - qv);
+      r2 += y[k] * y[k];
+      qi = qi * Nq[k] + idx[k];
+    }
+    if (r2 > Ro * Ro) continue;
+    fn(ctx, qi, y);
+  }
+}
+
+static void grid_point(int d, const int64_t *M, int64_t flat, double *x) {
+  int64_t m[3] = {0, 0, 0};
+  unflatten(d, M, flat, m);
+  for (int k = 0; k < d; ++k) x[k] = -M_PI + (double)m[k] * (TWO_PI / (double)M[k]);
+}
+
+/* sum over the cells at one q index of A~(q, p_l) G(x; q, p_l), eq. (2.24) */
+typedef struct {
+  int d;
+  const double *cells;
+  const cellstore_t *cs;
+  const int64_t *slo, *sn;
+  const double *dpm;
+  double eps;
+  int64_t nsl;
+  double complex acc;
+  int missing;
+} evalctx_t;
+
+static void eval_at_q(void *vp, int64_t qi, const double *y) {
+  evalctx_t *e = (evalctx_t *)vp;
+  const int d = e->d;
+  if (cell_slot(e->cs, 0, qi) < 0) {
+    e->missing = 1;
+    return;
+  }
+  double r2 = 0;
+  for (int k = 0; k < d; ++k) r2 += y[k] * y[k];
+  double g = exp(-r2 / (2 * e->eps));
+  for (int64_t l = 0; l < e->nsl; ++l) {
+    const double *cell = e->cells + 2 * cell_slot(e->cs, l, qi);
+    if (cell[0] == 0.0 && cell[1] == 0.0) continue;
+    int64_t lr = l, li[3];
+    for (int k = d - 1; k >= 0; --k) {
+      li[k] = lr % e->sn[k];
+      lr /= e->sn[k];
+    }
+    double py = 0;
+    for (int k = 0; k < d; ++k) py += (double)(e->slo[k] + li[k]) * e->dpm[k] * y[k];
+    double ph = py / e->eps;
+    e->acc += (cell[0] + I * cell[1]) * g * (cos(ph) + I * sin(ph));
+  }
+}
+
+/* the q indices (and their y) a point sees, collected in visiting order */
+typedef struct {
+  int d;
+  int64_t n, cap;
+  int64_t *qi;
+  double *y;
+} balllist_t;
+
+static void collect_q(void *vp, int64_t qi, const double *y) {
+  balllist_t *b = (balllist_t *)vp;
+  if (b->n == b->cap) {
+    b->cap = b->cap ? 2 * b->cap : 4096;
+    b->qi = (int64_t *)realloc(b->qi, sizeof(int64_t) * b->cap);
+    b->y = (double *)realloc(b->y, sizeof(double) * 3 * b->cap);
+  }
+  b->qi[b->n] = qi;
+  for (int k = 0; k < 3; ++k) b->y[3 * b->n + k] = k < b->d ? y[k] : 0.0;
+  b->n += 1;
+}
+
+static int eval_cells_store(int d, const double *cells, const cellstore_t *cs, const int64_t *slo,
+                            const int64_t *sn, const int64_t *Nq, const double *dpm, double eps,
+                            const int64_t *M, double Ro, int64_t npts, const int64_t *pts, double *u) {
+  if (d < 1 || d > 3 || !(eps > 0) || !(Ro > 0) || !(Ro < M_PI)) return -1;
+  int64_t total = 1, nsl = 1;
+  for (int k = 0; k < d; ++k) {
+    if (M[k] < 1 || Nq[k] < 2 || Nq[k] % 2 || sn[k] < 1) return -1;
+    total *= M[k];
+    nsl *= sn[k];
+  }
+  if (!pts) npts = total;
+  int missing = 0;
+  if (npts >= 4 * oracle_num_threads()) {
+    /* many points: one point per iteration */
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t ipt = 0; ipt < npts; ++ipt) {
+      double x[3] = {0, 0, 0};
+      grid_point(d, M, pts ? pts[ipt] : ipt, x);
+      evalctx_t e = {d, cells, cs, slo, sn, dpm, eps, nsl, 0.0, 0};
+      visit_ball(d, x, Nq, Ro, eval_at_q, &e);
+      if (e.missing) {
+#pragma omp atomic write
+        missing = 1;
+      }
+      u[2 * ipt] = creal(e.acc);
+      u[2 * ipt + 1] = cimag(e.acc);
+    }
+    return missing ? -5 : 0;
+  }
+  /* few points: the q indices of one point are shared out instead (the same
+     terms, summed in another order) */
+  balllist_t b = {d, 0, 0, NULL, NULL};
+  for (int64_t ipt = 0; ipt < npts; ++ipt) {
+    double x[3] = {0, 0, 0};
+    grid_point(d, M, pts ? pts[ipt] : ipt, x);
+    b.n = 0;
+    visit_ball(d, x, Nq, Ro, collect_q, &b);
+    double re = 0.0, im = 0.0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : re, im)
+    for (int64_t i = 0; i < b.n; ++i) {
+      evalctx_t e = {d, cells, cs, slo, sn, dpm, eps, nsl, 0.0, 0};
+      eval_at_q(&e, b.qi[i], b.y + 3 * i);
+      if (e.missing) {
+#pragma omp atomic write
+        missing = 1;
+      }
+      re += creal(e.acc);
+      im += cimag(e.acc);
+    }
+    u[2 * ipt] = re;
+    u[2 * ipt + 1] = im;
+  }
+  free(b.qi);
+  free(b.y);
+  return missing ? -5 : 0;
+}
+
+/*
  * u_m = sum over cells of A~(q_i, p_l) G(x_m; q_i, p_l), eq. (2.24), evaluated
  * directly: minimum image y = wrap(x_m - q_i), cells with |y| <= Ro only.
  * Layout of cells as in oracle_fggc_cells; pts / npts / u as in
@@ -728,70 +949,83 @@ int oracle_fggc_cells(int d, int64_t N, const double *Q, const double *P, const 
 int oracle_eval_cells(int d, const double *cells, const int64_t *slo, const int64_t *sn,
                       const int64_t *Nq, const double *dpm, double eps, const int64_t *M, double Ro,
                       int64_t npts, const int64_t *pts, double *u) {
-  if (d < 1 || d > 3 || !(eps > 0) || !(Ro > 0) || !(Ro < M_PI)) return -1;
-  int64_t total = 1, nqt = 1, nsl = 1;
+  if (d < 1 || d > 3) return -1;
+  cellstore_t cs = {NULL, 1};
+  for (int k = 0; k < d; ++k) cs.nstore *= Nq[k];
+  return eval_cells_store(d, cells, &cs, slo, sn, Nq, dpm, eps, M, Ro, npts, pts, u);
+}
+
+/* marks q indices (qmap[qi] = 0) */
+static void mark_q(void *vp, int64_t qi, const double *y) {
+  (void)y;
+  ((int64_t *)vp)[qi] = 0;
+}
+
+typedef struct {
+  const int64_t *qmap;
+  int64_t fresh;
+} countctx_t;
+
+static void count_new_q(void *vp, int64_t qi, const double *y) {
+  (void)y;
+  countctx_t *c = (countctx_t *)vp;
+  if (c->qmap[qi] < 0) c->fresh += 1;
+}
+
+/*
+ * FGGC at the grid points pts[0..npts) without the dense cell array: the same
+ * scatter (eq. 2.23-2.25) and the same plain evaluation of eq. (2.24) as
+ * oracle_fggc_cells followed by oracle_eval_cells, but only the cells whose q
+ * lies within Ro of the points are kept.  Points are taken in batches whose
+ * kept cells fit in max_bytes (at least one point per batch); every batch
+ * scatters all packets into its own cells.  slo / sn as in oracle_fggc_cells
+ * (they must contain every p-cell the packets touch).  u receives npts complex.
+ */
+int oracle_fggc_points(int d, int64_t N, const double *Q, const double *P, const double *S,
+                       const double *a, double eps, const int64_t *Nq, const double *dpm, int nq,
+                       const int *dq_off, int np, const int *dp_off, double rcond, double scale,
+                       const int64_t *slo, const int64_t *sn, const int64_t *M, double Ro, int64_t npts,
+                       const int64_t *pts, double max_bytes, double *u) {
+  if (d < 1 || d > 3 || npts < 0 || !pts || !(Ro > 0) || !(Ro < M_PI) || !(max_bytes > 0)) return -1;
+  int64_t nqt = 1, nsl = 1;
   for (int k = 0; k < d; ++k) {
-    if (M[k] < 1 || Nq[k] < 2 || Nq[k] % 2 || sn[k] < 1) return -1;
-    total *= M[k];
+    if (Nq[k] < 2 || Nq[k] % 2 || sn[k] < 1 || M[k] < 1) return -1;
     nqt *= Nq[k];
     nsl *= sn[k];
   }
-  if (!pts) npts = total;
-#pragma omp parallel for schedule(dynamic, 4)
-  for (int64_t ipt = 0; ipt < npts; ++ipt) {
-    int64_t flat = pts ? pts[ipt] : ipt, m[3] = {0, 0, 0};
-    double x[3] = {0, 0, 0};
-    unflatten(d, M, flat, m);
-    /* q indices within reach of x, per dimension (each visited once) */
-    int64_t i0[3] = {0, 0, 0}, ni[3] = {1, 1, 1};
-    for (int k = 0; k < d; ++k) {
-      x[k] = -M_PI + (double)m[k] * (TWO_PI / (double)M[k]);
-      double dqk = TWO_PI / (double)Nq[k];
-      int64_t lo = (int64_t)floor((x[k] - Ro + M_PI) / dqk) - 1;
-      int64_t hi = (int64_t)ceil((x[k] + Ro + M_PI) / dqk) + 1;
-      if (hi - lo + 1 >= Nq[k]) {
-        i0[k] = 0;
-        ni[k] = Nq[k];
-      } else {
-        i0[k] = lo;
-        ni[k] = hi - lo + 1;
-      }
+  int64_t *qmap = (int64_t *)malloc(sizeof(int64_t) * nqt);
+  if (!qmap) return -2;
+  int rc = 0;
+  for (int64_t i0 = 0; i0 < npts && rc == 0;) {
+    for (int64_t q = 0; q < nqt; ++q) qmap[q] = -1;
+    /* grow the batch while its cells fit */
+    int64_t nq_used = 0, i1 = i0;
+    while (i1 < npts) {
+      double x[3] = {0, 0, 0};
+      grid_point(d, M, pts[i1], x);
+      countctx_t c = {qmap, 0};
+      visit_ball(d, x, Nq, Ro, count_new_q, &c);
+      if (i1 > i0 && (double)(nq_used + c.fresh) * (double)nsl * 16.0 > max_bytes) break;
+      visit_ball(d, x, Nq, Ro, mark_q, qmap);
+      nq_used += c.fresh;
+      ++i1;
     }
-    int64_t nbox = 1;
-    for (int k = 0; k < d; ++k) nbox *= ni[k];
-    double complex acc = 0.0;
-    for (int64_t bq = 0; bq < nbox; ++bq) {
-      int64_t rem = bq, qi = 0;
-      double y[3] = {0, 0, 0}, r2 = 0;
-      int64_t idx[3];
-      for (int k = d - 1; k >= 0; --k) {
-        idx[k] = imod(i0[k] + rem % ni[k], Nq[k]);
-        rem /= ni[k];
-      }
-      for (int k = 0; k < d; ++k) {
-        double qv = -M_PI + (double)idx[k] * (TWO_PI / (double)Nq[k]);
-        y[k] = wrap_pi(x[k] - qv);
-        r2 += y[k] * y[k];
-        qi = qi * Nq[k] + idx[k];
-      }
-      if (r2 > Ro * Ro) continue;
-      double g = exp(-r2 / (2 * eps));
-      for (int64_t l = 0; l < nsl; ++l) {
-        const double *cell = cells + 2 * (l * nqt + qi);
-        if (cell[0] == 0.0 && cell[1] == 0.0) continue;
-        int64_t lr = l, li[3];
-        for (int k = d - 1; k >= 0; --k) {
-          li[k] = lr % sn[k];
-          lr /= sn[k];
-        }
-        double py = 0;
-        for (int k = 0; k < d; ++k) py += (double)(slo[k] + li[k]) * dpm[k] * y[k];
-        double ph = py / eps;
-        acc += (cell[0] + I * cell[1]) * g * (cos(ph) + I * sin(ph));
-      }
+    int64_t ns = 0;
+    for (int64_t q = 0; q < nqt; ++q)
+      if (qmap[q] >= 0) qmap[q] = ns++;
+    double *cells = (double *)calloc((size_t)(ns * nsl) * 2 + 2, sizeof(double));
+    if (!cells) {
+      rc = -2;
+      break;
     }
-    u[2 * ipt] = creal(acc);
-    u[2 * ipt + 1] = cimag(acc);
+    cellstore_t cs = {qmap, nsl};
+    rc = fggc_scatter(d, N, Q, P, S, a, eps, Nq, dpm, nq, dq_off, np, dp_off, rcond, scale, slo, sn, &cs,
+                      cells);
+    if (rc == 0)
+      rc = eval_cells_store(d, cells, &cs, slo, sn, Nq, dpm, eps, M, Ro, i1 - i0, pts + i0, u + 2 * i0);
+    free(cells);
+    i0 = i1;
   }
-  return 0;
+  free(qmap);
+  return rc;
 }

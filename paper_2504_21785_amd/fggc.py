@@ -224,18 +224,99 @@ def _ptr(x) -> int:
     raise TypeError(f"unsupported buffer type {type(x)}")
 
 
+# -- argument checks (before any library call: a wrong dtype, shape or
+# device would make the kernels read or write outside the buffers) ---------
+
+def _dtype(x) -> str:
+    return str(x.dtype).replace("torch.", "")
+
+
+def _where(x):
+    """'host' for numpy arrays and CPU tensors, ('cuda', index) for device tensors."""
+    if hasattr(x, "is_cuda") and x.is_cuda:
+        return ("cuda", x.device.index)
+    if hasattr(x, "data_ptr") or isinstance(x, np.ndarray):
+        return "host"
+    raise TypeError(f"unsupported buffer type {type(x)}")
+
+
+def _need(x, name: str, dtype: str, shape=None):
+    if x is None:
+        raise ValueError(f"{name} is missing")
+    if _dtype(x) != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {_dtype(x)}")
+    if shape is not None and tuple(int(v) for v in x.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(int(v) for v in x.shape)}")
+    _ptr(x)  # contiguity
+
+
+def _same_place(*xs):
+    places = {_where(x) for x in xs if x is not None}
+    if len(places) > 1:
+        raise ValueError(f"buffers must all be on the host or all on one device, got {sorted(map(str, places))}")
+
+
+def check_packets(Q, P, S, a) -> tuple:
+    """Q, P: [d][N] float64; S: [N] float64; a: [N] complex128, all in one place; returns (d, N)."""
+    for x, n in ((Q, "Q"), (P, "P"), (S, "S"), (a, "a")):
+        if x is None:
+            raise ValueError(f"{n} is missing")
+    if len(Q.shape) != 2:
+        raise ValueError(f"Q must be [d][N], got shape {tuple(Q.shape)}")
+    d, N = int(Q.shape[0]), int(Q.shape[1])
+    if d < 1 or d > 3:
+        raise ValueError(f"d must be 1, 2 or 3, got {d}")
+    _need(Q, "Q", "float64", (d, N))
+    _need(P, "P", "float64", (d, N))
+    _need(S, "S", "float64", (N,))
+    _need(a, "a", "complex128", (N,))
+    _same_place(Q, P, S, a)
+    return d, N
+
+
+def _check_grid(d: int, M):
+    n = list(M) if hasattr(M, "__len__") else [int(M)] * d
+    if len(n) != d:
+        raise ValueError(f"grid has {len(n)} sizes for d = {d}")
+    return n
+
+
+def _check_out(out, npts: int, precision: int, what: str = "out"):
+    if out is None:
+        return
+    want = "complex128" if precision == FP64 else "complex64"
+    if _dtype(out) != want:
+        raise ValueError(f"{what} must be {want} for this precision, got {_dtype(out)}")
+    numel = int(np.prod([int(v) for v in out.shape])) if len(out.shape) else 1
+    if numel != npts:
+        raise ValueError(f"{what} must hold {npts} values, has {numel}")
+    _ptr(out)
+
+
 def _packets(Q, P, S, a) -> Packets:
+    d, N = check_packets(Q, P, S, a)
     pk = Packets()
-    d = Q.shape[0]
     pk.d = d
-    pk.N = int(S.shape[0])
+    pk.N = N
     pk.Q, pk.P, pk.S, pk.a = _ptr(Q), _ptr(P), _ptr(S), _ptr(a)
     return pk
 
 
-def _as_real_view(a):
-    """complex128 tensor/array -> same memory (interleaved re, im)."""
-    return a
+def _npts(g: Grid) -> int:
+    return int(np.prod([int(g.n[k]) for k in range(g.d)]))
+
+
+def _check_out_for(out, like, npts: int, precision: int):
+    """A caller's output: the precision's dtype, one value per point, and (for a
+    device tensor) the device of the inputs when those are on a device."""
+    if precision not in (FP32, FP64):
+        raise ValueError(f"precision must be FP32 ({FP32}) or FP64 ({FP64})")
+    if out is None:
+        return
+    _check_out(out, npts, precision)
+    wo, wi = _where(out), _where(like)
+    if wo != "host" and wi != "host" and wo != wi:
+        raise ValueError(f"out is on {wo}, the packets on {wi}")
 
 
 def _stream_ptr(stream) -> Optional[int]:
@@ -279,8 +360,9 @@ class Context:
         the current stream) or numpy arrays (host path, synchronous).  Returns
         `out` (allocated like Q when None), shape = grid.
         """
-        d = Q.shape[0]
-        g = _grid(d, M)
+        d, _ = check_packets(Q, P, S, a)
+        g = _grid(d, _check_grid(d, M))
+        _check_out_for(out, Q, _npts(g), precision)
         out = self._alloc_out(Q, g, precision, out)
         pk = _packets(Q, P, S, a)
         _check(lib().fggc_direct_sum(self.h, ctypes.byref(pk), float(eps), ctypes.byref(g),
@@ -291,8 +373,11 @@ class Context:
     def direct_sum_box(self, Q, P, S, a, eps: float, M, box_lo, box_n, window_radius: float,
                        scale: float = 1.0, precision: int = FP32, out=None, stream=None):
         """fggc_direct_sum_box: the direct sum at the points of a box of the grid."""
-        d = Q.shape[0]
-        g = _grid(d, M)
+        d, _ = check_packets(Q, P, S, a)
+        g = _grid(d, _check_grid(d, M))
+        if len(list(box_lo)) != d or len(list(box_n)) != d:
+            raise ValueError("box_lo and box_n need one entry per dimension")
+        _check_out_for(out, Q, int(np.prod([int(v) for v in box_n])), precision)
         lo = (ctypes.c_int64 * 3)(*[int(v) for v in list(box_lo) + [0] * (3 - d)])
         n = (ctypes.c_int64 * 3)(*[int(v) for v in list(box_n) + [1] * (3 - d)])
         if out is None:
@@ -307,8 +392,9 @@ class Context:
     def direct_sum_separable(self, Q, P, S, a, eps: float, M, window_half_width: float, scale: float = 1.0,
                              precision: int = FP32, out=None, stream=None):
         """fggc_direct_sum_separable: the box-window direct sum on the matrix cores (d = 2, FP32)."""
-        d = Q.shape[0]
-        g = _grid(d, M)
+        d, _ = check_packets(Q, P, S, a)
+        g = _grid(d, _check_grid(d, M))
+        _check_out_for(out, Q, _npts(g), precision)
         out = self._alloc_out(Q, g, precision, out)
         pk = _packets(Q, P, S, a)
         _check(lib().fggc_direct_sum_separable(self.h, ctypes.byref(pk), float(eps), ctypes.byref(g),
@@ -322,8 +408,21 @@ class Context:
         u0: complex128 grid values (torch on the GPU, or numpy).  Returns A
         ([N] complex128, allocated like q when out is None).
         """
+        if len(q.shape) != 2:
+            raise ValueError(f"q must be [d][N], got shape {tuple(q.shape)}")
         d, N = int(q.shape[0]), int(q.shape[1])
-        g = _grid(d, M)
+        g = _grid(d, _check_grid(d, M))
+        _need(q, "q", "float64", (d, N))
+        _need(p, "p", "float64", (d, N))
+        _need(u0, "u0", "complex128")
+        if int(np.prod([int(v) for v in u0.shape])) != _npts(g):
+            raise ValueError(f"u0 must hold {_npts(g)} grid values")
+        _same_place(u0, q, p)
+        if out is not None:
+            _need(out, "out", "complex128")
+            if int(np.prod([int(v) for v in out.shape])) != N:
+                raise ValueError(f"out must hold {N} values")
+            _same_place(q, out)
         if out is None:
             if hasattr(q, "device"):
                 import torch
@@ -344,8 +443,19 @@ class Context:
         M = list(M) if hasattr(M, "__len__") else [int(M)]
         d = len(M)
         g = _grid(d, M)
+        _need(u0, "u0", "complex128")
+        if int(np.prod([int(v) for v in u0.shape])) != _npts(g):
+            raise ValueError(f"u0 must hold {_npts(g)} grid values")
+        for v, n in ((Nq, "Nq"), (q_lo, "q_lo"), (q_n, "q_n"), (dp, "dp"), (p_lo, "p_lo"), (p_n, "p_n")):
+            if len(list(v)) != d:
+                raise ValueError(f"{n} needs one entry per dimension")
         arr = lambda v, t: (t * 3)(*[(float(x) if t is _D else int(x)) for x in (list(v) + [0] * (3 - d))])
         total = int(np.prod(list(q_n))) * int(np.prod(list(p_n)))
+        if out is not None:
+            _need(out, "out", "complex128")
+            if int(np.prod([int(v) for v in out.shape])) != total:
+                raise ValueError(f"out must hold {total} values")
+            _same_place(u0, out)
         if out is None:
             if hasattr(u0, "device"):
                 import torch
@@ -365,7 +475,12 @@ class Context:
         [N][2][d][d] complex128.  Torch tensors on the GPU run stream-ordered;
         numpy arrays are staged (synchronous).
         """
-        d, N = int(Q.shape[0]), int(Q.shape[1])
+        d, N = check_packets(Q, P, S, a)
+        if jac is not None:
+            _need(jac, "jac", "complex128")
+            if int(np.prod([int(v) for v in jac.shape])) != N * 2 * d * d:
+                raise ValueError(f"jac must hold [N][2][d][d] = {N * 2 * d * d} values")
+            _same_place(Q, jac)
         for x in (Q, P, S, a) + ((jac,) if jac is not None else ()):
             if hasattr(x, "is_contiguous") and not x.is_contiguous():
                 raise ValueError("propagate works in place: arrays must be contiguous")
@@ -379,8 +494,9 @@ class Context:
     def reconstruct(self, Q, P, S, a, eps: float, M, strategy: Strategy, scale: float = 1.0,
                     precision: int = FP32, out=None, stream=None):
         """fggc_reconstruct (FGGC); same buffer conventions as direct_sum."""
-        d = Q.shape[0]
-        g = _grid(d, M)
+        d, _ = check_packets(Q, P, S, a)
+        g = _grid(d, _check_grid(d, M))
+        _check_out_for(out, Q, _npts(g), precision)
         out = self._alloc_out(Q, g, precision, out)
         pk = _packets(Q, P, S, a)
         _check(lib().fggc_reconstruct(self.h, ctypes.byref(pk), float(eps), ctypes.byref(g),
@@ -389,7 +505,7 @@ class Context:
         return out
 
     def cell_box(self, Q, P, S, a, strategy: Strategy, stream=None):
-        d = Q.shape[0]
+        d, _ = check_packets(Q, P, S, a)
         pk = _packets(Q, P, S, a)
         lo = (ctypes.c_int64 * 3)()
         n = (ctypes.c_int64 * 3)()
@@ -400,7 +516,9 @@ class Context:
     def cells(self, Q, P, S, a, eps: float, strategy: Strategy, scale: float = 1.0,
               precision: int = FP32, box=None, stream=None):
         """fggc_cells: the dense cell array of eq. (2.25) as a numpy array [slices][q]."""
-        d = Q.shape[0]
+        d, _ = check_packets(Q, P, S, a)
+        if precision not in (FP32, FP64):
+            raise ValueError(f"precision must be FP32 ({FP32}) or FP64 ({FP64})")
         if box is None:
             box = self.cell_box(Q, P, S, a, strategy, stream)
         lo, n = box
@@ -419,6 +537,14 @@ class Context:
     def fft(self, data, dims: Sequence[int], batch: int, direction: int, precision: int = FP32,
             stream=None):
         """fggc_fft in place on a torch complex tensor on the device."""
+        if not (1 <= len(list(dims)) <= 3):
+            raise ValueError("dims must have 1 to 3 entries")
+        _need(data, "data", "complex128" if precision == FP64 else "complex64")
+        if _where(data) == "host":
+            raise ValueError("fggc_fft transforms device memory: pass a GPU tensor")
+        want = int(batch) * int(np.prod([int(v) for v in dims]))
+        if int(np.prod([int(v) for v in data.shape])) != want:
+            raise ValueError(f"data must hold batch * prod(dims) = {want} values")
         nd = (ctypes.c_int64 * 3)(*[int(v) for v in list(dims) + [1] * (3 - len(dims))])
         _check(lib().fggc_fft(self.h, len(dims), nd, int(batch), int(direction), int(precision),
                               _ptr(data), _stream_ptr(stream)))
@@ -466,8 +592,9 @@ class Server:
         """Submit packets (numpy arrays, or device tensors kept alive until wait);
         returns (ticket, output) -- output is filled when the ticket completes.
         out defaults to a numpy array for host packets and a device tensor otherwise."""
-        d = Q.shape[0]
-        g = _grid(d, M)
+        d, _ = check_packets(Q, P, S, a)
+        g = _grid(d, _check_grid(d, M))
+        _check_out_for(out, Q, _npts(g), precision)
         shape = tuple(g.n[k] for k in range(d))
         if out is None:
             if _on_device(Q):

@@ -16,6 +16,7 @@ torch = pytest.importorskip("torch")
 
 from paper_2504_21785_amd import fggc as F  # noqa: E402
 from paper_2504_21785_amd import workloads as W  # noqa: E402
+from parity import check  # noqa: E402
 
 
 def log(*a):
@@ -64,19 +65,14 @@ def test_cfg0_fp64_full_grid(ctx, orc):
     log("cfg0 fp64", ps.N, ps.M)
     u = run_direct(ctx, ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R, F.FP64)
     ref = orc.direct_sum(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R)
-    e = rel(u, ref)
-    log("cfg0 fp64 rel-L2", e, "max-abs/max", np.abs(u - ref).max() / np.abs(ref).max())
-    assert e <= 1e-12
-    assert np.abs(u - ref).max() <= 1e-12 * np.abs(ref).max()
+    check(u, ref, 1e-12, "cfg0 direct fp64")
 
 
 def test_cfg0_fp32_full_grid(ctx, orc):
     ps = W.config(0)
     u = run_direct(ctx, ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R, F.FP32)
     ref = orc.direct_sum(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R)
-    e = rel(u, ref)
-    log("cfg0 fp32 rel-L2", e)
-    assert e <= 1e-6
+    check(u, ref, 1e-6, "cfg0 direct fp32")
 
 
 @pytest.mark.parametrize("prec,tol", [(F.FP64, 1e-12), (F.FP32, 1e-6)])
@@ -94,9 +90,7 @@ def test_small_sets_with_seams(ctx, orc, prec, tol, d, M, N, eps):
     log("small", d, M, N, eps, prec)
     u = run_direct(ctx, Q, P, S, a, eps, M, R, prec, scale=0.37)
     ref = orc.direct_sum(Q, P, S, a, eps, M, R, scale=0.37)
-    e = rel(u, ref)
-    log("  rel-L2", e)
-    assert e <= tol
+    check(u, ref, tol, f"direct small d={d} M={M} N={N} prec {prec}")
 
 
 def test_empty_and_single(ctx, orc):
@@ -115,7 +109,7 @@ def test_host_buffers(ctx, orc):
     Q, P, S, a = random_set(3, 1, 300)
     out = ctx.direct_sum(Q, P, S, a, 1 / 64, (512,), 0.75, precision=F.FP64)
     ref = orc.direct_sum(Q, P, S, a, 1 / 64, (512,), 0.75)
-    assert rel(out, ref) <= 1e-12
+    check(out, ref, 1e-12, "direct host buffers")
 
 
 def test_invalid_inputs(ctx):
@@ -145,9 +139,7 @@ def test_cfg1_fp32_full_size_sampled(ctx, orc):
     u = run_direct(ctx, ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R, F.FP32)
     pts = sample_points(ps.M, 384, 1)
     ref = orc.direct_sum(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R, pts=pts)
-    e = rel(u[pts], ref)
-    log("cfg1 fp32 sampled rel-L2", e)
-    assert e <= 1e-6
+    check(u[pts], ref, 1e-6, "cfg1 direct fp32 sampled")
 
 
 def test_cfg2_fp32_full_size_sampled(ctx, orc):
@@ -157,6 +149,4 @@ def test_cfg2_fp32_full_size_sampled(ctx, orc):
     # sample where the wave lives (|q| small) and elsewhere
     pts = sample_points(ps.M, 192, 2)
     ref = orc.direct_sum(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R, pts=pts)
-    e = rel(u[pts], ref)
-    log("cfg2 fp32 sampled rel-L2", e)
-    assert e <= 1e-6
+    check(u[pts], ref, 1e-6, "cfg2 direct fp32 sampled")

@@ -22,6 +22,7 @@ torch = pytest.importorskip("torch")
 
 from paper_2504_21785_amd import fggc as F  # noqa: E402
 from paper_2504_21785_amd import workloads as W  # noqa: E402
+from parity import check  # noqa: E402
 
 Q2 = [0, 1]
 Q4 = [-1, 0, 1, 2]
@@ -62,7 +63,7 @@ def test_fft_against_numpy(ctx, prec, tol, dims, batch):
         torch.cuda.synchronize()
         got = xd.cpu().numpy().astype(np.complex128)
         ref = np.fft.fftn(x, axes=axes) if direction < 0 else np.fft.ifftn(x, axes=axes) * np.prod(dims)
-        assert rel(got, ref) <= tol, (dims, direction, rel(got, ref))
+        check(got, ref, tol, f"fft {dims} x{batch} dir {direction} prec {prec}")
 
 
 def test_fft_16384_fp32(ctx):
@@ -71,7 +72,7 @@ def test_fft_16384_fp32(ctx):
     xd = torch.from_numpy(x).to(torch.complex64).cuda()
     ctx.fft(xd, (16384,), 1, 1, F.FP32)
     torch.cuda.synchronize()
-    assert rel(xd.cpu().numpy(), np.fft.ifft(x) * 16384) <= 1e-6
+    check(xd.cpu().numpy(), np.fft.ifft(x) * 16384, 1e-6, "fft 16384 fp32")
 
 
 def small_1d(seed, N=2000, eps=1.0 / 64, M=1024):
@@ -93,9 +94,7 @@ def test_cells_match_oracle_fp64(ctx, orc, layout):
     # for Q2P2 (cond ~1e5); Q4P2 (cond ~1e11) agrees only in the function the
     # cells represent (checked by the reconstruction tests), so loosely here
     tol = 1e-10 if layout == (Q2, Q2) else 1e-4
-    e = rel(cells.reshape(-1), ref.reshape(-1))
-    log("cells rel", layout, e)
-    assert e <= tol
+    check(cells, ref, tol, f"cells {layout}")
 
 
 def fggc_case(ctx, orc, ps, name, prec, layout=None, pts=None, scale=1.0):
@@ -117,17 +116,13 @@ def fggc_case(ctx, orc, ps, name, prec, layout=None, pts=None, scale=1.0):
 def test_reconstruct_1d_small(ctx, orc, prec, name, tol):
     ps = small_1d(12, N=3000)
     u, ref = fggc_case(ctx, orc, ps, name, prec, scale=0.8)
-    e = rel(u, ref)
-    log("fggc 1d", name, prec, e)
-    assert e <= tol
+    check(u, ref, tol, f"fggc 1d {name} prec {prec}")
 
 
 def test_reconstruct_cfg0_fp64(ctx, orc):
     ps = W.config(0)
     u, ref = fggc_case(ctx, orc, ps, "Q2P2", F.FP64)
-    e = rel(u, ref)
-    log("fggc cfg0 fp64 Q2P2", e)
-    assert e <= 1e-12
+    check(u, ref, 1e-12, "fggc cfg0 fp64 Q2P2")
 
 
 def heavy_points(ps, n_heavy, n_rand, seed):
@@ -158,9 +153,7 @@ def test_reconstruct_1d_wide_shifts(ctx, orc):
     sd = st.describe()
     ref = orc.fggc(ps.Q, ps.P, ps.S, ps.a, eps, ps.M, sd["Nq"][:1], sd["dp"][:1], sd["dq_off"],
                    sd["dp_off"])
-    e = rel(u, ref)
-    log("fggc 1d wide shifts (Cq Cp = %.2f)" % (cq * cp), e)
-    assert e <= 1e-12
+    check(u, ref, 1e-12, "fggc 1d wide shifts (Cq Cp = %.2f)" % (cq * cp))
 
 
 @pytest.mark.parametrize("prec,tol", [(F.FP32, 1e-6), (F.FP64, 1e-10)])
@@ -171,9 +164,7 @@ def test_reconstruct_1d_crowded_bins(ctx, orc, prec, tol):
     ps = W.gen_1d(1024, 640, 1.0 / 64, 1024, seed=21)
     pts = heavy_points(ps, 48, 16, 2)
     u, ref = fggc_case(ctx, orc, ps, "Q4P2", prec, pts=pts)
-    e = rel(u, ref)
-    log("fggc 1d crowded bins", prec, e)
-    assert e <= tol
+    check(u, ref, tol, f"fggc 1d crowded bins prec {prec}")
 
 
 STRATEGIES = {"Q2P2": (Q2, Q2), "Q4P2": (Q4, Q2), "Q2P4": (Q2, Q4), "Q4P4": (Q4, Q4)}
@@ -222,9 +213,7 @@ def test_reconstruct_1d_strategies(ctx, orc, name, C):
     for prec, bound in ((F.FP64, tol), (F.FP32, 1e-6)):
         u = ctx.reconstruct(t(ps.Q), t(ps.P), t(ps.S), t(ps.a), eps, ps.M, st, precision=prec)
         torch.cuda.synchronize()
-        e = rel(u.cpu().numpy().reshape(-1).astype(np.complex128), ref)
-        log("fggc 1d", name, "C = %.4f" % C, "cutoff", cutoff, prec, e, "bound", bound)
-        assert e <= bound
+        check(u.cpu().numpy(), ref, bound, f"fggc 1d {name} C = {C:.4f} cutoff {cutoff} prec {prec}")
 
 
 @pytest.mark.parametrize("name", ["Q2P4", "Q4P4"])
@@ -244,9 +233,7 @@ def test_reconstruct_2d_strategies(ctx, orc, name):
     for prec, bound in ((F.FP64, 2 * tol), (F.FP32, 1e-6)):
         u = ctx.reconstruct(t(ps.Q), t(ps.P), t(ps.S), t(ps.a), ps.eps, ps.M, st, precision=prec)
         torch.cuda.synchronize()
-        e = rel(u.cpu().numpy().reshape(-1).astype(np.complex128)[pts], ref)
-        log("fggc 2d", name, "cutoff", cutoff, prec, e, "bound", bound)
-        assert e <= bound
+        check(u.cpu().numpy().reshape(-1)[pts], ref, bound, f"fggc 2d {name} cutoff {cutoff} prec {prec}")
 
 
 @pytest.mark.parametrize("prec,name,tol", [(F.FP64, "Q2P2", 1e-12), (F.FP32, "Q4P2", 1e-6)])
@@ -254,18 +241,14 @@ def test_reconstruct_2d_small(ctx, orc, prec, name, tol):
     ps = W.gen_mesh(2, 16, 6, 0.5, (0.5, 0.3), 1.0 / 256, 128, seed=5)
     pts = heavy_points(ps, 150, 50, 1)
     u, ref = fggc_case(ctx, orc, ps, name, prec, pts=pts)
-    e = rel(u, ref)
-    log("fggc 2d", name, prec, e)
-    assert e <= tol
+    check(u, ref, tol, f"fggc 2d {name} prec {prec}")
 
 
 def test_reconstruct_3d_small(ctx, orc):
     ps = W.gen_mesh(3, 8, 3, 0.5, (0.5, 0.3, 0.3), 1.0 / 64, 64, seed=9)
     pts = heavy_points(ps, 80, 20, 2)
     u, ref = fggc_case(ctx, orc, ps, "Q2P2", F.FP64, pts=pts)
-    e = rel(u, ref)
-    log("fggc 3d fp64", e)
-    assert e <= 1e-12
+    check(u, ref, 1e-12, "fggc 3d fp64")
 
 
 def test_cells_3d_match_oracle_and_sub_box(ctx, orc):
@@ -282,9 +265,7 @@ def test_cells_3d_match_oracle_and_sub_box(ctx, orc):
     ref, slo, sn = orc.fggc_cells(ps.Q, ps.P, ps.S, ps.a, ps.eps, sd["Nq"][:3], sd["dp"][:3], sd["dq_off"],
                                   sd["dp_off"], scale=0.5)
     assert list(lo) == list(slo) and list(n) == list(sn)
-    e = rel(cells.reshape(-1), ref.reshape(-1))
-    log("cells 3d rel", e)
-    assert e <= 1e-10
+    check(cells, ref, 1e-10, "cells 3d")
     assert min(n) >= 3
     with pytest.raises(F.FggcError) as ei:
         ctx.cells(*args, scale=0.5, precision=F.FP64, box=(np.asarray(lo) + 1, np.asarray(n) - 2))
@@ -304,9 +285,7 @@ def test_fggc_vs_direct_cfg1(ctx):
     uf = ctx.reconstruct(Q, P, S, a, ps.eps, ps.M, st, precision=F.FP32)
     ud = ctx.direct_sum(Q, P, S, a, ps.eps, ps.M, ps.R, precision=F.FP32)
     torch.cuda.synchronize()
-    e = rel(uf.cpu().numpy(), ud.cpu().numpy())
-    log("cfg1 fggc vs direct", e)
-    assert e < 2e-6
+    check(uf.cpu().numpy(), ud.cpu().numpy(), 2e-6, "cfg1 fggc vs direct (Q4P2 LS level)")
 
 
 def test_repeated_calls_replay_graph_with_live_data(ctx, orc):
@@ -325,15 +304,12 @@ def test_repeated_calls_replay_graph_with_live_data(ctx, orc):
         ctx.reconstruct(Q, P, S, a, ps.eps, ps.M, st, precision=F.FP32, out=u)
         torch.cuda.synchronize()
         outs.append(u.cpu().numpy().copy())
-        log(f"call {i}: vs oracle {rel(outs[-1], ref):.2e}")
-        assert rel(outs[-1], ref) <= 1e-6
+        check(outs[-1], ref, 1e-6, f"call {i} vs oracle")
     a.mul_(2.0)  # the same buffers, new values
     torch.cuda.synchronize()
     ctx.reconstruct(Q, P, S, a, ps.eps, ps.M, st, precision=F.FP32, out=u)
     torch.cuda.synchronize()
-    e = rel(u.cpu().numpy(), 2 * ref)
-    log(f"replay after in-place update: {e:.2e}")
-    assert e <= 1e-6
+    check(u.cpu().numpy(), 2 * ref, 1e-6, "replay after in-place update")
 
 
 def test_calls_on_two_streams_are_ordered(ctx, orc):
@@ -359,9 +335,8 @@ def test_calls_on_two_streams_are_ordered(ctx, orc):
     r1 = orc.fggc(ps1.Q, ps1.P, ps1.S, ps1.a, ps1.eps, ps1.M, sd["Nq"][:1], sd["dp"][:1], sd["dq_off"],
                   sd["dp_off"])
     r2 = orc.direct_sum(ps2.Q, ps2.P, ps2.S, ps2.a, ps2.eps, ps2.M, ps2.R)
-    e1, e2 = rel(u1.cpu().numpy(), r1), rel(u2.cpu().numpy(), r2)
-    log(f"two streams: fggc {e1:.2e}, direct {e2:.2e}")
-    assert e1 <= 1e-6 and e2 <= 1e-6
+    check(u1.cpu().numpy(), r1, 1e-6, "two streams: fggc")
+    check(u2.cpu().numpy(), r2, 1e-6, "two streams: direct")
 
 
 def test_repeated_3d_calls_on_radix_sort_path(ctx, orc):
@@ -380,9 +355,7 @@ def test_repeated_3d_calls_on_radix_sort_path(ctx, orc):
         log(f"3d radix-path call {i}")
         ctx.reconstruct(Q, P, S, a, ps.eps, ps.M, st, precision=F.FP32, out=u)
         torch.cuda.synchronize()
-        e = rel(u.cpu().numpy().reshape(-1)[pts].astype(np.complex128), ref)
-        log(f"  vs oracle {e:.2e}")
-        assert e <= 1e-6
+        check(u.cpu().numpy().reshape(-1)[pts], ref, 1e-6, f"3d call {i} vs oracle")
 
 
 def edge_packets(d, eps, st, seed):
@@ -432,6 +405,4 @@ def test_reconstruct_edge_cases(ctx, orc, d, M, prec, tol):
         torch.cuda.synchronize()
         u = u.cpu().numpy().reshape(-1).astype(np.complex128)
         ref = orc.fggc(q, p, s_, a_, eps, grid, sd["Nq"][:d], sd["dp"][:d], sd["dq_off"], sd["dp_off"])
-        e = rel(u, ref)
-        log(f"edge d={d} prec={prec} N={q.shape[1]}: {e:.2e}")
-        assert e <= tol
+        check(u, ref, tol, f"edge d={d} prec={prec} N={q.shape[1]}")

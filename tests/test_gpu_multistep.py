@@ -17,6 +17,7 @@ torch = pytest.importorskip("torch")
 from oracle import flow  # noqa: E402
 from paper_2504_21785_amd import fggc as F  # noqa: E402
 from paper_2504_21785_amd.multistep import MultiStep  # noqa: E402
+from parity import check  # noqa: E402
 
 
 def log(*a):
@@ -62,12 +63,11 @@ def test_multistep_matches_oracle(orc, name):
         u = u.cpu().numpy().reshape(-1)
         ref, ev = flow.multistep(orc, u0, eps, [M], qm, pm, flow.potential(**kw), 1e-3, steps, runs, [Nq], [dp],
                                  [-1, 0, 1, 2], [0, 1], 8 * math.sqrt(eps))
-        e = rel(u, ref)
-        log("multistep", name, "gpu vs oracle", e, "evolved", ms.evolved, ev)
-        assert e <= 1e-9
+        log("multistep", name, "evolved", ms.evolved, ev)
+        check(u, ref, 1e-9, f"multistep {name}: gpu vs oracle")
         assert all(abs(a - b) <= 3 for a, b in zip(ms.evolved, ev))
         if name == "harmonic":
             exact = split_step_1d(u0, 0.5 * x * x, eps, runs * steps * 1e-3, 4000)
-            assert rel(u, exact) <= 2e-7
+            check(u, exact, 2e-7, "multistep: u")
     finally:
         ctx.close()

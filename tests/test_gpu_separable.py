@@ -19,6 +19,7 @@ torch = pytest.importorskip("torch")
 
 from paper_2504_21785_amd import fggc as F  # noqa: E402
 from paper_2504_21785_amd import workloads as W  # noqa: E402
+from parity import check  # noqa: E402
 
 
 def log(*a):
@@ -73,9 +74,7 @@ def test_small_sets(ctx, orc, M, N, eps, R):
     log("separable", M, N, eps, R)
     u = run_sep(ctx, Q, P, S, a, eps, M, R, scale=0.37)
     ref = orc.direct_sum(Q, P, S, a, eps, M, R, scale=0.37, window="box")
-    e = rel(u, ref)
-    log("  rel-L2", e)
-    assert e <= 1e-6
+    check(u, ref, 1e-6, f"separable M={M} N={N} eps={eps}")
     if R > 1.0:
         # the ball of the same radius drops the corners: not what was computed
         ball = orc.direct_sum(Q, P, S, a, eps, M, R, scale=0.37)
@@ -103,7 +102,7 @@ def test_empty_host_and_errors(ctx, orc):
     Q, P, S, a = random_set(5, 300)
     out = ctx.direct_sum_separable(Q, P, S, a, 1 / 64, (64, 32), 0.75)  # host buffers
     ref = orc.direct_sum(Q, P, S, a, 1 / 64, (64, 32), 0.75, window="box")
-    assert rel(out.reshape(-1), ref) <= 1e-6
+    check(out.reshape(-1), ref, 1e-6, "separable host buffers")
     with pytest.raises(F.FggcError) as ei:
         ctx.direct_sum_separable(Q, P, S, a, 1 / 64, (64, 32), 0.75, precision=F.FP64)
     assert ei.value.code == F.FGGC_EUNSUPPORTED
@@ -119,7 +118,7 @@ def test_repeated_calls(ctx, orc):
     Q, P, S, a = random_set(9, 2000)
     ref = orc.direct_sum(Q, P, S, a, 1 / 256, (128, 96), 0.375, window="box")
     for _ in range(3):
-        assert rel(run_sep(ctx, Q, P, S, a, 1 / 256, (128, 96), 0.375), ref) <= 1e-6
+        check(run_sep(ctx, Q, P, S, a, 1 / 256, (128, 96), 0.375), ref, 1e-6, "separable repeated call")
 
 
 def test_cfg2_full_size_sampled(ctx, orc):
@@ -129,13 +128,9 @@ def test_cfg2_full_size_sampled(ctx, orc):
     rng = np.random.default_rng(3)
     pts = np.sort(rng.choice(int(np.prod(ps.M)), 192, replace=False))
     ref = orc.direct_sum(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, ps.R, pts=pts, window="box")
-    e = rel(u[pts], ref)
-    log("cfg2 separable sampled rel-L2", e)
-    assert e <= 1e-6
+    check(u[pts], ref, 1e-6, "cfg2 separable sampled")
     # against the ball-window direct sum of the same radius: the corners add
     # terms below exp(-18) of the packet peaks
     ub = ctx.direct_sum(t(ps.Q), t(ps.P), t(ps.S), t(ps.a), ps.eps, ps.M, ps.R)
     torch.cuda.synchronize()
-    eb = rel(u, ub.cpu().numpy().reshape(-1).astype(np.complex128))
-    log("cfg2 separable vs ball rel-L2", eb)
-    assert eb <= 1e-6
+    check(u, ub.cpu().numpy(), 1e-6, "cfg2 separable vs ball window")

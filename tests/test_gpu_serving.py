@@ -18,6 +18,7 @@ torch = pytest.importorskip("torch")
 
 from paper_2504_21785_amd import fggc as F  # noqa: E402
 from paper_2504_21785_amd import workloads as W  # noqa: E402
+from parity import check  # noqa: E402
 
 
 def log(*a):
@@ -87,10 +88,8 @@ def test_server_mix_equals_alone_host_inputs(ctx, reqs):
             for i, (tk, out) in enumerate(tickets):
                 rc = srv.wait(tk, 120.0)
                 assert rc == F.FGGC_OK, (i, rc, F.last_error())
-                e = rel(out, ref[i])
-                log(f"round {rnd} req {reqs[i].name} d={reqs[i].d} N={reqs[i].N} M={reqs[i].M} "
-                    f"eps={reqs[i].eps:.5f}: mix vs alone {e:.2e}")
-                assert e <= 1e-6
+                check(out, ref[i], 1e-6, f"round {rnd} req {reqs[i].name} d={reqs[i].d} N={reqs[i].N} "
+                      f"M={reqs[i].M} eps={reqs[i].eps:.5f}: mix vs alone")
         c = srv.counters()
         log("counters", c, srv.stats())
         assert c["captured"] >= 1 and c["replayed"] >= 1
@@ -117,9 +116,7 @@ def test_server_device_inputs_and_direct(ctx, reqs):
             assert rc == F.FGGC_OK, (kind, rc, F.last_error())
             torch.cuda.synchronize()
             got = out.cpu().numpy()
-            e = rel(got, alone(ctx, ps, fggc=(kind == "fggc")))
-            log(f"device {kind} {ps.name}: {e:.2e}")
-            assert e <= 1e-6
+            check(got, alone(ctx, ps, fggc=(kind == "fggc")), 1e-6, f"device {kind} {ps.name}")
     finally:
         srv.close()
 
@@ -146,9 +143,7 @@ def test_server_against_oracle(ctx, orc):
     pts = np.unique(np.ravel_multi_index((m[0], m[1]), (256, 256)))
     ref = orc.fggc(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, sd["Nq"][:2], sd["dp"][:2], sd["dq_off"],
                    sd["dp_off"], pts=pts)
-    e = rel(out.reshape(-1)[pts].astype(np.complex128), ref)
-    log("server 2D (M < Nq) vs oracle FGGC, sampled:", e)
-    assert e <= 1e-6
+    check(out.reshape(-1)[pts], ref, 1e-6, "server 2D (M < Nq) vs oracle FGGC, sampled")
 
 
 def test_server_budget_and_timeout(ctx):

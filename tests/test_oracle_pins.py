@@ -429,3 +429,32 @@ def test_fggc_error_matches_prediction_multidim(orc, d, eps, M, Nq):
         E2.append(1 - keep)
     pred = math.sqrt(np.mean(E2))
     assert 0.4 < meas / pred < 2.5
+
+
+@pytest.mark.parametrize("d,eps,M,Nq,shifts", [(2, 1.0 / 64, 96, 64, (Q4, Q2)), (3, 1.0 / 16, 24, 32, (Q2, Q2)),
+                                              (3, 1.0 / 32, 20, 48, (Q2, Q4))])
+def test_fggc_points_equals_dense_cells(orc, d, eps, M, Nq, shifts):
+    """The sampled-point form keeps only the cells within Ro of the points; it must
+    give the dense cell array's evaluation to rounding, for any batch size (a
+    tiny byte budget forces one point per batch), with packets on the periodic
+    seam, negative momenta, and points on the seam."""
+    rng = np.random.default_rng(40 + d)
+    N = 400
+    Q = rng.uniform(-math.pi, math.pi, (d, N))
+    Q[:, :20] = -math.pi  # on the seam
+    P = 0.3 + 0.03 * rng.standard_normal((d, N))
+    P[0, 20:40] *= -1.0  # negative momenta
+    S = rng.uniform(0, 2 * math.pi, N)
+    a = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    dp = math.pi * math.sqrt(eps) / 8
+    seam = np.ravel_multi_index(tuple(np.zeros((d, 3), dtype=np.int64) + np.array([0, M - 1, M // 2])),
+                                (M,) * d)
+    pts = np.unique(np.concatenate([rng.choice(M ** d, 30, replace=False), seam]))
+    args = (Q, P, S, a, eps, [M] * d, [Nq] * d, [dp] * d, shifts[0], shifts[1])
+    dense = orc.fggc(*args, pts=pts, sparse=False, scale=0.7)
+    assert np.max(np.abs(dense)) > 0
+    for budget in (4e9, 1.0):
+        sp = orc.fggc_points(*args, pts, scale=0.7, max_bytes=budget)
+        e = np.linalg.norm(sp - dense) / np.linalg.norm(dense)
+        assert e <= 1e-14, (budget, e)
+        assert np.max(np.abs(sp - dense)) <= 1e-14 * np.max(np.abs(dense))
