@@ -10,6 +10,9 @@
             --workload W --command CMD --out FILE.json
         HBM bytes per launch of each FGGC stage (FETCH_SIZE + WRITE_SIZE,
         calibrated), stamped with the digest of the kernel sources
+    python -m paper_2504_21785_amd.rocprof_summary valu SQ.db --workload W --command CMD --out FILE.json
+        mean SQ_* counter values per dispatch of the direct-sum kernel (and
+        the other kernels), stamped with the digest of the kernel sources
 
 Only reads the database; nothing here touches a GPU.
 """
@@ -119,9 +122,25 @@ def traffic(fetch_db, write_db, calib_mib, workload, command):
     return out
 
 
+def valu(db, workload, command):
+    """Mean value per dispatch of every SQ_* counter in the run, per kernel
+    family (the template arguments dropped), e.g. kernels["ds_kernel"]."""
+    c = sqlite3.connect(db)
+    names = [r[0] for r in c.execute("select distinct counter_name from counters_collection")]
+    out = {"workload": workload, "command": command, "source_sha256": source_digest(), "kernels": {}}
+    for name in names:
+        for k, v in per_dispatch(db, name).items():
+            fam = re.sub(r"<.*$", "", short(k))
+            out["kernels"].setdefault(fam, {})[name] = v
+            out["kernels"][fam].setdefault("instances", [])
+            if short(k) not in out["kernels"][fam]["instances"]:
+                out["kernels"][fam]["instances"].append(short(k))
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["kernels", "counter", "traffic"])
+    ap.add_argument("what", choices=["kernels", "counter", "traffic", "valu"])
     ap.add_argument("db")
     ap.add_argument("name", nargs="?")
     ap.add_argument("--calib-mib", type=float, default=None)
@@ -131,6 +150,13 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.what == "kernels":
         print(kernels(a.db))
+    elif a.what == "valu":
+        t = valu(a.db, a.workload, a.command)
+        text = json.dumps(t, indent=1)
+        if a.out:
+            with open(a.out, "w") as f:
+                f.write(text + "\n")
+        print(text)
     elif a.what == "traffic":
         t = traffic(a.db, a.name, a.calib_mib or 256.0, a.workload, a.command)
         text = json.dumps(t, indent=1)
