@@ -23,7 +23,6 @@
 //                 G(x; q, p_l) of eq. (2.16) with q = 0, truncated to
 //                 |k_d - p_l,d/eps| <= cK / sqrt(eps); accumulated in FP64.
 //   inverse fft   of the M^d spectrum gives eq. (2.24) on the grid.
-#include <hipcub/hipcub.hpp>
 
 #include <cmath>
 

@@ -13,15 +13,19 @@
 //   scan    a wave per bin turns its row into offsets inside the bin and a
 //           bin total; one workgroup scans the totals into start[];
 //   pos     pos[i] = start[key] + offset of (key, chunk) + rank.
+// Larger key ranges (up to 2^30) sort in two levels, every step a counting
+// pass of our own: the same three steps on the coarse key (key >> fb, at most
+// kMaxLdsBins of them) place each slot's index in a permutation array in
+// coarse order; then one workgroup per coarse bin counts the fine keys
+// (key & (2^fb - 1)) of its contiguous range in LDS, scans them, writes the
+// bin's entries of start[] and the final positions.  Nothing is cleared by a
+// memset and no count lives across calls, so the whole sort can be captured in
+// a graph and replayed.
 // The order of slots inside a key follows the LDS atomics (unspecified).
-// Larger key ranges use a hipCUB radix sort of (key, slot) pairs and scatter
-// the sorted ranks back to the slots.
 //
 // packet_scan: per packet, NaN/Inf and magnitude checks, and per dimension the
 // range of floor(P/dp); a two-level reduction (per-workgroup results, then one
 // workgroup) -- no global atomics.
-#include <hipcub/hipcub.hpp>
-
 #include <climits>
 
 #include "common.h"
@@ -32,8 +36,10 @@ namespace {
 constexpr int64_t kMaxLdsBins = 32768;
 constexpr int kSortBlock = 1024;
 
+// (the counted key is keys[i] >> shift: the whole key, or the coarse key of
+// the two-level sort)
 __global__ __launch_bounds__(kSortBlock) void bucket_rank_kernel(const uint32_t *__restrict__ keys, int64_t N,
-                                                                int64_t chunk, int64_t nbins, int G,
+                                                                int64_t chunk, int64_t nbins, int G, int shift,
                                                                 uint32_t *__restrict__ table,
                                                                 uint32_t *__restrict__ rank) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -43,7 +49,7 @@ __global__ __launch_bounds__(kSortBlock) void bucket_rank_kernel(const uint32_t 
   const int64_t lo = blockIdx.x * chunk, hi = min(N, lo + chunk);
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     const uint32_t k = keys[i];
-    if (k != kNoKey) rank[i] = atomicAdd(&cnt[k], 1u);
+    if (k != kNoKey) rank[i] = atomicAdd(&cnt[k >> shift], 1u);
   }
   __syncthreads();
   const int64_t col = chunk_column(blockIdx.x, G);
@@ -121,21 +127,79 @@ __global__ __launch_bounds__(1024) void count_binscan_kernel(const uint32_t *__r
   if (tid == 1023) start[nbins] = run;
 }
 
-// radix path: keys with kNoKey sort last (as nbins)
-__global__ void radix_prep_kernel(const uint32_t *__restrict__ keys, int64_t N, int64_t nbins,
-                                  uint32_t *__restrict__ k, uint32_t *__restrict__ v) {
+// Two-level sort, step 2: the index of every keyed slot goes to its position
+// in coarse-key order; unkeyed slots get pos = kNoKey here (the fine step
+// writes the positions of the others).
+__global__ void coarse_perm_kernel(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ rank,
+                                   int64_t N, int64_t chunk, int G, int fb, const uint32_t *__restrict__ offs,
+                                   const int64_t *__restrict__ cstart, uint32_t *__restrict__ perm,
+                                   uint32_t *__restrict__ pos) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const uint32_t x = keys[i];
-  k[i] = x == kNoKey ? (uint32_t)nbins : x;
-  v[i] = (uint32_t)i;
+  const uint32_t k = keys[i];
+  if (k == kNoKey) {
+    pos[i] = kNoKey;
+    return;
+  }
+  const uint32_t c = k >> fb;
+  const int64_t at = cstart[c] + offs[(int64_t)c * G + chunk_column(i / chunk, G)] + rank[i];
+  perm[at] = (uint32_t)i;
 }
 
-__global__ void radix_pos_kernel(const uint32_t *__restrict__ sk, const uint32_t *__restrict__ sv,
-                                 int64_t N, int64_t nbins, uint32_t *__restrict__ pos) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  pos[sv[i]] = sk[i] == (uint32_t)nbins ? kNoKey : (uint32_t)i;
+// Two-level sort, step 3: one workgroup per coarse bin c.  Its slots occupy
+// perm[cstart[c], cstart[c + 1]); the fine keys are counted in LDS (each
+// slot's returned count is its rank inside the fine key), scanned in LDS, and
+// give start[] of the bin's keys and every slot's final position.
+constexpr int kFineThreads = 256;
+__global__ __launch_bounds__(kFineThreads) void fine_sort_kernel(const uint32_t *__restrict__ keys,
+                                                                 const uint32_t *__restrict__ perm,
+                                                                 const int64_t *__restrict__ cstart, int64_t nbins,
+                                                                 int64_t ncoarse, int fb,
+                                                                 uint32_t *__restrict__ rank2,
+                                                                 int64_t *__restrict__ start,
+                                                                 uint32_t *__restrict__ pos) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  uint32_t *cnt = reinterpret_cast<uint32_t *>(smem_raw);
+  __shared__ uint32_t wsum[kFineThreads / 64];
+  const int64_t c = blockIdx.x;
+  const int64_t kb = c << fb;
+  const int nf = (int)min<int64_t>((int64_t)1 << fb, nbins - kb);  // fine keys of this bin
+  const uint32_t fmask = (1u << fb) - 1u;
+  const int64_t lo = cstart[c], hi = cstart[c + 1];
+  const int tid = threadIdx.x;
+  for (int f = tid; f < nf; f += kFineThreads) cnt[f] = 0u;
+  __syncthreads();
+  for (int64_t j = lo + tid; j < hi; j += kFineThreads) rank2[j] = atomicAdd(&cnt[keys[perm[j]] & fmask], 1u);
+  __syncthreads();
+  // exclusive scan of cnt[0, nf): contiguous runs per thread, then the waves
+  const int per = (nf + kFineThreads - 1) / kFineThreads, f0 = tid * per;
+  uint32_t sum = 0;
+  for (int q = 0; q < per; ++q)
+    if (f0 + q < nf) sum += cnt[f0 + q];
+  const int lane = tid & 63, w = tid >> 6;
+  uint32_t incl = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += u;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t run = incl - sum;
+  for (int x = 0; x < w; ++x) run += wsum[x];
+  for (int q = 0; q < per; ++q)
+    if (f0 + q < nf) {
+      const uint32_t v = cnt[f0 + q];
+      cnt[f0 + q] = run;
+      start[kb + f0 + q] = lo + run;
+      run += v;
+    }
+  if (c == ncoarse - 1 && tid == 0) start[nbins] = hi;
+  __syncthreads();
+  for (int64_t j = lo + tid; j < hi; j += kFineThreads) {
+    const uint32_t i = perm[j];
+    pos[i] = (uint32_t)(lo + cnt[keys[i] & fmask] + rank2[j]);
+  }
 }
 
 // packet pre-pass ---------------------------------------------------------
@@ -240,67 +304,52 @@ __global__ __launch_bounds__(256) void packet_scan_final_kernel(const long long 
 constexpr int kScanBlocks = 1024;
 
 struct SortPlan {
-  bool lds;
+  bool lds;        // one level: nbins <= kMaxLdsBins
+  int fb;          // two levels: fine bits (fine keys per coarse bin = 2^fb)
+  int64_t ncoarse; // keys counted by the first level (nbins, or the coarse keys)
   int G;
   int64_t chunk;
-  int bits;
-  size_t off_table, off_offs, off_rank, off_tmp, tmp_bytes, off_k1, off_k2, off_v1, off_v2, total;
+  size_t off_table, off_offs, off_rank, off_tmp, off_cstart, off_perm, off_rank2, total;
 };
 
 SortPlan sort_plan(int64_t N, int64_t nbins, int unit = 1) {
   SortPlan sp{};
   const int64_t Nn = std::max<int64_t>(N, 1);
   sp.lds = nbins <= kMaxLdsBins;
+  sp.fb = 0;
+  if (!sp.lds) {
+    while (((nbins + ((int64_t)1 << sp.fb) - 1) >> sp.fb) > kMaxLdsBins) ++sp.fb;
+    if (sp.fb > 15) fail(FGGC_EUNSUPPORTED, "more than 2^30 sort keys");
+  }
+  sp.ncoarse = (nbins + ((int64_t)1 << sp.fb) - 1) >> sp.fb;
   size_t o = 0;
   auto put = [&](size_t b) {
     size_t at = o;
     o = align_up(o + b, 256);
     return at;
   };
-  if (sp.lds) {
-    // chunks of >= 8192 slots, at most 1024 of them (the row scan's limit),
-    // and a table of at most ~2^22 entries: every (bin, chunk) count is a
-    // separate write, so fewer, larger chunks keep the table cheap
-    int64_t G = std::min<int64_t>(64 * kRowMax, (Nn + 8191) / 8192);
-    G = std::max<int64_t>(1, std::min<int64_t>(G, ((int64_t)1 << 22) / std::max<int64_t>(nbins, 1)));
-    if (G >= 8) G &= ~(int64_t)7;  // whole XCD rounds (chunk_column)
-    sp.chunk = (Nn + G - 1) / G;
-    sp.chunk = (sp.chunk + unit - 1) / unit * unit;  // whole packets per chunk
-    sp.G = (int)((Nn + sp.chunk - 1) / sp.chunk);
-    const int64_t tn = nbins * sp.G;
-    sp.off_table = put(tn * 4);
-    sp.off_offs = put(tn * 4);
-    sp.off_rank = put(Nn * 4);
-    sp.off_tmp = put(nbins * 4);  // bin totals
-  } else {
-    sp.bits = 1;
-    while (((int64_t)1 << sp.bits) < nbins + 1) ++sp.bits;
-    size_t tmp = 0;
-    uint32_t *kk = nullptr, *vv = nullptr;
-    hipcub::DoubleBuffer<uint32_t> kb(kk, kk), vb(vv, vv);
-    FGGC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, kb, vb, (int)Nn, 0, sp.bits));
-    sp.tmp_bytes = tmp;
-    sp.off_k1 = put(Nn * 4);
-    sp.off_k2 = put(Nn * 4);
-    sp.off_v1 = put(Nn * 4);
-    sp.off_v2 = put(Nn * 4);
-    sp.off_tmp = put(tmp + 256);
+  // chunks of >= 8192 slots, at most 1024 of them (the row scan's limit),
+  // and a table of at most ~2^22 entries: every (bin, chunk) count is a
+  // separate write, so fewer, larger chunks keep the table cheap
+  const int64_t nb1 = std::max<int64_t>(sp.ncoarse, 1);
+  int64_t G = std::min<int64_t>(64 * kRowMax, (Nn + 8191) / 8192);
+  G = std::max<int64_t>(1, std::min<int64_t>(G, ((int64_t)1 << 22) / nb1));
+  if (G >= 8) G &= ~(int64_t)7;  // whole XCD rounds (chunk_column)
+  sp.chunk = (Nn + G - 1) / G;
+  sp.chunk = (sp.chunk + unit - 1) / unit * unit;  // whole packets per chunk
+  sp.G = (int)((Nn + sp.chunk - 1) / sp.chunk);
+  const int64_t tn = nb1 * sp.G;
+  sp.off_table = put(tn * 4);
+  sp.off_offs = put(tn * 4);
+  sp.off_rank = put(Nn * 4);
+  sp.off_tmp = put(nb1 * 4);  // bin totals
+  if (!sp.lds) {
+    sp.off_cstart = put((nb1 + 1) * 8);
+    sp.off_perm = put(Nn * 4);
+    sp.off_rank2 = put(Nn * 4);
   }
   sp.total = o;
   return sp;
-}
-
-__global__ void radix_start_kernel(int64_t N, const uint32_t *__restrict__ skeys, int64_t nbins,
-                                   int64_t *__restrict__ start) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b > nbins) return;
-  int64_t lo = 0, hi = N;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)skeys[mid] < b) lo = mid + 1;
-    else hi = mid;
-  }
-  start[b] = lo;
 }
 
 bool g_sort_attr = false;
@@ -342,10 +391,9 @@ void count_scan(const CountPlan &c, int64_t nbins, char *scratch, int64_t *start
   FGGC_HIP(hipGetLastError());
 }
 
-// The radix path runs the library's onesweep sort, which resets its lookback
-// states and histogram with memsets and its ordered block counter from the
-// host on the stream: none of that may be replayed from a captured graph.
-bool bucket_positions_graph_safe(int64_t N, int64_t nbins) { return sort_plan(N, nbins).lds; }
+// Every path is counting passes of our own with no memset and no state kept
+// between calls, so every size can be captured in a graph and replayed.
+bool bucket_positions_graph_safe(int64_t, int64_t) { return true; }
 
 void bucket_positions(const uint32_t *keys, int64_t N, int64_t nbins, uint32_t *pos, int64_t *start,
                       void *scratch, hipStream_t s) {
@@ -358,47 +406,46 @@ void bucket_positions(const uint32_t *keys, int64_t N, int64_t nbins, uint32_t *
     if (!g_sort_attr) {
       FGGC_HIP(hipFuncSetAttribute((const void *)bucket_rank_kernel,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxLdsBins * 4)));
+      FGGC_HIP(hipFuncSetAttribute((const void *)fine_sort_kernel,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kMaxLdsBins * 4)));
       g_sort_attr = true;
     }
   }
   const unsigned gN = (unsigned)((std::max<int64_t>(N, 1) + 255) / 256);
+  // first level: the whole key, or the coarse key
+  const int64_t nb1 = sp.ncoarse;
+  uint32_t *table = (uint32_t *)(base + sp.off_table), *offs = (uint32_t *)(base + sp.off_offs),
+           *rank = (uint32_t *)(base + sp.off_rank);
+  if (N > 0) {
+    bucket_rank_kernel<<<dim3(sp.G), dim3(kSortBlock), (size_t)nb1 * 4, s>>>(keys, N, sp.chunk, nb1, sp.G,
+                                                                             sp.fb, table, rank);
+    FGGC_HIP(hipGetLastError());
+  } else {
+    launch_zero(table, (size_t)nb1 * sp.G * 4, s);
+  }
+  uint32_t *rowsum = (uint32_t *)(base + sp.off_tmp);
+  int64_t *start1 = sp.lds ? start : (int64_t *)(base + sp.off_cstart);
+  count_rowscan_kernel<<<dim3((unsigned)((nb1 * 64 + 255) / 256)), dim3(256), 0, s>>>(table, nb1, sp.G, offs,
+                                                                                     rowsum);
+  FGGC_HIP(hipGetLastError());
+  count_binscan_kernel<<<dim3(1), dim3(1024), 0, s>>>(rowsum, nb1, start1);
+  FGGC_HIP(hipGetLastError());
   if (sp.lds) {
-    uint32_t *table = (uint32_t *)(base + sp.off_table), *offs = (uint32_t *)(base + sp.off_offs),
-             *rank = (uint32_t *)(base + sp.off_rank);
-    if (N > 0) {
-      bucket_rank_kernel<<<dim3(sp.G), dim3(kSortBlock), (size_t)nbins * 4, s>>>(keys, N, sp.chunk, nbins,
-                                                                                sp.G, table, rank);
-      FGGC_HIP(hipGetLastError());
-    } else {
-      launch_zero(table, (size_t)nbins * sp.G * 4, s);
-    }
-    uint32_t *rowsum = (uint32_t *)(base + sp.off_tmp);
-    count_rowscan_kernel<<<dim3((unsigned)((nbins * 64 + 255) / 256)), dim3(256), 0, s>>>(table, nbins, sp.G,
-                                                                                        offs, rowsum);
-    FGGC_HIP(hipGetLastError());
-    count_binscan_kernel<<<dim3(1), dim3(1024), 0, s>>>(rowsum, nbins, start);
-    FGGC_HIP(hipGetLastError());
     if (N > 0) {
       bucket_pos_kernel<<<dim3(gN), dim3(256), 0, s>>>(keys, rank, N, sp.chunk, sp.G, offs, start, pos);
       FGGC_HIP(hipGetLastError());
     }
     return;
   }
-  uint32_t *k1 = (uint32_t *)(base + sp.off_k1), *k2 = (uint32_t *)(base + sp.off_k2),
-           *v1 = (uint32_t *)(base + sp.off_v1), *v2 = (uint32_t *)(base + sp.off_v2);
+  // second level: slot indices in coarse order, then the fine keys per coarse bin
+  uint32_t *perm = (uint32_t *)(base + sp.off_perm), *rank2 = (uint32_t *)(base + sp.off_rank2);
   if (N > 0) {
-    radix_prep_kernel<<<dim3(gN), dim3(256), 0, s>>>(keys, N, nbins, k1, v1);
+    coarse_perm_kernel<<<dim3(gN), dim3(256), 0, s>>>(keys, rank, N, sp.chunk, sp.G, sp.fb, offs, start1, perm,
+                                                      pos);
     FGGC_HIP(hipGetLastError());
-    hipcub::DoubleBuffer<uint32_t> kb(k1, k2), vb(v1, v2);
-    size_t tmp = sp.tmp_bytes;
-    FGGC_HIP(hipcub::DeviceRadixSort::SortPairs(base + sp.off_tmp, tmp, kb, vb, (int)N, 0, sp.bits, s));
-    radix_pos_kernel<<<dim3(gN), dim3(256), 0, s>>>(kb.Current(), vb.Current(), N, nbins, pos);
-    FGGC_HIP(hipGetLastError());
-    radix_start_kernel<<<dim3((unsigned)((nbins + 1 + 255) / 256)), dim3(256), 0, s>>>(N, kb.Current(), nbins,
-                                                                                     start);
-  } else {
-    radix_start_kernel<<<dim3((unsigned)((nbins + 1 + 255) / 256)), dim3(256), 0, s>>>(0, k1, nbins, start);
   }
+  fine_sort_kernel<<<dim3((unsigned)nb1), dim3(kFineThreads), ((size_t)4 << sp.fb), s>>>(
+      keys, perm, start1, nbins, nb1, sp.fb, rank2, start, pos);
   FGGC_HIP(hipGetLastError());
 }
 

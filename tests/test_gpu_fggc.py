@@ -339,10 +339,10 @@ def test_calls_on_two_streams_are_ordered(ctx, orc):
     check(u2.cpu().numpy(), r2, 1e-6, "two streams: direct")
 
 
-def test_repeated_3d_calls_on_radix_sort_path(ctx, orc):
-    # A 3D layout with more than 2^15 bins sorts through the library radix
-    # sort, whose stream memsets must not be replayed from a graph: repeated
-    # calls with the same buffers run eagerly each time and must agree.
+def test_repeated_3d_calls_on_two_level_sort_path(ctx, orc):
+    # A 3D layout with more than 2^15 bins sorts in two counting levels.  With
+    # the same buffers, the first call runs eagerly, the second is captured in
+    # a graph and the later ones replay it: every call must match the oracle.
     ps = W.gen_mesh(3, 8, 3, 0.5, (0.5, 0.3, 0.3), 1.0 / 64, 64, seed=9)
     st = F.default_strategy(3, ps.eps, "Q2P2")
     Q, P, S, a = t(ps.Q), t(ps.P), t(ps.S), t(ps.a)
@@ -351,8 +351,8 @@ def test_repeated_3d_calls_on_radix_sort_path(ctx, orc):
     sd = st.describe()
     ref = orc.fggc(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, sd["Nq"][:3], sd["dp"][:3], sd["dq_off"],
                    sd["dp_off"], pts=pts)
-    for i in range(3):
-        log(f"3d radix-path call {i}")
+    for i in range(4):
+        log(f"3d two-level-sort call {i}")
         ctx.reconstruct(Q, P, S, a, ps.eps, ps.M, st, precision=F.FP32, out=u)
         torch.cuda.synchronize()
         check(u.cpu().numpy().reshape(-1)[pts], ref, 1e-6, f"3d call {i} vs oracle")

@@ -226,3 +226,33 @@ def test_server_padding_keeps_cells_balanced(ctx):
         srv.close()
     log(f"N={ps.N}: server {t_srv * 1e3:.2f} ms, synchronous {t_sync * 1e3:.2f} ms")
     assert t_srv <= 4 * t_sync + 0.010
+
+
+def test_server_replays_a_two_level_sort_shape(ctx):
+    # A 2D eps = 1/1024 request has more than 2^15 sort bins, so it sorts in two
+    # counting levels; its pipeline is captured on its second sighting and
+    # replayed after, and every result equals the request run alone.
+    ps = None
+    for r in range(2000):
+        u = W.uniform(W.BASE_SEED * 1000 + r, 10, 4)
+        N = int(math.floor(2.0 ** (12 + 10 * u[1])))
+        if u[0] >= 0.5 and min(int(u[2] * 3), 2) == 2 and N <= 2 ** 16:
+            ps = W.serving_request(r)
+            break
+    assert ps is not None and ps.d == 2 and ps.eps == 1.0 / 1024
+    log(f"request {ps.name}: N={ps.N} M={ps.M}")
+    ref = alone(ctx, ps)
+    dev = tuple(t(x) for x in (ps.Q, ps.P, ps.S, ps.a))
+    st = F.default_strategy(2, ps.eps, "Q4P2")
+    srv = F.Server(ctx, n_streams=1)
+    try:
+        for i in range(4):
+            out = torch.empty(ps.M, dtype=torch.complex64, device="cuda")
+            tk, _ = srv.submit(*dev, ps.eps, ps.M, st, out=out)
+            assert srv.wait(tk, 120.0) == F.FGGC_OK, F.last_error()
+            check(out.cpu().numpy(), ref, 1e-6, f"served call {i} vs alone")
+        c = srv.counters()
+        log("graph counters", c)
+        assert c["captured"] >= 1 and c["replayed"] >= 1, c
+    finally:
+        srv.close()
