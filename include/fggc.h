@@ -145,6 +145,28 @@ int fggc_direct_sum(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fgg
                     double window_radius, double scale, int precision, void *u_out, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * windowed direct sum as fggc_direct_sum, with the same kernels and results,
+ * that allocates nothing.  Its scratch (pre-pass results, sort keys and
+ * positions, packet records, partial grids) lives in one library-owned device
+ * array of FGGC_NOALLOC_SCRATCH_BYTES per GPU, set up by fggc_create and held
+ * until the process ends; the call makes no hipMalloc, hipFree or other
+ * allocating call.
+ * Packets and u_out must be device memory of ctx's device (host pointers:
+ * FGGC_EINVAL).  A request whose scratch exceeds the limit fails with
+ * FGGC_EBUDGET before anything is launched (about 120 bytes per packet plus
+ * the partial grids: ~2e6 packets on a 16384-point 1D grid).  Every call on
+ * one GPU shares that GPU's array, so calls that overlap in time on one GPU
+ * (other host threads, other streams) race: the caller orders them.  The call
+ * synchronises `stream` once (the packet check), like fggc_direct_sum.
+ * Errors: as fggc_direct_sum, plus FGGC_EBUDGET for the scratch limit.
+ */
+#define FGGC_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int fggc_direct_sum_noalloc(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_grid *grid,
+                            double window_radius, double scale, int precision, void *u_out, void *stream);
+
+/*
  * The direct sum of fggc_direct_sum at the grid points of a box only:
  * points m with box_lo[k] <= m_k < box_lo[k] + box_n[k] (0 <= box_lo,
  * box_lo + box_n <= grid->n); u_out holds prod(box_n) values, row-major over

@@ -8,23 +8,51 @@
 
 #include "common.h"
 
+// Scratch of fggc_direct_sum_noalloc: one array per GPU (each device holds its
+// own copy, at its own address), reached only through the address that
+// hipGetSymbolAddress returns for the device (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[FGGC_NOALLOC_SCRATCH_BYTES];
+
 namespace fggc {
 
 namespace {
 thread_local std::string g_last_error;
+
+std::mutex g_noalloc_mu;
+std::vector<void *> g_noalloc_ptr;  // device address of `scratch`, per device
+
+// Once per device, with that device current: look up the array's device address.
+void noalloc_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if ((int)g_noalloc_ptr.size() <= device) g_noalloc_ptr.resize((size_t)device + 1, nullptr);
+  if (g_noalloc_ptr[(size_t)device]) return;
+  void *ptr = nullptr;
+  FGGC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) fail(FGGC_EDEVICE, "no device address for the no-allocation scratch");
+  g_noalloc_ptr[(size_t)device] = ptr;
 }
+
+char *noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (device < 0 || (size_t)device >= g_noalloc_ptr.size() || !g_noalloc_ptr[(size_t)device])
+    fail(FGGC_EDEVICE, "no-allocation scratch not set up on this device");
+  return (char *)g_noalloc_ptr[(size_t)device];
+}
+}  // namespace
 
 void set_last_error(const std::string &msg) { g_last_error = msg; }
 
 void fail(int code, const std::string &msg) { throw Error{code, msg}; }
 
 Workspace::~Workspace() {
-  if (base_) (void)hipFree(base_);
+  if (base_ && owned_) (void)hipFree(base_);
 }
 
 void Workspace::reserve(size_t bytes, size_t budget) {
   used_ = 0;
   if (bytes <= cap_) return;
+  if (!owned_) fail(FGGC_EBUDGET, "request needs " + std::to_string(bytes) + " bytes of scratch, " +
+                                      std::to_string(cap_) + " are available");
   if (bytes > budget)
     fail(FGGC_EBUDGET, "request needs " + std::to_string(bytes) + " bytes of workspace, budget is " +
                            std::to_string(budget));
@@ -50,7 +78,7 @@ void Workspace::reserve(size_t bytes, size_t budget) {
 
 void Workspace::release() {
   used_ = 0;
-  if (!base_) return;
+  if (!base_ || !owned_) return;
   if (has_stream_) FGGC_HIP(hipStreamSynchronize(stream_));
   else FGGC_HIP(hipDeviceSynchronize());
   FGGC_HIP(hipFree(base_));
@@ -438,6 +466,7 @@ int fggc_create(fggc_ctx **out, int device, size_t hbm_budget_bytes) {
     FGGC_HIP(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) fail(FGGC_EINVAL, "no such device");
     FGGC_HIP(hipSetDevice(device));
+    noalloc_setup(device);
     fggc_ctx *c = new fggc_ctx();
     c->device = device;
     size_t fr = 0, tot = 0;
@@ -558,6 +587,58 @@ int fggc_direct_sum_box(fggc_ctx *ctx, const fggc_packets *pk, double eps, const
   }
   return direct_impl("fggc_direct_sum_box", ctx, pk, eps, grid, box_lo, box_n, window_radius, scale,
                      precision, u_out, stream);
+}
+
+int fggc_direct_sum_noalloc(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_grid *grid,
+                            double window_radius, double scale, int precision, void *u_out, void *stream) {
+  return guarded("fggc_direct_sum_noalloc", [&] {
+    if (!ctx) fail(FGGC_EINVAL, "ctx is NULL");
+    GridGeom g = check_grid(grid);
+    check_packets(pk, g.d);
+    check_eps(eps);
+    if (!(window_radius > 0) || !(window_radius < kPi))
+      fail(FGGC_EINVAL, "window_radius must be in (0, pi)");
+    if (!std::isfinite(scale)) fail(FGGC_EINVAL, "scale must be finite");
+    if (precision != FGGC_FP32 && precision != FGGC_FP64) fail(FGGC_EINVAL, "bad precision");
+    if (!u_out) fail(FGGC_EINVAL, "u_out is NULL");
+    Guard lock(ctx);
+    if (packets_on_host(*pk) || !device_accessible(u_out))
+      fail(FGGC_EINVAL, "packets and u_out must be device memory (staging host buffers would allocate)");
+    hipStream_t s = (hipStream_t)stream;
+    char *scr = noalloc_scratch(ctx->device);
+    DirectArgs da{};
+    fggc_packets dpk = *pk;
+    da.pk = &dpk;
+    da.eps = eps;
+    da.R = window_radius;
+    da.scale = scale;
+    da.g = g;
+    for (int k = 0; k < 3; ++k) {
+      da.box.lo[k] = 0;
+      da.box.n[k] = g.n[k];
+    }
+    da.precision = precision;
+    da.u = u_out;
+    da.prof = nullptr;
+    // [pre-pass partials and results][the direct sum's workspace]
+    const size_t scan_b = align_up(packet_scan_bytes() + 8 * sizeof(long long), 256);
+    const size_t need = scan_b + direct_workspace_bytes(da);
+    if (need > FGGC_NOALLOC_SCRATCH_BYTES)
+      fail(FGGC_EBUDGET, "request needs " + std::to_string(need) + " bytes of scratch, the limit is " +
+                             std::to_string((size_t)FGGC_NOALLOC_SCRATCH_BYTES));
+    if (pk->N > 0) {
+      long long *part = (long long *)scr, *res = part + packet_scan_bytes() / 8;
+      launch_packet_scan(dpk, nullptr, part, res, s);
+      long long host[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      FGGC_HIP(hipMemcpyAsync(host, res, sizeof(host), hipMemcpyDeviceToHost, s));
+      FGGC_HIP(hipStreamSynchronize(s));
+      if (host[0] != 0)
+        fail(FGGC_EINVAL, std::to_string(host[0]) +
+                              " packet(s) with NaN/Inf in Q, P, S or a, or |Q| or |P| above 1e9");
+    }
+    Workspace view(scr + scan_b, FGGC_NOALLOC_SCRATCH_BYTES - scan_b);
+    launch_direct(da, view, s);
+  });
 }
 
 int fggc_direct_sum_separable(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_grid *grid,

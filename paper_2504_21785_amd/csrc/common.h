@@ -40,6 +40,11 @@ void set_last_error(const std::string &msg);
 // front, then carves.
 class Workspace {
  public:
+  Workspace() = default;
+  // a view of memory owned elsewhere (never grown or freed)
+  Workspace(void *base, size_t cap) : base_((char *)base), cap_(cap), owned_(false) {}
+  Workspace(const Workspace &) = delete;
+  Workspace &operator=(const Workspace &) = delete;
   ~Workspace();
   void reserve(size_t bytes, size_t budget);  // ensure capacity (may reallocate)
   void reset() { used_ = 0; }
@@ -57,6 +62,7 @@ class Workspace {
   size_t cap_ = 0, used_ = 0;
   hipStream_t stream_ = nullptr;
   bool has_stream_ = false;
+  bool owned_ = true;
 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }

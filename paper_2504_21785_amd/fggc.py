@@ -25,6 +25,7 @@ FGGC_EUNSUPPORTED = -4
 FGGC_EDEVICE = -5
 FGGC_ECANCELLED = -6
 FGGC_ETIMEOUT = -7
+NOALLOC_SCRATCH_BYTES = 256 << 20  # FGGC_NOALLOC_SCRATCH_BYTES
 FP32 = 0
 FP64 = 1
 
@@ -81,6 +82,8 @@ _SIGS = [
     ("fggc_last_error", ctypes.c_char_p, []),
     ("fggc_version", ctypes.c_char_p, []),
     ("fggc_direct_sum", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid), _D, _D, _I, _VP, _VP]),
+    ("fggc_direct_sum_noalloc", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid), _D, _D, _I, _VP,
+                                     _VP]),
     ("fggc_direct_sum_box", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid),
                                  ctypes.POINTER(_I64), ctypes.POINTER(_I64), _D, _D, _I, _VP, _VP]),
     ("fggc_direct_sum_separable", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Grid), _D, _D, _I,
@@ -368,6 +371,21 @@ class Context:
         _check(lib().fggc_direct_sum(self.h, ctypes.byref(pk), float(eps), ctypes.byref(g),
                                      float(window_radius), float(scale), int(precision),
                                      _ptr(out), _stream_ptr(stream) if _on_device(Q) else None))
+        return out
+
+    def direct_sum_noalloc(self, Q, P, S, a, eps: float, M, window_radius: float, out, scale: float = 1.0,
+                           precision: int = FP32, stream=None):
+        """fggc_direct_sum_noalloc: fggc_direct_sum with the library's fixed
+        per-GPU scratch and no allocation; packets and `out` are device tensors."""
+        d, _ = check_packets(Q, P, S, a)
+        g = _grid(d, _check_grid(d, M))
+        if out is None:
+            raise ValueError("direct_sum_noalloc writes into a caller-supplied `out`")
+        _check_out_for(out, Q, _npts(g), precision)
+        pk = _packets(Q, P, S, a)
+        _check(lib().fggc_direct_sum_noalloc(self.h, ctypes.byref(pk), float(eps), ctypes.byref(g),
+                                             float(window_radius), float(scale), int(precision),
+                                             _ptr(out), _stream_ptr(stream)))
         return out
 
     def direct_sum_box(self, Q, P, S, a, eps: float, M, box_lo, box_n, window_radius: float,
