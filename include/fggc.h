@@ -291,6 +291,46 @@ int fggc_propagate(fggc_ctx *ctx, int32_t d, int64_t N, double *Q, double *P, do
                    double *jac, const fggc_potential *V, double dt, int64_t nsteps, void *stream);
 
 /*
+ * Multi-step FGGC (Sec. 3.2, Alg. 3): the bookkeeping of the learned map on
+ * the device.  A fixed mesh of Nm phase-space points (q, p) is decomposed at
+ * the start of every run (fggc_decompose / fggc_decompose_mesh give A0);
+ * points with |A0| <= prune * max |A0| are skipped in that run, and of the
+ * others only those no earlier run has evolved are propagated.  The flow is
+ * linear in A, so a point learns its final (Q, P, S) and the ratio
+ * A(T) / A(0) (evolved from A(0) = 1); later runs reconstruct from those with
+ * their own A0.  All buffers are device memory on ctx's device, stream-ordered
+ * on `stream`; complex arrays are interleaved complex128.
+ *
+ * fggc_learn_select: keep_idx[0 .. *n_keep) = the points with
+ * |A0| > prune * max |A0|, and new_idx[0 .. *n_new) = those of them whose
+ * learned[i] is 0, both in mesh order; learned[i] is set to 1 for the new
+ * ones.  keep_idx and new_idx hold Nm entries each; the call synchronises
+ * `stream` once to return the two counts.  Errors: FGGC_EINVAL (Nm < 0, NULL
+ * arrays, prune not in [0, 1)).
+ */
+int fggc_learn_select(fggc_ctx *ctx, int64_t Nm, const double *A0, double prune, uint8_t *learned,
+                      int64_t *keep_idx, int64_t *new_idx, int64_t *n_keep, int64_t *n_new, void *stream);
+
+/*
+ * fggc_learn_start: the n packets at mesh points idx[0 .. n) to be evolved:
+ * Q[k][j] = qm[k][idx[j]], P[k][j] = pm[k][idx[j]], S[j] = 0, A[j] = 1
+ * (qm, pm: [d][Nm]; Q, P: [d][n]; S: [n]; A: [n] complex).
+ * fggc_learn_store: the evolved packets back into the per-point tables
+ * Qf, Pf ([d][Nm]), Sf ([Nm]) and ratio ([Nm] complex) at idx.
+ * fggc_learn_packets: the reconstruction's packets of the kept points idx:
+ * (Q, P, S) = the learned (Qf, Pf, Sf) and a[j] = A0[idx[j]] * ratio[idx[j]].
+ * Errors: FGGC_EINVAL (d outside 1..3, n < 0, n > Nm, NULL arrays with n > 0).
+ */
+int fggc_learn_start(fggc_ctx *ctx, int32_t d, int64_t Nm, int64_t n, const int64_t *idx, const double *qm,
+                     const double *pm, double *Q, double *P, double *S, double *A, void *stream);
+int fggc_learn_store(fggc_ctx *ctx, int32_t d, int64_t Nm, int64_t n, const int64_t *idx, const double *Q,
+                     const double *P, const double *S, const double *A, double *Qf, double *Pf, double *Sf,
+                     double *ratio, void *stream);
+int fggc_learn_packets(fggc_ctx *ctx, int32_t d, int64_t Nm, int64_t n, const int64_t *idx, const double *Qf,
+                       const double *Pf, const double *Sf, const double *ratio, const double *A0, double *Q,
+                       double *P, double *S, double *a, void *stream);
+
+/*
  * FGGC reconstruction (Alg. 2 steps 3-4 with eq. 2.23-2.25):
  *   per packet and dimension, int/frac split (3.6)-(3.7), right-hand side
  *   (3.23), least squares against the precomputed Gram matrix (3.22) through

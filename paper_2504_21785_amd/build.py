@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfggc.so")
 SOURCES = ["api.cpp", "plan.cpp", "direct.hip", "fggc.hip", "fft.hip", "sort.hip", "server.cpp",
-           "propagate.hip", "workloads.cpp"]
+           "propagate.hip", "workloads.cpp", "learn.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <string>
 
 #include "common.h"
@@ -763,6 +764,86 @@ int fggc_propagate(fggc_ctx *ctx, int32_t d, int64_t N, double *Q, double *P, do
     for (const Arr &x : arrs)
       if (x.bytes) FGGC_HIP(hipMemcpyAsync(x.host, x.dev, x.bytes, hipMemcpyDefault, s));
     FGGC_HIP(hipStreamSynchronize(s));
+  });
+}
+
+namespace {
+// every pointer device memory of the current device (host buffers are refused)
+void need_device(std::initializer_list<const void *> ps) {
+  for (const void *p : ps)
+    if (!device_accessible(p)) fail(FGGC_EINVAL, "buffers must be device memory");
+}
+
+void check_learn(int d, int64_t Nm, int64_t n) {
+  if (d < 1 || d > 3) fail(FGGC_EINVAL, "d must be 1, 2 or 3");
+  if (Nm < 0 || Nm > 0x7fffffffLL) fail(FGGC_EINVAL, "mesh size out of range [0, 2^31)");
+  if (n < 0 || n > Nm) fail(FGGC_EINVAL, "n must be in [0, Nm]");
+}
+}  // namespace
+
+int fggc_learn_select(fggc_ctx *ctx, int64_t Nm, const double *A0, double prune, uint8_t *learned,
+                      int64_t *keep_idx, int64_t *new_idx, int64_t *n_keep, int64_t *n_new, void *stream) {
+  return guarded("fggc_learn_select", [&] {
+    if (!ctx || !n_keep || !n_new) fail(FGGC_EINVAL, "NULL argument");
+    check_learn(1, Nm, 0);
+    if (!(prune >= 0) || !(prune < 1)) fail(FGGC_EINVAL, "prune must be in [0, 1)");
+    *n_keep = *n_new = 0;
+    if (Nm == 0) return;
+    if (!A0 || !learned || !keep_idx || !new_idx) fail(FGGC_EINVAL, "NULL array");
+    Guard lock(ctx);
+    need_device({A0, learned, keep_idx, new_idx});
+    hipStream_t s = (hipStream_t)stream;
+    // the pre-pass scratch: the max reduction's partials, then the two counts
+    double *scr = (double *)ctx->dev_scan;
+    int64_t *counts = (int64_t *)(scr + learn_scratch_bytes() / 8);
+    static_assert(sizeof(long long) == sizeof(int64_t), "count size");
+    if (learn_scratch_bytes() + 16 > packet_scan_bytes() + 256) fail(FGGC_EDEVICE, "internal: scratch too small");
+    launch_learn_select(Nm, A0, prune, learned, keep_idx, new_idx, scr, counts, s);
+    FGGC_HIP(hipMemcpyAsync(ctx->host_scan, counts, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    FGGC_HIP(hipStreamSynchronize(s));
+    *n_keep = ctx->host_scan[0];
+    *n_new = ctx->host_scan[1];
+  });
+}
+
+int fggc_learn_start(fggc_ctx *ctx, int32_t d, int64_t Nm, int64_t n, const int64_t *idx, const double *qm,
+                     const double *pm, double *Q, double *P, double *S, double *A, void *stream) {
+  return guarded("fggc_learn_start", [&] {
+    if (!ctx) fail(FGGC_EINVAL, "ctx is NULL");
+    check_learn(d, Nm, n);
+    if (n == 0) return;
+    if (!idx || !qm || !pm || !Q || !P || !S || !A) fail(FGGC_EINVAL, "NULL array");
+    Guard lock(ctx);
+    need_device({idx, qm, pm, Q, P, S, A});
+    launch_learn_start(d, Nm, n, idx, qm, pm, Q, P, S, A, (hipStream_t)stream);
+  });
+}
+
+int fggc_learn_store(fggc_ctx *ctx, int32_t d, int64_t Nm, int64_t n, const int64_t *idx, const double *Q,
+                     const double *P, const double *S, const double *A, double *Qf, double *Pf, double *Sf,
+                     double *ratio, void *stream) {
+  return guarded("fggc_learn_store", [&] {
+    if (!ctx) fail(FGGC_EINVAL, "ctx is NULL");
+    check_learn(d, Nm, n);
+    if (n == 0) return;
+    if (!idx || !Q || !P || !S || !A || !Qf || !Pf || !Sf || !ratio) fail(FGGC_EINVAL, "NULL array");
+    Guard lock(ctx);
+    need_device({idx, Q, P, S, A, Qf, Pf, Sf, ratio});
+    launch_learn_store(d, Nm, n, idx, Q, P, S, A, Qf, Pf, Sf, ratio, (hipStream_t)stream);
+  });
+}
+
+int fggc_learn_packets(fggc_ctx *ctx, int32_t d, int64_t Nm, int64_t n, const int64_t *idx, const double *Qf,
+                       const double *Pf, const double *Sf, const double *ratio, const double *A0, double *Q,
+                       double *P, double *S, double *a, void *stream) {
+  return guarded("fggc_learn_packets", [&] {
+    if (!ctx) fail(FGGC_EINVAL, "ctx is NULL");
+    check_learn(d, Nm, n);
+    if (n == 0) return;
+    if (!idx || !Qf || !Pf || !Sf || !ratio || !A0 || !Q || !P || !S || !a) fail(FGGC_EINVAL, "NULL array");
+    Guard lock(ctx);
+    need_device({idx, Qf, Pf, Sf, ratio, A0, Q, P, S, a});
+    launch_learn_packets(d, Nm, n, idx, Qf, Pf, Sf, ratio, A0, Q, P, S, a, (hipStream_t)stream);
   });
 }
 

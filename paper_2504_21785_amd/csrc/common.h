@@ -255,6 +255,19 @@ void destroy_blas(void *blas);
 void launch_propagate(int d, int64_t N, double *Q, double *P, double *S, double *a, double *jac,
                       const fggc_potential &V, double dt, int64_t nsteps, hipStream_t s);
 
+// multi-step FGGC bookkeeping (learn.hip); scratch: learn_scratch_bytes()
+size_t learn_scratch_bytes();
+void launch_learn_select(int64_t Nm, const double *A0, double prune, uint8_t *learned, int64_t *keep_idx,
+                         int64_t *new_idx, double *scratch, int64_t *counts, hipStream_t s);
+void launch_learn_start(int d, int64_t Nm, int64_t n, const int64_t *idx, const double *qm, const double *pm,
+                        double *Q, double *P, double *S, double *A, hipStream_t s);
+void launch_learn_store(int d, int64_t Nm, int64_t n, const int64_t *idx, const double *Q, const double *P,
+                        const double *S, const double *A, double *Qf, double *Pf, double *Sf, double *ratio,
+                        hipStream_t s);
+void launch_learn_packets(int d, int64_t Nm, int64_t n, const int64_t *idx, const double *Qf, const double *Pf,
+                          const double *Sf, const double *ratio, const double *A0, double *Q, double *P,
+                          double *S, double *a, hipStream_t s);
+
 struct DirectArgs {
   const fggc_packets *pk;
   double eps, R, scale;

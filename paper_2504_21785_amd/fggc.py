@@ -96,6 +96,13 @@ _SIGS = [
                                  ctypes.POINTER(_I64), _VP, _VP]),
     ("fggc_propagate", _I, [_VP, ctypes.c_int32, _I64, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(Potential), _D,
                             _I64, _VP]),
+    ("fggc_learn_select", _I, [_VP, _I64, _VP, _D, _VP, _VP, _VP, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                               _VP]),
+    ("fggc_learn_start", _I, [_VP, ctypes.c_int32, _I64, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    ("fggc_learn_store", _I, [_VP, ctypes.c_int32, _I64, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                              _VP]),
+    ("fggc_learn_packets", _I, [_VP, ctypes.c_int32, _I64, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                _VP, _VP]),
     ("fggc_default_strategy", _I, [_I, _D, ctypes.c_char_p, ctypes.POINTER(Strategy)]),
     ("fggc_config_info", _I, [_I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_I64), ctypes.POINTER(_D),
                               ctypes.POINTER(Grid), ctypes.POINTER(_D)]),
@@ -508,6 +515,40 @@ class Context:
                                     _ptr(jac) if jac is not None else None, ctypes.byref(V), float(dt),
                                     int(nsteps), _stream_ptr(stream) if _on_device(Q) else None))
         return Q, P, S, a
+
+    # -- multi-step FGGC bookkeeping (Alg. 3); device tensors only ----------
+    def learn_select(self, A0, prune: float, learned, keep_idx, new_idx, stream=None):
+        """fggc_learn_select: fills keep_idx / new_idx (int64 [Nm]) and marks the
+        new points in learned (uint8 [Nm]); returns (n_keep, n_new)."""
+        Nm = int(A0.shape[0])
+        for x, nm, dt in ((A0, "A0", "complex128"), (learned, "learned", "uint8"), (keep_idx, "keep_idx", "int64"),
+                          (new_idx, "new_idx", "int64")):
+            _need(x, nm, dt)
+            if int(np.prod([int(v) for v in x.shape])) != Nm:
+                raise ValueError(f"{nm} must hold {Nm} values")
+        nk, nn = _I64(), _I64()
+        _check(lib().fggc_learn_select(self.h, Nm, _ptr(A0), float(prune), _ptr(learned), _ptr(keep_idx),
+                                       _ptr(new_idx), ctypes.byref(nk), ctypes.byref(nn), _stream_ptr(stream)))
+        return int(nk.value), int(nn.value)
+
+    def learn_start(self, idx, n: int, qm, pm, Q, P, S, A, stream=None):
+        """fggc_learn_start: packets at mesh points idx[:n] with S = 0 and A = 1."""
+        d, Nm = int(qm.shape[0]), int(qm.shape[1])
+        _check(lib().fggc_learn_start(self.h, d, Nm, int(n), _ptr(idx), _ptr(qm), _ptr(pm), _ptr(Q), _ptr(P),
+                                      _ptr(S), _ptr(A), _stream_ptr(stream)))
+
+    def learn_store(self, idx, n: int, Q, P, S, A, Qf, Pf, Sf, ratio, stream=None):
+        """fggc_learn_store: evolved packets into the per-point tables at idx[:n]."""
+        d, Nm = int(Qf.shape[0]), int(Qf.shape[1])
+        _check(lib().fggc_learn_store(self.h, d, Nm, int(n), _ptr(idx), _ptr(Q), _ptr(P), _ptr(S), _ptr(A),
+                                      _ptr(Qf), _ptr(Pf), _ptr(Sf), _ptr(ratio), _stream_ptr(stream)))
+
+    def learn_packets(self, idx, n: int, Qf, Pf, Sf, ratio, A0, Q, P, S, a, stream=None):
+        """fggc_learn_packets: the kept points' learned packets, a = A0 * ratio."""
+        d, Nm = int(Qf.shape[0]), int(Qf.shape[1])
+        _check(lib().fggc_learn_packets(self.h, d, Nm, int(n), _ptr(idx), _ptr(Qf), _ptr(Pf), _ptr(Sf),
+                                        _ptr(ratio), _ptr(A0), _ptr(Q), _ptr(P), _ptr(S), _ptr(a),
+                                        _stream_ptr(stream)))
 
     def reconstruct(self, Q, P, S, a, eps: float, M, strategy: Strategy, scale: float = 1.0,
                     precision: int = FP32, out=None, stream=None):

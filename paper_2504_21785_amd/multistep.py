@@ -12,8 +12,10 @@ The flow is linear in A, so what a mesh point "learns" is its final
 later run reuses it with its own A(0).  Mesh points whose |A(0)| is below
 `prune` times the largest are skipped in that run.
 
-This module only sequences library calls: the masks, gathers and the
-element-wise product A(0) * ratio are torch bookkeeping on device memory.
+This module only sequences library calls: the prune mask, the index
+compaction, the gathers and the product A(0) * ratio run in the library
+(fggc_learn_select, fggc_learn_start, fggc_learn_store, fggc_learn_packets);
+torch only allocates the device buffers.
 """
 import math
 
@@ -36,11 +38,13 @@ class MultiStep:
         self.prune, self.precision, self.mesh = float(prune), precision, mesh
         Nm = self.qm.shape[1]
         dev = self.qm.device
-        self.learned = torch.zeros(Nm, dtype=torch.bool, device=dev)
+        self.learned = torch.zeros(Nm, dtype=torch.uint8, device=dev)
         self.Qf = torch.zeros_like(self.qm)
         self.Pf = torch.zeros_like(self.pm)
         self.Sf = torch.zeros(Nm, dtype=torch.float64, device=dev)
         self.ratio = torch.zeros(Nm, dtype=torch.complex128, device=dev)
+        self.keep_idx = torch.empty(Nm, dtype=torch.int64, device=dev)
+        self.new_idx = torch.empty(Nm, dtype=torch.int64, device=dev)
         dq = [2 * math.pi / strategy.Nq[k] for k in range(self.d)]
         self.scale = math.prod(dq[k] * strategy.dp[k] for k in range(self.d)) / (2 * math.pi * eps) ** (1.5 * self.d)
         self.evolved = []
@@ -54,23 +58,24 @@ class MultiStep:
                 A0 = self.ctx.decompose_mesh(u64, self.eps, self.M, self.R_dec, *self.mesh)
             else:
                 A0 = self.ctx.decompose(u64, self.eps, self.M, self.R_dec, self.qm, self.pm)
-            mag = A0.abs()
-            keep = mag > self.prune * mag.max()
-            new = torch.nonzero(keep & ~self.learned).squeeze(1)
-            if new.numel():
-                Q = self.qm[:, new].contiguous()
-                P = self.pm[:, new].contiguous()
-                S = torch.zeros(new.numel(), dtype=torch.float64, device=Q.device)
-                A = torch.ones(new.numel(), dtype=torch.complex128, device=Q.device)
-                self.ctx.propagate(Q, P, S, A, self.V, self.dt, self.steps)
-                self.Qf[:, new] = Q
-                self.Pf[:, new] = P
-                self.Sf[new] = S
-                self.ratio[new] = A
-                self.learned[new] = True
-            self.evolved.append(int(new.numel()))
-            k = torch.nonzero(keep).squeeze(1)
-            u = self.ctx.reconstruct(self.Qf[:, k].contiguous(), self.Pf[:, k].contiguous(), self.Sf[k].contiguous(),
-                                     (A0[k] * self.ratio[k]).contiguous(), self.eps, self.M, self.st,
-                                     scale=self.scale, precision=self.precision)
+            ctx = self.ctx
+            nk, nn = ctx.learn_select(A0, self.prune, self.learned, self.keep_idx, self.new_idx)
+            if nn:
+                dev = A0.device
+                Q = torch.empty((self.d, nn), dtype=torch.float64, device=dev)
+                P = torch.empty_like(Q)
+                S = torch.empty(nn, dtype=torch.float64, device=dev)
+                A = torch.empty(nn, dtype=torch.complex128, device=dev)
+                ctx.learn_start(self.new_idx, nn, self.qm, self.pm, Q, P, S, A)
+                ctx.propagate(Q, P, S, A, self.V, self.dt, self.steps)
+                ctx.learn_store(self.new_idx, nn, Q, P, S, A, self.Qf, self.Pf, self.Sf, self.ratio)
+            self.evolved.append(int(nn))
+            dev = A0.device
+            Qk = torch.empty((self.d, nk), dtype=torch.float64, device=dev)
+            Pk = torch.empty_like(Qk)
+            Sk = torch.empty(nk, dtype=torch.float64, device=dev)
+            ak = torch.empty(nk, dtype=torch.complex128, device=dev)
+            ctx.learn_packets(self.keep_idx, nk, self.Qf, self.Pf, self.Sf, self.ratio, A0, Qk, Pk, Sk, ak)
+            u = ctx.reconstruct(Qk, Pk, Sk, ak, self.eps, self.M, self.st, scale=self.scale,
+                                precision=self.precision)
         return u

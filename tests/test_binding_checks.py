@@ -108,3 +108,15 @@ def test_other_entry_points(ctx):
         ctx.fft(np.zeros(64, np.complex64), (64,), 1, -1, F.FP32)  # host memory
     with pytest.raises(ValueError):
         ctx.decompose_mesh(u0[:-1], 1 / 64, (64,), 0.5, [16], [0], [16], [0.1], [0], [4])
+
+
+@pytest.mark.parametrize("bad", ["A0", "learned", "keep_idx", "new_idx"])
+def test_learn_select_refuses_wrong_dtypes_and_sizes(ctx, bad):
+    Nm = 12
+    args = {"A0": np.zeros(Nm, np.complex128), "learned": np.zeros(Nm, np.uint8),
+            "keep_idx": np.zeros(Nm, np.int64), "new_idx": np.zeros(Nm, np.int64)}
+    wrong = {"A0": np.zeros(Nm, np.complex64), "learned": np.zeros(Nm, np.bool_),
+             "keep_idx": np.zeros(Nm, np.int32), "new_idx": np.zeros(Nm - 1, np.int64)}
+    args[bad] = wrong[bad]
+    with pytest.raises(ValueError):
+        ctx.learn_select(args["A0"], 1e-12, args["learned"], args["keep_idx"], args["new_idx"])
