@@ -105,7 +105,7 @@ def sample_points(ps, n_heavy, n_rand, seed):
     return np.unique(np.ravel_multi_index(tuple(np.concatenate([m, r], axis=1)), tuple(M)))
 
 
-def stage_work(ps, st, sn):
+def stage_work(ps, st, sn, fused=False):
     """Algorithmic work per step of each FGGC stage: (bound, amount, unit, peak,
     launches per step, kernel).  Bytes count what the stage must read and write
     once; multi-pass stages count each pass's own input and output."""
@@ -137,14 +137,31 @@ def stage_work(ps, st, sn):
         # records in, the dense cell array written once
         w["fggc_accum"] = ("hbm", (N * rec_b + cells * es) / 1e9, "GB/s", HBM_PEAK_GBS, 1,
                            "fggc_accum_wave_kernel")
-        # one pass per dimension, last first: each reads its input once and
-        # writes its (smaller) output once
-        tot = 0
-        for k in range(d - 1, -1, -1):
+
+        def pass_bytes(k):
+            # the separable pass over dimension k reads its input once and
+            # writes its (smaller) output once
             O, A, B = int(np.prod(sn[:k])), int(np.prod(Nq[:k])), int(np.prod(M[k + 1:]))
-            tot += O * sn[k] * A * Nq[k] * B + O * A * M[k] * B
-        w["fggc_contract"] = ("hbm", tot * es / 1e9, "GB/s", HBM_PEAK_GBS, d, "fft_contract_kernel")
+            return (O * sn[k] * A * Nq[k] * B + O * A * M[k] * B) * es
+
+        if fused:
+            # 3D: the accumulation fused with the pass over the last dimension:
+            # every packet's record read once (one per packet; halo copies and
+            # re-reads are overhead), the pass's output written once
+            O, A = int(np.prod(sn[:2])), int(np.prod(Nq[:2]))
+            w["fggc_fused"] = ("hbm", (N * rec_b + O * A * M[2] * es) / 1e9, "GB/s", HBM_PEAK_GBS, 1,
+                               "fggc_fused3_kernel")
+            w["fggc_contract"] = ("hbm", sum(pass_bytes(k) for k in range(d - 2, -1, -1)) / 1e9, "GB/s",
+                                  HBM_PEAK_GBS, d - 1, "fft_contract_kernel")
+        else:
+            w["fggc_contract"] = ("hbm", sum(pass_bytes(k) for k in range(d - 1, -1, -1)) / 1e9, "GB/s",
+                                  HBM_PEAK_GBS, d, "fft_contract_kernel")
     method_bytes = N * ((2 * d + 1) * 8 + 16) + 2 * cells * es + 3 * mpts * es
+    if fused:
+        # no cell array: packets in, the records written and read once, the
+        # first pass's output written and read once, spectrum and u
+        O, A = int(np.prod(sn[:2])), int(np.prod(Nq[:2]))
+        method_bytes = N * ((2 * d + 1) * 8 + 16) + 2 * N * rec_b + 2 * O * A * M[2] * es + 3 * mpts * es
     return w, method_bytes
 
 
@@ -350,7 +367,7 @@ def main():
     # ---- pass B: per-stage HIP events ---------------------------------------
     fstages = profile_stages(ctx, torch, R["step_fggc"], args.steps,
                              ["prepass", "fggc_sort", "fggc_coef", "fggc_accum", "fggc_fft_q",
-                              "fggc_band_mac", "fggc_contract", "fggc_ifft"])
+                              "fggc_band_mac", "fggc_fused", "fggc_contract", "fggc_ifft"])
     dstages = profile_stages(ctx, torch, R["step_direct"], direct_steps,
                              ["prepass", "ds_prep", "ds_sort", "ds_kernel", "ds_reduce"])
     log("stages:", json.dumps(fstages), json.dumps(dstages))
@@ -368,7 +385,7 @@ def main():
     # ---- roofline of the dominant FGGC stage ---------------------------------
     lo, n = ctx.cell_box(Q, P, S, a, st)
     slices = int(np.prod(n))
-    work, method_bytes = stage_work(ps, st, n)
+    work, method_bytes = stage_work(ps, st, n, fused="fggc_fused" in fstages)
     cand = {s2: v for s2, v in fstages.items() if s2 in work and work[s2][4]}
     dom = max(cand, key=lambda s2: cand[s2]["ms_per_step"])
     bound, amount, unit, peak, launches, kname = work[dom]
@@ -383,8 +400,12 @@ def main():
     end_to_end = {"algorithmic_bytes": method_bytes,
                   "achieved_GBs": method_bytes / 1e9 / (fggc_ms * 1e-3),
                   "frac": method_bytes / 1e9 / (fggc_ms * 1e-3) / HBM_PEAK_GBS,
-                  "note": "packets in, the dense cell array written and read once, grid spectrum written and "
-                          "read, u written; over the whole FGGC step"}
+                  "note": ("packets in, the records written and read once, the first separable pass's output "
+                           "written and read once (no cell array: the accumulation is fused with that pass), grid "
+                           "spectrum written and read, u written; over the whole FGGC step")
+                  if "fggc_fused" in fstages else
+                  ("packets in, the dense cell array written and read once, grid spectrum written and "
+                   "read, u written; over the whole FGGC step")}
     stage_rates = {}
     for s2, v in fstages.items():
         if s2 in work:

@@ -333,6 +333,10 @@ struct KeyParams {
   double dq[3], dp[3];
   int mindq, maxdq;
   int ns;  // key slots per packet: 2^d with halo slots, 1 for the own tile only
+  // bin order: 0 = (p-cell, q-tile); 1 = (p-cells of the leading dimensions,
+  // q-tile, p-cell of the last dimension), so that the bins of a run of
+  // last-dimension p-cells are adjacent (the fused three-dimensional finish)
+  int pc_last;
 };
 
 // The key slots of packet j (kNoKey for unused halo slots).  The rank kernel,
@@ -368,6 +372,8 @@ __device__ __forceinline__ void packet_keys(const KeyParams &p, int64_t j, uint3
     return;
   }
   constexpr int NS = 1 << D;
+  const int64_t pch = p.pc_last ? pcf / p.npc[D - 1] : pcf, pcl = p.pc_last ? pcf % p.npc[D - 1] : 0,
+                nl = p.pc_last ? p.npc[D - 1] : 1;
 #pragma unroll
   for (int m = 0; m < NS; ++m) {
     bool ok = true;
@@ -377,7 +383,7 @@ __device__ __forceinline__ void packet_keys(const KeyParams &p, int64_t j, uint3
       if (bit && tb[k] == ta[k]) ok = false;
       tf = tf * p.ntq[k] + (bit ? tb[k] : ta[k]);
     }
-    key[m] = ok ? (uint32_t)(pcf * nqt + tf) : kNoKey;
+    key[m] = ok ? (uint32_t)((pch * nqt + tf) * nl + pcl) : kNoKey;
   }
 }
 
@@ -1566,6 +1572,180 @@ __global__ __launch_bounds__(kContractThreads) void fft_contract_kernel(Contract
   }
 }
 
+// Three dimensions: the accumulation of eq. (2.25) fused with the separable
+// pass over the last dimension, so that the dense cell array never exists.
+// One workgroup owns the q-lines (q0, q1) of one q-tile of dimensions 0 and 1
+// at one slice pair (l0, l1), over every q2 and every slice l2.  For Lc slices
+// l2 at a time it
+//   - adds the Kronecker contributions of the packets that reach its lines
+//     into those lines in LDS (LDS float atomics; the order of the terms in a
+//     cell is unspecified, so sums may differ at the rounding level),
+//   - transforms the lines over q2 in LDS,
+//   - folds the slices into the grid frequencies m2 with the band weights
+//     gamma_l2 (a table per chunk, FP64 sums per thread),
+// and finally writes what the pass over the last dimension writes,
+// Y[l0][l1][q0][q1][m2] (zeros at frequencies no band reaches).  Packets are
+// binned by (p-cell 0, p-cell 1, q-tile, p-cell 2), so the records that reach
+// a chunk are one contiguous run per (p-cell 0, p-cell 1).
+constexpr int kFusedThreads = 512;
+constexpr int kFusedOut = 8;  // outputs per thread
+
+struct Fused3Params {
+  const char *recs;
+  const int64_t *start;
+  int64_t sn[3], npc[3], Nq[3];
+  int64_t ntq0, ntq1;  // q-tiles of dimensions 0 and 1 (a tile is T0 x T1 x Nq2)
+  int T0, T1, lgN, Lc, TPL;
+  int dq[8], dp[8];
+  int mindp, maxdp;
+  int64_t M, kmin, kmax, slo;  // last dimension: grid points, band union, first slice
+  double eps, dp2, cK;
+};
+
+template <int NQ, int NP, typename T>
+__global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params p, T *__restrict__ Y,
+                                                                     const T *__restrict__ tw) {
+  using RR = decltype(T{}.x);
+  constexpr int N1 = NQ * NP;
+  constexpr int RB = rec_bytes<3, N1, T>();
+  constexpr int NV = RB / 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lgN = p.lgN, N = 1 << lgN, T0 = p.T0, T1 = p.T1, P = T0 * T1;
+  const int M = (int)p.M;
+  const int ng = (int)(p.kmax - p.kmin + 1);
+  const int nact = min(M, ng);
+  const int bs = (int)blockDim.x, tid = (int)threadIdx.x;
+  T *cl = reinterpret_cast<T *>(smem_raw);            // [Lc][P][N] the chunk's lines
+  T *stw = cl + (size_t)p.Lc * P * N;                 // [N] twiddles
+  double *gam = reinterpret_cast<double *>(stw + N);  // [Lc][ng] band weights
+  for (int i = tid; i < N; i += bs) stw[i] = tw[i];
+  // workgroup -> (q-tile, l0, l1); workgroups run on the eight XCDs in turn,
+  // and each XCD takes a contiguous range of the work, so that the slice pairs
+  // of one tile (which read the same bins) share that XCD's L2
+  const int64_t nblk = gridDim.x, bid = blockIdx.x;
+  const int64_t per = nblk >> 3, rem = nblk & 7, xcd = bid & 7, i8 = bid >> 3;
+  const int64_t g = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + i8;
+  const int64_t l1 = g % p.sn[1], l0 = (g / p.sn[1]) % p.sn[0], tq = g / (p.sn[1] * p.sn[0]);
+  const int q00 = (int)((tq / p.ntq1) * T0), q10 = (int)((tq % p.ntq1) * T1);
+  const int span = p.maxdp - p.mindp;
+  const int64_t a0lo = max<int64_t>(0, l0 - span), a0hi = min<int64_t>(p.npc[0] - 1, l0);
+  const int64_t a1lo = max<int64_t>(0, l1 - span), a1hi = min<int64_t>(p.npc[1] - 1, l1);
+  const int64_t nqt = p.ntq0 * p.ntq1, npc2 = p.npc[2];
+  const int msk0 = (int)p.Nq[0] - 1, msk1 = (int)p.Nq[1] - 1, msk2 = N - 1;
+  const int kmod = (int)(((p.kmin % M) + M) % M);
+  // fold and output mapping: TPL threads per line group (a power of two >=
+  // the active frequencies), G = blockDim / TPL groups
+  const int TPL = p.TPL, G = bs / TPL, t = tid & (TPL - 1), lg0 = tid / TPL;
+  double accr[kFusedOut], acci[kFusedOut];
+#pragma unroll
+  for (int c = 0; c < kFusedOut; ++c) accr[c] = acci[c] = 0.0;
+  const double cst = sqrt(kTwoPi * p.eps) / kTwoPi, cut = -0.5 * p.cK * p.cK * (1.0 + 1e-12);
+  const double inv2e = 1.0 / (2.0 * p.eps);
+  for (int c0 = 0; c0 < (int)p.sn[2]; c0 += p.Lc) {
+    const int lcn = min(p.Lc, (int)p.sn[2] - c0);
+    for (int e = tid; e < lcn * P * N; e += bs) cl[e] = T{0, 0};
+    for (int e = tid; e < lcn * ng; e += bs) {
+      const int l = e / ng, t = e - l * ng;
+      const double dk = p.eps * (double)(p.kmin + t) - (double)(p.slo + c0 + l) * p.dp2;  // eps (k - p_l / eps)
+      const double ex = -dk * dk * inv2e;
+      gam[e] = ex < cut ? 0.0 : cst * exp(ex);
+    }
+    __syncthreads();
+    // packets of p-cells (a0, a1, a2), a2 in [c0 - span, c0 + lcn - 1]
+    const int64_t a2lo = max<int64_t>(0, c0 - span), a2hi = min<int64_t>(npc2 - 1, c0 + lcn - 1);
+    for (int64_t a0 = a0lo; a0 <= a0hi && a2lo <= a2hi; ++a0)
+      for (int64_t a1 = a1lo; a1 <= a1hi; ++a1) {
+        const int64_t kb = ((a0 * p.npc[1] + a1) * nqt + tq) * npc2;
+        const int64_t r0 = p.start[kb + a2lo], r1 = p.start[kb + a2hi + 1];
+        for (int64_t r = r0 + tid; r < r1; r += bs) {
+          uint4 raw[NV];
+          const uint4 *src = reinterpret_cast<const uint4 *>(p.recs + r * (int64_t)RB);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) raw[v] = src[v];
+          const RecIdx<3> ri = *reinterpret_cast<const RecIdx<3> *>(raw);
+          const T *c = reinterpret_cast<const T *>(reinterpret_cast<const char *>(raw) + rec_idx_bytes<3>());
+          int b0 = -1, b1 = -1;
+#pragma unroll
+          for (int b = 0; b < NP; ++b) {
+            if ((int64_t)ri.pc[0] + p.dp[b] - p.mindp == l0) b0 = b;
+            if ((int64_t)ri.pc[1] + p.dp[b] - p.mindp == l1) b1 = b;
+          }
+          if (b0 < 0 || b1 < 0) continue;
+          int la0[NQ], la1[NQ], q2[NQ];
+#pragma unroll
+          for (int a = 0; a < NQ; ++a) {
+            const int v0 = ((ri.q[0] + p.dq[a]) & msk0) - q00, v1 = ((ri.q[1] + p.dq[a]) & msk1) - q10;
+            la0[a] = v0 >= 0 && v0 < T0 ? v0 : -1;
+            la1[a] = v1 >= 0 && v1 < T1 ? v1 : -1;
+            q2[a] = (ri.q[2] + p.dq[a]) & msk2;
+          }
+#pragma unroll
+          for (int b2 = 0; b2 < NP; ++b2) {
+            const int l2 = ri.pc[2] + p.dp[b2] - p.mindp - c0;
+            if (l2 < 0 || l2 >= lcn) continue;
+#pragma unroll
+            for (int a0i = 0; a0i < NQ; ++a0i) {
+              if (la0[a0i] < 0) continue;
+              // b0 and b1 are not compile-time: read the coefficient through a select
+              T u{0, 0}, w{0, 0};
+#pragma unroll
+              for (int b = 0; b < NP; ++b)
+                if (b == b0) u = c[a0i * NP + b];
+#pragma unroll
+              for (int a1i = 0; a1i < NQ; ++a1i) {
+                if (la1[a1i] < 0) continue;
+#pragma unroll
+                for (int b = 0; b < NP; ++b)
+                  if (b == b1) w = c[N1 + a1i * NP + b];
+                const T uw = T{u.x * w.x - u.y * w.y, u.x * w.y + u.y * w.x};
+                T *line = cl + ((size_t)l2 * P + la0[a0i] * T1 + la1[a1i]) * N;
+#pragma unroll
+                for (int a2i = 0; a2i < NQ; ++a2i) {
+                  const T z = c[2 * N1 + a2i * NP + b2];
+                  atomicAdd(&line[q2[a2i]].x, uw.x * z.x - uw.y * z.y);
+                  atomicAdd(&line[q2[a2i]].y, uw.x * z.y + uw.y * z.x);
+                }
+              }
+            }
+          }
+        }
+      }
+    __syncthreads();
+    lds_fft_rows<T, kContractBfly>(cl, lgN, lcn * P, N, 0, stw);
+    // thread (g, t): frequency t of lines g, g + G, g + 2 G, ... -- one band
+    // weight per (slice, alias) serves all of them
+    if (t < nact) {
+      for (int64_t kk = p.kmin + t; kk <= p.kmax; kk += M) {
+        const T *fq = cl + (size_t)lg0 * N + (int)(kk & msk2);
+        const double *gb = gam + (kk - p.kmin);
+        for (int l = 0; l < lcn; ++l) {
+          const double gv = gb[l * ng];
+#pragma unroll
+          for (int c = 0; c < kFusedOut; ++c) {
+            if (lg0 + c * G >= P) break;
+            const T v = fq[((size_t)l * P + c * G) * N];
+            accr[c] = fma(gv, (double)v.x, accr[c]);
+            acci[c] = fma(gv, (double)v.y, acci[c]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t base = (l0 * p.sn[1] + l1) * p.Nq[0];
+  // every frequency of this thread's lines: the band's sums, zeros elsewhere
+  for (int tt = t; tt < M; tt += TPL) {
+    const int kp = (kmod + tt) % M;
+#pragma unroll
+    for (int c = 0; c < kFusedOut; ++c) {
+      const int line = lg0 + c * G;
+      if (line >= P) break;
+      const int64_t q0 = q00 + line / T1, q1 = q10 + line % T1;
+      Y[((base + q0) * p.Nq[1] + q1) * p.M + kp] = tt < nact ? T{(RR)accr[c], (RR)acci[c]} : T{0, 0};
+    }
+  }
+}
+
 // One dimension: the aggregate's stencil writes each slice's q-spectrum
 // directly (fggc_stencil_fft1_kernel, one slice per workgroup in LDS).
 bool fft1_fused(const FggcArgs &a) { return a.g.d == 1 && a.Nq[0] <= 4096; }
@@ -1573,6 +1753,12 @@ bool fft1_fused(const FggcArgs &a) { return a.g.d == 1 && a.Nq[0] <= 4096; }
 struct FggcLayout {
   int d, N1, rec_b, ns;
   bool agg1;  // one dimension: aggregate + stencil instead of tile accumulation
+  // three dimensions: accumulation fused with the pass over the last
+  // dimension (no dense cell array); lines T0 x T1 per workgroup, Lc slices
+  // of the last dimension per LDS chunk, the kernel's LDS bytes
+  bool fused3;
+  int fT0, fT1, fLc, fnq, fnp, fTPL;
+  size_t fshm;
   int agg_splits;  // one dimension: workgroups (and copies of the aggregate) per bin
   int64_t ncells, nslices, npts, nbins, nslots, tiles, ntq[3], tile[3], npc[3], pmin[3], S[3], nsw[3];
   int64_t nb[3];
@@ -1583,7 +1769,70 @@ struct FggcLayout {
 
 int n1_bucket(int n1) { return n1 <= 4 ? 4 : (n1 <= 8 ? 8 : 16); }
 
-FggcLayout fggc_layout(const FggcArgs &a) {
+// Grid frequencies of dimension k that some slice's truncated band reaches
+// (before aliasing): |k - p_l / eps| <= cK / sqrt(eps), padded by one.
+void band_range(const FggcArgs &a, int k, int64_t &kmin, int64_t &kmax) {
+  const double se = std::sqrt(a.eps);
+  kmin = (int64_t)std::floor((double)a.slo[k] * a.dp[k] / a.eps - a.cK / se) - 1;
+  kmax = (int64_t)std::ceil((double)(a.slo[k] + a.sn[k] - 1) * a.dp[k] / a.eps + a.cK / se) + 1;
+}
+
+// The fused three-dimensional finish, when the strategy and sizes allow it:
+// a tensor shift set of 2 x 2, 4 x 2 or 2 x 4, power-of-two q-meshes of at
+// least 4 (dims 0, 1) and 8 to 2048 (dim 2) points, a workgroup's outputs and
+// its LDS chunk within their budgets.
+bool plan_fused3(const FggcArgs &a, FggcLayout &L, int nq, int np) {
+  if (a.g.d != 3) return false;
+  if (!((nq == 2 && np == 2) || (nq == 4 && np == 2) || (nq == 2 && np == 4))) return false;
+  if (L.N1 != nq * np) return false;
+  const int64_t N = a.Nq[2];
+  if (N < 8 || N > 2048 || (N & (N - 1)) || a.Nq[0] < 4 || a.Nq[1] < 4) return false;
+  const int qspan = L.maxdq - L.mindq + 1;
+  int64_t kmin, kmax;
+  band_range(a, 2, kmin, kmax);
+  const int64_t ng = kmax - kmin + 1, nact = std::min<int64_t>(a.g.n[2], ng);
+  // fold: TPL threads per group of lines, one frequency each (TPL a power of
+  // two >= the active frequencies), kFusedThreads / TPL groups
+  int64_t TPL = 1;
+  while (TPL < nact) TPL *= 2;
+  if (TPL > kFusedThreads) return false;
+  // lines per workgroup: 4 x 4, else 4 x 2, else 2 x 2 (a tile spans the q-shifts)
+  static const int tt[3][2] = {{4, 4}, {4, 2}, {2, 2}};
+  int T0 = 0, T1 = 0;
+  for (auto &t : tt)
+    if (t[0] >= qspan && t[1] >= qspan && t[0] <= a.Nq[0] && t[1] <= a.Nq[1] &&
+        (int64_t)t[0] * t[1] * TPL <= (int64_t)kFusedThreads * kFusedOut) {
+      T0 = t[0];
+      T1 = t[1];
+      break;
+    }
+  if (!T0) return false;
+  const bool f64 = a.precision == FGGC_FP64;
+  const size_t es = f64 ? 16 : 8;
+  int lg = 0;
+  while (((int64_t)1 << lg) < N) ++lg;
+  // the FFT's butterfly budget (lds_fft_rows, kContractBfly per thread): rows
+  // x N <= 8192, or 4096 when a radix-2 pass is taken (FP64 with odd log2 N)
+  const int64_t elems = (f64 && (lg & 1)) ? 4096 : 8192;
+  const int64_t P = (int64_t)T0 * T1;
+  int Lc = (int)std::min<int64_t>(a.sn[2], std::max<int64_t>(1, elems / (P * N)));
+  auto shm_of = [&](int lc) { return (size_t)lc * P * N * es + (size_t)N * es + (size_t)lc * ng * 8; };
+  // two workgroups per CU: at most ~80 KB of LDS each
+  while (Lc > 1 && shm_of(Lc) > 80 * 1024) --Lc;
+  if ((int64_t)Lc * P * N > elems || shm_of(Lc) > 160 * 1024) return false;
+  const int64_t blocks = a.sn[0] * a.sn[1] * (a.Nq[0] / T0) * (a.Nq[1] / T1);
+  if (blocks >= ((int64_t)1 << 31)) return false;
+  L.fT0 = T0;
+  L.fT1 = T1;
+  L.fTPL = (int)TPL;
+  L.fLc = Lc;
+  L.fnq = nq;
+  L.fnp = np;
+  L.fshm = shm_of(Lc);
+  return true;
+}
+
+FggcLayout fggc_layout(const FggcArgs &a, bool allow_fused = true) {
   FggcLayout L{};
   const int d = a.g.d;
   L.d = d;
@@ -1599,6 +1848,12 @@ FggcLayout fggc_layout(const FggcArgs &a) {
     L.maxdp = std::max(L.maxdp, l0.dp[m]);
     L.mindq = std::min(L.mindq, l0.dq[m]);
     L.maxdq = std::max(L.maxdq, l0.dq[m]);
+  }
+  {
+    int np = 0;
+    for (int m = 0; m < l0.n1; ++m)
+      if (l0.dq[m] == l0.dq[0]) ++np;
+    L.fused3 = allow_fused && plan_fused3(a, L, l0.n1 / np, np);
   }
   // q-tile and slice window of one accumulation workgroup: the LDS holds
   // S^d * tile^d cells; a tile is at least as wide as the q-shift set
@@ -1619,6 +1874,7 @@ FggcLayout fggc_layout(const FggcArgs &a) {
       // cells, the width of the aggregation workgroup
       L.tile[k] = d == 1 ? std::min<int64_t>(a.Nq[k], kAgg1Tile)
                          : std::min<int64_t>(a.Nq[k], std::max<int64_t>(deft[d], tmin));
+      if (L.fused3) L.tile[k] = k == 0 ? L.fT0 : (k == 1 ? L.fT1 : a.Nq[k]);
       L.ntq[k] = a.Nq[k] / L.tile[k];
       L.pmin[k] = a.slo[k] - L.mindp;
       L.npc[k] = a.sn[k] - (L.maxdp - L.mindp);
@@ -1638,7 +1894,9 @@ FggcLayout fggc_layout(const FggcArgs &a) {
   if (L.tiles >= ((int64_t)1 << 31)) fail(FGGC_EUNSUPPORTED, "too many accumulation workgroups");
   const int64_t N = std::max<int64_t>(a.pk->N, 1);
   L.agg1 = d == 1;
-  L.ns = L.agg1 ? 1 : (1 << d);  // key slots per packet: own tile, or 2^d with halo tiles
+  // key slots per packet: own tile, or 2^d with halo tiles (the fused finish
+  // has one tile along the last dimension: halo slots in dims 0 and 1 only)
+  L.ns = L.agg1 ? 1 : (L.fused3 ? 4 : (1 << d));
   L.nslots = a.pk->N * L.ns;
   const int64_t NS = std::max<int64_t>(L.nslots, 1);
   size_t o = 0;
@@ -1662,7 +1920,7 @@ FggcLayout fggc_layout(const FggcArgs &a) {
   }
   L.off_agg = put(L.agg1 ? (size_t)L.agg_splits * L.npc[0] * a.Nq[0] * L.N1 * es : 0);
   (void)N;
-  L.off_cells = put((size_t)L.ncells * es);
+  L.off_cells = put(L.fused3 ? 0 : (size_t)L.ncells * es);
   // after the cells: the cells-only entry point (whose cells are the
   // caller's) writes every tile and takes no occupancy map
   L.off_occ = put(d == 2 ? (size_t)L.nslices * L.ntq[0] * L.ntq[1] : 0);  // empty-tile map
@@ -1708,6 +1966,7 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
     else fggc_coef_kernel<D, N1, 0, 0, T><<<g, b, 0, s>>>(cp, pos, recs);
     FGGC_HIP(hipGetLastError());
   }
+  if (L.fused3) return;  // the fused finish accumulates the records itself
   AccParams ap{};
   ap.recs = recs;
   ap.start = start;
@@ -1883,6 +2142,7 @@ void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells
   kp.mindq = L.mindq;
   kp.maxdq = L.maxdq;
   kp.ns = L.ns;
+  kp.pc_last = L.fused3 ? 1 : 0;
   const CountPlan cpn = count_plan(L.nslots, L.nbins, L.ns);
   uint32_t *rank = (uint32_t *)(base + L.off_sort + cpn.off_rank);
   {
@@ -2037,6 +2297,65 @@ void launch_contract(const FggcArgs &a, const FggcLayout &L, int k, const T *in,
   FGGC_HIP(hipGetLastError());
 }
 
+bool g_fused_attr = false;
+std::mutex g_fused_mu;
+
+template <typename T>
+void launch_fused3(const FggcArgs &a, const FggcLayout &L, char *base, const MacParams &m, T *out,
+                   hipStream_t s) {
+  {
+    std::lock_guard<std::mutex> lk(g_fused_mu);
+    if (!g_fused_attr) {
+      const void *ks[] = {(const void *)fggc_fused3_kernel<2, 2, float2>,
+                          (const void *)fggc_fused3_kernel<4, 2, float2>,
+                          (const void *)fggc_fused3_kernel<2, 4, float2>,
+                          (const void *)fggc_fused3_kernel<2, 2, double2>,
+                          (const void *)fggc_fused3_kernel<4, 2, double2>,
+                          (const void *)fggc_fused3_kernel<2, 4, double2>};
+      for (const void *kf : ks)
+        FGGC_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+      g_fused_attr = true;
+    }
+  }
+  const DimLsq &l0 = a.lsq[0];
+  Fused3Params p{};
+  p.recs = base + L.off_recs;
+  p.start = (const int64_t *)(base + L.off_start);
+  for (int k = 0; k < 3; ++k) {
+    p.sn[k] = a.sn[k];
+    p.npc[k] = L.npc[k];
+    p.Nq[k] = a.Nq[k];
+  }
+  p.ntq0 = L.ntq[0];
+  p.ntq1 = L.ntq[1];
+  p.T0 = L.fT0;
+  p.T1 = L.fT1;
+  p.Lc = L.fLc;
+  p.TPL = L.fTPL;
+  p.lgN = 0;
+  while (((int64_t)1 << p.lgN) < a.Nq[2]) ++p.lgN;
+  for (int i = 0; i < 8; ++i) {
+    p.dq[i] = i < L.fnq ? l0.dq[i * L.fnp] : 0;
+    p.dp[i] = i < L.fnp ? l0.dp[i] : 0;
+  }
+  p.mindp = L.mindp;
+  p.maxdp = L.maxdp;
+  p.M = a.g.n[2];
+  p.kmin = m.kmin[2];
+  p.kmax = m.kmax[2];
+  p.slo = a.slo[2];
+  p.eps = a.eps;
+  p.dp2 = a.dp[2];
+  p.cK = a.cK;
+  const int64_t blocks = a.sn[0] * a.sn[1] * L.ntq[0] * L.ntq[1];
+  const T *tw = (const T *)fft_twiddles(a.Nq[2], a.precision);
+  const dim3 g((unsigned)blocks), b(kFusedThreads);
+  if (L.fnq == 2 && L.fnp == 2) fggc_fused3_kernel<2, 2, T><<<g, b, L.fshm, s>>>(p, out, tw);
+  else if (L.fnq == 4 && L.fnp == 2) fggc_fused3_kernel<4, 2, T><<<g, b, L.fshm, s>>>(p, out, tw);
+  else fggc_fused3_kernel<2, 4, T><<<g, b, L.fshm, s>>>(p, out, tw);
+  FGGC_HIP(hipGetLastError());
+}
+
 template <typename T, typename R>
 void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, const uint8_t *occ,
                   void *spec, Workspace &ws, hipStream_t s) {
@@ -2056,20 +2375,22 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, 
     m.slo[k] = a.slo[k];
     m.dp[k] = a.dp[k];
     m.inv_dp[k] = 1.0 / a.dp[k];
-    if (k < d) {
-      m.kmin[k] = (int64_t)std::floor((double)a.slo[k] * a.dp[k] / a.eps - a.cK / se) - 1;
-      m.kmax[k] = (int64_t)std::ceil((double)(a.slo[k] + a.sn[k] - 1) * a.dp[k] / a.eps + a.cK / se) + 1;
-    }
+    if (k < d) band_range(a, k, m.kmin[k], m.kmax[k]);
   }
   m.eps = a.eps;
   m.cK = a.cK;
   T *U = (T *)spec;
   if (d >= 2) {
     // F5 + F6 as d separable passes, last dimension first, into the spectrum
-    StageScope sc(a.prof, "fggc_contract", s);
+    // (three dimensions: the first pass fused with the accumulation)
     T *x1 = (T *)(base + L.off_x1), *x2 = (T *)(base + L.off_x2);
-    const T *in = cells;
-    for (int k = d - 1; k >= 0; --k) {
+    if (L.fused3) {
+      StageScope sc(a.prof, "fggc_fused", s);
+      launch_fused3<T>(a, L, base, m, x1, s);
+    }
+    StageScope sc(a.prof, "fggc_contract", s);
+    const T *in = L.fused3 ? x1 : cells;
+    for (int k = L.fused3 ? d - 2 : d - 1; k >= 0; --k) {
       T *out = k == 0 ? U : (k == d - 1 ? x1 : x2);
       launch_contract<T, R>(a, L, k, in, out, k == d - 1 ? occ : nullptr, m, s);
       in = out;
@@ -2093,12 +2414,12 @@ bool fggc_graph_safe(const FggcArgs &a) {
 }
 
 size_t fggc_cells_workspace_bytes(const FggcArgs &a) {
-  FggcLayout L = fggc_layout(a);
+  FggcLayout L = fggc_layout(a, false);
   return L.off_cells + 1024;
 }
 
 void launch_fggc_cells(const FggcArgs &a, void *cells, Workspace &ws, hipStream_t s) {
-  FggcLayout L = fggc_layout(a);
+  FggcLayout L = fggc_layout(a, false);
   char *base = (char *)ws.take(L.off_cells);
   cells_stage(a, L, base, cells, nullptr, false, s);
 }

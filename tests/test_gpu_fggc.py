@@ -406,3 +406,92 @@ def test_reconstruct_edge_cases(ctx, orc, d, M, prec, tol):
         u = u.cpu().numpy().reshape(-1).astype(np.complex128)
         ref = orc.fggc(q, p, s_, a_, eps, grid, sd["Nq"][:d], sd["dp"][:d], sd["dq_off"], sd["dp_off"])
         check(u, ref, tol, f"edge d={d} prec={prec} N={q.shape[1]}")
+
+
+def mesh3(seed, M, Nq=None, dp=None, eps=1.0 / 64, nq=8, npd=3, width=0.5):
+    """A 3D packet set on grid M (per dimension), with an optional strategy mesh."""
+    ps = W.gen_mesh(3, nq, npd, width, (0.5, 0.3, 0.3), eps, M[0], seed=seed)
+    ps.M = tuple(M)
+    return ps
+
+
+@pytest.mark.parametrize("name,prec,tol,M,Nq", [
+    ("Q2P2", F.FP64, 1e-12, (64, 64, 64), None),
+    ("Q2P2", F.FP32, 1e-6, (64, 64, 64), None),
+    ("Q4P2", F.FP32, 1e-6, (64, 64, 64), None),
+    ("Q2P4", F.FP32, 1e-6, (64, 64, 64), None),
+    # unequal meshes and grids: 4 x 4 line tiles over 64 x 32 q-cells, a q2
+    # line of 256, and a last-dimension grid (32) narrower than the band union
+    ("Q2P2", F.FP64, 1e-12, (32, 64, 32), (64, 32, 256)),
+    ("Q2P2", F.FP32, 1e-6, (128, 32, 64), (128, 64, 64)),
+    ("Q4P2", F.FP64, 1e-9, (64, 32, 128), (64, 64, 128)),
+])
+def test_reconstruct_3d_fused(ctx, orc, name, prec, tol, M, Nq):
+    # the three-dimensional finish (accumulation fused with the pass over the
+    # last dimension) for every shift set it takes, both precisions, and
+    # meshes and grids that differ per dimension
+    ps = mesh3(31, M)
+    st0 = F.default_strategy(3, ps.eps, name)
+    sd0 = st0.describe()
+    Nq = list(sd0["Nq"][:3]) if Nq is None else list(Nq)
+    st = F.make_strategy(3, Nq, sd0["dp"][:3], sd0["dq_off"], sd0["dp_off"])
+    sd = st.describe()
+    pts = heavy_points(ps, 60, 40, 5)
+    log(f"3d fused {name} prec {prec} M={M} Nq={Nq}")
+    u = ctx.reconstruct(t(ps.Q), t(ps.P), t(ps.S), t(ps.a), ps.eps, ps.M, st, scale=0.7, precision=prec)
+    torch.cuda.synchronize()
+    u = u.cpu().numpy().reshape(-1)[pts].astype(np.complex128)
+    ref = orc.fggc(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, sd["Nq"][:3], sd["dp"][:3], sd["dq_off"],
+                   sd["dp_off"], scale=0.7, pts=pts)
+    check(u, ref, tol, f"fggc 3d {name} prec {prec} M={M} Nq={Nq}")
+
+
+@pytest.mark.parametrize("prec,tol", [(F.FP64, 1e-12), (F.FP32, 1e-6)])
+def test_reconstruct_3d_edge_cases(ctx, orc, prec, tol):
+    # no packets; single packets; packets on q- and p-mesh points, on the
+    # periodic seam and at negative momenta (a compact p-range keeps the
+    # oracle's cells few), compared around each packet's centre
+    eps = 1.0 / 64
+    M = (32, 32, 32)
+    st = F.default_strategy(3, eps, "Q2P2")
+    sd = st.describe()
+    e0 = np.zeros((3, 0))
+    u = ctx.reconstruct(t(e0), t(e0), t(np.zeros(0)), t(np.zeros(0, complex)), eps, M, st, precision=prec)
+    torch.cuda.synchronize()
+    assert tuple(u.shape) == M and not torch.any(u != 0)
+    Nq, dp = sd["Nq"][:3], sd["dp"][:3]
+    dq = [2 * math.pi / n for n in Nq]
+    Qs, Ps = [], []
+    for i in (-(Nq[0] // 2), -3, 0, Nq[0] // 2 - 1):
+        for l in (-1, 0, 2):
+            Qs.append([-math.pi + (i + Nq[0] // 2) * dq[k] for k in range(3)])
+            Ps.append([l * dp[k] for k in range(3)])
+    Qs.append([-math.pi] * 3)
+    Ps.append([-0.5 * dp[0]] * 3)
+    Qs.append([math.pi - 1e-12, -math.pi, 0.3])
+    Ps.append([1.5 * dp[0], -0.9 * dp[1], 0.0])
+    Q = np.ascontiguousarray(np.array(Qs).T)
+    P = np.ascontiguousarray(np.array(Ps).T)
+    rng = np.random.default_rng(40)
+    N = Q.shape[1]
+    S = rng.uniform(0, 2 * math.pi, N)
+    a = rng.normal(size=N) + 1j * rng.normal(size=N)
+    # the grid points around every packet's centre (a single packet's values at
+    # random points are mostly tails far below the rounding of its peak), and
+    # some random ones
+    Mv = np.array(M)
+    near = []
+    for j in range(Q.shape[1]):
+        c = np.rint((Q[:, j] + math.pi) / (2 * math.pi) * Mv).astype(np.int64)
+        for off in np.ndindex(3, 3, 3):
+            near.append(np.ravel_multi_index(tuple((c + np.array(off) - 1) % Mv), M))
+    pts = np.unique(np.concatenate([np.array(near), rng.choice(int(np.prod(M)), 32, replace=False)]))
+    for sel in (slice(0, 1), slice(-1, None), slice(None)):
+        q, p, s_, a_ = (np.ascontiguousarray(Q[:, sel]), np.ascontiguousarray(P[:, sel]),
+                        np.ascontiguousarray(S[sel]), np.ascontiguousarray(a[sel]))
+        log(f"3d edge prec {prec} N={q.shape[1]}")
+        u = ctx.reconstruct(t(q), t(p), t(s_), t(a_), eps, M, st, precision=prec)
+        torch.cuda.synchronize()
+        u = u.cpu().numpy().reshape(-1)[pts].astype(np.complex128)
+        ref = orc.fggc(q, p, s_, a_, eps, M, Nq, dp, sd["dq_off"], sd["dp_off"], pts=pts)
+        check(u, ref, tol, f"3d edge prec={prec} N={q.shape[1]}")
