@@ -1588,7 +1588,9 @@ __global__ __launch_bounds__(kContractThreads) void fft_contract_kernel(Contract
 // binned by (p-cell 0, p-cell 1, q-tile, p-cell 2), so the records that reach
 // a chunk are one contiguous run per (p-cell 0, p-cell 1).
 constexpr int kFusedThreads = 512;
-constexpr int kFusedOut = 8;  // outputs per thread
+constexpr int kFusedOut = 8;   // outputs per thread
+constexpr int kFusedRuns = 16; // (p-cell 0, p-cell 1) pairs that reach a slice pair: (p-shift span + 1)^2
+constexpr size_t kFusedMaxLds = 144 * 1024;  // dynamic LDS (the kernel's static LDS comes on top)
 
 struct Fused3Params {
   const char *recs;
@@ -1614,11 +1616,15 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
   const int M = (int)p.M;
   const int ng = (int)(p.kmax - p.kmin + 1);
   const int nact = min(M, ng);
-  const int bs = (int)blockDim.x, tid = (int)threadIdx.x;
-  T *cl = reinterpret_cast<T *>(smem_raw);            // [Lc][P][N] the chunk's lines
-  T *stw = cl + (size_t)p.Lc * P * N;                 // [N] twiddles
+  const int bs = (int)blockDim.x, tid0 = (int)threadIdx.x;
+  // lines of up to 256 points are transformed in two register passes
+  // (lds_fft2_rows) on padded rows; longer ones by the Stockham passes
+  const bool two = lgN <= 8;
+  const int rs = two ? fft2_row_stride(lgN) : N;     // row stride of the lines
+  T *cl = reinterpret_cast<T *>(smem_raw);            // [Lc][P][rs] the chunk's lines
+  T *stw = cl + (size_t)p.Lc * P * rs;                // [N] twiddles
   double *gam = reinterpret_cast<double *>(stw + N);  // [Lc][ng] band weights
-  for (int i = tid; i < N; i += bs) stw[i] = tw[i];
+  for (int i = tid0; i < N; i += bs) stw[i] = tw[i];
   // workgroup -> (q-tile, l0, l1); workgroups run on the eight XCDs in turn,
   // and each XCD takes a contiguous range of the work, so that the slice pairs
   // of one tile (which read the same bins) share that XCD's L2
@@ -1635,15 +1641,34 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
   const int kmod = (int)(((p.kmin % M) + M) % M);
   // fold and output mapping: TPL threads per line group (a power of two >=
   // the active frequencies), G = blockDim / TPL groups
-  const int TPL = p.TPL, G = bs / TPL, t = tid & (TPL - 1), lg0 = tid / TPL;
+  const int TPL = p.TPL, G = bs / TPL;
   double accr[kFusedOut], acci[kFusedOut];
 #pragma unroll
   for (int c = 0; c < kFusedOut; ++c) accr[c] = acci[c] = 0.0;
   const double cst = sqrt(kTwoPi * p.eps) / kTwoPi, cut = -0.5 * p.cK * p.cK * (1.0 + 1e-12);
   const double inv2e = 1.0 / (2.0 * p.eps);
+  // the runs of records a chunk reads: one per (p-cell 0, p-cell 1) that
+  // reaches (l0, l1), each a contiguous range of bins over p-cell 2
+  __shared__ int64_t s_r0[kFusedRuns], s_n[kFusedRuns];
+  const int n1r = (int)(a1hi - a1lo + 1), nruns = (int)(a0hi - a0lo + 1) * n1r;
   for (int c0 = 0; c0 < (int)p.sn[2]; c0 += p.Lc) {
     const int lcn = min(p.Lc, (int)p.sn[2] - c0);
-    for (int e = tid; e < lcn * P * N; e += bs) cl[e] = T{0, 0};
+    // the thread index through a compiler fence: addresses are formed in each
+    // chunk where they are used, not hoisted out of the loop into registers
+    int tid = tid0;
+    asm volatile("" : "+v"(tid));
+    // packets of p-cells (a0, a1, a2), a2 in [c0 - span, c0 + lcn - 1]: the
+    // runs' bounds are loaded first, so that their latency overlaps the
+    // clearing of the lines and the band table
+    const int64_t a2lo = max<int64_t>(0, c0 - span), a2hi = min<int64_t>(npc2 - 1, c0 + lcn - 1);
+    if (tid < nruns) {
+      const int64_t a0 = a0lo + tid / n1r, a1 = a1lo + tid % n1r;
+      const int64_t kb = ((a0 * p.npc[1] + a1) * nqt + tq) * npc2;
+      const int64_t r0 = a2lo <= a2hi ? p.start[kb + a2lo] : 0, r1 = a2lo <= a2hi ? p.start[kb + a2hi + 1] : 0;
+      s_r0[tid] = r0;
+      s_n[tid] = r1 - r0;
+    }
+    for (int e = tid; e < lcn * P * rs; e += bs) cl[e] = T{0, 0};
     for (int e = tid; e < lcn * ng; e += bs) {
       const int l = e / ng, t = e - l * ng;
       const double dk = p.eps * (double)(p.kmin + t) - (double)(p.slo + c0 + l) * p.dp2;  // eps (k - p_l / eps)
@@ -1651,13 +1676,16 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
       gam[e] = ex < cut ? 0.0 : cst * exp(ex);
     }
     __syncthreads();
-    // packets of p-cells (a0, a1, a2), a2 in [c0 - span, c0 + lcn - 1]
-    const int64_t a2lo = max<int64_t>(0, c0 - span), a2hi = min<int64_t>(npc2 - 1, c0 + lcn - 1);
-    for (int64_t a0 = a0lo; a0 <= a0hi && a2lo <= a2hi; ++a0)
-      for (int64_t a1 = a1lo; a1 <= a1hi; ++a1) {
-        const int64_t kb = ((a0 * p.npc[1] + a1) * nqt + tq) * npc2;
-        const int64_t r0 = p.start[kb + a2lo], r1 = p.start[kb + a2hi + 1];
-        for (int64_t r = r0 + tid; r < r1; r += bs) {
+    // the chunk's records as one index space over the runs, one per thread
+    int64_t total = 0;
+    for (int x = 0; x < nruns; ++x) total += s_n[x];
+    for (int64_t i = tid; i < total; i += bs) {
+      int run = 0;
+      int64_t off = i;
+      while (off >= s_n[run]) off -= s_n[run++];
+      {
+        {
+          const int64_t r = s_r0[run] + off;
           uint4 raw[NV];
           const uint4 *src = reinterpret_cast<const uint4 *>(p.recs + r * (int64_t)RB);
 #pragma unroll
@@ -1698,32 +1726,36 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
                 for (int b = 0; b < NP; ++b)
                   if (b == b1) w = c[N1 + a1i * NP + b];
                 const T uw = T{u.x * w.x - u.y * w.y, u.x * w.y + u.y * w.x};
-                T *line = cl + ((size_t)l2 * P + la0[a0i] * T1 + la1[a1i]) * N;
+                const int line = (l2 * P + la0[a0i] * T1 + la1[a1i]) * rs;
 #pragma unroll
                 for (int a2i = 0; a2i < NQ; ++a2i) {
                   const T z = c[2 * N1 + a2i * NP + b2];
-                  atomicAdd(&line[q2[a2i]].x, uw.x * z.x - uw.y * z.y);
-                  atomicAdd(&line[q2[a2i]].y, uw.x * z.y + uw.y * z.x);
+                  RR *cell = &cl[line + q2[a2i]].x;
+                  atomicAdd(cell, uw.x * z.x - uw.y * z.y);
+                  atomicAdd(cell + 1, uw.x * z.y + uw.y * z.x);
                 }
               }
             }
           }
         }
       }
+    }
     __syncthreads();
-    lds_fft_rows<T, kContractBfly>(cl, lgN, lcn * P, N, 0, stw);
+    if (two) lds_fft2_rows<T>(cl, lgN, lcn * P, rs, stw, tid, bs);
+    else lds_fft_rows<T, kContractBfly>(cl, lgN, lcn * P, rs, 0, stw);
     // thread (g, t): frequency t of lines g, g + G, g + 2 G, ... -- one band
     // weight per (slice, alias) serves all of them
+    const int t = tid & (TPL - 1), lg0 = tid / TPL;
     if (t < nact) {
       for (int64_t kk = p.kmin + t; kk <= p.kmax; kk += M) {
-        const T *fq = cl + (size_t)lg0 * N + (int)(kk & msk2);
+        const T *fq = cl + (size_t)lg0 * rs + (int)(kk & msk2);
         const double *gb = gam + (kk - p.kmin);
         for (int l = 0; l < lcn; ++l) {
           const double gv = gb[l * ng];
 #pragma unroll
           for (int c = 0; c < kFusedOut; ++c) {
             if (lg0 + c * G >= P) break;
-            const T v = fq[((size_t)l * P + c * G) * N];
+            const T v = fq[((size_t)l * P + c * G) * rs];
             accr[c] = fma(gv, (double)v.x, accr[c]);
             acci[c] = fma(gv, (double)v.y, acci[c]);
           }
@@ -1733,6 +1765,7 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
     __syncthreads();
   }
   const int64_t base = (l0 * p.sn[1] + l1) * p.Nq[0];
+  const int t = tid0 & (TPL - 1), lg0 = tid0 / TPL;
   // every frequency of this thread's lines: the band's sums, zeros elsewhere
   for (int tt = t; tt < M; tt += TPL) {
     const int kp = (kmod + tt) % M;
@@ -1757,7 +1790,7 @@ struct FggcLayout {
   // dimension (no dense cell array); lines T0 x T1 per workgroup, Lc slices
   // of the last dimension per LDS chunk, the kernel's LDS bytes
   bool fused3;
-  int fT0, fT1, fLc, fnq, fnp, fTPL;
+  int fT0, fT1, fLc, fnq, fnp, fTPL, fThreads;
   size_t fshm;
   int agg_splits;  // one dimension: workgroups (and copies of the aggregate) per bin
   int64_t ncells, nslices, npts, nbins, nslots, tiles, ntq[3], tile[3], npc[3], pmin[3], S[3], nsw[3];
@@ -1787,7 +1820,8 @@ bool plan_fused3(const FggcArgs &a, FggcLayout &L, int nq, int np) {
   if (L.N1 != nq * np) return false;
   const int64_t N = a.Nq[2];
   if (N < 8 || N > 2048 || (N & (N - 1)) || a.Nq[0] < 4 || a.Nq[1] < 4) return false;
-  const int qspan = L.maxdq - L.mindq + 1;
+  const int qspan = L.maxdq - L.mindq + 1, pspan = L.maxdp - L.mindp + 1;
+  if (pspan * pspan > kFusedRuns) return false;  // the runs of bins a chunk reads
   int64_t kmin, kmax;
   band_range(a, 2, kmin, kmax);
   const int64_t ng = kmax - kmin + 1, nact = std::min<int64_t>(a.g.n[2], ng);
@@ -1796,14 +1830,17 @@ bool plan_fused3(const FggcArgs &a, FggcLayout &L, int nq, int np) {
   int64_t TPL = 1;
   while (TPL < nact) TPL *= 2;
   if (TPL > kFusedThreads) return false;
-  // lines per workgroup: 4 x 4, else 4 x 2, else 2 x 2 (a tile spans the q-shifts)
-  static const int tt[3][2] = {{4, 4}, {4, 2}, {2, 2}};
-  int T0 = 0, T1 = 0;
+  // lines per workgroup and threads: 4 x 2 lines on 256 threads (several
+  // workgroups per CU), else 4 x 4 on 512, else 2 x 2 on 256 or 512; a tile
+  // spans the q-shifts, and a thread holds at most kFusedOut outputs
+  static const int tt[4][3] = {{4, 2, 256}, {4, 4, 512}, {2, 2, 256}, {2, 2, 512}};
+  int T0 = 0, T1 = 0, threads = 0;
   for (auto &t : tt)
-    if (t[0] >= qspan && t[1] >= qspan && t[0] <= a.Nq[0] && t[1] <= a.Nq[1] &&
-        (int64_t)t[0] * t[1] * TPL <= (int64_t)kFusedThreads * kFusedOut) {
+    if (t[0] >= qspan && t[1] >= qspan && t[0] <= a.Nq[0] && t[1] <= a.Nq[1] && TPL <= t[2] &&
+        (int64_t)t[0] * t[1] * TPL <= (int64_t)t[2] * kFusedOut) {
       T0 = t[0];
       T1 = t[1];
+      threads = t[2];
       break;
     }
   if (!T0) return false;
@@ -1811,20 +1848,28 @@ bool plan_fused3(const FggcArgs &a, FggcLayout &L, int nq, int np) {
   const size_t es = f64 ? 16 : 8;
   int lg = 0;
   while (((int64_t)1 << lg) < N) ++lg;
-  // the FFT's butterfly budget (lds_fft_rows, kContractBfly per thread): rows
-  // x N <= 8192, or 4096 when a radix-2 pass is taken (FP64 with odd log2 N)
-  const int64_t elems = (f64 && (lg & 1)) ? 4096 : 8192;
   const int64_t P = (int64_t)T0 * T1;
-  int Lc = (int)std::min<int64_t>(a.sn[2], std::max<int64_t>(1, elems / (P * N)));
-  auto shm_of = [&](int lc) { return (size_t)lc * P * N * es + (size_t)N * es + (size_t)lc * ng * 8; };
+  // lines of N <= 256 points: the two-pass register FFT (lds_fft2_rows), one
+  // unit per thread in its first pass and two in its second, on rows padded
+  // to fft2_row_stride; longer lines: the Stockham passes, whose butterfly
+  // budget (kContractBfly per thread) is rows x N <= 8192, or 4096 when a
+  // radix-2 pass is taken (FP64 with odd log2 N)
+  const bool two = lg <= 8;
+  const int64_t rs = two ? fft2_row_stride(lg) : N;
+  const int64_t N1 = (int64_t)1 << ((lg + 1) / 2), N2 = (int64_t)1 << (lg / 2);
+  int64_t maxrows = two ? std::min<int64_t>(threads / N2, 2 * threads / N1)
+                        : ((f64 && (lg & 1)) ? 4096 : 8192) * threads / kFusedThreads / N;
+  int Lc = (int)std::min<int64_t>(a.sn[2], std::max<int64_t>(1, maxrows / P));
+  auto shm_of = [&](int lc) { return (size_t)lc * P * rs * es + (size_t)N * es + (size_t)lc * ng * 8; };
   // two workgroups per CU: at most ~80 KB of LDS each
   while (Lc > 1 && shm_of(Lc) > 80 * 1024) --Lc;
-  if ((int64_t)Lc * P * N > elems || shm_of(Lc) > 160 * 1024) return false;
+  if ((int64_t)Lc * P > maxrows || shm_of(Lc) > kFusedMaxLds) return false;
   const int64_t blocks = a.sn[0] * a.sn[1] * (a.Nq[0] / T0) * (a.Nq[1] / T1);
   if (blocks >= ((int64_t)1 << 31)) return false;
   L.fT0 = T0;
   L.fT1 = T1;
   L.fTPL = (int)TPL;
+  L.fThreads = threads;
   L.fLc = Lc;
   L.fnq = nq;
   L.fnp = np;
@@ -2313,7 +2358,7 @@ void launch_fused3(const FggcArgs &a, const FggcLayout &L, char *base, const Mac
                           (const void *)fggc_fused3_kernel<4, 2, double2>,
                           (const void *)fggc_fused3_kernel<2, 4, double2>};
       for (const void *kf : ks)
-        FGGC_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        FGGC_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedMaxLds));
       g_fused_attr = true;
     }
   }
@@ -2349,7 +2394,7 @@ void launch_fused3(const FggcArgs &a, const FggcLayout &L, char *base, const Mac
   p.cK = a.cK;
   const int64_t blocks = a.sn[0] * a.sn[1] * L.ntq[0] * L.ntq[1];
   const T *tw = (const T *)fft_twiddles(a.Nq[2], a.precision);
-  const dim3 g((unsigned)blocks), b(kFusedThreads);
+  const dim3 g((unsigned)blocks), b((unsigned)L.fThreads);
   if (L.fnq == 2 && L.fnp == 2) fggc_fused3_kernel<2, 2, T><<<g, b, L.fshm, s>>>(p, out, tw);
   else if (L.fnq == 4 && L.fnp == 2) fggc_fused3_kernel<4, 2, T><<<g, b, L.fshm, s>>>(p, out, tw);
   else fggc_fused3_kernel<2, 4, T><<<g, b, L.fshm, s>>>(p, out, tw);

@@ -138,5 +138,149 @@ __device__ __forceinline__ void lds_fft_rows(T *sm, int lg, int nrows, int rowst
   if (n2) lds_fft_pass<T, 1, MB>(sm, lg, lgNs, nrows, rowstride, inverse, tw);
 }
 
+// In-register forward DFTs of length 2, 4, 8 and 16 (natural order in and
+// out): X[k] = sum_n x[n] exp(-2 pi i n k / R).
+template <typename T> __device__ __forceinline__ void dft2f(T *x) {
+  const T a = x[0], b = x[1];
+  x[0] = cadd(a, b);
+  x[1] = csub(a, b);
+}
+
+template <typename T> __device__ __forceinline__ void dft4f(T *x) {
+  const T s0 = cadd(x[0], x[2]), d0 = csub(x[0], x[2]);
+  const T s1 = cadd(x[1], x[3]), d1 = rot_quarter(csub(x[1], x[3]), 0);
+  x[0] = cadd(s0, s1);
+  x[2] = csub(s0, s1);
+  x[1] = cadd(d0, d1);
+  x[3] = csub(d0, d1);
+}
+
+// 16 = 4 x 4: DFT4 over n1 of x[n2 + 4 n1] for each n2, twiddle
+// exp(-2 pi i n2 k1 / 16), DFT4 over n2: X[k1 + 4 k2].
+template <typename T> __device__ __forceinline__ void dft16f(T *x) {
+  using R = decltype(T{}.x);
+  constexpr R c1 = (R)0.92387953251128675613;  // cos(pi/8)
+  constexpr R s1 = (R)0.38268343236508977173;  // sin(pi/8)
+  constexpr R h = (R)0.70710678118654752440;   // cos(pi/4)
+  T y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    T v[4] = {x[n2], x[n2 + 4], x[n2 + 8], x[n2 + 12]};
+    dft4f(v);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = v[k1];
+  }
+  // exp(-2 pi i m / 16) for m = n2 k1 in {1, 2, 3, 4, 6, 9}
+  y[1][1] = cmul(y[1][1], T{c1, -s1});
+  y[1][2] = cmul(y[1][2], T{h, -h});
+  y[1][3] = cmul(y[1][3], T{s1, -c1});
+  y[2][1] = cmul(y[2][1], T{h, -h});
+  y[2][2] = rot_quarter(y[2][2], 0);
+  y[2][3] = cmul(y[2][3], T{-h, -h});
+  y[3][1] = cmul(y[3][1], T{s1, -c1});
+  y[3][2] = cmul(y[3][2], T{-h, -h});
+  y[3][3] = cmul(y[3][3], T{-c1, s1});
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    T v[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+    dft4f(v);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) x[k1 + 4 * k2] = v[k2];
+  }
+}
+
+template <typename T, int R> __device__ __forceinline__ void dftf(T *x) {
+  if constexpr (R == 2) dft2f(x);
+  else if constexpr (R == 4) dft4f(x);
+  else if constexpr (R == 8) dft8(x, 0);
+  else dft16f(x);
+}
+
+// Row stride (elements) for lds_fft2_rows on rows of N = 2^lg: the row
+// length padded so that rows start a whole number of N2-element blocks
+// apart in the LDS banks (N2 = 2^floor(lg/2)).
+__host__ __device__ inline int fft2_row_stride(int lg) { return (1 << lg) + (1 << (lg / 2)); }
+
+// Forward DFT of nrows rows of N = N1 N2 points in LDS (N1 = 2^ceil(lg/2),
+// N2 = 2^floor(lg/2), 8 <= N <= 256), rows `rs` elements apart, in two
+// passes with one unit of work per thread each:
+//   A  unit (row, n2): DFT over n1 of x[n2 + N2 n1], times exp(-2 pi i n2 k1 / N),
+//      stored at block k1, slot n2 ^ sigma(row, k1) (a swizzle that spreads
+//      the next pass's reads over the LDS banks);
+//   B  unit (row, k1): DFT over n2 of block k1 gives F[k1 + N1 k2], stored
+//      in natural order.
+// tw[m] = exp(-2 pi i m / N).  Requires nrows * N2 <= blockDim and
+// nrows * N1 <= 2 blockDim; all threads take part and synchronise.  The
+// caller passes the thread index (tid) and blockDim (bs): inside a loop it
+// can pass them through a compiler fence, so that the passes' addresses are
+// formed where they are used instead of being hoisted out of the loop and
+// held in registers for its whole length.
+template <typename T, int N1, int N2>
+__device__ __forceinline__ void lds_fft2_pass(T *sm, int nrows, int rs, const T *__restrict__ tw, int tid,
+                                              int bs) {
+  constexpr int N = N1 * N2;
+  auto sigma = [](int row, int k1) { return ((k1 >> 2) + 4 * row) & (N2 - 1); };
+  // pass A
+  T x[N1];
+  const int ua = tid;
+  const bool hasA = ua < nrows * N2;
+  const int rowA = ua / N2, n2 = ua % N2;
+  if (hasA) {
+    const T *src = sm + rowA * rs + n2;
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) x[n1] = src[N2 * n1];
+    dftf<T, N1>(x);
+#pragma unroll
+    for (int k1 = 1; k1 < N1; ++k1) x[k1] = cmul(x[k1], tw[n2 * k1]);
+  }
+  __syncthreads();
+  if (hasA) {
+    T *dst = sm + rowA * rs;
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) dst[N2 * k1 + (n2 ^ sigma(rowA, k1))] = x[k1];
+  }
+  __syncthreads();
+  // pass B: up to two units per thread (nrows N1 <= 2 blockDim; one when
+  // N1 = N2, as nrows N2 <= blockDim), held until the barrier
+  constexpr int UB = N1 > N2 ? 2 : 1;
+  T y[UB][N2];
+#pragma unroll
+  for (int u = 0; u < UB; ++u) {
+    const int ub = tid + u * bs;
+    if (ub >= nrows * N1) break;
+    const int row = ub / N1, k1 = ub % N1;
+    const T *src = sm + row * rs + N2 * k1;
+    const int sg = sigma(row, k1);
+#pragma unroll
+    for (int m = 0; m < N2; ++m) y[u][m] = src[m ^ sg];
+    dftf<T, N2>(y[u]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < UB; ++u) {
+    const int ub = tid + u * bs;
+    if (ub >= nrows * N1) break;
+    const int row = ub / N1, k1 = ub % N1;
+    T *dst = sm + row * rs + k1;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) dst[N1 * k2] = y[u][k2];
+  }
+  __syncthreads();
+  (void)N;
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_fft2_rows(T *sm, int lg, int nrows, int rs, const T *__restrict__ tw, int tid,
+                                              int bs) {
+  switch (lg) {
+    case 3: lds_fft2_pass<T, 4, 2>(sm, nrows, rs, tw, tid, bs); break;
+    case 4: lds_fft2_pass<T, 4, 4>(sm, nrows, rs, tw, tid, bs); break;
+    case 5: lds_fft2_pass<T, 8, 4>(sm, nrows, rs, tw, tid, bs); break;
+    case 6: lds_fft2_pass<T, 8, 8>(sm, nrows, rs, tw, tid, bs); break;
+    case 7: lds_fft2_pass<T, 16, 8>(sm, nrows, rs, tw, tid, bs); break;
+    default: lds_fft2_pass<T, 16, 16>(sm, nrows, rs, tw, tid, bs); break;
+  }
+}
+
 }  // namespace fggc
 #endif
