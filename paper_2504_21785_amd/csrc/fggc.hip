@@ -1602,7 +1602,22 @@ struct Fused3Params {
   int mindp, maxdp;
   int64_t M, kmin, kmax, slo;  // last dimension: grid points, band union, first slice
   double eps, dp2, cK;
+  const double *gtab;  // [sn2][kmax - kmin + 1] band weights (band_table_kernel)
 };
+
+// Band weights of the last dimension for the fused finish, once per call:
+// gtab[l][t] = gamma_l(kmin + t) = sqrt(2 pi eps) / (2 pi) exp(-eps (k - p_l / eps)^2 / 2),
+// p_l = (slo + l) dp, zero outside the truncated band |k - p_l / eps| <= cK / sqrt(eps).
+__global__ void band_table_kernel(Fused3Params p, double *__restrict__ gtab) {
+  const int ng = (int)(p.kmax - p.kmin + 1);
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= p.sn[2] * ng) return;
+  const int64_t l = e / ng, t = e - l * ng;
+  const double cst = sqrt(kTwoPi * p.eps) / kTwoPi, cut = -0.5 * p.cK * p.cK * (1.0 + 1e-12);
+  const double dk = p.eps * (double)(p.kmin + t) - (double)(p.slo + l) * p.dp2;  // eps (k - p_l / eps)
+  const double ex = -dk * dk / (2.0 * p.eps);
+  gtab[e] = ex < cut ? 0.0 : cst * exp(ex);
+}
 
 template <int NQ, int NP, typename T>
 __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params p, T *__restrict__ Y,
@@ -1617,10 +1632,9 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
   const int ng = (int)(p.kmax - p.kmin + 1);
   const int nact = min(M, ng);
   const int bs = (int)blockDim.x, tid0 = (int)threadIdx.x;
-  // lines of up to 256 points are transformed in two register passes
-  // (lds_fft2_rows) on padded rows; longer ones by the Stockham passes
-  const bool two = lgN <= 8;
-  const int rs = two ? fft2_row_stride(lgN) : N;     // row stride of the lines
+  // the lines (at most 256 points) are transformed in two register passes
+  // (lds_fft2_rows) on padded rows
+  const int rs = fft2_row_stride(lgN);               // row stride of the lines
   T *cl = reinterpret_cast<T *>(smem_raw);            // [Lc][P][rs] the chunk's lines
   T *stw = cl + (size_t)p.Lc * P * rs;                // [N] twiddles
   double *gam = reinterpret_cast<double *>(stw + N);  // [Lc][ng] band weights
@@ -1645,8 +1659,6 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
   double accr[kFusedOut], acci[kFusedOut];
 #pragma unroll
   for (int c = 0; c < kFusedOut; ++c) accr[c] = acci[c] = 0.0;
-  const double cst = sqrt(kTwoPi * p.eps) / kTwoPi, cut = -0.5 * p.cK * p.cK * (1.0 + 1e-12);
-  const double inv2e = 1.0 / (2.0 * p.eps);
   // the runs of records a chunk reads: one per (p-cell 0, p-cell 1) that
   // reaches (l0, l1), each a contiguous range of bins over p-cell 2
   __shared__ int64_t s_r0[kFusedRuns], s_n[kFusedRuns];
@@ -1668,13 +1680,8 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
       s_r0[tid] = r0;
       s_n[tid] = r1 - r0;
     }
+    for (int e = tid; e < lcn * ng; e += bs) gam[e] = p.gtab[(int64_t)c0 * ng + e];
     for (int e = tid; e < lcn * P * rs; e += bs) cl[e] = T{0, 0};
-    for (int e = tid; e < lcn * ng; e += bs) {
-      const int l = e / ng, t = e - l * ng;
-      const double dk = p.eps * (double)(p.kmin + t) - (double)(p.slo + c0 + l) * p.dp2;  // eps (k - p_l / eps)
-      const double ex = -dk * dk * inv2e;
-      gam[e] = ex < cut ? 0.0 : cst * exp(ex);
-    }
     __syncthreads();
     // the chunk's records as one index space over the runs, one per thread
     int64_t total = 0;
@@ -1741,8 +1748,7 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
       }
     }
     __syncthreads();
-    if (two) lds_fft2_rows<T>(cl, lgN, lcn * P, rs, stw, tid, bs);
-    else lds_fft_rows<T, kContractBfly>(cl, lgN, lcn * P, rs, 0, stw);
+    lds_fft2_rows<T>(cl, lgN, lcn * P, rs, stw, tid, bs);
     // thread (g, t): frequency t of lines g, g + G, g + 2 G, ... -- one band
     // weight per (slice, alias) serves all of them
     const int t = tid & (TPL - 1), lg0 = tid / TPL;
@@ -1796,6 +1802,7 @@ struct FggcLayout {
   int64_t ncells, nslices, npts, nbins, nslots, tiles, ntq[3], tile[3], npc[3], pmin[3], S[3], nsw[3];
   int64_t nb[3];
   int mindp, maxdp, mindq, maxdq;
+  size_t off_gam;  // fused finish: band weights gamma_l2(k) of every slice l2 [sn2][ng] (FP64)
   size_t off_lsq, off_keys, off_pos, off_sort, off_start, off_recs, off_agg, off_cells, off_occ,
       off_spec, off_x1, off_x2, total;
 };
@@ -1812,14 +1819,14 @@ void band_range(const FggcArgs &a, int k, int64_t &kmin, int64_t &kmax) {
 
 // The fused three-dimensional finish, when the strategy and sizes allow it:
 // a tensor shift set of 2 x 2, 4 x 2 or 2 x 4, power-of-two q-meshes of at
-// least 4 (dims 0, 1) and 8 to 2048 (dim 2) points, a workgroup's outputs and
+// least 4 (dims 0, 1) and 8 to 256 (dim 2) points, a workgroup's outputs and
 // its LDS chunk within their budgets.
 bool plan_fused3(const FggcArgs &a, FggcLayout &L, int nq, int np) {
   if (a.g.d != 3) return false;
   if (!((nq == 2 && np == 2) || (nq == 4 && np == 2) || (nq == 2 && np == 4))) return false;
   if (L.N1 != nq * np) return false;
   const int64_t N = a.Nq[2];
-  if (N < 8 || N > 2048 || (N & (N - 1)) || a.Nq[0] < 4 || a.Nq[1] < 4) return false;
+  if (N < 8 || N > 256 || (N & (N - 1)) || a.Nq[0] < 4 || a.Nq[1] < 4) return false;
   const int qspan = L.maxdq - L.mindq + 1, pspan = L.maxdp - L.mindp + 1;
   if (pspan * pspan > kFusedRuns) return false;  // the runs of bins a chunk reads
   int64_t kmin, kmax;
@@ -1850,19 +1857,17 @@ bool plan_fused3(const FggcArgs &a, FggcLayout &L, int nq, int np) {
   while (((int64_t)1 << lg) < N) ++lg;
   const int64_t P = (int64_t)T0 * T1;
   // lines of N <= 256 points: the two-pass register FFT (lds_fft2_rows), one
-  // unit per thread in its first pass and two in its second, on rows padded
-  // to fft2_row_stride; longer lines: the Stockham passes, whose butterfly
-  // budget (kContractBfly per thread) is rows x N <= 8192, or 4096 when a
-  // radix-2 pass is taken (FP64 with odd log2 N)
-  const bool two = lg <= 8;
-  const int64_t rs = two ? fft2_row_stride(lg) : N;
+  // unit per thread in its first pass and up to two in its second, on rows
+  // padded to fft2_row_stride
+  const int64_t rs = fft2_row_stride(lg);
   const int64_t N1 = (int64_t)1 << ((lg + 1) / 2), N2 = (int64_t)1 << (lg / 2);
-  int64_t maxrows = two ? std::min<int64_t>(threads / N2, 2 * threads / N1)
-                        : ((f64 && (lg & 1)) ? 4096 : 8192) * threads / kFusedThreads / N;
+  const int64_t maxrows = std::min<int64_t>(threads / N2, 2 * threads / N1);
   int Lc = (int)std::min<int64_t>(a.sn[2], std::max<int64_t>(1, maxrows / P));
   auto shm_of = [&](int lc) { return (size_t)lc * P * rs * es + (size_t)N * es + (size_t)lc * ng * 8; };
-  // two workgroups per CU: at most ~80 KB of LDS each
-  while (Lc > 1 && shm_of(Lc) > 80 * 1024) --Lc;
+  // LDS for five 256-thread (two 512-thread) workgroups per CU, the most the
+  // kernel's registers allow
+  const size_t budget = threads == 256 ? 32 * 1024 - 512 : 80 * 1024;
+  while (Lc > 1 && shm_of(Lc) > budget) --Lc;
   if ((int64_t)Lc * P > maxrows || shm_of(Lc) > kFusedMaxLds) return false;
   const int64_t blocks = a.sn[0] * a.sn[1] * (a.Nq[0] / T0) * (a.Nq[1] / T1);
   if (blocks >= ((int64_t)1 << 31)) return false;
@@ -1982,6 +1987,12 @@ FggcLayout fggc_layout(const FggcArgs &a, bool allow_fused = true) {
     };
     L.off_x1 = put(pass_out(d - 1) * es);
     if (d == 3) L.off_x2 = put(pass_out(1) * es);
+  }
+  L.off_gam = 0;
+  if (L.fused3) {
+    int64_t kmin, kmax;
+    band_range(a, 2, kmin, kmax);
+    L.off_gam = put((size_t)a.sn[2] * (size_t)(kmax - kmin + 1) * 8);
   }
   L.total = o;
   return L;
@@ -2392,6 +2403,12 @@ void launch_fused3(const FggcArgs &a, const FggcLayout &L, char *base, const Mac
   p.eps = a.eps;
   p.dp2 = a.dp[2];
   p.cK = a.cK;
+  p.gtab = (const double *)(base + L.off_gam);
+  {
+    const int64_t nt = a.sn[2] * (p.kmax - p.kmin + 1);
+    band_table_kernel<<<dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s>>>(p, (double *)(base + L.off_gam));
+    FGGC_HIP(hipGetLastError());
+  }
   const int64_t blocks = a.sn[0] * a.sn[1] * L.ntq[0] * L.ntq[1];
   const T *tw = (const T *)fft_twiddles(a.Nq[2], a.precision);
   const dim3 g((unsigned)blocks), b((unsigned)L.fThreads);
@@ -2449,6 +2466,114 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, 
   launch_fft_to(d, a.g.n, +1, prec, U, a.u, ws, s, a.prof, "fggc_ifft");
 }
 
+// Per-packet coefficients for inspection: the coefficient kernel's records
+// in packet order (identity positions), then the Kronecker product over
+// dimensions of each record's per-dimension coefficients, c_K for every basis
+// K (row-major over dimensions, each index over the one-dimensional shift
+// set in plan order), and the packet's cell (q index, p-cell) per dimension.
+__global__ void iota_kernel(uint32_t *__restrict__ pos, int64_t N) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j < N) pos[j] = (uint32_t)j;
+}
+
+template <int D, int N1>
+__global__ void coef_extract_kernel(int64_t N, int n1, const char *__restrict__ recs, double2 *__restrict__ c_out,
+                                    int32_t *__restrict__ cell_out) {
+  constexpr int RB = rec_bytes<D, N1, double2>();
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  const char *r = recs + j * (int64_t)RB;
+  const RecIdx<D> ri = *reinterpret_cast<const RecIdx<D> *>(r);
+  const double2 *c = reinterpret_cast<const double2 *>(r + rec_idx_bytes<D>());
+  for (int k = 0; k < D; ++k) {
+    cell_out[j * 2 * D + k] = ri.q[k];
+    cell_out[j * 2 * D + D + k] = ri.pc[k];
+  }
+  int nk = 1;
+  for (int k = 0; k < D; ++k) nk *= n1;
+  for (int K = 0; K < nk; ++K) {
+    double2 v = make_double2(1.0, 0.0);
+    int rem = K;
+    for (int k = D - 1; k >= 0; --k) {
+      const double2 ck = c[k * N1 + rem % n1];
+      rem /= n1;
+      v = make_double2(v.x * ck.x - v.y * ck.y, v.x * ck.y + v.y * ck.x);
+    }
+    c_out[j * nk + K] = v;
+  }
+}
+
+}  // namespace
+
+void launch_fggc_coefficients(const FggcArgs &a, double *c_out, int32_t *cell_out, Workspace &ws, hipStream_t s) {
+  const int d = a.g.d;
+  const int64_t N = a.pk->N;
+  if (N == 0) return;
+  const DimLsq &l0 = a.lsq[0];
+  const int N1 = n1_bucket(l0.n1);
+  const int rb = 16 * ((8 * d + 15) / 16) + d * N1 * 16;
+  char *base = (char *)ws.take(3 * sizeof(DimLsq) + 256 + (size_t)N * 4 + 256 + (size_t)N * rb);
+  DimLsq *dl = (DimLsq *)base;
+  uint32_t *pos = (uint32_t *)(base + align_up(3 * sizeof(DimLsq), 256));
+  char *recs = (char *)pos + align_up((size_t)N * 4, 256);
+  const DimLsq *dlsq = a.lsq_dev;
+  if (!dlsq) {
+    FGGC_HIP(hipMemcpyAsync(dl, a.lsq, d * sizeof(DimLsq), hipMemcpyHostToDevice, s));
+    dlsq = dl;
+  }
+  const dim3 g((unsigned)((N + 255) / 256)), b(256);
+  iota_kernel<<<g, b, 0, s>>>(pos, N);
+  FGGC_HIP(hipGetLastError());
+  CoefParams cp{};
+  cp.ns = 1;
+  cp.N = N;
+  cp.Q = a.pk->Q;
+  cp.P = a.pk->P;
+  cp.S = a.pk->S;
+  cp.a = a.pk->a;
+  cp.inv_2pi_eps = 1.0 / (kTwoPi * a.eps);
+  cp.scale = a.scale;
+  cp.lsq = dlsq;
+  for (int k = 0; k < 3; ++k) {
+    cp.Nq[k] = a.Nq[k];
+    cp.pmin[k] = 0;
+    cp.dq[k] = kTwoPi / (double)a.Nq[k];
+    cp.dp[k] = a.dp[k];
+  }
+  int cnp = 0;
+  for (int m = 0; m < l0.n1; ++m)
+    if (l0.dq[m] == l0.dq[0]) ++cnp;
+  const int cnq = l0.n1 / cnp;
+#define FGGC_COEF_ONE(DD, NN)                                                                                 \
+  {                                                                                                            \
+    if (NN == 4 && cnq == 2 && cnp == 2) fggc_coef_kernel<DD, NN, 2, 2, double2><<<g, b, 0, s>>>(cp, pos, recs); \
+    else if (NN == 8 && cnq == 4 && cnp == 2) fggc_coef_kernel<DD, NN, 4, 2, double2><<<g, b, 0, s>>>(cp, pos, recs); \
+    else if (NN == 8 && cnq == 2 && cnp == 4) fggc_coef_kernel<DD, NN, 2, 4, double2><<<g, b, 0, s>>>(cp, pos, recs); \
+    else if (NN == 16 && cnq == 4 && cnp == 4) fggc_coef_kernel<DD, NN, 4, 4, double2><<<g, b, 0, s>>>(cp, pos, recs); \
+    else fggc_coef_kernel<DD, NN, 0, 0, double2><<<g, b, 0, s>>>(cp, pos, recs);                                  \
+    FGGC_HIP(hipGetLastError());                                                                               \
+    coef_extract_kernel<DD, NN><<<g, b, 0, s>>>(N, l0.n1, recs, (double2 *)c_out, cell_out);                   \
+    FGGC_HIP(hipGetLastError());                                                                               \
+  }
+  if (d == 1) {
+    if (N1 == 4) FGGC_COEF_ONE(1, 4) else if (N1 == 8) FGGC_COEF_ONE(1, 8) else FGGC_COEF_ONE(1, 16)
+  } else if (d == 2) {
+    if (N1 == 4) FGGC_COEF_ONE(2, 4) else if (N1 == 8) FGGC_COEF_ONE(2, 8) else FGGC_COEF_ONE(2, 16)
+  } else {
+    if (N1 == 4) FGGC_COEF_ONE(3, 4) else if (N1 == 8) FGGC_COEF_ONE(3, 8)
+    else fail(FGGC_EUNSUPPORTED, "3D strategies need nq * np <= 8");
+  }
+#undef FGGC_COEF_ONE
+}
+
+size_t fggc_coefficients_workspace_bytes(const FggcArgs &a) {
+  const int d = a.g.d;
+  const int N1 = n1_bucket(a.lsq[0].n1);
+  const int rb = 16 * ((8 * d + 15) / 16) + d * N1 * 16;
+  return 3 * sizeof(DimLsq) + 256 + (size_t)a.pk->N * 4 + 256 + (size_t)a.pk->N * rb + 1024;
+}
+
+namespace {
 }  // namespace
 
 size_t fggc_workspace_bytes(const FggcArgs &a) { return fggc_layout(a).total + 1024; }
