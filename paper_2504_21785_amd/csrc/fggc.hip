@@ -1605,17 +1605,19 @@ struct Fused3Params {
   const double *gtab;  // [sn2][kmax - kmin + 1] band weights (band_table_kernel)
 };
 
-// Band weights of the last dimension for the fused finish, once per call:
-// gtab[l][t] = gamma_l(kmin + t) = sqrt(2 pi eps) / (2 pi) exp(-eps (k - p_l / eps)^2 / 2),
-// p_l = (slo + l) dp, zero outside the truncated band |k - p_l / eps| <= cK / sqrt(eps).
-__global__ void band_table_kernel(Fused3Params p, double *__restrict__ gtab) {
-  const int ng = (int)(p.kmax - p.kmin + 1);
+// Band weights of one dimension, once per call (the fused finish and the
+// dense passes): gtab[l][t] = gamma_l(kmin + t) =
+// sqrt(2 pi eps) / (2 pi) exp(-eps (k - p_l / eps)^2 / 2), p_l = (slo + l) dp,
+// zero outside the truncated band |k - p_l / eps| <= cK / sqrt(eps).
+__global__ void band_table_kernel(int64_t L, int64_t kmin, int64_t kmax, int64_t slo, double eps, double dp,
+                                  double cK, double *__restrict__ gtab) {
+  const int ng = (int)(kmax - kmin + 1);
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= p.sn[2] * ng) return;
+  if (e >= L * ng) return;
   const int64_t l = e / ng, t = e - l * ng;
-  const double cst = sqrt(kTwoPi * p.eps) / kTwoPi, cut = -0.5 * p.cK * p.cK * (1.0 + 1e-12);
-  const double dk = p.eps * (double)(p.kmin + t) - (double)(p.slo + l) * p.dp2;  // eps (k - p_l / eps)
-  const double ex = -dk * dk / (2.0 * p.eps);
+  const double cst = sqrt(kTwoPi * eps) / kTwoPi, cut = -0.5 * cK * cK * (1.0 + 1e-12);
+  const double dk = eps * (double)(kmin + t) - (double)(slo + l) * dp;  // eps (k - p_l / eps)
+  const double ex = -dk * dk / (2.0 * eps);
   gtab[e] = ex < cut ? 0.0 : cst * exp(ex);
 }
 
@@ -1785,6 +1787,94 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
   }
 }
 
+// A separable pass over a dense input (the passes after the first in three
+// dimensions, the last pass in two), the same contraction as
+// fft_contract_kernel: Y[o][a][k'][b] = sum_l sum_{kk = k' (mod M)}
+// gamma_l(kk) F_{o,l,a,b}[kk mod N].  A workgroup owns W consecutive b (one
+// 128-byte run of the input per (slice, n)) at one (o, a); for Lc slices at a
+// time it loads the W lines into LDS (as rows, padded for the register FFT),
+// transforms them with lds_fft2_rows and folds them through the band weights
+// gamma (a table per call) into FP64 sums, thread (group g, frequency t)
+// holding frequency t of lines g, g + G, ...  The sums go out through LDS, so
+// that the writes run along b as well.
+struct Contract2Params {
+  int64_t O, L, A, B, M;
+  int lgN, W, Lc, TPL;
+  int64_t kmin, kmax;    // union of the slices' bands
+  const double *gtab;    // [L][kmax - kmin + 1] band weights
+};
+
+template <typename T>
+__global__ __launch_bounds__(kFusedThreads) void fft_contract2_kernel(Contract2Params p, const T *__restrict__ X,
+                                                                      T *__restrict__ Y, const T *__restrict__ tw) {
+  using RR = decltype(T{}.x);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lgN = p.lgN, N = 1 << lgN, W = p.W, M = (int)p.M;
+  const int ng = (int)(p.kmax - p.kmin + 1), nact = min(M, ng);
+  const int bs = (int)blockDim.x, tid0 = (int)threadIdx.x;
+  const int rs = fft2_row_stride(lgN);
+  T *cl = reinterpret_cast<T *>(smem_raw);            // [Lc][W][rs]
+  T *stw = cl + (size_t)p.Lc * W * rs;                // [N]
+  double *gam = reinterpret_cast<double *>(stw + N);  // [Lc][ng]
+  for (int i = tid0; i < N; i += bs) stw[i] = tw[i];
+  const int64_t nbc = p.B / W;
+  const int64_t g = blockIdx.x, bc = g % nbc, oa = g / nbc;  // oa = o * A + a
+  const int64_t o = oa / p.A, a = oa % p.A, b0 = bc * W;
+  const int TPL = p.TPL, G = bs / TPL;
+  const int kmod = (int)(((p.kmin % M) + M) % M);
+  double accr[kFusedOut], acci[kFusedOut];
+#pragma unroll
+  for (int c = 0; c < kFusedOut; ++c) accr[c] = acci[c] = 0.0;
+  for (int l0 = 0; l0 < (int)p.L; l0 += p.Lc) {
+    const int lcn = min(p.Lc, (int)p.L - l0);
+    int tid = tid0;
+    asm volatile("" : "+v"(tid));
+    for (int e = tid; e < lcn * ng; e += bs) gam[e] = p.gtab[(int64_t)l0 * ng + e];
+    // rows (l, w) of N, loaded with w fastest (runs of W along b)
+    for (int e = tid; e < lcn * N * W; e += bs) {
+      const int w = e % W, n = (e / W) % N, l = e / (W * N);
+      cl[(l * W + w) * rs + n] = X[((((o * p.L + l0 + l) * p.A + a) << lgN) + n) * p.B + b0 + w];
+    }
+    __syncthreads();
+    lds_fft2_rows<T>(cl, lgN, lcn * W, rs, stw, tid, bs);
+    const int t = tid & (TPL - 1), lg0 = tid / TPL;
+    if (t < nact) {
+      for (int64_t kk = p.kmin + t; kk <= p.kmax; kk += M) {
+        const T *fq = cl + (size_t)lg0 * rs + (int)(kk & (N - 1));
+        const double *gb = gam + (kk - p.kmin);
+        for (int l = 0; l < lcn; ++l) {
+          const double gv = gb[l * ng];
+#pragma unroll
+          for (int c = 0; c < kFusedOut; ++c) {
+            if (lg0 + c * G >= W) break;
+            const T v = fq[((size_t)l * W + c * G) * rs];
+            accr[c] = fma(gv, (double)v.x, accr[c]);
+            acci[c] = fma(gv, (double)v.y, acci[c]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // the sums into LDS as [k'][w], then out along b
+  const int t = tid0 & (TPL - 1), lg0 = tid0 / TPL;
+  T *ob = cl;  // [M][W]
+  for (int tt = t; tt < M; tt += TPL) {
+    const int kp = (kmod + tt) % M;
+#pragma unroll
+    for (int c = 0; c < kFusedOut; ++c) {
+      const int w = lg0 + c * G;
+      if (w >= W) break;
+      ob[kp * W + w] = tt < nact ? T{(RR)accr[c], (RR)acci[c]} : T{0, 0};
+    }
+  }
+  __syncthreads();
+  for (int e = tid0; e < M * W; e += bs) {
+    const int w = e % W, kp = e / W;
+    Y[(oa * p.M + kp) * p.B + b0 + w] = ob[e];
+  }
+}
+
 // One dimension: the aggregate's stencil writes each slice's q-spectrum
 // directly (fggc_stencil_fft1_kernel, one slice per workgroup in LDS).
 bool fft1_fused(const FggcArgs &a) { return a.g.d == 1 && a.Nq[0] <= 4096; }
@@ -1802,7 +1892,7 @@ struct FggcLayout {
   int64_t ncells, nslices, npts, nbins, nslots, tiles, ntq[3], tile[3], npc[3], pmin[3], S[3], nsw[3];
   int64_t nb[3];
   int mindp, maxdp, mindq, maxdq;
-  size_t off_gam;  // fused finish: band weights gamma_l2(k) of every slice l2 [sn2][ng] (FP64)
+  size_t off_gam[3];  // band weights gamma_l(k) per dimension [sn_k][ng_k] (FP64; 0: not used)
   size_t off_lsq, off_keys, off_pos, off_sort, off_start, off_recs, off_agg, off_cells, off_occ,
       off_spec, off_x1, off_x2, total;
 };
@@ -1881,6 +1971,58 @@ bool plan_fused3(const FggcArgs &a, FggcLayout &L, int nq, int np) {
   L.fshm = shm_of(Lc);
   return true;
 }
+
+// The dense register-FFT pass (fft_contract2_kernel) over dimension k, when
+// it applies: a pass that reads a dense input (not the fused finish's, not
+// two dimensions' first pass over the cells with its empty-tile map), a
+// q-mesh of 8 to 256 points, and its lines, outputs and LDS within budget.
+struct Contract2Plan {
+  bool ok = false;
+  int W = 0, Lc = 0, TPL = 0;
+  size_t shm = 0;
+};
+
+Contract2Plan contract2_plan(const FggcArgs &a, int k, bool fused3) {
+  Contract2Plan c;
+  const int d = a.g.d;
+  if (d < 2 || k >= d || (d == 2 && k == 1) || (fused3 && k == 2)) return c;
+  const int64_t N = a.Nq[k];
+  if (N < 8 || N > 256 || (N & (N - 1))) return c;
+  int lg = 0;
+  while (((int64_t)1 << lg) < N) ++lg;
+  int64_t B = 1;
+  for (int j = k + 1; j < d; ++j) B *= a.g.n[j];
+  int W = 16;
+  while (W > 1 && B % W) W /= 2;
+  int64_t kmin, kmax;
+  band_range(a, k, kmin, kmax);
+  const int64_t ng = kmax - kmin + 1, M = a.g.n[k], nact = std::min<int64_t>(M, ng);
+  int64_t TPL = 1;
+  while (TPL < nact) TPL *= 2;
+  const int threads = kFusedThreads;
+  if (TPL > threads) return c;
+  const int64_t G = threads / TPL;
+  if ((W + G - 1) / G > kFusedOut) return c;
+  const size_t es = a.precision == FGGC_FP64 ? 16 : 8;
+  const int64_t rs = fft2_row_stride(lg), N1 = (int64_t)1 << ((lg + 1) / 2), N2 = (int64_t)1 << (lg / 2);
+  const int64_t maxrows = std::min<int64_t>(threads / N2, 2 * threads / N1);
+  int Lc = (int)std::min<int64_t>(a.sn[k], std::max<int64_t>(1, maxrows / W));
+  auto shm_of = [&](int lc) {
+    // the lines double as the output staging [M][W]
+    const size_t lines = std::max<size_t>((size_t)lc * W * rs, (size_t)M * W);
+    return lines * es + (size_t)N * es + (size_t)lc * ng * 8;
+  };
+  while (Lc > 1 && shm_of(Lc) > 80 * 1024) --Lc;
+  if ((int64_t)Lc * W > maxrows || shm_of(Lc) > kFusedMaxLds) return c;
+  c.ok = true;
+  c.W = W;
+  c.Lc = Lc;
+  c.TPL = (int)TPL;
+  c.shm = shm_of(Lc);
+  return c;
+}
+
+bool contract2_ok(const FggcArgs &a, const FggcLayout &L, int k) { return contract2_plan(a, k, L.fused3).ok; }
 
 FggcLayout fggc_layout(const FggcArgs &a, bool allow_fused = true) {
   FggcLayout L{};
@@ -1988,11 +2130,16 @@ FggcLayout fggc_layout(const FggcArgs &a, bool allow_fused = true) {
     L.off_x1 = put(pass_out(d - 1) * es);
     if (d == 3) L.off_x2 = put(pass_out(1) * es);
   }
-  L.off_gam = 0;
-  if (L.fused3) {
-    int64_t kmin, kmax;
-    band_range(a, 2, kmin, kmax);
-    L.off_gam = put((size_t)a.sn[2] * (size_t)(kmax - kmin + 1) * 8);
+  // band tables: the fused finish's last dimension, and every dimension a
+  // dense register-FFT pass contracts
+  for (int k = 0; k < 3; ++k) {
+    L.off_gam[k] = 0;
+    const bool fusedk = L.fused3 && k == 2, densek = d >= 2 && contract2_ok(a, L, k);
+    if (k < d && (fusedk || densek)) {
+      int64_t kmin, kmax;
+      band_range(a, k, kmin, kmax);
+      L.off_gam[k] = put((size_t)a.sn[k] * (size_t)(kmax - kmin + 1) * 8);
+    }
   }
   L.total = o;
   return L;
@@ -2353,6 +2500,62 @@ void launch_contract(const FggcArgs &a, const FggcLayout &L, int k, const T *in,
   FGGC_HIP(hipGetLastError());
 }
 
+void launch_band_table(const FggcArgs &a, int k, const MacParams &m, double *gtab, hipStream_t s) {
+  const int64_t nt = a.sn[k] * (m.kmax[k] - m.kmin[k] + 1);
+  band_table_kernel<<<dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s>>>(a.sn[k], m.kmin[k], m.kmax[k], a.slo[k],
+                                                                            a.eps, a.dp[k], a.cK, gtab);
+  FGGC_HIP(hipGetLastError());
+}
+
+bool g_c2_attr = false;
+std::mutex g_c2_mu;
+
+// One dense separable pass over dimension k on the register FFT (see
+// fft_contract2_kernel); the caller has checked contract2_plan(...).ok.
+template <typename T>
+void launch_contract2(const FggcArgs &a, const FggcLayout &L, int k, char *base, const T *in, T *out,
+                      const MacParams &m, hipStream_t s) {
+  {
+    std::lock_guard<std::mutex> lk(g_c2_mu);
+    if (!g_c2_attr) {
+      FGGC_HIP(hipFuncSetAttribute((const void *)fft_contract2_kernel<float2>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedMaxLds));
+      FGGC_HIP(hipFuncSetAttribute((const void *)fft_contract2_kernel<double2>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedMaxLds));
+      g_c2_attr = true;
+    }
+  }
+  const Contract2Plan c = contract2_plan(a, k, L.fused3);
+  if (!c.ok) fail(FGGC_EDEVICE, "internal: dense pass not planned");
+  const int d = a.g.d;
+  Contract2Params p{};
+  p.O = 1;
+  p.A = 1;
+  p.B = 1;
+  for (int j = 0; j < k; ++j) {
+    p.O *= a.sn[j];
+    p.A *= a.Nq[j];
+  }
+  for (int j = k + 1; j < d; ++j) p.B *= a.g.n[j];
+  p.L = a.sn[k];
+  p.M = a.g.n[k];
+  p.lgN = 0;
+  while (((int64_t)1 << p.lgN) < a.Nq[k]) ++p.lgN;
+  p.W = c.W;
+  p.Lc = c.Lc;
+  p.TPL = c.TPL;
+  p.kmin = m.kmin[k];
+  p.kmax = m.kmax[k];
+  double *gtab = (double *)(base + L.off_gam[k]);
+  p.gtab = gtab;
+  launch_band_table(a, k, m, gtab, s);
+  const int64_t blocks = p.O * p.A * (p.B / p.W);
+  if (blocks >= ((int64_t)1 << 31)) fail(FGGC_EUNSUPPORTED, "too many workgroups for the separable finish");
+  const T *tw = (const T *)fft_twiddles(a.Nq[k], a.precision);
+  fft_contract2_kernel<T><<<dim3((unsigned)blocks), dim3(kFusedThreads), c.shm, s>>>(p, in, out, tw);
+  FGGC_HIP(hipGetLastError());
+}
+
 bool g_fused_attr = false;
 std::mutex g_fused_mu;
 
@@ -2403,12 +2606,8 @@ void launch_fused3(const FggcArgs &a, const FggcLayout &L, char *base, const Mac
   p.eps = a.eps;
   p.dp2 = a.dp[2];
   p.cK = a.cK;
-  p.gtab = (const double *)(base + L.off_gam);
-  {
-    const int64_t nt = a.sn[2] * (p.kmax - p.kmin + 1);
-    band_table_kernel<<<dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s>>>(p, (double *)(base + L.off_gam));
-    FGGC_HIP(hipGetLastError());
-  }
+  p.gtab = (const double *)(base + L.off_gam[2]);
+  launch_band_table(a, 2, m, (double *)(base + L.off_gam[2]), s);
   const int64_t blocks = a.sn[0] * a.sn[1] * L.ntq[0] * L.ntq[1];
   const T *tw = (const T *)fft_twiddles(a.Nq[2], a.precision);
   const dim3 g((unsigned)blocks), b((unsigned)L.fThreads);
@@ -2428,7 +2627,6 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, 
   if (d == 1 && !fft1_fused(a)) launch_fft(d, a.Nq, L.nslices, -1, prec, cells, ws, s, a.prof, "fggc_fft_q");
   // F6: band multiply-accumulate into the grid spectrum (gamma evaluated in place)
   MacParams m{};
-  const double se = std::sqrt(a.eps);
   for (int k = 0; k < 3; ++k) {
     m.M[k] = k < d ? a.g.n[k] : 1;
     m.Nq[k] = k < d ? a.Nq[k] : 1;
@@ -2454,7 +2652,8 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, 
     const T *in = L.fused3 ? x1 : cells;
     for (int k = L.fused3 ? d - 2 : d - 1; k >= 0; --k) {
       T *out = k == 0 ? U : (k == d - 1 ? x1 : x2);
-      launch_contract<T, R>(a, L, k, in, out, k == d - 1 ? occ : nullptr, m, s);
+      if (contract2_ok(a, L, k)) launch_contract2<T>(a, L, k, base, in, out, m, s);
+      else launch_contract<T, R>(a, L, k, in, out, k == d - 1 ? occ : nullptr, m, s);
       in = out;
     }
   } else {
