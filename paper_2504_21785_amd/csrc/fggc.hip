@@ -1587,10 +1587,20 @@ __global__ __launch_bounds__(kContractThreads) void fft_contract_kernel(Contract
 // Y[l0][l1][q0][q1][m2] (zeros at frequencies no band reaches).  Packets are
 // binned by (p-cell 0, p-cell 1, q-tile, p-cell 2), so the records that reach
 // a chunk are one contiguous run per (p-cell 0, p-cell 1).
+// arr[i] for a run-time i, by selects (the array stays in registers)
+template <int K, typename V> __device__ __forceinline__ V pick(const V (&arr)[K], int i) {
+  V v = arr[0];
+#pragma unroll
+  for (int k = 1; k < K; ++k)
+    if (i == k) v = arr[k];
+  return v;
+}
+
 constexpr int kFusedThreads = 512;
 constexpr int kFusedOut = 8;   // outputs per thread
 constexpr int kFusedRuns = 16; // (p-cell 0, p-cell 1) pairs that reach a slice pair: (p-shift span + 1)^2
 constexpr size_t kFusedMaxLds = 144 * 1024;  // dynamic LDS (the kernel's static LDS comes on top)
+constexpr int kFusedWaves = kFusedThreads / 64;
 
 struct Fused3Params {
   const char *recs;
@@ -1661,9 +1671,19 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
   double accr[kFusedOut], acci[kFusedOut];
 #pragma unroll
   for (int c = 0; c < kFusedOut; ++c) accr[c] = acci[c] = 0.0;
-  // the runs of records a chunk reads: one per (p-cell 0, p-cell 1) that
-  // reaches (l0, l1), each a contiguous range of bins over p-cell 2
-  __shared__ int64_t s_r0[kFusedRuns], s_n[kFusedRuns];
+  // Accumulation, one slice per wave: wave w adds the contributions to slice
+  // l2 = c0 + w, read from the records whose p-cell 2 reaches it -- per
+  // (p-cell 0, p-cell 1) that reaches (l0, l1), one contiguous run of bins
+  // over p-cell 2.  Waves write disjoint rows, so the cells are updated with
+  // plain LDS read-modify-writes.  Inside a wave, two lanes write the same
+  // cell in one instruction only if their records share the q-cell (the
+  // instruction fixes the q-shifts; the slice is the wave's); such lanes are
+  // taken in turn, by claiming a slot of a hash of the q-cell in a per-wave
+  // table (the last writer of a slot goes first).  A wave issues its LDS operations in order, so
+  // updates of one cell by different instructions are ordered too.
+  constexpr int kClaim = 256;
+  __shared__ int64_t s_r0[kFusedWaves][kFusedRuns], s_n[kFusedWaves][kFusedRuns];
+  __shared__ int s_claim[kFusedWaves][kClaim];
   const int n1r = (int)(a1hi - a1lo + 1), nruns = (int)(a0hi - a0lo + 1) * n1r;
   for (int c0 = 0; c0 < (int)p.sn[2]; c0 += p.Lc) {
     const int lcn = min(p.Lc, (int)p.sn[2] - c0);
@@ -1671,77 +1691,113 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
     // chunk where they are used, not hoisted out of the loop into registers
     int tid = tid0;
     asm volatile("" : "+v"(tid));
-    // packets of p-cells (a0, a1, a2), a2 in [c0 - span, c0 + lcn - 1]: the
-    // runs' bounds are loaded first, so that their latency overlaps the
-    // clearing of the lines and the band table
-    const int64_t a2lo = max<int64_t>(0, c0 - span), a2hi = min<int64_t>(npc2 - 1, c0 + lcn - 1);
-    if (tid < nruns) {
-      const int64_t a0 = a0lo + tid / n1r, a1 = a1lo + tid % n1r;
+    const int wv = tid >> 6, lane = tid & 63;
+    // the runs' bounds of every wave's slice, loaded first, so that their
+    // latency overlaps the clearing of the lines and the band table
+    if (lane < nruns && wv < lcn) {
+      const int64_t l2 = c0 + wv;
+      const int64_t a2lo = max<int64_t>(0, l2 - span), a2hi = min<int64_t>(npc2 - 1, l2);
+      const int64_t a0 = a0lo + lane / n1r, a1 = a1lo + lane % n1r;
       const int64_t kb = ((a0 * p.npc[1] + a1) * nqt + tq) * npc2;
       const int64_t r0 = a2lo <= a2hi ? p.start[kb + a2lo] : 0, r1 = a2lo <= a2hi ? p.start[kb + a2hi + 1] : 0;
-      s_r0[tid] = r0;
-      s_n[tid] = r1 - r0;
+      s_r0[wv][lane] = r0;
+      s_n[wv][lane] = r1 - r0;
     }
     for (int e = tid; e < lcn * ng; e += bs) gam[e] = p.gtab[(int64_t)c0 * ng + e];
     for (int e = tid; e < lcn * P * rs; e += bs) cl[e] = T{0, 0};
     __syncthreads();
-    // the chunk's records as one index space over the runs, one per thread
-    int64_t total = 0;
-    for (int x = 0; x < nruns; ++x) total += s_n[x];
-    for (int64_t i = tid; i < total; i += bs) {
-      int run = 0;
-      int64_t off = i;
-      while (off >= s_n[run]) off -= s_n[run++];
-      {
-        {
-          const int64_t r = s_r0[run] + off;
-          uint4 raw[NV];
-          const uint4 *src = reinterpret_cast<const uint4 *>(p.recs + r * (int64_t)RB);
+    if (wv < lcn) {
+      const int l2 = c0 + wv;
+      int64_t total = 0;
+      for (int x = 0; x < nruns; ++x) total += s_n[wv][x];
+      volatile int *claim = s_claim[wv];
+      for (int64_t base = 0; base < total; base += 64) {
+        const int64_t i = base + lane;
+        bool todo = i < total;
+        const char *rec = nullptr;
+        if (todo) {
+          int run = 0;
+          int64_t off = i;
+          while (off >= s_n[wv][run]) off -= s_n[wv][run++];
+          rec = p.recs + (s_r0[wv][run] + off) * (int64_t)RB;
+        }
+        // records of up to 256 bytes are loaded whole (one round trip);
+        // larger ones (FP64 with four shifts) index first, then only the
+        // coefficients the slice takes, so as not to hold the whole record
+        constexpr bool kWhole = NV <= 16;
+        uint4 raw[kWhole ? NV : 2];
 #pragma unroll
-          for (int v = 0; v < NV; ++v) raw[v] = src[v];
-          const RecIdx<3> ri = *reinterpret_cast<const RecIdx<3> *>(raw);
+        for (int v = 0; v < (kWhole ? NV : 2); ++v)
+          raw[v] = todo ? reinterpret_cast<const uint4 *>(rec)[v] : make_uint4(0, 0, 0, 0);
+        const RecIdx<3> ri = *reinterpret_cast<const RecIdx<3> *>(raw);
+        int b0 = -1, b1 = -1, b2 = -1;
+#pragma unroll
+        for (int b = 0; b < NP; ++b) {
+          if ((int64_t)ri.pc[0] + p.dp[b] - p.mindp == l0) b0 = b;
+          if ((int64_t)ri.pc[1] + p.dp[b] - p.mindp == l1) b1 = b;
+          if (ri.pc[2] + p.dp[b] - p.mindp == l2) b2 = b;
+        }
+        todo = todo && b0 >= 0 && b1 >= 0 && b2 >= 0;
+        int la0[NQ], la1[NQ], q2[NQ];
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) {
+          const int v0 = ((ri.q[0] + p.dq[a]) & msk0) - q00, v1 = ((ri.q[1] + p.dq[a]) & msk1) - q10;
+          la0[a] = v0 >= 0 && v0 < T0 ? v0 : -1;
+          la1[a] = v1 >= 0 && v1 < T1 ? v1 : -1;
+          q2[a] = (ri.q[2] + p.dq[a]) & msk2;
+        }
+        // the coefficients this slice takes: dims 0 and 1 at (b0, b1), dim 2 at b2
+        T u0[NQ], u1[NQ], u2[NQ];
+        if constexpr (kWhole) {
           const T *c = reinterpret_cast<const T *>(reinterpret_cast<const char *>(raw) + rec_idx_bytes<3>());
-          int b0 = -1, b1 = -1;
-#pragma unroll
-          for (int b = 0; b < NP; ++b) {
-            if ((int64_t)ri.pc[0] + p.dp[b] - p.mindp == l0) b0 = b;
-            if ((int64_t)ri.pc[1] + p.dp[b] - p.mindp == l1) b1 = b;
-          }
-          if (b0 < 0 || b1 < 0) continue;
-          int la0[NQ], la1[NQ], q2[NQ];
 #pragma unroll
           for (int a = 0; a < NQ; ++a) {
-            const int v0 = ((ri.q[0] + p.dq[a]) & msk0) - q00, v1 = ((ri.q[1] + p.dq[a]) & msk1) - q10;
-            la0[a] = v0 >= 0 && v0 < T0 ? v0 : -1;
-            la1[a] = v1 >= 0 && v1 < T1 ? v1 : -1;
-            q2[a] = (ri.q[2] + p.dq[a]) & msk2;
+            u0[a] = u1[a] = u2[a] = T{0, 0};
+#pragma unroll
+            for (int b = 0; b < NP; ++b) {
+              if (b == b0) u0[a] = c[a * NP + b];
+              if (b == b1) u1[a] = c[N1 + a * NP + b];
+              if (b == b2) u2[a] = c[2 * N1 + a * NP + b];
+            }
           }
+        } else {
+          const T *c = reinterpret_cast<const T *>(rec + rec_idx_bytes<3>());
 #pragma unroll
-          for (int b2 = 0; b2 < NP; ++b2) {
-            const int l2 = ri.pc[2] + p.dp[b2] - p.mindp - c0;
-            if (l2 < 0 || l2 >= lcn) continue;
-#pragma unroll
+          for (int a = 0; a < NQ; ++a) {
+            u0[a] = todo ? c[a * NP + b0] : T{0, 0};
+            u1[a] = todo ? c[N1 + a * NP + b1] : T{0, 0};
+            u2[a] = todo ? c[2 * N1 + a * NP + b2] : T{0, 0};
+          }
+        }
+        const uint32_t h = ((uint32_t)ri.q[0] * 0x9E3779B1u + (uint32_t)ri.q[1] * 0x85EBCA77u +
+                            (uint32_t)ri.q[2] * 0xC2B2AE3Du) >> 24;
+        T *rows = cl + (size_t)wv * P * rs;
+        while (__ballot(todo)) {
+          if (todo) claim[h] = lane;
+          const bool win = todo && claim[h] == lane;
+          if (win) {
+            todo = false;
+            // two q-shifts: every contribution unrolled; four: the first
+            // dimension's shift in a loop (the 64-fold unrolling would not fit
+            // the registers), its values picked without indexing registers
+#pragma unroll(NQ == 2 ? NQ : 1)
             for (int a0i = 0; a0i < NQ; ++a0i) {
-              if (la0[a0i] < 0) continue;
-              // b0 and b1 are not compile-time: read the coefficient through a select
-              T u{0, 0}, w{0, 0};
-#pragma unroll
-              for (int b = 0; b < NP; ++b)
-                if (b == b0) u = c[a0i * NP + b];
+              const int la0v = pick<NQ>(la0, a0i);
+              if (la0v < 0) continue;
+              const T u0v = pick<NQ>(u0, a0i);
 #pragma unroll
               for (int a1i = 0; a1i < NQ; ++a1i) {
                 if (la1[a1i] < 0) continue;
-#pragma unroll
-                for (int b = 0; b < NP; ++b)
-                  if (b == b1) w = c[N1 + a1i * NP + b];
-                const T uw = T{u.x * w.x - u.y * w.y, u.x * w.y + u.y * w.x};
-                const int line = (l2 * P + la0[a0i] * T1 + la1[a1i]) * rs;
+                const T uw = cmul(u0v, u1[a1i]);
+                T *line = rows + (la0v * T1 + la1[a1i]) * rs;
 #pragma unroll
                 for (int a2i = 0; a2i < NQ; ++a2i) {
-                  const T z = c[2 * N1 + a2i * NP + b2];
-                  RR *cell = &cl[line + q2[a2i]].x;
-                  atomicAdd(cell, uw.x * z.x - uw.y * z.y);
-                  atomicAdd(cell + 1, uw.x * z.y + uw.y * z.x);
+                  const T z = cmul(uw, u2[a2i]);
+                  T o = line[q2[a2i]];
+                  o.x += z.x;
+                  o.y += z.y;
+                  line[q2[a2i]] = o;
+                  asm volatile("" ::: "memory");
                 }
               }
             }
@@ -1830,10 +1886,27 @@ __global__ __launch_bounds__(kFusedThreads) void fft_contract2_kernel(Contract2P
     int tid = tid0;
     asm volatile("" : "+v"(tid));
     for (int e = tid; e < lcn * ng; e += bs) gam[e] = p.gtab[(int64_t)l0 * ng + e];
-    // rows (l, w) of N, loaded with w fastest (runs of W along b)
-    for (int e = tid; e < lcn * N * W; e += bs) {
-      const int w = e % W, n = (e / W) % N, l = e / (W * N);
-      cl[(l * W + w) * rs + n] = X[((((o * p.L + l0 + l) * p.A + a) << lgN) + n) * p.B + b0 + w];
+    // rows (l, w) of N, loaded with w fastest (runs of W along b), eight
+    // loads in flight per thread before their LDS stores
+    const int tot = lcn * N * W;
+    for (int e0 = tid; e0 < tot; e0 += 8 * bs) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * bs;
+        if (e < tot) {
+          const int w = e % W, n = (e / W) % N, l = e / (W * N);
+          v[u] = X[((((o * p.L + l0 + l) * p.A + a) << lgN) + n) * p.B + b0 + w];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * bs;
+        if (e < tot) {
+          const int w = e % W, n = (e / W) % N, l = e / (W * N);
+          cl[(l * W + w) * rs + n] = v[u];
+        }
+      }
     }
     __syncthreads();
     lds_fft2_rows<T>(cl, lgN, lcn * W, rs, stw, tid, bs);
@@ -1952,7 +2025,8 @@ bool plan_fused3(const FggcArgs &a, FggcLayout &L, int nq, int np) {
   const int64_t rs = fft2_row_stride(lg);
   const int64_t N1 = (int64_t)1 << ((lg + 1) / 2), N2 = (int64_t)1 << (lg / 2);
   const int64_t maxrows = std::min<int64_t>(threads / N2, 2 * threads / N1);
-  int Lc = (int)std::min<int64_t>(a.sn[2], std::max<int64_t>(1, maxrows / P));
+  // at most one slice per wave (the accumulation gives each wave a slice)
+  int Lc = (int)std::min<int64_t>(std::min<int64_t>(a.sn[2], threads / 64), std::max<int64_t>(1, maxrows / P));
   auto shm_of = [&](int lc) { return (size_t)lc * P * rs * es + (size_t)N * es + (size_t)lc * ng * 8; };
   // LDS for five 256-thread (two 512-thread) workgroups per CU, the most the
   // kernel's registers allow
