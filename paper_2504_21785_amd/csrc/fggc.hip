@@ -1600,7 +1600,8 @@ constexpr int kFusedThreads = 512;
 constexpr int kFusedOut = 8;   // outputs per thread
 constexpr int kFusedRuns = 16; // (p-cell 0, p-cell 1) pairs that reach a slice pair: (p-shift span + 1)^2
 constexpr size_t kFusedMaxLds = 144 * 1024;  // dynamic LDS (the kernel's static LDS comes on top)
-constexpr int kFusedWaves = kFusedThreads / 64;
+constexpr int kFusedClaimBits = 8;
+constexpr int kFusedClaim = 1 << kFusedClaimBits;  // claim slots per wave
 
 struct Fused3Params {
   const char *recs;
@@ -1649,7 +1650,11 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
   const int rs = fft2_row_stride(lgN);               // row stride of the lines
   T *cl = reinterpret_cast<T *>(smem_raw);            // [Lc][P][rs] the chunk's lines
   T *stw = cl + (size_t)p.Lc * P * rs;                // [N] twiddles
-  double *gam = reinterpret_cast<double *>(stw + N);  // [Lc][ng] band weights
+  const int nw = (int)blockDim.x >> 6;
+  int64_t *s_r0 = reinterpret_cast<int64_t *>(stw + N);  // [waves][kFusedRuns] runs of records
+  int64_t *s_n = s_r0 + nw * kFusedRuns;
+  RR *gam = reinterpret_cast<RR *>(s_n + nw * kFusedRuns);  // [Lc][ng] band weights, working precision
+  int *s_claim = reinterpret_cast<int *>(gam + p.Lc * ng);  // [waves][kFusedClaim]
   for (int i = tid0; i < N; i += bs) stw[i] = tw[i];
   // workgroup -> (q-tile, l0, l1); workgroups run on the eight XCDs in turn,
   // and each XCD takes a contiguous range of the work, so that the slice pairs
@@ -1681,9 +1686,6 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
   // taken in turn, by claiming a slot of a hash of the q-cell in a per-wave
   // table (the last writer of a slot goes first).  A wave issues its LDS operations in order, so
   // updates of one cell by different instructions are ordered too.
-  constexpr int kClaim = 256;
-  __shared__ int64_t s_r0[kFusedWaves][kFusedRuns], s_n[kFusedWaves][kFusedRuns];
-  __shared__ int s_claim[kFusedWaves][kClaim];
   const int n1r = (int)(a1hi - a1lo + 1), nruns = (int)(a0hi - a0lo + 1) * n1r;
   for (int c0 = 0; c0 < (int)p.sn[2]; c0 += p.Lc) {
     const int lcn = min(p.Lc, (int)p.sn[2] - c0);
@@ -1700,17 +1702,18 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
       const int64_t a0 = a0lo + lane / n1r, a1 = a1lo + lane % n1r;
       const int64_t kb = ((a0 * p.npc[1] + a1) * nqt + tq) * npc2;
       const int64_t r0 = a2lo <= a2hi ? p.start[kb + a2lo] : 0, r1 = a2lo <= a2hi ? p.start[kb + a2hi + 1] : 0;
-      s_r0[wv][lane] = r0;
-      s_n[wv][lane] = r1 - r0;
+      s_r0[wv * kFusedRuns + lane] = r0;
+      s_n[wv * kFusedRuns + lane] = r1 - r0;
     }
-    for (int e = tid; e < lcn * ng; e += bs) gam[e] = p.gtab[(int64_t)c0 * ng + e];
+    for (int e = tid; e < lcn * ng; e += bs) gam[e] = (RR)p.gtab[(int64_t)c0 * ng + e];
     for (int e = tid; e < lcn * P * rs; e += bs) cl[e] = T{0, 0};
     __syncthreads();
     if (wv < lcn) {
       const int l2 = c0 + wv;
       int64_t total = 0;
-      for (int x = 0; x < nruns; ++x) total += s_n[wv][x];
-      volatile int *claim = s_claim[wv];
+      const int64_t *wr0 = s_r0 + wv * kFusedRuns, *wn = s_n + wv * kFusedRuns;
+      for (int x = 0; x < nruns; ++x) total += wn[x];
+      volatile int *claim = s_claim + wv * kFusedClaim;
       for (int64_t base = 0; base < total; base += 64) {
         const int64_t i = base + lane;
         bool todo = i < total;
@@ -1718,8 +1721,8 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
         if (todo) {
           int run = 0;
           int64_t off = i;
-          while (off >= s_n[wv][run]) off -= s_n[wv][run++];
-          rec = p.recs + (s_r0[wv][run] + off) * (int64_t)RB;
+          while (off >= wn[run]) off -= wn[run++];
+          rec = p.recs + (wr0[run] + off) * (int64_t)RB;
         }
         // records of up to 256 bytes are loaded whole (one round trip);
         // larger ones (FP64 with four shifts) index first, then only the
@@ -1770,7 +1773,7 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
           }
         }
         const uint32_t h = ((uint32_t)ri.q[0] * 0x9E3779B1u + (uint32_t)ri.q[1] * 0x85EBCA77u +
-                            (uint32_t)ri.q[2] * 0xC2B2AE3Du) >> 24;
+                            (uint32_t)ri.q[2] * 0xC2B2AE3Du) >> (32 - kFusedClaimBits);
         T *rows = cl + (size_t)wv * P * rs;
         while (__ballot(todo)) {
           if (todo) claim[h] = lane;
@@ -1813,9 +1816,9 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
     if (t < nact) {
       for (int64_t kk = p.kmin + t; kk <= p.kmax; kk += M) {
         const T *fq = cl + (size_t)lg0 * rs + (int)(kk & msk2);
-        const double *gb = gam + (kk - p.kmin);
+        const RR *gb = gam + (kk - p.kmin);
         for (int l = 0; l < lcn; ++l) {
-          const double gv = gb[l * ng];
+          const double gv = (double)gb[l * ng];
 #pragma unroll
           for (int c = 0; c < kFusedOut; ++c) {
             if (lg0 + c * G >= P) break;
@@ -2027,10 +2030,18 @@ bool plan_fused3(const FggcArgs &a, FggcLayout &L, int nq, int np) {
   const int64_t maxrows = std::min<int64_t>(threads / N2, 2 * threads / N1);
   // at most one slice per wave (the accumulation gives each wave a slice)
   int Lc = (int)std::min<int64_t>(std::min<int64_t>(a.sn[2], threads / 64), std::max<int64_t>(1, maxrows / P));
-  auto shm_of = [&](int lc) { return (size_t)lc * P * rs * es + (size_t)N * es + (size_t)lc * ng * 8; };
+  // lines, twiddles, runs, the chunk's band weights (in the working
+  // precision) and the claim tables
+  const size_t waves = threads / 64;
+  auto shm_of = [&](int lc) {
+    return (size_t)lc * P * rs * es + (size_t)N * es + waves * kFusedRuns * 16 + (size_t)lc * ng * (es / 2) +
+           waves * kFusedClaim * 4;
+  };
   // LDS for five 256-thread (two 512-thread) workgroups per CU, the most the
-  // kernel's registers allow
-  const size_t budget = threads == 256 ? 32 * 1024 - 512 : 80 * 1024;
+  // registers allow: more resident workgroups beat fuller lanes in the
+  // transforms (measured: chunks of 2, 3 and 4 slices, 22.7, 23.8 and 24.9 ms
+  // on the 3D workload)
+  const size_t budget = threads == 256 ? 32 * 1024 : 80 * 1024;
   while (Lc > 1 && shm_of(Lc) > budget) --Lc;
   if ((int64_t)Lc * P > maxrows || shm_of(Lc) > kFusedMaxLds) return false;
   const int64_t blocks = a.sn[0] * a.sn[1] * (a.Nq[0] / T0) * (a.Nq[1] / T1);
