@@ -291,6 +291,27 @@ int fggc_propagate(fggc_ctx *ctx, int32_t d, int64_t N, double *Q, double *P, do
                    double *jac, const fggc_potential *V, double dt, int64_t nsteps, void *stream);
 
 /*
+ * The least-squares coefficients of the FGGC correction, per packet, as the
+ * reconstruction's coefficient kernel computes them (Sec. 2.2-2.3: the
+ * int/frac split (3.6)-(3.7), right-hand side (3.23), the solve against the
+ * Gram matrix (3.22) through its eigenpairs, conjugation, shift (3.13),
+ * Kronecker product over dimensions), in FP64:
+ *   c_out[j][K] = scale * a_j exp(i S_j / eps) c_K(Q_j, P_j), K = (k_0, .., k_{d-1})
+ *   row-major, each k over the strategy's nq * np one-dimensional basis in
+ *   the order q-shift major, p-shift minor ([N][(nq np)^d] complex128);
+ *   cell_out[j][0][k] = the packet's q-cell index (floor(Q/dq) + Nq/2) mod Nq
+ *   and cell_out[j][1][k] = its p-cell floor(P/dp), per dimension ([N][2][d]).
+ * With a = 1 and S = 0 these are the c^(k) of the paper's least-squares
+ * approximation of G(x; Q, P) by its neighbouring on-grid packets (the
+ * coefficient maps of Sec. 2.2 and the E_LSA of Sec. 3.1 follow from them).
+ * Packets and outputs are device memory; the call synchronises `stream`
+ * once (the packet check).  Errors: FGGC_EINVAL as fggc_reconstruct;
+ * FGGC_EUNSUPPORTED for 3D shift sets above 8.
+ */
+int fggc_coefficients(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_strategy *st, double scale,
+                      double *c_out, int32_t *cell_out, void *stream);
+
+/*
  * Multi-step FGGC (Sec. 3.2, Alg. 3): the bookkeeping of the learned map on
  * the device.  A fixed mesh of Nm phase-space points (q, p) is decomposed at
  * the start of every run (fggc_decompose / fggc_decompose_mesh give A0);

@@ -9,6 +9,7 @@ function follows.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -172,6 +173,55 @@ def mlsa(dq, dp, Cq, Cp, rcond=0.0, ns=41, nt=41):
                                ctypes.c_int(nt), ctypes.byref(sup), ctypes.byref(sa),
                                ctypes.byref(ta)), "oracle_mlsa")
     return sup.value, sa.value, ta.value
+
+
+def mlsa_h1(dq, dp, eps, Cq, Cp, rcond=0.0, ns=41, nt=41, nx=2001):
+    """The H^1 quantity of the remark in Sec. 3.1 (the sup after eq. 3.28), d = 1:
+
+        sup over (Q, P) in [0, dq_mesh] x [0, dp_mesh] of
+            || dG/dx - sum_k c_k dG_k/dx ||_{L^2} / || G ||_{H^1},
+
+    with G(x) = exp(i P (x - Q) / eps - (x - Q)^2 / (2 eps)), the basis
+    G_k = G(x; dq_k dq_mesh, dp_k dp_mesh), dq_mesh = Cq sqrt(eps),
+    dp_mesh = Cp sqrt(eps), and c the L^2 least-squares coefficients of G on the
+    basis (normal equations A c = f, A_jk = <G_k, G_j>, f_j = <G, G_j>, solved
+    through the eigenpairs of A with eigenvalues below rcond * max dropped).
+    Every integral is a trapezoidal sum over x in [-16 sqrt(eps), 16 sqrt(eps)]
+    (nx points; the integrands are Gaussians centred within a few mesh steps of
+    0, so the sum converges spectrally), and the derivative of a packet is
+    taken analytically: dG/dx = (i P / eps - (x - Q) / eps) G.  The sup is taken
+    over an ns x nt grid of the cell, edges included.  Returns (sup, s, t) with
+    (s, t) = (Q / dq_mesh, P / dp_mesh) where it is reached."""
+    dq = np.asarray(dq, dtype=np.float64).ravel()
+    dp = np.asarray(dp, dtype=np.float64).ravel()
+    se = math.sqrt(eps)
+    Dq, Dp = Cq * se, Cp * se
+    x = np.linspace(-16.0 * se, 16.0 * se, nx)
+    w = np.full(nx, x[1] - x[0])
+    w[0] = w[-1] = 0.5 * (x[1] - x[0])
+
+    def packet(q, p):
+        g = np.exp(1j * p * (x - q) / eps - (x - q) ** 2 / (2.0 * eps))
+        return g, (1j * p / eps - (x - q) / eps) * g
+
+    basis = [packet(a * Dq, b * Dp) for a in dq for b in dp]
+    B = np.stack([g for g, _ in basis], axis=1)
+    dB = np.stack([h for _, h in basis], axis=1)
+    A = (B.conj().T * w) @ B
+    lam, V = np.linalg.eigh(A)
+    kept = lam > rcond * lam.max() if rcond > 0 else lam > 0
+    best = (-1.0, 0.0, 0.0)
+    for s in np.linspace(0.0, 1.0, ns):
+        for t in np.linspace(0.0, 1.0, nt):
+            g, h = packet(s * Dq, t * Dp)
+            f = (B.conj().T * w) @ g
+            c = V[:, kept] @ ((V[:, kept].conj().T @ f) / lam[kept])
+            r = h - dB @ c
+            num = math.sqrt(float(np.sum(w * np.abs(r) ** 2)))
+            den = math.sqrt(float(np.sum(w * (np.abs(g) ** 2 + np.abs(h) ** 2))))
+            if num / den > best[0]:
+                best = (num / den, float(s), float(t))
+    return best
 
 
 def pcell_bounds(P, dp):

@@ -871,6 +871,41 @@ int fggc_cell_box(fggc_ctx *ctx, const fggc_packets *pk, const fggc_strategy *st
   });
 }
 
+int fggc_coefficients(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_strategy *st, double scale,
+                      double *c_out, int32_t *cell_out, void *stream) {
+  return guarded("fggc_coefficients", [&] {
+    if (!ctx || !pk || !st || !c_out || !cell_out) fail(FGGC_EINVAL, "NULL argument");
+    if (pk->d < 1 || pk->d > 3) fail(FGGC_EINVAL, "packets->d must be 1, 2 or 3");
+    const int d = pk->d;
+    check_packets(pk, d);
+    check_eps(eps);
+    check_strategy(st, d);
+    if (!std::isfinite(scale)) fail(FGGC_EINVAL, "scale must be finite");
+    if (d == 3 && st->nq * st->np > 8) fail(FGGC_EUNSUPPORTED, "3D strategies need nq * np <= 8");
+    if (pk->N == 0) return;
+    Guard lock(ctx);
+    hipStream_t s = (hipStream_t)stream;
+    WsUse wsu(ctx, s);
+    if (packets_on_host(*pk) || !device_accessible(c_out) || !device_accessible(cell_out))
+      fail(FGGC_EINVAL, "packets and outputs must be device memory");
+    const Plan plan = plan_for(*st, d, eps);
+    GridGeom g{};
+    g.d = d;
+    for (int k = 0; k < 3; ++k) {
+      g.n[k] = 1;
+      g.dx[k] = 1.0;
+    }
+    const int64_t zero[3] = {0, 0, 0}, one[3] = {1, 1, 1};
+    fggc_packets dpk = *pk;
+    FggcArgs fa{};
+    fill_fggc_args(fa, &dpk, eps, g, *st, scale, FGGC_FP64, plan.host, zero, one);
+    fa.lsq_dev = plan.dev;
+    prepass(ctx, dpk, st->dp, s);
+    ctx->ws.reserve(fggc_coefficients_workspace_bytes(fa), ctx->budget);
+    launch_fggc_coefficients(fa, c_out, cell_out, ctx->ws, s);
+  });
+}
+
 int fggc_cells(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_strategy *st,
                double scale, int precision, const int64_t *slice_lo, const int64_t *slice_n,
                void *cells_out, size_t cells_bytes, void *stream) {

@@ -304,6 +304,10 @@ bool fggc_graph_safe(const FggcArgs &a);
 void launch_fggc(const FggcArgs &a, Workspace &ws, hipStream_t s);
 // Only the cell array (eq. 2.25) into `cells` (device).
 void launch_fggc_cells(const FggcArgs &a, void *cells, Workspace &ws, hipStream_t s);
+// The coefficient kernel's per-packet coefficients (FP64): c_out [N][n1^d]
+// complex, cell_out [N][2][d] (q index, p-cell); a.slo, a.sn are not used.
+void launch_fggc_coefficients(const FggcArgs &a, double *c_out, int32_t *cell_out, Workspace &ws, hipStream_t s);
+size_t fggc_coefficients_workspace_bytes(const FggcArgs &a);
 size_t fggc_cells_workspace_bytes(const FggcArgs &a);
 
 

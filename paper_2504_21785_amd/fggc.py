@@ -96,6 +96,7 @@ _SIGS = [
                                  ctypes.POINTER(_I64), _VP, _VP]),
     ("fggc_propagate", _I, [_VP, ctypes.c_int32, _I64, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(Potential), _D,
                             _I64, _VP]),
+    ("fggc_coefficients", _I, [_VP, ctypes.POINTER(Packets), _D, ctypes.POINTER(Strategy), _D, _VP, _VP, _VP]),
     ("fggc_learn_select", _I, [_VP, _I64, _VP, _D, _VP, _VP, _VP, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                _VP]),
     ("fggc_learn_start", _I, [_VP, ctypes.c_int32, _I64, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -516,6 +517,23 @@ class Context:
                                     int(nsteps), _stream_ptr(stream) if _on_device(Q) else None))
         return Q, P, S, a
 
+    def coefficients(self, Q, P, S, a, eps: float, strategy: Strategy, scale: float = 1.0, stream=None):
+        """fggc_coefficients: per-packet least-squares coefficients (device tensors).
+
+        Returns (c [N][(nq np)^d] complex128, cells [N][2][d] int32) on the
+        packets' device."""
+        import torch
+        d, N = check_packets(Q, P, S, a)
+        if not _on_device(Q):
+            raise ValueError("coefficients takes device tensors")
+        n1 = int(strategy.nq) * int(strategy.np)
+        c = torch.empty((N, n1 ** d), dtype=torch.complex128, device=Q.device)
+        cells = torch.empty((N, 2, d), dtype=torch.int32, device=Q.device)
+        pk = _packets(Q, P, S, a)
+        _check(lib().fggc_coefficients(self.h, ctypes.byref(pk), float(eps), ctypes.byref(strategy), float(scale),
+                                       _ptr(c), _ptr(cells), _stream_ptr(stream)))
+        return c, cells
+
     # -- multi-step FGGC bookkeeping (Alg. 3); device tensors only ----------
     def learn_select(self, A0, prune: float, learned, keep_idx, new_idx, stream=None):
         """fggc_learn_select: fills keep_idx / new_idx (int64 [Nm]) and marks the
@@ -625,7 +643,7 @@ class Context:
         shape = tuple(g.n[k] for k in range(g.d))
         if out is not None:
             return out
-        if hasattr(like, "device"):
+        if hasattr(like, "is_cuda"):  # a torch tensor (numpy arrays have .device too)
             import torch
             dt = torch.complex128 if precision == FP64 else torch.complex64
             return torch.empty(shape, dtype=dt, device=like.device)

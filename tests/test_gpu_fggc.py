@@ -495,3 +495,68 @@ def test_reconstruct_3d_edge_cases(ctx, orc, prec, tol):
         u = u.cpu().numpy().reshape(-1)[pts].astype(np.complex128)
         ref = orc.fggc(q, p, s_, a_, eps, M, Nq, dp, sd["dq_off"], sd["dp_off"], pts=pts)
         check(u, ref, tol, f"3d edge prec={prec} N={q.shape[1]}")
+
+
+@pytest.mark.parametrize("name", ["Q2P2", "Q4P2", "Q2P4"])
+def test_device_coefficients_match_oracle_lsa(ctx, orc, name):
+    # the coefficient kernel's least-squares coefficients (fggc_coefficients)
+    # on an 11 x 11 sweep of the first cell (Q = s dq, P = t dp: the shift of
+    # eq. 3.13 is 1 there) against the oracle's solve in the eps-free form
+    # (Theorem 3); the E_LSA of the device coefficients, by quadrature,
+    # against the oracle's E_LSA.  Q2P2 (kappa ~ 1e5) also fixes c itself;
+    # the sets of four are compared through E (c is not unique beyond their
+    # conditioning).
+    eps, C = 1.0 / 64, math.pi / 8
+    se = math.sqrt(eps)
+    Nq = int(round(2 * math.pi / (C * se)))
+    dqm, dpm = 2 * math.pi / Nq, C * se
+    Cq, Cp = dqm / se, dpm / se
+    dq_off, dp_off = STRATEGIES[name]
+    st = F.make_strategy(1, [Nq], [dpm], dq_off, dp_off)
+    s1 = np.linspace(0.0, 0.999, 11)
+    ss, tt = [g.ravel() for g in np.meshgrid(s1, s1, indexing="ij")]
+    Q, P = (ss * dqm)[None, :], (tt * dpm)[None, :]
+    N = Q.shape[1]
+    c, cells = ctx.coefficients(t(Q), t(P), t(np.zeros(N)), t(np.ones(N, complex)), eps, st)
+    torch.cuda.synchronize()
+    c, cells = c.cpu().numpy(), cells.cpu().numpy()
+    assert np.all(cells[:, 0, 0] == Nq // 2) and np.all(cells[:, 1, 0] == 0)
+    qk = np.array([a for a in dq_off for b in dp_off]) * dqm
+    pk = np.array([b for a in dq_off for b in dp_off]) * dpm
+    x = np.linspace(-14 * se, 14 * se + dqm, 40001)
+    h = x[1] - x[0]
+    worst_c, worst_e = 0.0, 0.0
+    for j in range(N):
+        cr, Er = orc.lsa([a for a in dq_off for b in dp_off], [b for a in dq_off for b in dp_off], Cq, Cp,
+                         ss[j], tt[j])
+        g = np.exp(1j * P[0, j] * (x - Q[0, j]) / eps - (x - Q[0, j]) ** 2 / (2 * eps))
+        basis = np.exp(1j * pk[None, :] * (x[:, None] - qk[None, :]) / eps - (x[:, None] - qk[None, :]) ** 2 / (2 * eps))
+        r = g - basis @ c[j]
+        E = math.sqrt(np.sum(np.abs(r) ** 2) * h / (np.sum(np.abs(g) ** 2) * h))
+        # relative to E, with an absolute floor for the mesh points (E ~ 0)
+        worst_e = max(worst_e, abs(E - Er) / (Er + 1e-6))
+        if name == "Q2P2":
+            worst_c = max(worst_c, float(np.max(np.abs(c[j] - cr))) / float(np.max(np.abs(cr))))
+    log(f"{name}: worst relative E_LSA difference {worst_e:.2e}, worst coefficient difference {worst_c:.2e}")
+    assert worst_e < 1e-3, worst_e
+    if name == "Q2P2":
+        assert worst_c < 1e-10, worst_c
+
+
+def test_lsa_maps_error_matches_oracle(ctx, orc):
+    # the coefficient and error maps of Sec. 2.2 (Q2P2, Cq = 1/2, Cp = pi/4),
+    # computed by the library (coefficient kernel + FP64 direct sum of the
+    # residual): E_LSA at every sweep point against the oracle's
+    from paper_2504_21785_amd import lsa_maps
+    m = lsa_maps.maps(ctx, "Q2P2", 0.5, math.pi / 4, n=5)
+    E = np.array(m["E_LSA"])
+    worst = 0.0
+    for i, s_ in enumerate(m["s"]):
+        for j, t_ in enumerate(m["t"]):
+            _, Er = orc.lsa([0, 0, 1, 1], [0, 1, 0, 1], 0.5, math.pi / 4, s_, t_)
+            if Er < 1e-9:  # a mesh point: both vanish
+                assert E[i, j] < 1e-7
+                continue
+            worst = max(worst, abs(E[i, j] / Er - 1))
+    log(f"lsa maps: worst relative E_LSA difference {worst:.2e}, max E {m['summary']['max_E']:.3e}")
+    assert worst < 1e-4, worst

@@ -113,6 +113,45 @@ def test_mlsa_recommended_strategy_values(orc):
     assert 1e-7 < sup < 1e-6
 
 
+with open(os.path.join(HERE, "golden", "mlsa1_table.json")) as fh:
+    MLSA1 = json.load(fh)
+
+# Reading: in the H^1 table the column "Q4P2" is the q-shift set of four
+# (dq {-1, 0, 1, 2} x dp {0, 1}) and "Q2P4" the p-set of four -- the natural
+# reading, unlike the L^2 tables above; the pseudo-inverse drops eigenvalues
+# below 1e-10 of the largest, as there.
+H1_LAYOUTS = {"Q2P2": (Q2, Q2), "Q4P2": (Q4, Q2), "Q2P4": (Q2, Q4), "Q4P4": (Q4, Q4)}
+
+
+@pytest.mark.parametrize("name", ["Q2P2", "Q4P2", "Q2P4", "Q4P4"])
+def test_mlsa_h1_reproduces_the_printed_table(orc, name):
+    """The H^1 quantity (Sec. 3.1 remark, the sup after eq. 3.28) against every
+    printed value of its column, eps = 2^-6 ... 2^-16 (4 printed digits)."""
+    j = MLSA1["columns"].index(name)
+    dq, dp = H1_LAYOUTS[name]
+    for i, eps in enumerate(MLSA1["eps"]):
+        sup, _, _ = orc.mlsa_h1(dq, dp, eps, 0.5, math.pi / 8, rcond=1e-10, ns=21, nt=21)
+        want = MLSA1["values"][i][j]
+        assert abs(sup / want - 1) < 1.5e-3, (name, eps, sup, want)
+
+
+def test_mlsa_h1_vanishes_on_the_mesh_and_needs_the_cutoff_reading(orc):
+    """A packet on a mesh point is its own basis function: with exact least
+    squares its H^1 residual vanishes (to the conditioning of the Gram matrix;
+    Q4P4's is singular at this mesh and is left out).  With the 1e-10 cutoff
+    the larger shift sets lose a direction that the on-mesh packet itself
+    needs, so their residual there is already the printed sup: the cutoff is
+    part of the reading, as for the L^2 tables."""
+    for name, bound in (("Q2P2", 1e-11), ("Q4P2", 1e-8), ("Q2P4", 1e-8)):
+        dq, dp = H1_LAYOUTS[name]
+        sup, _, _ = orc.mlsa_h1(dq, dp, 1 / 64, 0.5, math.pi / 8, rcond=0.0, ns=1, nt=1)
+        assert sup < bound, (name, sup)
+    for j, name in enumerate(MLSA1["columns"][1:], start=1):
+        dq, dp = H1_LAYOUTS[name]
+        sup, _, _ = orc.mlsa_h1(dq, dp, 1 / 64, 0.5, math.pi / 8, rcond=1e-10, ns=1, nt=1)
+        assert abs(sup / MLSA1["values"][0][j] - 1) < 1.5e-3, (name, sup)
+
+
 # --------------------------------------------------------------------------
 # least squares: the oracle's coefficients are the L2-best ones
 # --------------------------------------------------------------------------
