@@ -57,7 +57,7 @@ typedef enum {
   FGGC_EINVAL = -1,       /* invalid argument (NaN/Inf input, eps <= 0, bad d, bad size, ...) */
   FGGC_ENOMEM = -2,       /* device allocation failed */
   FGGC_EBUDGET = -3,      /* the request can never fit in the context's HBM budget */
-  FGGC_EUNSUPPORTED = -4, /* valid but not supported (e.g. non power-of-two FFT size) */
+  FGGC_EUNSUPPORTED = -4, /* valid but not supported (e.g. an FFT size with a prime factor above 5) */
   FGGC_EDEVICE = -5,      /* a HIP runtime call failed */
   FGGC_ECANCELLED = -6,   /* a served request was cancelled */
   FGGC_ETIMEOUT = -7      /* fggc_server_wait timed out; the request is still pending */
@@ -85,8 +85,11 @@ typedef struct {
 
 /*
  * Mesh and neighbour strategy of eq. (3.5) and Definition 1 (eq. 2.20).
- *   q-mesh: Nq[k] points over [-pi, pi) (dq = 2 pi / Nq[k], Nq[k] even, power
- *           of two, 4 <= Nq[k] <= 8192); cell anchoring floor(Q / dq) as in (2.20).
+ *   q-mesh: Nq[k] points over [-pi, pi) (dq = 2 pi / Nq[k]; Nq[k] even and of
+ *           the form 2^a 3^b 5^c, 4 <= Nq[k] <= 8192; in two and three
+ *           dimensions the power of two in Nq[k] must reach the span of the
+ *           q-shifts rounded up to a power of two, e.g. 4 for Q4 sets);
+ *           cell anchoring floor(Q / dq) as in (2.20).
  *   p-mesh: step dp[k] > 0, cells floor(P / dp), not wrapped.
  *   Shift set: the tensor product over dimensions of the one-dimensional set
  *           {(dq_off[i], dp_off[j])}, i < nq, j < np (nq * np <= 16), as in the
@@ -363,8 +366,8 @@ int fggc_learn_packets(fggc_ctx *ctx, int32_t d, int64_t Nm, int64_t n, const in
  *   p-slice, a Gaussian band multiply-accumulate into the grid spectrum
  *   (the Fourier transform of (2.16) with the on-grid centre and momentum),
  *   and one inverse FFT of size prod(grid->n).
- * grid->n[k] must be powers of two (2 .. 16384 for 1D FP32, 8192 for FP64,
- * 4096 for d >= 2).  Nq as in fggc_strategy.
+ * grid->n[k] must be of the form 2^a 3^b 5^c (2 .. 16384 for 1D FP32, 8192
+ * for FP64, 4096 for d >= 2).  Nq as in fggc_strategy.
  * FGGC_FP64: FP64 throughout.  FGGC_FP32: least squares, phase reductions
  * and band weights in FP64; cells, FFTs and products in FP32; spectrum
  * accumulated in FP64.
@@ -414,7 +417,11 @@ int fggc_cells(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fggc_str
  *   inverse (direction = +1): X[k] = sum_n x[n] exp(+2 pi i k.n / n), unnormalised.
  * data: batch consecutive arrays of prod(n[0..d-1]) complex values
  * (complex64 for FGGC_FP32, complex128 for FGGC_FP64), row-major.
- * Sizes: powers of two, 2 .. 16384 (FP32) or 8192 (FP64) per dimension.
+ * Sizes: 2^a 3^b 5^c, 2 .. 16384 (FP32) or 8192 (FP64) per dimension; in two
+ * and three dimensions at most 4096 unless a power of two.  Lengths with
+ * factors 3 or 5 take mixed-radix passes (radix 4, 2, 3 and 5); one
+ * dimension above 4096 points takes the four-step form n = n1 n2.
+ * Errors: FGGC_EUNSUPPORTED for other sizes.
  */
 int fggc_fft(fggc_ctx *ctx, int d, const int64_t *n, int64_t batch, int direction, int precision,
              void *data, void *stream);

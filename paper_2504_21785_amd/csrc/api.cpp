@@ -175,6 +175,13 @@ std::vector<std::string> Profiler::stages() {
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+bool is_fft_size(int64_t v) {
+  if (v < 2) return false;
+  for (int f : {2, 3, 5})
+    while (v % f == 0) v /= f;
+  return v == 1;
+}
+
 // true when `p` can be dereferenced by kernels on the current device as is
 bool device_accessible(const void *p) {
   hipPointerAttribute_t at;
@@ -307,8 +314,8 @@ void check_strategy(const fggc_strategy *st, int d) {
     if (b - a > 31 || e - c > 31) fail(FGGC_EINVAL, "shift sets must span at most 31 cells");
   }
   for (int k = 0; k < d; ++k) {
-    if (st->Nq[k] < 4 || st->Nq[k] > 8192 || !is_pow2(st->Nq[k]))
-      fail(FGGC_EUNSUPPORTED, "Nq must be a power of two in [4, 8192]");
+    if (st->Nq[k] < 4 || st->Nq[k] > 8192 || st->Nq[k] % 2 || !is_fft_size(st->Nq[k]))
+      fail(FGGC_EUNSUPPORTED, "Nq must be an even 2^a 3^b 5^c in [4, 8192]");
     if (!(st->dp[k] > 0) || !std::isfinite(st->dp[k])) fail(FGGC_EINVAL, "dp must be finite and > 0");
   }
 }
@@ -981,8 +988,8 @@ int fggc_reconstruct(fggc_ctx *ctx, const fggc_packets *pk, double eps, const fg
     if (!u_out) fail(FGGC_EINVAL, "u_out is NULL");
     const int64_t maxM = d == 1 ? (precision == FGGC_FP64 ? 8192 : 16384) : 4096;
     for (int k = 0; k < d; ++k)
-      if (!is_pow2(g.n[k]) || g.n[k] < 2 || g.n[k] > maxM)
-        fail(FGGC_EUNSUPPORTED, "FGGC needs power-of-two grid sizes in [2, " + std::to_string(maxM) + "]");
+      if (!is_fft_size(g.n[k]) || g.n[k] > maxM)
+        fail(FGGC_EUNSUPPORTED, "FGGC needs grid sizes 2^a 3^b 5^c in [2, " + std::to_string(maxM) + "]");
     Guard lock(ctx);
     hipStream_t s = (hipStream_t)stream;
     WsUse wsu(ctx, s);
@@ -1077,8 +1084,9 @@ int fggc_fft(fggc_ctx *ctx, int d, const int64_t *n, int64_t batch, int directio
     if (precision != FGGC_FP32 && precision != FGGC_FP64) fail(FGGC_EINVAL, "bad precision");
     const int64_t maxn = precision == FGGC_FP64 ? 8192 : 16384;
     for (int k = 0; k < d; ++k)
-      if (!is_pow2(n[k]) || n[k] < 2 || n[k] > maxn)
-        fail(FGGC_EUNSUPPORTED, "FFT sizes must be powers of two in [2, " + std::to_string(maxn) + "]");
+      if (!is_fft_size(n[k]) || n[k] > maxn || (d > 1 && !is_pow2(n[k]) && n[k] > 4096))
+        fail(FGGC_EUNSUPPORTED, "FFT sizes must be 2^a 3^b 5^c in [2, " + std::to_string(maxn) +
+                                    "] (at most 4096 unless a power of two, in two and three dimensions)");
     Guard lock(ctx);
     hipStream_t s = (hipStream_t)stream;
     WsUse wsu(ctx, s);

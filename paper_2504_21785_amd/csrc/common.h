@@ -327,6 +327,7 @@ void launch_fft_to(int d, const int64_t *n, int direction, int precision, void *
 // --------------------------------------------------------------------------
 
 bool is_pow2(int64_t v);
+bool is_fft_size(int64_t v);  // v >= 2 and v = 2^a 3^b 5^c
 // true when `p` can be dereferenced by kernels on the current device as is
 bool device_accessible(const void *p);
 // true when any packet array is not device-accessible

@@ -1,6 +1,8 @@
-// Batched complex FFT of power-of-two sizes, in place, in LDS: Stockham
-// autosort passes of radix 4 (and one radix 2 when log2 n is odd), one
-// workgroup per group of lines along one axis of a row-major array.  A
+// Batched complex FFT in LDS: Stockham autosort passes, one workgroup per
+// group of lines along one axis of a row-major array.  Power-of-two lengths
+// and strides take radix-8/4/2 passes and shift/mask indexing; other lengths
+// n = 2^a 3^b 5^c (and strides that are not powers of two) take the
+// mixed-radix passes (radix 4, 2, 3, 5) with general indexing.  A
 // d-dimensional transform is d such axis passes.  Twiddles come from a
 // table exp(-2 pi i k / n) computed in FP64 on the host (rounded once to the
 // working precision) and kept per device for the life of the process.
@@ -82,6 +84,57 @@ __global__ __launch_bounds__(1024) void fft_axis_kernel(const T *src, T *dst, Ff
   }
 }
 
+// Lines of any length n = 2^a 3^b 5^c and any inner stride: line `line` is
+// (bo, bi) = (line / inner, line % inner), element i at (bo n + i) inner + bi.
+struct FftAxisMr {
+  int64_t nlines, inner;
+  int n, L;  // line length, lines per workgroup
+  int inverse;
+  int transpose_out;  // store element i of line l at dst[i * nlines + l]
+  int64_t nbig;       // > 0: multiply output i of line (bo, bi) by exp(-+ 2 pi i bi i / nbig)
+};
+
+constexpr int kMrElems = 16;  // elements per thread of the mixed-radix passes
+
+template <typename T>
+__global__ __launch_bounds__(1024) void fft_axis_mr_kernel(const T *src, T *dst, FftAxisMr a,
+                                                           const T *__restrict__ tw,
+                                                           const T *__restrict__ twbig) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *sm = reinterpret_cast<T *>(smem_raw);
+  const int n = a.n, L = a.L, tot = L * n;
+  const int64_t line0 = (int64_t)blockIdx.x * L;
+  T *stw = sm + tot;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) stw[i] = tw[i];
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    // along the line when lines are contiguous, across lines otherwise
+    const int l = a.inner == 1 ? e / n : e % L, i = a.inner == 1 ? e % n : e / L;
+    const int64_t line = line0 + l;
+    if (line < a.nlines) {
+      const int64_t bo = line / a.inner, bi = line - bo * a.inner;
+      sm[l * n + i] = src[(bo * n + i) * a.inner + bi];
+    }
+  }
+  __syncthreads();
+  lds_fft_rows_mr<T, kMrElems>(sm, n, L, n, a.inverse, stw);
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const bool rowwise = a.inner == 1 && !a.transpose_out;
+    const int l = rowwise ? e / n : e % L, i = rowwise ? e % n : e / L;
+    const int64_t line = line0 + l;
+    if (line < a.nlines) {
+      const int64_t bo = line / a.inner, bi = line - bo * a.inner;
+      T v = sm[l * n + i];
+      if (a.nbig > 0) {  // four-step twiddle exp(-+ 2 pi i bi i / nbig)
+        T w = twbig[(bi * i) % a.nbig];
+        if (a.inverse) w.y = -w.y;
+        v = cmul(v, w);
+      }
+      if (a.transpose_out) dst[(int64_t)i * a.nlines + line] = v;
+      else dst[(bo * n + i) * a.inner + bi] = v;
+    }
+  }
+}
+
 // twiddle tables, per (device, n, precision), created on first use
 std::mutex g_tw_mu;
 std::map<std::tuple<int, int64_t, int>, void *> g_tw;
@@ -114,9 +167,48 @@ const void *twiddles(int64_t n, int precision) {
   return p;
 }
 
+// The mixed-radix form of launch_axis: L lines per workgroup within the
+// element budget (L n <= 1024 kMrElems) and the LDS (rows and twiddles).
+template <typename T>
+void launch_axis_mr(const T *src, T *dst, int64_t n, int64_t inner, int64_t outer, int inverse,
+                    hipStream_t s, int transpose_out, int64_t nbig) {
+  const int64_t elem = sizeof(T);
+  const int64_t lds_elems = 131072 / elem;
+  if (n > 1024 * kMrElems || 2 * n > lds_elems) fail(FGGC_EUNSUPPORTED, "FFT line too long");
+  const int64_t nlines = inner * outer;
+  int64_t L = inner == 1 && !transpose_out ? std::max<int64_t>(1, 4096 / n) : 64;
+  L = std::min(L, lds_elems / n - 1);
+  L = std::min(L, (int64_t)1024 * kMrElems / n);
+  // keep at least ~256 workgroups when there are enough lines
+  L = std::max<int64_t>(1, std::min(L, nlines / 256));
+  L = std::min(L, std::max<int64_t>(nlines, 1));
+  const int64_t elems = L * n;
+  int threads = (int)std::min<int64_t>(1024, std::max<int64_t>(64, (elems + kMrElems - 1) / kMrElems));
+  threads = (threads + 63) / 64 * 64;
+  FftAxisMr a;
+  a.nlines = nlines;
+  a.inner = inner;
+  a.n = (int)n;
+  a.L = (int)L;
+  a.inverse = inverse;
+  a.transpose_out = transpose_out;
+  a.nbig = nbig;
+  const T *tw = (const T *)twiddles(n, elem == 8 ? FGGC_FP32 : FGGC_FP64);
+  const T *twb = nbig > 0 ? (const T *)twiddles(nbig, elem == 8 ? FGGC_FP32 : FGGC_FP64) : tw;
+  const size_t shm = (size_t)(L + 1) * n * elem;  // rows, then twiddles
+  const int64_t nblocks = (nlines + L - 1) / L;
+  if (nblocks >= ((int64_t)1 << 31)) fail(FGGC_EUNSUPPORTED, "FFT: too many lines");
+  fft_axis_mr_kernel<T><<<dim3((unsigned)nblocks), dim3(threads), shm, s>>>(src, dst, a, tw, twb);
+  FGGC_HIP(hipGetLastError());
+}
+
 template <typename T>
 void launch_axis(const T *src, T *dst, int64_t n, int64_t inner, int64_t outer, int inverse,
                  hipStream_t s, int transpose_out = 0, int64_t nbig = 0) {
+  if (!is_pow2(n) || !is_pow2(inner) || (nbig > 0 && !is_pow2(nbig))) {
+    launch_axis_mr<T>(src, dst, n, inner, outer, inverse, s, transpose_out, nbig);
+    return;
+  }
   const int64_t elem = sizeof(T);
   const int64_t lds_max = (elem == 8 ? 16384 : 8192);  // elements (128 KB)
   int log2n = 0;
@@ -173,6 +265,14 @@ void launch_axis(const T *src, T *dst, int64_t n, int64_t inner, int64_t outer, 
   FGGC_HIP(hipGetLastError());
 }
 
+// n = n1 n2 for the four-step form: the divisor n1 <= sqrt(n) nearest sqrt(n)
+// with n2 <= 4096 (a power of two splits as 2^floor(lg/2) x 2^ceil(lg/2)).
+int64_t four_step_split(int64_t n) {
+  for (int64_t n1 = (int64_t)std::sqrt((double)n) + 1; n1 >= 2; --n1)
+    if (n1 * n1 <= n && n % n1 == 0 && n / n1 <= 4096) return n1;
+  fail(FGGC_EUNSUPPORTED, "FFT length has no four-step split");
+}
+
 // d-dimensional transform of one array, src -> dst (src may be dst; src is
 // overwritten when the four-step form is used).  One-dimensional sizes above
 // 4096 go through the four-step form: column FFTs of the n1 x n2 view with
@@ -180,9 +280,7 @@ void launch_axis(const T *src, T *dst, int64_t n, int64_t inner, int64_t outer, 
 template <typename T>
 void fft_one(int d, const int64_t *n, int inverse, T *src, T *dst, hipStream_t s) {
   if (d == 1 && n[0] > 4096) {
-    int lg = 0;
-    while (((int64_t)1 << lg) < n[0]) ++lg;
-    const int64_t n1 = (int64_t)1 << (lg / 2), n2 = n[0] / n1;
+    const int64_t n1 = four_step_split(n[0]), n2 = n[0] / n1;
     launch_axis<T>(src, src, n1, n2, 1, inverse, s, 0, n[0]);  // columns, twiddled
     launch_axis<T>(src, dst, n2, 1, n1, inverse, s, 1, 0);     // rows, stored transposed
     return;
@@ -206,6 +304,10 @@ void ensure_attrs() {
   FGGC_HIP(hipFuncSetAttribute((const void *)fft_axis_kernel<float2>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
   FGGC_HIP(hipFuncSetAttribute((const void *)fft_axis_kernel<double2>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+  FGGC_HIP(hipFuncSetAttribute((const void *)fft_axis_mr_kernel<float2>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+  FGGC_HIP(hipFuncSetAttribute((const void *)fft_axis_mr_kernel<double2>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
   g_attr_set = true;
 }

@@ -42,6 +42,19 @@ __device__ __forceinline__ void int_frac(double v, int64_t &i, double &f) {
   }
 }
 
+// x mod n in [0, n) (floor convention) for q-mesh indices of any mesh size;
+// the common case, x already in range, costs one comparison
+__device__ __forceinline__ int wrapq(int x, int n) {
+  if ((unsigned)x < (unsigned)n) return x;
+  x %= n;
+  return x < 0 ? x + n : x;
+}
+__device__ __forceinline__ int64_t wrapq(int64_t x, int64_t n) {
+  if ((uint64_t)x < (uint64_t)n) return x;
+  x %= n;
+  return x < 0 ? x + n : x;
+}
+
 // unit complex number exp(2 pi i rev), argument reduced in revolutions first
 __device__ __forceinline__ void cis_rev(double rev, double &c, double &s) {
   sincospi(2.0 * (rev - rint(rev)), &s, &c);
@@ -350,8 +363,7 @@ __device__ __forceinline__ void packet_keys(const KeyParams &p, int64_t j, uint3
     double s, t;
     int_frac(p.Q[k * p.N + j] / p.dq[k], iq, s);
     int_frac(p.P[k * p.N + j] / p.dp[k], ip, t);
-    const int64_t msk = p.Nq[k] - 1;
-    const int64_t qi = (iq + p.Nq[k] / 2) & msk;
+    const int64_t qi = wrapq(iq + p.Nq[k] / 2, p.Nq[k]);
     // the cell box comes from the same floor(P/dp), so this clamp never binds;
     // it keeps every key inside [0, nbins) whatever the caller's box
     int64_t pc = ip - p.pmin[k];
@@ -360,8 +372,8 @@ __device__ __forceinline__ void packet_keys(const KeyParams &p, int64_t j, uint3
     if (p.ns == 1) {
       ta[k] = tb[k] = qi / p.tile[k];
     } else {
-      ta[k] = ((qi + p.mindq) & msk) / p.tile[k];
-      tb[k] = ((qi + p.maxdq) & msk) / p.tile[k];
+      ta[k] = wrapq(qi + p.mindq, p.Nq[k]) / p.tile[k];
+      tb[k] = wrapq(qi + p.maxdq, p.Nq[k]) / p.tile[k];
     }
     nqt *= p.ntq[k];
   }
@@ -552,7 +564,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 1 && N
   RecIdx<D> ri;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    ri.q[k] = (int32_t)((iq[k] + p.Nq[k] / 2) & (p.Nq[k] - 1));
+    ri.q[k] = (int32_t)wrapq(iq[k] + p.Nq[k] / 2, p.Nq[k]);
     ri.pc[k] = (int32_t)(ip[k] - p.pmin[k]);
   }
 #pragma unroll
@@ -662,7 +674,7 @@ __global__ __launch_bounds__(256) void fggc_accum_generic_kernel(AccParams p, T 
           for (int a = 0; a < 8; ++a) {
             lq[k][a] = -1;
             if (a < p.nq) {
-              const int64_t qv = (ri.q[k] + p.dq[a] - tq[k] * p.tile[k]) & (p.Nq[k] - 1);
+              const int64_t qv = wrapq(ri.q[k] + p.dq[a] - tq[k] * p.tile[k], p.Nq[k]);
               if (qv < p.tile[k]) lq[k][a] = (int)qv;
             }
           }
@@ -775,10 +787,10 @@ __device__ __forceinline__ void add_record(const uint4 *__restrict__ src, const 
   int lq[D][NQ], ls[D][NP];
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    const int msk = (int)p.Nq[k] - 1, tl = (int)p.tile[k];
+    const int nqk = (int)p.Nq[k], tl = (int)p.tile[k];
 #pragma unroll
     for (int a = 0; a < NQ; ++a) {
-      const int qv = (ri.q[k] + p.dq[a] - tq0[k]) & msk;
+      const int qv = wrapq(ri.q[k] + p.dq[a] - tq0[k], nqk);
       lq[k][a] = qv < tl ? qv : -1;
     }
 #pragma unroll
@@ -1082,10 +1094,10 @@ __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__r
       uint32_t h = 0;
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        const int msk = (int)p.Nq[k] - 1, tl = (int)p.tile[k];
+        const int nqk = (int)p.Nq[k], tl = (int)p.tile[k];
 #pragma unroll
         for (int a = 0; a < NQ; ++a) {
-          const int qv = (ri.q[k] + p.dq[a] - tq0[k]) & msk;
+          const int qv = wrapq(ri.q[k] + p.dq[a] - tq0[k], nqk);
           lq[k][a] = qv < tl ? qv : -1;
         }
 #pragma unroll
@@ -1322,7 +1334,7 @@ __device__ __forceinline__ T stencil1_cell(const Stencil1Params &p, const T *__r
     const int64_t pc = sl + p.mindp - p.dp[b];
     if (pc < 0 || pc >= p.npc) continue;
     for (int a = 0; a < p.nq; ++a) {
-      const int64_t qs = (q - p.dq[a]) & (p.Nq - 1);
+      const int64_t qs = wrapq(q - p.dq[a], p.Nq);
       for (int c = 0; c < p.splits; ++c) {
         const T v = A[((c * p.npc + pc) * p.Nq + qs) * n1s + a * p.np + b];
         ar += v.x;
@@ -1352,14 +1364,15 @@ __global__ __launch_bounds__(256) void fggc_stencil_fft1_kernel(Stencil1Params p
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *row = reinterpret_cast<T *>(smem_raw);
   const int64_t sl = blockIdx.x;
-  const int N = 1 << lgN;
+  const int N = (int)p.Nq;  // 2^lgN, or any 2^a 3^b 5^c when lgN < 0
   T *stw = row + N;  // the twiddles, staged in LDS
   for (int q = threadIdx.x; q < N; q += blockDim.x) {
     row[q] = stencil1_cell(p, A, n1s, sl, q);
     stw[q] = tw[q];
   }
   __syncthreads();
-  lds_fft_rows<T>(row, lgN, 1, N, 0, stw);
+  if (lgN >= 0) lds_fft_rows<T>(row, lgN, 1, N, 0, stw);
+  else lds_fft_rows_mr<T, 16>(row, N, 1, N, 0, stw);
   T *dst = spec + sl * N;
   for (int q = threadIdx.x; q < N; q += blockDim.x) dst[q] = row[q];
 }
@@ -1437,7 +1450,8 @@ __global__ __launch_bounds__(256) void band_mac1_kernel(MacParams m, const T *__
 // with the band weights (FP64 accumulation) and writes [O][A][M][B].
 struct ContractParams {
   int64_t O, L, A, B, M;
-  int lgN, lgWA, lgW;  // q-line length; lines of consecutive a and of consecutive b per workgroup
+  int N, lgN, lgWA, lgW;  // q-line length (and its log2 when a power of two); lines of consecutive a and of
+                         // consecutive b per workgroup
   int Lc;              // slices per LDS chunk
   int MS;              // workgroups sharing one line group, each with a share of the frequencies
   int64_t kmin, kmax;  // union of the slices' bands (grid frequencies before aliasing)
@@ -1464,14 +1478,16 @@ constexpr int kContractFlags = 4096;  // (row, q-tile) emptiness flags of one ch
 // Lc slices of its 2^lgWA x 2^lgW lines into LDS, transforms them there and
 // adds each slice's band into per-thread FP64 sums of its outputs; gamma is
 // evaluated in place.  Frequencies no band reaches are written as zeros.
-template <typename T, typename R>
+// MR: q-lines of any length 2^a 3^b 5^c (mixed-radix passes, general
+// indexing); otherwise powers of two (shifts and masks).
+template <typename T, typename R, bool MR>
 __global__ __launch_bounds__(kContractThreads) void fft_contract_kernel(ContractParams p, const T *__restrict__ X,
                                                            T *__restrict__ Y, const T *__restrict__ tw) {
   using RR = decltype(T{}.x);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ uint8_t s_empty[kContractFlags];
   T *sm = reinterpret_cast<T *>(smem_raw);
-  const int lgN = p.lgN, N = 1 << lgN, WA = 1 << p.lgWA, W = 1 << p.lgW, P = WA * W;
+  const int lgN = p.lgN, N = MR ? p.N : 1 << lgN, WA = 1 << p.lgWA, W = 1 << p.lgW, P = WA * W;
   const int M = (int)p.M;
   const int64_t nbc = p.B >> p.lgW, nac = p.A >> p.lgWA;
   T *stw = sm + (size_t)p.Lc * P * N;  // the twiddles, staged in LDS
@@ -1486,8 +1502,9 @@ __global__ __launch_bounds__(kContractThreads) void fft_contract_kernel(Contract
   // frequencies in band order t = (k' - kmin) mod M: the first nact reach a
   // band; this workgroup takes t in [t0, t0 + Mg)
   const int nact = (int)min<int64_t>(M, p.kmax - p.kmin + 1);
-  const int Mg = M / p.MS, t0 = mg * Mg;
-  const int na = max(0, min(Mg, nact - t0));  // active frequencies of this workgroup
+  const int Mg = (M + p.MS - 1) / p.MS, t0 = mg * Mg;
+  const int Mgt = max(0, min(Mg, M - t0));     // this workgroup's share (the last may be short)
+  const int na = max(0, min(Mgt, nact - t0));  // active frequencies of this workgroup
   const int nown = na * P;
   const int kmod = (int)(((p.kmin % M) + M) % M);
   double accr[kContractOut], acci[kContractOut];
@@ -1515,15 +1532,16 @@ __global__ __launch_bounds__(kContractThreads) void fft_contract_kernel(Contract
       if (!__syncthreads_or(any)) continue;
     }
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-      const int w = e & (W - 1), n = (e >> p.lgW) & (N - 1), rest = e >> (p.lgW + lgN);
+      const int en = e >> p.lgW;
+      const int w = e & (W - 1), n = MR ? en % N : en & (N - 1), rest = MR ? en / N : en >> lgN;
       const int wa = rest & (WA - 1), l = rest >> p.lgWA;
       const int row = (((l << p.lgWA) + wa) << p.lgW) + w;
       const bool full = !p.empty || !s_empty[((l << p.lgWA) + wa) * (int)p.ntq1 + (n >> p.lgt1)];
-      sm[(row << lgN) + n] =
-          full ? X[((((o * p.L + lc0 + l) * p.A + a0 + wa) << lgN) + n) * p.B + b0 + w] : T{0, 0};
+      sm[row * N + n] = full ? X[(((o * p.L + lc0 + l) * p.A + a0 + wa) * N + n) * p.B + b0 + w] : T{0, 0};
     }
     __syncthreads();
-    lds_fft_rows<T, kContractBfly>(sm, lgN, lcn * P, N, 0, stw);
+    if constexpr (MR) lds_fft_rows_mr<T, 2 * kContractBfly>(sm, N, lcn * P, N, 0, stw);
+    else lds_fft_rows<T, kContractBfly>(sm, lgN, lcn * P, N, 0, stw);
 #pragma unroll
     for (int c = 0; c < kContractOut; ++c) {
       const int e = threadIdx.x + c * (int)blockDim.x;
@@ -1534,7 +1552,7 @@ __global__ __launch_bounds__(kContractThreads) void fft_contract_kernel(Contract
       const T *rows = sm + ((wa << p.lgW) + w) * N;  // slice l at rows + l * P * N
       double xr = 0.0, xi = 0.0;
       for (int64_t kk = p.kmin + t0 + t; kk <= p.kmax; kk += M) {
-        const T *fq = rows + (int)(kk & (N - 1));
+        const T *fq = rows + (MR ? (int)wrapq(kk, (int64_t)N) : (int)(kk & (N - 1)));
         const double dk0 = p.eps * (double)kk - (double)(p.slo + lc0) * p.dp;
         for (int l = 0; l < lcn; ++l) {
           const double dk = dk0 - (double)l * p.dp;  // eps (kk - p_l / eps)
@@ -1563,10 +1581,10 @@ __global__ __launch_bounds__(kContractThreads) void fft_contract_kernel(Contract
     Y[((o * p.A + a0 + wa) * p.M + kp) * p.B + b0 + w] = T{(RR)accr[c], (RR)acci[c]};
   }
   // frequencies of this workgroup's share that no band reaches
-  const int nz = (Mg - na) * P;
+  const int nz = (Mgt - na) * P;
   for (int e = threadIdx.x; e < nz; e += blockDim.x) {
     const int w = e & (W - 1), rest = e >> p.lgW;
-    const int t = na + rest % (Mg - na), wa = rest / (Mg - na);
+    const int t = na + rest % (Mgt - na), wa = rest / (Mgt - na);
     const int kp = (kmod + t0 + t) % M;
     Y[((o * p.A + a0 + wa) * p.M + kp) * p.B + b0 + w] = T{0, 0};
   }
@@ -1819,6 +1837,7 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
         const RR *gb = gam + (kk - p.kmin);
         for (int l = 0; l < lcn; ++l) {
           const double gv = (double)gb[l * ng];
+          if (gv == 0.0) continue;  // outside this slice's band (coherent: t runs along k)
 #pragma unroll
           for (int c = 0; c < kFusedOut; ++c) {
             if (lg0 + c * G >= P) break;
@@ -1920,6 +1939,7 @@ __global__ __launch_bounds__(kFusedThreads) void fft_contract2_kernel(Contract2P
         const double *gb = gam + (kk - p.kmin);
         for (int l = 0; l < lcn; ++l) {
           const double gv = gb[l * ng];
+          if (gv == 0.0) continue;  // outside this slice's band
 #pragma unroll
           for (int c = 0; c < kFusedOut; ++c) {
             if (lg0 + c * G >= W) break;
@@ -1992,7 +2012,8 @@ bool plan_fused3(const FggcArgs &a, FggcLayout &L, int nq, int np) {
   if (!((nq == 2 && np == 2) || (nq == 4 && np == 2) || (nq == 2 && np == 4))) return false;
   if (L.N1 != nq * np) return false;
   const int64_t N = a.Nq[2];
-  if (N < 8 || N > 256 || (N & (N - 1)) || a.Nq[0] < 4 || a.Nq[1] < 4) return false;
+  if (N < 8 || N > 256 || !is_pow2(N) || a.Nq[0] < 4 || a.Nq[1] < 4 || !is_pow2(a.Nq[0]) || !is_pow2(a.Nq[1]))
+    return false;
   const int qspan = L.maxdq - L.mindq + 1, pspan = L.maxdp - L.mindp + 1;
   if (pspan * pspan > kFusedRuns) return false;  // the runs of bins a chunk reads
   int64_t kmin, kmax;
@@ -2147,10 +2168,20 @@ FggcLayout fggc_layout(const FggcArgs &a, bool allow_fused = true) {
       L.nslices *= a.sn[k];
       nqt *= a.Nq[k];
       L.npts *= a.g.n[k];
-      // one dimension aggregates by own q-cell (no halo): tiles of exactly 32
-      // cells, the width of the aggregation workgroup
-      L.tile[k] = d == 1 ? std::min<int64_t>(a.Nq[k], kAgg1Tile)
-                         : std::min<int64_t>(a.Nq[k], std::max<int64_t>(deft[d], tmin));
+      // one dimension aggregates by own q-cell (no halo): tiles of at most 32
+      // cells, the width of the aggregation workgroup (the largest divisor
+      // of Nq up to 32); two and three dimensions take power-of-two tiles
+      // that divide Nq and span the q-shifts
+      if (d == 1) {
+        L.tile[k] = std::min<int64_t>(a.Nq[k], kAgg1Tile);
+        while (a.Nq[k] % L.tile[k]) --L.tile[k];
+      } else {
+        L.tile[k] = std::min<int64_t>(a.Nq[k], std::max<int64_t>(deft[d], tmin));
+        while (L.tile[k] > 1 && a.Nq[k] % L.tile[k]) L.tile[k] /= 2;
+        if (L.tile[k] < tmin)
+          fail(FGGC_EUNSUPPORTED, "q-mesh of " + std::to_string(a.Nq[k]) +
+                                      " cells: its power-of-two factor is below the q-shift span");
+      }
       if (L.fused3) L.tile[k] = k == 0 ? L.fT0 : (k == 1 ? L.fT1 : a.Nq[k]);
       L.ntq[k] = a.Nq[k] / L.tile[k];
       L.pmin[k] = a.slo[k] - L.mindp;
@@ -2315,6 +2346,7 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
       // cells straight into their q-spectra (the finish skips its q-DFT)
       int lgN = 0;
       while (((int64_t)1 << lgN) < a.Nq[0]) ++lgN;
+      if (((int64_t)1 << lgN) != a.Nq[0]) lgN = -1;  // mixed-radix passes
       // 256 threads: N <= 4096 keeps the FFT within 8 butterflies per thread
       const T *tw = (const T *)fft_twiddles(a.Nq[0], a.precision);
       {
@@ -2511,10 +2543,12 @@ void launch_contract(const FggcArgs &a, const FggcLayout &L, int k, const T *in,
   {
     std::lock_guard<std::mutex> lk(g_contract_mu);
     if (!g_contract_attr) {
-      FGGC_HIP(hipFuncSetAttribute((const void *)fft_contract_kernel<float2, float>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
-      FGGC_HIP(hipFuncSetAttribute((const void *)fft_contract_kernel<double2, double>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
+      const void *ks[] = {(const void *)fft_contract_kernel<float2, float, false>,
+                          (const void *)fft_contract_kernel<double2, double, false>,
+                          (const void *)fft_contract_kernel<float2, float, true>,
+                          (const void *)fft_contract_kernel<double2, double, true>};
+      for (const void *kf : ks)
+        FGGC_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, 131072));
       g_contract_attr = true;
     }
   }
@@ -2531,9 +2565,11 @@ void launch_contract(const FggcArgs &a, const FggcLayout &L, int k, const T *in,
   p.L = a.sn[k];
   p.M = a.g.n[k];
   const int64_t N = a.Nq[k];
+  const bool mr = !is_pow2(N);  // a q-mesh with factors 3 or 5: mixed-radix passes
   int lgN = 0;
   while (((int64_t)1 << lgN) < N) ++lgN;
-  p.lgN = lgN;
+  p.N = (int)N;
+  p.lgN = mr ? 0 : lgN;
   // lines per workgroup: runs of up to 4 consecutive b (contiguous in memory),
   // or, when b is a single line, up to 16 consecutive a (whole rows of N);
   // a chunk holds at most 4096 elements (the butterfly budget of
@@ -2541,11 +2577,12 @@ void launch_contract(const FggcArgs &a, const FggcLayout &L, int k, const T *in,
   // an odd log2 N)
   constexpr int64_t kElems = kContractThreads * kContractBfly * 2;
   if (N > kElems) fail(FGGC_EUNSUPPORTED, "q-mesh too long for the separable finish");
+  // (powers of two that divide B and A, so that the groups tile them)
   int lgW = 0, lgWA = 0;
-  while ((2 << lgW) <= std::min<int64_t>(4, p.B) && (N << (lgW + 1)) <= kElems) ++lgW;
+  while ((2 << lgW) <= std::min<int64_t>(4, p.B) && (N << (lgW + 1)) <= kElems && p.B % (2 << lgW) == 0) ++lgW;
   if (p.B == 1)
     while ((2 << lgWA) <= std::min<int64_t>(16, p.A) && (N << (lgWA + 1)) <= 1024 &&
-           (p.M << (lgWA + 1)) <= kContractThreads * kContractOut)
+           (p.M << (lgWA + 1)) <= kContractThreads * kContractOut && p.A % (2 << lgWA) == 0)
       ++lgWA;
   p.lgW = lgW;
   p.lgWA = lgWA;
@@ -2556,10 +2593,10 @@ void launch_contract(const FggcArgs &a, const FggcLayout &L, int k, const T *in,
   // each, and more splits (each redoing the group's DFTs) when there are
   // few line groups
   const int64_t groups = p.O * (p.A / (1 << lgWA)) * (p.B / (1 << lgW));
+  // (shares of ceil(M / MS) frequencies; the last share may be short)
   int MS = 1;
-  while ((p.M / MS) * P > kContractThreads * kContractOut) MS *= 2;
+  while (((p.M + MS - 1) / MS) * P > kContractThreads * kContractOut) MS *= 2;
   while (groups * MS < 1024 && MS * 2 <= 16 && (p.M / (MS * 2)) * P >= kContractThreads) MS *= 2;
-  if (p.M % MS) fail(FGGC_EUNSUPPORTED, "separable finish: uneven frequency split");
   p.MS = MS;
   p.kmin = m.kmin[k];
   p.kmax = m.kmax[k];
@@ -2581,7 +2618,8 @@ void launch_contract(const FggcArgs &a, const FggcLayout &L, int k, const T *in,
   const int64_t blocks = groups * MS;
   if (blocks >= ((int64_t)1 << 31)) fail(FGGC_EUNSUPPORTED, "too many workgroups for the separable finish");
   const T *tw = (const T *)fft_twiddles(N, a.precision);
-  fft_contract_kernel<T, R><<<dim3((unsigned)blocks), dim3(kContractThreads), shm, s>>>(p, in, out, tw);
+  if (mr) fft_contract_kernel<T, R, true><<<dim3((unsigned)blocks), dim3(kContractThreads), shm, s>>>(p, in, out, tw);
+  else fft_contract_kernel<T, R, false><<<dim3((unsigned)blocks), dim3(kContractThreads), shm, s>>>(p, in, out, tw);
   FGGC_HIP(hipGetLastError());
 }
 

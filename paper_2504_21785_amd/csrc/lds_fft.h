@@ -282,5 +282,137 @@ __device__ __forceinline__ void lds_fft2_rows(T *sm, int lg, int nrows, int rs, 
   }
 }
 
+// ---- lengths 2^a 3^b 5^c ------------------------------------------------
+// Mixed-radix Stockham passes over rows of any length n = 2^a 3^b 5^c held in
+// LDS: radix-4 passes, one radix-2 pass when a is odd, then radix 3 and radix
+// 5.  A pass of radix R over the length-n rows, after passes whose radices
+// multiply to Ns, takes butterfly j (0 <= j < n / R) of every row: the R
+// inputs j + r n / R, each times exp(-+ 2 pi i r (j mod Ns) / (Ns R)), one
+// R-point DFT, and the outputs at (j div Ns) Ns R + (j mod Ns) + r Ns.  After
+// the last pass the rows hold their DFTs in natural order.
+
+// 3-point DFT: X0 = a + t, X1,2 = a - t / 2 -+ i (sqrt(3) / 2) (b - c) for
+// the forward transform (t = b + c); the inverse flips the sign of i.
+template <typename T> __device__ __forceinline__ void dft3(T *x, int inverse) {
+  using R = decltype(T{}.x);
+  constexpr R h = (R)0.86602540378443864676372317075293618;  // sqrt(3) / 2
+  const T t = cadd(x[1], x[2]), dd = rot_quarter(csub(x[1], x[2]), inverse);
+  const T m = T{x[0].x - (R)0.5 * t.x, x[0].y - (R)0.5 * t.y};
+  const T r = T{h * dd.x, h * dd.y};
+  x[0] = cadd(x[0], t);
+  x[1] = cadd(m, r);
+  x[2] = csub(m, r);
+}
+
+// 5-point DFT from the symmetric pairs t1 = x1 + x4, t2 = x2 + x3 and
+// t3 = x1 - x4, t4 = x2 - x3 (c_j = cos(2 pi j / 5), s_j = sin(2 pi j / 5)):
+//   X1, X4 = x0 + c1 t1 + c2 t2 -+ i (s1 t3 + s2 t4)
+//   X2, X3 = x0 + c2 t1 + c1 t2 -+ i (s2 t3 - s1 t4)
+// (forward signs; the inverse flips the sign of i).
+template <typename T> __device__ __forceinline__ void dft5(T *x, int inverse) {
+  using R = decltype(T{}.x);
+  constexpr R c1 = (R)0.30901699437494742410229341718281906;
+  constexpr R c2 = (R)-0.80901699437494742410229341718281906;
+  constexpr R s1 = (R)0.95105651629515357211643933337938214;
+  constexpr R s2 = (R)0.58778525229247312916870595463907277;
+  const T t1 = cadd(x[1], x[4]), t2 = cadd(x[2], x[3]), t3 = csub(x[1], x[4]), t4 = csub(x[2], x[3]);
+  const T a1 = T{x[0].x + c1 * t1.x + c2 * t2.x, x[0].y + c1 * t1.y + c2 * t2.y};
+  const T a2 = T{x[0].x + c2 * t1.x + c1 * t2.x, x[0].y + c2 * t1.y + c1 * t2.y};
+  const T b1 = rot_quarter(T{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y}, inverse);
+  const T b2 = rot_quarter(T{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y}, inverse);
+  x[0] = T{x[0].x + t1.x + t2.x, x[0].y + t1.y + t2.y};
+  x[1] = cadd(a1, b1);
+  x[4] = csub(a1, b1);
+  x[2] = cadd(a2, b2);
+  x[3] = csub(a2, b2);
+}
+
+template <typename T, int R> __device__ __forceinline__ void dft_any(T *x, int inverse) {
+  if constexpr (R == 2) {
+    const T a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  } else if constexpr (R == 3) {
+    dft3(x, inverse);
+  } else if constexpr (R == 4) {
+    const T s0 = cadd(x[0], x[2]), d0 = csub(x[0], x[2]);
+    const T s1 = cadd(x[1], x[3]), d1 = rot_quarter(csub(x[1], x[3]), inverse);
+    x[0] = cadd(s0, s1);
+    x[2] = csub(s0, s1);
+    x[1] = cadd(d0, d1);
+    x[3] = csub(d0, d1);
+  } else {
+    dft5(x, inverse);
+  }
+}
+
+// One pass of radix R; CB butterflies per thread at most (the caller's
+// element budget: nrows * n <= blockDim * E with CB = ceil(E / R)).
+template <typename T, int R, int CB>
+__device__ __forceinline__ void lds_mr_pass(T *sm, int n, int Ns, int nrows, int rowstride, int inverse,
+                                            const T *__restrict__ tw) {
+  const int stride = n / R, nb = nrows * stride, tstep = n / (Ns * R);
+  T v[CB][R];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    const int b = threadIdx.x + c * (int)blockDim.x;
+    if (b >= nb) break;
+    const int l = b / stride, j = b - l * stride, k = j % Ns;
+    const T *sp = sm + l * rowstride;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[c][r] = sp[j + r * stride];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      T w = tw[r * k * tstep];
+      if (inverse) w.y = -w.y;
+      v[c][r] = cmul(v[c][r], w);
+    }
+    dft_any<T, R>(v[c], inverse);
+#pragma unroll
+    for (int r = 0; r < R; ++r) asm volatile("" : "+v"(v[c][r].x), "+v"(v[c][r].y));
+    asm volatile("" ::: "memory");
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    const int b = threadIdx.x + c * (int)blockDim.x;
+    if (b >= nb) break;
+    const int l = b / stride, j = b - l * stride, k = j % Ns;
+    T *dp = sm + l * rowstride + (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dp[r * Ns] = v[c][r];
+  }
+  __syncthreads();
+}
+
+// DFT of nrows rows of length n = 2^a 3^b 5^c in place (tw[m] =
+// exp(-2 pi i m / n); inverse = 1 conjugates).  Requires nrows * n <=
+// blockDim * E; all threads take part and synchronise.
+template <typename T, int E = 16>
+__device__ __forceinline__ void lds_fft_rows_mr(T *sm, int n, int nrows, int rowstride, int inverse,
+                                                const T *__restrict__ tw) {
+  int rem = n, Ns = 1;
+  while (rem % 4 == 0) {
+    lds_mr_pass<T, 4, (E + 3) / 4>(sm, n, Ns, nrows, rowstride, inverse, tw);
+    Ns *= 4;
+    rem /= 4;
+  }
+  if (rem % 2 == 0) {
+    lds_mr_pass<T, 2, (E + 1) / 2>(sm, n, Ns, nrows, rowstride, inverse, tw);
+    Ns *= 2;
+    rem /= 2;
+  }
+  while (rem % 3 == 0) {
+    lds_mr_pass<T, 3, (E + 2) / 3>(sm, n, Ns, nrows, rowstride, inverse, tw);
+    Ns *= 3;
+    rem /= 3;
+  }
+  while (rem % 5 == 0) {
+    lds_mr_pass<T, 5, (E + 4) / 5>(sm, n, Ns, nrows, rowstride, inverse, tw);
+    Ns *= 5;
+    rem /= 5;
+  }
+}
+
 }  // namespace fggc
 #endif

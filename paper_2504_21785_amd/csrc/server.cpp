@@ -528,8 +528,8 @@ int fggc_server_submit(fggc_server *srv, const fggc_packets *pk, double eps, con
       r->st = *st;
       const int64_t maxM = d == 1 ? (precision == FGGC_FP64 ? 8192 : 16384) : 4096;
       for (int k = 0; k < d; ++k)
-        if (!is_pow2(g.n[k]) || g.n[k] < 2 || g.n[k] > maxM)
-          fail(FGGC_EUNSUPPORTED, "FGGC needs power-of-two grid sizes in [2, " + std::to_string(maxM) + "]");
+        if (!is_fft_size(g.n[k]) || g.n[k] > maxM)
+          fail(FGGC_EUNSUPPORTED, "FGGC needs grid sizes 2^a 3^b 5^c in [2, " + std::to_string(maxM) + "]");
     } else {
       r->R = 6.0 * std::sqrt(eps);
       if (!(r->R < kPi)) fail(FGGC_EINVAL, "eps too large for the direct-sum window 6 sqrt(eps) < pi");

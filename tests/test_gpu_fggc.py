@@ -75,6 +75,37 @@ def test_fft_16384_fp32(ctx):
     check(xd.cpu().numpy(), np.fft.ifft(x) * 16384, 1e-6, "fft 16384 fp32")
 
 
+@pytest.mark.parametrize("prec,tol", [(F.FP64, 1e-13), (F.FP32, 1e-6)])
+@pytest.mark.parametrize("dims,batch", [((3,), 4), ((5,), 3), ((6,), 5), ((96,), 7), ((1000,), 3),
+                                        ((1536,), 2), ((3375,), 1), ((6000,), 2), ((64, 96), 2),
+                                        ((96, 40), 3), ((1000, 6), 1), ((12, 20, 30), 2), ((48, 32, 45), 1)])
+def test_fft_mixed_radix_against_numpy(ctx, prec, tol, dims, batch):
+    # lengths 2^a 3^b 5^c: the mixed-radix passes (radix 4, 2, 3, 5), strides
+    # that are not powers of two, and the four-step form above 4096 points
+    rng = np.random.default_rng(7 + sum(dims))
+    x = rng.standard_normal((batch, *dims)) + 1j * rng.standard_normal((batch, *dims))
+    axes = tuple(range(1, len(dims) + 1))
+    dt = torch.complex128 if prec == F.FP64 else torch.complex64
+    for direction in (-1, 1):
+        log(f"fft mixed {dims} x{batch} dir {direction} prec {prec}")
+        xd = torch.from_numpy(x).to(dt).cuda().contiguous()
+        ctx.fft(xd, dims, batch, direction, prec)
+        torch.cuda.synchronize()
+        got = xd.cpu().numpy().astype(np.complex128)
+        ref = np.fft.fftn(x, axes=axes) if direction < 0 else np.fft.ifftn(x, axes=axes) * np.prod(dims)
+        check(got, ref, tol, f"fft {dims} x{batch} dir {direction} prec {prec}")
+
+
+def test_fft_sizes_refused(ctx):
+    for dims in ((7,), (14,), (1,)):
+        x = torch.zeros(int(np.prod(dims)), dtype=torch.complex64, device="cuda")
+        with pytest.raises(RuntimeError, match="FFT sizes"):
+            ctx.fft(x, dims, 1, -1, F.FP32)
+    y = torch.zeros(2 * 4500, dtype=torch.complex64, device="cuda")
+    with pytest.raises(RuntimeError, match="FFT sizes"):  # above 4096 in 2D: powers of two only
+        ctx.fft(y, (2, 4500), 1, -1, F.FP32)
+
+
 def small_1d(seed, N=2000, eps=1.0 / 64, M=1024):
     ps = W.gen_1d(max(1, N // 50), 50, eps, M, seed)
     return ps
@@ -444,6 +475,60 @@ def test_reconstruct_3d_fused(ctx, orc, name, prec, tol, M, Nq):
     ref = orc.fggc(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, sd["Nq"][:3], sd["dp"][:3], sd["dq_off"],
                    sd["dp_off"], scale=0.7, pts=pts)
     check(u, ref, tol, f"fggc 3d {name} prec {prec} M={M} Nq={Nq}")
+
+
+@pytest.mark.parametrize("d,name,prec,tol,M,Nq", [
+    (1, "Q2P2", F.FP64, 1e-12, (1536,), (96,)),
+    (1, "Q4P2", F.FP32, 1e-6, (1536,), (96,)),
+    (1, "Q2P2", F.FP32, 1e-6, (1000,), (96,)),
+    (1, "Q4P2", F.FP64, 1e-9, (1000,), (90,)),
+    (2, "Q2P2", F.FP64, 1e-12, (240, 360), (96, 160)),
+    (2, "Q4P2", F.FP32, 1e-6, (1000, 1536), (96, 192)),
+    (2, "Q2P2", F.FP32, 1e-6, (1000, 1000), (96, 96)),
+    (2, "Q4P2", F.FP64, 1e-9, (96, 1000), (192, 96)),
+    (3, "Q2P2", F.FP64, 1e-12, (48, 40, 60), (48, 40, 30)),
+    (3, "Q2P2", F.FP32, 1e-6, (60, 64, 48), (24, 64, 96)),
+    (3, "Q2P2", F.FP32, 1e-6, (60, 40, 48), (32, 32, 64)),  # the fused finish on grids of 60, 40, 48
+])
+def test_reconstruct_mixed_radix_sizes(ctx, orc, d, name, prec, tol, M, Nq):
+    # grids and q-meshes of the form 2^a 3^b 5^c (even q-meshes), per
+    # dimension, against the oracle's evaluation of eq. (2.24)
+    if d == 1:
+        ps = small_1d(41, N=3000)
+    elif d == 2:
+        ps = W.gen_mesh(2, 16, 6, 0.5, (0.5, 0.3), 1.0 / 256, 128, seed=43)
+    else:
+        ps = W.gen_mesh(3, 8, 3, 0.5, (0.5, 0.3, 0.3), 1.0 / 64, 64, seed=47)
+    ps.M = tuple(M)
+    st0 = F.default_strategy(d, ps.eps, name)
+    sd0 = st0.describe()
+    st = F.make_strategy(d, list(Nq), sd0["dp"][:d], sd0["dq_off"], sd0["dp_off"])
+    sd = st.describe()
+    pts = None if d == 1 else heavy_points(ps, 120, 60, 9)
+    log(f"mixed sizes d={d} {name} prec {prec} M={M} Nq={Nq}")
+    u = ctx.reconstruct(t(ps.Q), t(ps.P), t(ps.S), t(ps.a), ps.eps, ps.M, st, scale=0.9, precision=prec)
+    torch.cuda.synchronize()
+    u = u.cpu().numpy().reshape(-1).astype(np.complex128)
+    if pts is not None:
+        u = u[pts]
+    ref = orc.fggc(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, sd["Nq"][:d], sd["dp"][:d], sd["dq_off"],
+                   sd["dp_off"], scale=0.9, pts=pts)
+    check(u, ref, tol, f"fggc mixed d={d} {name} prec {prec} M={M} Nq={Nq}")
+
+
+def test_mixed_radix_sizes_refused(ctx):
+    ps = W.gen_mesh(2, 16, 6, 0.5, (0.5, 0.3), 1.0 / 256, 128, seed=43)
+    st0 = F.default_strategy(2, ps.eps, "Q4P2")
+    sd0 = st0.describe()
+    args = (t(ps.Q), t(ps.P), t(ps.S), t(ps.a), ps.eps)
+    cases = [((128, 128), (75, 64), "Nq must be an even"),       # odd q-mesh
+             ((128, 128), (14, 64), "Nq must be an even"),       # factor 7
+             ((128, 126), (64, 64), "grid sizes"),               # grid with a factor 7
+             ((128, 128), (90, 64), "power-of-two factor")]      # 90 = 2 x 45 < the Q4 span
+    for M, Nq, msg in cases:
+        st = F.make_strategy(2, list(Nq), sd0["dp"][:2], sd0["dq_off"], sd0["dp_off"])
+        with pytest.raises(RuntimeError, match=msg):
+            ctx.reconstruct(*args, M, st, precision=F.FP32)
 
 
 @pytest.mark.parametrize("prec,tol", [(F.FP64, 1e-12), (F.FP32, 1e-6)])
