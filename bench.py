@@ -32,6 +32,7 @@ import numpy as np
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_T = 78.6  # FP64 vector TFLOP/s
 FP32_MFMA_PEAK_T = 157.3  # dense FP32 matrix-core TFLOP/s
+FP32_VEC_PEAK_T = 157.3  # FP32 vector TFLOP/s (256 CUs x 128 FMA lanes x 2 x 2.4 GHz)
 # VALU issue slots: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one non-packed op per lane per cycle)
 VALU_SLOT_PEAK_T = 256 * 64 * 2.4e9 / 1e12
 ACCURACY_BOUND = 1e-6
@@ -93,6 +94,22 @@ def direct_valu_slots(workload):
     return ((valu - trans) * 4 + trans * 16) * 16
 
 
+def fused_valu_busy(workload, ms):
+    """Share of the VALU issue slots the fused 3D kernel keeps busy, from the
+    committed SQ counters of this workload (SQ_INSTS_VALU per dispatch, 4
+    cycles of its SIMD per wave instruction, 64 lane slots per instruction)."""
+    t = committed_profile(f"valu_{workload}.json")
+    if t is None:
+        return None
+    k = t.get("kernels", {}).get("fggc_fused3_kernel")
+    if not k or "SQ_INSTS_VALU" not in k:
+        return None
+    slots = k["SQ_INSTS_VALU"] * 64
+    return {"lane_slots_per_launch": slots, "achieved_T": slots / (ms * 1e-3) / 1e12,
+            "peak_T": VALU_SLOT_PEAK_T, "frac": slots / (ms * 1e-3) / 1e12 / VALU_SLOT_PEAK_T,
+            "source": f"profiles/valu_{workload}.json (SQ_INSTS_VALU per dispatch)"}
+
+
 def sample_points(ps, n_heavy, n_rand, seed):
     """Grid points (flat) nearest the centres of the heaviest packets (every
     eighth of the heaviest, so that they spread) and random ones; chosen from
@@ -105,7 +122,7 @@ def sample_points(ps, n_heavy, n_rand, seed):
     return np.unique(np.ravel_multi_index(tuple(np.concatenate([m, r], axis=1)), tuple(M)))
 
 
-def stage_work(ps, st, sn, fused=False):
+def stage_work(ps, st, sn, fused=False, cK=6.0):
     """Algorithmic work per step of each FGGC stage: (bound, amount, unit, peak,
     launches per step, kernel).  Bytes count what the stage must read and write
     once; multi-pass stages count each pass's own input and output."""
@@ -145,12 +162,20 @@ def stage_work(ps, st, sn, fused=False):
             return (O * sn[k] * A * Nq[k] * B + O * A * M[k] * B) * es
 
         if fused:
-            # 3D: the accumulation fused with the pass over the last dimension:
-            # every packet's record read once (one per packet; halo copies and
-            # re-reads are overhead), the pass's output written once
+            # 3D: the accumulation fused with the pass over the last dimension.
+            # It reads one record per packet and writes the pass's output once
+            # (a few GB: far from the HBM roof), so it is priced by its FP32
+            # arithmetic: the Kronecker contributions (one complex multiply and
+            # add, 8 flops, per packet and (q, p) basis triple), the q2-DFT of
+            # every line of every slice (5 N log2 N flops) and the fold of each
+            # slice's band into the grid frequencies (a real weight times a
+            # complex value added, 4 flops, per line, slice and band frequency)
             O, A = int(np.prod(sn[:2])), int(np.prod(Nq[:2]))
-            w["fggc_fused"] = ("hbm", (N * rec_b + O * A * M[2] * es) / 1e9, "GB/s", HBM_PEAK_GBS, 1,
-                               "fggc_fused3_kernel")
+            lines = int(np.prod(sn)) * A
+            band = math.floor(2 * cK / math.sqrt(ps.eps)) + 1
+            flops = (N * n1 ** 3 * 8 + lines * 5 * Nq[2] * math.log2(Nq[2]) + lines * band * 4)
+            w["fggc_fused"] = ("alu", flops / 1e12, "TFLOP/s", FP32_VEC_PEAK_T, 1, "fggc_fused3_kernel")
+            w["fggc_fused_bytes"] = (N * rec_b + O * A * M[2] * es) / 1e9
             w["fggc_contract"] = ("hbm", sum(pass_bytes(k) for k in range(d - 2, -1, -1)) / 1e9, "GB/s",
                                   HBM_PEAK_GBS, d - 1, "fft_contract_kernel")
         else:
@@ -386,7 +411,7 @@ def main():
     lo, n = ctx.cell_box(Q, P, S, a, st)
     slices = int(np.prod(n))
     work, method_bytes = stage_work(ps, st, n, fused="fggc_fused" in fstages)
-    cand = {s2: v for s2, v in fstages.items() if s2 in work and work[s2][4]}
+    cand = {s2: v for s2, v in fstages.items() if s2 in work and isinstance(work[s2], tuple) and work[s2][4]}
     dom = max(cand, key=lambda s2: cand[s2]["ms_per_step"])
     bound, amount, unit, peak, launches, kname = work[dom]
     dom_ms = fstages[dom]["ms_per_step"]
@@ -397,6 +422,17 @@ def main():
                 "algorithmic_per_launch": amount / launches, "avg_launch_ms": dom_ms / launches,
                 "launches_per_step": launches,
                 "note": "amount per launch = the stage's algorithmic work per step / its launches per step"}
+    if dom == "fggc_fused":
+        fb = work["fggc_fused_bytes"]
+        roofline["algorithmic_flops_per_launch"] = amount * 1e12
+        roofline["note"] += ("; FP32 flops: Kronecker contributions 8 per packet and basis triple, 5 N log2 N per "
+                             "q2-line DFT, 4 per (line, slice, band frequency) of the fold")
+        roofline["hbm"] = {"algorithmic_bytes_per_launch": fb * 1e9, "achieved_GBs": fb / (dom_ms * 1e-3),
+                           "frac": fb / (dom_ms * 1e-3) / HBM_PEAK_GBS,
+                           "bytes": "one record per packet read, the pass output written once"}
+        sq = fused_valu_busy(args.workload, dom_ms)
+        if sq is not None:
+            roofline["valu_busy"] = sq
     end_to_end = {"algorithmic_bytes": method_bytes,
                   "achieved_GBs": method_bytes / 1e9 / (fggc_ms * 1e-3),
                   "frac": method_bytes / 1e9 / (fggc_ms * 1e-3) / HBM_PEAK_GBS,
@@ -408,7 +444,7 @@ def main():
                    "read, u written; over the whole FGGC step")}
     stage_rates = {}
     for s2, v in fstages.items():
-        if s2 in work:
+        if s2 in work and isinstance(work[s2], tuple):
             b2, amt, u2, pk2, _, kn2 = work[s2]
             ach2 = amt / (v["ms_per_step"] * 1e-3)
             stage_rates[s2] = {"ms_per_step": v["ms_per_step"], "achieved": ach2, "unit": u2, "frac": ach2 / pk2}
@@ -430,6 +466,27 @@ def main():
         else:
             direct_roofline.update({"achieved": None, "frac": None,
                                     "slots_source": "no committed SQ counters for the current sources"})
+
+    # ---- the other workloads (before the CPU baseline, whose host threads
+    # would otherwise share the host with their launches) ----------------------
+    others = {}
+    if not args.no_others:
+        for name in ("cfg1", "cfg2", "cfg3"):
+            if name == args.workload:
+                continue
+            dd = WORKLOAD_DIM[name]
+            Ro = measure(ctx, F, W, torch, name, args.steps, args.warmup,
+                         args.direct_steps_3d if dd == 3 else args.steps)
+            uf, ud = Ro["u_f"].cpu().numpy().astype(np.complex128), Ro["u_d"].cpu().numpy().astype(np.complex128)
+            others[name] = {"workload": f"{name}: {W.CONFIG_NAMES[WORKLOADS[name]]}", "strategy": Ro["sname"],
+                            "fggc_packets_per_s": Ro["ps"].N / (Ro["fggc_ms"] * 1e-3),
+                            "fggc_ms_per_step": Ro["fggc_ms"],
+                            "direct_packets_per_s": Ro["ps"].N / (Ro["direct_ms"] * 1e-3),
+                            "direct_ms_per_step": Ro["direct_ms"],
+                            "speedup_vs_direct": Ro["direct_ms"] / Ro["fggc_ms"],
+                            "fggc_vs_direct_rel_l2": rel(uf, ud), "fggc_vs_direct_max_abs": maxabs(uf, ud)}
+            del Ro, uf, ud
+            torch.cuda.empty_cache()
 
     # ---- CPU baseline: the oracle on a bounded sample -----------------------
     cpu = None
@@ -509,26 +566,6 @@ def main():
                          "direct_fp32_vs_oracle_max_abs": maxabs(gd, ref_d),
                          "oracle_points": npts, "max_abs_is": "max|u - ref| / max|ref| over the points"})
         log("accuracy:", accuracy)
-
-    # ---- the other workloads --------------------------------------------------
-    others = {}
-    if not args.no_others:
-        for name in ("cfg1", "cfg2", "cfg3"):
-            if name == args.workload:
-                continue
-            dd = WORKLOAD_DIM[name]
-            Ro = measure(ctx, F, W, torch, name, args.steps, args.warmup,
-                         args.direct_steps_3d if dd == 3 else args.steps)
-            uf, ud = Ro["u_f"].cpu().numpy().astype(np.complex128), Ro["u_d"].cpu().numpy().astype(np.complex128)
-            others[name] = {"workload": f"{name}: {W.CONFIG_NAMES[WORKLOADS[name]]}", "strategy": Ro["sname"],
-                            "fggc_packets_per_s": Ro["ps"].N / (Ro["fggc_ms"] * 1e-3),
-                            "fggc_ms_per_step": Ro["fggc_ms"],
-                            "direct_packets_per_s": Ro["ps"].N / (Ro["direct_ms"] * 1e-3),
-                            "direct_ms_per_step": Ro["direct_ms"],
-                            "speedup_vs_direct": Ro["direct_ms"] / Ro["fggc_ms"],
-                            "fggc_vs_direct_rel_l2": rel(uf, ud), "fggc_vs_direct_max_abs": maxabs(uf, ud)}
-            del Ro, uf, ud
-            torch.cuda.empty_cache()
 
     serving = None
     if not args.no_serving:

@@ -31,11 +31,14 @@ STAGE_KERNELS = {
     "fggc_coef": ["fggc_coef_kernel"],
     "fggc_accum": ["fggc_agg1_kernel", "fggc_stencil1_kernel", "fggc_stencil_fft1_kernel", "fggc_accum_wave_kernel",
                    "fggc_accum_kernel", "fggc_accum_generic_kernel"],
-    # bucket_pos_kernel also serves the direct sum's sort; its dispatches count here
+    # bucket_pos_kernel and the two-level sort's kernels also serve the
+    # direct sum's sort; their dispatches count here
     "fggc_sort": ["fggc_key_kernel", "fggc_rank_kernel", "count_rowscan_kernel", "count_binscan_kernel",
-                  "bucket_pos_kernel"],
+                  "bucket_pos_kernel", "bucket_rank_kernel", "coarse_perm_kernel", "fine_sort_kernel"],
     "fggc_band_mac": ["band_mac"],
-    "fggc_contract": ["fft_contract_kernel"],
+    "fggc_fused": ["fggc_fused3_kernel"],
+    "fggc_contract": ["fft_contract_kernel", "fft_contract2_kernel", "band_table_kernel"],
+    "fggc_ifft": ["fft_axis_kernel", "fft_axis_mr_kernel"],
     "ds_kernel": ["ds_kernel"],
     "ds_sep2": ["ds_sep2_kernel"],
 }
