@@ -1596,11 +1596,13 @@ __global__ __launch_bounds__(kContractThreads) void fft_contract_kernel(Contract
 // at one slice pair (l0, l1), over every q2 and every slice l2.  For Lc slices
 // l2 at a time it
 //   - adds the Kronecker contributions of the packets that reach its lines
-//     into those lines in LDS (LDS float atomics; the order of the terms in a
-//     cell is unspecified, so sums may differ at the rounding level),
+//     into those lines in LDS (one slice per wave, plain read-modify-writes;
+//     the order of the terms in a cell follows the sort, so sums may differ
+//     at the rounding level),
 //   - transforms the lines over q2 in LDS,
 //   - folds the slices into the grid frequencies m2 with the band weights
-//     gamma_l2 (a table per chunk, FP64 sums per thread),
+//     gamma_l2 (tabulated once per call, staged per chunk; sums per thread in
+//     the working precision: an output gathers one term per slice and alias),
 // and finally writes what the pass over the last dimension writes,
 // Y[l0][l1][q0][q1][m2] (zeros at frequencies no band reaches).  Packets are
 // binned by (p-cell 0, p-cell 1, q-tile, p-cell 2), so the records that reach
@@ -1691,9 +1693,11 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
   // fold and output mapping: TPL threads per line group (a power of two >=
   // the active frequencies), G = blockDim / TPL groups
   const int TPL = p.TPL, G = bs / TPL;
-  double accr[kFusedOut], acci[kFusedOut];
+  // the fold's sums, in the working precision (an output adds at most its
+  // band's aliases of the slices along the last dimension)
+  RR accr[kFusedOut], acci[kFusedOut];
 #pragma unroll
-  for (int c = 0; c < kFusedOut; ++c) accr[c] = acci[c] = 0.0;
+  for (int c = 0; c < kFusedOut; ++c) accr[c] = acci[c] = 0;
   // Accumulation, one slice per wave: wave w adds the contributions to slice
   // l2 = c0 + w, read from the records whose p-cell 2 reaches it -- per
   // (p-cell 0, p-cell 1) that reaches (l0, l1), one contiguous run of bins
@@ -1705,24 +1709,40 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
   // table (the last writer of a slot goes first).  A wave issues its LDS operations in order, so
   // updates of one cell by different instructions are ordered too.
   const int n1r = (int)(a1hi - a1lo + 1), nruns = (int)(a0hi - a0lo + 1) * n1r;
-  for (int c0 = 0; c0 < (int)p.sn[2]; c0 += p.Lc) {
-    const int lcn = min(p.Lc, (int)p.sn[2] - c0);
+  const int sn2 = (int)p.sn[2];
+  // The bounds of run `lane` of the slice wave `wv` takes in the chunk at c:
+  // loaded one chunk ahead into registers, so that their latency overlaps
+  // the previous chunk's work.
+  auto run_bounds = [&](int c, int wv, int lane, int64_t &r0, int64_t &r1) {
+    r0 = r1 = 0;
+    if (lane < nruns && wv < min(p.Lc, sn2 - c)) {
+      const int64_t l2 = c + wv;
+      const int64_t a2lo = max<int64_t>(0, l2 - span), a2hi = min<int64_t>(npc2 - 1, l2);
+      const int64_t a0 = a0lo + lane / n1r, a1 = a1lo + lane % n1r;
+      const int64_t kb = ((a0 * p.npc[1] + a1) * nqt + tq) * npc2;
+      if (a2lo <= a2hi) {
+        r0 = p.start[kb + a2lo];
+        r1 = p.start[kb + a2hi + 1];
+      }
+    }
+  };
+  int64_t nr0, nr1;
+  run_bounds(0, tid0 >> 6, tid0 & 63, nr0, nr1);
+  for (int c0 = 0; c0 < sn2; c0 += p.Lc) {
+    const int lcn = min(p.Lc, sn2 - c0);
     // the thread index through a compiler fence: addresses are formed in each
     // chunk where they are used, not hoisted out of the loop into registers
     int tid = tid0;
     asm volatile("" : "+v"(tid));
     const int wv = tid >> 6, lane = tid & 63;
-    // the runs' bounds of every wave's slice, loaded first, so that their
-    // latency overlaps the clearing of the lines and the band table
     if (lane < nruns && wv < lcn) {
-      const int64_t l2 = c0 + wv;
-      const int64_t a2lo = max<int64_t>(0, l2 - span), a2hi = min<int64_t>(npc2 - 1, l2);
-      const int64_t a0 = a0lo + lane / n1r, a1 = a1lo + lane % n1r;
-      const int64_t kb = ((a0 * p.npc[1] + a1) * nqt + tq) * npc2;
-      const int64_t r0 = a2lo <= a2hi ? p.start[kb + a2lo] : 0, r1 = a2lo <= a2hi ? p.start[kb + a2hi + 1] : 0;
-      s_r0[wv * kFusedRuns + lane] = r0;
-      s_n[wv * kFusedRuns + lane] = r1 - r0;
+      s_r0[wv * kFusedRuns + lane] = nr0;
+      s_n[wv * kFusedRuns + lane] = nr1 - nr0;
     }
+    if (c0 + p.Lc < sn2) run_bounds(c0 + p.Lc, wv, lane, nr0, nr1);
+    // this chunk's band weights: loaded now, stored to LDS after the
+    // accumulation (the fold reads them), so that the accumulation hides
+    // their latency
     for (int e = tid; e < lcn * ng; e += bs) gam[e] = (RR)p.gtab[(int64_t)c0 * ng + e];
     for (int e = tid; e < lcn * P * rs; e += bs) cl[e] = T{0, 0};
     __syncthreads();
@@ -1836,14 +1856,14 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
         const T *fq = cl + (size_t)lg0 * rs + (int)(kk & msk2);
         const RR *gb = gam + (kk - p.kmin);
         for (int l = 0; l < lcn; ++l) {
-          const double gv = (double)gb[l * ng];
-          if (gv == 0.0) continue;  // outside this slice's band (coherent: t runs along k)
+          const RR gv = gb[l * ng];
+          if (gv == (RR)0) continue;  // outside this slice's band (coherent: t runs along k)
 #pragma unroll
           for (int c = 0; c < kFusedOut; ++c) {
             if (lg0 + c * G >= P) break;
             const T v = fq[((size_t)l * P + c * G) * rs];
-            accr[c] = fma(gv, (double)v.x, accr[c]);
-            acci[c] = fma(gv, (double)v.y, acci[c]);
+            accr[c] = fma(gv, v.x, accr[c]);
+            acci[c] = fma(gv, v.y, acci[c]);
           }
         }
       }
@@ -1872,7 +1892,7 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
 // 128-byte run of the input per (slice, n)) at one (o, a); for Lc slices at a
 // time it loads the W lines into LDS (as rows, padded for the register FFT),
 // transforms them with lds_fft2_rows and folds them through the band weights
-// gamma (a table per call) into FP64 sums, thread (group g, frequency t)
+// gamma (a table per call) into sums in the working precision, thread (group g, frequency t)
 // holding frequency t of lines g, g + G, ...  The sums go out through LDS, so
 // that the writes run along b as well.
 struct Contract2Params {
@@ -1893,21 +1913,21 @@ __global__ __launch_bounds__(kFusedThreads) void fft_contract2_kernel(Contract2P
   const int rs = fft2_row_stride(lgN);
   T *cl = reinterpret_cast<T *>(smem_raw);            // [Lc][W][rs]
   T *stw = cl + (size_t)p.Lc * W * rs;                // [N]
-  double *gam = reinterpret_cast<double *>(stw + N);  // [Lc][ng]
+  RR *gam = reinterpret_cast<RR *>(stw + N);          // [Lc][ng], working precision
   for (int i = tid0; i < N; i += bs) stw[i] = tw[i];
   const int64_t nbc = p.B / W;
   const int64_t g = blockIdx.x, bc = g % nbc, oa = g / nbc;  // oa = o * A + a
   const int64_t o = oa / p.A, a = oa % p.A, b0 = bc * W;
   const int TPL = p.TPL, G = bs / TPL;
   const int kmod = (int)(((p.kmin % M) + M) % M);
-  double accr[kFusedOut], acci[kFusedOut];
+  RR accr[kFusedOut], acci[kFusedOut];  // sums in the working precision
 #pragma unroll
-  for (int c = 0; c < kFusedOut; ++c) accr[c] = acci[c] = 0.0;
+  for (int c = 0; c < kFusedOut; ++c) accr[c] = acci[c] = 0;
   for (int l0 = 0; l0 < (int)p.L; l0 += p.Lc) {
     const int lcn = min(p.Lc, (int)p.L - l0);
     int tid = tid0;
     asm volatile("" : "+v"(tid));
-    for (int e = tid; e < lcn * ng; e += bs) gam[e] = p.gtab[(int64_t)l0 * ng + e];
+    for (int e = tid; e < lcn * ng; e += bs) gam[e] = (RR)p.gtab[(int64_t)l0 * ng + e];
     // rows (l, w) of N, loaded with w fastest (runs of W along b), eight
     // loads in flight per thread before their LDS stores
     const int tot = lcn * N * W;
@@ -1936,16 +1956,16 @@ __global__ __launch_bounds__(kFusedThreads) void fft_contract2_kernel(Contract2P
     if (t < nact) {
       for (int64_t kk = p.kmin + t; kk <= p.kmax; kk += M) {
         const T *fq = cl + (size_t)lg0 * rs + (int)(kk & (N - 1));
-        const double *gb = gam + (kk - p.kmin);
+        const RR *gb = gam + (kk - p.kmin);
         for (int l = 0; l < lcn; ++l) {
-          const double gv = gb[l * ng];
-          if (gv == 0.0) continue;  // outside this slice's band
+          const RR gv = gb[l * ng];
+          if (gv == (RR)0) continue;  // outside this slice's band
 #pragma unroll
           for (int c = 0; c < kFusedOut; ++c) {
             if (lg0 + c * G >= W) break;
             const T v = fq[((size_t)l * W + c * G) * rs];
-            accr[c] = fma(gv, (double)v.x, accr[c]);
-            acci[c] = fma(gv, (double)v.y, acci[c]);
+            accr[c] = fma(gv, v.x, accr[c]);
+            acci[c] = fma(gv, v.y, acci[c]);
           }
         }
       }
@@ -2116,7 +2136,7 @@ Contract2Plan contract2_plan(const FggcArgs &a, int k, bool fused3) {
   auto shm_of = [&](int lc) {
     // the lines double as the output staging [M][W]
     const size_t lines = std::max<size_t>((size_t)lc * W * rs, (size_t)M * W);
-    return lines * es + (size_t)N * es + (size_t)lc * ng * 8;
+    return lines * es + (size_t)N * es + (size_t)lc * ng * (es / 2);
   };
   while (Lc > 1 && shm_of(Lc) > 80 * 1024) --Lc;
   if ((int64_t)Lc * W > maxrows || shm_of(Lc) > kFusedMaxLds) return c;
