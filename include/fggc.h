@@ -369,8 +369,10 @@ int fggc_learn_packets(fggc_ctx *ctx, int32_t d, int64_t Nm, int64_t n, const in
  * grid->n[k] must be of the form 2^a 3^b 5^c (2 .. 16384 for 1D FP32, 8192
  * for FP64, 4096 for d >= 2).  Nq as in fggc_strategy.
  * FGGC_FP64: FP64 throughout.  FGGC_FP32: least squares, phase reductions
- * and band weights in FP64; cells, FFTs and products in FP32; spectrum
- * accumulated in FP64.
+ * and band weights in FP64; cells, FFTs and products in FP32; the band folds
+ * sum one term per slice and alias, in FP64 in one dimension and in the
+ * general separable pass, in FP32 in the register-FFT passes and the fused
+ * three-dimensional finish.
  * Errors: as fggc_direct_sum, plus FGGC_EUNSUPPORTED for sizes outside the
  * ranges above and FGGC_EBUDGET when the cell array cannot fit.
  */
