@@ -1652,12 +1652,17 @@ __global__ void band_table_kernel(int64_t L, int64_t kmin, int64_t kmax, int64_t
   gtab[e] = ex < cut ? 0.0 : cst * exp(ex);
 }
 
-template <int NQ, int NP, typename T>
-__global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params p, T *__restrict__ Y,
-                                                                     const T *__restrict__ tw) {
+template <int D, int NQ, int NP, typename T, int MAXLG = 8, int NF = 1>
+__global__ __launch_bounds__(kFusedThreads) void fggc_fused_kernel(Fused3Params p, T *__restrict__ Y,
+                                                                    const T *__restrict__ tw) {
   using RR = decltype(T{}.x);
   constexpr int N1 = NQ * NP;
-  constexpr int RB = rec_bytes<3, N1, T>();
+  constexpr int RB = rec_bytes<D, N1, T>();
+  // the lines' leading dimensions: 0 and 1 in three dimensions, 0 alone in
+  // two (the parameters then give dimension 1 one slice, one q-cell and a
+  // tile of one line); the last dimension is the lines' own
+  constexpr int NQ1 = D == 3 ? NQ : 1;
+  constexpr int CPL = kFusedOut / NF;  // lines per thread in the fold
   constexpr int NV = RB / 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lgN = p.lgN, N = 1 << lgN, T0 = p.T0, T1 = p.T1, P = T0 * T1;
@@ -1665,7 +1670,7 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
   const int ng = (int)(p.kmax - p.kmin + 1);
   const int nact = min(M, ng);
   const int bs = (int)blockDim.x, tid0 = (int)threadIdx.x;
-  // the lines (at most 256 points) are transformed in two register passes
+  // the lines (at most 512 points) are transformed in two register passes
   // (lds_fft2_rows) on padded rows
   const int rs = fft2_row_stride(lgN);               // row stride of the lines
   T *cl = reinterpret_cast<T *>(smem_raw);            // [Lc][P][rs] the chunk's lines
@@ -1740,18 +1745,25 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
       s_n[wv * kFusedRuns + lane] = nr1 - nr0;
     }
     if (c0 + p.Lc < sn2) run_bounds(c0 + p.Lc, wv, lane, nr0, nr1);
-    // this chunk's band weights: loaded now, stored to LDS after the
-    // accumulation (the fold reads them), so that the accumulation hides
-    // their latency
+    // this chunk's band weights into LDS (the fold reads them)
     for (int e = tid; e < lcn * ng; e += bs) gam[e] = (RR)p.gtab[(int64_t)c0 * ng + e];
     for (int e = tid; e < lcn * P * rs; e += bs) cl[e] = T{0, 0};
     __syncthreads();
+    // the chunk's records over all its slices (read before the barrier that
+    // ends the accumulation, so that the next chunk may rewrite the runs)
+    int64_t ctotal = 0;
+    for (int w = 0; w < lcn; ++w)
+      for (int x = 0; x < nruns; ++x) ctotal += s_n[w * kFusedRuns + x];
     if (wv < lcn) {
       const int l2 = c0 + wv;
       int64_t total = 0;
       const int64_t *wr0 = s_r0 + wv * kFusedRuns, *wn = s_n + wv * kFusedRuns;
       for (int x = 0; x < nruns; ++x) total += wn[x];
-      volatile int *claim = s_claim + wv * kFusedClaim;
+      // (through an LDS-qualified pointer: the table lives in dynamic LDS,
+      // and a generic volatile pointer would be accessed with flat
+      // instructions)
+      volatile __attribute__((address_space(3))) int *claim =
+          (volatile __attribute__((address_space(3))) int *)(s_claim + wv * kFusedClaim);
       for (int64_t base = 0; base < total; base += 64) {
         const int64_t i = base + lane;
         bool todo = i < total;
@@ -1770,48 +1782,60 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
 #pragma unroll
         for (int v = 0; v < (kWhole ? NV : 2); ++v)
           raw[v] = todo ? reinterpret_cast<const uint4 *>(rec)[v] : make_uint4(0, 0, 0, 0);
-        const RecIdx<3> ri = *reinterpret_cast<const RecIdx<3> *>(raw);
-        int b0 = -1, b1 = -1, b2 = -1;
+        const RecIdx<D> ri = *reinterpret_cast<const RecIdx<D> *>(raw);
+        constexpr int KL = D - 1;  // the last dimension's index in the record
+        int b0 = -1, b1 = D == 3 ? -1 : 0, b2 = -1;
 #pragma unroll
         for (int b = 0; b < NP; ++b) {
           if ((int64_t)ri.pc[0] + p.dp[b] - p.mindp == l0) b0 = b;
-          if ((int64_t)ri.pc[1] + p.dp[b] - p.mindp == l1) b1 = b;
-          if (ri.pc[2] + p.dp[b] - p.mindp == l2) b2 = b;
+          if constexpr (D == 3)
+            if ((int64_t)ri.pc[1] + p.dp[b] - p.mindp == l1) b1 = b;
+          if (ri.pc[KL] + p.dp[b] - p.mindp == l2) b2 = b;
         }
         todo = todo && b0 >= 0 && b1 >= 0 && b2 >= 0;
-        int la0[NQ], la1[NQ], q2[NQ];
+        int la0[NQ], la1[NQ1], q2[NQ];
 #pragma unroll
         for (int a = 0; a < NQ; ++a) {
-          const int v0 = ((ri.q[0] + p.dq[a]) & msk0) - q00, v1 = ((ri.q[1] + p.dq[a]) & msk1) - q10;
+          const int v0 = ((ri.q[0] + p.dq[a]) & msk0) - q00;
           la0[a] = v0 >= 0 && v0 < T0 ? v0 : -1;
-          la1[a] = v1 >= 0 && v1 < T1 ? v1 : -1;
-          q2[a] = (ri.q[2] + p.dq[a]) & msk2;
+          if constexpr (D == 3) {
+            const int v1 = ((ri.q[1] + p.dq[a]) & msk1) - q10;
+            la1[a] = v1 >= 0 && v1 < T1 ? v1 : -1;
+          }
+          q2[a] = (ri.q[KL] + p.dq[a]) & msk2;
         }
-        // the coefficients this slice takes: dims 0 and 1 at (b0, b1), dim 2 at b2
-        T u0[NQ], u1[NQ], u2[NQ];
+        if constexpr (D == 2) la1[0] = 0;
+        // the coefficients this slice takes: the leading dimensions at (b0,
+        // b1), the last at b2 (two dimensions: dimension 1 is the last, and
+        // u1 = 1 stands for the missing middle one)
+        T u0[NQ], u1[NQ1], u2[NQ];
+        if constexpr (D == 2) u1[0] = T{1, 0};
         if constexpr (kWhole) {
-          const T *c = reinterpret_cast<const T *>(reinterpret_cast<const char *>(raw) + rec_idx_bytes<3>());
+          const T *c = reinterpret_cast<const T *>(reinterpret_cast<const char *>(raw) + rec_idx_bytes<D>());
 #pragma unroll
           for (int a = 0; a < NQ; ++a) {
-            u0[a] = u1[a] = u2[a] = T{0, 0};
+            u0[a] = u2[a] = T{0, 0};
+            if constexpr (D == 3) u1[a] = T{0, 0};
 #pragma unroll
             for (int b = 0; b < NP; ++b) {
               if (b == b0) u0[a] = c[a * NP + b];
-              if (b == b1) u1[a] = c[N1 + a * NP + b];
-              if (b == b2) u2[a] = c[2 * N1 + a * NP + b];
+              if constexpr (D == 3)
+                if (b == b1) u1[a] = c[N1 + a * NP + b];
+              if (b == b2) u2[a] = c[KL * N1 + a * NP + b];
             }
           }
         } else {
-          const T *c = reinterpret_cast<const T *>(rec + rec_idx_bytes<3>());
+          const T *c = reinterpret_cast<const T *>(rec + rec_idx_bytes<D>());
 #pragma unroll
           for (int a = 0; a < NQ; ++a) {
             u0[a] = todo ? c[a * NP + b0] : T{0, 0};
-            u1[a] = todo ? c[N1 + a * NP + b1] : T{0, 0};
-            u2[a] = todo ? c[2 * N1 + a * NP + b2] : T{0, 0};
+            if constexpr (D == 3) u1[a] = todo ? c[N1 + a * NP + b1] : T{0, 0};
+            u2[a] = todo ? c[KL * N1 + a * NP + b2] : T{0, 0};
           }
         }
-        const uint32_t h = ((uint32_t)ri.q[0] * 0x9E3779B1u + (uint32_t)ri.q[1] * 0x85EBCA77u +
-                            (uint32_t)ri.q[2] * 0xC2B2AE3Du) >> (32 - kFusedClaimBits);
+        uint32_t h = (uint32_t)ri.q[0] * 0x9E3779B1u + (uint32_t)ri.q[KL] * 0xC2B2AE3Du;
+        if constexpr (D == 3) h += (uint32_t)ri.q[1] * 0x85EBCA77u;
+        h >>= 32 - kFusedClaimBits;
         T *rows = cl + (size_t)wv * P * rs;
         while (__ballot(todo)) {
           if (todo) claim[h] = lane;
@@ -1821,15 +1845,15 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
             // two q-shifts: every contribution unrolled; four: the first
             // dimension's shift in a loop (the 64-fold unrolling would not fit
             // the registers), its values picked without indexing registers
-#pragma unroll(NQ == 2 ? NQ : 1)
+#pragma unroll(NQ == 2 || D == 2 ? NQ : 1)
             for (int a0i = 0; a0i < NQ; ++a0i) {
               const int la0v = pick<NQ>(la0, a0i);
               if (la0v < 0) continue;
               const T u0v = pick<NQ>(u0, a0i);
 #pragma unroll
-              for (int a1i = 0; a1i < NQ; ++a1i) {
+              for (int a1i = 0; a1i < NQ1; ++a1i) {
                 if (la1[a1i] < 0) continue;
-                const T uw = cmul(u0v, u1[a1i]);
+                const T uw = D == 3 ? cmul(u0v, u1[a1i]) : u0v;
                 T *line = rows + (la0v * T1 + la1[a1i]) * rs;
 #pragma unroll
                 for (int a2i = 0; a2i < NQ; ++a2i) {
@@ -1847,23 +1871,30 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
       }
     }
     __syncthreads();
-    lds_fft2_rows<T>(cl, lgN, lcn * P, rs, stw, tid, bs);
+    // a chunk whose slices took no record left its lines zero: nothing to
+    // transform or fold (sparse packet sets skip most chunks)
+    if (ctotal == 0) continue;
+    lds_fft2_rows<T, MAXLG>(cl, lgN, lcn * P, rs, stw, tid, bs);
     // thread (g, t): frequency t of lines g, g + G, g + 2 G, ... -- one band
     // weight per (slice, alias) serves all of them
+    // sum f * CPL + c of a thread: frequency t + f TPL of line lg0 + c G
     const int t = tid & (TPL - 1), lg0 = tid / TPL;
-    if (t < nact) {
-      for (int64_t kk = p.kmin + t; kk <= p.kmax; kk += M) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int tf = t + f * TPL;
+      if (tf >= nact) break;
+      for (int64_t kk = p.kmin + tf; kk <= p.kmax; kk += M) {
         const T *fq = cl + (size_t)lg0 * rs + (int)(kk & msk2);
         const RR *gb = gam + (kk - p.kmin);
         for (int l = 0; l < lcn; ++l) {
           const RR gv = gb[l * ng];
           if (gv == (RR)0) continue;  // outside this slice's band (coherent: t runs along k)
 #pragma unroll
-          for (int c = 0; c < kFusedOut; ++c) {
+          for (int c = 0; c < CPL; ++c) {
             if (lg0 + c * G >= P) break;
             const T v = fq[((size_t)l * P + c * G) * rs];
-            accr[c] = fma(gv, v.x, accr[c]);
-            acci[c] = fma(gv, v.y, acci[c]);
+            accr[f * CPL + c] = fma(gv, v.x, accr[f * CPL + c]);
+            acci[f * CPL + c] = fma(gv, v.y, acci[f * CPL + c]);
           }
         }
       }
@@ -1872,15 +1903,20 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused3_kernel(Fused3Params
   }
   const int64_t base = (l0 * p.sn[1] + l1) * p.Nq[0];
   const int t = tid0 & (TPL - 1), lg0 = tid0 / TPL;
-  // every frequency of this thread's lines: the band's sums, zeros elsewhere
-  for (int tt = t; tt < M; tt += TPL) {
+  // every frequency of this thread's lines: the band's sums in the first NF
+  // blocks of TPL frequencies, zeros elsewhere
+  for (int tt = t, f = 0; tt < M; tt += TPL, ++f) {
     const int kp = (kmod + tt) % M;
 #pragma unroll
-    for (int c = 0; c < kFusedOut; ++c) {
+    for (int c = 0; c < CPL; ++c) {
       const int line = lg0 + c * G;
       if (line >= P) break;
       const int64_t q0 = q00 + line / T1, q1 = q10 + line % T1;
-      Y[((base + q0) * p.Nq[1] + q1) * p.M + kp] = tt < nact ? T{(RR)accr[c], (RR)acci[c]} : T{0, 0};
+      T v = T{0, 0};
+#pragma unroll
+      for (int f2 = 0; f2 < NF; ++f2)
+        if (f == f2 && tt < nact) v = T{(RR)accr[f2 * CPL + c], (RR)acci[f2 * CPL + c]};
+      Y[((base + q0) * p.Nq[1] + q1) * p.M + kp] = v;
     }
   }
 }
@@ -2001,8 +2037,8 @@ struct FggcLayout {
   // three dimensions: accumulation fused with the pass over the last
   // dimension (no dense cell array); lines T0 x T1 per workgroup, Lc slices
   // of the last dimension per LDS chunk, the kernel's LDS bytes
-  bool fused3;
-  int fT0, fT1, fLc, fnq, fnp, fTPL, fThreads;
+  bool fused;
+  int fT0, fT1, fLc, fnq, fnp, fTPL, fNF, fThreads;
   size_t fshm;
   int agg_splits;  // one dimension: workgroups (and copies of the aggregate) per bin
   int64_t ncells, nslices, npts, nbins, nslots, tiles, ntq[3], tile[3], npc[3], pmin[3], S[3], nsw[3];
@@ -2023,54 +2059,78 @@ void band_range(const FggcArgs &a, int k, int64_t &kmin, int64_t &kmax) {
   kmax = (int64_t)std::ceil((double)(a.slo[k] + a.sn[k] - 1) * a.dp[k] / a.eps + a.cK / se) + 1;
 }
 
-// The fused three-dimensional finish, when the strategy and sizes allow it:
-// a tensor shift set of 2 x 2, 4 x 2 or 2 x 4, power-of-two q-meshes of at
-// least 4 (dims 0, 1) and 8 to 256 (dim 2) points, a workgroup's outputs and
-// its LDS chunk within their budgets.
-bool plan_fused3(const FggcArgs &a, FggcLayout &L, int nq, int np) {
-  if (a.g.d != 3) return false;
+// The fused finish (accumulation and the pass over the last dimension in one
+// kernel), when the strategy and sizes allow it: two or three dimensions, a
+// tensor shift set of 2 x 2, 4 x 2 or 2 x 4, power-of-two q-meshes of at
+// least 4 points along the leading dimensions and 8 to 256 along the last
+// (512 in two dimensions in FP32),
+// a workgroup's outputs and its LDS chunk within their budgets.
+bool plan_fused(const FggcArgs &a, FggcLayout &L, int nq, int np) {
+  const int d = a.g.d;
+  if (d != 2 && d != 3) return false;
   if (!((nq == 2 && np == 2) || (nq == 4 && np == 2) || (nq == 2 && np == 4))) return false;
   if (L.N1 != nq * np) return false;
-  const int64_t N = a.Nq[2];
-  if (N < 8 || N > 256 || !is_pow2(N) || a.Nq[0] < 4 || a.Nq[1] < 4 || !is_pow2(a.Nq[0]) || !is_pow2(a.Nq[1]))
-    return false;
+  const int kl = d - 1;
+  const int64_t N = a.Nq[kl];
+  if (N < 8 || N > 512 || !is_pow2(N) || a.Nq[0] < 4 || !is_pow2(a.Nq[0])) return false;
+  // 512-point lines: two dimensions in FP32 only (their first FFT pass holds
+  // 32 points per thread)
+  if (N == 512 && (d != 2 || a.precision == FGGC_FP64)) return false;
+  if (d == 3 && (a.Nq[1] < 4 || !is_pow2(a.Nq[1]))) return false;
   const int qspan = L.maxdq - L.mindq + 1, pspan = L.maxdp - L.mindp + 1;
-  if (pspan * pspan > kFusedRuns) return false;  // the runs of bins a chunk reads
+  if ((d == 3 ? pspan * pspan : pspan) > kFusedRuns) return false;  // the runs of bins a chunk reads
+  // two dimensions: fused only when the packets' contributions are fewer than
+  // the cells (a sparse box, where the dense array would be mostly zeros);
+  // dense sets are faster through the cell array and its tiled accumulation
+  if (d == 2) {
+    const double contrib = (double)a.pk->N * (double)(nq * np) * (double)(nq * np);
+    const double cells = (double)a.sn[0] * (double)a.sn[1] * (double)a.Nq[0] * (double)a.Nq[1];
+    if (contrib >= cells) return false;
+  }
   int64_t kmin, kmax;
-  band_range(a, 2, kmin, kmax);
-  const int64_t ng = kmax - kmin + 1, nact = std::min<int64_t>(a.g.n[2], ng);
-  // fold: TPL threads per group of lines, one frequency each (TPL a power of
-  // two >= the active frequencies), kFusedThreads / TPL groups
-  int64_t TPL = 1;
-  while (TPL < nact) TPL *= 2;
-  if (TPL > kFusedThreads) return false;
-  // lines per workgroup and threads: 4 x 2 lines on 256 threads (several
-  // workgroups per CU), else 4 x 4 on 512, else 2 x 2 on 256 or 512; a tile
-  // spans the q-shifts, and a thread holds at most kFusedOut outputs
-  static const int tt[4][3] = {{4, 2, 256}, {4, 4, 512}, {2, 2, 256}, {2, 2, 512}};
+  band_range(a, kl, kmin, kmax);
+  const int64_t ng = kmax - kmin + 1, nact = std::min<int64_t>(a.g.n[kl], ng);
+  // fold: TPL threads per group of lines (a power of two), one frequency
+  // each in every one of NF <= 2 blocks of TPL frequencies
+  int64_t TPL0 = 1;
+  while (TPL0 < nact) TPL0 *= 2;
+  if (TPL0 > 2 * kFusedThreads) return false;
+  // lines per workgroup and threads.  Three dimensions: 4 x 2 lines on 256
+  // threads (several workgroups per CU), else 4 x 4 on 512, else 2 x 2 on 256
+  // or 512.  Two dimensions: 8 lines on 256 or 512 threads, else 4.  A tile
+  // spans the q-shifts, and a thread holds at most kFusedOut outputs.
+  static const int t3[4][3] = {{4, 2, 256}, {4, 4, 512}, {2, 2, 256}, {2, 2, 512}};
+  static const int t2[4][3] = {{8, 1, 256}, {8, 1, 512}, {4, 1, 256}, {4, 1, 512}};
   int T0 = 0, T1 = 0, threads = 0;
-  for (auto &t : tt)
-    if (t[0] >= qspan && t[1] >= qspan && t[0] <= a.Nq[0] && t[1] <= a.Nq[1] && TPL <= t[2] &&
-        (int64_t)t[0] * t[1] * TPL <= (int64_t)t[2] * kFusedOut) {
-      T0 = t[0];
-      T1 = t[1];
-      threads = t[2];
-      break;
-    }
+  int64_t TPL = 0, NF = 0, CPL = 0;
+  for (auto &t : (d == 3 ? t3 : t2)) {
+    if (t[0] < qspan || (d == 3 && t[1] < qspan) || t[0] > a.Nq[0] || (d == 3 && t[1] > a.Nq[1])) continue;
+    const int64_t tpl = std::min<int64_t>(TPL0, t[2]), nf = (nact + tpl - 1) / tpl, g = t[2] / tpl;
+    const int64_t cpl = ((int64_t)t[0] * t[1] + g - 1) / g;
+    if (nf > (d == 3 ? 1 : 2) || nf * cpl > kFusedOut) continue;
+    T0 = t[0];
+    T1 = t[1];
+    threads = t[2];
+    TPL = tpl;
+    NF = nf;
+    CPL = cpl;
+    break;
+  }
   if (!T0) return false;
   const bool f64 = a.precision == FGGC_FP64;
   const size_t es = f64 ? 16 : 8;
   int lg = 0;
   while (((int64_t)1 << lg) < N) ++lg;
   const int64_t P = (int64_t)T0 * T1;
-  // lines of N <= 256 points: the two-pass register FFT (lds_fft2_rows), one
+  // lines of N <= 512 points: the two-pass register FFT (lds_fft2_rows), one
   // unit per thread in its first pass and up to two in its second, on rows
   // padded to fft2_row_stride
   const int64_t rs = fft2_row_stride(lg);
   const int64_t N1 = (int64_t)1 << ((lg + 1) / 2), N2 = (int64_t)1 << (lg / 2);
   const int64_t maxrows = std::min<int64_t>(threads / N2, 2 * threads / N1);
+  if (P > maxrows) return false;
   // at most one slice per wave (the accumulation gives each wave a slice)
-  int Lc = (int)std::min<int64_t>(std::min<int64_t>(a.sn[2], threads / 64), std::max<int64_t>(1, maxrows / P));
+  int Lc = (int)std::min<int64_t>(std::min<int64_t>(a.sn[kl], threads / 64), std::max<int64_t>(1, maxrows / P));
   // lines, twiddles, runs, the chunk's band weights (in the working
   // precision) and the claim tables
   const size_t waves = threads / 64;
@@ -2085,11 +2145,12 @@ bool plan_fused3(const FggcArgs &a, FggcLayout &L, int nq, int np) {
   const size_t budget = threads == 256 ? 32 * 1024 : 80 * 1024;
   while (Lc > 1 && shm_of(Lc) > budget) --Lc;
   if ((int64_t)Lc * P > maxrows || shm_of(Lc) > kFusedMaxLds) return false;
-  const int64_t blocks = a.sn[0] * a.sn[1] * (a.Nq[0] / T0) * (a.Nq[1] / T1);
+  const int64_t blocks = a.sn[0] * (d == 3 ? a.sn[1] * (a.Nq[1] / T1) : 1) * (a.Nq[0] / T0);
   if (blocks >= ((int64_t)1 << 31)) return false;
   L.fT0 = T0;
   L.fT1 = T1;
   L.fTPL = (int)TPL;
+  L.fNF = (int)NF;
   L.fThreads = threads;
   L.fLc = Lc;
   L.fnq = nq;
@@ -2108,10 +2169,10 @@ struct Contract2Plan {
   size_t shm = 0;
 };
 
-Contract2Plan contract2_plan(const FggcArgs &a, int k, bool fused3) {
+Contract2Plan contract2_plan(const FggcArgs &a, int k, bool fused) {
   Contract2Plan c;
   const int d = a.g.d;
-  if (d < 2 || k >= d || (d == 2 && k == 1) || (fused3 && k == 2)) return c;
+  if (d < 2 || k >= d || (d == 2 && k == 1) || (fused && k == d - 1)) return c;
   const int64_t N = a.Nq[k];
   if (N < 8 || N > 256 || (N & (N - 1))) return c;
   int lg = 0;
@@ -2148,7 +2209,7 @@ Contract2Plan contract2_plan(const FggcArgs &a, int k, bool fused3) {
   return c;
 }
 
-bool contract2_ok(const FggcArgs &a, const FggcLayout &L, int k) { return contract2_plan(a, k, L.fused3).ok; }
+bool contract2_ok(const FggcArgs &a, const FggcLayout &L, int k) { return contract2_plan(a, k, L.fused).ok; }
 
 FggcLayout fggc_layout(const FggcArgs &a, bool allow_fused = true) {
   FggcLayout L{};
@@ -2171,7 +2232,7 @@ FggcLayout fggc_layout(const FggcArgs &a, bool allow_fused = true) {
     int np = 0;
     for (int m = 0; m < l0.n1; ++m)
       if (l0.dq[m] == l0.dq[0]) ++np;
-    L.fused3 = allow_fused && plan_fused3(a, L, l0.n1 / np, np);
+    L.fused = allow_fused && plan_fused(a, L, l0.n1 / np, np);
   }
   // q-tile and slice window of one accumulation workgroup: the LDS holds
   // S^d * tile^d cells; a tile is at least as wide as the q-shift set
@@ -2202,7 +2263,7 @@ FggcLayout fggc_layout(const FggcArgs &a, bool allow_fused = true) {
           fail(FGGC_EUNSUPPORTED, "q-mesh of " + std::to_string(a.Nq[k]) +
                                       " cells: its power-of-two factor is below the q-shift span");
       }
-      if (L.fused3) L.tile[k] = k == 0 ? L.fT0 : (k == 1 ? L.fT1 : a.Nq[k]);
+      if (L.fused) L.tile[k] = k == d - 1 ? a.Nq[k] : (k == 0 ? L.fT0 : L.fT1);
       L.ntq[k] = a.Nq[k] / L.tile[k];
       L.pmin[k] = a.slo[k] - L.mindp;
       L.npc[k] = a.sn[k] - (L.maxdp - L.mindp);
@@ -2224,7 +2285,7 @@ FggcLayout fggc_layout(const FggcArgs &a, bool allow_fused = true) {
   L.agg1 = d == 1;
   // key slots per packet: own tile, or 2^d with halo tiles (the fused finish
   // has one tile along the last dimension: halo slots in dims 0 and 1 only)
-  L.ns = L.agg1 ? 1 : (L.fused3 ? 4 : (1 << d));
+  L.ns = L.agg1 ? 1 : (L.fused ? 1 << (d - 1) : (1 << d));
   L.nslots = a.pk->N * L.ns;
   const int64_t NS = std::max<int64_t>(L.nslots, 1);
   size_t o = 0;
@@ -2248,7 +2309,7 @@ FggcLayout fggc_layout(const FggcArgs &a, bool allow_fused = true) {
   }
   L.off_agg = put(L.agg1 ? (size_t)L.agg_splits * L.npc[0] * a.Nq[0] * L.N1 * es : 0);
   (void)N;
-  L.off_cells = put(L.fused3 ? 0 : (size_t)L.ncells * es);
+  L.off_cells = put(L.fused ? 0 : (size_t)L.ncells * es);
   // after the cells: the cells-only entry point (whose cells are the
   // caller's) writes every tile and takes no occupancy map
   L.off_occ = put(d == 2 ? (size_t)L.nslices * L.ntq[0] * L.ntq[1] : 0);  // empty-tile map
@@ -2270,7 +2331,7 @@ FggcLayout fggc_layout(const FggcArgs &a, bool allow_fused = true) {
   // dense register-FFT pass contracts
   for (int k = 0; k < 3; ++k) {
     L.off_gam[k] = 0;
-    const bool fusedk = L.fused3 && k == 2, densek = d >= 2 && contract2_ok(a, L, k);
+    const bool fusedk = L.fused && k == d - 1, densek = d >= 2 && contract2_ok(a, L, k);
     if (k < d && (fusedk || densek)) {
       int64_t kmin, kmax;
       band_range(a, k, kmin, kmax);
@@ -2305,7 +2366,7 @@ void launch_coef_accum(const FggcArgs &a, const FggcLayout &L, const CoefParams 
     else fggc_coef_kernel<D, N1, 0, 0, T><<<g, b, 0, s>>>(cp, pos, recs);
     FGGC_HIP(hipGetLastError());
   }
-  if (L.fused3) return;  // the fused finish accumulates the records itself
+  if (L.fused) return;  // the fused finish accumulates the records itself
   AccParams ap{};
   ap.recs = recs;
   ap.start = start;
@@ -2482,7 +2543,7 @@ void cells_stage(const FggcArgs &a, const FggcLayout &L, char *base, void *cells
   kp.mindq = L.mindq;
   kp.maxdq = L.maxdq;
   kp.ns = L.ns;
-  kp.pc_last = L.fused3 ? 1 : 0;
+  kp.pc_last = L.fused ? 1 : 0;
   const CountPlan cpn = count_plan(L.nslots, L.nbins, L.ns);
   uint32_t *rank = (uint32_t *)(base + L.off_sort + cpn.off_rank);
   {
@@ -2668,7 +2729,7 @@ void launch_contract2(const FggcArgs &a, const FggcLayout &L, int k, char *base,
       g_c2_attr = true;
     }
   }
-  const Contract2Plan c = contract2_plan(a, k, L.fused3);
+  const Contract2Plan c = contract2_plan(a, k, L.fused);
   if (!c.ok) fail(FGGC_EDEVICE, "internal: dense pass not planned");
   const int d = a.g.d;
   Contract2Params p{};
@@ -2703,60 +2764,111 @@ bool g_fused_attr = false;
 std::mutex g_fused_mu;
 
 template <typename T>
-void launch_fused3(const FggcArgs &a, const FggcLayout &L, char *base, const MacParams &m, T *out,
-                   hipStream_t s) {
+void launch_fused(const FggcArgs &a, const FggcLayout &L, char *base, const MacParams &m, T *out,
+                  hipStream_t s) {
   {
     std::lock_guard<std::mutex> lk(g_fused_mu);
     if (!g_fused_attr) {
-      const void *ks[] = {(const void *)fggc_fused3_kernel<2, 2, float2>,
-                          (const void *)fggc_fused3_kernel<4, 2, float2>,
-                          (const void *)fggc_fused3_kernel<2, 4, float2>,
-                          (const void *)fggc_fused3_kernel<2, 2, double2>,
-                          (const void *)fggc_fused3_kernel<4, 2, double2>,
-                          (const void *)fggc_fused3_kernel<2, 4, double2>};
+      const void *ks[] = {(const void *)fggc_fused_kernel<3, 2, 2, float2>,
+                          (const void *)fggc_fused_kernel<3, 4, 2, float2>,
+                          (const void *)fggc_fused_kernel<3, 2, 4, float2>,
+                          (const void *)fggc_fused_kernel<3, 2, 2, double2>,
+                          (const void *)fggc_fused_kernel<3, 4, 2, double2>,
+                          (const void *)fggc_fused_kernel<3, 2, 4, double2>,
+                          (const void *)fggc_fused_kernel<2, 2, 2, float2>,
+                          (const void *)fggc_fused_kernel<2, 4, 2, float2>,
+                          (const void *)fggc_fused_kernel<2, 2, 4, float2>,
+                          (const void *)fggc_fused_kernel<2, 2, 2, double2>,
+                          (const void *)fggc_fused_kernel<2, 4, 2, double2>,
+                          (const void *)fggc_fused_kernel<2, 2, 4, double2>,
+                          (const void *)fggc_fused_kernel<2, 2, 2, float2, 8, 2>,
+                          (const void *)fggc_fused_kernel<2, 4, 2, float2, 8, 2>,
+                          (const void *)fggc_fused_kernel<2, 2, 4, float2, 8, 2>,
+                          (const void *)fggc_fused_kernel<2, 2, 2, double2, 8, 2>,
+                          (const void *)fggc_fused_kernel<2, 4, 2, double2, 8, 2>,
+                          (const void *)fggc_fused_kernel<2, 2, 4, double2, 8, 2>,
+                          (const void *)fggc_fused_kernel<2, 2, 2, float2, 9>,
+                          (const void *)fggc_fused_kernel<2, 4, 2, float2, 9>,
+                          (const void *)fggc_fused_kernel<2, 2, 4, float2, 9>,
+                          (const void *)fggc_fused_kernel<2, 2, 2, float2, 9, 2>,
+                          (const void *)fggc_fused_kernel<2, 4, 2, float2, 9, 2>,
+                          (const void *)fggc_fused_kernel<2, 2, 4, float2, 9, 2>};
       for (const void *kf : ks)
         FGGC_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedMaxLds));
       g_fused_attr = true;
     }
   }
+  const int d = a.g.d, kl = d - 1;
   const DimLsq &l0 = a.lsq[0];
   Fused3Params p{};
   p.recs = base + L.off_recs;
   p.start = (const int64_t *)(base + L.off_start);
+  // [leading dimension 0, leading dimension 1, last dimension]; two
+  // dimensions give the middle entry one slice, one p-cell and one q-cell
   for (int k = 0; k < 3; ++k) {
-    p.sn[k] = a.sn[k];
-    p.npc[k] = L.npc[k];
-    p.Nq[k] = a.Nq[k];
+    const int src = k == 2 ? kl : k;
+    const bool dummy = d == 2 && k == 1;
+    p.sn[k] = dummy ? 1 : a.sn[src];
+    p.npc[k] = dummy ? 1 : L.npc[src];
+    p.Nq[k] = dummy ? 1 : a.Nq[src];
   }
   p.ntq0 = L.ntq[0];
-  p.ntq1 = L.ntq[1];
+  p.ntq1 = d == 3 ? L.ntq[1] : 1;
   p.T0 = L.fT0;
   p.T1 = L.fT1;
   p.Lc = L.fLc;
   p.TPL = L.fTPL;
   p.lgN = 0;
-  while (((int64_t)1 << p.lgN) < a.Nq[2]) ++p.lgN;
+  while (((int64_t)1 << p.lgN) < a.Nq[kl]) ++p.lgN;
   for (int i = 0; i < 8; ++i) {
     p.dq[i] = i < L.fnq ? l0.dq[i * L.fnp] : 0;
     p.dp[i] = i < L.fnp ? l0.dp[i] : 0;
   }
   p.mindp = L.mindp;
   p.maxdp = L.maxdp;
-  p.M = a.g.n[2];
-  p.kmin = m.kmin[2];
-  p.kmax = m.kmax[2];
-  p.slo = a.slo[2];
+  p.M = a.g.n[kl];
+  p.kmin = m.kmin[kl];
+  p.kmax = m.kmax[kl];
+  p.slo = a.slo[kl];
   p.eps = a.eps;
-  p.dp2 = a.dp[2];
+  p.dp2 = a.dp[kl];
   p.cK = a.cK;
-  p.gtab = (const double *)(base + L.off_gam[2]);
-  launch_band_table(a, 2, m, (double *)(base + L.off_gam[2]), s);
-  const int64_t blocks = a.sn[0] * a.sn[1] * L.ntq[0] * L.ntq[1];
-  const T *tw = (const T *)fft_twiddles(a.Nq[2], a.precision);
+  p.gtab = (const double *)(base + L.off_gam[kl]);
+  launch_band_table(a, kl, m, (double *)(base + L.off_gam[kl]), s);
+  const int64_t blocks = p.sn[0] * p.sn[1] * p.ntq0 * p.ntq1;
+  const T *tw = (const T *)fft_twiddles(a.Nq[kl], a.precision);
   const dim3 g((unsigned)blocks), b((unsigned)L.fThreads);
-  if (L.fnq == 2 && L.fnp == 2) fggc_fused3_kernel<2, 2, T><<<g, b, L.fshm, s>>>(p, out, tw);
-  else if (L.fnq == 4 && L.fnp == 2) fggc_fused3_kernel<4, 2, T><<<g, b, L.fshm, s>>>(p, out, tw);
-  else fggc_fused3_kernel<2, 4, T><<<g, b, L.fshm, s>>>(p, out, tw);
+  // <dimensions, q-shifts, p-shifts, type, longest line (log2), frequency blocks>
+  auto go = [&](auto kern) { kern<<<g, b, L.fshm, s>>>(p, out, tw); };
+  const int sh = L.fnq == 2 && L.fnp == 2 ? 0 : (L.fnq == 4 ? 1 : 2);
+  if (d == 3) {
+    if (sh == 0) go(fggc_fused_kernel<3, 2, 2, T>);
+    else if (sh == 1) go(fggc_fused_kernel<3, 4, 2, T>);
+    else go(fggc_fused_kernel<3, 2, 4, T>);
+  } else if (p.lgN <= 8 && L.fNF == 1) {
+    if (sh == 0) go(fggc_fused_kernel<2, 2, 2, T>);
+    else if (sh == 1) go(fggc_fused_kernel<2, 4, 2, T>);
+    else go(fggc_fused_kernel<2, 2, 4, T>);
+  } else if (p.lgN <= 8) {
+    if (sh == 0) go(fggc_fused_kernel<2, 2, 2, T, 8, 2>);
+    else if (sh == 1) go(fggc_fused_kernel<2, 4, 2, T, 8, 2>);
+    else go(fggc_fused_kernel<2, 2, 4, T, 8, 2>);
+  } else {
+    // 512-point lines (FP32 only, see plan_fused)
+    if constexpr (sizeof(T) == 8) {
+      if (L.fNF == 1) {
+        if (sh == 0) go(fggc_fused_kernel<2, 2, 2, T, 9>);
+        else if (sh == 1) go(fggc_fused_kernel<2, 4, 2, T, 9>);
+        else go(fggc_fused_kernel<2, 2, 4, T, 9>);
+      } else {
+        if (sh == 0) go(fggc_fused_kernel<2, 2, 2, T, 9, 2>);
+        else if (sh == 1) go(fggc_fused_kernel<2, 4, 2, T, 9, 2>);
+        else go(fggc_fused_kernel<2, 2, 4, T, 9, 2>);
+      }
+    } else {
+      fail(FGGC_EDEVICE, "internal: 512-point fused lines planned in FP64");
+    }
+  }
   FGGC_HIP(hipGetLastError());
 }
 
@@ -2787,13 +2899,13 @@ void finish_stage(const FggcArgs &a, const FggcLayout &L, char *base, T *cells, 
     // F5 + F6 as d separable passes, last dimension first, into the spectrum
     // (three dimensions: the first pass fused with the accumulation)
     T *x1 = (T *)(base + L.off_x1), *x2 = (T *)(base + L.off_x2);
-    if (L.fused3) {
+    if (L.fused) {
       StageScope sc(a.prof, "fggc_fused", s);
-      launch_fused3<T>(a, L, base, m, x1, s);
+      launch_fused<T>(a, L, base, m, x1, s);
     }
     StageScope sc(a.prof, "fggc_contract", s);
-    const T *in = L.fused3 ? x1 : cells;
-    for (int k = L.fused3 ? d - 2 : d - 1; k >= 0; --k) {
+    const T *in = L.fused ? x1 : cells;
+    for (int k = L.fused ? d - 2 : d - 1; k >= 0; --k) {
       T *out = k == 0 ? U : (k == d - 1 ? x1 : x2);
       if (contract2_ok(a, L, k)) launch_contract2<T>(a, L, k, base, in, out, m, s);
       else launch_contract<T, R>(a, L, k, in, out, k == d - 1 ? occ : nullptr, m, s);

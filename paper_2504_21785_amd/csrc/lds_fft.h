@@ -189,11 +189,44 @@ template <typename T> __device__ __forceinline__ void dft16f(T *x) {
   }
 }
 
+// 32 = 2 x 16: the DFT16s of the even and the odd samples, then
+// X[k] = E[k] + w^k O[k], X[k + 16] = E[k] - w^k O[k], w = exp(-2 pi i / 32).
+template <typename T> __device__ __forceinline__ void dft32f(T *x) {
+  using R = decltype(T{}.x);
+  // cos(pi k / 16), k = 0 .. 8 (sin(pi k / 16) = cos(pi (8 - k) / 16))
+  constexpr R cs[9] = {(R)1.0,
+                       (R)0.980785280403230449126182236134,
+                       (R)0.923879532511286756128183189397,
+                       (R)0.831469612302545237078788377618,
+                       (R)0.707106781186547524400844362105,
+                       (R)0.555570233019602224742830813949,
+                       (R)0.38268343236508977172845998403,
+                       (R)0.195090322016128267848284868477,
+                       (R)0.0};
+  T e[16], o[16];
+#pragma unroll
+  for (int n = 0; n < 16; ++n) {
+    e[n] = x[2 * n];
+    o[n] = x[2 * n + 1];
+  }
+  dft16f(e);
+  dft16f(o);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    // w^k = cos(pi k / 16) - i sin(pi k / 16)
+    const R c = k <= 8 ? cs[k] : -cs[16 - k], sn = k <= 8 ? cs[8 - k] : cs[k - 8];
+    const T t = k == 0 ? o[0] : cmul(o[k], T{c, -sn});
+    x[k] = cadd(e[k], t);
+    x[k + 16] = csub(e[k], t);
+  }
+}
+
 template <typename T, int R> __device__ __forceinline__ void dftf(T *x) {
   if constexpr (R == 2) dft2f(x);
   else if constexpr (R == 4) dft4f(x);
   else if constexpr (R == 8) dft8(x, 0);
-  else dft16f(x);
+  else if constexpr (R == 16) dft16f(x);
+  else dft32f(x);
 }
 
 // Row stride (elements) for lds_fft2_rows on rows of N = 2^lg: the row
@@ -202,7 +235,7 @@ template <typename T, int R> __device__ __forceinline__ void dftf(T *x) {
 __host__ __device__ inline int fft2_row_stride(int lg) { return (1 << lg) + (1 << (lg / 2)); }
 
 // Forward DFT of nrows rows of N = N1 N2 points in LDS (N1 = 2^ceil(lg/2),
-// N2 = 2^floor(lg/2), 8 <= N <= 256), rows `rs` elements apart, in two
+// N2 = 2^floor(lg/2), 8 <= N <= 512), rows `rs` elements apart, in two
 // passes with one unit of work per thread each:
 //   A  unit (row, n2): DFT over n1 of x[n2 + N2 n1], times exp(-2 pi i n2 k1 / N),
 //      stored at block k1, slot n2 ^ sigma(row, k1) (a swizzle that spreads
@@ -269,9 +302,18 @@ __device__ __forceinline__ void lds_fft2_pass(T *sm, int nrows, int rs, const T 
   (void)N;
 }
 
-template <typename T>
+// MAXLG: the longest rows the caller takes (8: 256 points, 9: 512); the
+// 512-point case holds 32 points per thread in its first pass, so kernels
+// that never see it are built without it and keep their registers.
+template <typename T, int MAXLG = 8>
 __device__ __forceinline__ void lds_fft2_rows(T *sm, int lg, int nrows, int rs, const T *__restrict__ tw, int tid,
                                               int bs) {
+  if constexpr (MAXLG >= 9) {
+    if (lg == 9) {
+      lds_fft2_pass<T, 32, 16>(sm, nrows, rs, tw, tid, bs);
+      return;
+    }
+  }
   switch (lg) {
     case 3: lds_fft2_pass<T, 4, 2>(sm, nrows, rs, tw, tid, bs); break;
     case 4: lds_fft2_pass<T, 4, 4>(sm, nrows, rs, tw, tid, bs); break;

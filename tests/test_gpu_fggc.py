@@ -531,6 +531,38 @@ def test_mixed_radix_sizes_refused(ctx):
             ctx.reconstruct(*args, M, st, precision=F.FP32)
 
 
+@pytest.mark.parametrize("name,prec,tol,eps,M,Nq", [
+    ("Q2P2", F.FP64, 1e-12, 1.0 / 256, (128, 128), None),
+    ("Q4P2", F.FP32, 1e-6, 1.0 / 256, (256, 128), None),
+    ("Q2P4", F.FP32, 1e-6, 1.0 / 256, (128, 256), None),
+    ("Q4P2", F.FP64, 1e-9, 1.0 / 256, (128, 128), None),     # FP64 records of 272 bytes: read in two steps
+    ("Q2P2", F.FP32, 1e-6, 1.0 / 256, (64, 96), (128, 64)),  # unequal meshes; a grid of 96 along the lines
+    ("Q4P2", F.FP32, 1e-6, 1.0 / 1024, (256, 256), (256, 512)),  # 512-point lines
+    ("Q2P2", F.FP32, 1e-6, 1.0 / 1024, (512, 512), (512, 512)),  # 512-point lines, wide band union
+    ("Q2P2", F.FP32, 1e-6, 1.0 / 1024, (256, 1024), (256, 512)),  # two blocks of frequencies per thread
+    ("Q4P2", F.FP32, 1e-6, 1.0 / 1024, (128, 1024), (256, 256)),
+])
+def test_reconstruct_2d_fused(ctx, orc, name, prec, tol, eps, M, Nq):
+    # the two-dimensional fused finish (accumulation with the pass over the
+    # last dimension) for each shift set it takes, both precisions, lines of
+    # up to 512 points, meshes and grids that differ per dimension
+    ps = W.gen_mesh(2, 16, 6, 0.5, (0.5, 0.3), eps, 128, seed=53)
+    ps.M = tuple(M)
+    st0 = F.default_strategy(2, ps.eps, name)
+    sd0 = st0.describe()
+    Nq = list(sd0["Nq"][:2]) if Nq is None else list(Nq)
+    st = F.make_strategy(2, Nq, sd0["dp"][:2], sd0["dq_off"], sd0["dp_off"])
+    sd = st.describe()
+    pts = heavy_points(ps, 120, 60, 5)
+    log(f"2d fused {name} prec {prec} eps {eps} M={M} Nq={Nq}")
+    u = ctx.reconstruct(t(ps.Q), t(ps.P), t(ps.S), t(ps.a), ps.eps, ps.M, st, scale=0.7, precision=prec)
+    torch.cuda.synchronize()
+    u = u.cpu().numpy().reshape(-1)[pts].astype(np.complex128)
+    ref = orc.fggc(ps.Q, ps.P, ps.S, ps.a, ps.eps, ps.M, sd["Nq"][:2], sd["dp"][:2], sd["dq_off"],
+                   sd["dp_off"], scale=0.7, pts=pts)
+    check(u, ref, tol, f"fggc 2d fused {name} prec {prec} eps {eps} M={M} Nq={Nq}")
+
+
 @pytest.mark.parametrize("prec,tol", [(F.FP64, 1e-12), (F.FP32, 1e-6)])
 def test_reconstruct_3d_edge_cases(ctx, orc, prec, tol):
     # no packets; single packets; packets on q- and p-mesh points, on the
