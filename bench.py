@@ -101,7 +101,7 @@ def fused_valu_busy(workload, ms):
     t = committed_profile(f"valu_{workload}.json")
     if t is None:
         return None
-    k = t.get("kernels", {}).get("fggc_fused3_kernel")
+    k = t.get("kernels", {}).get("fggc_fused_kernel")
     if not k or "SQ_INSTS_VALU" not in k:
         return None
     slots = k["SQ_INSTS_VALU"] * 64
@@ -162,7 +162,7 @@ def stage_work(ps, st, sn, fused=False, cK=6.0):
             return (O * sn[k] * A * Nq[k] * B + O * A * M[k] * B) * es
 
         if fused:
-            # 3D: the accumulation fused with the pass over the last dimension.
+            # the accumulation fused with the pass over the last dimension.
             # It reads one record per packet and writes the pass's output once
             # (a few GB: far from the HBM roof), so it is priced by its FP32
             # arithmetic: the Kronecker contributions (one complex multiply and
@@ -170,12 +170,13 @@ def stage_work(ps, st, sn, fused=False, cK=6.0):
             # every line of every slice (5 N log2 N flops) and the fold of each
             # slice's band into the grid frequencies (a real weight times a
             # complex value added, 4 flops, per line, slice and band frequency)
-            O, A = int(np.prod(sn[:2])), int(np.prod(Nq[:2]))
+            kl = d - 1
+            O, A = int(np.prod(sn[:kl])), int(np.prod(Nq[:kl]))
             lines = int(np.prod(sn)) * A
             band = math.floor(2 * cK / math.sqrt(ps.eps)) + 1
-            flops = (N * n1 ** 3 * 8 + lines * 5 * Nq[2] * math.log2(Nq[2]) + lines * band * 4)
-            w["fggc_fused"] = ("alu", flops / 1e12, "TFLOP/s", FP32_VEC_PEAK_T, 1, "fggc_fused3_kernel")
-            w["fggc_fused_bytes"] = (N * rec_b + O * A * M[2] * es) / 1e9
+            flops = (N * n1 ** d * 8 + lines * 5 * Nq[kl] * math.log2(Nq[kl]) + lines * band * 4)
+            w["fggc_fused"] = ("alu", flops / 1e12, "TFLOP/s", FP32_VEC_PEAK_T, 1, "fggc_fused_kernel")
+            w["fggc_fused_bytes"] = (N * rec_b + O * A * M[kl] * es) / 1e9
             w["fggc_contract"] = ("hbm", sum(pass_bytes(k) for k in range(d - 2, -1, -1)) / 1e9, "GB/s",
                                   HBM_PEAK_GBS, d - 1, "fft_contract_kernel")
         else:
@@ -185,8 +186,8 @@ def stage_work(ps, st, sn, fused=False, cK=6.0):
     if fused:
         # no cell array: packets in, the records written and read once, the
         # first pass's output written and read once, spectrum and u
-        O, A = int(np.prod(sn[:2])), int(np.prod(Nq[:2]))
-        method_bytes = N * ((2 * d + 1) * 8 + 16) + 2 * N * rec_b + 2 * O * A * M[2] * es + 3 * mpts * es
+        O, A = int(np.prod(sn[:d - 1])), int(np.prod(Nq[:d - 1]))
+        method_bytes = N * ((2 * d + 1) * 8 + 16) + 2 * N * rec_b + 2 * O * A * M[d - 1] * es + 3 * mpts * es
     return w, method_bytes
 
 

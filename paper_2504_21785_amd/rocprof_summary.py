@@ -36,7 +36,7 @@ STAGE_KERNELS = {
     "fggc_sort": ["fggc_key_kernel", "fggc_rank_kernel", "count_rowscan_kernel", "count_binscan_kernel",
                   "bucket_pos_kernel", "bucket_rank_kernel", "coarse_perm_kernel", "fine_sort_kernel"],
     "fggc_band_mac": ["band_mac"],
-    "fggc_fused": ["fggc_fused3_kernel"],
+    "fggc_fused": ["fggc_fused_kernel"],
     "fggc_contract": ["fft_contract_kernel", "fft_contract2_kernel", "band_table_kernel"],
     "fggc_ifft": ["fft_axis_kernel", "fft_axis_mr_kernel"],
     "ds_kernel": ["ds_kernel"],
