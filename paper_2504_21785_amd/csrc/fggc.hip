@@ -1733,6 +1733,7 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused_kernel(Fused3Params 
   };
   int64_t nr0, nr1;
   run_bounds(0, tid0 >> 6, tid0 & 63, nr0, nr1);
+  bool dirty = true;  // the lines may hold data (a chunk without records leaves them zero)
   for (int c0 = 0; c0 < sn2; c0 += p.Lc) {
     const int lcn = min(p.Lc, sn2 - c0);
     // the thread index through a compiler fence: addresses are formed in each
@@ -1745,15 +1746,18 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused_kernel(Fused3Params 
       s_n[wv * kFusedRuns + lane] = nr1 - nr0;
     }
     if (c0 + p.Lc < sn2) run_bounds(c0 + p.Lc, wv, lane, nr0, nr1);
-    // this chunk's band weights into LDS (the fold reads them)
-    for (int e = tid; e < lcn * ng; e += bs) gam[e] = (RR)p.gtab[(int64_t)c0 * ng + e];
-    for (int e = tid; e < lcn * P * rs; e += bs) cl[e] = T{0, 0};
+    if (dirty)
+      for (int e = tid; e < lcn * P * rs; e += bs) cl[e] = T{0, 0};
     __syncthreads();
     // the chunk's records over all its slices (read before the barrier that
     // ends the accumulation, so that the next chunk may rewrite the runs)
     int64_t ctotal = 0;
     for (int w = 0; w < lcn; ++w)
       for (int x = 0; x < nruns; ++x) ctotal += s_n[w * kFusedRuns + x];
+    // this chunk's band weights into LDS (the fold reads them, after the
+    // barrier that ends the accumulation)
+    if (ctotal > 0)
+      for (int e = tid; e < lcn * ng; e += bs) gam[e] = (RR)p.gtab[(int64_t)c0 * ng + e];
     if (wv < lcn) {
       const int l2 = c0 + wv;
       int64_t total = 0;
@@ -1872,8 +1876,10 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused_kernel(Fused3Params 
     }
     __syncthreads();
     // a chunk whose slices took no record left its lines zero: nothing to
-    // transform or fold (sparse packet sets skip most chunks)
-    if (ctotal == 0) continue;
+    // transform or fold, nor to clear for the next chunk (sparse packet sets
+    // skip most chunks)
+    dirty = ctotal > 0;
+    if (!dirty) continue;
     lds_fft2_rows<T, MAXLG>(cl, lgN, lcn * P, rs, stw, tid, bs);
     // thread (g, t): frequency t of lines g, g + G, g + 2 G, ... -- one band
     // weight per (slice, alias) serves all of them
