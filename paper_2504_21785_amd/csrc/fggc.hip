@@ -994,10 +994,13 @@ __global__ __launch_bounds__(256) void fggc_accum_kernel(AccParams p, T *__restr
 
 // Accumulation without atomics (d = 2, 3): one wave per (slice, q-tile); the
 // tile lives in LDS as interleaved complex values and is updated with plain
-// read-modify-writes.  Two lanes can hit the same cell in one instruction only
-// when their records share (p-cell, q-cell); before adding, lanes claim an LDS
-// hash slot of that key and only the lane that holds its slot adds in this
-// pass, the others in later passes -- so each pass writes distinct cells.
+// read-modify-writes.  Each lane first picks, per dimension, the one p-shift
+// that lands its record on the slice and the coefficients at it, so that
+// every lane runs the same n_q^d contributions.  Two lanes can hit the same
+// cell in one instruction only when their records share the q-cell; before
+// adding, lanes claim an LDS hash slot of it and only the lane that holds its
+// slot adds in this pass, the others in later passes -- so each pass writes
+// distinct cells.
 constexpr int kHashSlots = 1024;
 
 template <int D, int NQ, int NP, typename T>
@@ -1090,7 +1093,9 @@ __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__r
       const RecIdx<D> ri = *reinterpret_cast<const RecIdx<D> *>(raw);
       const T *c = reinterpret_cast<const T *>(reinterpret_cast<const char *>(raw) + rec_idx_bytes<D>());
       int lq[D][NQ];
-      bool okb[D][NP];
+      // the p-shift of each dimension that lands on this slice (at most one:
+      // the window is one slice), and the coefficients at it
+      int bsel[D];
       uint32_t h = 0;
 #pragma unroll
       for (int k = 0; k < D; ++k) {
@@ -1100,15 +1105,32 @@ __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__r
           const int qv = wrapq(ri.q[k] + p.dq[a] - tq0[k], nqk);
           lq[k][a] = qv < tl ? qv : -1;
         }
+        bsel[k] = -1;
 #pragma unroll
-        for (int b = 0; b < NP; ++b) okb[k][b] = (int64_t)ri.pc[k] + p.dp[b] - p.mindp == sl[k];
-        h = h * 0x9E3779B1u + (uint32_t)ri.q[k] * 0x85EBCA77u + (uint32_t)ri.pc[k] * 0xC2B2AE3Du;
+        for (int b = 0; b < NP; ++b)
+          if ((int64_t)ri.pc[k] + p.dp[b] - p.mindp == sl[k]) bsel[k] = b;
+        h = h * 0x9E3779B1u + (uint32_t)ri.q[k] * 0x85EBCA77u;
       }
       h = (h ^ (h >> 15)) & (kHashSlots - 1);
+      bool reach = true;
+      T cu[D][NQ];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        reach = reach && bsel[k] >= 0;
+#pragma unroll
+        for (int a = 0; a < NQ; ++a) {
+          cu[k][a] = T{0, 0};
+#pragma unroll
+          for (int b = 0; b < NP; ++b)
+            if (b == bsel[k]) cu[k][a] = c[k * N1 + a * NP + b];
+        }
+      }
       // passes: the loop condition is wave-uniform; the barriers (a single
-      // wave here) order the claims and the cell updates between lanes
+      // wave here) order the claims and the cell updates between lanes.  One
+      // instruction fixes the q-shifts, so two lanes write the same cell in it
+      // only if their records share the q-cell: the claims are keyed by q-cell.
       volatile int *claim = s_claim;
-      bool todo = valid;
+      bool todo = valid && reach;
       while (__ballot(todo)) {
         if (todo) claim[h] = lane;
         __syncthreads();
@@ -1117,70 +1139,52 @@ __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__r
           todo = false;
           if constexpr (D == 1) {
 #pragma unroll
-            for (int b = 0; b < NP; ++b) {
-              if (!okb[0][b]) continue;
-#pragma unroll
-              for (int a = 0; a < NQ; ++a) {
-                if (lq[0][a] < 0) continue;
-                const T v = c[a * NP + b];
-                T o = tile[lq[0][a]];
-                o.x += v.x;
-                o.y += v.y;
-                tile[lq[0][a]] = o;
-              }
+            for (int a = 0; a < NQ; ++a) {
+              if (lq[0][a] < 0) continue;
+              const T v = cu[0][a];
+              T o = tile[lq[0][a]];
+              o.x += v.x;
+              o.y += v.y;
+              tile[lq[0][a]] = o;
             }
           } else if constexpr (D == 2) {
 #pragma unroll
-            for (int b0 = 0; b0 < NP; ++b0)
+            for (int a0 = 0; a0 < NQ; ++a0) {
+              if (lq[0][a0] < 0) continue;
+              const T u = cu[0][a0];
 #pragma unroll
-              for (int b1 = 0; b1 < NP; ++b1) {
-                if (!okb[0][b0] || !okb[1][b1]) continue;
-#pragma unroll
-                for (int a0 = 0; a0 < NQ; ++a0) {
-                  if (lq[0][a0] < 0) continue;
-                  const T u = c[a0 * NP + b0];
-#pragma unroll
-                  for (int a1 = 0; a1 < NQ; ++a1) {
-                    if (lq[1][a1] < 0) continue;
-                    const T v = c[N1 + a1 * NP + b1];
-                    const int li = lq[0][a0] * tile1 + lq[1][a1];
-                    T o = tile[li];
-                    o.x += u.x * v.x - u.y * v.y;
-                    o.y += u.x * v.y + u.y * v.x;
-                    tile[li] = o;
-                  }
-                }
+              for (int a1 = 0; a1 < NQ; ++a1) {
+                if (lq[1][a1] < 0) continue;
+                const T v = cu[1][a1];
+                const int li = lq[0][a0] * tile1 + lq[1][a1];
+                T o = tile[li];
+                o.x += u.x * v.x - u.y * v.y;
+                o.y += u.x * v.y + u.y * v.x;
+                tile[li] = o;
               }
+            }
           } else {
 #pragma unroll
-            for (int b0 = 0; b0 < NP; ++b0)
+            for (int a0 = 0; a0 < NQ; ++a0) {
+              if (lq[0][a0] < 0) continue;
+              const T u = cu[0][a0];
 #pragma unroll
-              for (int b1 = 0; b1 < NP; ++b1)
+              for (int a1 = 0; a1 < NQ; ++a1) {
+                if (lq[1][a1] < 0) continue;
+                const T v = cu[1][a1];
+                const T uv = T{u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x};
 #pragma unroll
-                for (int b2 = 0; b2 < NP; ++b2) {
-                  if (!okb[0][b0] || !okb[1][b1] || !okb[2][b2]) continue;
-#pragma unroll
-                  for (int a0 = 0; a0 < NQ; ++a0) {
-                    if (lq[0][a0] < 0) continue;
-                    const T u = c[a0 * NP + b0];
-#pragma unroll
-                    for (int a1 = 0; a1 < NQ; ++a1) {
-                      if (lq[1][a1] < 0) continue;
-                      const T v = c[N1 + a1 * NP + b1];
-                      const T uv = T{u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x};
-#pragma unroll
-                      for (int a2 = 0; a2 < NQ; ++a2) {
-                        if (lq[2][a2] < 0) continue;
-                        const T w = c[2 * N1 + a2 * NP + b2];
-                        const int li = (lq[0][a0] * tile1 + lq[1][a1]) * tile2 + lq[2][a2];
-                        T o = tile[li];
-                        o.x += uv.x * w.x - uv.y * w.y;
-                        o.y += uv.x * w.y + uv.y * w.x;
-                        tile[li] = o;
-                      }
-                    }
-                  }
+                for (int a2 = 0; a2 < NQ; ++a2) {
+                  if (lq[2][a2] < 0) continue;
+                  const T w = cu[2][a2];
+                  const int li = (lq[0][a0] * tile1 + lq[1][a1]) * tile2 + lq[2][a2];
+                  T o = tile[li];
+                  o.x += uv.x * w.x - uv.y * w.y;
+                  o.y += uv.x * w.y + uv.y * w.x;
+                  tile[li] = o;
                 }
+              }
+            }
           }
         }
         __syncthreads();
