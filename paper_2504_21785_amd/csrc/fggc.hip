@@ -1001,7 +1001,7 @@ __global__ __launch_bounds__(256) void fggc_accum_kernel(AccParams p, T *__restr
 // adding, lanes claim an LDS hash slot of it and only the lane that holds its
 // slot adds in this pass, the others in later passes -- so each pass writes
 // distinct cells.
-constexpr int kHashSlots = 1024;
+constexpr int kHashSlots = 512;
 
 template <int D, int NQ, int NP, typename T>
 __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__restrict__ cells) {
