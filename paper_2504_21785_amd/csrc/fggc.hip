@@ -1680,25 +1680,32 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused_kernel(Fused3Params 
   T *cl = reinterpret_cast<T *>(smem_raw);            // [Lc][P][rs] the chunk's lines
   T *stw = cl + (size_t)p.Lc * P * rs;                // [N] twiddles
   const int nw = (int)blockDim.x >> 6;
-  int64_t *s_r0 = reinterpret_cast<int64_t *>(stw + N);  // [waves][kFusedRuns] runs of records
-  int64_t *s_n = s_r0 + nw * kFusedRuns;
+  // [waves][kFusedRuns] runs of records: first record and length (record
+  // indices are below 2^32, the key-slot count)
+  uint32_t *s_r0 = reinterpret_cast<uint32_t *>(stw + N);
+  int *s_n = reinterpret_cast<int *>(s_r0 + nw * kFusedRuns);
   RR *gam = reinterpret_cast<RR *>(s_n + nw * kFusedRuns);  // [Lc][ng] band weights, working precision
   int *s_claim = reinterpret_cast<int *>(gam + p.Lc * ng);  // [waves][kFusedClaim]
   for (int i = tid0; i < N; i += bs) stw[i] = tw[i];
   // workgroup -> (q-tile, l0, l1); workgroups run on the eight XCDs in turn,
   // and each XCD takes a contiguous range of the work, so that the slice pairs
   // of one tile (which read the same bins) share that XCD's L2
-  const int64_t nblk = gridDim.x, bid = blockIdx.x;
-  const int64_t per = nblk >> 3, rem = nblk & 7, xcd = bid & 7, i8 = bid >> 3;
-  const int64_t g = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + i8;
-  const int64_t l1 = g % p.sn[1], l0 = (g / p.sn[1]) % p.sn[0], tq = g / (p.sn[1] * p.sn[0]);
-  const int q00 = (int)((tq / p.ntq1) * T0), q10 = (int)((tq % p.ntq1) * T1);
+  // (32-bit index arithmetic: the grid, the slices and the bins are below
+  // 2^31, 2^16 and 2^32)
+  const uint32_t nblk = gridDim.x, bid = blockIdx.x;
+  const uint32_t per = nblk >> 3, rem = nblk & 7, xcd = bid & 7, i8 = bid >> 3;
+  const uint32_t g = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + i8;
+  const uint32_t sn0 = (uint32_t)p.sn[0], sn1 = (uint32_t)p.sn[1], ntq1 = (uint32_t)p.ntq1;
+  const int l1 = (int)(g % sn1), l0 = (int)((g / sn1) % sn0);
+  const uint32_t tq = g / (sn1 * sn0);
+  const int q00 = (int)(tq / ntq1) * T0, q10 = (int)(tq % ntq1) * T1;
   const int span = p.maxdp - p.mindp;
-  const int64_t a0lo = max<int64_t>(0, l0 - span), a0hi = min<int64_t>(p.npc[0] - 1, l0);
-  const int64_t a1lo = max<int64_t>(0, l1 - span), a1hi = min<int64_t>(p.npc[1] - 1, l1);
-  const int64_t nqt = p.ntq0 * p.ntq1, npc2 = p.npc[2];
+  const int a0lo = max(0, l0 - span), a0hi = min((int)p.npc[0] - 1, l0);
+  const int a1lo = max(0, l1 - span), a1hi = min((int)p.npc[1] - 1, l1);
+  const uint32_t nqt = (uint32_t)(p.ntq0 * p.ntq1), npc1 = (uint32_t)p.npc[1], npc2 = (uint32_t)p.npc[2];
   const int msk0 = (int)p.Nq[0] - 1, msk1 = (int)p.Nq[1] - 1, msk2 = N - 1;
   const int kmod = (int)(((p.kmin % M) + M) % M);
+  const int kmin = (int)p.kmin, kmax = (int)p.kmax;  // the band union (|k| < 2^31)
   // fold and output mapping: TPL threads per line group (a power of two >=
   // the active frequencies), G = blockDim / TPL groups
   const int TPL = p.TPL, G = bs / TPL;
@@ -1725,13 +1732,13 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused_kernel(Fused3Params 
   auto run_bounds = [&](int c, int wv, int lane, int64_t &r0, int64_t &r1) {
     r0 = r1 = 0;
     if (lane < nruns && wv < min(p.Lc, sn2 - c)) {
-      const int64_t l2 = c + wv;
-      const int64_t a2lo = max<int64_t>(0, l2 - span), a2hi = min<int64_t>(npc2 - 1, l2);
-      const int64_t a0 = a0lo + lane / n1r, a1 = a1lo + lane % n1r;
-      const int64_t kb = ((a0 * p.npc[1] + a1) * nqt + tq) * npc2;
+      const int l2 = c + wv;
+      const int a2lo = max(0, l2 - span), a2hi = min((int)npc2 - 1, l2);
+      const uint32_t a0 = (uint32_t)(a0lo + lane / n1r), a1 = (uint32_t)(a1lo + lane % n1r);
+      const uint32_t kb = ((a0 * npc1 + a1) * nqt + tq) * npc2;
       if (a2lo <= a2hi) {
-        r0 = p.start[kb + a2lo];
-        r1 = p.start[kb + a2hi + 1];
+        r0 = p.start[(size_t)kb + a2lo];
+        r1 = p.start[(size_t)kb + a2hi + 1];
       }
     }
   };
@@ -1746,8 +1753,8 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused_kernel(Fused3Params 
     asm volatile("" : "+v"(tid));
     const int wv = tid >> 6, lane = tid & 63;
     if (lane < nruns && wv < lcn) {
-      s_r0[wv * kFusedRuns + lane] = nr0;
-      s_n[wv * kFusedRuns + lane] = nr1 - nr0;
+      s_r0[wv * kFusedRuns + lane] = (uint32_t)nr0;
+      s_n[wv * kFusedRuns + lane] = (int)(nr1 - nr0);
     }
     if (c0 + p.Lc < sn2) run_bounds(c0 + p.Lc, wv, lane, nr0, nr1);
     if (dirty)
@@ -1755,7 +1762,7 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused_kernel(Fused3Params 
     __syncthreads();
     // the chunk's records over all its slices (read before the barrier that
     // ends the accumulation, so that the next chunk may rewrite the runs)
-    int64_t ctotal = 0;
+    int ctotal = 0;
     for (int w = 0; w < lcn; ++w)
       for (int x = 0; x < nruns; ++x) ctotal += s_n[w * kFusedRuns + x];
     // this chunk's band weights into LDS (the fold reads them, after the
@@ -1764,23 +1771,23 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused_kernel(Fused3Params 
       for (int e = tid; e < lcn * ng; e += bs) gam[e] = (RR)p.gtab[(int64_t)c0 * ng + e];
     if (wv < lcn) {
       const int l2 = c0 + wv;
-      int64_t total = 0;
-      const int64_t *wr0 = s_r0 + wv * kFusedRuns, *wn = s_n + wv * kFusedRuns;
+      int total = 0;
+      const uint32_t *wr0 = s_r0 + wv * kFusedRuns;
+      const int *wn = s_n + wv * kFusedRuns;
       for (int x = 0; x < nruns; ++x) total += wn[x];
       // (through an LDS-qualified pointer: the table lives in dynamic LDS,
       // and a generic volatile pointer would be accessed with flat
       // instructions)
       volatile __attribute__((address_space(3))) int *claim =
           (volatile __attribute__((address_space(3))) int *)(s_claim + wv * kFusedClaim);
-      for (int64_t base = 0; base < total; base += 64) {
-        const int64_t i = base + lane;
+      for (int base = 0; base < total; base += 64) {
+        const int i = base + lane;
         bool todo = i < total;
         const char *rec = nullptr;
         if (todo) {
-          int run = 0;
-          int64_t off = i;
+          int run = 0, off = i;
           while (off >= wn[run]) off -= wn[run++];
-          rec = p.recs + (wr0[run] + off) * (int64_t)RB;
+          rec = p.recs + ((size_t)wr0[run] + (size_t)off) * RB;
         }
         // records of up to 256 bytes are loaded whole (one round trip);
         // larger ones (FP64 with four shifts) index first, then only the
@@ -1795,9 +1802,9 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused_kernel(Fused3Params 
         int b0 = -1, b1 = D == 3 ? -1 : 0, b2 = -1;
 #pragma unroll
         for (int b = 0; b < NP; ++b) {
-          if ((int64_t)ri.pc[0] + p.dp[b] - p.mindp == l0) b0 = b;
+          if (ri.pc[0] + p.dp[b] - p.mindp == l0) b0 = b;
           if constexpr (D == 3)
-            if ((int64_t)ri.pc[1] + p.dp[b] - p.mindp == l1) b1 = b;
+            if (ri.pc[1] + p.dp[b] - p.mindp == l1) b1 = b;
           if (ri.pc[KL] + p.dp[b] - p.mindp == l2) b2 = b;
         }
         todo = todo && b0 >= 0 && b1 >= 0 && b2 >= 0;
@@ -1893,9 +1900,9 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused_kernel(Fused3Params 
     for (int f = 0; f < NF; ++f) {
       const int tf = t + f * TPL;
       if (tf >= nact) break;
-      for (int64_t kk = p.kmin + tf; kk <= p.kmax; kk += M) {
-        const T *fq = cl + (size_t)lg0 * rs + (int)(kk & msk2);
-        const RR *gb = gam + (kk - p.kmin);
+      for (int kk = kmin + tf; kk <= kmax; kk += M) {
+        const T *fq = cl + lg0 * rs + (kk & msk2);
+        const RR *gb = gam + (kk - kmin);
         for (int l = 0; l < lcn; ++l) {
           const RR gv = gb[l * ng];
           if (gv == (RR)0) continue;  // outside this slice's band (coherent: t runs along k)
