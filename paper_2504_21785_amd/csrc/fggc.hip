@@ -1950,7 +1950,7 @@ __global__ __launch_bounds__(kFusedThreads) void fggc_fused_kernel(Fused3Params 
 // that the writes run along b as well.
 struct Contract2Params {
   int64_t O, L, A, B, M;
-  int lgN, W, Lc, TPL;
+  int lgN, W, lgW, Lc, TPL;
   int64_t kmin, kmax;    // union of the slices' bands
   const double *gtab;    // [L][kmax - kmin + 1] band weights
 };
@@ -1968,11 +1968,17 @@ __global__ __launch_bounds__(kFusedThreads) void fft_contract2_kernel(Contract2P
   T *stw = cl + (size_t)p.Lc * W * rs;                // [N]
   RR *gam = reinterpret_cast<RR *>(stw + N);          // [Lc][ng], working precision
   for (int i = tid0; i < N; i += bs) stw[i] = tw[i];
-  const int64_t nbc = p.B / W;
-  const int64_t g = blockIdx.x, bc = g % nbc, oa = g / nbc;  // oa = o * A + a
-  const int64_t o = oa / p.A, a = oa % p.A, b0 = bc * W;
+  // (32-bit index arithmetic within the grid, 64-bit addresses; W and N
+  // are powers of two)
+  const int lgW = p.lgW;
+  const uint32_t nbc = (uint32_t)(p.B >> lgW), A = (uint32_t)p.A, g = blockIdx.x;
+  const uint32_t oa = g / nbc, bc = g - oa * nbc;  // oa = o * A + a
+  const uint32_t o = oa / A, a = oa - o * A;
+  const size_t B = (size_t)p.B, b0 = (size_t)bc << lgW;
+  const size_t sL = (size_t)A * ((size_t)N * B);  // input stride of a slice
   const int TPL = p.TPL, G = bs / TPL;
   const int kmod = (int)(((p.kmin % M) + M) % M);
+  const int kmin = (int)p.kmin, kmax = (int)p.kmax;
   RR accr[kFusedOut], acci[kFusedOut];  // sums in the working precision
 #pragma unroll
   for (int c = 0; c < kFusedOut; ++c) accr[c] = acci[c] = 0;
@@ -1984,21 +1990,22 @@ __global__ __launch_bounds__(kFusedThreads) void fft_contract2_kernel(Contract2P
     // rows (l, w) of N, loaded with w fastest (runs of W along b), eight
     // loads in flight per thread before their LDS stores
     const int tot = lcn * N * W;
+    const T *Xc = X + ((((size_t)o * p.L + l0) * A + a) << lgN) * B + b0;
     for (int e0 = tid; e0 < tot; e0 += 8 * bs) {
       T v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + u * bs;
         if (e < tot) {
-          const int w = e % W, n = (e / W) % N, l = e / (W * N);
-          v[u] = X[((((o * p.L + l0 + l) * p.A + a) << lgN) + n) * p.B + b0 + w];
+          const int w = e & (W - 1), n = (e >> lgW) & (N - 1), l = e >> (lgW + lgN);
+          v[u] = Xc[(size_t)l * sL + (size_t)n * B + w];
         }
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + u * bs;
         if (e < tot) {
-          const int w = e % W, n = (e / W) % N, l = e / (W * N);
+          const int w = e & (W - 1), n = (e >> lgW) & (N - 1), l = e >> (lgW + lgN);
           cl[(l * W + w) * rs + n] = v[u];
         }
       }
@@ -2007,9 +2014,9 @@ __global__ __launch_bounds__(kFusedThreads) void fft_contract2_kernel(Contract2P
     lds_fft2_rows<T>(cl, lgN, lcn * W, rs, stw, tid, bs);
     const int t = tid & (TPL - 1), lg0 = tid / TPL;
     if (t < nact) {
-      for (int64_t kk = p.kmin + t; kk <= p.kmax; kk += M) {
-        const T *fq = cl + (size_t)lg0 * rs + (int)(kk & (N - 1));
-        const RR *gb = gam + (kk - p.kmin);
+      for (int kk = kmin + t; kk <= kmax; kk += M) {
+        const T *fq = cl + lg0 * rs + (kk & (N - 1));
+        const RR *gb = gam + (kk - kmin);
         for (int l = 0; l < lcn; ++l) {
           const RR gv = gb[l * ng];
           if (gv == (RR)0) continue;  // outside this slice's band
@@ -2038,9 +2045,10 @@ __global__ __launch_bounds__(kFusedThreads) void fft_contract2_kernel(Contract2P
     }
   }
   __syncthreads();
+  T *Yo = Y + (size_t)oa * p.M * B + b0;
   for (int e = tid0; e < M * W; e += bs) {
-    const int w = e % W, kp = e / W;
-    Y[(oa * p.M + kp) * p.B + b0 + w] = ob[e];
+    const int w = e & (W - 1), kp = e >> lgW;
+    Yo[(size_t)kp * B + w] = ob[e];
   }
 }
 
@@ -2763,6 +2771,8 @@ void launch_contract2(const FggcArgs &a, const FggcLayout &L, int k, char *base,
   p.lgN = 0;
   while (((int64_t)1 << p.lgN) < a.Nq[k]) ++p.lgN;
   p.W = c.W;
+  p.lgW = 0;
+  while ((1 << p.lgW) < c.W) ++p.lgW;
   p.Lc = c.Lc;
   p.TPL = c.TPL;
   p.kmin = m.kmin[k];
