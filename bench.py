@@ -135,7 +135,7 @@ def stage_work(ps, st, sn, fused=False, cK=6.0):
     mpts = int(np.prod(M))
     n1 = int(st.nq * st.np)
     n1b = 4 if n1 <= 4 else (8 if n1 <= 8 else 16)
-    rec_b = 16 * ((8 * d + 15) // 16) + d * n1b * es
+    rec_b = 16 + d * n1b * es  # one 16-byte word of indices, then the coefficients
     ns = 1 if d == 1 else 2 ** d
     w = {
         # FP64: two complex n1 x n1 mat-vecs per dimension, rhs and shift, Kronecker weights

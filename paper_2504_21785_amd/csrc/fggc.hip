@@ -25,6 +25,7 @@
 //   inverse fft   of the M^d spectrum gives eq. (2.24) on the grid.
 
 #include <cmath>
+#include <type_traits>
 
 #include "common.h"
 #include "lds_fft.h"
@@ -452,8 +453,14 @@ __global__ __launch_bounds__(1024) void fggc_rank_kernel(KeyParams p, int64_t ch
 // dimension, then the per-dimension least-squares coefficients c_d[a*np+b]
 // (after conjugation and shift), the first dimension's multiplied by
 // scale * a exp(i S / eps).
+// In three dimensions the indices are 16-bit (q < 8192, and the layout
+// refuses p-cell boxes wider than 65535), so that the index part of a record
+// is one 16-byte word as in one and two dimensions.
 template <int D> struct RecIdx { int32_t q[D], pc[D]; };
-template <int D> __host__ __device__ constexpr int rec_idx_bytes() { return 16 * ((8 * D + 15) / 16); }
+template <> struct RecIdx<3> { uint16_t q[3], pc[3]; };
+template <int D> __host__ __device__ constexpr int rec_idx_bytes() {
+  return 16 * (((int)sizeof(RecIdx<D>) + 15) / 16);
+}
 template <int D, int N1, typename T> __host__ __device__ constexpr int rec_bytes() {
   return rec_idx_bytes<D>() + D * N1 * (int)sizeof(T);
 }
@@ -564,8 +571,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 1 && N
   RecIdx<D> ri;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    ri.q[k] = (int32_t)wrapq(iq[k] + p.Nq[k] / 2, p.Nq[k]);
-    ri.pc[k] = (int32_t)(ip[k] - p.pmin[k]);
+    // (narrowed to the record's index type: 16-bit in three dimensions)
+    ri.q[k] = static_cast<std::remove_reference_t<decltype(ri.q[k])>>(wrapq(iq[k] + p.Nq[k] / 2, p.Nq[k]));
+    ri.pc[k] = static_cast<std::remove_reference_t<decltype(ri.pc[k])>>(ip[k] - p.pmin[k]);
   }
 #pragma unroll
   for (int m = 0; m < NS; ++m)
@@ -2244,7 +2252,7 @@ FggcLayout fggc_layout(const FggcArgs &a, bool allow_fused = true) {
   const size_t es = f64 ? 16 : 8;
   const DimLsq &l0 = a.lsq[0];
   L.N1 = n1_bucket(l0.n1);
-  L.rec_b = 16 * ((8 * d + 15) / 16) + d * L.N1 * (int)es;
+  L.rec_b = (d == 1 ? rec_idx_bytes<1>() : (d == 2 ? rec_idx_bytes<2>() : rec_idx_bytes<3>())) + d * L.N1 * (int)es;
   L.mindp = L.maxdp = l0.dp[0];
   L.mindq = L.maxdq = l0.dq[0];
   for (int m = 1; m < l0.n1; ++m) {
@@ -2304,6 +2312,9 @@ FggcLayout fggc_layout(const FggcArgs &a, bool allow_fused = true) {
     }
   }
   if (L.nbins >= ((int64_t)1 << 32)) fail(FGGC_EUNSUPPORTED, "too many packet bins");
+  if (d == 3)
+    for (int k = 0; k < 3; ++k)
+      if (L.npc[k] > 65535) fail(FGGC_EUNSUPPORTED, "3D p-cell box wider than 65535 cells");
   L.ncells = L.nslices * nqt;
   if (L.tiles >= ((int64_t)1 << 31)) fail(FGGC_EUNSUPPORTED, "too many accumulation workgroups");
   const int64_t N = std::max<int64_t>(a.pk->N, 1);
