@@ -516,6 +516,21 @@ def test_reconstruct_mixed_radix_sizes(ctx, orc, d, name, prec, tol, M, Nq):
     check(u, ref, tol, f"fggc mixed d={d} {name} prec {prec} M={M} Nq={Nq}")
 
 
+def test_3d_box_wider_than_record_indices_refused(ctx):
+    # three-dimensional records hold 16-bit p-cell indices: a box of more than
+    # 65535 p-cells along a dimension is refused before any kernel runs
+    eps = 1.0 / 64
+    st = F.default_strategy(3, eps, "Q2P2")
+    dp = st.describe()["dp"][0]
+    Q = np.zeros((3, 2))
+    P = np.zeros((3, 2))
+    P[0, 1] = 70000 * dp
+    S = np.zeros(2)
+    a = np.ones(2, dtype=np.complex128)
+    with pytest.raises(RuntimeError, match="65535"):
+        ctx.reconstruct(t(Q), t(P), t(S), t(a), eps, (32, 32, 32), st, precision=F.FP32)
+
+
 def test_mixed_radix_sizes_refused(ctx):
     ps = W.gen_mesh(2, 16, 6, 0.5, (0.5, 0.3), 1.0 / 256, 128, seed=43)
     st0 = F.default_strategy(2, ps.eps, "Q4P2")
