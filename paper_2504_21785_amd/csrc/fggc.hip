@@ -1108,11 +1108,9 @@ __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__r
     __syncthreads();
     const int64_t total = s_pre[nb];
     any_rec = any_rec || total > 0;
-    for (int64_t base = 0; base < total; base += 64) {
-      const int64_t i = base + lane;
-      const bool valid = i < total;
-      uint4 raw[NV];
-      if (valid) {
+    // record i of this pass (zeros past the end)
+    auto load = [&](int64_t i, uint4 (&r)[NV]) {
+      if (i < total) {
         int lo = 0, hi = nb - 1;  // last bin with s_pre[bin] <= i
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
@@ -1121,10 +1119,27 @@ __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__r
         }
         const uint4 *src = reinterpret_cast<const uint4 *>(p.recs + (s_r0[lo] + (i - s_pre[lo])) * (int64_t)RB);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) raw[v] = src[v];
+        for (int v = 0; v < NV; ++v) r[v] = src[v];
       } else {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) raw[v] = make_uint4(0, 0, 0, 0);
+        for (int v = 0; v < NV; ++v) r[v] = make_uint4(0, 0, 0, 0);
+      }
+    };
+    // small records: the next chunk's loads are issued before this chunk is
+    // accumulated, so that their latency overlaps the LDS work
+    constexpr bool kAhead = NV <= 10;
+    uint4 nxt[kAhead ? NV : 1];
+    if constexpr (kAhead) load(lane, nxt);
+    for (int64_t base = 0; base < total; base += 64) {
+      const int64_t i = base + lane;
+      const bool valid = i < total;
+      uint4 raw[NV];
+      if constexpr (kAhead) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) raw[v] = nxt[v];
+        if (base + 64 < total) load(i + 64, nxt);
+      } else {
+        load(i, raw);
       }
       const RecIdx<D> ri = *reinterpret_cast<const RecIdx<D> *>(raw);
       const T *c = reinterpret_cast<const T *>(reinterpret_cast<const char *>(raw) + rec_idx_bytes<D>());
@@ -1165,7 +1180,9 @@ __global__ __launch_bounds__(64) void fggc_accum_wave_kernel(AccParams p, T *__r
       // wave here) order the claims and the cell updates between lanes.  One
       // instruction fixes the q-shifts, so two lanes write the same cell in it
       // only if their records share the q-cell: the claims are keyed by q-cell.
-      volatile int *claim = s_claim;
+      // an LDS-qualified pointer: a generic volatile one is accessed with
+      // flat instructions that wait on the vector memory counter
+      volatile __attribute__((address_space(3))) int *claim = (volatile __attribute__((address_space(3))) int *)s_claim;
       bool todo = valid && reach;
       while (__ballot(todo)) {
         if (todo) claim[h] = lane;
