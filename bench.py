@@ -336,7 +336,7 @@ def main():
                     help="run a plain elementwise copy (read and write this many MiB) before timing, "
                          "to scale HBM counters read under a profiler")
     ap.add_argument("--serving-pool", type=int, default=48)
-    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-streams", type=int, default=4)
     ap.add_argument("--cpu-target-s", type=float, default=12.0,
                     help="approximate CPU seconds for the oracle sample in 1D")
