@@ -275,6 +275,19 @@ def test_reconstruct_2d_small(ctx, orc, prec, name, tol):
     check(u, ref, tol, f"fggc 2d {name} prec {prec}")
 
 
+@pytest.mark.parametrize("prec,tol", [(F.FP32, 1e-6), (F.FP64, 1e-10)])
+def test_reconstruct_2d_crowded_bins(ctx, orc, prec, tol):
+    # 147456 packets in 3 x 3 p-cells (a p-range of 0.06 per dimension):
+    # about 250 records per bin, so that a workgroup of the two-dimensional
+    # accumulation (one slice, one q-tile: 2 x 2 bins) takes some sixteen
+    # chunks of 64 records with a ragged last one -- the FP32 records are
+    # loaded a chunk ahead, the FP64 ones are not
+    ps = W.gen_mesh(2, 48, 8, 0.06, (0.5, 0.3), 1.0 / 256, 128, seed=23)
+    pts = heavy_points(ps, 60, 20, 3)
+    u, ref = fggc_case(ctx, orc, ps, "Q4P2", prec, pts=pts)
+    check(u, ref, tol, f"fggc 2d crowded bins prec {prec}")
+
+
 def test_reconstruct_3d_small(ctx, orc):
     ps = W.gen_mesh(3, 8, 3, 0.5, (0.5, 0.3, 0.3), 1.0 / 64, 64, seed=9)
     pts = heavy_points(ps, 80, 20, 2)
